@@ -1,0 +1,73 @@
+"""Penalty matrices lambda M^* M (oracle; test infrastructure only)."""
+from __future__ import annotations
+
+import numpy as np
+
+from .fourier import modes
+
+
+def sobolev_weights(m: int, d: int, s: float) -> np.ndarray:
+    """S^2 diagonal of Sec. 3.1: p_k = 1 + ||k||_2^(2s) over k in {-m..m}^d."""
+    k = modes(m, d).astype(np.float64)
+    r2 = (k * k).sum(axis=1)
+    return 1.0 + r2 ** s
+
+
+def sobolev_bessel_weights(m: int, d: int, s: float) -> np.ndarray:
+    """The equivalent Sobolev norm (1 + ||k||^2)^s (Sec. 3.1 notes the norms are equivalent)."""
+    k = modes(m, d).astype(np.float64)
+    return (1.0 + (k * k).sum(axis=1)) ** s
+
+
+def _box_integral(q: np.ndarray, lo: float, hi: float) -> np.ndarray:
+    """int_lo^hi exp(i q x) dx for integer q (closed form)."""
+    q = np.asarray(q, dtype=np.float64)
+    out = np.empty(q.shape, dtype=np.complex128)
+    z = q == 0
+    out[z] = hi - lo
+    qq = q[~z]
+    out[~z] = (np.exp(1j * qq * hi) - np.exp(1j * qq * lo)) / (1j * qq)
+    return out
+
+
+def piml_box_fourier_matrix(m: int, lo, hi, L: float) -> np.ndarray:
+    """Fourier matrix C of a box domain (Sec. 4, tractable domains):
+    C[k1, k2] = (4L)^-d int_Omega exp(i <k1 - k2, x> pi / (2L)) dx, in torus
+    radians u = pi x / (2L), i.e. (4L)^-d (2L/pi)^d int_{Omega'} exp(i <k1-k2, u>) du
+    = (2 pi)^-d int_{Omega'} exp(i <k1-k2, u>) du over the box Omega' in radians.
+    lo, hi are the box corners in radians."""
+    lo = np.atleast_1d(np.asarray(lo, dtype=np.float64))
+    hi = np.atleast_1d(np.asarray(hi, dtype=np.float64))
+    d = lo.shape[0]
+    ks = modes(m, d)
+    diff = ks[:, None, :] - ks[None, :, :]
+    C = np.ones(diff.shape[:2], dtype=np.complex128)
+    for a in range(d):
+        C *= _box_integral(diff[..., a], lo[a], hi[a])
+    del L
+    return C / (2.0 * np.pi) ** d
+
+
+def heat_symbol(m: int) -> np.ndarray:
+    """Diagonal D of the heat operator d_t - d_xx on the basis exp(i (k_t t + k_x x)).
+
+    The derivative of exp(i k.x) is (+i k) exp(i k.x); the paper prints
+    (-i pi / 2L)^|alpha|, which would be the symbol for the conjugate basis.
+    Modes are ordered (k_t, k_x).  D_k = i k_t - (i k_x)^2 = i k_t + k_x^2."""
+    k = modes(m, 2).astype(np.float64)
+    return 1j * k[:, 0] + k[:, 1] ** 2
+
+
+def piml_heat_penalty(m: int, lam: float, mu: float, lo=(-np.pi / 2, -np.pi / 2),
+                      hi=(np.pi / 2, np.pi / 2)) -> np.ndarray:
+    """lambda S^2 + mu D^* C D (Sec. 4) with s = 1 (S^2 = 1 + ||k||^2) and the
+    heat operator on the box [lo, hi] (radians)."""
+    p = sobolev_weights(m, 2, 1.0)
+    C = piml_box_fourier_matrix(m, lo, hi, L=np.pi / 2)
+    D = heat_symbol(m)
+    return lam * np.diag(p).astype(np.complex128) + mu * (np.conj(D)[:, None] * C * D[None, :])
+
+
+def additive_penalty(m: int, d: int, s: float) -> np.ndarray:
+    """Block-diagonal Sobolev weights for the additive model, [d(2m+1)]."""
+    return np.concatenate([sobolev_weights(m, 1, s)] * d)
