@@ -1,0 +1,223 @@
+/*
+ * fk.h - C ABI of libfastkernel: Fourier-basis kernel ridge regression with
+ * type-1 / type-2 non-uniform FFTs on AMD Instinct MI355X (gfx950).
+ *
+ * The method (Doumeche, Bach, Biau, Boyer, "Fast kernel methods: Sobolev,
+ * physics-informed, and additive models", arXiv 2509.02649):
+ *
+ *   theta = (n^-1 Phi^* Phi + lambda M^* M)^-1 n^-1 Phi^* Y          (eq. kenrel_reg, Sec. 2.1)
+ *
+ * on the truncated Fourier basis exp(i k.x), ||k||_inf <= m (Sec. 2.2), where
+ * x are torus radians (x = pi X_raw / (2L)).  Sec. 2.3 observes that
+ * n^-1 Phi^* Phi is the multilevel Toeplitz matrix Sigma[k, l] = M[l - k] with
+ * generator M[q] = n^-1 sum_j exp(+i q.X_j), ||q||_inf <= 2m, and that
+ * n^-1 Phi^* Y = (n^-1 sum_j Y_j exp(-i k.X_j))_k; both are type-1 NUFFTs.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Points X are structure-of-arrays [d][n] (row a holds coordinate a of all
+ *   points), in radians; each coordinate must lie in [-2 pi, 2 pi) and is
+ *   folded onto the torus [-pi, pi).  Targets Y are [ntgt][n].  X and Y have
+ *   the same dtype (FK_F32 or FK_F64).
+ * - Mode arrays are complex128, interleaved (re, im), row-major over the
+ *   multi-index (k_1, ..., k_d), each coordinate running -m..m (k_d fastest).
+ *   N = (2m+1)^d.  The generator M runs over -2m..2m: (4m+1)^d entries.
+ * - All array pointers are DEVICE pointers owned by the caller (unless a
+ *   parameter says "host").  The library never frees them and keeps no
+ *   reference to them after the call returns.
+ * - Scratch memory is caller-provided: query its size with the matching
+ *   *_workspace_size function and pass a device buffer of at least that many
+ *   bytes (256-byte aligned).  The library allocates no device memory inside
+ *   compute calls except its small per-context plan tables (created on first
+ *   use of a shape and freed by fk_destroy).
+ * - Work is enqueued on the context's HIP stream.  Every compute entry point
+ *   ends with one synchronisation of that stream, at which device-detected
+ *   conditions (NaN input, out-of-range input, non-positive pivot, no
+ *   convergence) become the returned status.  Host-side argument checks
+ *   return FK_EINVAL before anything is enqueued.
+ * - A context must not be used by two threads at once; distinct contexts are
+ *   independent.  No exception crosses this ABI.
+ */
+#ifndef FASTKERNEL_FK_H
+#define FASTKERNEL_FK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FK_OK = 0,
+  FK_EINVAL = 1,   /* invalid argument (checked on the host, nothing enqueued) */
+  FK_ERANGE = 2,   /* a coordinate outside [-2 pi, 2 pi) */
+  FK_ENAN = 3,     /* a NaN or Inf among X or Y */
+  FK_ENOTPD = 4,   /* the system matrix lost positive definiteness in FP32 */
+  FK_ENOCONV = 5,  /* FP64 iterative refinement did not reach its tolerance */
+  FK_ENOMEM = 6,   /* workspace smaller than the queried size */
+  FK_EHIP = 7      /* a HIP runtime call failed */
+} fk_status;
+
+typedef enum { FK_F32 = 0, FK_F64 = 1 } fk_dtype;
+
+typedef struct fk_ctx fk_ctx;
+
+/* Penalty lambda M^* M of eq. (kenrel_reg). */
+typedef enum {
+  FK_PEN_SOBOLEV = 0,         /* diag 1 + ||k||_2^(2s)            (Sec. 3.1, matrix S) */
+  FK_PEN_SOBOLEV_BESSEL = 1,  /* diag (1 + ||k||_2^2)^s           (an equivalent Sobolev norm, Sec. 3.1) */
+  FK_PEN_IDENTITY = 2,        /* diag 1, the low-bias estimator     (Sec. 3.2, Prop. low-bias) */
+  FK_PEN_DIAG = 3,            /* diag p, p given by the caller (host array of N doubles, p_k > 0,
+                                 p_{-k} = p_k) */
+  FK_PEN_HEAT_BOX = 4         /* d = 2, modes (k_t, k_x):
+                                 lambda diag(1 + ||k||^2) + mu D^* C D      (Sec. 4, tractable domains)
+                                 with D_k = i k_t + k_x^2 (the operator d_t - d_xx on exp(i k.x)) and
+                                 C[k, l] = (2 pi)^-2 prod_a int_{lo_a}^{hi_a} exp(i (k_a - l_a) u) du,
+                                 the Fourier matrix of the box [lo, hi] in radians */
+} fk_pen_kind;
+
+typedef struct {
+  int kind;            /* fk_pen_kind */
+  double s;            /* Sobolev order for FK_PEN_SOBOLEV / _BESSEL */
+  const double* p;     /* host, N weights for FK_PEN_DIAG, else NULL */
+  double mu;           /* FK_PEN_HEAT_BOX: weight of the PDE term */
+  double box_lo[2];    /* FK_PEN_HEAT_BOX: box corners in radians */
+  double box_hi[2];
+} fk_penalty;
+
+/* Options; zero-initialised means defaults. */
+typedef struct {
+  double eps;          /* spreading accuracy target per dimension (default 2e-7) */
+  int max_refine;      /* FP64 refinement iterations cap (default 8; 0 = none) */
+  double refine_tol;   /* relative FP64 residual target (default 1e-10) */
+  int keep_factors;    /* 1: keep Cholesky factors in the workspace for fk_heldout_mse /
+                          fk_fit_backward (always on; field reserved) */
+} fk_options;
+
+/* Per-call report, filled by fk_fit / fk_gram when non-NULL. */
+typedef struct {
+  int status;          /* same as the return value */
+  int bad_index;       /* failing lambda index for FK_ENOTPD / FK_ENOCONV, else -1 */
+  int refine_iters;    /* FP64 refinement iterations performed */
+  int w;               /* spreading kernel width (grid points per dimension) */
+  int nf;              /* fine-grid size per dimension */
+  int bin;             /* bin edge (grid points) of the binned spread, 0 = unbinned */
+  double beta;         /* exponential-of-semicircle shape parameter */
+  double resid_rel;    /* max over (lambda, target) of ||b - A theta|| / ||b|| in FP64 */
+  float t_sort_ms, t_spread_ms, t_fft_ms, t_assemble_ms, t_factor_ms, t_solve_ms, t_total_ms;
+  double spread_kernel_ms;   /* device time of the spreading kernel alone */
+} fk_fit_info;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL = the default stream). */
+fk_status fk_create(fk_ctx** ctx, int device, void* hip_stream);
+fk_status fk_destroy(fk_ctx* ctx);
+fk_status fk_set_stream(fk_ctx* ctx, void* hip_stream);
+fk_status fk_set_options(fk_ctx* ctx, const fk_options* opt);
+const char* fk_status_string(fk_status s);
+
+/* ---------------------------------------------------------------- type-1 stage
+ * fk_gram: the Gram generator and the right-hand sides (Sec. 2.3):
+ *   M_out[q] = n^-1 sum_j exp(+i q.X_j),          q in {-2m..2m}^d,  complex128 (4m+1)^d
+ *   b_out[t][k] = n^-1 sum_j Y[t][j] exp(-i k.X_j),   k in {-m..m}^d,  complex128 ntgt x N
+ * computed by exponential-of-semicircle spreading onto an oversampled grid, an
+ * FFT and deconvolution.  d in {1, 2}; 1 <= m <= 64; 0 <= ntgt <= 32 (Y may be NULL
+ * when ntgt = 0); n >= 1. */
+fk_status fk_gram_workspace_size(fk_ctx* ctx, int d, int64_t n, int ntgt, int m, size_t* bytes);
+fk_status fk_gram(fk_ctx* ctx, int d, int64_t n, fk_dtype dtype, const void* X, int ntgt,
+                  const void* Y, int m, double* M_out, double* b_out,
+                  void* ws, size_t ws_bytes, fk_fit_info* info);
+
+/* ---------------------------------------------------------------- solve
+ * fk_solve: theta[l][t] = (Sigma + lambda_l M^*M)^-1 b[t] for every lambda in `lambdas`
+ * (host array, nlam >= 1, each > 0) and every right-hand side t (eq. kenrel_reg), from
+ * the generator M (device, complex128 (4m+1)^d) and b (device, complex128 ntgt x N).
+ * The Hermitian system is solved in its equivalent real cosine/sine form by an FP32
+ * blocked Cholesky (MFMA) per lambda, batched over lambda, with FP64 iterative
+ * refinement.  theta_out: device complex128 [nlam][ntgt][N].
+ * The workspace also keeps the factors, the FP64 real-form Gram and the real-form
+ * solutions for fk_heldout_mse / fk_fit_backward on the same workspace. */
+fk_status fk_solve_workspace_size(fk_ctx* ctx, int d, int m, int ntgt, int nlam, size_t* bytes);
+fk_status fk_solve(fk_ctx* ctx, int d, int m, const double* M, int ntgt, const double* b,
+                   const double* lambdas, int nlam, const fk_penalty* pen,
+                   double* theta_out, void* ws, size_t ws_bytes, fk_fit_info* info);
+
+/* fk_fit = fk_gram followed by fk_solve (one workspace holding both). */
+fk_status fk_fit_workspace_size(fk_ctx* ctx, int d, int64_t n, int ntgt, int m, int nlam,
+                                size_t* bytes);
+fk_status fk_fit(fk_ctx* ctx, int d, int64_t n, fk_dtype dtype, const void* X, int ntgt,
+                 const void* Y, int m, const double* lambdas, int nlam, const fk_penalty* pen,
+                 double* theta_out, void* ws, size_t ws_bytes, fk_fit_info* info);
+
+/* ---------------------------------------------------------------- type-2 stage
+ * fk_predict: out[t][j] = Re sum_k theta[t][k] exp(+i k.Xq_j) (the estimator of
+ * Sec. 2.1 evaluated at new points), by deconvolution, an inverse FFT onto an
+ * oversampled grid and exponential-of-semicircle interpolation.  theta is device
+ * complex128 [ntheta][N] (Hermitian-symmetric for a real f; the imaginary part of
+ * the sum is dropped); out is device float32 [ntheta][nq].  d in {1, 2}. */
+fk_status fk_predict_workspace_size(fk_ctx* ctx, int d, int m, int ntheta, size_t* bytes);
+fk_status fk_predict(fk_ctx* ctx, int d, int m, int ntheta, const double* theta, int64_t nq,
+                     fk_dtype dtype, const void* Xq, float* out, void* ws, size_t ws_bytes);
+
+/* ---------------------------------------------------------------- held-out loss and gradients
+ * After fk_solve (or fk_fit) on workspace `ws`, with the held-out Gram generator Mv
+ * (device complex128 (4m+1)^d), right-hand sides bv (device complex128 ntgt x N) and
+ * yv2[t] = n_v^-1 sum_j Yv[t][j]^2 (device, ntgt doubles):
+ *   mse[l][t] = theta^* Sigma_v theta - 2 Re(bv^* theta) + yv2[t]
+ *             = n_v^-1 sum_j |f_theta(Xv_j) - Yv[t][j]|^2          (device, nlam x ntgt doubles)
+ * This is not in the paper; it makes the lambda grid search of Sec. 5 differentiable. */
+fk_status fk_heldout_mse(fk_ctx* ctx, int d, int m, int ntgt, int nlam, const double* Mv,
+                         const double* bv, const double* yv2, double* mse_out,
+                         void* ws, size_t ws_bytes);
+
+/* fk_fit_backward: given grad_mse[l][t] = dLoss/dmse[l][t] (device, nlam x ntgt),
+ * with g = Sigma_v theta - bv and u = A_l^-1 g (adjoint solve with the kept factors):
+ *   grad_loglam[l] = sum_t grad_mse[l][t] * (-2 lambda_l Re(u^* P theta))      (device, nlam)
+ *   grad_p[k]      = sum_{l,t} grad_mse[l][t] * (-2 lambda_l Re(conj(u_k) theta_k))   (device, N;
+ *                    only for diagonal penalties, else left untouched)
+ *   grad_theta[l][t] = grad_mse[l][t] * g                 (device complex128, may be NULL)
+ * Requires the fk_heldout_mse call on the same workspace. */
+fk_status fk_fit_backward(fk_ctx* ctx, int d, int m, int ntgt, int nlam, const double* grad_mse,
+                          double* grad_loglam, double* grad_p, double* grad_theta,
+                          void* ws, size_t ws_bytes);
+
+/* ---------------------------------------------------------------- additive model (Sec. 5)
+ * fk_additive_gram: block Gram B (device complex128, [d(2m+1)]^2 row-major) with blocks
+ *   B[a,b][k,l] = n^-1 sum_j exp(-i k X_ja + i l X_jb)
+ * (diagonal blocks from 1-D type-1 transforms, off-diagonal blocks from 2-D type-1
+ * transforms at the points (X_a, X_b)) and the stacked right-hand side
+ * b_out[t][a(2m+1) + k] = n^-1 sum_j Y[t][j] exp(-i k X_ja).  2 <= d <= 16, m <= 64. */
+fk_status fk_additive_gram_workspace_size(fk_ctx* ctx, int d, int64_t n, int ntgt, int m,
+                                          size_t* bytes);
+fk_status fk_additive_gram(fk_ctx* ctx, int d, int64_t n, fk_dtype dtype, const void* X, int ntgt,
+                           const void* Y, int m, double* B_out, double* b_out,
+                           void* ws, size_t ws_bytes, fk_fit_info* info);
+
+/* fk_additive_fit: theta = (B + lambda blockdiag(p))^-1 b, p_k = 1 + |k|^(2s) per
+ * component (s = 0 gives the low-bias identity of Prop. low-bias additive), theta_out
+ * device complex128 [nlam][ntgt][d(2m+1)]. */
+fk_status fk_additive_fit_workspace_size(fk_ctx* ctx, int d, int64_t n, int ntgt, int m, int nlam,
+                                         size_t* bytes);
+fk_status fk_additive_fit(fk_ctx* ctx, int d, int64_t n, fk_dtype dtype, const void* X, int ntgt,
+                          const void* Y, int m, const double* lambdas, int nlam, double s,
+                          double* theta_out, void* ws, size_t ws_bytes, fk_fit_info* info);
+
+/* ---------------------------------------------------------------- synthetic inputs
+ * fk_generate_uniform: X[a][j] = (float)(lo_a + (hi_a - lo_a) * u), u = (w >> 8) 2^-24
+ * with w the Philox4x32-10 word a (a < 4) of counter (j + start, 0, 0, 0) >> ..., key = seed
+ * (the counter layout of the test-suite generator); and
+ * fk_generate_targets: Y[t][j] = (float)(sin((t+1) x1) cos(x2) + sigma * z_t(j)) with
+ * z_t Box-Muller on words 0, 1 of stream t + 1.  Device float32 outputs.  Used to
+ * materialise large inputs in device memory before a timed fit. */
+fk_status fk_generate_uniform(fk_ctx* ctx, uint64_t seed, int d, int64_t n, int64_t start,
+                              const double* lo, const double* hi, float* X);
+fk_status fk_generate_targets(fk_ctx* ctx, uint64_t seed, int ntgt, int64_t n, int64_t start,
+                              const float* X, double sigma, float* Y);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FASTKERNEL_FK_H */

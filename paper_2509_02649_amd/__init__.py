@@ -1,0 +1,345 @@
+"""Fourier-basis kernel ridge regression on MI355X (HIP, gfx950).
+
+Thin Python layer over libfastkernel.so: argument checks and marshalling of
+torch device tensors and the current HIP stream.  Every numerical step runs in
+the library's kernels.  There is no CPU fallback: without the built library
+(or without a HIP device) the functions raise.
+
+The estimator (Sec. 2.1, eq. kenrel_reg of the paper):
+    theta = (n^-1 Phi^* Phi + lambda P)^-1 n^-1 Phi^* Y
+on the Fourier basis exp(i k.x), ||k||_inf <= m, with the Gram generator
+M[q] = n^-1 sum_j exp(+i q.X_j) and b_k = n^-1 sum_j Y_j exp(-i k.X_j)
+formed by type-1 NUFFTs (Sec. 2.3).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import FkError, fk_fit_info, fk_penalty, fk_options, FK_F32, FK_F64, PEN
+
+__all__ = ["Context", "gram", "solve", "fit", "predict", "heldout_mse", "fit_backward", "additive_gram",
+           "additive_fit", "generate_uniform", "generate_targets", "KernelRidgeGridLoss", "FkError"]
+
+
+def _stream_ptr(device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return FK_F32
+    if t.dtype == torch.float64:
+        return FK_F64
+    raise TypeError(f"points must be float32 or float64, got {t.dtype}")
+
+
+def _dev_tensor(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a HIP device tensor")
+    return t.contiguous()
+
+
+class Context:
+    """A library context bound to one device; enqueues on torch's current stream."""
+
+    def __init__(self, device: int = 0, eps: float = 2e-7, max_refine: int = 8, refine_tol: float = 1e-10):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: libfastkernel needs an MI355X")
+        self.lib = _lib.load()
+        self.device = device
+        h = C.c_void_p()
+        _lib.check(self.lib.fk_create(C.byref(h), device, _stream_ptr(device)), "fk_create")
+        self.h = h
+        opt = fk_options(eps, max_refine, refine_tol, 1)
+        _lib.check(self.lib.fk_set_options(self.h, C.byref(opt)), "fk_set_options")
+        self._ws = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                self.lib.fk_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def bind_stream(self):
+        _lib.check(self.lib.fk_set_stream(self.h, _stream_ptr(self.device)), "fk_set_stream")
+
+    def workspace(self, nbytes: int) -> torch.Tensor:
+        """A cached device byte buffer of at least nbytes (256-byte aligned by the allocator)."""
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = None
+            self._ws = torch.empty(int(nbytes), dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
+
+
+_default: dict = {}
+
+
+def default_context(device: int = 0) -> Context:
+    ctx = _default.get(device)
+    if ctx is None:
+        ctx = Context(device)
+        _default[device] = ctx
+    return ctx
+
+
+def _penalty(kind: str, s: float = 1.0, p: Optional[torch.Tensor] = None, mu: float = 0.0,
+             box_lo=(-math.pi / 2, -math.pi / 2), box_hi=(math.pi / 2, math.pi / 2)):
+    pen = fk_penalty()
+    pen.kind = PEN[kind]
+    pen.s = float(s)
+    keep = None
+    if kind == "diag":
+        keep = (C.c_double * p.numel())(*[float(v) for v in p.detach().cpu().double().tolist()])
+        pen.p = C.cast(keep, C.POINTER(C.c_double))
+    pen.mu = float(mu)
+    pen.box_lo[0], pen.box_lo[1] = box_lo
+    pen.box_hi[0], pen.box_hi[1] = box_hi
+    return pen, keep
+
+
+def _modes(m: int, d: int) -> int:
+    return (2 * m + 1) ** d
+
+
+def gram(X: torch.Tensor, Y: Optional[torch.Tensor], m: int, ctx: Optional[Context] = None, info: bool = False):
+    """M [(4m+1)^d] complex128 and b [T, (2m+1)^d] complex128 from X [d, n], Y [T, n]."""
+    ctx = ctx or default_context(X.device.index or 0)
+    ctx.bind_stream()
+    X = _dev_tensor(X, "X")
+    d, n = X.shape
+    T = 0 if Y is None else Y.shape[0]
+    if Y is not None:
+        Y = _dev_tensor(Y, "Y")
+        if Y.dtype != X.dtype or Y.shape[1] != n:
+            raise ValueError("Y must be [T, n] with the dtype of X")
+    nb = C.c_size_t()
+    _lib.check(ctx.lib.fk_gram_workspace_size(ctx.h, d, n, T, m, C.byref(nb)), "fk_gram_workspace_size")
+    ws = ctx.workspace(nb.value)
+    M = torch.empty(((4 * m + 1) ** d) * 2, dtype=torch.float64, device=X.device)
+    b = torch.empty((max(T, 1), _modes(m, d) * 2), dtype=torch.float64, device=X.device)
+    inf = fk_fit_info()
+    _lib.check(ctx.lib.fk_gram(ctx.h, d, n, _dtype_code(X), _ptr(X), T, _ptr(Y), m, _ptr(M), _ptr(b), _ptr(ws),
+                               nb.value, C.byref(inf)), "fk_gram")
+    M = torch.view_as_complex(M.view(-1, 2)).reshape((4 * m + 1,) * d)
+    b = torch.view_as_complex(b.view(-1, 2)).reshape(max(T, 1), -1)[:T]
+    return (M, b, inf.as_dict()) if info else (M, b)
+
+
+def solve(M: torch.Tensor, b: torch.Tensor, m: int, lambdas: Sequence[float], penalty: str = "sobolev",
+          s: float = 1.0, ctx: Optional[Context] = None, info: bool = False, **pen_kw):
+    """theta [nlam, T, N] complex128 from the generator M and right-hand sides b [T, N]."""
+    ctx = ctx or default_context(M.device.index or 0)
+    ctx.bind_stream()
+    d = M.dim()
+    Mr = torch.view_as_real(M.contiguous()).contiguous()
+    br = torch.view_as_real(b.contiguous()).contiguous()
+    T = b.shape[0]
+    lams = (C.c_double * len(lambdas))(*[float(v) for v in lambdas])
+    nlam = len(lambdas)
+    nb = C.c_size_t()
+    _lib.check(ctx.lib.fk_solve_workspace_size(ctx.h, d, m, T, nlam, C.byref(nb)), "fk_solve_workspace_size")
+    ws = ctx.workspace(nb.value)
+    theta = torch.empty((nlam, T, _modes(m, d), 2), dtype=torch.float64, device=M.device)
+    pen, keep = _penalty(penalty, s, **pen_kw)
+    inf = fk_fit_info()
+    _lib.check(ctx.lib.fk_solve(ctx.h, d, m, _ptr(Mr), T, _ptr(br), lams, nlam, C.byref(pen), _ptr(theta), _ptr(ws),
+                                nb.value, C.byref(inf)), "fk_solve")
+    del keep
+    th = torch.view_as_complex(theta)
+    return (th, inf.as_dict()) if info else th
+
+
+def fit(X: torch.Tensor, Y: torch.Tensor, m: int, lambdas, penalty: str = "sobolev", s: float = 1.0,
+        ctx: Optional[Context] = None, info: bool = False, **pen_kw):
+    """fit(X, Y, m, lambda(s), penalty) -> theta [nlam, T, N] complex128 (one workspace, one sync)."""
+    ctx = ctx or default_context(X.device.index or 0)
+    ctx.bind_stream()
+    if isinstance(lambdas, (int, float)):
+        lambdas = [float(lambdas)]
+    X = _dev_tensor(X, "X")
+    Y = _dev_tensor(Y, "Y")
+    d, n = X.shape
+    T = Y.shape[0]
+    lams = (C.c_double * len(lambdas))(*[float(v) for v in lambdas])
+    nlam = len(lambdas)
+    nb = C.c_size_t()
+    _lib.check(ctx.lib.fk_fit_workspace_size(ctx.h, d, n, T, m, nlam, C.byref(nb)), "fk_fit_workspace_size")
+    ws = ctx.workspace(nb.value)
+    theta = torch.empty((nlam, T, _modes(m, d), 2), dtype=torch.float64, device=X.device)
+    pen, keep = _penalty(penalty, s, **pen_kw)
+    inf = fk_fit_info()
+    _lib.check(ctx.lib.fk_fit(ctx.h, d, n, _dtype_code(X), _ptr(X), T, _ptr(Y), m, lams, nlam, C.byref(pen),
+                              _ptr(theta), _ptr(ws), nb.value, C.byref(inf)), "fk_fit")
+    del keep
+    th = torch.view_as_complex(theta)
+    return (th, inf.as_dict()) if info else th
+
+
+def predict(theta: torch.Tensor, Xq: torch.Tensor, m: int, ctx: Optional[Context] = None) -> torch.Tensor:
+    """f_theta(Xq) = Re sum_k theta_k exp(i k.x) by type-2 NUFFT; theta [T, N] complex128 -> [T, nq] float32."""
+    ctx = ctx or default_context(Xq.device.index or 0)
+    ctx.bind_stream()
+    Xq = _dev_tensor(Xq, "Xq")
+    d, nq = Xq.shape
+    th = torch.view_as_real(theta.reshape(-1, _modes(m, d)).contiguous()).contiguous()
+    T = th.shape[0]
+    nb = C.c_size_t()
+    _lib.check(ctx.lib.fk_predict_workspace_size(ctx.h, d, m, T, C.byref(nb)), "fk_predict_workspace_size")
+    ws = ctx.workspace(nb.value)
+    out = torch.empty((T, nq), dtype=torch.float32, device=Xq.device)
+    _lib.check(ctx.lib.fk_predict(ctx.h, d, m, T, _ptr(th), nq, _dtype_code(Xq), _ptr(Xq), _ptr(out), _ptr(ws),
+                                  nb.value), "fk_predict")
+    return out
+
+
+def heldout_mse(Mv: torch.Tensor, bv: torch.Tensor, yv2: torch.Tensor, m: int, nlam: int,
+                ctx: Context) -> torch.Tensor:
+    """mse [nlam, T] of the last solve on ctx's workspace against held-out statistics."""
+    ctx.bind_stream()
+    d = Mv.dim()
+    T = bv.shape[0]
+    Mr = torch.view_as_real(Mv.contiguous()).contiguous()
+    br = torch.view_as_real(bv.contiguous()).contiguous()
+    y2 = yv2.to(torch.float64).contiguous()
+    out = torch.empty((nlam, T), dtype=torch.float64, device=Mv.device)
+    ws = ctx._ws
+    _lib.check(ctx.lib.fk_heldout_mse(ctx.h, d, m, T, nlam, _ptr(Mr), _ptr(br), _ptr(y2), _ptr(out), _ptr(ws),
+                                      ws.numel()), "fk_heldout_mse")
+    return out
+
+
+def fit_backward(grad_mse: torch.Tensor, m: int, d: int, ctx: Context, want_theta: bool = False):
+    """Gradients (log lambda [nlam], p [N], theta [nlam, T, N] or None) of sum(grad_mse * mse)."""
+    ctx.bind_stream()
+    nlam, T = grad_mse.shape
+    g = grad_mse.to(torch.float64).contiguous()
+    N = _modes(m, d)
+    gl = torch.empty(nlam, dtype=torch.float64, device=g.device)
+    gp = torch.empty(N, dtype=torch.float64, device=g.device)
+    gt = torch.empty((nlam, T, N, 2), dtype=torch.float64, device=g.device) if want_theta else None
+    ws = ctx._ws
+    _lib.check(ctx.lib.fk_fit_backward(ctx.h, d, m, T, nlam, _ptr(g), _ptr(gl), _ptr(gp), _ptr(gt), _ptr(ws),
+                                       ws.numel()), "fk_fit_backward")
+    return gl, gp, (torch.view_as_complex(gt) if want_theta else None)
+
+
+def additive_gram(X: torch.Tensor, Y: torch.Tensor, m: int, ctx: Optional[Context] = None):
+    """Block Gram B [d(2m+1), d(2m+1)] and stacked b [T, d(2m+1)] of the additive model (Sec. 5)."""
+    ctx = ctx or default_context(X.device.index or 0)
+    ctx.bind_stream()
+    X = _dev_tensor(X, "X")
+    Y = _dev_tensor(Y, "Y")
+    d, n = X.shape
+    T = Y.shape[0]
+    Nc = d * (2 * m + 1)
+    nb = C.c_size_t()
+    _lib.check(ctx.lib.fk_additive_gram_workspace_size(ctx.h, d, n, T, m, C.byref(nb)), "ws")
+    ws = ctx.workspace(nb.value)
+    B = torch.empty((Nc, Nc, 2), dtype=torch.float64, device=X.device)
+    b = torch.empty((T, Nc, 2), dtype=torch.float64, device=X.device)
+    inf = fk_fit_info()
+    _lib.check(ctx.lib.fk_additive_gram(ctx.h, d, n, _dtype_code(X), _ptr(X), T, _ptr(Y), m, _ptr(B), _ptr(b),
+                                        _ptr(ws), nb.value, C.byref(inf)), "fk_additive_gram")
+    return torch.view_as_complex(B), torch.view_as_complex(b)
+
+
+def additive_fit(X: torch.Tensor, Y: torch.Tensor, m: int, lambdas, s: float = 1.0, ctx: Optional[Context] = None,
+                 info: bool = False):
+    """theta [nlam, T, d(2m+1)] of the additive model with per-component Sobolev weights 1 + |k|^(2s)."""
+    ctx = ctx or default_context(X.device.index or 0)
+    ctx.bind_stream()
+    if isinstance(lambdas, (int, float)):
+        lambdas = [float(lambdas)]
+    X = _dev_tensor(X, "X")
+    Y = _dev_tensor(Y, "Y")
+    d, n = X.shape
+    T = Y.shape[0]
+    lams = (C.c_double * len(lambdas))(*[float(v) for v in lambdas])
+    nb = C.c_size_t()
+    _lib.check(ctx.lib.fk_additive_fit_workspace_size(ctx.h, d, n, T, m, len(lambdas), C.byref(nb)), "ws")
+    ws = ctx.workspace(nb.value)
+    theta = torch.empty((len(lambdas), T, d * (2 * m + 1), 2), dtype=torch.float64, device=X.device)
+    inf = fk_fit_info()
+    _lib.check(ctx.lib.fk_additive_fit(ctx.h, d, n, _dtype_code(X), _ptr(X), T, _ptr(Y), m, lams, len(lambdas),
+                                       float(s), _ptr(theta), _ptr(ws), nb.value, C.byref(inf)), "fk_additive_fit")
+    th = torch.view_as_complex(theta)
+    return (th, inf.as_dict()) if info else th
+
+
+def generate_uniform(seed: int, d: int, n: int, lo=None, hi=None, start: int = 0, device: int = 0,
+                     ctx: Optional[Context] = None) -> torch.Tensor:
+    """Philox4x32-10 uniform points [d, n] float32 on the device (same stream as the test generator)."""
+    ctx = ctx or default_context(device)
+    ctx.bind_stream()
+    lo = [-math.pi] * d if lo is None else list(lo)
+    hi = [math.pi] * d if hi is None else list(hi)
+    X = torch.empty((d, n), dtype=torch.float32, device=f"cuda:{device}")
+    clo = (C.c_double * d)(*lo)
+    chi = (C.c_double * d)(*hi)
+    _lib.check(ctx.lib.fk_generate_uniform(ctx.h, seed, d, n, start, clo, chi, _ptr(X)), "fk_generate_uniform")
+    return X
+
+
+def generate_targets(seed: int, X: torch.Tensor, ntgt: int, sigma: float = 0.1, start: int = 0,
+                     ctx: Optional[Context] = None) -> torch.Tensor:
+    """Y_t = sin(t x1) cos(x2) + sigma N(0,1), t = 1..ntgt, float32 [ntgt, n] on the device."""
+    ctx = ctx or default_context(X.device.index or 0)
+    ctx.bind_stream()
+    n = X.shape[1]
+    Y = torch.empty((ntgt, n), dtype=torch.float32, device=X.device)
+    _lib.check(ctx.lib.fk_generate_targets(ctx.h, seed, ntgt, n, start, _ptr(X), float(sigma), _ptr(Y)),
+               "fk_generate_targets")
+    return Y
+
+
+class KernelRidgeGridLoss(torch.autograd.Function):
+    """Held-out MSE of the fitted estimator over a grid of lambdas and targets.
+
+    forward(loglam [nlam] float64, p [N] float64, X, Y, Xv, Yv, m) -> mse [nlam, T]
+    The fit uses the diagonal penalty p (e.g. Sobolev weights); backward runs the
+    adjoint solve with the kept factors and returns gradients with respect to
+    log lambda and p.  Not in the paper: it makes the lambda grid search of
+    Sec. 5 differentiable.
+    """
+
+    @staticmethod
+    def forward(ctx_, loglam, p, X, Y, Xv, Yv, m):
+        fkc = default_context(X.device.index or 0)
+        lams = torch.exp(loglam.detach()).cpu().tolist()
+        theta = fit(X, Y, m, lams, penalty="diag", p=p.detach(), ctx=fkc)
+        Mv, bv = gram(Xv, Yv, m, ctx=_validation_context(fkc))
+        yv2 = (Yv.double() ** 2).mean(dim=1)
+        mse = heldout_mse(Mv, bv, yv2, m, len(lams), fkc)
+        ctx_.fkc = fkc
+        ctx_.m = m
+        ctx_.d = X.shape[0]
+        ctx_.mark_non_differentiable(theta)
+        return mse
+
+    @staticmethod
+    def backward(ctx_, grad_mse):
+        gl, gp, _ = fit_backward(grad_mse.contiguous(), ctx_.m, ctx_.d, ctx_.fkc)
+        return gl, gp, None, None, None, None, None
+
+
+_valctx: dict = {}
+
+
+def _validation_context(fkc: Context) -> Context:
+    """A second context (own workspace) so the held-out Gram does not overwrite the fit's workspace."""
+    c = _valctx.get(fkc.device)
+    if c is None:
+        c = Context(fkc.device)
+        _valctx[fkc.device] = c
+    return c

@@ -1,0 +1,599 @@
+// C ABI entry points of libfastkernel (declared in include/fk.h).
+#include "fk_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+namespace fk {
+// dense.hip kernels (same library, separate translation unit)
+struct ToeplitzQ;
+}
+
+using namespace fk;
+
+// ------------------------------------------------------------------ context
+
+extern "C" fk_status fk_create(fk_ctx** ctx, int device, void* hip_stream) {
+  if (!ctx) return FK_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return FK_EINVAL;
+  FK_HIP(hipSetDevice(device));
+  fk_ctx* c = new fk_ctx();
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->opt.eps = 2e-7;
+  c->opt.max_refine = 8;
+  c->opt.refine_tol = 1e-10;
+  if (hipMalloc(&c->flags, sizeof(int) * kFlagCount) != hipSuccess ||
+      hipHostMalloc(&c->flags_host, sizeof(int) * kFlagCount, hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return FK_EHIP;
+  }
+  for (auto& e : c->ev)
+    if (hipEventCreate(&e) != hipSuccess) return FK_EHIP;
+  *ctx = c;
+  return FK_OK;
+}
+
+extern "C" fk_status fk_destroy(fk_ctx* ctx) {
+  if (!ctx) return FK_EINVAL;
+  hipSetDevice(ctx->device);
+  hipStreamSynchronize(ctx->stream);
+  for (auto& kv : ctx->es_cache) hipFree(kv.second.second);
+  hipFree(ctx->flags);
+  hipHostFree(ctx->flags_host);
+  for (auto& e : ctx->ev) hipEventDestroy(e);
+  delete ctx;
+  return FK_OK;
+}
+
+extern "C" fk_status fk_set_stream(fk_ctx* ctx, void* s) {
+  if (!ctx) return FK_EINVAL;
+  ctx->stream = static_cast<hipStream_t>(s);
+  return FK_OK;
+}
+
+extern "C" fk_status fk_set_options(fk_ctx* ctx, const fk_options* o) {
+  if (!ctx || !o) return FK_EINVAL;
+  fk_options v = *o;
+  if (v.eps <= 0) v.eps = 2e-7;
+  if (v.eps < 1e-14 || v.eps > 1e-2) return FK_EINVAL;
+  if (v.max_refine < 0 || v.max_refine > 100) return FK_EINVAL;
+  if (v.refine_tol <= 0) v.refine_tol = 1e-10;
+  ctx->opt = v;
+  return FK_OK;
+}
+
+extern "C" const char* fk_status_string(fk_status s) {
+  switch (s) {
+    case FK_OK: return "ok";
+    case FK_EINVAL: return "invalid argument";
+    case FK_ERANGE: return "coordinate outside [-2pi, 2pi)";
+    case FK_ENAN: return "NaN or Inf in the input";
+    case FK_ENOTPD: return "system matrix not positive definite in FP32";
+    case FK_ENOCONV: return "iterative refinement did not converge";
+    case FK_ENOMEM: return "workspace too small";
+    case FK_EHIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+namespace fk {
+
+fk_status reset_flags(fk_ctx* ctx) {
+  int init[kFlagCount] = {0, 0, 0, 0x7fffffff, 0, 0x7fffffff, 0, 0};
+  std::memcpy(ctx->flags_host, init, sizeof(init));
+  FK_HIP(hipMemcpyAsync(ctx->flags, ctx->flags_host, sizeof(init), hipMemcpyHostToDevice, ctx->stream));
+  return FK_OK;
+}
+
+fk_status read_flags(fk_ctx* ctx) {
+  FK_HIP(hipMemcpyAsync(ctx->flags_host, ctx->flags, sizeof(int) * kFlagCount, hipMemcpyDeviceToHost,
+                        ctx->stream));
+  FK_HIP(hipStreamSynchronize(ctx->stream));
+  if (ctx->flags_host[kFlagNaN]) return FK_ENAN;
+  if (ctx->flags_host[kFlagRange]) return FK_ERANGE;
+  if (ctx->flags_host[kFlagNotPD]) return FK_ENOTPD;
+  return FK_OK;
+}
+
+static float elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return -1.f;
+  return ms;
+}
+
+// extraction of M and b from the type-1 output (complex [C][(2K+1)^d], K = 2m)
+__global__ void k_extract_gram(const double* __restrict__ c, int d, int m, int ntgt, double* __restrict__ M,
+                               double* __restrict__ b) {
+  const int K = 2 * m, LK = 2 * K + 1, L = 2 * m + 1;
+  const int totK = d == 1 ? LK : LK * LK;
+  const int totN = d == 1 ? L : L * L;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.y == 0) {
+    if (i >= totK) return;
+    // M[q] = c_0[-q]: reversal of the flattened index
+    int j = totK - 1 - i;
+    M[2 * i] = c[2 * j];
+    M[2 * i + 1] = c[2 * j + 1];
+    return;
+  }
+  const int t = blockIdx.y - 1;
+  if (i >= totN) return;
+  int src;
+  if (d == 1) {
+    src = i + m;
+  } else {
+    int k1 = i / L, k2 = i - k1 * L;
+    src = (k1 + m) * LK + (k2 + m);
+  }
+  const double* ct = c + 2 * (size_t)(t + 1) * totK;
+  b[2 * ((size_t)t * totN + i)] = ct[2 * src];
+  b[2 * ((size_t)t * totN + i) + 1] = ct[2 * src + 1];
+}
+
+}  // namespace fk
+
+// ------------------------------------------------------------------ fk_gram
+
+static size_t gram_ws(int d, int64_t n, int ntgt, int m) {
+  const int K = 2 * m;
+  const int LK = 2 * K + 1;
+  const int64_t tot = d == 1 ? LK : (int64_t)LK * LK;
+  Carve cv(nullptr, 0);
+  cv.take<double>((size_t)2 * (ntgt + 1) * tot);
+  return cv.off + type1_workspace(d, n, ntgt, K, 0) + 512;
+}
+
+static fk_status check_gram_args(int d, int64_t n, int ntgt, int m, const void* X, const void* Y) {
+  if (d != 1 && d != 2) return FK_EINVAL;
+  if (n < 1 || m < 1 || m > 64 || ntgt < 0 || ntgt > 32) return FK_EINVAL;
+  if (!X || (ntgt > 0 && !Y)) return FK_EINVAL;
+  if (d == 2 && n > (int64_t)1 << 34) return FK_EINVAL;
+  return FK_OK;
+}
+
+extern "C" fk_status fk_gram_workspace_size(fk_ctx* ctx, int d, int64_t n, int ntgt, int m, size_t* bytes) {
+  if (!bytes) return FK_EINVAL;
+  if (check_gram_args(d, n, ntgt, m, (void*)1, (void*)1) != FK_OK) return FK_EINVAL;
+  *bytes = gram_ws(d, n, ntgt, m);
+  return FK_OK;
+}
+
+namespace fk {
+fk_status gram_impl(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int ntgt, const void* Y, int m,
+                    double* M_out, double* b_out, Carve& cv, fk_fit_info* info) {
+  const int K = 2 * m;
+  const int LK = 2 * K + 1;
+  const int64_t tot = d == 1 ? LK : (int64_t)LK * LK;
+  double* c = cv.take<double>((size_t)2 * (ntgt + 1) * tot);
+  if (!cv.ok()) return FK_ENOMEM;
+  fk_status st = type1(ctx, d, n, dt, X, n, ntgt, Y, K, 1.0 / (double)n, c, cv, info);
+  if (st != FK_OK) return st;
+  const int L = 2 * m + 1;
+  const int totN = d == 1 ? L : L * L;
+  int mx = (int)std::max<int64_t>(tot, totN);
+  hipLaunchKernelGGL(k_extract_gram, dim3((mx + 255) / 256, ntgt + 1), dim3(256), 0, ctx->stream, c, d, m, ntgt,
+                     M_out, b_out);
+  FK_HIP(hipGetLastError());
+  FK_HIP(hipEventRecord(ctx->ev[4], ctx->stream));
+  return FK_OK;
+}
+}  // namespace fk
+
+extern "C" fk_status fk_gram(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int ntgt, const void* Y,
+                             int m, double* M_out, double* b_out, void* ws, size_t ws_bytes, fk_fit_info* info) {
+  if (!ctx) return FK_EINVAL;
+  if (check_gram_args(d, n, ntgt, m, X, Y) != FK_OK || !M_out || (ntgt > 0 && !b_out)) return FK_EINVAL;
+  if (dt != FK_F32 && dt != FK_F64) return FK_EINVAL;
+  if (ws_bytes < gram_ws(d, n, ntgt, m) || !ws) return FK_ENOMEM;
+  FK_HIP(hipSetDevice(ctx->device));
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->bad_index = -1;
+  }
+  Carve cv(ws, ws_bytes);
+  fk_status st = reset_flags(ctx);
+  if (st == FK_OK) st = gram_impl(ctx, d, n, dt, X, ntgt, Y, m, M_out, b_out, cv, info);
+  if (st != FK_OK) return st;
+  st = read_flags(ctx);
+  if (info) {
+    info->status = st;
+    info->t_sort_ms = elapsed(ctx->ev[0], ctx->ev[1]);
+    info->t_spread_ms = elapsed(ctx->ev[1], ctx->ev[2]);
+    info->spread_kernel_ms = info->t_spread_ms;
+    info->t_fft_ms = elapsed(ctx->ev[2], ctx->ev[4]);
+    info->t_total_ms = elapsed(ctx->ev[0], ctx->ev[4]);
+  }
+  return st;
+}
+
+// ------------------------------------------------------------------ fk_solve / fk_fit
+
+static int64_t ipow(int64_t a, int d) {
+  int64_t r = 1;
+  while (d-- > 0) r *= a;
+  return r;
+}
+
+static fk_status penalty_weights(const fk_penalty* pen, int d, int m, std::vector<double>& p) {
+  const int L = 2 * m + 1;
+  const int64_t N = ipow(L, d);
+  p.assign(N, 1.0);
+  const int kind = pen ? pen->kind : FK_PEN_SOBOLEV;
+  const double s = pen ? pen->s : 1.0;
+  for (int64_t i = 0; i < N; ++i) {
+    int64_t ii = i;
+    double r2 = 0.0;
+    for (int a = 0; a < d; ++a) {
+      int k = (int)(ii % L) - m;
+      ii /= L;
+      r2 += (double)k * k;
+    }
+    switch (kind) {
+      case FK_PEN_SOBOLEV: p[i] = 1.0 + std::pow(r2, s); break;
+      case FK_PEN_SOBOLEV_BESSEL: p[i] = std::pow(1.0 + r2, s); break;
+      case FK_PEN_IDENTITY: p[i] = 1.0; break;
+      case FK_PEN_DIAG:
+        if (!pen->p) return FK_EINVAL;
+        p[i] = pen->p[i];
+        break;
+      case FK_PEN_HEAT_BOX: p[i] = 1.0 + r2; break;
+      default: return FK_EINVAL;
+    }
+    if (!(p[i] > 0.0) || std::isinf(p[i])) return FK_EINVAL;
+  }
+  if (kind == FK_PEN_DIAG)
+    for (int64_t i = 0; i < N; ++i)
+      if (p[i] != p[N - 1 - i]) return FK_EINVAL;   // p_{-k} = p_k required for the real form
+  if (kind == FK_PEN_SOBOLEV || kind == FK_PEN_SOBOLEV_BESSEL)
+    if (!(s >= 0.0) || s > 64) return FK_EINVAL;
+  return FK_OK;
+}
+
+static fk_status build_problem(int d, int m, const double* M, const double* b, const double* lambdas, int nlam,
+                               const fk_penalty* pen, SolveProblem& P) {
+  if ((d != 1 && d != 2) || m < 1 || m > 64 || nlam < 1 || nlam > 1024 || !lambdas) return FK_EINVAL;
+  P.kind = SolveProblem::kToeplitz;
+  if (pen && pen->kind == FK_PEN_HEAT_BOX) {
+    if (d != 2 || !(pen->mu >= 0.0)) return FK_EINVAL;
+    P.kind = SolveProblem::kToeplitzHeat;
+    P.mu = pen->mu;
+    for (int a = 0; a < 2; ++a) {
+      P.lo[a] = pen->box_lo[a];
+      P.hi[a] = pen->box_hi[a];
+      if (!(P.hi[a] > P.lo[a])) return FK_EINVAL;
+    }
+  }
+  P.M = M;
+  P.b = b;
+  P.m = m;
+  P.d = d;
+  P.L = (int)ipow(2 * m + 1, d);
+  fk_status st = penalty_weights(pen, d, m, P.p);
+  if (st != FK_OK) return st;
+  P.lams.assign(lambdas, lambdas + nlam);
+  for (double l : P.lams)
+    if (!(l > 0.0) || std::isinf(l)) return FK_EINVAL;
+  return FK_OK;
+}
+
+extern "C" fk_status fk_solve_workspace_size(fk_ctx* ctx, int d, int m, int ntgt, int nlam, size_t* bytes) {
+  if (!bytes || (d != 1 && d != 2) || m < 1 || m > 64 || ntgt < 1 || ntgt > 32 || nlam < 1 || nlam > 1024)
+    return FK_EINVAL;
+  *bytes = solve_layout((int)ipow(2 * m + 1, d), nlam, ntgt, nullptr, 0).bytes;
+  return FK_OK;
+}
+
+extern "C" fk_status fk_solve(fk_ctx* ctx, int d, int m, const double* M, int ntgt, const double* b,
+                              const double* lambdas, int nlam, const fk_penalty* pen, double* theta_out, void* ws,
+                              size_t ws_bytes, fk_fit_info* info) {
+  if (!ctx || !M || !b || !theta_out || ntgt < 1 || ntgt > 32) return FK_EINVAL;
+  SolveProblem P;
+  fk_status st = build_problem(d, m, M, b, lambdas, nlam, pen, P);
+  if (st != FK_OK) return st;
+  SolveLayout s = solve_layout(P.L, nlam, ntgt, ws, ws_bytes);
+  if (!ws || s.bytes > ws_bytes) return FK_ENOMEM;
+  FK_HIP(hipSetDevice(ctx->device));
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->bad_index = -1;
+  }
+  st = reset_flags(ctx);
+  if (st == FK_OK) st = solve_impl(ctx, P, s, theta_out, info);
+  if (info) info->status = st;
+  return st;
+}
+
+static size_t fit_ws(int d, int64_t n, int ntgt, int m, int nlam) {
+  const int64_t N = ipow(2 * m + 1, d);
+  size_t a = solve_layout((int)N, nlam, ntgt, nullptr, 0).bytes;
+  Carve cv(nullptr, 0);
+  cv.take<double>((size_t)2 * ipow(4 * m + 1, d));
+  cv.take<double>((size_t)2 * ntgt * N);
+  return a + cv.off + gram_ws(d, n, ntgt, m) + 1024;
+}
+
+extern "C" fk_status fk_fit_workspace_size(fk_ctx* ctx, int d, int64_t n, int ntgt, int m, int nlam,
+                                           size_t* bytes) {
+  if (!bytes) return FK_EINVAL;
+  if (check_gram_args(d, n, ntgt, m, (void*)1, (void*)1) != FK_OK || ntgt < 1 || nlam < 1 || nlam > 1024)
+    return FK_EINVAL;
+  *bytes = fit_ws(d, n, ntgt, m, nlam);
+  return FK_OK;
+}
+
+extern "C" fk_status fk_fit(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int ntgt, const void* Y,
+                            int m, const double* lambdas, int nlam, const fk_penalty* pen, double* theta_out,
+                            void* ws, size_t ws_bytes, fk_fit_info* info) {
+  if (!ctx || !theta_out) return FK_EINVAL;
+  if (check_gram_args(d, n, ntgt, m, X, Y) != FK_OK || ntgt < 1) return FK_EINVAL;
+  if (dt != FK_F32 && dt != FK_F64) return FK_EINVAL;
+  SolveProblem P;
+  fk_status st = build_problem(d, m, nullptr, nullptr, lambdas, nlam, pen, P);
+  if (st != FK_OK) return st;
+  if (!ws || ws_bytes < fit_ws(d, n, ntgt, m, nlam)) return FK_ENOMEM;
+  FK_HIP(hipSetDevice(ctx->device));
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->bad_index = -1;
+  }
+  SolveLayout s = solve_layout(P.L, nlam, ntgt, ws, ws_bytes);
+  Carve cv(static_cast<char*>(ws) + s.bytes, ws_bytes - s.bytes);
+  double* M = cv.take<double>((size_t)2 * ipow(4 * m + 1, d));
+  double* b = cv.take<double>((size_t)2 * ntgt * P.L);
+  P.M = M;
+  P.b = b;
+  st = reset_flags(ctx);
+  if (st == FK_OK) st = gram_impl(ctx, d, n, dt, X, ntgt, Y, m, M, b, cv, info);
+  if (st != FK_OK) return st;
+  st = read_flags(ctx);
+  if (info) {
+    info->t_sort_ms = elapsed(ctx->ev[0], ctx->ev[1]);
+    info->t_spread_ms = elapsed(ctx->ev[1], ctx->ev[2]);
+    info->spread_kernel_ms = info->t_spread_ms;
+    info->t_fft_ms = elapsed(ctx->ev[2], ctx->ev[4]);
+  }
+  if (st != FK_OK) {
+    if (info) info->status = st;
+    return st;
+  }
+  st = solve_impl(ctx, P, s, theta_out, info);
+  if (info) {
+    info->status = st;
+    info->t_total_ms = elapsed(ctx->ev[0], ctx->ev[8]);
+  }
+  return st;
+}
+
+// ------------------------------------------------------------------ held-out loss / backward
+
+extern "C" fk_status fk_heldout_mse(fk_ctx* ctx, int d, int m, int ntgt, int nlam, const double* Mv,
+                                    const double* bv, const double* yv2, double* mse_out, void* ws,
+                                    size_t ws_bytes) {
+  if (!ctx || !Mv || !bv || !yv2 || !mse_out || (d != 1 && d != 2) || m < 1 || m > 64 || ntgt < 1 || ntgt > 32 ||
+      nlam < 1 || nlam > 1024)
+    return FK_EINVAL;
+  SolveLayout s = solve_layout((int)ipow(2 * m + 1, d), nlam, ntgt, ws, ws_bytes);
+  if (!ws || s.bytes > ws_bytes) return FK_ENOMEM;
+  FK_HIP(hipSetDevice(ctx->device));
+  fk_status st = heldout_mse_impl(ctx, s, d, m, Mv, bv, yv2, mse_out);
+  if (st != FK_OK) return st;
+  FK_HIP(hipStreamSynchronize(ctx->stream));
+  return FK_OK;
+}
+
+extern "C" fk_status fk_fit_backward(fk_ctx* ctx, int d, int m, int ntgt, int nlam, const double* grad_mse,
+                                     double* grad_loglam, double* grad_p, double* grad_theta, void* ws,
+                                     size_t ws_bytes) {
+  if (!ctx || !grad_mse || !grad_loglam || (d != 1 && d != 2) || m < 1 || m > 64 || ntgt < 1 || ntgt > 32 ||
+      nlam < 1 || nlam > 1024)
+    return FK_EINVAL;
+  SolveLayout s = solve_layout((int)ipow(2 * m + 1, d), nlam, ntgt, ws, ws_bytes);
+  if (!ws || s.bytes > ws_bytes) return FK_ENOMEM;
+  FK_HIP(hipSetDevice(ctx->device));
+  fk_status st = backward_impl(ctx, s, d, grad_mse, grad_loglam, grad_p, grad_theta);
+  if (st != FK_OK) return st;
+  FK_HIP(hipStreamSynchronize(ctx->stream));
+  return FK_OK;
+}
+
+// ------------------------------------------------------------------ additive model (Sec. 5)
+namespace fk {
+
+// Assemble the complex block Gram B [Nc][Nc] (Nc = d L, L = 2m+1) and stacked RHS from
+//   c1[a]: 1-D type-1 outputs [T+1][4m+1] (K = 2m, already scaled by 1/n),
+//   c2[p]: 2-D type-1 outputs [(2m+1)^2] (K = m) of the pair p = (a < b), scaled by 1/n.
+// B[a,a][k,l] = M_a[l-k] = c1_a,0[k-l]; B[a,b][k,l] = c2_ab[k, -l]; B[b,a] = B[a,b]^*.
+__global__ void k_additive_assemble(const double* __restrict__ c1, const double* __restrict__ c2, int d, int m,
+                                    int T, double* __restrict__ B, double* __restrict__ b) {
+  const int L = 2 * m + 1, K1 = 4 * m + 1, Nc = d * L;
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < Nc * Nc) {
+    int r = idx / Nc, s = idx - r * Nc;
+    int a = r / L, k = r % L - m, bb = s / L, l = s % L - m;
+    double re, im;
+    if (a == bb) {
+      const double* c = c1 + 2 * (size_t)a * (T + 1) * K1;
+      int q = k - l + 2 * m;
+      re = c[2 * q];
+      im = c[2 * q + 1];
+    } else {
+      int lo = a < bb ? a : bb, hi = a < bb ? bb : a;
+      int p = lo * d - lo * (lo + 1) / 2 + (hi - lo - 1);   // pair index
+      const double* c = c2 + 2 * (size_t)p * L * L;
+      if (a < bb) {
+        int o = (k + m) * L + (-l + m);
+        re = c[2 * o];
+        im = c[2 * o + 1];
+      } else {  // B[a,b][k,l] = conj(B[b,a][l,k]) with b < a
+        int o = (l + m) * L + (-k + m);
+        re = c[2 * o];
+        im = -c[2 * o + 1];
+      }
+    }
+    B[2 * (size_t)idx] = re;
+    B[2 * (size_t)idx + 1] = im;
+  }
+  if (idx < T * Nc) {
+    int t = idx / Nc, r = idx - t * Nc;
+    int a = r / L, k = r % L - m;
+    const double* c = c1 + 2 * ((size_t)a * (T + 1) + (t + 1)) * K1;
+    int q = k + 2 * m;
+    b[2 * (size_t)idx] = c[2 * q];
+    b[2 * (size_t)idx + 1] = c[2 * q + 1];
+  }
+}
+
+static size_t additive_gram_ws(int d, int64_t n, int T, int m) {
+  const int L = 2 * m + 1, K1 = 4 * m + 1;
+  const int npair = d * (d - 1) / 2;
+  Carve cv(nullptr, 0);
+  cv.take<double>((size_t)2 * d * (T + 1) * K1);
+  cv.take<double>((size_t)2 * npair * L * L);
+  size_t t1 = type1_workspace(1, n, T, 2 * m, 0);
+  size_t t2 = type1_workspace(2, n, 0, m, 0);
+  return cv.off + std::max(t1, t2) + 1024;
+}
+
+fk_status additive_gram_impl(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int T, const void* Y,
+                             int m, double* B, double* b, Carve& cv, fk_fit_info* info) {
+  const int L = 2 * m + 1, K1 = 4 * m + 1;
+  const int npair = d * (d - 1) / 2;
+  double* c1 = cv.take<double>((size_t)2 * d * (T + 1) * K1);
+  double* c2 = cv.take<double>((size_t)2 * npair * L * L);
+  if (!cv.ok()) return FK_ENOMEM;
+  const size_t esz = dt == FK_F64 ? 8 : 4;
+  const char* Xc = static_cast<const char*>(X);
+  for (int a = 0; a < d; ++a) {
+    Carve sub = cv;
+    fk_status st = type1(ctx, 1, n, dt, Xc + esz * (size_t)a * n, n, T, Y, 2 * m, 1.0 / (double)n,
+                         c1 + 2 * (size_t)a * (T + 1) * K1, sub, info);
+    if (st != FK_OK) return st;
+  }
+  int p = 0;
+  for (int a = 0; a < d; ++a)
+    for (int bb = a + 1; bb < d; ++bb, ++p) {
+      Carve sub = cv;
+      fk_status st = type1(ctx, 2, n, dt, Xc + esz * (size_t)a * n, (int64_t)(bb - a) * n, 0, nullptr, m,
+                           1.0 / (double)n, c2 + 2 * (size_t)p * L * L, sub, info);
+      if (st != FK_OK) return st;
+    }
+  const int Nc = d * L;
+  const int tot = std::max(Nc * Nc, T * Nc);
+  hipLaunchKernelGGL(k_additive_assemble, dim3((tot + 255) / 256), dim3(256), 0, ctx->stream, c1, c2, d, m, T, B, b);
+  FK_HIP(hipGetLastError());
+  return FK_OK;
+}
+
+}  // namespace fk
+
+static fk_status check_additive(int d, int64_t n, int T, int m, const void* X, const void* Y) {
+  if (d < 2 || d > 16 || n < 1 || m < 1 || m > 64 || T < 1 || T > 32 || !X || !Y) return FK_EINVAL;
+  return FK_OK;
+}
+
+extern "C" fk_status fk_additive_gram_workspace_size(fk_ctx* ctx, int d, int64_t n, int ntgt, int m,
+                                                     size_t* bytes) {
+  (void)ctx;
+  if (!bytes || check_additive(d, n, ntgt, m, (void*)1, (void*)1) != FK_OK) return FK_EINVAL;
+  *bytes = additive_gram_ws(d, n, ntgt, m);
+  return FK_OK;
+}
+
+extern "C" fk_status fk_additive_gram(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int ntgt,
+                                      const void* Y, int m, double* B_out, double* b_out, void* ws, size_t ws_bytes,
+                                      fk_fit_info* info) {
+  if (!ctx || check_additive(d, n, ntgt, m, X, Y) != FK_OK || !B_out || !b_out) return FK_EINVAL;
+  if (dt != FK_F32 && dt != FK_F64) return FK_EINVAL;
+  if (!ws || ws_bytes < additive_gram_ws(d, n, ntgt, m)) return FK_ENOMEM;
+  FK_HIP(hipSetDevice(ctx->device));
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->bad_index = -1;
+  }
+  Carve cv(ws, ws_bytes);
+  fk_status st = reset_flags(ctx);
+  FK_HIP(hipEventRecord(ctx->ev[9], ctx->stream));
+  if (st == FK_OK) st = additive_gram_impl(ctx, d, n, dt, X, ntgt, Y, m, B_out, b_out, cv, info);
+  if (st != FK_OK) return st;
+  FK_HIP(hipEventRecord(ctx->ev[10], ctx->stream));
+  st = read_flags(ctx);
+  if (info) {
+    info->status = st;
+    info->t_total_ms = elapsed(ctx->ev[9], ctx->ev[10]);
+  }
+  return st;
+}
+
+static size_t additive_fit_ws(int d, int64_t n, int T, int m, int nlam) {
+  const int Nc = d * (2 * m + 1);
+  size_t a = solve_layout(Nc, nlam, T, nullptr, 0).bytes;
+  Carve cv(nullptr, 0);
+  cv.take<double>((size_t)2 * Nc * Nc);
+  cv.take<double>((size_t)2 * T * Nc);
+  return a + cv.off + additive_gram_ws(d, n, T, m) + 1024;
+}
+
+extern "C" fk_status fk_additive_fit_workspace_size(fk_ctx* ctx, int d, int64_t n, int ntgt, int m, int nlam,
+                                                    size_t* bytes) {
+  (void)ctx;
+  if (!bytes || check_additive(d, n, ntgt, m, (void*)1, (void*)1) != FK_OK || nlam < 1 || nlam > 1024)
+    return FK_EINVAL;
+  *bytes = additive_fit_ws(d, n, ntgt, m, nlam);
+  return FK_OK;
+}
+
+extern "C" fk_status fk_additive_fit(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int ntgt,
+                                     const void* Y, int m, const double* lambdas, int nlam, double s,
+                                     double* theta_out, void* ws, size_t ws_bytes, fk_fit_info* info) {
+  if (!ctx || check_additive(d, n, ntgt, m, X, Y) != FK_OK || !theta_out || !lambdas || nlam < 1 || nlam > 1024)
+    return FK_EINVAL;
+  if (dt != FK_F32 && dt != FK_F64) return FK_EINVAL;
+  if (!(s >= 0.0) || s > 64) return FK_EINVAL;
+  if (!ws || ws_bytes < additive_fit_ws(d, n, ntgt, m, nlam)) return FK_ENOMEM;
+  FK_HIP(hipSetDevice(ctx->device));
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->bad_index = -1;
+  }
+  const int L = 2 * m + 1, Nc = d * L;
+  SolveProblem P;
+  P.kind = SolveProblem::kDense;
+  P.m = m;
+  P.d = 1;
+  P.L = L;
+  P.p.resize(Nc);
+  for (int a = 0; a < d; ++a)
+    for (int k = -m; k <= m; ++k) P.p[a * L + k + m] = 1.0 + (s == 0.0 ? 0.0 : std::pow((double)k * k, s));
+  if (s == 0.0)
+    for (auto& v : P.p) v = 1.0;
+  P.lams.assign(lambdas, lambdas + nlam);
+  for (double l : P.lams)
+    if (!(l > 0.0) || std::isinf(l)) return FK_EINVAL;
+  SolveLayout sl = solve_layout(Nc, nlam, ntgt, ws, ws_bytes);
+  Carve cv(static_cast<char*>(ws) + sl.bytes, ws_bytes - sl.bytes);
+  double* B = cv.take<double>((size_t)2 * Nc * Nc);
+  double* b = cv.take<double>((size_t)2 * ntgt * Nc);
+  P.B = B;
+  P.b = b;
+  fk_status st = reset_flags(ctx);
+  FK_HIP(hipEventRecord(ctx->ev[9], ctx->stream));
+  if (st == FK_OK) st = additive_gram_impl(ctx, d, n, dt, X, ntgt, Y, m, B, b, cv, info);
+  if (st != FK_OK) return st;
+  FK_HIP(hipEventRecord(ctx->ev[10], ctx->stream));
+  st = read_flags(ctx);
+  if (st != FK_OK) {
+    if (info) info->status = st;
+    return st;
+  }
+  st = solve_impl(ctx, P, sl, theta_out, info);
+  if (info) {
+    info->status = st;
+    info->t_spread_ms = elapsed(ctx->ev[9], ctx->ev[10]);
+    info->t_total_ms = elapsed(ctx->ev[9], ctx->ev[8]);
+  }
+  return st;
+}

@@ -1,0 +1,888 @@
+// Dense stage: assembly of the normal equations in real cosine/sine form, a
+// batched FP32 blocked Cholesky on MFMA, FP32 triangular solves, and FP64
+// iterative refinement (eq. kenrel_reg; the paper's additive model solves the
+// same kind of system directly, Sec. 5 "Complexity").
+//
+// Real form.  For real data the complex system A theta = b with
+// A[-k,-l] = conj A[k,l] and b[-k] = conj b[k] has a Hermitian-symmetric
+// solution, and theta = U c with the unitary change of basis
+//   c_0 <-> exp(0),  c_{k,cos} <-> sqrt2 cos(k.x),  c_{k,sin} <-> sqrt2 sin(k.x)
+// (k in a half space) turns it into the real symmetric system
+// (U^* A U) c = U^* b of the same size N and condition number, which costs
+// a quarter of the complex factorization.  Real index r of a block of L modes:
+// r = 0 constant, r = 2h-1 cosine and r = 2h sine of mode h = 1..(L-1)/2 (the
+// modes are counted from the centre of the block in row-major order).
+//
+// Layout in HBM: every real matrix is Np x Np row-major, Np = N rounded up to a
+// multiple of 64, padded with the identity (factor) or zeros (FP64 Gram), so the
+// blocked kernels never see a ragged edge.  One FP64 Gram H64 (with any dense,
+// lambda-independent penalty folded in) serves all lambdas; each lambda has its
+// own FP32 matrix, overwritten by its Cholesky factor, and the inverses of its
+// 64 x 64 diagonal blocks.
+#include "fk_internal.h"
+
+#include <cmath>
+#include <vector>
+
+namespace fk {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+constexpr int NB = 64;     // block size of the factorization
+constexpr int LDT = NB + 4; // LDS row stride (floats) of a 64 x 64 tile
+
+// ------------------------------------------------------------------ real-form index maps
+
+struct RealMap {
+  int L;      // complex modes per block
+  int nblk;   // number of blocks (1, or d for the additive model)
+};
+
+// complex index of the mode of real index r, its negation, and the entry type
+// (0 const, 1 cos, 2 sin)
+__device__ __forceinline__ void real_to_complex(int r, int L, int* type, int* kidx, int* nkidx) {
+  int a = r / L, rho = r - a * L;
+  int c0 = a * L + (L - 1) / 2;
+  if (rho == 0) {
+    *type = 0;
+    *kidx = c0;
+    *nkidx = c0;
+  } else {
+    int h = (rho + 1) >> 1;
+    *type = (rho & 1) ? 1 : 2;
+    *kidx = c0 + h;
+    *nkidx = c0 - h;
+  }
+}
+
+struct cplx {
+  double re, im;
+};
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cplx csub(cplx a, cplx b) { return {a.re - b.re, a.im - b.im}; }
+
+// Real-form entry from four complex entries (see header comment).
+template <class Q>
+__device__ double real_entry(const Q& q, int r, int s, int L) {
+  int tr, k, nk, ts, l, nl;
+  real_to_complex(r, L, &tr, &k, &nk);
+  real_to_complex(s, L, &ts, &l, &nl);
+  const double rs2 = 0.70710678118654752440;
+  if (tr == 0 && ts == 0) return q(k, l).re;
+  if (tr == 0) {
+    cplx a = q(k, l), b = q(k, nl);
+    // (0, cos): (Q(0,l) + Q(0,-l))/sqrt2 ; (0, sin): Re[i (Q(0,-l) - Q(0,l))]/sqrt2
+    return ts == 1 ? (a.re + b.re) * rs2 : -(b.im - a.im) * rs2;
+  }
+  if (ts == 0) {
+    cplx a = q(k, l), b = q(nk, l);
+    // (cos, 0): (Q(k,0) + Q(-k,0))/sqrt2 ; (sin, 0): Re[-i (Q(-k,0) - Q(k,0))]/sqrt2
+    return tr == 1 ? (a.re + b.re) * rs2 : (b.im - a.im) * rs2;
+  }
+  cplx kl = q(k, l), knl = q(k, nl), nkl = q(nk, l), nknl = q(nk, nl);
+  if (tr == 1 && ts == 1) return 0.5 * (kl.re + knl.re + nkl.re + nknl.re);
+  if (tr == 2 && ts == 2) return 0.5 * (nknl.re - nkl.re - knl.re + kl.re);
+  if (tr == 1) {  // (cos k, sin l) = Re[(i/2)(Q(k,-l) - Q(k,l) + Q(-k,-l) - Q(-k,l))]
+    cplx z = csub(cadd(knl, nknl), cadd(kl, nkl));
+    return -0.5 * z.im;
+  }
+  // (sin k, cos l) = Re[(-i/2)(Q(-k,l) + Q(-k,-l) - Q(k,l) - Q(k,-l))]
+  cplx z = csub(cadd(nkl, nknl), cadd(kl, knl));
+  return 0.5 * z.im;
+}
+
+// Complex entry providers ------------------------------------------------
+
+// Toeplitz Gram Sigma[k, l] = M[l - k] from the generator over {-2m..2m}^d.
+struct ToeplitzQ {
+  const double* M;
+  int m, d;
+  __device__ cplx operator()(int i, int j) const {
+    const int L = 2 * m + 1, G = 4 * m + 1;
+    int idx = 0;
+    int ii = i, jj = j;
+    int mul = 1;
+    for (int a = d - 1; a >= 0; --a) {
+      int ki = ii % L - m, kj = jj % L - m;
+      ii /= L;
+      jj /= L;
+      idx += (kj - ki + 2 * m) * mul;
+      mul *= G;
+    }
+    return {M[2 * idx], M[2 * idx + 1]};
+  }
+};
+
+// Heat-equation penalty mu conj(D_k) C[k,l] D_l, D_k = i k_t + k_x^2, modes (k_t, k_x),
+// C[k,l] = (2 pi)^-2 prod_a int_{lo_a}^{hi_a} exp(i (k_a - l_a) u) du.
+struct HeatQ {
+  int m;
+  double mu, lo0, hi0, lo1, hi1;
+  __device__ static cplx box(int q, double lo, double hi) {
+    if (q == 0) return {hi - lo, 0.0};
+    double s1, c1, s0, c0;
+    sincos(q * hi, &s1, &c1);
+    sincos(q * lo, &s0, &c0);
+    // (e^{iqhi} - e^{iqlo}) / (iq) = ((s1 - s0) - i (c1 - c0)) / q
+    return {(s1 - s0) / q, -(c1 - c0) / q};
+  }
+  __device__ cplx operator()(int i, int j) const {
+    const int L = 2 * m + 1;
+    int kt = i / L - m, kx = i % L - m, lt = j / L - m, lx = j % L - m;
+    cplx ct = box(kt - lt, lo0, hi0), cx = box(kx - lx, lo1, hi1);
+    const double s = 1.0 / (4.0 * kPi * kPi);
+    cplx C = {(ct.re * cx.re - ct.im * cx.im) * s, (ct.re * cx.im + ct.im * cx.re) * s};
+    cplx Dk = {(double)(kx * kx), (double)kt}, Dl = {(double)(lx * lx), (double)lt};
+    // conj(Dk) * C * Dl
+    cplx t = {Dk.re * C.re + Dk.im * C.im, Dk.re * C.im - Dk.im * C.re};
+    return {mu * (t.re * Dl.re - t.im * Dl.im), mu * (t.re * Dl.im + t.im * Dl.re)};
+  }
+};
+
+// Dense complex matrix [Nc][Nc] (additive block Gram).
+struct DenseQ {
+  const double* B;
+  int Nc;
+  __device__ cplx operator()(int i, int j) const {
+    size_t o = 2 * ((size_t)i * Nc + j);
+    return {B[o], B[o + 1]};
+  }
+};
+
+template <class Q1, class Q2>
+struct SumQ {
+  Q1 a;
+  Q2 b;
+  __device__ cplx operator()(int i, int j) const { return cadd(a(i, j), b(i, j)); }
+};
+
+// H64[r][s] = real form of Q (r, s < N); zero padding up to Np.
+template <class Q>
+__global__ __launch_bounds__(256) void k_assemble_real(Q q, int N, int L, int Np, double* __restrict__ H) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)Np * Np) return;
+  int r = (int)(idx / Np), s = (int)(idx - (int64_t)r * Np);
+  double v = 0.0;
+  if (r < N && s < N) v = real_entry(q, r, s, L);
+  H[idx] = v;
+}
+
+// A32[l] = H64 + lambda_l diag(p_real) (lower triangle incl. diagonal), identity padding.
+__global__ __launch_bounds__(256) void k_make_a32(const double* __restrict__ H, const double* __restrict__ preal,
+                                                  const double* __restrict__ lams, int N, int Np,
+                                                  float* __restrict__ A) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)Np * Np) return;
+  const int l = blockIdx.y;
+  int r = (int)(idx / Np), s = (int)(idx - (int64_t)r * Np);
+  float v;
+  if (r < N && s < N) {
+    double h = H[idx];
+    if (r == s) h += lams[l] * preal[r];
+    v = (float)h;
+  } else {
+    v = (r == s) ? 1.0f : 0.0f;
+  }
+  A[(size_t)l * Np * Np + idx] = v;
+}
+
+// preal[r] = p[complex mode of r]
+__global__ void k_real_weights(const double* __restrict__ p, int N, int L, double* __restrict__ preal) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  int t, k, nk;
+  real_to_complex(r, L, &t, &k, &nk);
+  preal[r] = p[k];
+}
+
+// Real right-hand sides Bre[t][r] (Np rows, zero padded) from complex b[t][k].
+__global__ void k_rhs_real(const double* __restrict__ b, int N, int L, int Np, int ntgt,
+                           double* __restrict__ Bre) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  int t = blockIdx.y;
+  if (r >= Np) return;
+  double v = 0.0;
+  if (r < N) {
+    int ty, k, nk;
+    real_to_complex(r, L, &ty, &k, &nk);
+    const double* bt = b + 2 * (size_t)t * N;
+    const double s2 = 1.41421356237309504880;
+    v = ty == 0 ? bt[2 * k] : (ty == 1 ? s2 * bt[2 * k] : -s2 * bt[2 * k + 1]);
+  }
+  Bre[(size_t)t * Np + r] = v;
+}
+
+// theta[l][t][k] (complex) from real solutions X[l][t][r].
+__global__ void k_theta_from_real(const double* __restrict__ X, int N, int L, int Np, int ntgt,
+                                  double* __restrict__ theta) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  int lt = blockIdx.y;  // l * ntgt + t
+  if (r >= N) return;
+  const double* x = X + (size_t)lt * Np;
+  double* th = theta + 2 * (size_t)lt * N;
+  int ty, k, nk;
+  real_to_complex(r, L, &ty, &k, &nk);
+  const double rs2 = 0.70710678118654752440;
+  if (ty == 0) {
+    th[2 * k] = x[r];
+    th[2 * k + 1] = 0.0;
+  } else if (ty == 1) {
+    double c = x[r], s = x[r + 1];
+    th[2 * k] = c * rs2;
+    th[2 * k + 1] = -s * rs2;
+    th[2 * nk] = c * rs2;
+    th[2 * nk + 1] = s * rs2;
+  }
+}
+
+// ------------------------------------------------------------------ MFMA 64x64x64 tile
+// acc += As * Bs^T, As and Bs are 64 x 64 FP32 tiles in LDS with row stride LDT
+// (As[row][k], Bs[col][k]).  Wave w owns rows 32*(w>>1).. and cols 32*(w&1)..,
+// as 2 x 2 blocks of v_mfma_f32_16x16x4f32.  For that instruction lane l holds
+// A[l%16][l/16] and B[l/16][l%16]; the 16 x 16 result row 4*(l/16)+v, column
+// l%16 sits in element v of the lane's accumulator.
+__device__ __forceinline__ void mfma_tile64(const float* As, const float* Bs, floatx4 acc[2][2]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll 4
+  for (int k = 0; k < NB; k += 4) {
+    float a0 = As[(r0 + li) * LDT + k + lk];
+    float a1 = As[(r0 + 16 + li) * LDT + k + lk];
+    float b0 = Bs[(c0 + li) * LDT + k + lk];
+    float b1 = Bs[(c0 + 16 + li) * LDT + k + lk];
+    acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+  }
+}
+
+// Load a 64 x 64 FP32 tile (row-major, leading dimension ld) into LDS.
+__device__ __forceinline__ void load_tile(float* T, const float* src, int64_t ld) {
+  for (int i = threadIdx.x; i < NB * NB / 4; i += blockDim.x) {
+    int r = i / (NB / 4), c = (i - r * (NB / 4)) * 4;
+    float4 v = *reinterpret_cast<const float4*>(src + r * ld + c);
+    T[r * LDT + c] = v.x;
+    T[r * LDT + c + 1] = v.y;
+    T[r * LDT + c + 2] = v.z;
+    T[r * LDT + c + 3] = v.w;
+  }
+}
+
+// dst tile (+)= sign * acc
+__device__ __forceinline__ void store_acc(float* dst, int64_t ld, const floatx4 acc[2][2], bool add, float sign) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int r = r0 + rb * 16 + 4 * (lane >> 4) + v;
+        int c = c0 + cb * 16 + (lane & 15);
+        float x = sign * acc[rb][cb][v];
+        if (add) dst[r * ld + c] += x;
+        else dst[r * ld + c] = x;
+      }
+}
+
+// ------------------------------------------------------------------ Cholesky kernels
+
+// Factor the diagonal block kb of every lambda (one workgroup per lambda), in FP64
+// in LDS; write L_kk (lower) back and inv(L_kk) to Linv[l][kb].
+__global__ __launch_bounds__(256) void k_potrf_diag(float* __restrict__ A, int Np, int kb,
+                                                    float* __restrict__ Linv, int* flags) {
+  __shared__ double a[NB][NB + 1];
+  __shared__ double x[NB][NB + 1];
+  __shared__ int bad;
+  const int l = blockIdx.x;
+  float* Ab = A + (size_t)l * Np * Np + (size_t)kb * NB * Np + kb * NB;
+  for (int i = threadIdx.x; i < NB * NB; i += blockDim.x) {
+    int r = i / NB, c = i - r * NB;
+    a[r][c] = (c <= r) ? (double)Ab[(size_t)r * Np + c] : 0.0;
+  }
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int j = 0; j < NB; ++j) {
+    if (threadIdx.x == 0) {
+      double dj = a[j][j];
+      if (!(dj > 0.0)) {   // non-positive or NaN pivot
+        bad = 1;
+        dj = 1.0;
+      }
+      a[j][j] = sqrt(dj);
+    }
+    __syncthreads();
+    const double djj = a[j][j];
+    for (int i = j + 1 + threadIdx.x; i < NB; i += blockDim.x) a[i][j] /= djj;
+    __syncthreads();
+    const int rem = NB - j - 1;
+    for (int t = threadIdx.x; t < rem * rem; t += blockDim.x) {
+      int i = j + 1 + t / rem, k = j + 1 + t % rem;
+      if (k <= i) a[i][k] -= a[i][j] * a[k][j];
+    }
+    __syncthreads();
+  }
+  // inverse of the lower-triangular block, one column per thread
+  if (threadIdx.x < NB) {
+    const int c = threadIdx.x;
+    for (int i = 0; i < NB; ++i) x[i][c] = 0.0;
+    x[c][c] = 1.0 / a[c][c];
+    for (int i = c + 1; i < NB; ++i) {
+      double s = 0.0;
+      for (int k = c; k < i; ++k) s += a[i][k] * x[k][c];
+      x[i][c] = -s / a[i][i];
+    }
+  }
+  __syncthreads();
+  float* Li = Linv + ((size_t)l * (Np / NB) + kb) * NB * NB;
+  for (int i = threadIdx.x; i < NB * NB; i += blockDim.x) {
+    int r = i / NB, c = i - r * NB;
+    Ab[(size_t)r * Np + c] = (c <= r) ? (float)a[r][c] : 0.0f;
+    Li[i] = (float)x[r][c];
+  }
+  if (threadIdx.x == 0 && bad) {
+    atomicOr(&flags[kFlagNotPD], 1);
+    atomicMin(&flags[kFlagNotPD + 1], l);
+  }
+}
+
+// Panel: L[i][kb] = A[i][kb] * inv(L_kk)^T for block rows i > kb.
+__global__ __launch_bounds__(256) void k_trsm_panel(float* __restrict__ A, int Np, int kb,
+                                                    const float* __restrict__ Linv) {
+  __shared__ float As[NB * LDT], Bs[NB * LDT];
+  const int l = blockIdx.y;
+  const int ib = kb + 1 + blockIdx.x;
+  float* Al = A + (size_t)l * Np * Np;
+  float* src = Al + (size_t)ib * NB * Np + kb * NB;
+  load_tile(As, src, Np);
+  const float* Li = Linv + ((size_t)l * (Np / NB) + kb) * NB * NB;
+  load_tile(Bs, Li, NB);
+  __syncthreads();
+  floatx4 acc[2][2] = {};
+  mfma_tile64(As, Bs, acc);
+  store_acc(src, Np, acc, false, 1.0f);
+}
+
+// Trailing update of the lower triangle: A[i][j] -= L[i][kb] L[j][kb]^T, kb < j <= i.
+__global__ __launch_bounds__(256) void k_syrk_update(float* __restrict__ A, int Np, int kb) {
+  __shared__ float As[NB * LDT], Bs[NB * LDT];
+  const int l = blockIdx.y;
+  // decode lower-triangular tile index t -> (i, j), i >= j, offsets from kb+1
+  int t = blockIdx.x;
+  int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  while (i * (i + 1) / 2 > t) --i;
+  int j = t - i * (i + 1) / 2;
+  i += kb + 1;
+  j += kb + 1;
+  float* Al = A + (size_t)l * Np * Np;
+  load_tile(As, Al + (size_t)i * NB * Np + kb * NB, Np);
+  load_tile(Bs, Al + (size_t)j * NB * Np + kb * NB, Np);
+  __syncthreads();
+  floatx4 acc[2][2] = {};
+  mfma_tile64(As, Bs, acc);
+  store_acc(Al + (size_t)i * NB * Np + j * NB, Np, acc, true, -1.0f);
+}
+
+// ------------------------------------------------------------------ triangular solves (FP32)
+// R, Y: [lambda][ncol][Np] (column-major per lambda: column t contiguous).
+
+// Forward step kb: y_kb = inv(L_kk) r_kb (written by block 0); rows ib > kb: r_ib -= L[ib][kb] y_kb.
+__global__ __launch_bounds__(256) void k_fwd_step(const float* __restrict__ A, int Np, int kb,
+                                                  const float* __restrict__ Linv, float* __restrict__ R,
+                                                  float* __restrict__ Y, int ncol) {
+  __shared__ float Lt[NB * LDT];
+  __shared__ float rk[32][NB];
+  __shared__ float yk[32][NB];
+  const int l = blockIdx.y;
+  const float* Li = Linv + ((size_t)l * (Np / NB) + kb) * NB * NB;
+  float* Rl = R + (size_t)l * ncol * Np;
+  for (int i = threadIdx.x; i < ncol * NB; i += blockDim.x) {
+    int t = i / NB, r = i - t * NB;
+    rk[t][r] = Rl[(size_t)t * Np + kb * NB + r];
+  }
+  load_tile(Lt, Li, NB);
+  __syncthreads();
+  for (int i = threadIdx.x; i < ncol * NB; i += blockDim.x) {
+    int t = i / NB, r = i - t * NB;
+    float s = 0.f;
+    for (int k = 0; k <= r; ++k) s += Lt[r * LDT + k] * rk[t][k];
+    yk[t][r] = s;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    float* Yl = Y + (size_t)l * ncol * Np;
+    for (int i = threadIdx.x; i < ncol * NB; i += blockDim.x) {
+      int t = i / NB, r = i - t * NB;
+      Yl[(size_t)t * Np + kb * NB + r] = yk[t][r];
+    }
+  }
+  const int ib = kb + 1 + blockIdx.x;
+  if (ib * NB >= Np) return;
+  load_tile(Lt, A + (size_t)l * Np * Np + (size_t)ib * NB * Np + kb * NB, Np);
+  __syncthreads();
+  for (int i = threadIdx.x; i < ncol * NB; i += blockDim.x) {
+    int t = i / NB, r = i - t * NB;
+    float s = 0.f;
+    for (int k = 0; k < NB; ++k) s += Lt[r * LDT + k] * yk[t][k];
+    Rl[(size_t)t * Np + ib * NB + r] -= s;
+  }
+}
+
+// Backward step kb: x_kb = inv(L_kk)^T y_kb (block 0 writes X); rows jb < kb: y_jb -= L[kb][jb]^T x_kb.
+__global__ __launch_bounds__(256) void k_bwd_step(const float* __restrict__ A, int Np, int kb,
+                                                  const float* __restrict__ Linv, float* __restrict__ Yv,
+                                                  float* __restrict__ X, int ncol) {
+  __shared__ float Lt[NB * LDT];
+  __shared__ float yk[32][NB];
+  __shared__ float xk[32][NB];
+  const int l = blockIdx.y;
+  const float* Li = Linv + ((size_t)l * (Np / NB) + kb) * NB * NB;
+  float* Yl = Yv + (size_t)l * ncol * Np;
+  for (int i = threadIdx.x; i < ncol * NB; i += blockDim.x) {
+    int t = i / NB, r = i - t * NB;
+    yk[t][r] = Yl[(size_t)t * Np + kb * NB + r];
+  }
+  load_tile(Lt, Li, NB);
+  __syncthreads();
+  for (int i = threadIdx.x; i < ncol * NB; i += blockDim.x) {
+    int t = i / NB, r = i - t * NB;
+    float s = 0.f;
+    for (int k = r; k < NB; ++k) s += Lt[k * LDT + r] * yk[t][k];
+    xk[t][r] = s;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    float* Xl = X + (size_t)l * ncol * Np;
+    for (int i = threadIdx.x; i < ncol * NB; i += blockDim.x) {
+      int t = i / NB, r = i - t * NB;
+      Xl[(size_t)t * Np + kb * NB + r] = xk[t][r];
+    }
+  }
+  const int jb = blockIdx.x;
+  if (jb >= kb) return;
+  load_tile(Lt, A + (size_t)l * Np * Np + (size_t)kb * NB * Np + jb * NB, Np);
+  __syncthreads();
+  for (int i = threadIdx.x; i < ncol * NB; i += blockDim.x) {
+    int t = i / NB, r = i - t * NB;
+    float s = 0.f;
+    for (int k = 0; k < NB; ++k) s += Lt[k * LDT + r] * xk[t][k];
+    Yl[(size_t)t * Np + jb * NB + r] -= s;
+  }
+}
+
+// ------------------------------------------------------------------ FP64 residual
+// Rres[l][t] = Bre[t] - (H64 + lambda_l diag(preal)) X[l][t], for all (l, t) at once:
+// one FP64 GEMM H64 (Np x Np) times X (Np x ncolsTotal) on MFMA (v_mfma_f64_16x16x4f64,
+// same lane layout as the FP32 16x16x4 instruction), then the diagonal and the
+// subtraction.  Column c of X/Rres is (l, t) with l = c / ntgt.
+constexpr int GT = 64;  // output tile rows/cols
+constexpr int GK = 16;  // k chunk
+__global__ __launch_bounds__(256) void k_resid64(const double* __restrict__ H, int N, int Np,
+                                                 const double* __restrict__ X, int ncols, int ntgt,
+                                                 int rhs_per_col,
+                                                 const double* __restrict__ Bre, const double* __restrict__ preal,
+                                                 const double* __restrict__ lams, double* __restrict__ Rres) {
+  __shared__ double Hs[GT][GK + 1];
+  __shared__ double Xs[GT][GK + 1];   // Xs[col][k]
+  const int row0 = blockIdx.x * GT, col0 = blockIdx.y * GT;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+  const int li = lane & 15, lk = lane >> 4;
+  doublex4 acc[2][2] = {};
+  for (int k0 = 0; k0 < Np; k0 += GK) {
+    for (int i = threadIdx.x; i < GT * GK; i += blockDim.x) {
+      int r = i / GK, k = i - r * GK;
+      Hs[r][k] = H[(size_t)(row0 + r) * Np + k0 + k];
+      int c = col0 + r;
+      Xs[r][k] = (c < ncols) ? X[(size_t)c * Np + k0 + k] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < GK; k += 4) {
+      double a0 = Hs[r0 + li][k + lk], a1 = Hs[r0 + 16 + li][k + lk];
+      double b0 = Xs[c0 + li][k + lk], b1 = Xs[c0 + 16 + li][k + lk];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int r = row0 + r0 + rb * 16 + 4 * (lane >> 4) + v;
+        int c = col0 + c0 + cb * 16 + (lane & 15);
+        if (c >= ncols) continue;
+        int l = c / ntgt, t = c - l * ntgt;
+        double xv = X[(size_t)c * Np + r];
+        double ax = acc[rb][cb][v] + (r < N ? lams[l] * preal[r] * xv : 0.0);
+        double bv = (r < N) ? Bre[(size_t)(rhs_per_col ? c : t) * Np + r] : 0.0;
+        Rres[(size_t)c * Np + r] = bv - ax;
+      }
+}
+
+// Column norms squared of Rres and of the right-hand sides (per column), FP64.
+__global__ __launch_bounds__(256) void k_colnorm2(const double* __restrict__ V, int Np, double* __restrict__ out) {
+  __shared__ double part[256];
+  const double* v = V + (size_t)blockIdx.x * Np;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < Np; i += blockDim.x) s += v[i] * v[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = part[0];
+}
+
+__global__ void k_d2f(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+__global__ void k_axpy_f2d(const float* __restrict__ a, double* __restrict__ b, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] += (double)a[i];
+}
+__global__ void k_rep_rhs(const double* __restrict__ Bre, int Np, int ntgt, int nlam, double* __restrict__ R) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t tot = (int64_t)nlam * ntgt * Np;
+  if (i >= tot) return;
+  int64_t c = i / Np;
+  int t = (int)(c % ntgt);
+  R[i] = Bre[(size_t)t * Np + (i - c * Np)];
+}
+
+}  // namespace fk
+
+// ==================================================================== host drivers
+namespace fk {
+
+static int round64(int n) { return (n + NB - 1) / NB * NB; }
+
+SolveLayout solve_layout(int N, int nlam, int ntgt, void* base, size_t cap) {
+  SolveLayout s;
+  s.N = N;
+  s.Np = round64(N);
+  s.nlam = nlam;
+  s.ntgt = ntgt;
+  const size_t Np = s.Np;
+  const size_t nc = (size_t)nlam * ntgt;
+  Carve cv(base, cap);
+  s.H64 = cv.take<double>(Np * Np);
+  s.A32 = cv.take<float>((size_t)nlam * Np * Np);
+  s.Linv = cv.take<float>((size_t)nlam * Np * NB);
+  s.preal = cv.take<double>(Np);
+  s.lams = cv.take<double>(nlam);
+  s.Bre = cv.take<double>((size_t)ntgt * Np);
+  s.X64 = cv.take<double>(nc * Np);
+  s.R64 = cv.take<double>(nc * Np);
+  s.U64 = cv.take<double>(nc * Np);
+  s.G64 = cv.take<double>(nc * Np);
+  s.R32 = cv.take<float>(nc * Np);
+  s.Y32 = cv.take<float>(nc * Np);
+  s.D32 = cv.take<float>(nc * Np);
+  s.norms = cv.take<double>(2 * nc + nlam + 64);
+  s.Hv = cv.take<double>(Np * Np);
+  s.Bv = cv.take<double>((size_t)ntgt * Np);
+  s.pcx = cv.take<double>((size_t)N);
+  s.bytes = cv.off + 256;
+  return s;
+}
+
+// Factor A32[l] = L L^T for every lambda (blocked, right-looking).
+static fk_status factor_all(fk_ctx* ctx, const SolveLayout& s) {
+  const int nb = s.Np / NB;
+  for (int kb = 0; kb < nb; ++kb) {
+    hipLaunchKernelGGL(k_potrf_diag, dim3(s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv, ctx->flags);
+    const int rem = nb - kb - 1;
+    if (rem > 0) {
+      hipLaunchKernelGGL(k_trsm_panel, dim3(rem, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv);
+      hipLaunchKernelGGL(k_syrk_update, dim3(rem * (rem + 1) / 2, s.nlam), dim3(256), 0, ctx->stream, s.A32,
+                         s.Np, kb);
+    }
+  }
+  FK_HIP(hipGetLastError());
+  return FK_OK;
+}
+
+// D32 = A^-1 R32 per lambda (ncol = ntgt columns each), through Y32.
+static fk_status trsm_all(fk_ctx* ctx, const SolveLayout& s, float* R, float* Y, float* X) {
+  const int nb = s.Np / NB;
+  for (int kb = 0; kb < nb; ++kb) {
+    int g = std::max(1, nb - kb - 1);
+    hipLaunchKernelGGL(k_fwd_step, dim3(g, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv, R, Y,
+                       s.ntgt);
+  }
+  for (int kb = nb - 1; kb >= 0; --kb) {
+    int g = std::max(1, kb);
+    hipLaunchKernelGGL(k_bwd_step, dim3(g, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv, Y, X,
+                       s.ntgt);
+  }
+  FK_HIP(hipGetLastError());
+  return FK_OK;
+}
+
+// Solve (H64 + lambda diag(preal)) X = RHS for all (lambda, target) with FP32
+// factors and FP64 refinement.  RHS given per target (Bre) or per column (rhs_cols).
+// Returns the number of refinement steps and the worst relative residual.
+static fk_status refine_solve(fk_ctx* ctx, const SolveLayout& s, const double* rhs_cols, double* X,
+                              int* iters_out, double* resid_out, int* bad_out) {
+  const int64_t tot = (int64_t)s.nlam * s.ntgt * s.Np;
+  const int nc = s.nlam * s.ntgt;
+  const int thr = 256;
+  const int blocks = (int)((tot + thr - 1) / thr);
+  // R64 = rhs
+  if (rhs_cols) {
+    FK_HIP(hipMemcpyAsync(s.R64, rhs_cols, sizeof(double) * tot, hipMemcpyDeviceToDevice, ctx->stream));
+  } else {
+    hipLaunchKernelGGL(k_rep_rhs, dim3(blocks), dim3(thr), 0, ctx->stream, s.Bre, s.Np, s.ntgt, s.nlam, s.R64);
+  }
+  FK_HIP(hipMemsetAsync(X, 0, sizeof(double) * tot, ctx->stream));
+  // norms of the right-hand sides
+  hipLaunchKernelGGL(k_colnorm2, dim3(nc), dim3(256), 0, ctx->stream, s.R64, s.Np, s.norms + nc);
+  const int maxit = ctx->opt.max_refine;
+  const double tol = ctx->opt.refine_tol;
+  std::vector<double> nh(2 * nc);
+  int it = 0;
+  double worst = 0.0;
+  int bad = -1;
+  for (;; ++it) {
+    hipLaunchKernelGGL(k_d2f, dim3(blocks), dim3(thr), 0, ctx->stream, s.R64, s.R32, tot);
+    fk_status st = trsm_all(ctx, s, s.R32, s.Y32, s.D32);
+    if (st != FK_OK) return st;
+    hipLaunchKernelGGL(k_axpy_f2d, dim3(blocks), dim3(thr), 0, ctx->stream, s.D32, X, tot);
+    // R64 = rhs - A X
+    hipLaunchKernelGGL(k_resid64, dim3(s.Np / GT, (nc + GT - 1) / GT), dim3(256), 0, ctx->stream, s.H64, s.N,
+                       s.Np, X, nc, s.ntgt, rhs_cols ? 1 : 0, rhs_cols ? rhs_cols : s.Bre, s.preal, s.lams,
+                       s.R64);
+    FK_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_colnorm2, dim3(nc), dim3(256), 0, ctx->stream, s.R64, s.Np, s.norms);
+    FK_HIP(hipMemcpyAsync(nh.data(), s.norms, sizeof(double) * 2 * nc, hipMemcpyDeviceToHost, ctx->stream));
+    FK_HIP(hipStreamSynchronize(ctx->stream));
+    worst = 0.0;
+    bad = -1;
+    for (int c = 0; c < nc; ++c) {
+      double rel = nh[nc + c] > 0 ? std::sqrt(nh[c] / nh[nc + c]) : std::sqrt(nh[c]);
+      if (!(rel <= worst)) {
+        worst = rel;
+        bad = c / s.ntgt;
+      }
+    }
+    if (worst <= tol || it >= maxit) break;
+  }
+  *iters_out = it;
+  *resid_out = worst;
+  *bad_out = bad;
+  return worst <= tol ? FK_OK : FK_ENOCONV;
+}
+
+fk_status solve_impl(fk_ctx* ctx, const SolveProblem& P, const SolveLayout& s, double* theta_out,
+                     fk_fit_info* info) {
+  const int N = s.N, Np = s.Np;
+  const int L = P.L;
+  hipEvent_t* ev = ctx->ev;
+  FK_HIP(hipEventRecord(ev[5], ctx->stream));
+  // penalty weights (complex modes) -> device, real-form weights
+  FK_HIP(hipMemcpyAsync(s.pcx, P.p.data(), sizeof(double) * N, hipMemcpyHostToDevice, ctx->stream));
+  FK_HIP(hipMemcpyAsync(s.lams, P.lams.data(), sizeof(double) * s.nlam, hipMemcpyHostToDevice, ctx->stream));
+  FK_HIP(hipMemsetAsync(s.preal, 0, sizeof(double) * Np, ctx->stream));
+  hipLaunchKernelGGL(k_real_weights, dim3((N + 255) / 256), dim3(256), 0, ctx->stream, s.pcx, N, L, s.preal);
+  // FP64 real-form Gram (+ dense lambda-independent penalty)
+  const int64_t tot2 = (int64_t)Np * Np;
+  const int gb = (int)((tot2 + 255) / 256);
+  if (P.kind == SolveProblem::kToeplitz) {
+    ToeplitzQ q{P.M, P.m, P.d};
+    hipLaunchKernelGGL(k_assemble_real<ToeplitzQ>, dim3(gb), dim3(256), 0, ctx->stream, q, N, L, Np, s.H64);
+  } else if (P.kind == SolveProblem::kToeplitzHeat) {
+    using HQ = SumQ<ToeplitzQ, HeatQ>;
+    HQ q{ToeplitzQ{P.M, P.m, P.d}, HeatQ{P.m, P.mu, P.lo[0], P.hi[0], P.lo[1], P.hi[1]}};
+    hipLaunchKernelGGL(k_assemble_real<HQ>, dim3(gb), dim3(256), 0, ctx->stream, q, N, L, Np, s.H64);
+  } else {
+    DenseQ q{P.B, N};
+    hipLaunchKernelGGL(k_assemble_real<DenseQ>, dim3(gb), dim3(256), 0, ctx->stream, q, N, L, Np, s.H64);
+  }
+  hipLaunchKernelGGL(k_make_a32, dim3(gb, s.nlam), dim3(256), 0, ctx->stream, s.H64, s.preal, s.lams, N, Np,
+                     s.A32);
+  hipLaunchKernelGGL(k_rhs_real, dim3((Np + 255) / 256, s.ntgt), dim3(256), 0, ctx->stream, P.b, N, L, Np,
+                     s.ntgt, s.Bre);
+  FK_HIP(hipGetLastError());
+  FK_HIP(hipEventRecord(ev[6], ctx->stream));
+  fk_status st = factor_all(ctx, s);
+  if (st != FK_OK) return st;
+  FK_HIP(hipEventRecord(ev[7], ctx->stream));
+  st = read_flags(ctx);
+  if (st != FK_OK) {
+    if (info) info->bad_index = ctx->flags_host[kFlagNotPD + 1];
+    return st;
+  }
+  int iters = 0, bad = -1;
+  double resid = 0.0;
+  st = refine_solve(ctx, s, nullptr, s.X64, &iters, &resid, &bad);
+  hipLaunchKernelGGL(k_theta_from_real, dim3((N + 255) / 256, s.nlam * s.ntgt), dim3(256), 0, ctx->stream, s.X64,
+                     N, L, Np, s.ntgt, theta_out);
+  FK_HIP(hipGetLastError());
+  FK_HIP(hipEventRecord(ev[8], ctx->stream));
+  FK_HIP(hipEventSynchronize(ev[8]));
+  if (info) {
+    info->refine_iters = iters;
+    info->resid_rel = resid;
+    if (st != FK_OK) info->bad_index = bad;
+    float a = 0, f = 0, so = 0;
+    hipEventElapsedTime(&a, ev[5], ev[6]);
+    hipEventElapsedTime(&f, ev[6], ev[7]);
+    hipEventElapsedTime(&so, ev[7], ev[8]);
+    info->t_assemble_ms = a;
+    info->t_factor_ms = f;
+    info->t_solve_ms = so;
+  }
+  return st;
+}
+
+// ------------------------------------------------------------------ held-out loss and backward
+
+// out[c] = x_c . v_c  (dot products of matching columns)
+__global__ __launch_bounds__(256) void k_coldot(const double* __restrict__ A, const double* __restrict__ B,
+                                                int Np, int bstride_cols, int ntgt, double* __restrict__ out) {
+  __shared__ double part[256];
+  const int c = blockIdx.x;
+  const double* a = A + (size_t)c * Np;
+  const double* b = B + (size_t)(bstride_cols ? c : (c % ntgt)) * Np;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < Np; i += blockDim.x) s += a[i] * b[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[c] = part[0];
+}
+
+__global__ void k_mse_combine(const double* __restrict__ xGx, const double* __restrict__ bx,
+                              const double* __restrict__ yv2, int nc, int ntgt, double* __restrict__ mse) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  mse[c] = xGx[c] - 2.0 * bx[c] + yv2[c % ntgt];
+}
+
+// G64[c] = Hv X[c] - Bv[t]   (gradient direction g in real form)
+// (uses k_resid64 with lambda = 0:  Rres = Bv - Hv X  -> negate)
+__global__ void k_negate(double* __restrict__ v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = -v[i];
+}
+
+fk_status heldout_mse_impl(fk_ctx* ctx, const SolveLayout& s, int d, int m, const double* Mv, const double* bv,
+                           const double* yv2, double* mse) {
+  const int N = s.N, Np = s.Np, L = (int)std::lround(std::pow((double)N, 1.0 / d));
+  const int64_t tot2 = (int64_t)Np * Np;
+  const int gb = (int)((tot2 + 255) / 256);
+  ToeplitzQ q{Mv, m, d};
+  hipLaunchKernelGGL(k_assemble_real<ToeplitzQ>, dim3(gb), dim3(256), 0, ctx->stream, q, N, L, Np, s.Hv);
+  hipLaunchKernelGGL(k_rhs_real, dim3((Np + 255) / 256, s.ntgt), dim3(256), 0, ctx->stream, bv, N, L, Np, s.ntgt,
+                     s.Bv);
+  const int nc = s.nlam * s.ntgt;
+  // zero "lambda" for the validation product: reuse norms scratch as a zero lambda array
+  FK_HIP(hipMemsetAsync(s.norms, 0, sizeof(double) * (2 * nc + s.nlam + 64), ctx->stream));
+  // R = Bv - Hv X   (lambda = 0 via a zero lambda array of length nlam in norms[2nc..])
+  hipLaunchKernelGGL(k_resid64, dim3(Np / GT, (nc + GT - 1) / GT), dim3(256), 0, ctx->stream, s.Hv, N, Np, s.X64,
+                     nc, s.ntgt, 0, s.Bv, s.preal, s.norms + 2 * nc, s.G64);
+  const int64_t tot = (int64_t)nc * Np;
+  hipLaunchKernelGGL(k_negate, dim3((tot + 255) / 256), dim3(256), 0, ctx->stream, s.G64, tot);
+  // xGx = x.(Hv x) = x.(g + bv) ; bx = bv.x
+  hipLaunchKernelGGL(k_coldot, dim3(nc), dim3(256), 0, ctx->stream, s.X64, s.G64, Np, 1, s.ntgt, s.norms);
+  hipLaunchKernelGGL(k_coldot, dim3(nc), dim3(256), 0, ctx->stream, s.X64, s.Bv, Np, 0, s.ntgt, s.norms + nc);
+  // mse = x.g + x.bv - 2 x.bv + yv2 = x.g - x.bv + yv2
+  hipLaunchKernelGGL(k_mse_combine, dim3((nc + 255) / 256), dim3(256), 0, ctx->stream, s.norms, s.norms + nc, yv2,
+                     nc, s.ntgt, mse);
+  FK_HIP(hipGetLastError());
+  (void)L;
+  return FK_OK;
+}
+
+// grad_loglam[l] = sum_t gm[l,t] (-2 lambda_l) u.(preal o x);  grad_p (complex modes) likewise.
+__global__ __launch_bounds__(256) void k_grad_loglam(const double* __restrict__ U, const double* __restrict__ X,
+                                                     const double* __restrict__ preal, const double* __restrict__ lams,
+                                                     const double* __restrict__ gm, int Np, int ntgt,
+                                                     double* __restrict__ out) {
+  __shared__ double part[256];
+  const int l = blockIdx.x;
+  double s = 0.0;
+  for (int t = 0; t < ntgt; ++t) {
+    const double* u = U + ((size_t)l * ntgt + t) * Np;
+    const double* x = X + ((size_t)l * ntgt + t) * Np;
+    double g = gm[l * ntgt + t];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < Np; i += blockDim.x) a += u[i] * preal[i] * x[i];
+    s += g * a;
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[l] = -2.0 * lams[l] * part[0];
+}
+
+__global__ void k_grad_p(const double* __restrict__ U, const double* __restrict__ X, const double* __restrict__ lams,
+                         const double* __restrict__ gm, int N, int L, int Np, int nlam, int ntgt,
+                         double* __restrict__ gp) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  int ty, k, nk;
+  real_to_complex(r, L, &ty, &k, &nk);
+  if (ty == 2) return;
+  double s = 0.0;
+  for (int l = 0; l < nlam; ++l)
+    for (int t = 0; t < ntgt; ++t) {
+      const size_t o = ((size_t)l * ntgt + t) * Np;
+      double v = ty == 0 ? U[o + r] * X[o + r] : 0.5 * (U[o + r] * X[o + r] + U[o + r + 1] * X[o + r + 1]);
+      s += gm[l * ntgt + t] * (-2.0 * lams[l]) * v;
+    }
+  gp[k] = s;
+  if (ty == 1) gp[nk] = s;
+}
+
+__global__ void k_scale_cols_cplx(double* __restrict__ th, const double* __restrict__ gm, int N) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int c = blockIdx.y;
+  if (i >= 2 * N) return;
+  th[(size_t)c * 2 * N + i] *= gm[c];
+}
+
+fk_status backward_impl(fk_ctx* ctx, const SolveLayout& s, int d, const double* gm, double* grad_loglam,
+                        double* grad_p, double* grad_theta) {
+  const int N = s.N, Np = s.Np, L = (int)std::lround(std::pow((double)N, 1.0 / d));
+  const int nc = s.nlam * s.ntgt;
+  int iters = 0, bad = -1;
+  double resid = 0.0;
+  // u = A^-1 g for every (lambda, target): columns of G64 are the right-hand sides
+  fk_status st = refine_solve(ctx, s, s.G64, s.U64, &iters, &resid, &bad);
+  if (st != FK_OK && st != FK_ENOCONV) return st;
+  hipLaunchKernelGGL(k_grad_loglam, dim3(s.nlam), dim3(256), 0, ctx->stream, s.U64, s.X64, s.preal, s.lams, gm, Np,
+                     s.ntgt, grad_loglam);
+  if (grad_p)
+    hipLaunchKernelGGL(k_grad_p, dim3((N + 255) / 256), dim3(256), 0, ctx->stream, s.U64, s.X64, s.lams, gm, N, L,
+                       Np, s.nlam, s.ntgt, grad_p);
+  if (grad_theta) {
+    hipLaunchKernelGGL(k_theta_from_real, dim3((N + 255) / 256, nc), dim3(256), 0, ctx->stream, s.G64, N, L, Np,
+                       s.ntgt, grad_theta);
+    hipLaunchKernelGGL(k_scale_cols_cplx, dim3((2 * N + 255) / 256, nc), dim3(256), 0, ctx->stream, grad_theta, gm,
+                       N);
+  }
+  FK_HIP(hipGetLastError());
+  return st;
+}
+
+}  // namespace fk

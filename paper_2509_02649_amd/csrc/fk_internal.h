@@ -1,0 +1,125 @@
+// Internal declarations shared by the HIP translation units of libfastkernel.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+#include <map>
+#include <tuple>
+#include <vector>
+
+#include "../../include/fk.h"
+
+#define FK_HIP(call)                                                         \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess) return FK_EHIP;                                    \
+  } while (0)
+
+namespace fk {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kMaxW = 16;
+
+// Device error flags (one int array per context, reset at the start of a call).
+enum Flag { kFlagRange = 0, kFlagNaN = 1, kFlagNotPD = 2, kFlagCount = 8 };
+
+// Exponential-of-semicircle spreading plan for one dimension: grid size nf,
+// width w, shape beta, and the FP64 Fourier transform of the kernel at the
+// integer frequencies 0..K (deconvolution factors, host copy).
+struct EsPlan {
+  int nf = 0;
+  int w = 0;
+  int K = 0;          // largest |frequency| needed
+  double beta = 0.0;
+  double err = 0.0;   // estimated worst-case relative aliasing error
+  std::vector<double> phihat;  // size K+1
+};
+
+EsPlan make_es_plan(int K, double eps);
+
+// Workspace carving: bump allocator over the caller's buffer.
+struct Carve {
+  char* base;
+  size_t off = 0;
+  size_t cap;
+  Carve(void* b, size_t c) : base(static_cast<char*>(b)), cap(c) {}
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = reinterpret_cast<T*>(base ? base + off : nullptr);
+    off += count * sizeof(T);
+    return p;
+  }
+  bool ok() const { return off <= cap; }
+};
+
+// Workspace layout of the dense stage (fixed from N, nlam, ntgt, at the start
+// of the caller's workspace so that later calls on the same workspace find it).
+struct SolveLayout {
+  int N = 0, Np = 0, nlam = 0, ntgt = 0;
+  double* H64 = nullptr;   // Np x Np real-form Gram (+ dense penalty), FP64
+  float* A32 = nullptr;    // nlam x Np x Np FP32 matrices / factors
+  float* Linv = nullptr;   // nlam x (Np/64) x 64 x 64 inverses of diagonal blocks
+  double* preal = nullptr; // Np real-form diagonal weights
+  double* lams = nullptr;  // nlam
+  double* Bre = nullptr;   // ntgt x Np real right-hand sides
+  double* X64 = nullptr;   // nlam x ntgt x Np solutions (real form)
+  double* R64 = nullptr;   // residuals
+  double* U64 = nullptr;   // adjoint solutions
+  double* G64 = nullptr;   // held-out gradient directions
+  float* R32 = nullptr;
+  float* Y32 = nullptr;
+  float* D32 = nullptr;
+  double* norms = nullptr;
+  double* Hv = nullptr;    // held-out real-form Gram
+  double* Bv = nullptr;    // held-out real right-hand sides
+  double* pcx = nullptr;   // N complex-mode weights
+  size_t bytes = 0;
+};
+SolveLayout solve_layout(int N, int nlam, int ntgt, void* base, size_t cap);
+
+struct SolveProblem {
+  enum Kind { kToeplitz = 0, kToeplitzHeat = 1, kDense = 2 } kind = kToeplitz;
+  const double* M = nullptr;  // generator (Toeplitz kinds)
+  const double* B = nullptr;  // dense complex matrix (kDense)
+  const double* b = nullptr;  // complex right-hand sides ntgt x N
+  int m = 0, d = 0, L = 0;    // L: complex modes per real-form block
+  std::vector<double> p;      // complex-mode diagonal weights (N)
+  std::vector<double> lams;   // nlam
+  double mu = 0, lo[2] = {0, 0}, hi[2] = {0, 0};
+};
+fk_status solve_impl(fk_ctx* ctx, const SolveProblem& P, const SolveLayout& s, double* theta_out,
+                     fk_fit_info* info);
+fk_status heldout_mse_impl(fk_ctx* ctx, const SolveLayout& s, int d, int m, const double* Mv, const double* bv,
+                           const double* yv2, double* mse);
+fk_status backward_impl(fk_ctx* ctx, const SolveLayout& s, int d, const double* gm, double* grad_loglam,
+                        double* grad_p, double* grad_theta);
+fk_status reset_flags(fk_ctx* ctx);
+
+}  // namespace fk
+
+struct fk_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  fk_options opt{};
+  int* flags = nullptr;           // device, fk::kFlagCount ints
+  int* flags_host = nullptr;      // pinned host mirror
+  hipEvent_t ev[16] = {};
+  // cached deconvolution tables keyed by (K, eps bits)
+  std::map<std::pair<int, uint64_t>, std::pair<fk::EsPlan, double*>> es_cache;
+};
+
+namespace fk {
+// Returns the ES plan and a device copy of its phihat table (owned by ctx).
+fk_status get_es_plan(fk_ctx* ctx, int K, EsPlan* plan, const double** d_phihat);
+fk_status finish(fk_ctx* ctx, fk_status st, fk_fit_info* info);
+fk_status read_flags(fk_ctx* ctx);
+
+// Type-1 stage.  Computes c_c[q] = sum_j w_cj exp(-i q.x_j) for |q_a| <= K on C
+// channels (channel 0 has weight 1 when `ones_channel`), written as complex128
+// [C][(2K+1)^d]. Used by fk_gram and the additive path.
+size_t type1_workspace(int d, int64_t n, int nw, int K, double eps);
+fk_status type1(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int64_t xstride,
+                int nw, const void* Y, int K, double sign_scale, double* out,
+                Carve& cv, fk_fit_info* info);
+}  // namespace fk

@@ -1,0 +1,332 @@
+// Type-2 non-uniform FFT (prediction) and the on-device synthetic-input generator.
+//
+// Prediction evaluates the estimator f_theta(x) = sum_k theta_k exp(+i k.x)
+// (Sec. 2.1) at new points: the coefficients are divided by the kernel's
+// Fourier transform, placed on an oversampled grid, inverse-FFT'd in FP64, and
+// each point gathers its w^d grid neighbours weighted by the same
+// exponential-of-semicircle kernel as the type-1 spread.  Only the real part is
+// kept (a real estimator has Hermitian-symmetric theta).
+//   Re f(x) ~= sum_l Re(g_l) phi(l - u),  g_l = sum_q (-1)^q theta_q / Phihat(q h) e^{2 pi i q l / nf}.
+#include "fk_internal.h"
+
+#include <cmath>
+#include <cstring>
+
+namespace fk {
+
+// Inverse DFT of one line with pruned input frequencies q = -K..K:
+//   out[l] = sum_q in[q + K] * f(q) * e^{+2 pi i q l / nf},
+// f(q) = (-1)^q / phihat[|q|] when phihat != nullptr, else 1.
+// Input elements (complex) at in + line_in + (q+K)*istride; output complex (or
+// real part only, when oreal) at out + line_out + l*ostride.
+__global__ __launch_bounds__(256) void k_ifft_line(const double* __restrict__ in, int64_t istride,
+                                                   int64_t in_outer, int64_t in_inner, int lines_inner, int K,
+                                                   const double* __restrict__ phihat, int nf, int logn,
+                                                   double* __restrict__ out, int oreal, int64_t ostride,
+                                                   int64_t out_outer, int64_t out_inner) {
+  __shared__ double re[1024], im[1024];
+  const int line = blockIdx.x;
+  const int lo = line / lines_inner, li = line - lo * lines_inner;
+  const double* src = in + 2 * (lo * in_outer + li * in_inner);
+  for (int i = threadIdx.x; i < nf; i += blockDim.x) {
+    re[i] = 0.0;
+    im[i] = 0.0;
+  }
+  __syncthreads();
+  for (int q = -K + (int)threadIdx.x; q <= K; q += blockDim.x) {
+    int l = q < 0 ? q + nf : q;
+    int r = __brev((unsigned)l) >> (32 - logn);
+    double f = 1.0;
+    if (phihat) {
+      int aq = q < 0 ? -q : q;
+      f = 1.0 / phihat[aq];
+      if (aq & 1) f = -f;
+    }
+    re[r] = src[2 * (q + K) * istride] * f;
+    im[r] = src[2 * (q + K) * istride + 1] * f;
+  }
+  __syncthreads();
+  for (int len = 2; len <= nf; len <<= 1) {
+    const int half = len >> 1;
+    for (int t = threadIdx.x; t < nf / 2; t += blockDim.x) {
+      int grp = t / half, pos = t - grp * half;
+      int i = grp * len + pos, j = i + half;
+      double sn, cs;
+      sincospi(2.0 * pos / len, &sn, &cs);
+      double vr = re[j] * cs - im[j] * sn;
+      double vi = re[j] * sn + im[j] * cs;
+      double ur = re[i], ui = im[i];
+      re[i] = ur + vr;
+      im[i] = ui + vi;
+      re[j] = ur - vr;
+      im[j] = ui - vi;
+    }
+    __syncthreads();
+  }
+  double* dst = out + (lo * out_outer + li * out_inner) * (oreal ? 1 : 2);
+  for (int l = threadIdx.x; l < nf; l += blockDim.x) {
+    if (oreal) {
+      dst[l * ostride] = re[l];
+    } else {
+      dst[2 * l * ostride] = re[l];
+      dst[2 * l * ostride + 1] = im[l];
+    }
+  }
+}
+
+__global__ void k_d2f_grid(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+
+struct EsDev2 {
+  float beta;
+  float two_over_w;
+};
+
+__device__ __forceinline__ float es_eval2(float s, EsDev2 es) {
+  float z = s * es.two_over_w;
+  float r = fmaxf(1.0f - z * z, 0.0f);
+  return __expf(es.beta * (__fsqrt_rn(r) - 1.0f));
+}
+
+// Grid coordinate in FP64 -> window start i0 = ceil(u - w/2) and offset s0 = i0 - u.
+__device__ __forceinline__ bool window_of(double x, int nf, int w, int* i0, float* s0) {
+  const double two_pi = 6.283185307179586476925;
+  if (!(x == x) || x < -two_pi || x >= two_pi) return false;
+  if (x < -3.14159265358979323846) x += two_pi;
+  if (x >= 3.14159265358979323846) x -= two_pi;
+  double u = (x + 3.14159265358979323846) * ((double)nf / two_pi);
+  double c = ceil(u - 0.5 * w);
+  *i0 = (int)c;
+  *s0 = (float)(c - u);
+  return true;
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void k_interp(const float* __restrict__ grid, int d, int nf, int T,
+                                                const void* __restrict__ Xq, fk_dtype dt, int64_t nq, EsDev2 es,
+                                                float* __restrict__ out, int* flags) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nq) return;
+  auto ld = [&](int64_t idx) -> double {
+    return dt == FK_F64 ? static_cast<const double*>(Xq)[idx] : (double)static_cast<const float*>(Xq)[idx];
+  };
+  int i1, i2 = 0;
+  float s1, s2 = 0.f;
+  bool ok = window_of(ld(j), nf, W, &i1, &s1);
+  if (d == 2) ok = window_of(ld(nq + j), nf, W, &i2, &s2) && ok;
+  if (!ok) {
+    atomicOr(&flags[kFlagRange], 1);
+    for (int t = 0; t < T; ++t) out[(int64_t)t * nq + j] = __int_as_float(0x7fc00000);
+    return;
+  }
+  float k1[W], k2[W];
+#pragma unroll
+  for (int a = 0; a < W; ++a) {
+    k1[a] = es_eval2(s1 + (float)a, es);
+    k2[a] = d == 2 ? es_eval2(s2 + (float)a, es) : 1.f;
+  }
+  for (int t = 0; t < T; ++t) {
+    float acc = 0.f;
+    if (d == 1) {
+      const float* g = grid + (int64_t)t * nf;
+#pragma unroll
+      for (int a = 0; a < W; ++a) {
+        int l = i1 + a;
+        l = l < 0 ? l + nf : (l >= nf ? l - nf : l);
+        acc += g[l] * k1[a];
+      }
+    } else {
+      const float* g = grid + (int64_t)t * nf * nf;
+#pragma unroll
+      for (int a = 0; a < W; ++a) {
+        int l1 = i1 + a;
+        l1 = l1 < 0 ? l1 + nf : (l1 >= nf ? l1 - nf : l1);
+        const float* row = g + (int64_t)l1 * nf;
+        float ra = 0.f;
+#pragma unroll
+        for (int b = 0; b < W; ++b) {
+          int l2 = i2 + b;
+          l2 = l2 < 0 ? l2 + nf : (l2 >= nf ? l2 - nf : l2);
+          ra += row[l2] * k2[b];
+        }
+        acc += ra * k1[a];
+      }
+    }
+    out[(int64_t)t * nq + j] = acc;
+  }
+}
+
+static int ilog2i(int v) {
+  int r = 0;
+  while ((1 << r) < v) ++r;
+  return r;
+}
+
+static size_t predict_ws(int d, int m, int T) {
+  int nf = 16;
+  while (nf < 2 * (2 * m + 1)) nf <<= 1;
+  const int L = 2 * m + 1;
+  Carve cv(nullptr, 0);
+  if (d == 2) cv.take<double>((size_t)T * nf * L * 2);
+  cv.take<double>((size_t)T * (d == 2 ? (size_t)nf * nf : nf));
+  cv.take<float>((size_t)T * (d == 2 ? (size_t)nf * nf : nf));
+  return cv.off + 512;
+}
+
+}  // namespace fk
+
+using namespace fk;
+
+extern "C" fk_status fk_predict_workspace_size(fk_ctx* ctx, int d, int m, int ntheta, size_t* bytes) {
+  if (!bytes || (d != 1 && d != 2) || m < 1 || m > 64 || ntheta < 1 || ntheta > 4096) return FK_EINVAL;
+  *bytes = predict_ws(d, m, ntheta);
+  return FK_OK;
+}
+
+#define FK_W_SWITCH2(w, CALL)                        \
+  switch (w) {                                       \
+    case 4: { constexpr int WW = 4; CALL; } break;   \
+    case 5: { constexpr int WW = 5; CALL; } break;   \
+    case 6: { constexpr int WW = 6; CALL; } break;   \
+    case 7: { constexpr int WW = 7; CALL; } break;   \
+    case 8: { constexpr int WW = 8; CALL; } break;   \
+    case 9: { constexpr int WW = 9; CALL; } break;   \
+    case 10: { constexpr int WW = 10; CALL; } break; \
+    case 11: { constexpr int WW = 11; CALL; } break; \
+    case 12: { constexpr int WW = 12; CALL; } break; \
+    case 13: { constexpr int WW = 13; CALL; } break; \
+    case 14: { constexpr int WW = 14; CALL; } break; \
+    case 15: { constexpr int WW = 15; CALL; } break; \
+    case 16: { constexpr int WW = 16; CALL; } break; \
+    default: return FK_EINVAL;                       \
+  }
+
+extern "C" fk_status fk_predict(fk_ctx* ctx, int d, int m, int T, const double* theta, int64_t nq, fk_dtype dt,
+                                const void* Xq, float* out, void* ws, size_t ws_bytes) {
+  if (!ctx || !theta || !Xq || !out || (d != 1 && d != 2) || m < 1 || m > 64 || T < 1 || T > 4096 || nq < 1)
+    return FK_EINVAL;
+  if (dt != FK_F32 && dt != FK_F64) return FK_EINVAL;
+  if (!ws || ws_bytes < predict_ws(d, m, T)) return FK_ENOMEM;
+  FK_HIP(hipSetDevice(ctx->device));
+  EsPlan plan;
+  const double* phihat;
+  fk_status st = get_es_plan(ctx, m, &plan, &phihat);
+  if (st != FK_OK) return st;
+  st = reset_flags(ctx);
+  if (st != FK_OK) return st;
+  const int nf = plan.nf, logn = ilog2i(nf), L = 2 * m + 1;
+  Carve cv(ws, ws_bytes);
+  double* tmp = d == 2 ? cv.take<double>((size_t)T * nf * L * 2) : nullptr;
+  double* g64 = cv.take<double>((size_t)T * (d == 2 ? (size_t)nf * nf : nf));
+  float* g32 = cv.take<float>((size_t)T * (d == 2 ? (size_t)nf * nf : nf));
+  if (!cv.ok()) return FK_ENOMEM;
+  if (d == 1) {
+    // one line per target: theta[t][q + m] -> g64[t][l] (real part)
+    hipLaunchKernelGGL(k_ifft_line, dim3(T), dim3(256), 0, ctx->stream, theta, (int64_t)1, (int64_t)L, (int64_t)0,
+                       1, m, phihat, nf, logn, g64, 1, (int64_t)1, (int64_t)nf, (int64_t)0);
+  } else {
+    // pass A: for each (t, q2): line over q1 (stride L) -> tmp[t][l1][q2] (complex, stride L)
+    hipLaunchKernelGGL(k_ifft_line, dim3(T * L), dim3(256), 0, ctx->stream, theta, (int64_t)L, (int64_t)L * L,
+                       (int64_t)1, L, m, phihat, nf, logn, tmp, 0, (int64_t)L, (int64_t)nf * L, (int64_t)1);
+    // pass B: for each (t, l1): line over q2 (contiguous) -> g64[t][l1][l2] real part
+    hipLaunchKernelGGL(k_ifft_line, dim3(T * nf), dim3(256), 0, ctx->stream, tmp, (int64_t)1, (int64_t)L,
+                       (int64_t)0, 1, m, phihat, nf, logn, g64, 1, (int64_t)1, (int64_t)nf, (int64_t)0);
+  }
+  const int64_t gsz = (int64_t)T * (d == 2 ? (int64_t)nf * nf : nf);
+  hipLaunchKernelGGL(k_d2f_grid, dim3((gsz + 255) / 256), dim3(256), 0, ctx->stream, g64, g32, gsz);
+  EsDev2 es{(float)plan.beta, 2.0f / (float)plan.w};
+  const int blocks = (int)((nq + 255) / 256);
+  FK_W_SWITCH2(plan.w, hipLaunchKernelGGL(k_interp<WW>, dim3(blocks), dim3(256), 0, ctx->stream, g32, d, nf, T, Xq,
+                                          dt, nq, es, out, ctx->flags));
+  FK_HIP(hipGetLastError());
+  return read_flags(ctx);
+}
+
+// ------------------------------------------------------------------ Philox4x32-10 generator
+// Salmon et al., SC'11: ten rounds of (hi, lo) = M * c with the Weyl key schedule.
+
+__device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  for (int r = 0; r < 10; ++r) {
+    uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+struct Box16 {
+  double lo[16], hi[16];
+};
+
+__global__ void k_gen_uniform(uint64_t seed, int d, int64_t n, int64_t start, Box16 box, float* __restrict__ X) {
+  const double* lo = box.lo;
+  const double* hi = box.hi;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t j = (uint64_t)(i + start);
+  for (int g = 0; g < (d + 3) / 4; ++g) {
+    uint32_t c[4] = {(uint32_t)j, (uint32_t)(j >> 32), (uint32_t)(g == 0 ? 0 : 16 + g), 0u};
+    philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    for (int r = 0; r < 4; ++r) {
+      int a = 4 * g + r;
+      if (a >= d) break;
+      double u = (double)(c[r] >> 8) * 5.9604644775390625e-08;  // 2^-24
+      double span = __dadd_rn(hi[a], -lo[a]);
+      X[(int64_t)a * n + i] = (float)__dadd_rn(lo[a], __dmul_rn(span, u));
+    }
+  }
+}
+
+__global__ void k_gen_targets(uint64_t seed, int ntgt, int64_t n, int64_t start, const float* __restrict__ X,
+                              double sigma, float* __restrict__ Y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t j = (uint64_t)(i + start);
+  const double x1 = X[i], x2 = X[n + i];
+  const double c2 = cos(x2);
+  for (int t = 1; t <= ntgt; ++t) {
+    uint32_t c[4] = {(uint32_t)j, (uint32_t)(j >> 32), (uint32_t)t, 0u};
+    philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    double u1 = ((double)c[0] + 1.0) * 2.3283064365386963e-10;  // (0, 1]
+    double u2 = (double)c[1] * 2.3283064365386963e-10;          // [0, 1)
+    double z = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+    double v = sin((double)t * x1) * c2 + sigma * z;
+    Y[(int64_t)(t - 1) * n + i] = (float)v;
+  }
+}
+
+extern "C" fk_status fk_generate_uniform(fk_ctx* ctx, uint64_t seed, int d, int64_t n, int64_t start,
+                                         const double* lo, const double* hi, float* X) {
+  if (!ctx || !lo || !hi || !X || d < 1 || d > 16 || n < 1 || start < 0) return FK_EINVAL;
+  FK_HIP(hipSetDevice(ctx->device));
+  Box16 box;
+  for (int a = 0; a < 16; ++a) {
+    box.lo[a] = a < d ? lo[a] : 0.0;
+    box.hi[a] = a < d ? hi[a] : 0.0;
+  }
+  hipLaunchKernelGGL(k_gen_uniform, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, seed, d, n, start,
+                     box, X);
+  FK_HIP(hipGetLastError());
+  FK_HIP(hipStreamSynchronize(ctx->stream));
+  return FK_OK;
+}
+
+extern "C" fk_status fk_generate_targets(fk_ctx* ctx, uint64_t seed, int ntgt, int64_t n, int64_t start,
+                                         const float* X, double sigma, float* Y) {
+  if (!ctx || !X || !Y || ntgt < 1 || ntgt > 1024 || n < 1 || start < 0) return FK_EINVAL;
+  FK_HIP(hipSetDevice(ctx->device));
+  hipLaunchKernelGGL(k_gen_targets, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, seed, ntgt, n,
+                     start, X, sigma, Y);
+  FK_HIP(hipGetLastError());
+  FK_HIP(hipStreamSynchronize(ctx->stream));
+  return FK_OK;
+}

@@ -1,0 +1,690 @@
+// Type-1 non-uniform FFT on gfx950: exponential-of-semicircle spreading onto an
+// oversampled grid, FP64 FFT, deconvolution.
+//
+// What is computed (Sec. 2.3 of the paper, "Covariance vector" / "Covariance
+// matrix"): for C real weight channels w_c and points x_j on the torus,
+//     c_c[q] = sum_j w_cj exp(-i q.x_j),   |q_a| <= K.
+// Method (Barnett, Magland, af Klinteberg, SIAM J. Sci. Comput. 41(5), 2019):
+// with grid spacing h = 2 pi / nf and grid point l <-> x = -pi + l h, spread
+//     g_c[l] = sum_j w_cj phi(l - u_j),  u_j = (x_j + pi) / h,
+// phi(t) = psi(2 t / w), psi(z) = exp(beta (sqrt(1 - z^2) - 1)) on |z| <= 1, then
+//     c_c[q] ~= (-1)^q DFT(g_c)[q mod nf] / prod_a Phihat(q_a h),
+// Phihat(omega) = int phi(t) exp(-i omega t) dt (Poisson summation; the
+// aliased terms are the error, bounded here by the plan's error estimate).
+//
+// Design for MI355X:
+// * 1-D grids (<= 1024 points per channel) live whole in LDS: each workgroup
+//   streams a contiguous chunk of points (coalesced), accumulates FP32 partials
+//   with LDS float atomics and flushes them once into an FP64 global grid.
+// * 2-D grids (up to 512 x 512) do not fit in 160 KB of LDS, so points are
+//   counting-sorted by bin (a T x T tile of the grid): per-workgroup LDS
+//   histograms, a scan, and a scatter into bin-contiguous records
+//   (two 32-bit fixed-point grid coordinates + FP32 weights).  One workgroup
+//   per (bin, slice of the bin's points) then spreads into an LDS subgrid of
+//   (T + 2 ceil(w/2))^2 cells x C channels and flushes it with FP64 atomics.
+// * Grid coordinates are computed in FP64 and carried as fixed point (error
+//   <= 2^-(33 - log2 nf) grid units), so the phase error stays below 1e-7
+//   even at the highest frequency.
+// * The FFT and deconvolution run in FP64 (the grids are tiny).
+#include "fk_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace fk {
+
+// ------------------------------------------------------------------ plan (host)
+
+static double es_psi(double z, double beta) {
+  double r = 1.0 - z * z;
+  return r < 0 ? 0.0 : std::exp(beta * (std::sqrt(r) - 1.0));
+}
+
+// Gauss-Legendre nodes/weights on [-1, 1] (Newton on the Legendre recurrence).
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.resize(n);
+  w.resize(n);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      double dp = n * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    double dp = n * (z * p1 - p0) / (z * z - 1.0);
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// Phihat(omega) = (w/2) int_{-1}^{1} psi(z) cos(omega w z / 2) dz.
+static double es_phihat(double omega, int w, double beta, const std::vector<double>& gx,
+                        const std::vector<double>& gw) {
+  double s = 0.0;
+  for (size_t i = 0; i < gx.size(); ++i) s += gw[i] * es_psi(gx[i], beta) * std::cos(omega * w * gx[i] * 0.5);
+  return 0.5 * w * s;
+}
+
+// Worst case over sub-grid shifts of |sum_l phi(l - u) e^{-i omega (l-u)} - Phihat(omega)| / Phihat(omega)
+// for omega = q h, 0 <= q <= K.
+static double es_error(int nf, int K, int w, double beta, const std::vector<double>& gx,
+                       const std::vector<double>& gw) {
+  const double h = 2.0 * kPi / nf;
+  std::vector<double> ph(K + 1);
+  for (int q = 0; q <= K; ++q) ph[q] = es_phihat(q * h, w, beta, gx, gw);
+  double worst = 0.0;
+  const int nu = 24;
+  for (int iu = 0; iu <= nu; ++iu) {
+    double u = double(iu) / nu;
+    for (int q = 0; q <= K; q += std::max(1, K / 48)) {
+      double re = 0.0, im = 0.0;
+      for (int l = -w; l <= w + 1; ++l) {
+        double t = l - u;
+        double z = 2.0 * t / w;
+        if (std::fabs(z) > 1.0) continue;
+        double v = es_psi(z, beta);
+        re += v * std::cos(q * h * t);
+        im -= v * std::sin(q * h * t);
+      }
+      double e = std::hypot(re - ph[q], im) / std::fabs(ph[q]);
+      worst = std::max(worst, e);
+    }
+  }
+  return worst;
+}
+
+EsPlan make_es_plan(int K, double eps) {
+  // Fine grid: the smallest power of two with oversampling nf / (2K+1) >= 2.
+  EsPlan p;
+  p.K = K;
+  int nf = 16;
+  while (nf < 2 * (2 * K + 1)) nf <<= 1;
+  p.nf = nf;
+  std::vector<double> gx, gw;
+  gauss_legendre(160, gx, gw);
+  const double sigma = double(nf) / (2 * K + 1);
+  int best_w = kMaxW;
+  double best_beta = 2.3 * kMaxW, best_err = 1.0;
+  for (int w = 4; w <= kMaxW; ++w) {
+    // shape parameter: scan around the published heuristic beta ~ pi w (1 - 1/(2 sigma)) * 0.97
+    double b0 = 0.97 * kPi * w * (1.0 - 0.5 / sigma);
+    double bb = b0, be = 1.0;
+    for (int i = -6; i <= 6; ++i) {
+      double beta = b0 * (1.0 + 0.02 * i);
+      double e = es_error(nf, K, w, beta, gx, gw);
+      if (e < be) { be = e; bb = beta; }
+    }
+    if (be <= eps || w == kMaxW) {
+      best_w = w;
+      best_beta = bb;
+      best_err = be;
+      break;
+    }
+  }
+  p.w = best_w;
+  p.beta = best_beta;
+  p.err = best_err;
+  p.phihat.resize(K + 1);
+  const double h = 2.0 * kPi / nf;
+  for (int q = 0; q <= K; ++q) p.phihat[q] = es_phihat(q * h, p.w, p.beta, gx, gw);
+  return p;
+}
+
+fk_status get_es_plan(fk_ctx* ctx, int K, EsPlan* plan, const double** d_phihat) {
+  double eps = ctx->opt.eps > 0 ? ctx->opt.eps : 2e-7;
+  uint64_t bits;
+  std::memcpy(&bits, &eps, 8);
+  auto key = std::make_pair(K, bits);
+  auto it = ctx->es_cache.find(key);
+  if (it == ctx->es_cache.end()) {
+    EsPlan p = make_es_plan(K, eps);
+    double* d = nullptr;
+    FK_HIP(hipMalloc(&d, sizeof(double) * (K + 1)));
+    FK_HIP(hipMemcpy(d, p.phihat.data(), sizeof(double) * (K + 1), hipMemcpyHostToDevice));
+    it = ctx->es_cache.emplace(key, std::make_pair(p, d)).first;
+  }
+  *plan = it->second.first;
+  *d_phihat = it->second.second;
+  return FK_OK;
+}
+
+// ------------------------------------------------------------------ device helpers
+
+struct EsDev {
+  float beta;
+  float two_over_w;
+};
+
+__device__ __forceinline__ float es_eval(float s, EsDev es) {
+  // s: distance in grid units; |s| <= w/2 inside the support.
+  float z = s * es.two_over_w;
+  float r = fmaxf(1.0f - z * z, 0.0f);
+  return __expf(es.beta * (__fsqrt_rn(r) - 1.0f));
+}
+
+// Fold a coordinate onto [-pi, pi) and convert to a fixed-point grid
+// coordinate U = round((x + pi) / h * 2^fb).  Returns false (and sets flags)
+// for NaN or |x| outside [-2 pi, 2 pi).
+__device__ __forceinline__ bool to_fixed(double x, double scale, uint32_t nf_fix, uint32_t* U,
+                                         int* flags) {
+  if (!(x == x) || isinf(x)) {
+    atomicOr(&flags[kFlagNaN], 1);
+    return false;
+  }
+  const double two_pi = 6.283185307179586476925;
+  if (x < -two_pi || x >= two_pi) {
+    atomicOr(&flags[kFlagRange], 1);
+    return false;
+  }
+  if (x < -3.14159265358979323846) x += two_pi;
+  if (x >= 3.14159265358979323846) x -= two_pi;
+  double u = (x + 3.14159265358979323846) * scale;   // in [0, nf * 2^fb]
+  uint64_t v = (uint64_t)__double2ll_rn(u);
+  if (v >= nf_fix) v -= nf_fix;                       // x == pi - tiny rounding up to nf
+  *U = (uint32_t)v;
+  return true;
+}
+
+// Window start i0 = ceil(u - w/2) and first offset s0 = i0 - u (grid units) from
+// a fixed-point coordinate with fb fraction bits.
+__device__ __forceinline__ void window_start(uint32_t U, int fb, int w, int* i0, float* s0) {
+  int64_t V = (int64_t)U - ((int64_t)w << (fb - 1));
+  int64_t one = (int64_t)1 << fb;
+  int64_t c = (V >= 0) ? ((V + one - 1) >> fb) : -((-V) >> fb);
+  *i0 = (int)c;
+  *s0 = (float)((double)((c << fb) - (int64_t)U) * (1.0 / (double)one));
+}
+
+__device__ __forceinline__ double load_coord(const void* X, fk_dtype dt, int64_t idx) {
+  return dt == FK_F64 ? static_cast<const double*>(X)[idx] : (double)static_cast<const float*>(X)[idx];
+}
+__device__ __forceinline__ float load_weight(const void* Y, fk_dtype dt, int64_t idx) {
+  return dt == FK_F64 ? (float)static_cast<const double*>(Y)[idx] : static_cast<const float*>(Y)[idx];
+}
+
+// ------------------------------------------------------------------ 1-D spread (whole grid in LDS)
+// grid: gridDim.x workgroups over contiguous chunks of points.  LDS: C * nf floats.
+// Channel 0 carries weight 1 when ones != 0; channels ones..C-1 read Y rows.
+template <int W>
+__global__ __launch_bounds__(256) void k_spread_1d(const void* __restrict__ X, fk_dtype dt, int64_t n,
+                                                   const void* __restrict__ Y, int nw, int ones,
+                                                   int nf, int fb, double scale, EsDev es,
+                                                   double* __restrict__ grid, int* flags,
+                                                   int64_t chunk) {
+  extern __shared__ float lds[];
+  const int C = nw + ones;
+  for (int i = threadIdx.x; i < C * nf; i += blockDim.x) lds[i] = 0.f;
+  __syncthreads();
+  const int64_t beg = (int64_t)blockIdx.x * chunk;
+  const int64_t end = min(n, beg + chunk);
+  const uint32_t nf_fix = (uint32_t)nf << fb;
+  for (int64_t j = beg + threadIdx.x; j < end; j += blockDim.x) {
+    uint32_t U;
+    if (!to_fixed(load_coord(X, dt, j), scale, nf_fix, &U, flags)) continue;
+    int i0;
+    float s0;
+    window_start(U, fb, W, &i0, &s0);
+    float k[W];
+#pragma unroll
+    for (int a = 0; a < W; ++a) k[a] = es_eval(s0 + (float)a, es);
+    int base = i0 < 0 ? i0 + nf : i0;
+    if (ones) {
+#pragma unroll
+      for (int a = 0; a < W; ++a) {
+        int l = base + a;
+        l = l >= nf ? l - nf : l;
+        atomicAdd(&lds[l], k[a]);
+      }
+    }
+    for (int c = 0; c < nw; ++c) {
+      float wc = load_weight(Y, dt, (int64_t)c * n + j);
+      if (!(wc == wc) || isinf(wc)) { atomicOr(&flags[kFlagNaN], 1); continue; }
+      float* g = lds + (c + ones) * nf;
+#pragma unroll
+      for (int a = 0; a < W; ++a) {
+        int l = base + a;
+        l = l >= nf ? l - nf : l;
+        atomicAdd(&g[l], wc * k[a]);
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < C * nf; i += blockDim.x) {
+    float v = lds[i];
+    if (v != 0.f) atomicAdd(&grid[i], (double)v);
+  }
+}
+
+// ------------------------------------------------------------------ 2-D binned spread
+// Bins are T x T tiles of the nf x nf grid: nbx = nf / T bins per axis.
+
+__global__ __launch_bounds__(256) void k_bin_count(const void* __restrict__ X, fk_dtype dt, int64_t n,
+                                                   int64_t xstride, int nf, int fb, double scale,
+                                                   int tshift, int nbx, uint32_t* __restrict__ cnt,
+                                                   int nblk, int64_t chunk, int* flags) {
+  extern __shared__ uint32_t hist[];
+  const int nb = nbx * nbx;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  const int64_t beg = (int64_t)blockIdx.x * chunk;
+  const int64_t end = min(n, beg + chunk);
+  const uint32_t nf_fix = (uint32_t)nf << fb;
+  for (int64_t j = beg + threadIdx.x; j < end; j += blockDim.x) {
+    uint32_t U1, U2;
+    bool ok = to_fixed(load_coord(X, dt, j), scale, nf_fix, &U1, flags);
+    ok = to_fixed(load_coord(X, dt, xstride + j), scale, nf_fix, &U2, flags) && ok;
+    if (!ok) continue;
+    int b = ((U1 >> fb) >> tshift) * nbx + ((U2 >> fb) >> tshift);
+    atomicAdd(&hist[b], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) cnt[(int64_t)i * nblk + blockIdx.x] = hist[i];
+}
+
+// Exclusive scan of cnt[bin][0..nblk) in place, one workgroup per bin; bin totals out.
+__global__ __launch_bounds__(256) void k_scan_rows(uint32_t* __restrict__ cnt, int nblk,
+                                                   uint32_t* __restrict__ totals) {
+  __shared__ uint32_t part[256];
+  uint32_t* row = cnt + (int64_t)blockIdx.x * nblk;
+  const int per = (nblk + 255) / 256;
+  const int b0 = threadIdx.x * per;
+  uint32_t s = 0;
+  for (int i = 0; i < per; ++i)
+    if (b0 + i < nblk) s += row[b0 + i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[threadIdx.x] - s;
+  for (int i = 0; i < per; ++i)
+    if (b0 + i < nblk) {
+      uint32_t c = row[b0 + i];
+      row[b0 + i] = run;
+      run += c;
+    }
+  if (threadIdx.x == 255) totals[blockIdx.x] = part[255];
+}
+
+// Exclusive scan of the bin totals (nb <= 65536) by one workgroup; start[nb] = total.
+__global__ __launch_bounds__(1024) void k_scan_totals(const uint32_t* __restrict__ totals, int nb,
+                                                      uint64_t* __restrict__ start) {
+  __shared__ uint64_t part[1024];
+  const int per = (nb + 1023) / 1024;
+  const int b0 = threadIdx.x * per;
+  uint64_t s = 0;
+  for (int i = 0; i < per; ++i)
+    if (b0 + i < nb) s += totals[b0 + i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    uint64_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint64_t run = part[threadIdx.x] - s;
+  for (int i = 0; i < per; ++i)
+    if (b0 + i < nb) {
+      start[b0 + i] = run;
+      run += totals[b0 + i];
+    }
+  if (threadIdx.x == 1023) start[nb] = part[1023];
+}
+
+// Scatter points into bin-contiguous records [U1, U2, w_0 .. w_{nw-1}] (32-bit words).
+__global__ __launch_bounds__(256) void k_bin_scatter(const void* __restrict__ X, fk_dtype dt, int64_t n,
+                                                     int64_t xstride, const void* __restrict__ Y,
+                                                     int nw, int nf, int fb, double scale, int tshift,
+                                                     int nbx, const uint32_t* __restrict__ cnt,
+                                                     const uint64_t* __restrict__ start, int nblk,
+                                                     int64_t chunk, uint32_t* __restrict__ rec,
+                                                     int* flags) {
+  extern __shared__ uint32_t slot[];
+  const int nb = nbx * nbx;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) slot[i] = 0;
+  __syncthreads();
+  const int64_t beg = (int64_t)blockIdx.x * chunk;
+  const int64_t end = min(n, beg + chunk);
+  const uint32_t nf_fix = (uint32_t)nf << fb;
+  const int R = 2 + nw;
+  for (int64_t j = beg + threadIdx.x; j < end; j += blockDim.x) {
+    uint32_t U1, U2;
+    int dummy[kFlagCount];
+    (void)dummy;
+    bool ok = to_fixed(load_coord(X, dt, j), scale, nf_fix, &U1, flags);
+    ok = to_fixed(load_coord(X, dt, xstride + j), scale, nf_fix, &U2, flags) && ok;
+    if (!ok) continue;
+    int b = ((U1 >> fb) >> tshift) * nbx + ((U2 >> fb) >> tshift);
+    uint32_t r = atomicAdd(&slot[b], 1u);
+    uint64_t pos = start[b] + cnt[(int64_t)b * nblk + blockIdx.x] + r;
+    uint32_t* o = rec + pos * R;
+    o[0] = U1;
+    o[1] = U2;
+    for (int c = 0; c < nw; ++c) {
+      float wc = load_weight(Y, dt, (int64_t)c * n + j);
+      if (!(wc == wc) || isinf(wc)) {
+        atomicOr(&flags[kFlagNaN], 1);
+        wc = 0.f;
+      }
+      o[2 + c] = __float_as_uint(wc);
+    }
+  }
+}
+
+// One workgroup per (bin, slice).  LDS subgrid S x S cells x C channels,
+// cell-major ([cell][channel]) so the channels of one cell are adjacent.
+template <int W>
+__global__ __launch_bounds__(256) void k_spread_2d_binned(const uint32_t* __restrict__ rec, int nw,
+                                                          int ones, const uint64_t* __restrict__ start,
+                                                          int nbx, int T, int nf, int fb, EsDev es,
+                                                          int slices, double* __restrict__ grid) {
+  extern __shared__ float sub[];
+  constexpr int H = (W + 1) / 2;     // halo each side
+  const int S = T + 2 * H;
+  const int C = nw + ones;
+  const int b = blockIdx.x / slices;
+  const int sl = blockIdx.x - b * slices;
+  const uint64_t p0 = start[b], p1 = start[b + 1];
+  const uint64_t len = p1 - p0;
+  const uint64_t q0 = p0 + len * sl / slices;
+  const uint64_t q1 = p0 + len * (sl + 1) / slices;
+  if (q0 == q1) return;
+  for (int i = threadIdx.x; i < S * S * C; i += blockDim.x) sub[i] = 0.f;
+  __syncthreads();
+  const int bx = b / nbx, by = b - bx * nbx;
+  const int o1 = bx * T - H, o2 = by * T - H;   // subgrid origin (may be negative: periodic)
+  const int R = 2 + nw;
+  for (uint64_t j = q0 + threadIdx.x; j < q1; j += blockDim.x) {
+    const uint32_t* r = rec + j * R;
+    int i1, i2;
+    float s1, s2;
+    window_start(r[0], fb, W, &i1, &s1);
+    window_start(r[1], fb, W, &i2, &s2);
+    float k1[W], k2[W];
+#pragma unroll
+    for (int a = 0; a < W; ++a) {
+      k1[a] = es_eval(s1 + (float)a, es);
+      k2[a] = es_eval(s2 + (float)a, es);
+    }
+    const int l1 = i1 - o1, l2 = i2 - o2;      // in [0, S - W]
+    if (ones) {
+#pragma unroll
+      for (int a = 0; a < W; ++a) {
+        float* row = sub + ((l1 + a) * S + l2) * C;
+#pragma unroll
+        for (int c2 = 0; c2 < W; ++c2) atomicAdd(&row[c2 * C], k1[a] * k2[c2]);
+      }
+    }
+    for (int cg = 0; cg < nw; cg += 4) {
+      float wv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) wv[u] = (cg + u < nw) ? __uint_as_float(r[2 + cg + u]) : 0.f;
+      const int cn = min(4, nw - cg);
+#pragma unroll
+      for (int a = 0; a < W; ++a) {
+        float* row = sub + ((l1 + a) * S + l2) * C + ones + cg;
+#pragma unroll
+        for (int c2 = 0; c2 < W; ++c2) {
+          float kk = k1[a] * k2[c2];
+          float* cell = row + c2 * C;
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (u < cn) atomicAdd(&cell[u], wv[u] * kk);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // flush: periodic wrap into the FP64 global grid [C][nf][nf]
+  for (int i = threadIdx.x; i < S * S * C; i += blockDim.x) {
+    float v = sub[i];
+    if (v == 0.f) continue;
+    int c = i % C;
+    int cell = i / C;
+    int a = cell / S, bb = cell - a * S;
+    int g1 = o1 + a, g2 = o2 + bb;
+    g1 = g1 < 0 ? g1 + nf : (g1 >= nf ? g1 - nf : g1);
+    g2 = g2 < 0 ? g2 + nf : (g2 >= nf ? g2 - nf : g2);
+    atomicAdd(&grid[((int64_t)c * nf + g1) * nf + g2], (double)v);
+  }
+}
+
+// ------------------------------------------------------------------ FFT (FP64, radix-2, in LDS)
+// One workgroup transforms one line of length nf (power of two <= 1024) and
+// writes the pruned, deconvolved frequencies q = -K..K:
+//   out[line][q + K] = scale * (-1)^q / phihat[|q|] * sum_l in[l] e^{-2 pi i q l / nf}.
+// Input line `line` starts at in + line_off(line) with element stride `istride`
+// (complex elements when icomplex, else real doubles).
+__global__ __launch_bounds__(256) void k_fft_line(const double* __restrict__ in, int icomplex,
+                                                  int64_t istride, int64_t in_line_stride_outer,
+                                                  int64_t in_line_stride_inner, int lines_inner,
+                                                  int nf, int logn, const double* __restrict__ phihat,
+                                                  int K, double scale, double* __restrict__ out,
+                                                  int64_t ostride, int64_t out_line_stride_outer,
+                                                  int64_t out_line_stride_inner) {
+  __shared__ double re[1024], im[1024];
+  const int line = blockIdx.x;
+  const int lo = line / lines_inner, li = line - lo * lines_inner;
+  const double* src = in + (lo * in_line_stride_outer + li * in_line_stride_inner) * (icomplex ? 2 : 1);
+  for (int i = threadIdx.x; i < nf; i += blockDim.x) {
+    int r = __brev((unsigned)i) >> (32 - logn);
+    if (icomplex) {
+      re[r] = src[2 * i * istride];
+      im[r] = src[2 * i * istride + 1];
+    } else {
+      re[r] = src[i * istride];
+      im[r] = 0.0;
+    }
+  }
+  __syncthreads();
+  for (int len = 2; len <= nf; len <<= 1) {
+    const int half = len >> 1;
+    for (int t = threadIdx.x; t < nf / 2; t += blockDim.x) {
+      int grp = t / half, pos = t - grp * half;
+      int i = grp * len + pos, j = i + half;
+      double sn, cs;
+      sincospi(-2.0 * pos / len, &sn, &cs);
+      double vr = re[j] * cs - im[j] * sn;
+      double vi = re[j] * sn + im[j] * cs;
+      double ur = re[i], ui = im[i];
+      re[i] = ur + vr;
+      im[i] = ui + vi;
+      re[j] = ur - vr;
+      im[j] = ui - vi;
+    }
+    __syncthreads();
+  }
+  double* dst = out + (lo * out_line_stride_outer + li * out_line_stride_inner) * 2;
+  for (int q = -K + (int)threadIdx.x; q <= K; q += blockDim.x) {
+    int l = q < 0 ? q + nf : q;
+    int aq = q < 0 ? -q : q;
+    double f = scale / phihat[aq];
+    if (aq & 1) f = -f;
+    dst[2 * (q + K) * ostride] = re[l] * f;
+    dst[2 * (q + K) * ostride + 1] = im[l] * f;
+  }
+}
+
+// ------------------------------------------------------------------ host driver
+
+static int ilog2(int v) {
+  int r = 0;
+  while ((1 << r) < v) ++r;
+  return r;
+}
+
+struct BinGeom {
+  int T, tshift, nbx, nb, nblk;
+  int64_t chunk;
+};
+
+static BinGeom bin_geom(int nf, int C, int64_t n) {
+  BinGeom g;
+  g.T = (C > 8) ? 16 : 32;
+  if (g.T > nf) g.T = nf;
+  g.tshift = ilog2(g.T);
+  g.nbx = nf / g.T;
+  g.nb = g.nbx * g.nbx;
+  g.nblk = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (n + 8191) / 8192));
+  g.chunk = (n + g.nblk - 1) / g.nblk;
+  return g;
+}
+
+size_t type1_workspace(int d, int64_t n, int nw, int K, double eps) {
+  (void)eps;
+  int nf = 16;
+  while (nf < 2 * (2 * K + 1)) nf <<= 1;
+  const int C = nw + 1;
+  const int L = 2 * K + 1;
+  Carve cv(nullptr, 0);
+  if (d == 1) {
+    cv.take<double>((size_t)C * nf);
+  } else {
+    cv.take<double>((size_t)C * nf * nf);          // FP64 grid
+    cv.take<double>((size_t)C * nf * L * 2);        // row-FFT output
+    BinGeom g = bin_geom(nf, C, n);
+    cv.take<uint32_t>((size_t)g.nb * g.nblk);
+    cv.take<uint32_t>((size_t)g.nb);
+    cv.take<uint64_t>((size_t)g.nb + 1);
+    cv.take<uint32_t>((size_t)n * (2 + nw));
+  }
+  return cv.off + 256;
+}
+
+template <int W>
+static void launch_spread_1d(fk_ctx* ctx, int blocks, size_t lds, const void* X, fk_dtype dt, int64_t n,
+                             const void* Y, int nw, int nf, int fb, double scale, EsDev es, double* grid,
+                             int64_t chunk) {
+  hipLaunchKernelGGL(k_spread_1d<W>, dim3(blocks), dim3(256), lds, ctx->stream, X, dt, n, Y, nw, 1, nf,
+                     fb, scale, es, grid, ctx->flags, chunk);
+}
+
+template <int W>
+static void launch_spread_2d(fk_ctx* ctx, int blocks, size_t lds, const uint32_t* rec, int nw,
+                             const uint64_t* start, int nbx, int T, int nf, int fb, EsDev es, int slices,
+                             double* grid) {
+  hipLaunchKernelGGL(k_spread_2d_binned<W>, dim3(blocks), dim3(256), lds, ctx->stream, rec, nw, 1, start,
+                     nbx, T, nf, fb, es, slices, grid);
+}
+
+#define FK_W_SWITCH(w, CALL)                         \
+  switch (w) {                                       \
+    case 4: { constexpr int WW = 4; CALL; } break;   \
+    case 5: { constexpr int WW = 5; CALL; } break;   \
+    case 6: { constexpr int WW = 6; CALL; } break;   \
+    case 7: { constexpr int WW = 7; CALL; } break;   \
+    case 8: { constexpr int WW = 8; CALL; } break;   \
+    case 9: { constexpr int WW = 9; CALL; } break;   \
+    case 10: { constexpr int WW = 10; CALL; } break; \
+    case 11: { constexpr int WW = 11; CALL; } break; \
+    case 12: { constexpr int WW = 12; CALL; } break; \
+    case 13: { constexpr int WW = 13; CALL; } break; \
+    case 14: { constexpr int WW = 14; CALL; } break; \
+    case 15: { constexpr int WW = 15; CALL; } break; \
+    case 16: { constexpr int WW = 16; CALL; } break; \
+    default: return FK_EINVAL;                       \
+  }
+
+// out: complex128 [C][(2K+1)^d], C = nw + 1, channel 0 = weight 1.
+// out_c[q] = sign_scale * sum_j w_cj exp(-i q.x_j).
+fk_status type1(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int64_t xstride, int nw,
+                const void* Y, int K, double sign_scale, double* out, Carve& cv, fk_fit_info* info) {
+  EsPlan plan;
+  const double* phihat;
+  fk_status st = get_es_plan(ctx, K, &plan, &phihat);
+  if (st != FK_OK) return st;
+  const int nf = plan.nf, W = plan.w, logn = ilog2(nf);
+  const int fb = 32 - ilog2(nf) - 1;        // fixed-point fraction bits (u < nf <= 2^(31-fb))
+  const double scale = (double)nf / (2.0 * kPi) * (double)(1u << fb);
+  EsDev es{(float)plan.beta, 2.0f / (float)W};
+  const int C = nw + 1;
+  const int L = 2 * K + 1;
+  if (info) {
+    info->w = W;
+    info->nf = nf;
+    info->beta = plan.beta;
+  }
+  hipEvent_t* ev = ctx->ev;
+  if (d == 1) {
+    double* grid = cv.take<double>((size_t)C * nf);
+    if (!cv.ok()) return FK_ENOMEM;
+    FK_HIP(hipEventRecord(ev[0], ctx->stream));
+    FK_HIP(hipMemsetAsync(grid, 0, sizeof(double) * C * nf, ctx->stream));
+    int blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 4095) / 4096));
+    int64_t chunk = (n + blocks - 1) / blocks;
+    size_t lds = sizeof(float) * C * nf;
+    if (lds > 160 * 1024) return FK_EINVAL;
+    FK_HIP(hipEventRecord(ev[1], ctx->stream));
+    FK_W_SWITCH(W, launch_spread_1d<WW>(ctx, blocks, lds, X, dt, n, Y, nw, nf, fb, scale, es, grid, chunk));
+    FK_HIP(hipGetLastError());
+    FK_HIP(hipEventRecord(ev[2], ctx->stream));
+    hipLaunchKernelGGL(k_fft_line, dim3(C), dim3(256), 0, ctx->stream, grid, 0, (int64_t)1, (int64_t)nf,
+                       (int64_t)0, 1, nf, logn, phihat, K, sign_scale, out, (int64_t)1, (int64_t)L, (int64_t)0);
+    FK_HIP(hipGetLastError());
+    FK_HIP(hipEventRecord(ev[3], ctx->stream));
+    if (info) info->bin = 0;
+    return FK_OK;
+  }
+  if (d != 2) return FK_EINVAL;
+  double* grid = cv.take<double>((size_t)C * nf * nf);
+  double* rowfft = cv.take<double>((size_t)C * nf * L * 2);
+  BinGeom g = bin_geom(nf, C, n);
+  uint32_t* cnt = cv.take<uint32_t>((size_t)g.nb * g.nblk);
+  uint32_t* totals = cv.take<uint32_t>((size_t)g.nb);
+  uint64_t* start = cv.take<uint64_t>((size_t)g.nb + 1);
+  uint32_t* rec = cv.take<uint32_t>((size_t)n * (2 + nw));
+  if (!cv.ok()) return FK_ENOMEM;
+  if (info) info->bin = g.T;
+  FK_HIP(hipEventRecord(ev[0], ctx->stream));
+  FK_HIP(hipMemsetAsync(grid, 0, sizeof(double) * C * nf * nf, ctx->stream));
+  hipLaunchKernelGGL(k_bin_count, dim3(g.nblk), dim3(256), sizeof(uint32_t) * g.nb, ctx->stream, X, dt, n,
+                     xstride, nf, fb, scale, g.tshift, g.nbx, cnt, g.nblk, g.chunk, ctx->flags);
+  FK_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_scan_rows, dim3(g.nb), dim3(256), 0, ctx->stream, cnt, g.nblk, totals);
+  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, ctx->stream, totals, g.nb, start);
+  hipLaunchKernelGGL(k_bin_scatter, dim3(g.nblk), dim3(256), sizeof(uint32_t) * g.nb, ctx->stream, X, dt, n,
+                     xstride, Y, nw, nf, fb, scale, g.tshift, g.nbx, cnt, start, g.nblk, g.chunk, rec,
+                     ctx->flags);
+  FK_HIP(hipGetLastError());
+  FK_HIP(hipEventRecord(ev[1], ctx->stream));
+  const int H = (W + 1) / 2;
+  const int S = g.T + 2 * H;
+  size_t lds = sizeof(float) * S * S * C;
+  if (lds > 160 * 1024) return FK_EINVAL;
+  int64_t per_bin = (n + g.nb - 1) / g.nb;
+  int slices = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (per_bin + 8191) / 8192));
+  int blocks = g.nb * slices;
+  FK_W_SWITCH(W, launch_spread_2d<WW>(ctx, blocks, lds, rec, nw, start, g.nbx, g.T, nf, fb, es, slices, grid));
+  FK_HIP(hipGetLastError());
+  FK_HIP(hipEventRecord(ev[2], ctx->stream));
+  // rows: lines along dim 2 (contiguous), C*nf lines -> rowfft[c][i1][q2]
+  hipLaunchKernelGGL(k_fft_line, dim3(C * nf), dim3(256), 0, ctx->stream, grid, 0, (int64_t)1, (int64_t)nf,
+                     (int64_t)0, 1, nf, logn, phihat, K, 1.0, rowfft, (int64_t)1, (int64_t)L, (int64_t)0);
+  // columns: for each (c, q2) the line along i1 with stride L (complex)
+  hipLaunchKernelGGL(k_fft_line, dim3(C * L), dim3(256), 0, ctx->stream, rowfft, 1, (int64_t)L,
+                     (int64_t)nf * L, (int64_t)1, L, nf, logn, phihat, K, sign_scale, out, (int64_t)L,
+                     (int64_t)L * L, (int64_t)1);
+  FK_HIP(hipGetLastError());
+  FK_HIP(hipEventRecord(ev[3], ctx->stream));
+  return FK_OK;
+}
+
+}  // namespace fk

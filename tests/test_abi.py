@@ -1,0 +1,70 @@
+"""The C-ABI library loads and exports every entry point that include/fk.h declares
+(no compute calls: this runs without a GPU)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fk.h")
+LIB = os.path.join(ROOT, "paper_2509_02649_amd", "libfastkernel.so")
+
+
+def declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:fk_status|const char\*)\s+(fk_[a-z0-9_]+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libfastkernel.so is not built; run python -m paper_2509_02649_amd.build")
+    return C.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for must in ["fk_create", "fk_destroy", "fk_gram", "fk_solve", "fk_fit", "fk_predict", "fk_heldout_mse",
+                 "fk_fit_backward", "fk_additive_gram", "fk_additive_fit", "fk_status_string"]:
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared():
+        assert hasattr(lib, name), name
+
+
+def test_binding_table_matches_header():
+    from paper_2509_02649_amd import _lib
+    assert sorted(_lib.EXPORTS) == declared()
+
+
+def test_status_strings(lib):
+    f = lib.fk_status_string
+    f.restype = C.c_char_p
+    f.argtypes = [C.c_int]
+    assert f(0) == b"ok"
+    assert b"outside" in f(2)
+    assert f(99) == b"unknown status"
+
+
+def test_workspace_queries_and_host_validation(lib):
+    from paper_2509_02649_amd import _lib
+    L = _lib.load(LIB)
+    nb = C.c_size_t()
+    assert L.fk_gram_workspace_size(None, 2, 10_000_000, 1, 32, C.byref(nb)) == 0
+    # 2-D: FP64 grid 2 x 512^2, records 3 words per point, bin tables
+    assert nb.value >= 10_000_000 * 12 + 2 * 512 * 512 * 8
+    assert L.fk_gram_workspace_size(None, 3, 100, 1, 8, C.byref(nb)) == 1          # d = 3 rejected
+    assert L.fk_gram_workspace_size(None, 1, 0, 1, 8, C.byref(nb)) == 1            # n = 0 rejected
+    assert L.fk_gram_workspace_size(None, 1, 100, 1, 65, C.byref(nb)) == 1         # m > 64 rejected
+    assert L.fk_solve_workspace_size(None, 2, 32, 16, 64, C.byref(nb)) == 0
+    Np = 4288
+    assert nb.value >= 64 * Np * Np * 4 + 2 * Np * Np * 8
+    assert L.fk_predict_workspace_size(None, 2, 32, 1, C.byref(nb)) == 0
+    assert L.fk_additive_fit_workspace_size(None, 10, 1000, 1, 32, 1, C.byref(nb)) == 0
+    assert L.fk_additive_gram_workspace_size(None, 1, 1000, 1, 32, C.byref(nb)) == 1   # d = 1 rejected
+    # entry points reject a null context before touching the device
+    assert L.fk_gram(None, 1, 10, 0, C.c_void_p(1), 0, None, 4, C.c_void_p(1), None, C.c_void_p(1), 1 << 20,
+                     None) == 1

@@ -1,0 +1,142 @@
+"""Parity of the dense stage (real-form FP32 MFMA Cholesky + FP64 refinement) and of the
+end-to-end fit with the FP64 oracle.  Bar: ||theta_gpu - theta|| / ||theta|| <= 1e-4 where
+the oracle's condition number is <= 1e6 (both solver-only and end-to-end)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def fk():
+    import paper_2509_02649_amd as fk
+    return fk
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _cplx(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("d,m,n,s,lam", [(1, 50, 10_000, 1.0, 1e4 ** (-2 / 3)), (2, 8, 50_000, 2.0, 1e-3),
+                                         (2, 32, 100_000, 2.0, 1e-3)])
+def test_solver_only_parity(fk, d, m, n, s, lam):
+    rng = np.random.default_rng(d * 100 + m)
+    X = rng.uniform(-np.pi, np.pi, size=(d, n))
+    Y = np.sin(X[0]) + 0.1 * rng.standard_normal(n)
+    M = oracle.gram_generator(X, m)
+    b = oracle.rhs(X, Y[None, :], m)
+    p = oracle.sobolev_weights(m, d, s)
+    A = oracle.system_matrix(M, m, lam, p)
+    th = oracle.solve_system(A, b)
+    kappa = oracle.condition_number(A)
+    tg, info = fk.solve(_cplx(M), _cplx(b), m, [lam], penalty="sobolev", s=s, info=True)
+    e = _rel(tg[0].cpu().numpy(), th)
+    print(f"solver-only d={d} m={m}: rel={e:.2e} kappa={kappa:.2e} iters={info['refine_iters']} "
+          f"resid={info['resid_rel']:.1e} factor={info['t_factor_ms']:.2f} ms")
+    assert kappa <= 1e6
+    assert e <= TOL
+
+
+def test_fit_1d_small_config(fk):
+    w = synth.workload_1d()
+    X, Y, m = w["X"], w["Y"], w["m"]
+    p = oracle.sobolev_weights(m, 1, 1.0)
+    th, M, b = oracle.fit(X, Y, m, w["lam"], p)
+    tg = fk.fit(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(), m, w["lam"], penalty="sobolev", s=1.0)
+    e = _rel(tg[0].cpu().numpy(), th)
+    print(f"fit 1-D: rel={e:.2e}")
+    assert e <= TOL
+    # the sin 3x + cos(7x)/2 target is recovered: theta_{+-3} ~ -+ i/2, theta_{+-7} ~ 1/4
+    t = tg[0, 0].cpu().numpy()
+    assert abs(t[m + 3] + 0.5j) < 0.05 and abs(t[m - 3] - 0.5j) < 0.05 and abs(t[m + 7] - 0.25) < 0.05
+
+
+def test_fit_2d_medium(fk):
+    w = synth.workload_2d(n=1_000_000)
+    X, Y, m = w["X"], w["Y"], w["m"]
+    lam = 1e7 ** (-4 / 5)
+    p = oracle.sobolev_weights(m, 2, 2.0)
+    th, M, b = oracle.fit(X.astype(np.float64), Y.astype(np.float64), m, lam, p)
+    A = oracle.system_matrix(M, m, lam, p)
+    kappa = oracle.condition_number(A)
+    tg, info = fk.fit(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(), m, lam, penalty="sobolev", s=2.0,
+                      info=True)
+    e = _rel(tg[0].cpu().numpy(), th)
+    print(f"fit 2-D n=1e6: rel={e:.2e} kappa={kappa:.2e} info={info}")
+    assert kappa <= 1e6 and e <= TOL
+
+
+def test_fit_many_lambdas_and_targets(fk):
+    X = synth.uniform_points(99, 2, 200_000)
+    Y = synth.batched_targets(X, 99, ntgt=4)
+    m = 12
+    lams = [1e-5, 1e-3, 1e-1]
+    p = oracle.sobolev_weights(m, 2, 2.0)
+    M = oracle.gram_generator(X.astype(np.float64), m)
+    b = oracle.rhs(X.astype(np.float64), Y.astype(np.float64), m)
+    tg = fk.fit(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(), m, lams, penalty="sobolev", s=2.0)
+    tg = tg.cpu().numpy()
+    for i, lam in enumerate(lams):
+        A = oracle.system_matrix(M, m, lam, p)
+        th = oracle.solve_system(A, b)
+        for t in range(4):
+            assert _rel(tg[i, t], th[t]) <= TOL
+
+
+def test_fit_low_bias_and_bessel_penalties(fk):
+    X = synth.uniform_points(5, 2, 100_000)
+    Y = synth.batched_targets(X, 5, ntgt=1)
+    m = 10
+    M = oracle.gram_generator(X.astype(np.float64), m)
+    b = oracle.rhs(X.astype(np.float64), Y.astype(np.float64), m)
+    for pen, p in [("identity", np.ones((2 * m + 1) ** 2)), ("sobolev_bessel", oracle.sobolev_bessel_weights(m, 2, 2.0))]:
+        th = oracle.solve_system(oracle.system_matrix(M, m, 1e-4, p), b)
+        tg = fk.fit(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(), m, 1e-4, penalty=pen, s=2.0)
+        assert _rel(tg[0].cpu().numpy(), th) <= TOL
+
+
+@pytest.mark.parametrize("mu", [1e-3, 1.0])
+def test_fit_physics_informed_heat(fk, mu):
+    w = synth.workload_piml(n=300_000)
+    X, Y, m = w["X"], w["Y"], w["m"]
+    lam = w["lam"]
+    Q = oracle.piml_heat_penalty(m, lam, mu)
+    M = oracle.gram_generator(X.astype(np.float64), m)
+    b = oracle.rhs(X.astype(np.float64), Y.astype(np.float64), m)
+    A = oracle.system_matrix(M, m, 0.0, Q)
+    th = oracle.solve_system(A, b)
+    kappa = oracle.condition_number(A)
+    tg, info = fk.fit(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(), m, lam, penalty="heat_box", mu=mu,
+                      info=True)
+    e = _rel(tg[0].cpu().numpy(), th)
+    print(f"PIML mu={mu}: rel={e:.2e} kappa={kappa:.2e} iters={info['refine_iters']}")
+    if kappa <= 1e6:
+        assert e <= TOL
+    else:
+        assert e <= 1e-2   # reported, above the conditioning bar
+
+
+def test_error_paths(fk):
+    X = torch.from_numpy(synth.uniform_points(3, 2, 10_000)).cuda()
+    Y = torch.ones((1, 10_000), dtype=torch.float32, device="cuda")
+    with pytest.raises(fk.FkError) as e:
+        fk.fit(X, Y, 8, -1.0)
+    assert e.value.code == 1
+    with pytest.raises(fk.FkError) as e:
+        fk.fit(X, Y, 8, 1e-3, penalty="sobolev", s=-1.0)
+    assert e.value.code == 1
+    # refinement cap 0 with a tight tolerance cannot be met
+    ctx = fk.Context(0, max_refine=0, refine_tol=1e-15)
+    with pytest.raises(fk.FkError) as e:
+        fk.fit(X, Y, 8, 1e-3, ctx=ctx)
+    assert e.value.code == 5
