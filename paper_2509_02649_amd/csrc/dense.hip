@@ -168,10 +168,27 @@ __global__ __launch_bounds__(256) void k_assemble_real(Q q, int N, int L, int Np
   H[idx] = v;
 }
 
-// A32[l] = H64 + lambda_l diag(p_real) (lower triangle incl. diagonal), identity padding.
+// Symmetric diagonal equilibration of each lambda's matrix: scl[l][r] =
+// 1/sqrt(H64[r][r] + lambda_l preal[r]) (1 on the padding).  The FP32 factor is
+// taken of S A S, which keeps the PDE-penalty systems (diagonal spread over many
+// decades) inside FP32's reach; refinement applies S on both sides.
+__global__ void k_make_scale(const double* __restrict__ H, const double* __restrict__ preal,
+                             const double* __restrict__ lams, int N, int Np, double* __restrict__ scl) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int l = blockIdx.y;
+  if (r >= Np) return;
+  double v = 1.0;
+  if (r < N) {
+    double dgl = H[(size_t)r * Np + r] + lams[l] * preal[r];
+    v = dgl > 0.0 ? 1.0 / sqrt(dgl) : 1.0;
+  }
+  scl[(size_t)l * Np + r] = v;
+}
+
+// A32[l] = S_l (H64 + lambda_l diag(p_real)) S_l in FP32, identity padding.
 __global__ __launch_bounds__(256) void k_make_a32(const double* __restrict__ H, const double* __restrict__ preal,
-                                                  const double* __restrict__ lams, int N, int Np,
-                                                  float* __restrict__ A) {
+                                                  const double* __restrict__ lams, const double* __restrict__ scl,
+                                                  int N, int Np, float* __restrict__ A) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)Np * Np) return;
   const int l = blockIdx.y;
@@ -180,7 +197,8 @@ __global__ __launch_bounds__(256) void k_make_a32(const double* __restrict__ H, 
   if (r < N && s < N) {
     double h = H[idx];
     if (r == s) h += lams[l] * preal[r];
-    v = (float)h;
+    const double* sl = scl + (size_t)l * Np;
+    v = (float)(sl[r] * h * sl[s]);
   } else {
     v = (r == s) ? 1.0f : 0.0f;
   }
@@ -477,9 +495,10 @@ __global__ __launch_bounds__(256) void k_bwd_step(const float* __restrict__ A, i
 
 // ------------------------------------------------------------------ FP64 residual
 // Rres[l][t] = Bre[t] - (H64 + lambda_l diag(preal)) X[l][t], for all (l, t) at once:
-// one FP64 GEMM H64 (Np x Np) times X (Np x ncolsTotal) on MFMA (v_mfma_f64_16x16x4f64,
-// same lane layout as the FP32 16x16x4 instruction), then the diagonal and the
-// subtraction.  Column c of X/Rres is (l, t) with l = c / ntgt.
+// one FP64 GEMM H64 (Np x Np) times X (Np x ncolsTotal), then the diagonal and the
+// subtraction.  Column c of X/Rres is (l, t) with l = c / ntgt.  FP64 FMAs on the
+// vector ALUs (MI355X: the same 78.6 TF/s peak as FP64 MFMA): LDS tiles of 64 rows
+// x 64 columns, each thread a 4 x 4 register block.
 constexpr int GT = 64;  // output tile rows/cols
 constexpr int GK = 16;  // k chunk
 __global__ __launch_bounds__(256) void k_resid64(const double* __restrict__ H, int N, int Np,
@@ -487,47 +506,47 @@ __global__ __launch_bounds__(256) void k_resid64(const double* __restrict__ H, i
                                                  int rhs_per_col,
                                                  const double* __restrict__ Bre, const double* __restrict__ preal,
                                                  const double* __restrict__ lams, double* __restrict__ Rres) {
-  __shared__ double Hs[GT][GK + 1];
-  __shared__ double Xs[GT][GK + 1];   // Xs[col][k]
+  __shared__ double Hs[GK][GT + 1];   // Hs[k][row]
+  __shared__ double Xs[GK][GT + 1];   // Xs[k][col]
   const int row0 = blockIdx.x * GT, col0 = blockIdx.y * GT;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
-  const int li = lane & 15, lk = lane >> 4;
-  doublex4 acc[2][2] = {};
+  const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+  double acc[4][4] = {};
   for (int k0 = 0; k0 < Np; k0 += GK) {
     for (int i = threadIdx.x; i < GT * GK; i += blockDim.x) {
       int r = i / GK, k = i - r * GK;
-      Hs[r][k] = H[(size_t)(row0 + r) * Np + k0 + k];
+      Hs[k][r] = H[(size_t)(row0 + r) * Np + k0 + k];
       int c = col0 + r;
-      Xs[r][k] = (c < ncols) ? X[(size_t)c * Np + k0 + k] : 0.0;
+      Xs[k][r] = (c < ncols) ? X[(size_t)c * Np + k0 + k] : 0.0;
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < GK; k += 4) {
-      double a0 = Hs[r0 + li][k + lk], a1 = Hs[r0 + 16 + li][k + lk];
-      double b0 = Xs[c0 + li][k + lk], b1 = Xs[c0 + 16 + li][k + lk];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    for (int k = 0; k < GK; ++k) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[i] = Hs[k][tr * 4 + i];
+        b[i] = Xs[k][tc * 4 + i];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int rb = 0; rb < 2; ++rb)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        int r = row0 + r0 + rb * 16 + 4 * (lane >> 4) + v;
-        int c = col0 + c0 + cb * 16 + (lane & 15);
-        if (c >= ncols) continue;
-        int l = c / ntgt, t = c - l * ntgt;
-        double xv = X[(size_t)c * Np + r];
-        double ax = acc[rb][cb][v] + (r < N ? lams[l] * preal[r] * xv : 0.0);
-        double bv = (r < N) ? Bre[(size_t)(rhs_per_col ? c : t) * Np + r] : 0.0;
-        Rres[(size_t)c * Np + r] = bv - ax;
-      }
+    for (int j = 0; j < 4; ++j) {
+      int r = row0 + tr * 4 + i;
+      int c = col0 + tc * 4 + j;
+      if (c >= ncols) continue;
+      int l = c / ntgt, t = c - l * ntgt;
+      double xv = X[(size_t)c * Np + r];
+      double ax = acc[i][j] + (r < N ? lams[l] * preal[r] * xv : 0.0);
+      double bv = (r < N) ? Bre[(size_t)(rhs_per_col ? c : t) * Np + r] : 0.0;
+      Rres[(size_t)c * Np + r] = bv - ax;
+    }
 }
 
 // Column norms squared of Rres and of the right-hand sides (per column), FP64.
@@ -545,13 +564,23 @@ __global__ __launch_bounds__(256) void k_colnorm2(const double* __restrict__ V, 
   if (threadIdx.x == 0) out[blockIdx.x] = part[0];
 }
 
-__global__ void k_d2f(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+// b = (float)(S a) and x += S d, with the per-lambda scaling; element i is
+// (lambda, target, row) = (i / (ntgt Np), ., i % Np).
+__global__ void k_scale_d2f(const double* __restrict__ a, const double* __restrict__ scl, int Np, int ntgt,
+                            float* __restrict__ b, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) b[i] = (float)a[i];
+  if (i >= n) return;
+  int64_t l = i / ((int64_t)ntgt * Np);
+  int r = (int)(i % Np);
+  b[i] = (float)(a[i] * scl[l * Np + r]);
 }
-__global__ void k_axpy_f2d(const float* __restrict__ a, double* __restrict__ b, int64_t n) {
+__global__ void k_scale_axpy_f2d(const float* __restrict__ a, const double* __restrict__ scl, int Np, int ntgt,
+                                 double* __restrict__ b, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) b[i] += (double)a[i];
+  if (i >= n) return;
+  int64_t l = i / ((int64_t)ntgt * Np);
+  int r = (int)(i % Np);
+  b[i] += scl[l * Np + r] * (double)a[i];
 }
 __global__ void k_rep_rhs(const double* __restrict__ Bre, int Np, int ntgt, int nlam, double* __restrict__ R) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -595,6 +624,7 @@ SolveLayout solve_layout(int N, int nlam, int ntgt, void* base, size_t cap) {
   s.Hv = cv.take<double>(Np * Np);
   s.Bv = cv.take<double>((size_t)ntgt * Np);
   s.pcx = cv.take<double>((size_t)N);
+  s.scl = cv.take<double>((size_t)nlam * Np);
   s.bytes = cv.off + 256;
   return s;
 }
@@ -657,10 +687,12 @@ static fk_status refine_solve(fk_ctx* ctx, const SolveLayout& s, const double* r
   double worst = 0.0;
   int bad = -1;
   for (;; ++it) {
-    hipLaunchKernelGGL(k_d2f, dim3(blocks), dim3(thr), 0, ctx->stream, s.R64, s.R32, tot);
+    hipLaunchKernelGGL(k_scale_d2f, dim3(blocks), dim3(thr), 0, ctx->stream, s.R64, s.scl, s.Np, s.ntgt, s.R32,
+                       tot);
     fk_status st = trsm_all(ctx, s, s.R32, s.Y32, s.D32);
     if (st != FK_OK) return st;
-    hipLaunchKernelGGL(k_axpy_f2d, dim3(blocks), dim3(thr), 0, ctx->stream, s.D32, X, tot);
+    hipLaunchKernelGGL(k_scale_axpy_f2d, dim3(blocks), dim3(thr), 0, ctx->stream, s.D32, s.scl, s.Np, s.ntgt, X,
+                       tot);
     // R64 = rhs - A X
     hipLaunchKernelGGL(k_resid64, dim3(s.Np / GT, (nc + GT - 1) / GT), dim3(256), 0, ctx->stream, s.H64, s.N,
                        s.Np, X, nc, s.ntgt, rhs_cols ? 1 : 0, rhs_cols ? rhs_cols : s.Bre, s.preal, s.lams,
@@ -711,8 +743,10 @@ fk_status solve_impl(fk_ctx* ctx, const SolveProblem& P, const SolveLayout& s, d
     DenseQ q{P.B, N};
     hipLaunchKernelGGL(k_assemble_real<DenseQ>, dim3(gb), dim3(256), 0, ctx->stream, q, N, L, Np, s.H64);
   }
-  hipLaunchKernelGGL(k_make_a32, dim3(gb, s.nlam), dim3(256), 0, ctx->stream, s.H64, s.preal, s.lams, N, Np,
-                     s.A32);
+  hipLaunchKernelGGL(k_make_scale, dim3((Np + 255) / 256, s.nlam), dim3(256), 0, ctx->stream, s.H64, s.preal,
+                     s.lams, N, Np, s.scl);
+  hipLaunchKernelGGL(k_make_a32, dim3(gb, s.nlam), dim3(256), 0, ctx->stream, s.H64, s.preal, s.lams, s.scl, N,
+                     Np, s.A32);
   hipLaunchKernelGGL(k_rhs_real, dim3((Np + 255) / 256, s.ntgt), dim3(256), 0, ctx->stream, P.b, N, L, Np,
                      s.ntgt, s.Bre);
   FK_HIP(hipGetLastError());
@@ -768,11 +802,11 @@ __global__ __launch_bounds__(256) void k_coldot(const double* __restrict__ A, co
   if (threadIdx.x == 0) out[c] = part[0];
 }
 
-__global__ void k_mse_combine(const double* __restrict__ xGx, const double* __restrict__ bx,
+__global__ void k_mse_combine(const double* __restrict__ xg, const double* __restrict__ bx,
                               const double* __restrict__ yv2, int nc, int ntgt, double* __restrict__ mse) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nc) return;
-  mse[c] = xGx[c] - 2.0 * bx[c] + yv2[c % ntgt];
+  mse[c] = xg[c] - bx[c] + yv2[c % ntgt];   // x.(Hv x - bv) - x.bv + mean(Yv^2)
 }
 
 // G64[c] = Hv X[c] - Bv[t]   (gradient direction g in real form)

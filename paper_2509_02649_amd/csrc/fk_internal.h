@@ -74,6 +74,7 @@ struct SolveLayout {
   double* Hv = nullptr;    // held-out real-form Gram
   double* Bv = nullptr;    // held-out real right-hand sides
   double* pcx = nullptr;   // N complex-mode weights
+  double* scl = nullptr;   // nlam x Np diagonal equilibration of the FP32 factor
   size_t bytes = 0;
 };
 SolveLayout solve_layout(int N, int nlam, int ntgt, void* base, size_t cap);
