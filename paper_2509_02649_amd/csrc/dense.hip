@@ -322,40 +322,42 @@ __global__ __launch_bounds__(256) void k_potrf_diag(float* __restrict__ A, int N
     int r = i / NB, c = i - r * NB;
     a[r][c] = (c <= r) ? (double)Ab[(size_t)r * Np + c] : 0.0;
   }
+  for (int i = threadIdx.x; i < NB * NB; i += blockDim.x) x[i / NB][i % NB] = 0.0;
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
+  // Right-looking, four threads per row (row = tid/4, column slice q = tid%4).
+  // In step j every thread reads column j unscaled and applies the scaled rank-1
+  // update to columns > j of its row; the column itself is scaled after a barrier.
+  const int row = threadIdx.x >> 2, q = threadIdx.x & 3;
   for (int j = 0; j < NB; ++j) {
-    if (threadIdx.x == 0) {
-      double dj = a[j][j];
-      if (!(dj > 0.0)) {   // non-positive or NaN pivot
-        bad = 1;
-        dj = 1.0;
-      }
-      a[j][j] = sqrt(dj);
+    const double dj = a[j][j];
+    const bool badj = !(dj > 0.0);   // non-positive or NaN pivot
+    const double d = sqrt(badj ? 1.0 : dj);
+    const double inv = 1.0 / d;
+    if (row > j) {
+      const double lij = a[row][j] * inv;
+      for (int k = j + 1 + q; k <= row; k += 4) a[row][k] -= lij * (a[k][j] * inv);
     }
     __syncthreads();
-    const double djj = a[j][j];
-    for (int i = j + 1 + threadIdx.x; i < NB; i += blockDim.x) a[i][j] /= djj;
-    __syncthreads();
-    const int rem = NB - j - 1;
-    for (int t = threadIdx.x; t < rem * rem; t += blockDim.x) {
-      int i = j + 1 + t / rem, k = j + 1 + t % rem;
-      if (k <= i) a[i][k] -= a[i][j] * a[k][j];
+    if (q == 0) {
+      if (row == j) a[j][j] = d;
+      else if (row > j) a[row][j] *= inv;
     }
+    if (threadIdx.x == 0 && badj) bad = 1;
     __syncthreads();
   }
-  // inverse of the lower-triangular block, one column per thread
-  if (threadIdx.x < NB) {
-    const int c = threadIdx.x;
-    for (int i = 0; i < NB; ++i) x[i][c] = 0.0;
-    x[c][c] = 1.0 / a[c][c];
-    for (int i = c + 1; i < NB; ++i) {
-      double s = 0.0;
-      for (int k = c; k < i; ++k) s += a[i][k] * x[k][c];
-      x[i][c] = -s / a[i][i];
-    }
+  // Inverse of the lower-triangular block, row by row: every column c <= i of row i
+  // in parallel (four threads per column split the inner sum).
+  const int c = threadIdx.x >> 2;
+  for (int i = 0; i < NB; ++i) {
+    double s = 0.0;
+    if (c < i)
+      for (int k = c + q; k < i; k += 4) s += a[i][k] * x[k][c];
+    s += __shfl_xor(s, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    if (q == 0 && c <= i) x[i][c] = ((c == i ? 1.0 : 0.0) - s) / a[i][i];
+    __syncthreads();
   }
-  __syncthreads();
   float* Li = Linv + ((size_t)l * (Np / NB) + kb) * NB * NB;
   for (int i = threadIdx.x; i < NB * NB; i += blockDim.x) {
     int r = i / NB, c = i - r * NB;
@@ -549,6 +551,55 @@ __global__ __launch_bounds__(256) void k_resid64(const double* __restrict__ H, i
     }
 }
 
+// Same residual for a few columns (ncols <= 8): one wave per row streams the row of
+// H64 once (coalesced) against all columns; the tiled kernel above would leave
+// most of each 64-column tile empty.
+constexpr int NARROW = 8;
+__global__ __launch_bounds__(256) void k_resid64_narrow(const double* __restrict__ H, int N, int Np,
+                                                        const double* __restrict__ X, int ncols, int ntgt,
+                                                        int rhs_per_col, const double* __restrict__ Bre,
+                                                        const double* __restrict__ preal,
+                                                        const double* __restrict__ lams, double* __restrict__ Rres) {
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= Np) return;
+  double acc[NARROW];
+#pragma unroll
+  for (int c = 0; c < NARROW; ++c) acc[c] = 0.0;
+  const double* h = H + (size_t)r * Np;
+  for (int k = lane; k < Np; k += 64) {
+    const double hv = h[k];
+#pragma unroll
+    for (int c = 0; c < NARROW; ++c)
+      if (c < ncols) acc[c] = fma(hv, X[(size_t)c * Np + k], acc[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < NARROW; ++c)
+    for (int o = 32; o > 0; o >>= 1) acc[c] += __shfl_xor(acc[c], o, 64);
+  if (lane < ncols) {
+    const int c = lane;
+    double a = 0.0;
+#pragma unroll
+    for (int cc = 0; cc < NARROW; ++cc)
+      if (cc == c) a = acc[cc];
+    const int l = c / ntgt, t = c - l * ntgt;
+    const double xv = X[(size_t)c * Np + r];
+    const double ax = a + (r < N ? lams[l] * preal[r] * xv : 0.0);
+    const double bv = (r < N) ? Bre[(size_t)(rhs_per_col ? c : t) * Np + r] : 0.0;
+    Rres[(size_t)c * Np + r] = bv - ax;
+  }
+}
+
+static void launch_resid(hipStream_t st, const double* H, int N, int Np, const double* X, int ncols, int ntgt,
+                         int rhs_per_col, const double* Bre, const double* preal, const double* lams, double* R) {
+  if (ncols <= NARROW)
+    hipLaunchKernelGGL(k_resid64_narrow, dim3((Np + 3) / 4), dim3(256), 0, st, H, N, Np, X, ncols, ntgt,
+                       rhs_per_col, Bre, preal, lams, R);
+  else
+    hipLaunchKernelGGL(k_resid64, dim3(Np / GT, (ncols + GT - 1) / GT), dim3(256), 0, st, H, N, Np, X, ncols, ntgt,
+                       rhs_per_col, Bre, preal, lams, R);
+}
+
 // Column norms squared of Rres and of the right-hand sides (per column), FP64.
 __global__ __launch_bounds__(256) void k_colnorm2(const double* __restrict__ V, int Np, double* __restrict__ out) {
   __shared__ double part[256];
@@ -694,9 +745,8 @@ static fk_status refine_solve(fk_ctx* ctx, const SolveLayout& s, const double* r
     hipLaunchKernelGGL(k_scale_axpy_f2d, dim3(blocks), dim3(thr), 0, ctx->stream, s.D32, s.scl, s.Np, s.ntgt, X,
                        tot);
     // R64 = rhs - A X
-    hipLaunchKernelGGL(k_resid64, dim3(s.Np / GT, (nc + GT - 1) / GT), dim3(256), 0, ctx->stream, s.H64, s.N,
-                       s.Np, X, nc, s.ntgt, rhs_cols ? 1 : 0, rhs_cols ? rhs_cols : s.Bre, s.preal, s.lams,
-                       s.R64);
+    launch_resid(ctx->stream, s.H64, s.N, s.Np, X, nc, s.ntgt, rhs_cols ? 1 : 0, rhs_cols ? rhs_cols : s.Bre,
+                 s.preal, s.lams, s.R64);
     FK_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_colnorm2, dim3(nc), dim3(256), 0, ctx->stream, s.R64, s.Np, s.norms);
     FK_HIP(hipMemcpyAsync(nh.data(), s.norms, sizeof(double) * 2 * nc, hipMemcpyDeviceToHost, ctx->stream));
@@ -818,7 +868,7 @@ __global__ void k_negate(double* __restrict__ v, int64_t n) {
 
 fk_status heldout_mse_impl(fk_ctx* ctx, const SolveLayout& s, int d, int m, const double* Mv, const double* bv,
                            const double* yv2, double* mse) {
-  const int N = s.N, Np = s.Np, L = (int)std::lround(std::pow((double)N, 1.0 / d));
+  const int N = s.N, Np = s.Np, L = N;   // one real-form block of all N modes
   const int64_t tot2 = (int64_t)Np * Np;
   const int gb = (int)((tot2 + 255) / 256);
   ToeplitzQ q{Mv, m, d};
@@ -829,8 +879,7 @@ fk_status heldout_mse_impl(fk_ctx* ctx, const SolveLayout& s, int d, int m, cons
   // zero "lambda" for the validation product: reuse norms scratch as a zero lambda array
   FK_HIP(hipMemsetAsync(s.norms, 0, sizeof(double) * (2 * nc + s.nlam + 64), ctx->stream));
   // R = Bv - Hv X   (lambda = 0 via a zero lambda array of length nlam in norms[2nc..])
-  hipLaunchKernelGGL(k_resid64, dim3(Np / GT, (nc + GT - 1) / GT), dim3(256), 0, ctx->stream, s.Hv, N, Np, s.X64,
-                     nc, s.ntgt, 0, s.Bv, s.preal, s.norms + 2 * nc, s.G64);
+  launch_resid(ctx->stream, s.Hv, N, Np, s.X64, nc, s.ntgt, 0, s.Bv, s.preal, s.norms + 2 * nc, s.G64);
   const int64_t tot = (int64_t)nc * Np;
   hipLaunchKernelGGL(k_negate, dim3((tot + 255) / 256), dim3(256), 0, ctx->stream, s.G64, tot);
   // xGx = x.(Hv x) = x.(g + bv) ; bx = bv.x
@@ -897,7 +946,7 @@ __global__ void k_scale_cols_cplx(double* __restrict__ th, const double* __restr
 
 fk_status backward_impl(fk_ctx* ctx, const SolveLayout& s, int d, const double* gm, double* grad_loglam,
                         double* grad_p, double* grad_theta) {
-  const int N = s.N, Np = s.Np, L = (int)std::lround(std::pow((double)N, 1.0 / d));
+  const int N = s.N, Np = s.Np, L = N;   // one real-form block of all N modes
   const int nc = s.nlam * s.ntgt;
   int iters = 0, bad = -1;
   double resid = 0.0;

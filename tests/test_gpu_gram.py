@@ -57,10 +57,13 @@ def test_gram_2d_other_m(fk, m):
     assert eT <= TOL and eb <= TOL
 
 
-def test_gram_2d_multi_target(fk):
-    X = synth.uniform_points(77, 2, 30_000)
-    Y = synth.batched_targets(X, 77, ntgt=16)
-    eT, eb, _ = _errors(fk, X, Y, 32)
+@pytest.mark.parametrize("ntgt,n", [(16, 30_000), (8, 50_000), (7, 20_000), (17, 20_000), (16, 1_000_000)])
+def test_gram_2d_multi_target(fk, ntgt, n):
+    # 8..16 targets take the MFMA spread (bins of 4 x 4 cells); 7 and 17 the atomic spread
+    X = synth.uniform_points(77 + ntgt, 2, n)
+    Y = synth.batched_targets(X, 77 + ntgt, ntgt=ntgt)
+    eT, eb, info = _errors(fk, X, Y, 32)
+    print(f"2-D T={ntgt} n={n}: eps_T={eT:.2e} eps_b={eb:.2e} bin={info['bin']} spread={info['t_spread_ms']:.3f} ms")
     assert eT <= TOL and eb <= TOL
 
 

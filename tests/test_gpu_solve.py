@@ -116,14 +116,22 @@ def test_fit_physics_informed_heat(fk, mu):
     A = oracle.system_matrix(M, m, 0.0, Q)
     th = oracle.solve_system(A, b)
     kappa = oracle.condition_number(A)
+    print(f"PIML mu={mu}: kappa={kappa:.2e}")
+    if kappa > 1e7:
+        # beyond FP32's reach even after equilibration: the documented outcome is a
+        # status (FK_ENOTPD or FK_ENOCONV) naming the failing lambda, not a wrong theta
+        try:
+            tg = fk.fit(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(), m, lam, penalty="heat_box", mu=mu)
+        except fk.FkError as e:
+            assert e.code in (4, 5)
+            return
+        assert _rel(tg[0].cpu().numpy(), th) <= 1e-2
+        return
     tg, info = fk.fit(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(), m, lam, penalty="heat_box", mu=mu,
                       info=True)
     e = _rel(tg[0].cpu().numpy(), th)
-    print(f"PIML mu={mu}: rel={e:.2e} kappa={kappa:.2e} iters={info['refine_iters']}")
-    if kappa <= 1e6:
-        assert e <= TOL
-    else:
-        assert e <= 1e-2   # reported, above the conditioning bar
+    print(f"PIML mu={mu}: rel={e:.2e} iters={info['refine_iters']}")
+    assert e <= TOL
 
 
 def test_error_paths(fk):
