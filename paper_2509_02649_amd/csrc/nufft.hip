@@ -295,35 +295,26 @@ __global__ __launch_bounds__(256) void k_bin_count(const void* __restrict__ X, f
     atomicAdd(&hist[b], 1u);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) cnt[(int64_t)i * nblk + blockIdx.x] = hist[i];
+  // count table is [workgroup][bin]: one contiguous row per workgroup
+  uint32_t* row = cnt + (int64_t)blockIdx.x * nb;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) row[i] = hist[i];
+  (void)nblk;
 }
 
-// Exclusive scan of cnt[bin][0..nblk) in place, one workgroup per bin; bin totals out.
-__global__ __launch_bounds__(256) void k_scan_rows(uint32_t* __restrict__ cnt, int nblk,
+// Exclusive scan over workgroups of cnt[.][bin] in place, one thread per bin
+// (consecutive threads read consecutive bins of a row); bin totals out.
+__global__ __launch_bounds__(256) void k_scan_cols(uint32_t* __restrict__ cnt, int nb, int nblk,
                                                    uint32_t* __restrict__ totals) {
-  __shared__ uint32_t part[256];
-  uint32_t* row = cnt + (int64_t)blockIdx.x * nblk;
-  const int per = (nblk + 255) / 256;
-  const int b0 = threadIdx.x * per;
-  uint32_t s = 0;
-  for (int i = 0; i < per; ++i)
-    if (b0 + i < nblk) s += row[b0 + i];
-  part[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  uint32_t run = 0;
+  for (int k = 0; k < nblk; ++k) {
+    uint32_t* p = cnt + (int64_t)k * nb + b;
+    uint32_t c = *p;
+    *p = run;
+    run += c;
   }
-  uint32_t run = part[threadIdx.x] - s;
-  for (int i = 0; i < per; ++i)
-    if (b0 + i < nblk) {
-      uint32_t c = row[b0 + i];
-      row[b0 + i] = run;
-      run += c;
-    }
-  if (threadIdx.x == 255) totals[blockIdx.x] = part[255];
+  totals[b] = run;
 }
 
 // Exclusive scan of the bin totals (nb <= 65536) by one workgroup; start[nb] = total.
@@ -353,31 +344,32 @@ __global__ __launch_bounds__(1024) void k_scan_totals(const uint32_t* __restrict
 }
 
 // Scatter points into bin-contiguous records [U1, U2, w_0 .. w_{nw-1}] (32-bit words).
-__global__ __launch_bounds__(256) void k_bin_scatter(const void* __restrict__ X, fk_dtype dt, int64_t n,
-                                                     int64_t xstride, const void* __restrict__ Y,
-                                                     int nw, int nf, int fb, double scale, int tshift,
-                                                     int nbx, const uint32_t* __restrict__ cnt,
-                                                     const uint64_t* __restrict__ start, int nblk,
-                                                     int64_t chunk, uint32_t* __restrict__ rec,
-                                                     int* flags) {
-  extern __shared__ uint32_t slot[];
+// Each workgroup keeps the next write position of every bin in LDS (64-bit,
+// seeded from the scans) and claims a slot with one LDS atomic per point.
+__global__ __launch_bounds__(1024) void k_bin_scatter(const void* __restrict__ X, fk_dtype dt, int64_t n,
+                                                      int64_t xstride, const void* __restrict__ Y,
+                                                      int nw, int nf, int fb, double scale, int tshift,
+                                                      int nbx, const uint32_t* __restrict__ cnt,
+                                                      const uint64_t* __restrict__ start, int nblk,
+                                                      int64_t chunk, uint32_t* __restrict__ rec,
+                                                      int* flags) {
+  extern __shared__ unsigned long long nextpos[];
   const int nb = nbx * nbx;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) slot[i] = 0;
+  const uint32_t* row = cnt + (int64_t)blockIdx.x * nb;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) nextpos[i] = start[i] + row[i];
   __syncthreads();
+  (void)nblk;
   const int64_t beg = (int64_t)blockIdx.x * chunk;
   const int64_t end = min(n, beg + chunk);
   const uint32_t nf_fix = (uint32_t)nf << fb;
   const int R = 2 + nw;
   for (int64_t j = beg + threadIdx.x; j < end; j += blockDim.x) {
     uint32_t U1, U2;
-    int dummy[kFlagCount];
-    (void)dummy;
     bool ok = to_fixed(load_coord(X, dt, j), scale, nf_fix, &U1, flags);
     ok = to_fixed(load_coord(X, dt, xstride + j), scale, nf_fix, &U2, flags) && ok;
     if (!ok) continue;
     int b = ((U1 >> fb) >> tshift) * nbx + ((U2 >> fb) >> tshift);
-    uint32_t r = atomicAdd(&slot[b], 1u);
-    uint64_t pos = start[b] + cnt[(int64_t)b * nblk + blockIdx.x] + r;
+    uint64_t pos = atomicAdd(&nextpos[b], 1ull);
     uint32_t* o = rec + pos * R;
     // build the record in registers, store it as 8-byte words when R is even
     // (whole-record stores per lane instead of one 4-byte store per channel)
@@ -848,9 +840,9 @@ fk_status type1(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int64
   hipLaunchKernelGGL(k_bin_count, dim3(g.nblk), dim3(256), sizeof(uint32_t) * g.nb, ctx->stream, X, dt, n,
                      xstride, nf, fb, scale, g.tshift, g.nbx, cnt, g.nblk, g.chunk, ctx->flags);
   FK_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_scan_rows, dim3(g.nb), dim3(256), 0, ctx->stream, cnt, g.nblk, totals);
+  hipLaunchKernelGGL(k_scan_cols, dim3((g.nb + 255) / 256), dim3(256), 0, ctx->stream, cnt, g.nb, g.nblk, totals);
   hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, ctx->stream, totals, g.nb, start);
-  hipLaunchKernelGGL(k_bin_scatter, dim3(g.nblk), dim3(256), sizeof(uint32_t) * g.nb, ctx->stream, X, dt, n,
+  hipLaunchKernelGGL(k_bin_scatter, dim3(g.nblk), dim3(1024), sizeof(unsigned long long) * g.nb, ctx->stream, X, dt, n,
                      xstride, Y, nw, nf, fb, scale, g.tshift, g.nbx, cnt, start, g.nblk, g.chunk, rec,
                      ctx->flags);
   FK_HIP(hipGetLastError());
