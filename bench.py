@@ -83,6 +83,7 @@ def main():
         Xv = fk.generate_uniform(seed + 1000, 2, nv, ctx=ctx)
         Yv = fk.generate_targets(seed + 1000, Xv, ntgt, ctx=ctx)
         lams = [10.0 ** (-8.0 + 7.0 * i / (nlam - 1)) for i in range(nlam)]
+        yv2 = (Yv.double() ** 2).mean(dim=1)   # a constant of the held-out set
         kk = np.stack(np.meshgrid(np.arange(-m, m + 1), np.arange(-m, m + 1), indexing="ij"), -1).reshape(-1, 2)
         p0 = torch.tensor(1.0 + ((kk ** 2).sum(1).astype(np.float64)) ** 2.0, device=dev)
         bytes_per_point = 4 * 2 + 4 * ntgt
@@ -103,7 +104,6 @@ def main():
             p = p0.clone().requires_grad_(True)
             theta, info = fk.fit(X, Y, m, lams, penalty="diag", p=p.detach(), ctx=ctx, info=True)
             Mv, bv = fk.gram(Xv, Yv, m, ctx=vctx)
-            yv2 = (Yv.double() ** 2).mean(dim=1)
             mse = fk.heldout_mse(Mv, bv, yv2, m, nlam, ctx)
             gl, gp, _ = fk.fit_backward(torch.ones_like(mse), m, 2, ctx)
             infos.append(info)

@@ -97,6 +97,12 @@ fk_status backward_impl(fk_ctx* ctx, const SolveLayout& s, int d, const double* 
                         double* grad_p, double* grad_theta);
 fk_status reset_flags(fk_ctx* ctx);
 
+// MFMA spread for 8..16 weight channels over MB x MB-cell bins (spread_mfma.hip).
+int spread_mfma_bin();
+bool spread_mfma_ok(int nw, int W);
+fk_status launch_spread_mfma(hipStream_t st, int W, const uint32_t* rec, int nw, const uint64_t* start, int nbx,
+                             int nb, int nf, int fb, double beta, int64_t n, double* grid);
+
 }  // namespace fk
 
 struct fk_ctx {

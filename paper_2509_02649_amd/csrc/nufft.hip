@@ -471,179 +471,6 @@ __global__ __launch_bounds__(256) void k_spread_2d_binned(const uint32_t* __rest
   }
 }
 
-// ------------------------------------------------------------------ 2-D binned spread on MFMA
-// For many weight channels (8..16 targets) the per-point LDS atomics of
-// k_spread_2d_binned (w^2 (T+1) per point) bound the spread.  Here the bins are
-// MB x MB cells (MB = 4); inside a bin the points are grouped by the start
-// (l1, l2) of their w x w window (MB+1)^2 = 25 groups, counting-sorted in LDS,
-// and each group is a dense product
-//     G[c][a, b] += sum_j  W[c][j] * psi1_j[a] psi2_j[b]
-// computed with v_mfma_f32_16x16x4f32: rows = the 16 target channels, columns =
-// the w^2 <= 64 window cells (4 tiles of 16), K = 4 points per instruction.
-// The ones channel (the Gram) is the column sum of the same kernel products,
-// accumulated on the vector ALUs.  FP32 accumulators live in registers across a
-// slice of the bin's points (each wave owns 7 of the 25 groups) and are added
-// every FLUSH batches into an FP64 LDS subgrid, which is added into the FP64 grid
-// at the end.  Lane layout of the instruction: lane l holds A[l%16][l/16] and
-// B[l/16][l%16]; result row 4*(l/16)+v, column l%16 is element v.
-constexpr int MB = 4;                       // bin edge in grid cells
-constexpr int MG = (MB + 1) * (MB + 1);     // window-start groups per bin
-constexpr int MGW = (MG + 3) / 4;           // groups per wave
-constexpr int MP = 512;                     // points per LDS batch
-constexpr int MFLUSH = 8;                   // batches between FP32 -> FP64 flushes
-
-typedef float floatx4_t __attribute__((ext_vector_type(4)));
-
-template <int W>
-__global__ __launch_bounds__(256) void k_spread_2d_mfma(const uint32_t* __restrict__ rec, int nw,
-                                                        const uint64_t* __restrict__ start, int nbx, int nf,
-                                                        int fb, EsDev es, int slices, double* __restrict__ grid) {
-  static_assert(W <= 8, "window must fit 4 column tiles and 16 lanes");
-  constexpr int S = MB + W;
-  extern __shared__ double smem_d[];
-  const int C = nw + 1;
-  const int R = 2 + nw;
-  double* sub = smem_d;                                         // S*S*C doubles
-  uint32_t* stage = reinterpret_cast<uint32_t*>(sub + S * S * C);  // MP*R words
-  uint16_t* perm = reinterpret_cast<uint16_t*>(stage + MP * R);  // MP
-  uint16_t* rank = perm + MP;                                     // MP
-  uint8_t* keyv = reinterpret_cast<uint8_t*>(rank + MP);          // MP
-  int* gcount = reinterpret_cast<int*>(keyv + MP);                // 32
-  int* gstart = gcount + 32;                                      // 32
-
-  const int b = blockIdx.x / slices;
-  const int sl = blockIdx.x - b * slices;
-  const uint64_t p0 = start[b], p1 = start[b + 1];
-  const uint64_t len = p1 - p0;
-  const uint64_t q0 = p0 + len * sl / slices;
-  const uint64_t q1 = p0 + len * (sl + 1) / slices;
-  if (q0 == q1) return;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int bx = b / nbx, by = b - bx * nbx;
-  const int o1 = bx * MB - W / 2, o2 = by * MB - W / 2;   // window starts lie in [o, o + MB]
-  for (int i = tid; i < S * S * C; i += blockDim.x) sub[i] = 0.0;
-
-  floatx4_t acc[MGW][4];
-  float ones[MGW][4];
-#pragma unroll
-  for (int s = 0; s < MGW; ++s)
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      acc[s][t] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-      ones[s][t] = 0.f;
-    }
-
-  const int kslot = lane >> 4, jj = lane & 15;
-  const int kbase = lane & 48;
-  int batch = 0;
-  for (uint64_t base = q0; base < q1; base += MP, ++batch) {
-    const int np = (int)min<uint64_t>(MP, q1 - base);
-    __syncthreads();
-    for (int i = tid; i < np * R; i += blockDim.x) stage[i] = rec[base * R + i];
-    if (tid < 32) gcount[tid] = 0;
-    __syncthreads();
-    for (int p = tid; p < np; p += blockDim.x) {
-      int i1, i2;
-      float s1, s2;
-      window_start(stage[p * R], fb, W, &i1, &s1);
-      window_start(stage[p * R + 1], fb, W, &i2, &s2);
-      int k = (i1 - o1) * (MB + 1) + (i2 - o2);
-      keyv[p] = (uint8_t)k;
-      rank[p] = (uint16_t)atomicAdd(&gcount[k], 1);
-    }
-    __syncthreads();
-    if (tid == 0) {
-      int run = 0;
-      for (int g = 0; g < MG; ++g) {
-        gstart[g] = run;
-        run += gcount[g];
-      }
-    }
-    __syncthreads();
-    for (int p = tid; p < np; p += blockDim.x) perm[gstart[keyv[p]] + rank[p]] = (uint16_t)p;
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < MGW; ++s) {
-      const int g = wv + 4 * s;
-      if (g >= MG) continue;
-      const int cnt = gcount[g], gs = gstart[g];
-      for (int c0 = 0; c0 < cnt; c0 += 4) {
-        const int idx = c0 + kslot;
-        const bool valid = idx < cnt;
-        const int p = valid ? perm[gs + idx] : 0;
-        float psi = 0.f, aop = 0.f;
-        if (valid) {
-          int i1, i2;
-          float s1, s2;
-          window_start(stage[p * R], fb, W, &i1, &s1);
-          window_start(stage[p * R + 1], fb, W, &i2, &s2);
-          if (jj < W) psi = es_eval(s1 + (float)jj, es);
-          else if (jj < 2 * W) psi = es_eval(s2 + (float)(jj - W), es);
-          if (jj < nw) aop = __uint_as_float(stage[p * R + 2 + jj]);
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int cell = t * 16 + jj;
-          const int aa = cell / W, bb = cell - (cell / W) * W;
-          const float v1 = __shfl(psi, kbase + (aa < W ? aa : 0), 64);
-          const float v2 = __shfl(psi, kbase + W + bb, 64);
-          const float bv = cell < W * W ? v1 * v2 : 0.f;
-          acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bv, acc[s][t], 0, 0, 0);
-          ones[s][t] += bv;
-        }
-      }
-    }
-    const bool last = base + MP >= q1;
-    if (last || (batch % MFLUSH) == MFLUSH - 1) {
-#pragma unroll
-      for (int s = 0; s < MGW; ++s) {
-        const int g = wv + 4 * s;
-        if (g >= MG) continue;
-        const int l1 = g / (MB + 1), l2 = g - (g / (MB + 1)) * (MB + 1);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int cell = t * 16 + jj;
-          const int aa = cell / W, bb = cell - (cell / W) * W;
-          float o = ones[s][t];
-          o += __shfl_xor(o, 16, 64);
-          o += __shfl_xor(o, 32, 64);
-          if (cell < W * W) {
-            double* cp = sub + ((l1 + aa) * S + (l2 + bb)) * C;
-            if (kslot == 0 && o != 0.f) atomicAdd(cp, (double)o);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const int row = 4 * kslot + v;
-              const float x = acc[s][t][v];
-              if (row < nw && x != 0.f) atomicAdd(cp + 1 + row, (double)x);
-            }
-          }
-          acc[s][t] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-          ones[s][t] = 0.f;
-        }
-      }
-    }
-  }
-  __syncthreads();
-  for (int i = tid; i < S * S * C; i += blockDim.x) {
-    double v = sub[i];
-    if (v == 0.0) continue;
-    int c = i % C;
-    int cell = i / C;
-    int a = cell / S, bb = cell - a * S;
-    int g1 = o1 + a, g2 = o2 + bb;
-    g1 = g1 < 0 ? g1 + nf : (g1 >= nf ? g1 - nf : g1);
-    g2 = g2 < 0 ? g2 + nf : (g2 >= nf ? g2 - nf : g2);
-    atomicAdd(&grid[((int64_t)c * nf + g1) * nf + g2], v);
-  }
-}
-
-static size_t mfma_lds_bytes(int W, int nw) {
-  const int S = MB + W, C = nw + 1, R = 2 + nw;
-  size_t b = sizeof(double) * S * S * C + sizeof(uint32_t) * MP * R + 2 * sizeof(uint16_t) * MP + MP;
-  b = (b + 3) & ~size_t(3);
-  return b + 64 * sizeof(int);
-}
-
 // ------------------------------------------------------------------ FFT (FP64, radix-2, in LDS)
 // One workgroup transforms one line of length nf (power of two <= 1024) and
 // writes the pruned, deconvolved frequencies q = -K..K:
@@ -713,13 +540,13 @@ struct BinGeom {
   int64_t chunk;
 };
 
-// Channels whose spread runs on MFMA (k_spread_2d_mfma): 8..16 weighted channels.
+// Channels whose spread runs on MFMA (spread_mfma.hip): 8..16 weighted channels.
 static bool use_mfma_spread(int nw) { return nw >= 8 && nw <= 16; }
 
 static BinGeom bin_geom(int nf, int C, int64_t n) {
   BinGeom g;
   const bool mf = use_mfma_spread(C - 1);
-  g.T = mf ? MB : ((C > 8) ? 16 : 32);
+  g.T = mf ? spread_mfma_bin() : ((C > 8) ? 16 : 32);
   if (g.T > nf) g.T = nf;
   g.tshift = ilog2(g.T);
   g.nbx = nf / g.T;
@@ -848,21 +675,10 @@ fk_status type1(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int64
   FK_HIP(hipGetLastError());
   FK_HIP(hipEventRecord(ev[1], ctx->stream));
   int64_t per_bin = (n + g.nb - 1) / g.nb;
-  if (use_mfma_spread(nw) && W <= 8 && g.T == MB) {
-    size_t lds = mfma_lds_bytes(W, nw);
-    int slices = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (per_bin + 16383) / 16384));
-    int blocks = g.nb * slices;
-    switch (W) {
-      case 5: hipLaunchKernelGGL(k_spread_2d_mfma<5>, dim3(blocks), dim3(256), lds, ctx->stream, rec, nw, start,
-                                 g.nbx, nf, fb, es, slices, grid); break;
-      case 6: hipLaunchKernelGGL(k_spread_2d_mfma<6>, dim3(blocks), dim3(256), lds, ctx->stream, rec, nw, start,
-                                 g.nbx, nf, fb, es, slices, grid); break;
-      case 7: hipLaunchKernelGGL(k_spread_2d_mfma<7>, dim3(blocks), dim3(256), lds, ctx->stream, rec, nw, start,
-                                 g.nbx, nf, fb, es, slices, grid); break;
-      default: hipLaunchKernelGGL(k_spread_2d_mfma<8>, dim3(blocks), dim3(256), lds, ctx->stream, rec, nw, start,
-                                  g.nbx, nf, fb, es, slices, grid); break;
-    }
-    if (info) info->bin = -MB;   // negative: MFMA spread over MB x MB bins
+  if (use_mfma_spread(nw) && spread_mfma_ok(nw, W) && g.T == spread_mfma_bin()) {
+    fk_status s2 = launch_spread_mfma(ctx->stream, W, rec, nw, start, g.nbx, g.nb, nf, fb, plan.beta, n, grid);
+    if (s2 != FK_OK) return s2;
+    if (info) info->bin = -g.T;   // negative: MFMA spread over T x T bins
   } else {
     const int H = (W + 1) / 2;
     const int S = g.T + 2 * H;
