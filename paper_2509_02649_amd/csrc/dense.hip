@@ -411,89 +411,118 @@ __global__ __launch_bounds__(256) void k_syrk_update(float* __restrict__ A, int 
 // ------------------------------------------------------------------ triangular solves (FP32)
 // R, Y: [lambda][ncol][Np] (column-major per lambda: column t contiguous).
 
-// Forward step kb: y_kb = inv(L_kk) r_kb (written by block 0); rows ib > kb: r_ib -= L[ib][kb] y_kb.
-__global__ __launch_bounds__(256) void k_fwd_step(const float* __restrict__ A, int Np, int kb,
+// MFMA product of a 64 x 64 LDS tile (or its transpose) with a 64 x (16*NCT) LDS
+// block: wave w computes rows 16w..16w+15.  Lane layout as in mfma_tile64.
+constexpr int LDB = 33;   // row stride of the 64 x ncol blocks (ncol <= 32)
+template <bool TRANS, int NCT>
+__device__ __forceinline__ void mfma_64xK(const float* Ls, const float (*Bs)[LDB], floatx4 acc[NCT]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+  for (int k0 = 0; k0 < NB; k0 += 4) {
+    const float a = TRANS ? Ls[(k0 + lk) * LDT + 16 * w + li] : Ls[(16 * w + li) * LDT + k0 + lk];
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) {
+      const float b = Bs[k0 + lk][ct * 16 + li];
+      acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[ct], 0, 0, 0);
+    }
+  }
+}
+
+// Forward step kb of L y = r for every lambda (grid.y): y_kb = inv(L_kk) r_kb, written
+// by block 0; block x updates rows ib = kb + 1 + x: r_ib -= L[ib][kb] y_kb.
+template <int NCT>
+__global__ __launch_bounds__(256) void k_fwd_mfma(const float* __restrict__ A, int Np, int kb,
                                                   const float* __restrict__ Linv, float* __restrict__ R,
                                                   float* __restrict__ Y, int ncol) {
-  __shared__ float Lt[NB * LDT];
-  __shared__ float rk[32][NB];
-  __shared__ float yk[32][NB];
+  __shared__ float Ls[NB * LDT];
+  __shared__ float Bs[NB][LDB];
   const int l = blockIdx.y;
-  const float* Li = Linv + ((size_t)l * (Np / NB) + kb) * NB * NB;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
   float* Rl = R + (size_t)l * ncol * Np;
-  for (int i = threadIdx.x; i < ncol * NB; i += blockDim.x) {
-    int t = i / NB, r = i - t * NB;
-    rk[t][r] = Rl[(size_t)t * Np + kb * NB + r];
+  for (int i = threadIdx.x; i < NB * 16 * NCT; i += blockDim.x) {
+    const int t = i / NB, k = i - t * NB;
+    Bs[k][t] = t < ncol ? Rl[(size_t)t * Np + kb * NB + k] : 0.f;
   }
-  load_tile(Lt, Li, NB);
+  load_tile(Ls, Linv + ((size_t)l * (Np / NB) + kb) * NB * NB, NB);
   __syncthreads();
-  for (int i = threadIdx.x; i < ncol * NB; i += blockDim.x) {
-    int t = i / NB, r = i - t * NB;
-    float s = 0.f;
-    for (int k = 0; k <= r; ++k) s += Lt[r * LDT + k] * rk[t][k];
-    yk[t][r] = s;
-  }
+  floatx4 acc[NCT];
+  mfma_64xK<false, NCT>(Ls, Bs, acc);
+  __syncthreads();
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Bs[16 * w + 4 * lk + v][ct * 16 + li] = acc[ct][v];
+  const int ib = kb + 1 + blockIdx.x;
+  if (ib * NB < Np) load_tile(Ls, A + (size_t)l * Np * Np + (size_t)ib * NB * Np + kb * NB, Np);
   __syncthreads();
   if (blockIdx.x == 0) {
     float* Yl = Y + (size_t)l * ncol * Np;
     for (int i = threadIdx.x; i < ncol * NB; i += blockDim.x) {
-      int t = i / NB, r = i - t * NB;
-      Yl[(size_t)t * Np + kb * NB + r] = yk[t][r];
+      const int t = i / NB, r = i - t * NB;
+      Yl[(size_t)t * Np + kb * NB + r] = Bs[r][t];
     }
   }
-  const int ib = kb + 1 + blockIdx.x;
   if (ib * NB >= Np) return;
-  load_tile(Lt, A + (size_t)l * Np * Np + (size_t)ib * NB * Np + kb * NB, Np);
-  __syncthreads();
-  for (int i = threadIdx.x; i < ncol * NB; i += blockDim.x) {
-    int t = i / NB, r = i - t * NB;
-    float s = 0.f;
-    for (int k = 0; k < NB; ++k) s += Lt[r * LDT + k] * yk[t][k];
-    Rl[(size_t)t * Np + ib * NB + r] -= s;
-  }
+  mfma_64xK<false, NCT>(Ls, Bs, acc);
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int t = ct * 16 + li;
+      if (t < ncol) Rl[(size_t)t * Np + ib * NB + 16 * w + 4 * lk + v] -= acc[ct][v];
+    }
 }
 
-// Backward step kb: x_kb = inv(L_kk)^T y_kb (block 0 writes X); rows jb < kb: y_jb -= L[kb][jb]^T x_kb.
-__global__ __launch_bounds__(256) void k_bwd_step(const float* __restrict__ A, int Np, int kb,
+// Backward step kb of L^T x = y: x_kb = inv(L_kk)^T y_kb (block 0 writes X); block x
+// updates rows jb = x < kb: y_jb -= L[kb][jb]^T x_kb.
+template <int NCT>
+__global__ __launch_bounds__(256) void k_bwd_mfma(const float* __restrict__ A, int Np, int kb,
                                                   const float* __restrict__ Linv, float* __restrict__ Yv,
                                                   float* __restrict__ X, int ncol) {
-  __shared__ float Lt[NB * LDT];
-  __shared__ float yk[32][NB];
-  __shared__ float xk[32][NB];
+  __shared__ float Ls[NB * LDT];
+  __shared__ float Bs[NB][LDB];
   const int l = blockIdx.y;
-  const float* Li = Linv + ((size_t)l * (Np / NB) + kb) * NB * NB;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
   float* Yl = Yv + (size_t)l * ncol * Np;
-  for (int i = threadIdx.x; i < ncol * NB; i += blockDim.x) {
-    int t = i / NB, r = i - t * NB;
-    yk[t][r] = Yl[(size_t)t * Np + kb * NB + r];
+  for (int i = threadIdx.x; i < NB * 16 * NCT; i += blockDim.x) {
+    const int t = i / NB, k = i - t * NB;
+    Bs[k][t] = t < ncol ? Yl[(size_t)t * Np + kb * NB + k] : 0.f;
   }
-  load_tile(Lt, Li, NB);
+  load_tile(Ls, Linv + ((size_t)l * (Np / NB) + kb) * NB * NB, NB);
   __syncthreads();
-  for (int i = threadIdx.x; i < ncol * NB; i += blockDim.x) {
-    int t = i / NB, r = i - t * NB;
-    float s = 0.f;
-    for (int k = r; k < NB; ++k) s += Lt[k * LDT + r] * yk[t][k];
-    xk[t][r] = s;
-  }
+  floatx4 acc[NCT];
+  mfma_64xK<true, NCT>(Ls, Bs, acc);
+  __syncthreads();
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Bs[16 * w + 4 * lk + v][ct * 16 + li] = acc[ct][v];
+  const int jb = blockIdx.x;
+  if (jb < kb) load_tile(Ls, A + (size_t)l * Np * Np + (size_t)kb * NB * Np + jb * NB, Np);
   __syncthreads();
   if (blockIdx.x == 0) {
     float* Xl = X + (size_t)l * ncol * Np;
     for (int i = threadIdx.x; i < ncol * NB; i += blockDim.x) {
-      int t = i / NB, r = i - t * NB;
-      Xl[(size_t)t * Np + kb * NB + r] = xk[t][r];
+      const int t = i / NB, r = i - t * NB;
+      Xl[(size_t)t * Np + kb * NB + r] = Bs[r][t];
     }
   }
-  const int jb = blockIdx.x;
   if (jb >= kb) return;
-  load_tile(Lt, A + (size_t)l * Np * Np + (size_t)kb * NB * Np + jb * NB, Np);
-  __syncthreads();
-  for (int i = threadIdx.x; i < ncol * NB; i += blockDim.x) {
-    int t = i / NB, r = i - t * NB;
-    float s = 0.f;
-    for (int k = 0; k < NB; ++k) s += Lt[k * LDT + r] * xk[t][k];
-    Yl[(size_t)t * Np + jb * NB + r] -= s;
-  }
+  mfma_64xK<true, NCT>(Ls, Bs, acc);
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int t = ct * 16 + li;
+      if (t < ncol) Yl[(size_t)t * Np + jb * NB + 16 * w + 4 * lk + v] -= acc[ct][v];
+    }
 }
+
 
 // ------------------------------------------------------------------ FP64 residual
 // Rres[l][t] = Bre[t] - (H64 + lambda_l diag(preal)) X[l][t], for all (l, t) at once:
@@ -699,15 +728,24 @@ static fk_status factor_all(fk_ctx* ctx, const SolveLayout& s) {
 // D32 = A^-1 R32 per lambda (ncol = ntgt columns each), through Y32.
 static fk_status trsm_all(fk_ctx* ctx, const SolveLayout& s, float* R, float* Y, float* X) {
   const int nb = s.Np / NB;
+  const bool two = s.ntgt > 16;
   for (int kb = 0; kb < nb; ++kb) {
     int g = std::max(1, nb - kb - 1);
-    hipLaunchKernelGGL(k_fwd_step, dim3(g, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv, R, Y,
-                       s.ntgt);
+    if (two)
+      hipLaunchKernelGGL(k_fwd_mfma<2>, dim3(g, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv, R, Y,
+                         s.ntgt);
+    else
+      hipLaunchKernelGGL(k_fwd_mfma<1>, dim3(g, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv, R, Y,
+                         s.ntgt);
   }
   for (int kb = nb - 1; kb >= 0; --kb) {
     int g = std::max(1, kb);
-    hipLaunchKernelGGL(k_bwd_step, dim3(g, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv, Y, X,
-                       s.ntgt);
+    if (two)
+      hipLaunchKernelGGL(k_bwd_mfma<2>, dim3(g, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv, Y, X,
+                         s.ntgt);
+    else
+      hipLaunchKernelGGL(k_bwd_mfma<1>, dim3(g, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv, Y, X,
+                         s.ntgt);
   }
   FK_HIP(hipGetLastError());
   return FK_OK;

@@ -100,8 +100,9 @@ fk_status reset_flags(fk_ctx* ctx);
 // MFMA spread for 8..16 weight channels over MB x MB-cell bins (spread_mfma.hip).
 int spread_mfma_bin();
 bool spread_mfma_ok(int nw, int W);
-fk_status launch_spread_mfma(hipStream_t st, int W, const uint32_t* rec, int nw, const uint64_t* start, int nbx,
-                             int nb, int nf, int fb, double beta, int64_t n, double* grid);
+fk_status launch_spread_mfma(hipStream_t st, int W, const uint32_t* crd, const uint32_t* wts, int nw,
+                             const uint64_t* start, int nbx, int nb, int nf, int fb, double beta, int64_t n,
+                             double* grid);
 
 }  // namespace fk
 

@@ -352,7 +352,7 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const void* __restrict__ X
                                                       int nbx, const uint32_t* __restrict__ cnt,
                                                       const uint64_t* __restrict__ start, int nblk,
                                                       int64_t chunk, uint32_t* __restrict__ rec,
-                                                      int* flags) {
+                                                      uint32_t* __restrict__ wts, int* flags) {
   extern __shared__ unsigned long long nextpos[];
   const int nb = nbx * nbx;
   const uint32_t* row = cnt + (int64_t)blockIdx.x * nb;
@@ -370,25 +370,38 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const void* __restrict__ X
     if (!ok) continue;
     int b = ((U1 >> fb) >> tshift) * nbx + ((U2 >> fb) >> tshift);
     uint64_t pos = atomicAdd(&nextpos[b], 1ull);
-    uint32_t* o = rec + pos * R;
-    // build the record in registers, store it as 8-byte words when R is even
-    // (whole-record stores per lane instead of one 4-byte store per channel)
-    uint32_t wr[2 + 32];
-    wr[0] = U1;
-    wr[1] = U2;
-    for (int c = 0; c < nw; ++c) {
-      float wc = load_weight(Y, dt, (int64_t)c * n + j);
-      if (!(wc == wc) || isinf(wc)) {
-        atomicOr(&flags[kFlagNaN], 1);
-        wc = 0.f;
+    if (wts) {
+      // split layout: coordinates (8 B) and a 64-byte-aligned block of 16 weights
+      // (zero padded), written by one lane as four 16-byte stores, so every 64-byte
+      // sector of the weight array is written whole.  The 16 weights stay in
+      // registers (compile-time indices).
+      uint32_t v[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        float wc = c < nw ? load_weight(Y, dt, (int64_t)c * n + j) : 0.f;
+        if (!(wc == wc) || isinf(wc)) {
+          atomicOr(&flags[kFlagNaN], 1);
+          wc = 0.f;
+        }
+        v[c] = __float_as_uint(wc);
       }
-      wr[2 + c] = __float_as_uint(wc);
-    }
-    if ((R & 1) == 0) {
-      uint2* o2 = reinterpret_cast<uint2*>(o);
-      for (int c = 0; c < R / 2; ++c) o2[c] = make_uint2(wr[2 * c], wr[2 * c + 1]);
+      reinterpret_cast<uint2*>(rec)[pos] = make_uint2(U1, U2);
+      uint4* wq = reinterpret_cast<uint4*>(wts + pos * 16);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) wq[q] = make_uint4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
     } else {
-      for (int c = 0; c < R; ++c) o[c] = wr[c];
+      // record [U1, U2, w_0 .. w_{nw-1}]: one store per word
+      uint32_t* o = rec + pos * R;
+      o[0] = U1;
+      o[1] = U2;
+      for (int c = 0; c < nw; ++c) {
+        float wc = load_weight(Y, dt, (int64_t)c * n + j);
+        if (!(wc == wc) || isinf(wc)) {
+          atomicOr(&flags[kFlagNaN], 1);
+          wc = 0.f;
+        }
+        o[2 + c] = __float_as_uint(wc);
+      }
     }
   }
 }
@@ -573,7 +586,12 @@ size_t type1_workspace(int d, int64_t n, int nw, int K, double eps) {
     cv.take<uint32_t>((size_t)g.nb * g.nblk);
     cv.take<uint32_t>((size_t)g.nb);
     cv.take<uint64_t>((size_t)g.nb + 1);
-    cv.take<uint32_t>((size_t)n * (2 + nw));
+    if (use_mfma_spread(nw)) {
+      cv.take<uint32_t>((size_t)n * 2);
+      cv.take<uint32_t>((size_t)n * 16);
+    } else {
+      cv.take<uint32_t>((size_t)n * (2 + nw));
+    }
   }
   return cv.off + 256;
 }
@@ -659,7 +677,9 @@ fk_status type1(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int64
   uint32_t* cnt = cv.take<uint32_t>((size_t)g.nb * g.nblk);
   uint32_t* totals = cv.take<uint32_t>((size_t)g.nb);
   uint64_t* start = cv.take<uint64_t>((size_t)g.nb + 1);
-  uint32_t* rec = cv.take<uint32_t>((size_t)n * (2 + nw));
+  const bool split = use_mfma_spread(nw);
+  uint32_t* rec = cv.take<uint32_t>((size_t)n * (split ? 2 : 2 + nw));
+  uint32_t* wts = split ? cv.take<uint32_t>((size_t)n * 16) : nullptr;
   if (!cv.ok()) return FK_ENOMEM;
   if (info) info->bin = g.T;
   FK_HIP(hipEventRecord(ev[0], ctx->stream));
@@ -670,13 +690,13 @@ fk_status type1(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int64
   hipLaunchKernelGGL(k_scan_cols, dim3((g.nb + 255) / 256), dim3(256), 0, ctx->stream, cnt, g.nb, g.nblk, totals);
   hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, ctx->stream, totals, g.nb, start);
   hipLaunchKernelGGL(k_bin_scatter, dim3(g.nblk), dim3(1024), sizeof(unsigned long long) * g.nb, ctx->stream, X, dt, n,
-                     xstride, Y, nw, nf, fb, scale, g.tshift, g.nbx, cnt, start, g.nblk, g.chunk, rec,
+                     xstride, Y, nw, nf, fb, scale, g.tshift, g.nbx, cnt, start, g.nblk, g.chunk, rec, wts,
                      ctx->flags);
   FK_HIP(hipGetLastError());
   FK_HIP(hipEventRecord(ev[1], ctx->stream));
   int64_t per_bin = (n + g.nb - 1) / g.nb;
   if (use_mfma_spread(nw) && spread_mfma_ok(nw, W) && g.T == spread_mfma_bin()) {
-    fk_status s2 = launch_spread_mfma(ctx->stream, W, rec, nw, start, g.nbx, g.nb, nf, fb, plan.beta, n, grid);
+    fk_status s2 = launch_spread_mfma(ctx->stream, W, rec, wts, nw, start, g.nbx, g.nb, nf, fb, plan.beta, n, grid);
     if (s2 != FK_OK) return s2;
     if (info) info->bin = -g.T;   // negative: MFMA spread over T x T bins
   } else {

@@ -7,9 +7,11 @@
 // dense matrix product on the matrix cores:
 //
 // * bins are MB x MB grid cells (MB = 4), counting-sorted beforehand so a bin's
-//   points are contiguous records [U1, U2, w_1..w_T];
-// * a workgroup takes a slice of one bin and stages batches of MP records in
-//   LDS; each point's window start (l1, l2) relative to the bin takes
+//   points are contiguous: fixed-point coordinates [U1, U2] (8 B) and a
+//   64-byte block of 16 FP32 weights (zero padded) per point;
+// * a workgroup takes a slice of one bin and stages batches of MP points in
+//   LDS (the next batch is loaded into registers while the current one is
+//   processed); each point's window start (l1, l2) relative to the bin takes
 //   (MB+1)^2 = 25 values, and the batch is counting-sorted by it;
 // * the exponential-of-semicircle values psi1[0..w), psi2[0..w) of every point
 //   are evaluated once per point into LDS;
@@ -33,9 +35,11 @@ namespace {
 constexpr int MB = 4;                       // bin edge in grid cells
 constexpr int MG = (MB + 1) * (MB + 1);     // window-start groups per bin
 constexpr int NWAVE = 8;
+constexpr int NTHR = 64 * NWAVE;
 constexpr int MGW = (MG + NWAVE - 1) / NWAVE;   // groups per wave
 constexpr int MP = 512;                     // points per LDS batch
 constexpr int MFLUSH = 8;                   // batches between FP32 -> FP64 flushes
+constexpr int WQ = MP * 4 / NTHR;           // 16-byte weight quads per thread per batch
 
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
@@ -54,24 +58,43 @@ __device__ __forceinline__ void win_start(uint32_t U, int fb, int w, int* i0, fl
   *s0 = (float)((double)((c << fb) - (int64_t)U) * (1.0 / (double)one));
 }
 
+struct Prefetch {
+  uint2 c;
+  uint4 w[WQ];
+};
+
+// Load the batch [base, base + np) of coordinates and weight blocks into registers.
+__device__ __forceinline__ void prefetch(Prefetch& pf, const uint2* __restrict__ crd, const uint4* __restrict__ wts,
+                                         uint64_t base, int np, int tid) {
+  if (tid < np) pf.c = crd[base + tid];
+#pragma unroll
+  for (int q = 0; q < WQ; ++q) {
+    const int i = tid + q * NTHR;
+    if (i < np * 4) pf.w[q] = wts[base * 4 + i];
+  }
+}
+
 template <int W>
-__global__ __launch_bounds__(512) void k_spread_mfma(const uint32_t* __restrict__ rec, int nw,
-                                                     const uint64_t* __restrict__ start, int nbx, int nf, int fb,
-                                                     float beta, int slices, double* __restrict__ grid) {
+__global__ __launch_bounds__(NTHR) void k_spread_mfma(const uint2* __restrict__ crd, const uint4* __restrict__ wts,
+                                                      int nw, const uint64_t* __restrict__ start, int nbx, int nf,
+                                                      int fb, float beta, int slices, double* __restrict__ grid) {
   static_assert(W <= 8, "the window must fit 4 column tiles and 16 lanes");
+  static_assert(MP <= NTHR, "one coordinate per thread per batch");
   constexpr int S = MB + W;
   extern __shared__ double smem_d[];
   const int C = nw + 1;
-  const int R = 2 + nw;
   const float two_over_w = 2.0f / (float)W;
+  const int subn = (S * S * C + 1) & ~1;                          // keep 16-byte alignment below
   double* sub = smem_d;                                            // S*S*C doubles
-  float* psi = reinterpret_cast<float*>(sub + S * S * C);          // MP*16 floats
-  uint32_t* stage = reinterpret_cast<uint32_t*>(psi + MP * 16);    // MP*R words
-  uint16_t* perm = reinterpret_cast<uint16_t*>(stage + MP * R);    // MP
+  float* psi = reinterpret_cast<float*>(sub + subn);               // MP*16 floats
+  uint4* sw = reinterpret_cast<uint4*>(psi + MP * 16);             // MP*4 quads (16 weights per point)
+  uint2* sc = reinterpret_cast<uint2*>(sw + MP * 4);               // MP coordinates
+  uint16_t* perm = reinterpret_cast<uint16_t*>(sc + MP);           // MP
   uint16_t* rank = perm + MP;                                      // MP
   uint8_t* keyv = reinterpret_cast<uint8_t*>(rank + MP);           // MP
   int* gcount = reinterpret_cast<int*>(keyv + MP);                 // 32
   int* gstart = gcount + 32;                                       // 32
+  const float* swf = reinterpret_cast<const float*>(sw);
 
   const int b = blockIdx.x / slices;
   const int sl = blockIdx.x - b * slices;
@@ -83,7 +106,7 @@ __global__ __launch_bounds__(512) void k_spread_mfma(const uint32_t* __restrict_
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int bx = b / nbx, by = b - bx * nbx;
   const int o1 = bx * MB - W / 2, o2 = by * MB - W / 2;   // window starts lie in [o, o + MB]
-  for (int i = tid; i < S * S * C; i += blockDim.x) sub[i] = 0.0;
+  for (int i = tid; i < S * S * C; i += NTHR) sub[i] = 0.0;
 
   floatx4_t acc[MGW][4];
   float ones[MGW][4];
@@ -96,7 +119,6 @@ __global__ __launch_bounds__(512) void k_spread_mfma(const uint32_t* __restrict_
     }
 
   const int kslot = lane >> 4, jj = lane & 15;
-  // per-lane window cell of each column tile (constant)
   int ca[4], cb[4];
   bool cin[4];
 #pragma unroll
@@ -106,28 +128,29 @@ __global__ __launch_bounds__(512) void k_spread_mfma(const uint32_t* __restrict_
     ca[t] = cin[t] ? cell / W : 0;
     cb[t] = cin[t] ? cell - (cell / W) * W : 0;
   }
+
+  Prefetch pf;
+  prefetch(pf, crd, wts, q0, (int)min<uint64_t>(MP, q1 - q0), tid);
   int batch = 0;
   for (uint64_t base = q0; base < q1; base += MP, ++batch) {
     const int np = (int)min<uint64_t>(MP, q1 - base);
-    __syncthreads();
-    {
-      // stage the batch: whole records are contiguous; 8-byte loads when R is even
-      const uint32_t* src = rec + base * R;
-      if ((R & 1) == 0) {
-        const uint2* s2 = reinterpret_cast<const uint2*>(src);
-        uint2* d2 = reinterpret_cast<uint2*>(stage);
-        for (int i = tid; i < np * R / 2; i += blockDim.x) d2[i] = s2[i];
-      } else {
-        for (int i = tid; i < np * R; i += blockDim.x) stage[i] = src[i];
-      }
+    __syncthreads();   // the previous batch is fully consumed
+    if (tid < np) sc[tid] = pf.c;
+#pragma unroll
+    for (int q = 0; q < WQ; ++q) {
+      const int i = tid + q * NTHR;
+      if (i < np * 4) sw[i] = pf.w[q];
     }
     if (tid < 32) gcount[tid] = 0;
+    if (base + MP < q1) prefetch(pf, crd, wts, base + MP, (int)min<uint64_t>(MP, q1 - base - MP), tid);
     __syncthreads();
-    for (int p = tid; p < np; p += blockDim.x) {
+    if (tid < np) {
+      const int p = tid;
       int i1, i2;
       float s1, s2;
-      win_start(stage[p * R], fb, W, &i1, &s1);
-      win_start(stage[p * R + 1], fb, W, &i2, &s2);
+      const uint2 U = sc[p];
+      win_start(U.x, fb, W, &i1, &s1);
+      win_start(U.y, fb, W, &i2, &s2);
       const int k = (i1 - o1) * (MB + 1) + (i2 - o2);
       keyv[p] = (uint8_t)k;
       rank[p] = (uint16_t)atomicAdd(&gcount[k], 1);
@@ -150,7 +173,7 @@ __global__ __launch_bounds__(512) void k_spread_mfma(const uint32_t* __restrict_
       if (lane < MG) gstart[lane] = x - v;
     }
     __syncthreads();
-    for (int p = tid; p < np; p += blockDim.x) perm[gstart[keyv[p]] + rank[p]] = (uint16_t)p;
+    if (tid < np) perm[gstart[keyv[tid]] + rank[tid]] = (uint16_t)tid;
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < MGW; ++s) {
@@ -161,7 +184,7 @@ __global__ __launch_bounds__(512) void k_spread_mfma(const uint32_t* __restrict_
         const int idx = c0 + kslot;
         const bool valid = idx < cnt;
         const int p = valid ? perm[gs + idx] : 0;
-        const float aop = (valid && jj < nw) ? __uint_as_float(stage[p * R + 2 + jj]) : 0.f;
+        const float aop = (valid && jj < nw) ? swf[p * 16 + jj] : 0.f;
         const float* ps = psi + p * 16;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
@@ -200,7 +223,7 @@ __global__ __launch_bounds__(512) void k_spread_mfma(const uint32_t* __restrict_
     }
   }
   __syncthreads();
-  for (int i = tid; i < S * S * C; i += blockDim.x) {
+  for (int i = tid; i < S * S * C; i += NTHR) {
     double v = sub[i];
     if (v == 0.0) continue;
     int c = i % C;
@@ -214,8 +237,8 @@ __global__ __launch_bounds__(512) void k_spread_mfma(const uint32_t* __restrict_
 }
 
 size_t lds_bytes(int W, int nw) {
-  const int S = MB + W, C = nw + 1, R = 2 + nw;
-  size_t b = sizeof(double) * S * S * C + sizeof(float) * MP * 16 + sizeof(uint32_t) * MP * R +
+  const int S = MB + W, C = nw + 1;
+  size_t b = sizeof(double) * ((S * S * C + 1) & ~1) + sizeof(float) * MP * 16 + 16 * MP * 4 + 8 * MP +
              2 * sizeof(uint16_t) * MP + MP;
   b = (b + 3) & ~size_t(3);
   return b + 64 * sizeof(int);
@@ -227,25 +250,28 @@ int spread_mfma_bin() { return MB; }
 
 bool spread_mfma_ok(int nw, int W) { return nw >= 8 && nw <= 16 && W >= 4 && W <= 8; }
 
-fk_status launch_spread_mfma(hipStream_t st, int W, const uint32_t* rec, int nw, const uint64_t* start, int nbx,
-                             int nb, int nf, int fb, double beta, int64_t n, double* grid) {
+fk_status launch_spread_mfma(hipStream_t st, int W, const uint32_t* crd, const uint32_t* wts, int nw,
+                             const uint64_t* start, int nbx, int nb, int nf, int fb, double beta, int64_t n,
+                             double* grid) {
   const int64_t per_bin = (n + nb - 1) / nb;
   const int slices = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (per_bin + 16383) / 16384));
   const int blocks = nb * slices;
   const size_t lds = lds_bytes(W, nw);
   if (lds > 160 * 1024) return FK_EINVAL;
   const float bt = (float)beta;
+  const uint2* c2 = reinterpret_cast<const uint2*>(crd);
+  const uint4* w4 = reinterpret_cast<const uint4*>(wts);
   switch (W) {
-    case 4: hipLaunchKernelGGL(k_spread_mfma<4>, dim3(blocks), dim3(64 * NWAVE), lds, st, rec, nw, start, nbx, nf, fb, bt,
-                               slices, grid); break;
-    case 5: hipLaunchKernelGGL(k_spread_mfma<5>, dim3(blocks), dim3(64 * NWAVE), lds, st, rec, nw, start, nbx, nf, fb, bt,
-                               slices, grid); break;
-    case 6: hipLaunchKernelGGL(k_spread_mfma<6>, dim3(blocks), dim3(64 * NWAVE), lds, st, rec, nw, start, nbx, nf, fb, bt,
-                               slices, grid); break;
-    case 7: hipLaunchKernelGGL(k_spread_mfma<7>, dim3(blocks), dim3(64 * NWAVE), lds, st, rec, nw, start, nbx, nf, fb, bt,
-                               slices, grid); break;
-    case 8: hipLaunchKernelGGL(k_spread_mfma<8>, dim3(blocks), dim3(64 * NWAVE), lds, st, rec, nw, start, nbx, nf, fb, bt,
-                               slices, grid); break;
+    case 4: hipLaunchKernelGGL(k_spread_mfma<4>, dim3(blocks), dim3(NTHR), lds, st, c2, w4, nw, start, nbx, nf, fb,
+                               bt, slices, grid); break;
+    case 5: hipLaunchKernelGGL(k_spread_mfma<5>, dim3(blocks), dim3(NTHR), lds, st, c2, w4, nw, start, nbx, nf, fb,
+                               bt, slices, grid); break;
+    case 6: hipLaunchKernelGGL(k_spread_mfma<6>, dim3(blocks), dim3(NTHR), lds, st, c2, w4, nw, start, nbx, nf, fb,
+                               bt, slices, grid); break;
+    case 7: hipLaunchKernelGGL(k_spread_mfma<7>, dim3(blocks), dim3(NTHR), lds, st, c2, w4, nw, start, nbx, nf, fb,
+                               bt, slices, grid); break;
+    case 8: hipLaunchKernelGGL(k_spread_mfma<8>, dim3(blocks), dim3(NTHR), lds, st, c2, w4, nw, start, nbx, nf, fb,
+                               bt, slices, grid); break;
     default: return FK_EINVAL;
   }
   return hipGetLastError() == hipSuccess ? FK_OK : FK_EHIP;
