@@ -173,6 +173,10 @@ fk_status fk_heldout_mse(fk_ctx* ctx, int d, int m, int ntgt, int nlam, const do
                          const double* bv, const double* yv2, double* mse_out,
                          void* ws, size_t ws_bytes);
 
+/* fk_mean_square: out[t] = n^-1 sum_j Y[t][j]^2 in FP64 (device, ntgt doubles), the constant
+ * term of the held-out loss above.  Y is device [ntgt][n] (fp32 or fp64); n >= 1. */
+fk_status fk_mean_square(fk_ctx* ctx, int ntgt, int64_t n, fk_dtype dtype, const void* Y, double* out);
+
 /* fk_fit_backward: given grad_mse[l][t] = dLoss/dmse[l][t] (device, nlam x ntgt),
  * with g = Sigma_v theta - bv and u = A_l^-1 g (adjoint solve with the kept factors):
  *   grad_loglam[l] = sum_t grad_mse[l][t] * (-2 lambda_l Re(u^* P theta))      (device, nlam)

@@ -219,6 +219,18 @@ def heldout_mse(Mv: torch.Tensor, bv: torch.Tensor, yv2: torch.Tensor, m: int, n
     return out
 
 
+def mean_square(Y: torch.Tensor, ctx: Optional[Context] = None) -> torch.Tensor:
+    """[T] float64: mean of Y[t]**2 over the points (the constant term of the held-out MSE)."""
+    ctx = ctx or default_context(Y.device.index or 0)
+    ctx.bind_stream()
+    Y = _dev_tensor(Y, "Y")
+    Y2 = Y.reshape(-1, Y.shape[-1]) if Y.dim() > 1 else Y.reshape(1, -1)
+    out = torch.empty(Y2.shape[0], dtype=torch.float64, device=Y.device)
+    _lib.check(ctx.lib.fk_mean_square(ctx.h, Y2.shape[0], Y2.shape[1], _dtype_code(Y2), _ptr(Y2), _ptr(out)),
+               "fk_mean_square")
+    return out
+
+
 def fit_backward(grad_mse: torch.Tensor, m: int, d: int, ctx: Context, want_theta: bool = False):
     """Gradients (log lambda [nlam], p [N], theta [nlam, T, N] or None) of sum(grad_mse * mse)."""
     ctx.bind_stream()
@@ -318,8 +330,9 @@ class KernelRidgeGridLoss(torch.autograd.Function):
         fkc = default_context(X.device.index or 0)
         lams = torch.exp(loglam.detach()).cpu().tolist()
         theta = fit(X, Y, m, lams, penalty="diag", p=p.detach(), ctx=fkc)
-        Mv, bv = gram(Xv, Yv, m, ctx=_validation_context(fkc))
-        yv2 = (Yv.double() ** 2).mean(dim=1)
+        vctx = _validation_context(fkc)
+        Mv, bv = gram(Xv, Yv, m, ctx=vctx)
+        yv2 = mean_square(Yv, vctx)
         mse = heldout_mse(Mv, bv, yv2, m, len(lams), fkc)
         ctx_.fkc = fkc
         ctx_.m = m

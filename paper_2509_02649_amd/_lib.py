@@ -81,6 +81,7 @@ EXPORTS = {
                                   C.c_size_t, C.POINTER(fk_fit_info)]),
     "fk_generate_uniform": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int, C.c_int64, C.c_int64,
                                       C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]),
+    "fk_mean_square": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int, C.c_void_p, C.c_void_p]),
     "fk_generate_targets": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int, C.c_int64, C.c_int64, C.c_void_p,
                                       C.c_double, C.c_void_p]),
 }

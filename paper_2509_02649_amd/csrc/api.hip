@@ -385,6 +385,49 @@ extern "C" fk_status fk_heldout_mse(fk_ctx* ctx, int d, int m, int ntgt, int nla
   return FK_OK;
 }
 
+namespace fk {
+// out[t] += sum_j Y[t][j]^2 over this workgroup's part of row t (FP64; grid.y = t).
+template <typename TY>
+__global__ __launch_bounds__(256) void k_sum_squares(const TY* __restrict__ Y, int64_t n, double* __restrict__ out) {
+  __shared__ double part[4];
+  const TY* y = Y + (int64_t)blockIdx.y * n;
+  double s = 0.0;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    const double v = (double)y[j];
+    s += v * v;
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(&out[blockIdx.y], part[0] + part[1] + part[2] + part[3]);
+}
+__global__ void k_fill_zero(double* __restrict__ p, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0.0;
+}
+__global__ void k_scale(double* __restrict__ p, int count, double a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] *= a;
+}
+}  // namespace fk
+
+extern "C" fk_status fk_mean_square(fk_ctx* ctx, int ntgt, int64_t n, fk_dtype dtype, const void* Y, double* out) {
+  if (!ctx || !Y || !out || ntgt < 1 || ntgt > 65535 || n < 1 || (dtype != FK_F32 && dtype != FK_F64))
+    return FK_EINVAL;
+  FK_HIP(hipSetDevice(ctx->device));
+  const int blocks = (int)std::min<int64_t>(1024, (n + 255) / 256);
+  hipLaunchKernelGGL(k_fill_zero, dim3((ntgt + 255) / 256), dim3(256), 0, ctx->stream, out, ntgt);
+  if (dtype == FK_F32)
+    hipLaunchKernelGGL(k_sum_squares<float>, dim3(blocks, ntgt), dim3(256), 0, ctx->stream,
+                       static_cast<const float*>(Y), n, out);
+  else
+    hipLaunchKernelGGL(k_sum_squares<double>, dim3(blocks, ntgt), dim3(256), 0, ctx->stream,
+                       static_cast<const double*>(Y), n, out);
+  hipLaunchKernelGGL(k_scale, dim3((ntgt + 255) / 256), dim3(256), 0, ctx->stream, out, ntgt, 1.0 / (double)n);
+  FK_HIP(hipGetLastError());
+  return FK_OK;
+}
+
 extern "C" fk_status fk_fit_backward(fk_ctx* ctx, int d, int m, int ntgt, int nlam, const double* grad_mse,
                                      double* grad_loglam, double* grad_p, double* grad_theta, void* ws,
                                      size_t ws_bytes) {

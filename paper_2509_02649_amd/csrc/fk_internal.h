@@ -104,6 +104,23 @@ fk_status launch_spread_mfma(hipStream_t st, int W, const uint32_t* crd, const u
                              const uint64_t* start, int nbx, int nb, int nf, int fb, double beta, int64_t n,
                              double* grid);
 
+// Two-pass bin sort for the MFMA spread (sort2.hip): scratch buffers carved from
+// the caller's workspace, and the sort itself (bin starts in start[0..nbx^2]).
+struct Sort2Bufs {
+  uint32_t* cnt1 = nullptr;
+  uint32_t* off1 = nullptr;
+  uint64_t* start1 = nullptr;
+  uint32_t* cnt2 = nullptr;
+  uint32_t* off2 = nullptr;
+  uint32_t* crd1 = nullptr;
+  uint32_t* wts1 = nullptr;
+};
+bool sort2_ok(int nbx);
+void sort2_carve(Carve& cv, int64_t n, int nbx, Sort2Bufs* b);
+fk_status sort2(hipStream_t st, const void* X, fk_dtype dt, int64_t n, int64_t xstride, const void* Y, int nw,
+                int nf, int fb, double scale, int tshift, int nbx, const Sort2Bufs& b, uint32_t* crd,
+                uint32_t* wts, uint64_t* start, int* flags);
+
 }  // namespace fk
 
 struct fk_ctx {

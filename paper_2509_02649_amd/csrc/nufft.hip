@@ -30,9 +30,11 @@
 //   even at the highest frequency.
 // * The FFT and deconvolution run in FP64 (the grids are tiny).
 #include "fk_internal.h"
+#include "fk_device.h"
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 namespace fk {
@@ -179,29 +181,6 @@ __device__ __forceinline__ float es_eval(float s, EsDev es) {
   return __expf(es.beta * (__fsqrt_rn(r) - 1.0f));
 }
 
-// Fold a coordinate onto [-pi, pi) and convert to a fixed-point grid
-// coordinate U = round((x + pi) / h * 2^fb).  Returns false (and sets flags)
-// for NaN or |x| outside [-2 pi, 2 pi).
-__device__ __forceinline__ bool to_fixed(double x, double scale, uint32_t nf_fix, uint32_t* U,
-                                         int* flags) {
-  if (!(x == x) || isinf(x)) {
-    atomicOr(&flags[kFlagNaN], 1);
-    return false;
-  }
-  const double two_pi = 6.283185307179586476925;
-  if (x < -two_pi || x >= two_pi) {
-    atomicOr(&flags[kFlagRange], 1);
-    return false;
-  }
-  if (x < -3.14159265358979323846) x += two_pi;
-  if (x >= 3.14159265358979323846) x -= two_pi;
-  double u = (x + 3.14159265358979323846) * scale;   // in [0, nf * 2^fb]
-  uint64_t v = (uint64_t)__double2ll_rn(u);
-  if (v >= nf_fix) v -= nf_fix;                       // x == pi - tiny rounding up to nf
-  *U = (uint32_t)v;
-  return true;
-}
-
 // Window start i0 = ceil(u - w/2) and first offset s0 = i0 - u (grid units) from
 // a fixed-point coordinate with fb fraction bits.
 __device__ __forceinline__ void window_start(uint32_t U, int fb, int w, int* i0, float* s0) {
@@ -210,13 +189,6 @@ __device__ __forceinline__ void window_start(uint32_t U, int fb, int w, int* i0,
   int64_t c = (V >= 0) ? ((V + one - 1) >> fb) : -((-V) >> fb);
   *i0 = (int)c;
   *s0 = (float)((double)((c << fb) - (int64_t)U) * (1.0 / (double)one));
-}
-
-__device__ __forceinline__ double load_coord(const void* X, fk_dtype dt, int64_t idx) {
-  return dt == FK_F64 ? static_cast<const double*>(X)[idx] : (double)static_cast<const float*>(X)[idx];
-}
-__device__ __forceinline__ float load_weight(const void* Y, fk_dtype dt, int64_t idx) {
-  return dt == FK_F64 ? (float)static_cast<const double*>(Y)[idx] : static_cast<const float*>(Y)[idx];
 }
 
 // ------------------------------------------------------------------ 1-D spread (whole grid in LDS)
@@ -350,15 +322,13 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const void* __restrict__ X
                                                       int64_t xstride, const void* __restrict__ Y,
                                                       int nw, int nf, int fb, double scale, int tshift,
                                                       int nbx, const uint32_t* __restrict__ cnt,
-                                                      const uint64_t* __restrict__ start, int nblk,
-                                                      int64_t chunk, uint32_t* __restrict__ rec,
-                                                      uint32_t* __restrict__ wts, int* flags) {
+                                                      const uint64_t* __restrict__ start, int64_t chunk,
+                                                      uint32_t* __restrict__ rec, int* flags) {
   extern __shared__ unsigned long long nextpos[];
   const int nb = nbx * nbx;
   const uint32_t* row = cnt + (int64_t)blockIdx.x * nb;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) nextpos[i] = start[i] + row[i];
   __syncthreads();
-  (void)nblk;
   const int64_t beg = (int64_t)blockIdx.x * chunk;
   const int64_t end = min(n, beg + chunk);
   const uint32_t nf_fix = (uint32_t)nf << fb;
@@ -370,38 +340,16 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const void* __restrict__ X
     if (!ok) continue;
     int b = ((U1 >> fb) >> tshift) * nbx + ((U2 >> fb) >> tshift);
     uint64_t pos = atomicAdd(&nextpos[b], 1ull);
-    if (wts) {
-      // split layout: coordinates (8 B) and a 64-byte-aligned block of 16 weights
-      // (zero padded), written by one lane as four 16-byte stores, so every 64-byte
-      // sector of the weight array is written whole.  The 16 weights stay in
-      // registers (compile-time indices).
-      uint32_t v[16];
-#pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        float wc = c < nw ? load_weight(Y, dt, (int64_t)c * n + j) : 0.f;
-        if (!(wc == wc) || isinf(wc)) {
-          atomicOr(&flags[kFlagNaN], 1);
-          wc = 0.f;
-        }
-        v[c] = __float_as_uint(wc);
+    uint32_t* o = rec + pos * R;
+    o[0] = U1;
+    o[1] = U2;
+    for (int c = 0; c < nw; ++c) {
+      float wc = load_weight(Y, dt, (int64_t)c * n + j);
+      if (!(wc == wc) || isinf(wc)) {
+        atomicOr(&flags[kFlagNaN], 1);
+        wc = 0.f;
       }
-      reinterpret_cast<uint2*>(rec)[pos] = make_uint2(U1, U2);
-      uint4* wq = reinterpret_cast<uint4*>(wts + pos * 16);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) wq[q] = make_uint4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
-    } else {
-      // record [U1, U2, w_0 .. w_{nw-1}]: one store per word
-      uint32_t* o = rec + pos * R;
-      o[0] = U1;
-      o[1] = U2;
-      for (int c = 0; c < nw; ++c) {
-        float wc = load_weight(Y, dt, (int64_t)c * n + j);
-        if (!(wc == wc) || isinf(wc)) {
-          atomicOr(&flags[kFlagNaN], 1);
-          wc = 0.f;
-        }
-        o[2 + c] = __float_as_uint(wc);
-      }
+      o[2 + c] = __float_as_uint(wc);
     }
   }
 }
@@ -556,9 +504,9 @@ struct BinGeom {
 // Channels whose spread runs on MFMA (spread_mfma.hip): 8..16 weighted channels.
 static bool use_mfma_spread(int nw) { return nw >= 8 && nw <= 16; }
 
-static BinGeom bin_geom(int nf, int C, int64_t n) {
+// mf: the points go through the two-pass sort and the MFMA spread (MB x MB bins).
+static BinGeom bin_geom(int nf, int C, int64_t n, bool mf) {
   BinGeom g;
-  const bool mf = use_mfma_spread(C - 1);
   g.T = mf ? spread_mfma_bin() : ((C > 8) ? 16 : 32);
   if (g.T > nf) g.T = nf;
   g.tshift = ilog2(g.T);
@@ -582,13 +530,16 @@ size_t type1_workspace(int d, int64_t n, int nw, int K, double eps) {
   } else {
     cv.take<double>((size_t)C * nf * nf);          // FP64 grid
     cv.take<double>((size_t)C * nf * L * 2);        // row-FFT output
-    BinGeom g = bin_geom(nf, C, n);
+    // the MFMA layout (when the channel count allows it) is the larger of the two
+    BinGeom g = bin_geom(nf, C, n, use_mfma_spread(nw));
     cv.take<uint32_t>((size_t)g.nb * g.nblk);
     cv.take<uint32_t>((size_t)g.nb);
     cv.take<uint64_t>((size_t)g.nb + 1);
     if (use_mfma_spread(nw)) {
       cv.take<uint32_t>((size_t)n * 2);
       cv.take<uint32_t>((size_t)n * 16);
+      Sort2Bufs sb;
+      sort2_carve(cv, n, g.nbx, &sb);
     } else {
       cv.take<uint32_t>((size_t)n * (2 + nw));
     }
@@ -673,29 +624,39 @@ fk_status type1(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int64
   if (d != 2) return FK_EINVAL;
   double* grid = cv.take<double>((size_t)C * nf * nf);
   double* rowfft = cv.take<double>((size_t)C * nf * L * 2);
-  BinGeom g = bin_geom(nf, C, n);
+  const bool split = use_mfma_spread(nw) && spread_mfma_ok(nw, W) && sort2_ok(nf / spread_mfma_bin());
+  BinGeom g = bin_geom(nf, C, n, split);
   uint32_t* cnt = cv.take<uint32_t>((size_t)g.nb * g.nblk);
   uint32_t* totals = cv.take<uint32_t>((size_t)g.nb);
   uint64_t* start = cv.take<uint64_t>((size_t)g.nb + 1);
-  const bool split = use_mfma_spread(nw);
   uint32_t* rec = cv.take<uint32_t>((size_t)n * (split ? 2 : 2 + nw));
   uint32_t* wts = split ? cv.take<uint32_t>((size_t)n * 16) : nullptr;
+  Sort2Bufs sb;
+  if (split) sort2_carve(cv, n, g.nbx, &sb);
   if (!cv.ok()) return FK_ENOMEM;
   if (info) info->bin = g.T;
   FK_HIP(hipEventRecord(ev[0], ctx->stream));
   FK_HIP(hipMemsetAsync(grid, 0, sizeof(double) * C * nf * nf, ctx->stream));
-  hipLaunchKernelGGL(k_bin_count, dim3(g.nblk), dim3(256), sizeof(uint32_t) * g.nb, ctx->stream, X, dt, n,
-                     xstride, nf, fb, scale, g.tshift, g.nbx, cnt, g.nblk, g.chunk, ctx->flags);
-  FK_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_scan_cols, dim3((g.nb + 255) / 256), dim3(256), 0, ctx->stream, cnt, g.nb, g.nblk, totals);
-  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, ctx->stream, totals, g.nb, start);
-  hipLaunchKernelGGL(k_bin_scatter, dim3(g.nblk), dim3(1024), sizeof(unsigned long long) * g.nb, ctx->stream, X, dt, n,
-                     xstride, Y, nw, nf, fb, scale, g.tshift, g.nbx, cnt, start, g.nblk, g.chunk, rec, wts,
-                     ctx->flags);
+  if (split) {
+    // records for the MFMA spread: two-pass sort, coordinates and weight blocks
+    fk_status s2 = sort2(ctx->stream, X, dt, n, xstride, Y, nw, nf, fb, scale, g.tshift, g.nbx, sb, rec, wts, start,
+                         ctx->flags);
+    if (s2 != FK_OK) return s2;
+  } else {
+    hipLaunchKernelGGL(k_bin_count, dim3(g.nblk), dim3(256), sizeof(uint32_t) * g.nb, ctx->stream, X, dt, n,
+                       xstride, nf, fb, scale, g.tshift, g.nbx, cnt, g.nblk, g.chunk, ctx->flags);
+    FK_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_scan_cols, dim3((g.nb + 255) / 256), dim3(256), 0, ctx->stream, cnt, g.nb, g.nblk,
+                       totals);
+    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, ctx->stream, totals, g.nb, start);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(g.nblk), dim3(1024), sizeof(unsigned long long) * g.nb, ctx->stream, X,
+                       dt, n, xstride, Y, nw, nf, fb, scale, g.tshift, g.nbx, cnt, start, g.chunk, rec,
+                       ctx->flags);
+  }
   FK_HIP(hipGetLastError());
   FK_HIP(hipEventRecord(ev[1], ctx->stream));
   int64_t per_bin = (n + g.nb - 1) / g.nb;
-  if (use_mfma_spread(nw) && spread_mfma_ok(nw, W) && g.T == spread_mfma_bin()) {
+  if (split) {
     fk_status s2 = launch_spread_mfma(ctx->stream, W, rec, wts, nw, start, g.nbx, g.nb, nf, fb, plan.beta, n, grid);
     if (s2 != FK_OK) return s2;
     if (info) info->bin = -g.T;   // negative: MFMA spread over T x T bins

@@ -1,0 +1,390 @@
+// Two-pass bin sort of the point stream for the MFMA spread (8..16 weight channels).
+//
+// The matrix-core spread takes the points of one MB x MB-cell bin four at a time,
+// so the type-1 stage first orders the stream by bin: per point the fixed-point
+// grid coordinates [U1, U2] (8 B) and a 64-byte block of 16 FP32 weights (zero
+// padded).  A one-pass counting sort into the nbx^2 bins sends consecutive points
+// to unrelated addresses, and on HBM3E such scattered 8- and 64-byte writes run
+// far below the streaming rate.  Here the order is reached in two counting passes
+// over nbx buckets each (the bin row bx, then the bin column by inside a row).
+// A workgroup ranks a batch of BT = 1024 points by bucket in LDS, stages the
+// batch in bucket order, and writes each bucket's part as one contiguous run
+// (about BT / nbx points), so both passes write in runs and read in streams.
+//
+//   pass 1: X, Y (structure of arrays)          -> crd1 / wts1, grouped by bx
+//   pass 2: one workgroup per (bx, slice) of it -> crd / wts, grouped by bin
+//
+// The order of points inside a bin is not specified (LDS atomics rank them).
+#include "fk_internal.h"
+#include "fk_device.h"
+
+#include <algorithm>
+
+namespace fk {
+
+namespace {
+
+constexpr int BT = 1024;       // points per staged batch, one per thread
+constexpr int KMAX = 256;      // largest bucket count (nf / MB for nf <= 1024)
+
+struct Stage {
+  unsigned long long cur[KMAX];   // next output position of every bucket
+  uint32_t hist[KMAX];            // bucket counts of the current batch
+  uint32_t lofs[KMAX];            // their exclusive prefix sums
+  uint32_t total;
+  uint16_t sbin[BT];              // bucket of every staged slot
+  uint2 scrd[BT];
+  uint4 swts[BT * 4];
+};
+
+// Rank the batch by bucket, stage it in bucket order and write the runs.
+// Every thread of the workgroup calls this once per batch.
+__device__ __forceinline__ void stage_batch(Stage& sm, int nk, bool ok, int key, uint2 U, uint4 v0, uint4 v1,
+                                            uint4 v2, uint4 v3, uint2* __restrict__ crd_out,
+                                            uint4* __restrict__ wts_out) {
+  const int tid = threadIdx.x;
+  const uint32_t rank = ok ? atomicAdd(&sm.hist[key], 1u) : 0u;
+  __syncthreads();
+  if (tid < 64) {   // exclusive scan of the nk <= 256 counts in one wave
+    const int per = (nk + 63) / 64;
+    uint32_t s = 0;
+    for (int i = 0; i < per; ++i) {
+      const int b = tid * per + i;
+      if (b < nk) s += sm.hist[b];
+    }
+    uint32_t x = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (tid >= o) x += y;
+    }
+    uint32_t run = x - s;
+    for (int i = 0; i < per; ++i) {
+      const int b = tid * per + i;
+      if (b < nk) {
+        sm.lofs[b] = run;
+        run += sm.hist[b];
+      }
+    }
+    if (tid == 63) sm.total = x;
+  }
+  __syncthreads();
+  if (ok) {
+    const uint32_t s = sm.lofs[key] + rank;
+    sm.sbin[s] = (uint16_t)key;
+    sm.scrd[s] = U;
+    sm.swts[s * 4 + 0] = v0;
+    sm.swts[s * 4 + 1] = v1;
+    sm.swts[s * 4 + 2] = v2;
+    sm.swts[s * 4 + 3] = v3;
+  }
+  __syncthreads();
+  const uint32_t total = sm.total;
+  if ((uint32_t)tid < total) {
+    const int b = sm.sbin[tid];
+    crd_out[sm.cur[b] + (tid - sm.lofs[b])] = sm.scrd[tid];
+  }
+  for (uint32_t q = tid; q < total * 4; q += BT) {
+    const uint32_t s = q >> 2;
+    const int b = sm.sbin[s];
+    wts_out[(sm.cur[b] + (s - sm.lofs[b])) * 4 + (q & 3)] = sm.swts[q];
+  }
+  __syncthreads();
+  for (int b = tid; b < nk; b += BT) {
+    sm.cur[b] += sm.hist[b];
+    sm.hist[b] = 0;
+  }
+  __syncthreads();
+}
+
+// Pass 1 counts: bucket = bin row of every valid point, one row of nbx counts per
+// workgroup (contiguous chunks of the input).  Each thread takes CU1 points per
+// step, their loads issued together.
+constexpr int CU1 = 4;
+template <typename TX>
+__global__ __launch_bounds__(BT) void k_s2_count1(const TX* __restrict__ X, int64_t n, int64_t xstride,
+                                                  double scale, uint32_t nf_fix, int fb, int tshift, int nbx,
+                                                  int64_t chunk, uint32_t* __restrict__ cnt, int* flags) {
+  __shared__ uint32_t hist[KMAX];
+  for (int i = threadIdx.x; i < nbx; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  const int64_t beg = (int64_t)blockIdx.x * chunk;
+  const int64_t end = min(n, beg + chunk);
+  for (int64_t j0 = beg + threadIdx.x; j0 < end; j0 += (int64_t)CU1 * BT) {
+    double x1[CU1], x2[CU1];
+#pragma unroll
+    for (int u = 0; u < CU1; ++u) {
+      const int64_t jc = min(j0 + (int64_t)u * BT, end - 1);
+      x1[u] = (double)X[jc];
+      x2[u] = (double)X[xstride + jc];
+    }
+#pragma unroll
+    for (int u = 0; u < CU1; ++u) {
+      if (j0 + (int64_t)u * BT >= end) break;
+      uint32_t U1, U2;
+      bool ok = to_fixed(x1[u], scale, nf_fix, &U1, flags);
+      ok = to_fixed(x2[u], scale, nf_fix, &U2, flags) && ok;
+      if (ok) atomicAdd(&hist[(U1 >> fb) >> tshift], 1u);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nbx; i += blockDim.x) cnt[(int64_t)blockIdx.x * nbx + i] = hist[i];
+}
+
+// Pass 1 scatter.  off holds, per workgroup and bucket, the count of the bucket's
+// points in earlier workgroups; start1 the bucket starts.  The inputs of the next
+// batch are loaded (unconditionally, index clamped to the chunk) while the current
+// batch is ranked, staged and written.
+template <typename TX>
+__global__ __launch_bounds__(BT) void k_s2_scatter1(const TX* __restrict__ X, int64_t n,
+                                                    int64_t xstride, const TX* __restrict__ Y, int nw,
+                                                    double scale, uint32_t nf_fix, int fb, int tshift, int nbx,
+                                                    int64_t chunk, const uint32_t* __restrict__ off,
+                                                    const uint64_t* __restrict__ start1,
+                                                    uint2* __restrict__ crd1, uint4* __restrict__ wts1,
+                                                    int* flags) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  Stage& sm = *reinterpret_cast<Stage*>(smem_raw);
+  const int tid = threadIdx.x;
+  for (int b = tid; b < nbx; b += BT) {
+    sm.cur[b] = start1[b] + off[(int64_t)blockIdx.x * nbx + b];
+    sm.hist[b] = 0;
+  }
+  __syncthreads();
+  const int64_t beg = (int64_t)blockIdx.x * chunk;
+  const int64_t end = min(n, beg + chunk);
+  if (beg >= end) return;
+  double nx1, nx2;
+  float nw_[16];
+  auto fetch = [&](int64_t j) {
+    const int64_t jc = min(j, end - 1);
+    nx1 = (double)X[jc];
+    nx2 = (double)X[xstride + jc];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) nw_[c] = (float)Y[(int64_t)min(c, nw - 1) * n + jc];
+  };
+  fetch(beg + tid);
+  for (int64_t base = beg; base < end; base += BT) {
+    const int64_t j = base + tid;
+    const double x1 = nx1, x2 = nx2;
+    float w[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) w[c] = nw_[c];
+    fetch(base + BT + tid);
+    bool ok = false;
+    uint2 U = make_uint2(0u, 0u);
+    if (j < end) {
+      ok = to_fixed(x1, scale, nf_fix, &U.x, flags);
+      ok = to_fixed(x2, scale, nf_fix, &U.y, flags) && ok;
+    }
+    uint32_t wb[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      float wc = (ok && c < nw) ? w[c] : 0.f;
+      if (!(wc == wc) || isinf(wc)) {
+        atomicOr(&flags[kFlagNaN], 1);
+        wc = 0.f;
+      }
+      wb[c] = __float_as_uint(wc);
+    }
+    const int key = ok ? (int)((U.x >> fb) >> tshift) : 0;
+    stage_batch(sm, nbx, ok, key, U, make_uint4(wb[0], wb[1], wb[2], wb[3]), make_uint4(wb[4], wb[5], wb[6], wb[7]),
+                make_uint4(wb[8], wb[9], wb[10], wb[11]), make_uint4(wb[12], wb[13], wb[14], wb[15]), crd1, wts1);
+  }
+}
+
+// Pass 2 counts: workgroup (bx, slice) counts the bin columns of its slice of row bx.
+__global__ __launch_bounds__(256) void k_s2_count2(const uint2* __restrict__ crd1,
+                                                   const uint64_t* __restrict__ start1, int slices, int fb,
+                                                   int tshift, int nbx, uint32_t* __restrict__ cnt2) {
+  __shared__ uint32_t hist[KMAX];
+  for (int i = threadIdx.x; i < nbx; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  const int bx = blockIdx.x / slices, sl = blockIdx.x - bx * slices;
+  const uint64_t p0 = start1[bx], len = start1[bx + 1] - p0;
+  const uint64_t q0 = p0 + len * sl / slices, q1 = p0 + len * (sl + 1) / slices;
+  for (uint64_t p = q0 + threadIdx.x; p < q1; p += blockDim.x) atomicAdd(&hist[(crd1[p].y >> fb) >> tshift], 1u);
+  __syncthreads();
+  for (int i = threadIdx.x; i < nbx; i += blockDim.x) cnt2[(int64_t)blockIdx.x * nbx + i] = hist[i];
+}
+
+// Pass 2 offsets, one workgroup per row bx: off2[(bx, slice, by)] = count of bin
+// (bx, by) in earlier slices of the row, and start[bx * nbx + by] = the bin start.
+__global__ __launch_bounds__(KMAX) void k_s2_scan2(const uint32_t* __restrict__ cnt2,
+                                                  const uint64_t* __restrict__ start1, int slices, int nbx,
+                                                  uint32_t* __restrict__ off2, uint64_t* __restrict__ start) {
+  __shared__ uint64_t tot[KMAX];
+  const int bx = blockIdx.x, by = threadIdx.x;
+  uint64_t run = 0;
+  if (by < nbx) {
+    for (int s = 0; s < slices; ++s) {
+      const int64_t i = ((int64_t)bx * slices + s) * nbx + by;
+      off2[i] = (uint32_t)run;
+      run += cnt2[i];
+    }
+    tot[by] = run;
+  }
+  __syncthreads();
+  if (by == 0) {
+    uint64_t acc = start1[bx];
+    for (int i = 0; i < nbx; ++i) {
+      const uint64_t t = tot[i];
+      tot[i] = acc;
+      acc += t;
+    }
+  }
+  __syncthreads();
+  if (by < nbx) start[(int64_t)bx * nbx + by] = tot[by];
+  if (bx == nbx - 1 && by == 0) start[(int64_t)nbx * nbx] = start1[nbx];
+}
+
+// Pass 2 scatter: workgroup (bx, slice) moves its slice of row bx into bin order.
+__global__ __launch_bounds__(BT) void k_s2_scatter2(const uint2* __restrict__ crd1, const uint4* __restrict__ wts1,
+                                                    const uint64_t* __restrict__ start1,
+                                                    const uint32_t* __restrict__ off2,
+                                                    const uint64_t* __restrict__ start, int slices, int fb,
+                                                    int tshift, int nbx, uint2* __restrict__ crd,
+                                                    uint4* __restrict__ wts) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  Stage& sm = *reinterpret_cast<Stage*>(smem_raw);
+  const int tid = threadIdx.x;
+  const int bx = blockIdx.x / slices, sl = blockIdx.x - bx * slices;
+  for (int b = tid; b < nbx; b += BT) {
+    sm.cur[b] = start[(int64_t)bx * nbx + b] + off2[(int64_t)blockIdx.x * nbx + b];
+    sm.hist[b] = 0;
+  }
+  __syncthreads();
+  const uint64_t p0 = start1[bx], len = start1[bx + 1] - p0;
+  const uint64_t q0 = p0 + len * sl / slices, q1 = p0 + len * (sl + 1) / slices;
+  if (q0 >= q1) return;
+  // The next batch is loaded (index clamped to the slice) while this one is staged.
+  uint2 nU;
+  uint4 n0, n1, n2, n3;
+  auto fetch = [&](uint64_t p) {
+    const uint64_t pc = min(p, q1 - 1);
+    nU = crd1[pc];
+    const uint4* src = wts1 + pc * 4;
+    n0 = src[0];
+    n1 = src[1];
+    n2 = src[2];
+    n3 = src[3];
+  };
+  fetch(q0 + tid);
+  for (uint64_t base = q0; base < q1; base += BT) {
+    const uint64_t p = base + tid;
+    const bool ok = p < q1;
+    const uint2 U = nU;
+    const uint4 v0 = n0, v1 = n1, v2 = n2, v3 = n3;
+    fetch(base + BT + tid);
+    const int key = ok ? (int)((U.y >> fb) >> tshift) : 0;
+    stage_batch(sm, nbx, ok, key, U, v0, v1, v2, v3, crd, wts);
+  }
+}
+
+// Offsets of pass 1: off[k][b] = number of points of bucket b in workgroups < k,
+// and start1[b] (start1[nk] = number of valid points).  One workgroup of 1024
+// threads: thread (grp, b) sums a range of workgroups, the group sums are
+// scanned, then each range is rewritten as running offsets.
+constexpr int SG = 1024 / KMAX;   // workgroup ranges per bucket
+__global__ __launch_bounds__(1024) void k_s2_scan1(const uint32_t* __restrict__ cnt, int nk, int nblk,
+                                                  uint32_t* __restrict__ off, uint64_t* __restrict__ start1) {
+  __shared__ uint64_t part[SG][KMAX];
+  __shared__ uint64_t tot[KMAX];
+  const int b = threadIdx.x % KMAX, grp = threadIdx.x / KMAX;
+  const int per = (nblk + SG - 1) / SG;
+  const int k0 = grp * per, k1 = min(nblk, k0 + per);
+  uint64_t s = 0;
+  if (b < nk)
+    for (int k = k0; k < k1; ++k) s += cnt[(int64_t)k * nk + b];
+  part[grp][b] = s;
+  __syncthreads();
+  if (grp == 0 && b < nk) {
+    uint64_t run = 0;
+    for (int g = 0; g < SG; ++g) {
+      const uint64_t t = part[g][b];
+      part[g][b] = run;
+      run += t;
+    }
+    tot[b] = run;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t acc = 0;
+    for (int i = 0; i < nk; ++i) {
+      start1[i] = acc;
+      acc += tot[i];
+    }
+    start1[nk] = acc;
+  }
+  if (b < nk) {
+    uint64_t run = part[grp][b];
+    for (int k = k0; k < k1; ++k) {
+      off[(int64_t)k * nk + b] = (uint32_t)run;
+      run += cnt[(int64_t)k * nk + b];
+    }
+  }
+}
+
+struct Sort2Geom {
+  int nblk1, slices;
+  int64_t chunk1;
+};
+
+Sort2Geom sort2_geom(int64_t n, int nbx) {
+  Sort2Geom g;
+  g.nblk1 = (int)std::min<int64_t>(512, std::max<int64_t>(1, (n + 65535) / 65536));
+  g.chunk1 = (n + g.nblk1 - 1) / g.nblk1;
+  g.slices = (int)std::min<int64_t>(256, std::max<int64_t>(1, (n / nbx + 65535) / 65536));
+  return g;
+}
+
+}  // namespace
+
+bool sort2_ok(int nbx) { return nbx >= 1 && nbx <= KMAX; }
+
+void sort2_carve(Carve& cv, int64_t n, int nbx, Sort2Bufs* b) {
+  Sort2Geom g = sort2_geom(n, nbx);
+  b->cnt1 = cv.take<uint32_t>((size_t)g.nblk1 * nbx);
+  b->off1 = cv.take<uint32_t>((size_t)g.nblk1 * nbx);
+  b->start1 = cv.take<uint64_t>((size_t)nbx + 1);
+  b->cnt2 = cv.take<uint32_t>((size_t)nbx * g.slices * nbx);
+  b->off2 = cv.take<uint32_t>((size_t)nbx * g.slices * nbx);
+  b->crd1 = cv.take<uint32_t>((size_t)n * 2);
+  b->wts1 = cv.take<uint32_t>((size_t)n * 16);
+}
+
+fk_status sort2(hipStream_t st, const void* X, fk_dtype dt, int64_t n, int64_t xstride, const void* Y, int nw,
+                int nf, int fb, double scale, int tshift, int nbx, const Sort2Bufs& b, uint32_t* crd,
+                uint32_t* wts, uint64_t* start, int* flags) {
+  if (!sort2_ok(nbx) || nw > 16) return FK_EINVAL;
+  const Sort2Geom g = sort2_geom(n, nbx);
+  const uint32_t nf_fix = (uint32_t)nf << fb;
+  const size_t lds = sizeof(Stage);
+  if (dt == FK_F64) {
+    const double* Xd = static_cast<const double*>(X);
+    hipLaunchKernelGGL(k_s2_count1<double>, dim3(g.nblk1), dim3(BT), 0, st, Xd, n, xstride, scale, nf_fix, fb,
+                       tshift, nbx, g.chunk1, b.cnt1, flags);
+    hipLaunchKernelGGL(k_s2_scan1, dim3(1), dim3(1024), 0, st, b.cnt1, nbx, g.nblk1, b.off1, b.start1);
+    hipLaunchKernelGGL(k_s2_scatter1<double>, dim3(g.nblk1), dim3(BT), lds, st, Xd, n, xstride,
+                       static_cast<const double*>(Y), nw, scale, nf_fix, fb, tshift, nbx, g.chunk1, b.off1,
+                       b.start1, reinterpret_cast<uint2*>(b.crd1), reinterpret_cast<uint4*>(b.wts1), flags);
+  } else {
+    const float* Xf = static_cast<const float*>(X);
+    hipLaunchKernelGGL(k_s2_count1<float>, dim3(g.nblk1), dim3(BT), 0, st, Xf, n, xstride, scale, nf_fix, fb,
+                       tshift, nbx, g.chunk1, b.cnt1, flags);
+    hipLaunchKernelGGL(k_s2_scan1, dim3(1), dim3(1024), 0, st, b.cnt1, nbx, g.nblk1, b.off1, b.start1);
+    hipLaunchKernelGGL(k_s2_scatter1<float>, dim3(g.nblk1), dim3(BT), lds, st, Xf, n, xstride,
+                       static_cast<const float*>(Y), nw, scale, nf_fix, fb, tshift, nbx, g.chunk1, b.off1,
+                       b.start1, reinterpret_cast<uint2*>(b.crd1), reinterpret_cast<uint4*>(b.wts1), flags);
+  }
+  hipLaunchKernelGGL(k_s2_count2, dim3(nbx * g.slices), dim3(256), 0, st, reinterpret_cast<const uint2*>(b.crd1),
+                     b.start1, g.slices, fb, tshift, nbx, b.cnt2);
+  hipLaunchKernelGGL(k_s2_scan2, dim3(nbx), dim3(KMAX), 0, st, b.cnt2, b.start1, g.slices, nbx, b.off2, start);
+  hipLaunchKernelGGL(k_s2_scatter2, dim3(nbx * g.slices), dim3(BT), lds, st,
+                     reinterpret_cast<const uint2*>(b.crd1), reinterpret_cast<const uint4*>(b.wts1), b.start1,
+                     b.off2, start, g.slices, fb, tshift, nbx, reinterpret_cast<uint2*>(crd),
+                     reinterpret_cast<uint4*>(wts));
+  return hipGetLastError() == hipSuccess ? FK_OK : FK_EHIP;
+}
+
+}  // namespace fk

@@ -3,98 +3,83 @@
 // The type-1 sums of Sec. 2.3 for T targets share the kernel weights of each
 // point: every point adds W[c] psi1[a] psi2[b] to the w x w grid cells of its
 // window, for the ones channel (the Gram, c = 0) and the T target channels.
-// With LDS atomics that is w^2 (T+1) atomic adds per point; here it becomes a
-// dense matrix product on the matrix cores:
+// With LDS atomics that is w^2 (T+1) atomic adds per point; here it is a dense
+// matrix product on the matrix cores.
 //
-// * bins are MB x MB grid cells (MB = 4), counting-sorted beforehand so a bin's
-//   points are contiguous: fixed-point coordinates [U1, U2] (8 B) and a
-//   64-byte block of 16 FP32 weights (zero padded) per point;
-// * a workgroup takes a slice of one bin and stages batches of MP points in
-//   LDS (the next batch is loaded into registers while the current one is
-//   processed); each point's window start (l1, l2) relative to the bin takes
-//   (MB+1)^2 = 25 values, and the batch is counting-sorted by it;
-// * the exponential-of-semicircle values psi1[0..w), psi2[0..w) of every point
-//   are evaluated once per point into LDS;
-// * for one window-start group, 4 points at a time,
-//     D[c][cell] += sum_k W[c][k] * (psi1_k[cell / w] psi2_k[cell % w])
-//   is v_mfma_f32_16x16x4f32 with rows = 16 target channels, columns = 16 of
-//   the w^2 <= 64 window cells (4 column tiles), K = the 4 points; the ones
-//   channel is the column sum of the same kernel products (vector ALUs);
-// * each wave owns fixed groups, so its FP32 accumulators stay in registers
-//   across batches; every MFLUSH batches they are added into an FP64 LDS
-//   subgrid (LDS ds_add_f64), which is added into the FP64 grid at the end.
+// * Bins are MB x MB grid cells (MB = 4), sorted beforehand (sort2.hip) so a
+//   bin's points are contiguous: fixed-point coordinates [U1, U2] (8 B) and a
+//   64-byte block of 16 FP32 weights (zero padded) per point.
+// * A workgroup of SWAVE waves takes a slice of one bin; each wave takes the
+//   slice's points 4 at a time (one "chunk"), in stored order and on its own
+//   (no workgroup barrier in the loop).  All windows of a bin's points lie in
+//   its S x S subgrid, S = MB + w, so with the kernel value zero outside a
+//   point's own window,
+//     D[c][cell] += sum_k W[c][k] * psi1_k[cell / S] * psi2_k[cell % S]
+//   over the S^2 cells is NT = ceil(S^2 / 16) v_mfma_f32_16x16x4f32 per chunk:
+//   rows = the 16 target channels, columns = 16 subgrid cells, K = the 4 points.
+//   The ones channel is the column sum of the same kernel products (vector ALUs).
+// * Lane (k = l/16, j = l%16) evaluates psi1 and psi2 of point k at subgrid
+//   offset j (two exponentials); the product for cell (a, b) is gathered from
+//   lanes (k, a) and (k, b) with two lane permutes.
+// * The coordinates and weights of the next SPD chunks are loaded while the
+//   current ones are processed.
+// * FP32 accumulators are added into the workgroup's FP64 LDS subgrid (ds_add_f64)
+//   every SFLUSH chunks and at the end; the subgrid is then added into the FP64
+//   fine grid with global FP64 atomics.
 //
 // Lane layout of v_mfma_f32_16x16x4f32 (wave64): lane l supplies A[l%16][l/16]
 // and B[l/16][l%16]; element v of the result holds row 4*(l/16)+v, column l%16.
 #include "fk_internal.h"
 
+#include <algorithm>
+
 namespace fk {
 
 namespace {
 
-constexpr int MB = 4;                       // bin edge in grid cells
-constexpr int MG = (MB + 1) * (MB + 1);     // window-start groups per bin
-constexpr int NWAVE = 8;
-constexpr int NTHR = 64 * NWAVE;
-constexpr int MGW = (MG + NWAVE - 1) / NWAVE;   // groups per wave
-constexpr int MP = 512;                     // points per LDS batch
-constexpr int MFLUSH = 8;                   // batches between FP32 -> FP64 flushes
-constexpr int WQ = MP * 4 / NTHR;           // 16-byte weight quads per thread per batch
+constexpr int MB = 4;   // bin edge in grid cells
 
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ float psi_es(float s, float beta, float two_over_w) {
+// Exponential of semicircle psi(s) = exp(beta (sqrt(1 - (2s/w)^2) - 1)), with beta
+// pre-multiplied by log2(e): the exponent lies in [-beta log2 e, 0], far from the
+// denormal range, so the hardware exp2 needs no range handling.
+__device__ __forceinline__ float psi_es2(float s, float beta_log2e, float two_over_w) {
   float z = s * two_over_w;
   float r = fmaxf(1.0f - z * z, 0.0f);
-  return __expf(beta * (__fsqrt_rn(r) - 1.0f));
+  return __builtin_amdgcn_exp2f(beta_log2e * (__fsqrt_rn(r) - 1.0f));
 }
 
-// i0 = ceil(u - w/2), s0 = i0 - u from a fixed-point coordinate with fb fraction bits.
+// i0 = ceil(u - w/2), s0 = i0 - u from a fixed-point coordinate U = u 2^fb < 2^31,
+// in 32-bit integer arithmetic: the bias of 8 cells keeps the dividend positive, and
+// i0 2^fb - U is small, so its 32-bit wrap-around difference is exact, as is its
+// conversion to float (|.| < 2^24) and the scaling by a power of two.
 __device__ __forceinline__ void win_start(uint32_t U, int fb, int w, int* i0, float* s0) {
-  int64_t V = (int64_t)U - ((int64_t)w << (fb - 1));
-  int64_t one = (int64_t)1 << fb;
-  int64_t c = (V >= 0) ? ((V + one - 1) >> fb) : -((-V) >> fb);
-  *i0 = (int)c;
-  *s0 = (float)((double)((c << fb) - (int64_t)U) * (1.0 / (double)one));
+  const uint32_t one = 1u << fb;
+  const uint32_t t = U + (one - 1u) + 8u * one - ((uint32_t)w << (fb - 1));
+  const int c = (int)(t >> fb) - 8;
+  *i0 = c;
+  *s0 = (float)(int)(((uint32_t)c << fb) - U) * __uint_as_float((uint32_t)(127 - fb) << 23);
 }
 
-struct Prefetch {
-  uint2 c;
-  uint4 w[WQ];
-};
-
-// Load the batch [base, base + np) of coordinates and weight blocks into registers.
-__device__ __forceinline__ void prefetch(Prefetch& pf, const uint2* __restrict__ crd, const uint4* __restrict__ wts,
-                                         uint64_t base, int np, int tid) {
-  if (tid < np) pf.c = crd[base + tid];
-#pragma unroll
-  for (int q = 0; q < WQ; ++q) {
-    const int i = tid + q * NTHR;
-    if (i < np * 4) pf.w[q] = wts[base * 4 + i];
-  }
-}
+constexpr int SWAVE = 4;
+constexpr int SFLUSH = 256;
+constexpr int SPD = 4;      // chunks in flight per wave
 
 template <int W>
-__global__ __launch_bounds__(NTHR) void k_spread_mfma(const uint2* __restrict__ crd, const uint4* __restrict__ wts,
-                                                      int nw, const uint64_t* __restrict__ start, int nbx, int nf,
-                                                      int fb, float beta, int slices, double* __restrict__ grid) {
-  static_assert(W <= 8, "the window must fit 4 column tiles and 16 lanes");
-  static_assert(MP <= NTHR, "one coordinate per thread per batch");
+__global__ __launch_bounds__(64 * SWAVE) void k_spread_mfma(const uint2* __restrict__ crd,
+                                                            const float* __restrict__ wts, int nw,
+                                                            const uint64_t* __restrict__ start, int nbx, int nf,
+                                                            int fb, float beta, int slices,
+                                                            double* __restrict__ grid) {
   constexpr int S = MB + W;
+  constexpr int NT = (S * S + 15) / 16;
+  static_assert(S <= 16, "one subgrid row per 16 lanes");
   extern __shared__ double smem_d[];
   const int C = nw + 1;
   const float two_over_w = 2.0f / (float)W;
-  const int subn = (S * S * C + 1) & ~1;                          // keep 16-byte alignment below
-  double* sub = smem_d;                                            // S*S*C doubles
-  float* psi = reinterpret_cast<float*>(sub + subn);               // MP*16 floats
-  uint4* sw = reinterpret_cast<uint4*>(psi + MP * 16);             // MP*4 quads (16 weights per point)
-  uint2* sc = reinterpret_cast<uint2*>(sw + MP * 4);               // MP coordinates
-  uint16_t* perm = reinterpret_cast<uint16_t*>(sc + MP);           // MP
-  uint16_t* rank = perm + MP;                                      // MP
-  uint8_t* keyv = reinterpret_cast<uint8_t*>(rank + MP);           // MP
-  int* gcount = reinterpret_cast<int*>(keyv + MP);                 // 32
-  int* gstart = gcount + 32;                                       // 32
-  const float* swf = reinterpret_cast<const float*>(sw);
+  const float bl2 = beta * 1.44269504088896340736f;
+  double* sub = smem_d;   // S*S*C doubles
 
   const int b = blockIdx.x / slices;
   const int sl = blockIdx.x - b * slices;
@@ -105,143 +90,123 @@ __global__ __launch_bounds__(NTHR) void k_spread_mfma(const uint2* __restrict__ 
   if (q0 == q1) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int bx = b / nbx, by = b - bx * nbx;
-  const int o1 = bx * MB - W / 2, o2 = by * MB - W / 2;   // window starts lie in [o, o + MB]
-  for (int i = tid; i < S * S * C; i += NTHR) sub[i] = 0.0;
+  const int o1 = bx * MB - W / 2, o2 = by * MB - W / 2;
+  for (int i = tid; i < S * S * C; i += 64 * SWAVE) sub[i] = 0.0;
+  __syncthreads();
 
-  floatx4_t acc[MGW][4];
-  float ones[MGW][4];
+  const int k = lane >> 4, j = lane & 15;
+  // Source lanes (byte addresses for ds_bpermute) of psi1[a] and psi2[b] for the
+  // cell (a, b) of column tile t.  Padding cells (>= S*S) read lane 15 of the
+  // point's row, whose kernel values are zero (15 >= S), so they add nothing.
+  int srca[NT], srcb[NT];
+  bool cin[NT];
 #pragma unroll
-  for (int s = 0; s < MGW; ++s)
+  for (int t = 0; t < NT; ++t) {
+    const int cell = t * 16 + j;
+    cin[t] = cell < S * S;
+    const int a = cin[t] ? cell / S : 15;
+    const int bb = cin[t] ? cell - (cell / S) * S : 15;
+    srca[t] = (k * 16 + a) * 4;
+    srcb[t] = (k * 16 + bb) * 4;
+  }
+  floatx4_t acc[NT];
+  float ones[NT];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      acc[s][t] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-      ones[s][t] = 0.f;
-    }
-
-  const int kslot = lane >> 4, jj = lane & 15;
-  int ca[4], cb[4];
-  bool cin[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int cell = t * 16 + jj;
-    cin[t] = cell < W * W;
-    ca[t] = cin[t] ? cell / W : 0;
-    cb[t] = cin[t] ? cell - (cell / W) * W : 0;
+  for (int t = 0; t < NT; ++t) {
+    acc[t] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    ones[t] = 0.f;
   }
 
-  Prefetch pf;
-  prefetch(pf, crd, wts, q0, (int)min<uint64_t>(MP, q1 - q0), tid);
-  int batch = 0;
-  for (uint64_t base = q0; base < q1; base += MP, ++batch) {
-    const int np = (int)min<uint64_t>(MP, q1 - base);
-    __syncthreads();   // the previous batch is fully consumed
-    if (tid < np) sc[tid] = pf.c;
+  auto flush = [&]() {
 #pragma unroll
-    for (int q = 0; q < WQ; ++q) {
-      const int i = tid + q * NTHR;
-      if (i < np * 4) sw[i] = pf.w[q];
+    for (int t = 0; t < NT; ++t) {
+      float o = ones[t];
+      o += __shfl_xor(o, 16, 64);
+      o += __shfl_xor(o, 32, 64);
+      if (cin[t]) {
+        double* cp = sub + (t * 16 + j) * C;
+        if (k == 0 && o != 0.f) atomicAdd(cp, (double)o);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 4 * k + v;
+          const float x = acc[t][v];
+          if (row < nw && x != 0.f) atomicAdd(cp + 1 + row, (double)x);
+        }
+      }
+      acc[t] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+      ones[t] = 0.f;
     }
-    if (tid < 32) gcount[tid] = 0;
-    if (base + MP < q1) prefetch(pf, crd, wts, base + MP, (int)min<uint64_t>(MP, q1 - base - MP), tid);
-    __syncthreads();
-    if (tid < np) {
-      const int p = tid;
+  };
+
+  // Slice-relative 32-bit indices (a slice holds < 2^31 points).
+  const uint32_t npts = (uint32_t)(q1 - q0);
+  const uint32_t nchunk = (npts + 3) / 4;
+  const uint2* __restrict__ cs = crd + q0;
+  const float* __restrict__ ws = wts + q0 * 16;
+  // Software pipeline: while the SPD chunks of the current group are processed, the
+  // coordinates and weights of the next group are in flight.  The loads are
+  // unconditional (index clamped to the slice; weight blocks are zero padded to 16)
+  // and the tail is masked instead of branched around, so that the only wait for a
+  // group's loads is where the group is first used.
+  uint2 Uc[SPD], Un[SPD];
+  float Wc[SPD], Wn[SPD];
+  auto load = [&](uint32_t cc, uint2& U, float& w) {
+    const uint32_t p = min(cc * 4 + k, npts - 1);
+    U = cs[p];
+    w = ws[p * 16 + j];
+  };
+#pragma unroll
+  for (int d = 0; d < SPD; ++d) load(wv + d * SWAVE, Uc[d], Wc[d]);
+  // Outer loop: groups of SFLUSH chunks per wave, then a flush of the FP32
+  // accumulators into the FP64 LDS subgrid (kept out of the inner loop so that
+  // the accumulators stay in the matrix-core registers).
+  for (uint32_t c0 = wv; c0 < nchunk; c0 += SFLUSH * SWAVE) {
+  const uint32_t cend = min(nchunk, c0 + SFLUSH * SWAVE);
+  for (uint32_t c = c0; c < cend; c += SPD * SWAVE) {
+#pragma unroll
+    for (int d = 0; d < SPD; ++d) load(c + (SPD + d) * SWAVE, Un[d], Wn[d]);
+#pragma unroll
+    for (int d = 0; d < SPD; ++d) {
+      const uint2 U = Uc[d];
+      const bool valid = (c + d * SWAVE) * 4 + k < npts;
+      const float aop = valid ? Wc[d] : 0.f;
       int i1, i2;
       float s1, s2;
-      const uint2 U = sc[p];
       win_start(U.x, fb, W, &i1, &s1);
       win_start(U.y, fb, W, &i2, &s2);
-      const int k = (i1 - o1) * (MB + 1) + (i2 - o2);
-      keyv[p] = (uint8_t)k;
-      rank[p] = (uint16_t)atomicAdd(&gcount[k], 1);
-      float* ps = psi + p * 16;
+      const int r1 = j - (i1 - o1), r2 = j - (i2 - o2);   // offset of cell j inside the window
+      const float px = (valid && r1 >= 0 && r1 < W) ? psi_es2(s1 + (float)r1, bl2, two_over_w) : 0.f;
+      const float py = (r2 >= 0 && r2 < W) ? psi_es2(s2 + (float)r2, bl2, two_over_w) : 0.f;
+      const int ipx = __float_as_int(px), ipy = __float_as_int(py);
 #pragma unroll
-      for (int a = 0; a < W; ++a) {
-        ps[a] = psi_es(s1 + (float)a, beta, two_over_w);
-        ps[W + a] = psi_es(s2 + (float)a, beta, two_over_w);
+      for (int t = 0; t < NT; ++t) {
+        const float xa = __int_as_float(__builtin_amdgcn_ds_bpermute(srca[t], ipx));
+        const float yb = __int_as_float(__builtin_amdgcn_ds_bpermute(srcb[t], ipy));
+        const float bv = xa * yb;
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bv, acc[t], 0, 0, 0);
+        ones[t] += bv;
       }
     }
-    __syncthreads();
-    if (wv == 0) {   // exclusive scan of the 25 group counts in one wave
-      int v = lane < MG ? gcount[lane] : 0;
-      int x = v;
 #pragma unroll
-      for (int o = 1; o < 32; o <<= 1) {
-        int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-      }
-      if (lane < MG) gstart[lane] = x - v;
-    }
-    __syncthreads();
-    if (tid < np) perm[gstart[keyv[tid]] + rank[tid]] = (uint16_t)tid;
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < MGW; ++s) {
-      const int g = wv + NWAVE * s;
-      if (g >= MG) continue;
-      const int cnt = gcount[g], gs = gstart[g];
-      for (int c0 = 0; c0 < cnt; c0 += 4) {
-        const int idx = c0 + kslot;
-        const bool valid = idx < cnt;
-        const int p = valid ? perm[gs + idx] : 0;
-        const float aop = (valid && jj < nw) ? swf[p * 16 + jj] : 0.f;
-        const float* ps = psi + p * 16;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const float bv = (valid && cin[t]) ? ps[ca[t]] * ps[W + cb[t]] : 0.f;
-          acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bv, acc[s][t], 0, 0, 0);
-          ones[s][t] += bv;
-        }
-      }
-    }
-    const bool last = base + MP >= q1;
-    if (last || (batch % MFLUSH) == MFLUSH - 1) {
-#pragma unroll
-      for (int s = 0; s < MGW; ++s) {
-        const int g = wv + NWAVE * s;
-        if (g >= MG) continue;
-        const int l1 = g / (MB + 1), l2 = g - (g / (MB + 1)) * (MB + 1);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          float o = ones[s][t];
-          o += __shfl_xor(o, 16, 64);
-          o += __shfl_xor(o, 32, 64);
-          if (cin[t]) {
-            double* cp = sub + ((l1 + ca[t]) * S + (l2 + cb[t])) * C;
-            if (kslot == 0 && o != 0.f) atomicAdd(cp, (double)o);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const int row = 4 * kslot + v;
-              const float x = acc[s][t][v];
-              if (row < nw && x != 0.f) atomicAdd(cp + 1 + row, (double)x);
-            }
-          }
-          acc[s][t] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-          ones[s][t] = 0.f;
-        }
-      }
+    for (int d = 0; d < SPD; ++d) {
+      Uc[d] = Un[d];
+      Wc[d] = Wn[d];
     }
   }
+  flush();
+  }
   __syncthreads();
-  for (int i = tid; i < S * S * C; i += NTHR) {
+  for (int i = tid; i < S * S * C; i += 64 * SWAVE) {
     double v = sub[i];
     if (v == 0.0) continue;
-    int c = i % C;
+    int ch = i % C;
     int cell = i / C;
     int a = cell / S, bb = cell - a * S;
     int g1 = o1 + a, g2 = o2 + bb;
     g1 = g1 < 0 ? g1 + nf : (g1 >= nf ? g1 - nf : g1);
     g2 = g2 < 0 ? g2 + nf : (g2 >= nf ? g2 - nf : g2);
-    atomicAdd(&grid[((int64_t)c * nf + g1) * nf + g2], v);
+    atomicAdd(&grid[((int64_t)ch * nf + g1) * nf + g2], v);
   }
-}
-
-size_t lds_bytes(int W, int nw) {
-  const int S = MB + W, C = nw + 1;
-  size_t b = sizeof(double) * ((S * S * C + 1) & ~1) + sizeof(float) * MP * 16 + 16 * MP * 4 + 8 * MP +
-             2 * sizeof(uint16_t) * MP + MP;
-  b = (b + 3) & ~size_t(3);
-  return b + 64 * sizeof(int);
 }
 
 }  // namespace
@@ -253,25 +218,25 @@ bool spread_mfma_ok(int nw, int W) { return nw >= 8 && nw <= 16 && W >= 4 && W <
 fk_status launch_spread_mfma(hipStream_t st, int W, const uint32_t* crd, const uint32_t* wts, int nw,
                              const uint64_t* start, int nbx, int nb, int nf, int fb, double beta, int64_t n,
                              double* grid) {
+  if (!spread_mfma_ok(nw, W)) return FK_EINVAL;
   const int64_t per_bin = (n + nb - 1) / nb;
   const int slices = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (per_bin + 16383) / 16384));
   const int blocks = nb * slices;
-  const size_t lds = lds_bytes(W, nw);
-  if (lds > 160 * 1024) return FK_EINVAL;
+  const size_t lds = sizeof(double) * (MB + W) * (MB + W) * (nw + 1);
   const float bt = (float)beta;
   const uint2* c2 = reinterpret_cast<const uint2*>(crd);
-  const uint4* w4 = reinterpret_cast<const uint4*>(wts);
+  const float* wf = reinterpret_cast<const float*>(wts);
   switch (W) {
-    case 4: hipLaunchKernelGGL(k_spread_mfma<4>, dim3(blocks), dim3(NTHR), lds, st, c2, w4, nw, start, nbx, nf, fb,
-                               bt, slices, grid); break;
-    case 5: hipLaunchKernelGGL(k_spread_mfma<5>, dim3(blocks), dim3(NTHR), lds, st, c2, w4, nw, start, nbx, nf, fb,
-                               bt, slices, grid); break;
-    case 6: hipLaunchKernelGGL(k_spread_mfma<6>, dim3(blocks), dim3(NTHR), lds, st, c2, w4, nw, start, nbx, nf, fb,
-                               bt, slices, grid); break;
-    case 7: hipLaunchKernelGGL(k_spread_mfma<7>, dim3(blocks), dim3(NTHR), lds, st, c2, w4, nw, start, nbx, nf, fb,
-                               bt, slices, grid); break;
-    case 8: hipLaunchKernelGGL(k_spread_mfma<8>, dim3(blocks), dim3(NTHR), lds, st, c2, w4, nw, start, nbx, nf, fb,
-                               bt, slices, grid); break;
+    case 4: hipLaunchKernelGGL(k_spread_mfma<4>, dim3(blocks), dim3(64 * SWAVE), lds, st, c2, wf, nw, start, nbx,
+                               nf, fb, bt, slices, grid); break;
+    case 5: hipLaunchKernelGGL(k_spread_mfma<5>, dim3(blocks), dim3(64 * SWAVE), lds, st, c2, wf, nw, start, nbx,
+                               nf, fb, bt, slices, grid); break;
+    case 6: hipLaunchKernelGGL(k_spread_mfma<6>, dim3(blocks), dim3(64 * SWAVE), lds, st, c2, wf, nw, start, nbx,
+                               nf, fb, bt, slices, grid); break;
+    case 7: hipLaunchKernelGGL(k_spread_mfma<7>, dim3(blocks), dim3(64 * SWAVE), lds, st, c2, wf, nw, start, nbx,
+                               nf, fb, bt, slices, grid); break;
+    case 8: hipLaunchKernelGGL(k_spread_mfma<8>, dim3(blocks), dim3(64 * SWAVE), lds, st, c2, wf, nw, start, nbx,
+                               nf, fb, bt, slices, grid); break;
     default: return FK_EINVAL;
   }
   return hipGetLastError() == hipSuccess ? FK_OK : FK_EHIP;

@@ -94,3 +94,13 @@ def test_heldout_mse_and_gradients(fk):
     print("dlog lambda gpu", gl, "oracle", g_ll)
     assert np.abs(gl - g_ll).max() <= 1e-4 * np.abs(g_ll).max()
     assert np.abs(gp - g_p).max() <= 1e-4 * np.abs(g_p).max()
+
+
+@pytest.mark.parametrize("T,n,dt", [(16, 1_000_003, np.float32), (3, 1, np.float64), (1, 70_000, np.float64)])
+def test_mean_square(fk, T, n, dt):
+    # the constant term of the held-out loss: exact FP64 sums of squares of the stored values
+    rng = np.random.default_rng(T * 7 + n)
+    Y = (rng.standard_normal((T, n)) * 3.0).astype(dt)
+    got = fk.mean_square(torch.from_numpy(Y).cuda()).cpu().numpy()
+    want = np.array([np.sum(Y[t].astype(np.float64) ** 2) / n for t in range(T)])
+    assert np.allclose(got, want, rtol=1e-12, atol=0)
