@@ -277,15 +277,12 @@ __device__ __forceinline__ void mfma_tile64(const float* As, const float* Bs, fl
   }
 }
 
-// Load a 64 x 64 FP32 tile (row-major, leading dimension ld) into LDS.
+// Load a 64 x 64 FP32 tile (row-major, leading dimension ld) into LDS (rows of LDT
+// floats, 16-byte aligned).
 __device__ __forceinline__ void load_tile(float* T, const float* src, int64_t ld) {
   for (int i = threadIdx.x; i < NB * NB / 4; i += blockDim.x) {
     int r = i / (NB / 4), c = (i - r * (NB / 4)) * 4;
-    float4 v = *reinterpret_cast<const float4*>(src + r * ld + c);
-    T[r * LDT + c] = v.x;
-    T[r * LDT + c + 1] = v.y;
-    T[r * LDT + c + 2] = v.z;
-    T[r * LDT + c + 3] = v.w;
+    *reinterpret_cast<float4*>(T + r * LDT + c) = *reinterpret_cast<const float4*>(src + r * ld + c);
   }
 }
 
@@ -387,25 +384,67 @@ __global__ __launch_bounds__(256) void k_trsm_panel(float* __restrict__ A, int N
   store_acc(src, Np, acc, false, 1.0f);
 }
 
-// Trailing update of the lower triangle: A[i][j] -= L[i][kb] L[j][kb]^T, kb < j <= i.
-__global__ __launch_bounds__(256) void k_syrk_update(float* __restrict__ A, int Np, int kb) {
-  __shared__ float As[NB * LDT], Bs[NB * LDT];
+// Left-looking update of block column kb for every lambda (grid.y):
+//   A[i][kb] -= sum_{k < kb} L[i][k] L[kb][k]^T,   i = kb + blockIdx.x,
+// the K loop over the finished panels streamed through double-buffered LDS (the next
+// pair of tiles is loaded into registers while the current pair is on the matrix
+// cores), so every output tile is read and written once per factorization.
+__global__ __launch_bounds__(256) void k_left_update(float* __restrict__ A, int Np, int kb) {
+  __shared__ __align__(16) float As[2][NB * LDT];
+  __shared__ __align__(16) float Bs[2][NB * LDT];
   const int l = blockIdx.y;
-  // decode lower-triangular tile index t -> (i, j), i >= j, offsets from kb+1
-  int t = blockIdx.x;
-  int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-  while ((i + 1) * (i + 2) / 2 <= t) ++i;
-  while (i * (i + 1) / 2 > t) --i;
-  int j = t - i * (i + 1) / 2;
-  i += kb + 1;
-  j += kb + 1;
+  const int i = kb + blockIdx.x;
   float* Al = A + (size_t)l * Np * Np;
-  load_tile(As, Al + (size_t)i * NB * Np + kb * NB, Np);
-  load_tile(Bs, Al + (size_t)j * NB * Np + kb * NB, Np);
-  __syncthreads();
+  const float* Ai = Al + (size_t)i * NB * Np;
+  const float* Ak = Al + (size_t)kb * NB * Np;
+  constexpr int PER = NB * NB / 4 / 256;   // float4 per thread per tile
+  int off_g[PER], off_s[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int idx = threadIdx.x + q * 256, r = idx / (NB / 4), c = (idx % (NB / 4)) * 4;
+    off_g[q] = r * Np + c;
+    off_s[q] = r * LDT + c;
+  }
+  float4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+  static_assert(PER == 4, "four float4 per thread per tile");
+#define FK_GLOAD(k)                                                                  \
+  do {                                                                               \
+    const float* pa = Ai + (k) * NB;                                                 \
+    const float* pb = Ak + (k) * NB;                                                 \
+    ra0 = *reinterpret_cast<const float4*>(pa + off_g[0]);                            \
+    ra1 = *reinterpret_cast<const float4*>(pa + off_g[1]);                            \
+    ra2 = *reinterpret_cast<const float4*>(pa + off_g[2]);                            \
+    ra3 = *reinterpret_cast<const float4*>(pa + off_g[3]);                            \
+    rb0 = *reinterpret_cast<const float4*>(pb + off_g[0]);                            \
+    rb1 = *reinterpret_cast<const float4*>(pb + off_g[1]);                            \
+    rb2 = *reinterpret_cast<const float4*>(pb + off_g[2]);                            \
+    rb3 = *reinterpret_cast<const float4*>(pb + off_g[3]);                            \
+  } while (0)
+#define FK_SSTORE(buf)                                                               \
+  do {                                                                               \
+    *reinterpret_cast<float4*>(&As[buf][off_s[0]]) = ra0;                             \
+    *reinterpret_cast<float4*>(&As[buf][off_s[1]]) = ra1;                             \
+    *reinterpret_cast<float4*>(&As[buf][off_s[2]]) = ra2;                             \
+    *reinterpret_cast<float4*>(&As[buf][off_s[3]]) = ra3;                             \
+    *reinterpret_cast<float4*>(&Bs[buf][off_s[0]]) = rb0;                             \
+    *reinterpret_cast<float4*>(&Bs[buf][off_s[1]]) = rb1;                             \
+    *reinterpret_cast<float4*>(&Bs[buf][off_s[2]]) = rb2;                             \
+    *reinterpret_cast<float4*>(&Bs[buf][off_s[3]]) = rb3;                             \
+  } while (0)
   floatx4 acc[2][2] = {};
-  mfma_tile64(As, Bs, acc);
-  store_acc(Al + (size_t)i * NB * Np + j * NB, Np, acc, true, -1.0f);
+  FK_GLOAD(0);
+  FK_SSTORE(0);
+  __syncthreads();
+  for (int k = 0; k < kb; ++k) {
+    const int cur = k & 1;
+    if (k + 1 < kb) FK_GLOAD(k + 1);
+    mfma_tile64(As[cur], Bs[cur], acc);
+    if (k + 1 < kb) FK_SSTORE(cur ^ 1);
+    __syncthreads();
+  }
+#undef FK_GLOAD
+#undef FK_SSTORE
+  store_acc(Al + (size_t)i * NB * Np + kb * NB, Np, acc, true, -1.0f);
 }
 
 // ------------------------------------------------------------------ triangular solves (FP32)
@@ -710,16 +749,17 @@ SolveLayout solve_layout(int N, int nlam, int ntgt, void* base, size_t cap) {
 }
 
 // Factor A32[l] = L L^T for every lambda (blocked, right-looking).
+// Left-looking blocked Cholesky: per block column, update with the finished panels
+// (one pass over the column), factor the diagonal block, solve the panel below it.
 static fk_status factor_all(fk_ctx* ctx, const SolveLayout& s) {
   const int nb = s.Np / NB;
   for (int kb = 0; kb < nb; ++kb) {
+    if (kb > 0)
+      hipLaunchKernelGGL(k_left_update, dim3(nb - kb, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb);
     hipLaunchKernelGGL(k_potrf_diag, dim3(s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv, ctx->flags);
     const int rem = nb - kb - 1;
-    if (rem > 0) {
+    if (rem > 0)
       hipLaunchKernelGGL(k_trsm_panel, dim3(rem, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv);
-      hipLaunchKernelGGL(k_syrk_update, dim3(rem * (rem + 1) / 2, s.nlam), dim3(256), 0, ctx->stream, s.A32,
-                         s.Np, kb);
-    }
   }
   FK_HIP(hipGetLastError());
   return FK_OK;

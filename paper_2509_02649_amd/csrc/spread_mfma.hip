@@ -62,9 +62,10 @@ __device__ __forceinline__ void win_start(uint32_t U, int fb, int w, int* i0, fl
   *s0 = (float)(int)(((uint32_t)c << fb) - U) * __uint_as_float((uint32_t)(127 - fb) << 23);
 }
 
-constexpr int SWAVE = 4;
-constexpr int SFLUSH = 256;
-constexpr int SPD = 4;      // chunks in flight per wave
+constexpr int SWAVE = 4;     // waves per workgroup, each independent
+constexpr int SFLUSH = 16;   // batches of 64 points between FP32 -> FP64 flushes
+constexpr int SPD = 4;       // weight chunks in flight per wave
+constexpr int PS = 36;       // kernel-value table row (16 psi1 + 16 psi2, padded; 16-byte rows)
 
 template <int W>
 __global__ __launch_bounds__(64 * SWAVE) void k_spread_mfma(const uint2* __restrict__ crd,
@@ -74,12 +75,13 @@ __global__ __launch_bounds__(64 * SWAVE) void k_spread_mfma(const uint2* __restr
                                                             double* __restrict__ grid) {
   constexpr int S = MB + W;
   constexpr int NT = (S * S + 15) / 16;
-  static_assert(S <= 16, "one subgrid row per 16 lanes");
+  static_assert(S <= 15, "subgrid offsets 0..S-1, offset 15 reads zero");
   extern __shared__ double smem_d[];
   const int C = nw + 1;
   const float two_over_w = 2.0f / (float)W;
   const float bl2 = beta * 1.44269504088896340736f;
-  double* sub = smem_d;   // S*S*C doubles
+  const int subn = (S * S * C + 1) & ~1;   // keep the tables 16-byte aligned
+  double* sub = smem_d;                    // S*S*C doubles
 
   const int b = blockIdx.x / slices;
   const int sl = blockIdx.x - b * slices;
@@ -89,25 +91,23 @@ __global__ __launch_bounds__(64 * SWAVE) void k_spread_mfma(const uint2* __restr
   const uint64_t q1 = p0 + len * (sl + 1) / slices;
   if (q0 == q1) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  float* tab = reinterpret_cast<float*>(sub + subn) + wv * 64 * PS;   // this wave's 64 rows
   const int bx = b / nbx, by = b - bx * nbx;
   const int o1 = bx * MB - W / 2, o2 = by * MB - W / 2;
   for (int i = tid; i < S * S * C; i += 64 * SWAVE) sub[i] = 0.0;
   __syncthreads();
 
   const int k = lane >> 4, j = lane & 15;
-  // Source lanes (byte addresses for ds_bpermute) of psi1[a] and psi2[b] for the
-  // cell (a, b) of column tile t.  Padding cells (>= S*S) read lane 15 of the
-  // point's row, whose kernel values are zero (15 >= S), so they add nothing.
-  int srca[NT], srcb[NT];
+  // Table offsets of psi1[a] and psi2[b] for the cell (a, b) of column tile t.
+  // Padding cells (>= S*S) read entry 15 of each half, which stays zero.
+  int offa[NT], offb[NT];
   bool cin[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int cell = t * 16 + j;
     cin[t] = cell < S * S;
-    const int a = cin[t] ? cell / S : 15;
-    const int bb = cin[t] ? cell - (cell / S) * S : 15;
-    srca[t] = (k * 16 + a) * 4;
-    srcb[t] = (k * 16 + bb) * 4;
+    offa[t] = cin[t] ? cell / S : 15;
+    offb[t] = 16 + (cin[t] ? cell - (cell / S) * S : 15);
   }
   floatx4_t acc[NT];
   float ones[NT];
@@ -138,63 +138,75 @@ __global__ __launch_bounds__(64 * SWAVE) void k_spread_mfma(const uint2* __restr
     }
   };
 
-  // Slice-relative 32-bit indices (a slice holds < 2^31 points).
+  // Slice-relative 32-bit indices (a slice holds < 2^31 points).  A wave takes
+  // batches of 64 points (16 chunks of 4): batch bb covers points 64 bb ..
   const uint32_t npts = (uint32_t)(q1 - q0);
-  const uint32_t nchunk = (npts + 3) / 4;
+  const uint32_t nbatch = (npts + 63) / 64;
   const uint2* __restrict__ cs = crd + q0;
   const float* __restrict__ ws = wts + q0 * 16;
-  // Software pipeline: while the SPD chunks of the current group are processed, the
-  // coordinates and weights of the next group are in flight.  The loads are
-  // unconditional (index clamped to the slice; weight blocks are zero padded to 16)
-  // and the tail is masked instead of branched around, so that the only wait for a
-  // group's loads is where the group is first used.
-  uint2 Uc[SPD], Un[SPD];
-  float Wc[SPD], Wn[SPD];
-  auto load = [&](uint32_t cc, uint2& U, float& w) {
-    const uint32_t p = min(cc * 4 + k, npts - 1);
-    U = cs[p];
-    w = ws[p * 16 + j];
-  };
+  // Loads are unconditional (index clamped to the slice; weight blocks are zero
+  // padded to 16) so that no branch makes the compiler wait for them early: the
+  // coordinates of the next batch and the weights of the next SPD chunks are in
+  // flight while the current ones are used.
+  auto wload = [&](uint32_t chunk) { return ws[min(chunk * 4 + k, npts - 1) * 16 + j]; };
+  auto cload = [&](uint32_t batch) { return cs[min(batch * 64 + lane, npts - 1)]; };
+  uint2 Un = cload(wv);
+  float Wq[SPD];
 #pragma unroll
-  for (int d = 0; d < SPD; ++d) load(wv + d * SWAVE, Uc[d], Wc[d]);
-  // Outer loop: groups of SFLUSH chunks per wave, then a flush of the FP32
-  // accumulators into the FP64 LDS subgrid (kept out of the inner loop so that
-  // the accumulators stay in the matrix-core registers).
-  for (uint32_t c0 = wv; c0 < nchunk; c0 += SFLUSH * SWAVE) {
-  const uint32_t cend = min(nchunk, c0 + SFLUSH * SWAVE);
-  for (uint32_t c = c0; c < cend; c += SPD * SWAVE) {
-#pragma unroll
-    for (int d = 0; d < SPD; ++d) load(c + (SPD + d) * SWAVE, Un[d], Wn[d]);
-#pragma unroll
-    for (int d = 0; d < SPD; ++d) {
-      const uint2 U = Uc[d];
-      const bool valid = (c + d * SWAVE) * 4 + k < npts;
-      const float aop = valid ? Wc[d] : 0.f;
+  for (int d = 0; d < SPD; ++d) Wq[d] = wload(wv * 16 + d);
+  float* row = tab + lane * PS;
+  int since = 0;
+  for (uint32_t bb = wv; bb < nbatch; bb += SWAVE) {
+    // Phase 1, one lane per point: window starts and the w kernel values per axis,
+    // written into the point's table row (zeros elsewhere).
+    const uint2 U = Un;
+    Un = cload(bb + SWAVE);
+    {
+      const bool valid = bb * 64 + lane < npts;
       int i1, i2;
       float s1, s2;
       win_start(U.x, fb, W, &i1, &s1);
       win_start(U.y, fb, W, &i2, &s2);
-      const int r1 = j - (i1 - o1), r2 = j - (i2 - o2);   // offset of cell j inside the window
-      const float px = (valid && r1 >= 0 && r1 < W) ? psi_es2(s1 + (float)r1, bl2, two_over_w) : 0.f;
-      const float py = (r2 >= 0 && r2 < W) ? psi_es2(s2 + (float)r2, bl2, two_over_w) : 0.f;
-      const int ipx = __float_as_int(px), ipy = __float_as_int(py);
+      float4* r4 = reinterpret_cast<float4*>(row);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) r4[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (valid) {
+        const int rel1 = i1 - o1, rel2 = 16 + i2 - o2;
+#pragma unroll
+        for (int r = 0; r < W; ++r) {
+          row[rel1 + r] = psi_es2(s1 + (float)r, bl2, two_over_w);
+          row[rel2 + r] = psi_es2(s2 + (float)r, bl2, two_over_w);
+        }
+      }
+    }
+    // the rows written by other lanes of this wave are read below
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // Phase 2: 16 chunks of 4 points on the matrix cores.
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const float aop = Wq[q % SPD];
+      // next weights of this slot: chunk q + SPD of this batch, or of the wave's next batch
+      const uint32_t nxt = (q + SPD < 16) ? bb * 16 + q + SPD : (bb + SWAVE) * 16 + (q + SPD - 16);
+      Wq[q % SPD] = wload(nxt);
+      const float* rk = tab + (4 * q + k) * PS;
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        const float xa = __int_as_float(__builtin_amdgcn_ds_bpermute(srca[t], ipx));
-        const float yb = __int_as_float(__builtin_amdgcn_ds_bpermute(srcb[t], ipy));
-        const float bv = xa * yb;
+        const float bv = rk[offa[t]] * rk[offb[t]];
         acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bv, acc[t], 0, 0, 0);
         ones[t] += bv;
       }
     }
-#pragma unroll
-    for (int d = 0; d < SPD; ++d) {
-      Uc[d] = Un[d];
-      Wc[d] = Wn[d];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (++since == SFLUSH) {
+      flush();
+      since = 0;
     }
   }
   flush();
-  }
   __syncthreads();
   for (int i = tid; i < S * S * C; i += 64 * SWAVE) {
     double v = sub[i];
@@ -222,7 +234,8 @@ fk_status launch_spread_mfma(hipStream_t st, int W, const uint32_t* crd, const u
   const int64_t per_bin = (n + nb - 1) / nb;
   const int slices = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (per_bin + 16383) / 16384));
   const int blocks = nb * slices;
-  const size_t lds = sizeof(double) * (MB + W) * (MB + W) * (nw + 1);
+  const size_t lds = sizeof(double) * (((MB + W) * (MB + W) * (nw + 1) + 1) & ~1) +
+                    sizeof(float) * SWAVE * 64 * PS;
   const float bt = (float)beta;
   const uint2* c2 = reinterpret_cast<const uint2*>(crd);
   const float* wf = reinterpret_cast<const float*>(wts);
