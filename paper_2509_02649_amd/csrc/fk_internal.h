@@ -98,9 +98,9 @@ fk_status backward_impl(fk_ctx* ctx, const SolveLayout& s, int d, const double* 
 fk_status reset_flags(fk_ctx* ctx);
 
 // MFMA spread for 8..16 weight channels over MB x MB-cell bins (spread_mfma.hip).
-int spread_mfma_bin();
+int spread_mfma_bin(int nf, int64_t n);
 bool spread_mfma_ok(int nw, int W);
-fk_status launch_spread_mfma(hipStream_t st, int W, const uint32_t* crd, const uint32_t* wts, int nw,
+fk_status launch_spread_mfma(hipStream_t st, int W, int MB, const uint32_t* crd, const uint32_t* wts, int nw,
                              const uint64_t* start, int nbx, int nb, int nf, int fb, double beta, int64_t n,
                              double* grid);
 

@@ -507,7 +507,7 @@ static bool use_mfma_spread(int nw) { return nw >= 8 && nw <= 16; }
 // mf: the points go through the two-pass sort and the MFMA spread (MB x MB bins).
 static BinGeom bin_geom(int nf, int C, int64_t n, bool mf) {
   BinGeom g;
-  g.T = mf ? spread_mfma_bin() : ((C > 8) ? 16 : 32);
+  g.T = mf ? spread_mfma_bin(nf, n) : ((C > 8) ? 16 : 32);
   if (g.T > nf) g.T = nf;
   g.tshift = ilog2(g.T);
   g.nbx = nf / g.T;
@@ -624,7 +624,7 @@ fk_status type1(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int64
   if (d != 2) return FK_EINVAL;
   double* grid = cv.take<double>((size_t)C * nf * nf);
   double* rowfft = cv.take<double>((size_t)C * nf * L * 2);
-  const bool split = use_mfma_spread(nw) && spread_mfma_ok(nw, W) && sort2_ok(nf / spread_mfma_bin());
+  const bool split = use_mfma_spread(nw) && spread_mfma_ok(nw, W) && sort2_ok(nf / spread_mfma_bin(nf, n));
   BinGeom g = bin_geom(nf, C, n, split);
   uint32_t* cnt = cv.take<uint32_t>((size_t)g.nb * g.nblk);
   uint32_t* totals = cv.take<uint32_t>((size_t)g.nb);
@@ -657,7 +657,8 @@ fk_status type1(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int64
   FK_HIP(hipEventRecord(ev[1], ctx->stream));
   int64_t per_bin = (n + g.nb - 1) / g.nb;
   if (split) {
-    fk_status s2 = launch_spread_mfma(ctx->stream, W, rec, wts, nw, start, g.nbx, g.nb, nf, fb, plan.beta, n, grid);
+    fk_status s2 = launch_spread_mfma(ctx->stream, W, g.T, rec, wts, nw, start, g.nbx, g.nb, nf, fb, plan.beta, n,
+                                      grid);
     if (s2 != FK_OK) return s2;
     if (info) info->bin = -g.T;   // negative: MFMA spread over T x T bins
   } else {

@@ -6,9 +6,10 @@
 // With LDS atomics that is w^2 (T+1) atomic adds per point; here it is a dense
 // matrix product on the matrix cores.
 //
-// * Bins are MB x MB grid cells (MB = 4), sorted beforehand (sort2.hip) so a
-//   bin's points are contiguous: fixed-point coordinates [U1, U2] (8 B) and a
-//   64-byte block of 16 FP32 weights (zero padded) per point.
+// * Bins are MB x MB grid cells, sorted beforehand (sort2.hip) so a bin's points
+//   are contiguous: fixed-point coordinates [U1, U2] (8 B) and a 64-byte block of
+//   16 FP32 weights (zero padded) per point.  MB = 2 when the bins are well
+//   filled (fewer subgrid cells per point: (2 + w)^2 against (4 + w)^2), else 4.
 // * A workgroup of SWAVE waves takes a slice of one bin; each wave takes the
 //   slice's points 4 at a time (one "chunk"), in stored order and on its own
 //   (no workgroup barrier in the loop).  All windows of a bin's points lie in
@@ -36,8 +37,6 @@
 namespace fk {
 
 namespace {
-
-constexpr int MB = 4;   // bin edge in grid cells
 
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
@@ -67,7 +66,7 @@ constexpr int SFLUSH = 16;   // batches of 64 points between FP32 -> FP64 flushe
 constexpr int SPD = 4;       // weight chunks in flight per wave
 constexpr int PS = 36;       // kernel-value table row (16 psi1 + 16 psi2, padded; 16-byte rows)
 
-template <int W>
+template <int W, int MB>
 __global__ __launch_bounds__(64 * SWAVE) void k_spread_mfma(const uint2* __restrict__ crd,
                                                             const float* __restrict__ wts, int nw,
                                                             const uint64_t* __restrict__ start, int nbx, int nf,
@@ -223,35 +222,46 @@ __global__ __launch_bounds__(64 * SWAVE) void k_spread_mfma(const uint2* __restr
 
 }  // namespace
 
-int spread_mfma_bin() { return MB; }
+int spread_mfma_bin(int nf, int64_t n) {
+  const int64_t nb2 = (int64_t)(nf / 2) * (nf / 2);
+  return (sort2_ok(nf / 2) && n >= 4096 * nb2) ? 2 : 4;
+}
 
 bool spread_mfma_ok(int nw, int W) { return nw >= 8 && nw <= 16 && W >= 4 && W <= 8; }
 
-fk_status launch_spread_mfma(hipStream_t st, int W, const uint32_t* crd, const uint32_t* wts, int nw,
+template <int W, int MB>
+static void launch_w(hipStream_t st, int blocks, size_t lds, const uint2* c2, const float* wf, int nw,
+                     const uint64_t* start, int nbx, int nf, int fb, float bt, int slices, double* grid) {
+  hipLaunchKernelGGL((k_spread_mfma<W, MB>), dim3(blocks), dim3(64 * SWAVE), lds, st, c2, wf, nw, start, nbx, nf, fb,
+                     bt, slices, grid);
+}
+
+fk_status launch_spread_mfma(hipStream_t st, int W, int MB, const uint32_t* crd, const uint32_t* wts, int nw,
                              const uint64_t* start, int nbx, int nb, int nf, int fb, double beta, int64_t n,
                              double* grid) {
-  if (!spread_mfma_ok(nw, W)) return FK_EINVAL;
+  if (!spread_mfma_ok(nw, W) || (MB != 2 && MB != 4)) return FK_EINVAL;
   const int64_t per_bin = (n + nb - 1) / nb;
   const int slices = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (per_bin + 16383) / 16384));
   const int blocks = nb * slices;
   const size_t lds = sizeof(double) * (((MB + W) * (MB + W) * (nw + 1) + 1) & ~1) +
-                    sizeof(float) * SWAVE * 64 * PS;
+                     sizeof(float) * SWAVE * 64 * PS;
   const float bt = (float)beta;
   const uint2* c2 = reinterpret_cast<const uint2*>(crd);
   const float* wf = reinterpret_cast<const float*>(wts);
+#define FK_SPREAD_W(WW)                                                                              \
+  case WW:                                                                                           \
+    if (MB == 2) launch_w<WW, 2>(st, blocks, lds, c2, wf, nw, start, nbx, nf, fb, bt, slices, grid); \
+    else launch_w<WW, 4>(st, blocks, lds, c2, wf, nw, start, nbx, nf, fb, bt, slices, grid);         \
+    break;
   switch (W) {
-    case 4: hipLaunchKernelGGL(k_spread_mfma<4>, dim3(blocks), dim3(64 * SWAVE), lds, st, c2, wf, nw, start, nbx,
-                               nf, fb, bt, slices, grid); break;
-    case 5: hipLaunchKernelGGL(k_spread_mfma<5>, dim3(blocks), dim3(64 * SWAVE), lds, st, c2, wf, nw, start, nbx,
-                               nf, fb, bt, slices, grid); break;
-    case 6: hipLaunchKernelGGL(k_spread_mfma<6>, dim3(blocks), dim3(64 * SWAVE), lds, st, c2, wf, nw, start, nbx,
-                               nf, fb, bt, slices, grid); break;
-    case 7: hipLaunchKernelGGL(k_spread_mfma<7>, dim3(blocks), dim3(64 * SWAVE), lds, st, c2, wf, nw, start, nbx,
-                               nf, fb, bt, slices, grid); break;
-    case 8: hipLaunchKernelGGL(k_spread_mfma<8>, dim3(blocks), dim3(64 * SWAVE), lds, st, c2, wf, nw, start, nbx,
-                               nf, fb, bt, slices, grid); break;
+    FK_SPREAD_W(4)
+    FK_SPREAD_W(5)
+    FK_SPREAD_W(6)
+    FK_SPREAD_W(7)
+    FK_SPREAD_W(8)
     default: return FK_EINVAL;
   }
+#undef FK_SPREAD_W
   return hipGetLastError() == hipSuccess ? FK_OK : FK_EHIP;
 }
 

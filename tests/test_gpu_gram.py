@@ -67,6 +67,18 @@ def test_gram_2d_multi_target(fk, ntgt, n):
     assert eT <= TOL and eb <= TOL
 
 
+@pytest.mark.parametrize("ntgt,n,m", [(16, 5_000_000, 4), (9, 4_300_000, 4)])
+def test_gram_2d_multi_target_dense_bins(fk, ntgt, n, m):
+    # dense bins (>= 4096 points per 2 x 2-cell bin on the 64 x 64 grid of m = 4) take the
+    # MFMA spread over 2 x 2-cell bins; the same path serves the 1e9-point workload (m = 32)
+    X = synth.uniform_points(91 + ntgt, 2, n)
+    Y = synth.batched_targets(X, 91 + ntgt, ntgt=ntgt)
+    eT, eb, info = _errors(fk, X, Y, m)
+    print(f"2-D T={ntgt} n={n} m={m}: eps_T={eT:.2e} eps_b={eb:.2e} bin={info['bin']} nf={info['nf']}")
+    assert info["bin"] == -2
+    assert eT <= TOL and eb <= TOL
+
+
 def test_gram_boundary_points_fold(fk):
     # points on the seam: -pi, fp32(pi) > pi, values just inside [-2pi, 2pi) that fold
     pts = np.array([-np.pi, np.float32(np.pi), 0.0, -2 * np.pi + 1e-3, 2 * np.pi - 1e-3, 3.0, -3.0],
