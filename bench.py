@@ -52,6 +52,23 @@ def _cpu_baseline(workload: str, ntgt: int, m: int):
                       f"({dt:.1f} s)"}
 
 
+def _traffic(kernel: str, n: int):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if it was taken on the
+    current source of the kernel (else None)."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"{kernel}_hbm_traffic.md")
+    src = os.path.join(ROOT, "paper_2509_02649_amd", "csrc", "spread_mfma.hip")
+    if not os.path.exists(path) or not os.path.exists(src):
+        return None
+    text = open(path).read()
+    h = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
+    b = re.search(r"hbm_bytes_per_point:\s*([0-9.eE+-]+)", text)
+    if not h or not b or h.group(1) != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    return float(b.group(1)) * n
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,6 +77,8 @@ def main():
     ap.add_argument("--workload", default="batched", choices=["batched", "sobolev2d"])
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="copy 1 GiB device to device before the steps (reference dispatch for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the point stream would shard "
@@ -95,6 +114,13 @@ def main():
         lams = [float(n) ** (-4.0 / 5.0)]
         bytes_per_point = 4 * 2 + 4
     torch.cuda.synchronize()
+    if args.calibrate:
+        # a plain copy of known size (1 GiB read, 1 GiB written) for scaling the HBM byte counters
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     infos = []
 
@@ -162,7 +188,7 @@ def main():
                      ["t_sort_ms", "t_spread_ms", "t_fft_ms", "t_assemble_ms", "t_factor_ms", "t_solve_ms"]},
         "refine_iters": int(infos[-1]["refine_iters"]),
         "roofline": {"bound": bound, "kernel": kernel, "achieved": achieved, "peak": peak, "unit": unit,
-                     "frac": achieved / peak, "traffic": None},
+                     "frac": achieved / peak, "traffic": _traffic(kernel, n)},
         "gram_rhs_hbm_frac": n * bytes_per_point / (gr_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
     }
     if args.workload == "batched":

@@ -193,17 +193,25 @@ __global__ __launch_bounds__(BT) void k_s2_scatter1(const TX* __restrict__ X, in
   }
 }
 
-// Pass 2 counts: workgroup (bx, slice) counts the bin columns of its slice of row bx.
-__global__ __launch_bounds__(256) void k_s2_count2(const uint2* __restrict__ crd1,
-                                                   const uint64_t* __restrict__ start1, int slices, int fb,
-                                                   int tshift, int nbx, uint32_t* __restrict__ cnt2) {
+// Pass 2 counts: workgroup (bx, slice) counts the bin columns of its slice of row bx,
+// CU1 loads in flight per thread.
+__global__ __launch_bounds__(BT) void k_s2_count2(const uint2* __restrict__ crd1,
+                                                  const uint64_t* __restrict__ start1, int slices, int fb,
+                                                  int tshift, int nbx, uint32_t* __restrict__ cnt2) {
   __shared__ uint32_t hist[KMAX];
   for (int i = threadIdx.x; i < nbx; i += blockDim.x) hist[i] = 0;
   __syncthreads();
   const int bx = blockIdx.x / slices, sl = blockIdx.x - bx * slices;
   const uint64_t p0 = start1[bx], len = start1[bx + 1] - p0;
   const uint64_t q0 = p0 + len * sl / slices, q1 = p0 + len * (sl + 1) / slices;
-  for (uint64_t p = q0 + threadIdx.x; p < q1; p += blockDim.x) atomicAdd(&hist[(crd1[p].y >> fb) >> tshift], 1u);
+  for (uint64_t p = q0 + threadIdx.x; p < q1; p += (uint64_t)CU1 * BT) {
+    uint32_t y[CU1];
+#pragma unroll
+    for (int u = 0; u < CU1; ++u) y[u] = crd1[min(p + (uint64_t)u * BT, q1 - 1)].y;
+#pragma unroll
+    for (int u = 0; u < CU1; ++u)
+      if (p + (uint64_t)u * BT < q1) atomicAdd(&hist[(y[u] >> fb) >> tshift], 1u);
+  }
   __syncthreads();
   for (int i = threadIdx.x; i < nbx; i += blockDim.x) cnt2[(int64_t)blockIdx.x * nbx + i] = hist[i];
 }
@@ -377,7 +385,7 @@ fk_status sort2(hipStream_t st, const void* X, fk_dtype dt, int64_t n, int64_t x
                        static_cast<const float*>(Y), nw, scale, nf_fix, fb, tshift, nbx, g.chunk1, b.off1,
                        b.start1, reinterpret_cast<uint2*>(b.crd1), reinterpret_cast<uint4*>(b.wts1), flags);
   }
-  hipLaunchKernelGGL(k_s2_count2, dim3(nbx * g.slices), dim3(256), 0, st, reinterpret_cast<const uint2*>(b.crd1),
+  hipLaunchKernelGGL(k_s2_count2, dim3(nbx * g.slices), dim3(BT), 0, st, reinterpret_cast<const uint2*>(b.crd1),
                      b.start1, g.slices, fb, tshift, nbx, b.cnt2);
   hipLaunchKernelGGL(k_s2_scan2, dim3(nbx), dim3(KMAX), 0, st, b.cnt2, b.start1, g.slices, nbx, b.off2, start);
   hipLaunchKernelGGL(k_s2_scatter2, dim3(nbx * g.slices), dim3(BT), lds, st,
