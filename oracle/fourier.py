@@ -85,6 +85,24 @@ def rhs(X: np.ndarray, Y: np.ndarray, m: int) -> np.ndarray:
     return _weighted_sum(X, Y, m, -1) / n
 
 
+def fourier_entry(X: np.ndarray, w, q, sign: int, chunk: int = 1 << 22) -> complex:
+    """One entry n^-1 sum_j w_j exp(sign * i q.X_j) of the sums above, for a single frequency
+    vector q (w = None for weight 1), by direct evaluation of the exponential per point in
+    float64 (Sec. 2.3).  For checking sampled entries of large inputs one at a time."""
+    X = np.atleast_2d(X)
+    d, n = X.shape
+    q = np.asarray(q, dtype=np.float64).reshape(d)
+    acc = 0.0 + 0.0j
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        phase = np.zeros(e - s)
+        for a in range(d):
+            phase += q[a] * X[a, s:e].astype(np.float64)
+        z = np.exp(sign * 1j * phase)
+        acc += z.sum() if w is None else (np.asarray(w[s:e], dtype=np.float64) * z).sum()
+    return acc / n
+
+
 def toeplitz_matrix(M: np.ndarray, m: int) -> np.ndarray:
     """The multilevel Toeplitz matrix Sigma[k, l] = M[l - k] over k, l in {-m..m}^d."""
     d = M.ndim

@@ -137,3 +137,40 @@ def test_device_generator_matches_host_generator(fk):
     ulp = np.abs(Yd.view(np.int32).astype(np.int64) - Yh.view(np.int32).astype(np.int64))
     assert ulp.max() <= 1
     assert (ulp == 0).mean() > 0.999
+
+
+def test_gram_full_size_batched_sampled(fk):
+    # The batched workload at full size, in the configuration bench.py times: n = 1e9 points and
+    # 16 targets generated on the device (seed of the benchmark), m = 32, two-pass sort into
+    # 2 x 2-cell bins and the MFMA spread.  The oracle evaluates sampled entries one by one.
+    import gc
+    n, T, m, seed = 1_000_000_000, 16, 32, 2509026495
+    gc.collect()
+    torch.cuda.empty_cache()
+    ctx = fk.Context(0)
+    X = fk.generate_uniform(seed, 2, n, ctx=ctx)
+    Y = fk.generate_targets(seed, X, T, ctx=ctx)
+    M, b, info = fk.gram(X, Y, m, ctx=ctx, info=True)
+    assert info["bin"] == -2
+    M = M.cpu().numpy()
+    b = b.cpu().numpy()
+    Xh = X.cpu().numpy()
+    y0 = Y[0].cpu().numpy()
+    del X, Y, ctx
+    gc.collect()
+    torch.cuda.empty_cache()
+    c = 2 * m
+    assert abs(M[c, c] - 1.0) <= 1e-6
+    errs = []
+    for q in [(1, 0), (64, -64)]:
+        mo = oracle.fourier_entry(Xh, None, q, +1)
+        errs.append(abs(M[c + q[0], c + q[1]] - mo))
+        print(f"M{q}: {errs[-1]:.2e}", flush=True)
+    scale = float(np.abs(y0.astype(np.float64)).mean())
+    b0 = b[0].reshape(2 * m + 1, 2 * m + 1)
+    for k in [(-32, 31)]:
+        bo = oracle.fourier_entry(Xh, y0, k, -1)
+        errs.append(abs(b0[m + k[0], m + k[1]] - bo) / scale)
+        print(f"b0{k}: {errs[-1]:.2e}", flush=True)
+    print(f"n=1e9 T=16 sampled: errors {['%.2e' % e for e in errs]}")
+    assert max(errs) <= TOL

@@ -180,3 +180,27 @@ def test_additive_blocks_match_stacked_design_matrix():
     # space of dimension exactly d - 1 (for n large enough)
     ev = np.linalg.eigvalsh(B)
     assert (ev < 1e-10).sum() == d - 1
+
+
+def test_fourier_entry_closed_forms_and_tables():
+    # single point: exp(sign i q.x0) exactly; x0 = (-pi, pi/2) gives (-1)^q1 i^q2 for sign +
+    x0 = np.array([[-np.pi], [np.pi / 2]])
+    for q in [(0, 0), (1, 0), (3, 2), (-5, 7), (64, -64)]:
+        want = (-1.0) ** q[0] * (1j) ** (q[1] % 4)
+        assert abs(oracle.fourier_entry(x0, None, q, +1) - want) < 1e-12
+        assert abs(oracle.fourier_entry(x0, None, q, -1) - np.conj(want)) < 1e-12
+    # equispaced points: zero for 0 < |q| < n, weights linear
+    n = 1000
+    xe = (-np.pi + 2 * np.pi * np.arange(n) / n)[None, :]
+    for q in [1, 17, 499]:
+        assert abs(oracle.fourier_entry(xe, None, [q], +1)) < 1e-12
+    # chunked sum equals the tabulated sums of gram_generator / rhs entry by entry
+    rng = np.random.default_rng(3)
+    X = rng.uniform(-np.pi, np.pi, size=(2, 3001))
+    Y = rng.standard_normal((1, 3001))
+    M = oracle.gram_generator(X, 3)
+    b = oracle.rhs(X, Y, 3)[0].reshape(7, 7)
+    for (q1, q2) in [(0, 0), (6, -6), (-2, 5)]:
+        assert abs(oracle.fourier_entry(X, None, (q1, q2), +1, chunk=1000) - M[q1 + 6, q2 + 6]) < 1e-13
+    for (k1, k2) in [(1, 2), (-3, 3)]:
+        assert abs(oracle.fourier_entry(X, Y[0], (k1, k2), -1, chunk=777) - b[k1 + 3, k2 + 3]) < 1e-13
