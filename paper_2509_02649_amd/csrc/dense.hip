@@ -576,34 +576,64 @@ __global__ __launch_bounds__(256) void k_resid64(const double* __restrict__ H, i
                                                  int rhs_per_col,
                                                  const double* __restrict__ Bre, const double* __restrict__ preal,
                                                  const double* __restrict__ lams, double* __restrict__ Rres) {
-  __shared__ double Hs[GK][GT + 1];   // Hs[k][row]
-  __shared__ double Xs[GK][GT + 1];   // Xs[k][col]
+  // double-buffered: the next k chunk is loaded into registers while the current one
+  // is multiplied out of LDS (one barrier per chunk)
+  __shared__ double Hs[2][GK][GT + 1];   // Hs[k][row]
+  __shared__ double Xs[2][GK][GT + 1];   // Xs[k][col]
   const int row0 = blockIdx.x * GT, col0 = blockIdx.y * GT;
   const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
-  double acc[4][4] = {};
-  for (int k0 = 0; k0 < Np; k0 += GK) {
-    for (int i = threadIdx.x; i < GT * GK; i += blockDim.x) {
-      int r = i / GK, k = i - r * GK;
-      Hs[k][r] = H[(size_t)(row0 + r) * Np + k0 + k];
-      int c = col0 + r;
-      Xs[k][r] = (c < ncols) ? X[(size_t)c * Np + k0 + k] : 0.0;
-    }
-    __syncthreads();
+  constexpr int PER = GT * GK / 256;   // elements of each tile per thread
+  double ph[PER], px[PER];
+  int lr[PER], lk[PER];
+  bool cok[PER];
 #pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int i = threadIdx.x + u * 256;
+    lr[u] = i / GK;
+    lk[u] = i - lr[u] * GK;
+    cok[u] = col0 + lr[u] < ncols;
+  }
+  const int cmax = ncols - 1;
+#define FK_RLOAD(k0)                                                                              \
+  do {                                                                                            \
+    _Pragma("unroll") for (int u = 0; u < PER; ++u) {                                             \
+      ph[u] = H[(size_t)(row0 + lr[u]) * Np + (k0) + lk[u]];                                      \
+      px[u] = X[(size_t)min(col0 + lr[u], cmax) * Np + (k0) + lk[u]];                             \
+    }                                                                                             \
+  } while (0)
+#define FK_RSTORE(buf)                                                                            \
+  do {                                                                                            \
+    _Pragma("unroll") for (int u = 0; u < PER; ++u) {                                             \
+      Hs[buf][lk[u]][lr[u]] = ph[u];                                                              \
+      Xs[buf][lk[u]][lr[u]] = cok[u] ? px[u] : 0.0;                                               \
+    }                                                                                             \
+  } while (0)
+  double acc[4][4] = {};
+  FK_RLOAD(0);
+  FK_RSTORE(0);
+  __syncthreads();
+  const int nk = Np / GK;
+  for (int kc = 0; kc < nk; ++kc) {
+    const int cur = kc & 1;
+    if (kc + 1 < nk) FK_RLOAD((kc + 1) * GK);
+#pragma unroll 2
     for (int k = 0; k < GK; ++k) {
       double a[4], b[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        a[i] = Hs[k][tr * 4 + i];
-        b[i] = Xs[k][tc * 4 + i];
+        a[i] = Hs[cur][k][tr * 4 + i];
+        b[i] = Xs[cur][k][tc * 4 + i];
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
     }
+    if (kc + 1 < nk) FK_RSTORE(cur ^ 1);
     __syncthreads();
   }
+#undef FK_RLOAD
+#undef FK_RSTORE
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
