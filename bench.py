@@ -35,7 +35,7 @@ def _cpu_baseline(workload: str, ntgt: int, m: int):
     import synth
     threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
     if workload == "batched":
-        n = 200_000
+        n = 1_500_000
         X = synth.uniform_points(synth.SEED_BASE + 5, 2, n)
         Y = synth.batched_targets(X, synth.SEED_BASE + 5, ntgt)
     else:

@@ -26,10 +26,11 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
 ]
-# Per-unit extras: the spread keeps its matrix-core accumulators in ordinary VGPRs
-# (no copies between the accumulation and vector register files in its loops).
+# Per-unit extras: the matrix-core kernels keep their accumulators in ordinary VGPRs
+# (no copies between the accumulation and vector register files in their loops).
 EXTRA = {
     "spread_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+    "dense.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
 }
 
 

@@ -306,60 +306,100 @@ __device__ __forceinline__ void store_acc(float* dst, int64_t ld, const floatx4 
 
 // ------------------------------------------------------------------ Cholesky kernels
 
-// Factor the diagonal block kb of every lambda (one workgroup per lambda), in FP64
-// in LDS; write L_kk (lower) back and inv(L_kk) to Linv[l][kb].
+// Factor the diagonal block kb of every lambda (one workgroup per lambda) in FP64;
+// write L_kk (lower) back and inv(L_kk) to Linv[l][kb].
+// Thread (r, q) = (tid / 4, tid % 4) keeps entries r, q + 4u (u = 0..15) of the block
+// in registers.  Right-looking, unscaled: at step j column j has received every update,
+// its owners publish it to P[.][j] (never written again), one barrier, and each row
+// below applies a[r][k] -= P[r][j] P[k][j] / P[j][j].  Then L[r][c] = P[r][c] / sqrt(P[c][c]).
+// The inverse X = inv(L) uses T = diag(sqrt P) X, which obeys
+// T[i][c] = delta_ic - sum_{k<i} (P[i][k] / P[k][k]) T[k][c]: the same right-looking
+// sweep over rows, each finished row published to a two-slot LDS buffer.
 __global__ __launch_bounds__(256) void k_potrf_diag(float* __restrict__ A, int Np, int kb,
                                                     float* __restrict__ Linv, int* flags) {
-  __shared__ double a[NB][NB + 1];
-  __shared__ double x[NB][NB + 1];
+  __shared__ double P[NB][NB + 1];
+  __shared__ double trow[2][NB];
+  __shared__ double piv[NB], rpiv[NB], sq[NB], rsq[NB];
   __shared__ int bad;
   const int l = blockIdx.x;
   float* Ab = A + (size_t)l * Np * Np + (size_t)kb * NB * Np + kb * NB;
-  for (int i = threadIdx.x; i < NB * NB; i += blockDim.x) {
-    int r = i / NB, c = i - r * NB;
-    a[r][c] = (c <= r) ? (double)Ab[(size_t)r * Np + c] : 0.0;
+  const int r = threadIdx.x >> 2, q = threadIdx.x & 3;
+  double a[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int k = 4 * u + q;
+    a[u] = (k <= r) ? (double)Ab[(size_t)r * Np + k] : 0.0;
   }
-  for (int i = threadIdx.x; i < NB * NB; i += blockDim.x) x[i / NB][i % NB] = 0.0;
   if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  // Right-looking, four threads per row (row = tid/4, column slice q = tid%4).
-  // In step j every thread reads column j unscaled and applies the scaled rank-1
-  // update to columns > j of its row; the column itself is scaled after a barrier.
-  const int row = threadIdx.x >> 2, q = threadIdx.x & 3;
   for (int j = 0; j < NB; ++j) {
-    const double dj = a[j][j];
-    const bool badj = !(dj > 0.0);   // non-positive or NaN pivot
-    const double d = sqrt(badj ? 1.0 : dj);
-    const double inv = 1.0 / d;
-    if (row > j) {
-      const double lij = a[row][j] * inv;
-      for (int k = j + 1 + q; k <= row; k += 4) a[row][k] -= lij * (a[k][j] * inv);
+    if (q == (j & 3) && r >= j) {
+      double v = a[0];
+#pragma unroll
+      for (int u = 1; u < 16; ++u)
+        if (u == (j >> 2)) v = a[u];
+      P[r][j] = v;
     }
     __syncthreads();
-    if (q == 0) {
-      if (row == j) a[j][j] = d;
-      else if (row > j) a[row][j] *= inv;
+    // all loads first and unconditionally (rows k < j of P[.][j] are not yet written:
+    // their values are discarded by the select), so the reads share one wait
+    const double pj = P[j][j];
+    const double prj = P[r][j];
+    double pk[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) pk[u] = P[4 * u + q][j];
+    const bool badj = !(pj > 0.0);  // non-positive or NaN pivot
+    const double rp = 1.0 / (badj ? 1.0 : pj);
+    const double f = prj * rp;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int k = 4 * u + q;
+      const double upd = fma(-f, pk[u], a[u]);
+      a[u] = (k > j && k <= r) ? upd : a[u];
     }
-    if (threadIdx.x == 0 && badj) bad = 1;
-    __syncthreads();
+    if (threadIdx.x == 0) {
+      piv[j] = badj ? 1.0 : pj;
+      rpiv[j] = rp;
+      if (badj) bad = 1;
+    }
   }
-  // Inverse of the lower-triangular block, row by row: every column c <= i of row i
-  // in parallel (four threads per column split the inner sum).
-  const int c = threadIdx.x >> 2;
-  for (int i = 0; i < NB; ++i) {
-    double s = 0.0;
-    if (c < i)
-      for (int k = c + q; k < i; k += 4) s += a[i][k] * x[k][c];
-    s += __shfl_xor(s, 1, 64);
-    s += __shfl_xor(s, 2, 64);
-    if (q == 0 && c <= i) x[i][c] = ((c == i ? 1.0 : 0.0) - s) / a[i][i];
+  // inverse: a[] now holds T[r][q + 4u]
+#pragma unroll
+  for (int u = 0; u < 16; ++u) a[u] = (4 * u + q == r) ? 1.0 : 0.0;
+  for (int j = 0; j < NB; ++j) {
+    if (r == j) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) trow[j & 1][4 * u + q] = a[u];
+    }
     __syncthreads();
+    // row j of T is zero beyond its diagonal, so columns c > j take a zero update
+    if (r > j) {
+      const double g = P[r][j] * rpiv[j];
+      double tv[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) tv[u] = trow[j & 1][4 * u + q];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) a[u] = fma(-g, tv[u], a[u]);
+    }
   }
+  if (threadIdx.x < NB) {
+    const double d = sqrt(piv[threadIdx.x]);
+    sq[threadIdx.x] = d;
+    rsq[threadIdx.x] = 1.0 / d;
+  }
+  __syncthreads();
   float* Li = Linv + ((size_t)l * (Np / NB) + kb) * NB * NB;
+  const double rs = rsq[r];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int c = 4 * u + q;
+    Li[r * NB + c] = (c <= r) ? (float)(a[u] * rs) : 0.0f;
+  }
   for (int i = threadIdx.x; i < NB * NB; i += blockDim.x) {
-    int r = i / NB, c = i - r * NB;
-    Ab[(size_t)r * Np + c] = (c <= r) ? (float)a[r][c] : 0.0f;
-    Li[i] = (float)x[r][c];
+    const int rr = i / NB, c = i - rr * NB;
+    float v = 0.0f;
+    if (c == rr) v = (float)sq[c];
+    else if (c < rr) v = (float)(P[rr][c] * rsq[c]);
+    Ab[(size_t)rr * Np + c] = v;
   }
   if (threadIdx.x == 0 && bad) {
     atomicOr(&flags[kFlagNotPD], 1);
@@ -566,68 +606,69 @@ __global__ __launch_bounds__(256) void k_bwd_mfma(const float* __restrict__ A, i
 // ------------------------------------------------------------------ FP64 residual
 // Rres[l][t] = Bre[t] - (H64 + lambda_l diag(preal)) X[l][t], for all (l, t) at once:
 // one FP64 GEMM H64 (Np x Np) times X (Np x ncolsTotal), then the diagonal and the
-// subtraction.  Column c of X/Rres is (l, t) with l = c / ntgt.  FP64 FMAs on the
-// vector ALUs (MI355X: the same 78.6 TF/s peak as FP64 MFMA): LDS tiles of 64 rows
-// x 64 columns, each thread a 4 x 4 register block.
-constexpr int GT = 64;  // output tile rows/cols
-constexpr int GK = 16;  // k chunk
-__global__ __launch_bounds__(256) void k_resid64(const double* __restrict__ H, int N, int Np,
-                                                 const double* __restrict__ X, int ncols, int ntgt,
-                                                 int rhs_per_col,
-                                                 const double* __restrict__ Bre, const double* __restrict__ preal,
-                                                 const double* __restrict__ lams, double* __restrict__ Rres) {
-  // double-buffered: the next k chunk is loaded into registers while the current one
-  // is multiplied out of LDS (one barrier per chunk)
-  __shared__ double Hs[2][GK][GT + 1];   // Hs[k][row]
-  __shared__ double Xs[2][GK][GT + 1];   // Xs[k][col]
-  const int row0 = blockIdx.x * GT, col0 = blockIdx.y * GT;
-  const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
-  constexpr int PER = GT * GK / 256;   // elements of each tile per thread
-  double ph[PER], px[PER];
-  int lr[PER], lk[PER];
-  bool cok[PER];
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int i = threadIdx.x + u * 256;
-    lr[u] = i / GK;
-    lk[u] = i - lr[u] * GK;
-    cok[u] = col0 + lr[u] < ncols;
-  }
+// subtraction.  Column c of X/Rres is (l, t) with l = c / ntgt.
+// On the FP64 matrix cores (v_mfma_f64_16x16x4f64): lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16]; element v of lane l's accumulator is D[l / 16 + 4 v][l % 16]
+// (the FP32 form holds D[4 (l / 16) + v][l % 16] instead).  A workgroup computes 64 rows
+// x 32 WN columns, its four waves 32 rows x 16 WN columns each (2 x WN blocks of
+// 16 x 16).  The k dimension streams in chunks of 16 through double-buffered LDS (the
+// next chunk in registers meanwhile).  Every operand value read from LDS feeds 16
+// multiply-adds (a 4 x 4 register block on the vector units gets 2), so the kernel is
+// bound by the FP64 matrix rate.
+template <int WN>
+__global__ __launch_bounds__(256) void k_resid64_mfma(const double* __restrict__ H, int N, int Np,
+                                                      const double* __restrict__ X, int ncols, int ntgt,
+                                                      int rhs_per_col, const double* __restrict__ Bre,
+                                                      const double* __restrict__ preal,
+                                                      const double* __restrict__ lams, double* __restrict__ Rres) {
+  constexpr int TM = 64, TN = 32 * WN, KC = 16;
+  constexpr int PH = TM * KC / 256, PX = TN * KC / 256;
+  __shared__ double Hs[2][KC][TM + 4];  // Hs[k][row]
+  __shared__ double Xs[2][KC][TN + 4];  // Xs[k][col]
+  const int row0 = blockIdx.x * TM, col0 = blockIdx.y * TN;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 16 * WN;
+  const int li = lane & 15, lk = lane >> 4;
+  // global element e = tid + 256 u of a chunk: (row or column e / 16, k e % 16)
+  const int gk = threadIdx.x & (KC - 1), gr = threadIdx.x >> 4;
   const int cmax = ncols - 1;
+  double ph[PH], px[PX];
 #define FK_RLOAD(k0)                                                                              \
   do {                                                                                            \
-    _Pragma("unroll") for (int u = 0; u < PER; ++u) {                                             \
-      ph[u] = H[(size_t)(row0 + lr[u]) * Np + (k0) + lk[u]];                                      \
-      px[u] = X[(size_t)min(col0 + lr[u], cmax) * Np + (k0) + lk[u]];                             \
-    }                                                                                             \
+    _Pragma("unroll") for (int u = 0; u < PH; ++u)                                                \
+      ph[u] = H[(size_t)(row0 + gr + 16 * u) * Np + (k0) + gk];                                  \
+    _Pragma("unroll") for (int u = 0; u < PX; ++u)                                                \
+      px[u] = X[(size_t)min(col0 + gr + 16 * u, cmax) * Np + (k0) + gk];                         \
   } while (0)
 #define FK_RSTORE(buf)                                                                            \
   do {                                                                                            \
-    _Pragma("unroll") for (int u = 0; u < PER; ++u) {                                             \
-      Hs[buf][lk[u]][lr[u]] = ph[u];                                                              \
-      Xs[buf][lk[u]][lr[u]] = cok[u] ? px[u] : 0.0;                                               \
-    }                                                                                             \
+    _Pragma("unroll") for (int u = 0; u < PH; ++u) Hs[buf][gk][gr + 16 * u] = ph[u];              \
+    _Pragma("unroll") for (int u = 0; u < PX; ++u)                                                \
+      Xs[buf][gk][gr + 16 * u] = (col0 + gr + 16 * u <= cmax) ? px[u] : 0.0;                      \
   } while (0)
-  double acc[4][4] = {};
+  doublex4 acc[2][WN];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
   FK_RLOAD(0);
   FK_RSTORE(0);
   __syncthreads();
-  const int nk = Np / GK;
+  const int nk = Np / KC;
   for (int kc = 0; kc < nk; ++kc) {
     const int cur = kc & 1;
-    if (kc + 1 < nk) FK_RLOAD((kc + 1) * GK);
-#pragma unroll 2
-    for (int k = 0; k < GK; ++k) {
-      double a[4], b[4];
+    if (kc + 1 < nk) FK_RLOAD((kc + 1) * KC);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        a[i] = Hs[cur][k][tr * 4 + i];
-        b[i] = Xs[cur][k][tc * 4 + i];
-      }
+    for (int ks = 0; ks < KC; ks += 4) {
+      double a[2], b[WN];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 2; ++i) a[i] = Hs[cur][ks + lk][wr + 16 * i + li];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+      for (int j = 0; j < WN; ++j) b[j] = Xs[cur][ks + lk][wc + 16 * j + li];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     if (kc + 1 < nk) FK_RSTORE(cur ^ 1);
     __syncthreads();
@@ -635,23 +676,27 @@ __global__ __launch_bounds__(256) void k_resid64(const double* __restrict__ H, i
 #undef FK_RLOAD
 #undef FK_RSTORE
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int j = 0; j < WN; ++j) {
+    const int c = col0 + wc + 16 * j + li;
+    if (c >= ncols) continue;
+    const int l = c / ntgt, t = c - l * ntgt;
+    const double lam = lams[l];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      int r = row0 + tr * 4 + i;
-      int c = col0 + tc * 4 + j;
-      if (c >= ncols) continue;
-      int l = c / ntgt, t = c - l * ntgt;
-      double xv = X[(size_t)c * Np + r];
-      double ax = acc[i][j] + (r < N ? lams[l] * preal[r] * xv : 0.0);
-      double bv = (r < N) ? Bre[(size_t)(rhs_per_col ? c : t) * Np + r] : 0.0;
-      Rres[(size_t)c * Np + r] = bv - ax;
-    }
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = row0 + wr + 16 * i + lk + 4 * v;
+        const double xv = X[(size_t)c * Np + r];
+        const double ax = acc[i][j][v] + (r < N ? lam * preal[r] * xv : 0.0);
+        const double bv = (r < N) ? Bre[(size_t)(rhs_per_col ? c : t) * Np + r] : 0.0;
+        Rres[(size_t)c * Np + r] = bv - ax;
+      }
+  }
 }
 
 // Same residual for a few columns (ncols <= 8): one wave per row streams the row of
 // H64 once (coalesced) against all columns; the tiled kernel above would leave
-// most of each 64-column tile empty.
+// most of each column tile empty.
 constexpr int NARROW = 8;
 __global__ __launch_bounds__(256) void k_resid64_narrow(const double* __restrict__ H, int N, int Np,
                                                         const double* __restrict__ X, int ncols, int ntgt,
@@ -693,9 +738,12 @@ static void launch_resid(hipStream_t st, const double* H, int N, int Np, const d
   if (ncols <= NARROW)
     hipLaunchKernelGGL(k_resid64_narrow, dim3((Np + 3) / 4), dim3(256), 0, st, H, N, Np, X, ncols, ntgt,
                        rhs_per_col, Bre, preal, lams, R);
+  else if (ncols <= 256)
+    hipLaunchKernelGGL(k_resid64_mfma<2>, dim3(Np / 64, (ncols + 63) / 64), dim3(256), 0, st, H, N, Np, X, ncols,
+                       ntgt, rhs_per_col, Bre, preal, lams, R);
   else
-    hipLaunchKernelGGL(k_resid64, dim3(Np / GT, (ncols + GT - 1) / GT), dim3(256), 0, st, H, N, Np, X, ncols, ntgt,
-                       rhs_per_col, Bre, preal, lams, R);
+    hipLaunchKernelGGL(k_resid64_mfma<4>, dim3(Np / 64, (ncols + 127) / 128), dim3(256), 0, st, H, N, Np, X, ncols,
+                       ntgt, rhs_per_col, Bre, preal, lams, R);
 }
 
 // Column norms squared of Rres and of the right-hand sides (per column), FP64.
@@ -968,7 +1016,7 @@ __global__ void k_mse_combine(const double* __restrict__ xg, const double* __res
 }
 
 // G64[c] = Hv X[c] - Bv[t]   (gradient direction g in real form)
-// (uses k_resid64 with lambda = 0:  Rres = Bv - Hv X  -> negate)
+// (the residual kernels with lambda = 0:  Rres = Bv - Hv X  -> negate)
 __global__ void k_negate(double* __restrict__ v, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) v[i] = -v[i];
