@@ -306,6 +306,16 @@ __device__ __forceinline__ void store_acc(float* dst, int64_t ld, const floatx4 
 
 // ------------------------------------------------------------------ Cholesky kernels
 
+// 1/x for a positive normal x: hardware reciprocal and two Newton steps
+// (r <- r + r (1 - x r)), a few ulp in FP64.
+__device__ inline double recip64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 // Factor the diagonal block kb of every lambda (one workgroup per lambda) in FP64;
 // write L_kk (lower) back and inv(L_kk) to Linv[l][kb].
 // Thread (r, q) = (tid / 4, tid % 4) keeps entries r, q + 4u (u = 0..15) of the block
@@ -331,6 +341,8 @@ __global__ __launch_bounds__(256) void k_potrf_diag(float* __restrict__ A, int N
     a[u] = (k <= r) ? (double)Ab[(size_t)r * Np + k] : 0.0;
   }
   if (threadIdx.x == 0) bad = 0;
+  // unrolled, so that the register holding column j is known at compile time
+#pragma unroll
   for (int j = 0; j < NB; ++j) {
     if (q == (j & 3) && r >= j) {
       double v = a[0];
@@ -348,7 +360,7 @@ __global__ __launch_bounds__(256) void k_potrf_diag(float* __restrict__ A, int N
 #pragma unroll
     for (int u = 0; u < 16; ++u) pk[u] = P[4 * u + q][j];
     const bool badj = !(pj > 0.0);  // non-positive or NaN pivot
-    const double rp = 1.0 / (badj ? 1.0 : pj);
+    const double rp = recip64(badj ? 1.0 : pj);
     const double f = prj * rp;
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
