@@ -38,7 +38,12 @@ struct Stage {
 };
 
 // Rank the batch by bucket, stage it in bucket order and write the runs.
-// Every thread of the workgroup calls this once per batch.
+// Every thread of the workgroup calls this once per batch.  Thread t brings point t
+// (key, U).  Its weights v0..v3 are the four 16-byte quarters of point t, or, with
+// kLaneQuarters, the quarter (lane % 4) of the wave's points 16 u + lane / 4 (u = 0..3):
+// loads in that order are contiguous across the wave, and the slots are exchanged
+// inside the wave before the weights are staged.
+template <bool kLaneQuarters>
 __device__ __forceinline__ void stage_batch(Stage& sm, int nk, bool ok, int key, uint2 U, uint4 v0, uint4 v1,
                                             uint4 v2, uint4 v3, uint2* __restrict__ crd_out,
                                             uint4* __restrict__ wts_out) {
@@ -69,7 +74,22 @@ __device__ __forceinline__ void stage_batch(Stage& sm, int nk, bool ok, int key,
     if (tid == 63) sm.total = x;
   }
   __syncthreads();
-  if (ok) {
+  if (kLaneQuarters) {
+    const uint32_t s = ok ? sm.lofs[key] + rank : 0xffffffffu;
+    if (ok) {
+      sm.sbin[s] = (uint16_t)key;
+      sm.scrd[s] = U;
+    }
+    const int lane = tid & 63;
+    const uint32_t s0 = __shfl(s, (lane >> 2), 64);
+    const uint32_t s1 = __shfl(s, 16 + (lane >> 2), 64);
+    const uint32_t s2 = __shfl(s, 32 + (lane >> 2), 64);
+    const uint32_t s3 = __shfl(s, 48 + (lane >> 2), 64);
+    if (s0 != 0xffffffffu) sm.swts[s0 * 4 + (lane & 3)] = v0;
+    if (s1 != 0xffffffffu) sm.swts[s1 * 4 + (lane & 3)] = v1;
+    if (s2 != 0xffffffffu) sm.swts[s2 * 4 + (lane & 3)] = v2;
+    if (s3 != 0xffffffffu) sm.swts[s3 * 4 + (lane & 3)] = v3;
+  } else if (ok) {
     const uint32_t s = sm.lofs[key] + rank;
     sm.sbin[s] = (uint16_t)key;
     sm.scrd[s] = U;
@@ -188,7 +208,7 @@ __global__ __launch_bounds__(BT) void k_s2_scatter1(const TX* __restrict__ X, in
       wb[c] = __float_as_uint(wc);
     }
     const int key = ok ? (int)((U.x >> fb) >> tshift) : 0;
-    stage_batch(sm, nbx, ok, key, U, make_uint4(wb[0], wb[1], wb[2], wb[3]), make_uint4(wb[4], wb[5], wb[6], wb[7]),
+    stage_batch<false>(sm, nbx, ok, key, U, make_uint4(wb[0], wb[1], wb[2], wb[3]), make_uint4(wb[4], wb[5], wb[6], wb[7]),
                 make_uint4(wb[8], wb[9], wb[10], wb[11]), make_uint4(wb[12], wb[13], wb[14], wb[15]), crd1, wts1);
   }
 }
@@ -265,27 +285,29 @@ __global__ __launch_bounds__(BT) void k_s2_scatter2(const uint2* __restrict__ cr
   const uint64_t p0 = start1[bx], len = start1[bx + 1] - p0;
   const uint64_t q0 = p0 + len * sl / slices, q1 = p0 + len * (sl + 1) / slices;
   if (q0 >= q1) return;
-  // The next batch is loaded (index clamped to the slice) while this one is staged.
+  // The next batch is loaded (indices clamped to the slice) while this one is staged:
+  // the coordinates of point base + tid, and of the wave's 64 weight blocks the
+  // 16-byte words lane, lane + 64, ... (contiguous across the wave).
+  const int lane = tid & 63;
+  const uint64_t wq = (uint64_t)(tid & ~63) + (lane >> 2);
   uint2 nU;
   uint4 n0, n1, n2, n3;
-  auto fetch = [&](uint64_t p) {
-    const uint64_t pc = min(p, q1 - 1);
-    nU = crd1[pc];
-    const uint4* src = wts1 + pc * 4;
-    n0 = src[0];
-    n1 = src[1];
-    n2 = src[2];
-    n3 = src[3];
+  auto fetch = [&](uint64_t b) {
+    nU = crd1[min(b + tid, q1 - 1)];
+    n0 = wts1[min(b + wq, q1 - 1) * 4 + (lane & 3)];
+    n1 = wts1[min(b + wq + 16, q1 - 1) * 4 + (lane & 3)];
+    n2 = wts1[min(b + wq + 32, q1 - 1) * 4 + (lane & 3)];
+    n3 = wts1[min(b + wq + 48, q1 - 1) * 4 + (lane & 3)];
   };
-  fetch(q0 + tid);
+  fetch(q0);
   for (uint64_t base = q0; base < q1; base += BT) {
     const uint64_t p = base + tid;
     const bool ok = p < q1;
     const uint2 U = nU;
     const uint4 v0 = n0, v1 = n1, v2 = n2, v3 = n3;
-    fetch(base + BT + tid);
+    fetch(base + BT);
     const int key = ok ? (int)((U.y >> fb) >> tshift) : 0;
-    stage_batch(sm, nbx, ok, key, U, v0, v1, v2, v3, crd, wts);
+    stage_batch<true>(sm, nbx, ok, key, U, v0, v1, v2, v3, crd, wts);
   }
 }
 
