@@ -28,6 +28,16 @@ __device__ __forceinline__ bool to_fixed(double x, double scale, uint32_t nf_fix
   return true;
 }
 
+// Bin coordinate of a point on one axis for the matrix-core spread.  The window of
+// a point at grid coordinate u (U = u 2^fb) covers the w cells from i0 = ceil(u - w/2);
+// its bin is (i0 mod nf) / 2^tshift, so the windows of a bin's points all start in the
+// bin's 2^tshift cells.  wbias = 2^fb - 1 + 8 2^fb - w 2^(fb-1), computed on the host
+// (the 8 cells of bias keep the 32-bit sum positive); nf is a power of two.
+__device__ __forceinline__ int window_bin(uint32_t U, int fb, uint32_t wbias, int nf, int tshift) {
+  const int i0 = (int)((U + wbias) >> fb) - 8;
+  return (i0 & (nf - 1)) >> tshift;
+}
+
 __device__ __forceinline__ double load_coord(const void* X, fk_dtype dt, int64_t idx) {
   return dt == FK_F64 ? static_cast<const double*>(X)[idx] : (double)static_cast<const float*>(X)[idx];
 }

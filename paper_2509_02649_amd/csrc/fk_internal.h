@@ -118,7 +118,7 @@ struct Sort2Bufs {
 bool sort2_ok(int nbx);
 void sort2_carve(Carve& cv, int64_t n, int nbx, Sort2Bufs* b);
 fk_status sort2(hipStream_t st, const void* X, fk_dtype dt, int64_t n, int64_t xstride, const void* Y, int nw,
-                int nf, int fb, double scale, int tshift, int nbx, const Sort2Bufs& b, uint32_t* crd,
+                int nf, int fb, int W, double scale, int tshift, int nbx, const Sort2Bufs& b, uint32_t* crd,
                 uint32_t* wts, uint64_t* start, int* flags);
 
 }  // namespace fk

@@ -639,7 +639,7 @@ fk_status type1(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int64
   FK_HIP(hipMemsetAsync(grid, 0, sizeof(double) * C * nf * nf, ctx->stream));
   if (split) {
     // records for the MFMA spread: two-pass sort, coordinates and weight blocks
-    fk_status s2 = sort2(ctx->stream, X, dt, n, xstride, Y, nw, nf, fb, scale, g.tshift, g.nbx, sb, rec, wts, start,
+    fk_status s2 = sort2(ctx->stream, X, dt, n, xstride, Y, nw, nf, fb, W, scale, g.tshift, g.nbx, sb, rec, wts, start,
                          ctx->flags);
     if (s2 != FK_OK) return s2;
   } else {

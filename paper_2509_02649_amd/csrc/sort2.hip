@@ -7,6 +7,8 @@
 // to unrelated addresses, and on HBM3E such scattered 8- and 64-byte writes run
 // far below the streaming rate.  Here the order is reached in two counting passes
 // over nbx buckets each (the bin row bx, then the bin column by inside a row).
+// A point's bin on an axis is set by the first cell of its kernel window, not by
+// the cell it lies in, so that a bin's windows cover MB + w - 1 cells per axis.
 // A workgroup ranks a batch of BT = 1024 points by bucket in LDS, stages the
 // batch in bucket order, and writes each bucket's part as one contiguous run
 // (about BT / nbx points), so both passes write in runs and read in streams.
@@ -123,8 +125,9 @@ __device__ __forceinline__ void stage_batch(Stage& sm, int nk, bool ok, int key,
 constexpr int CU1 = 4;
 template <typename TX>
 __global__ __launch_bounds__(BT) void k_s2_count1(const TX* __restrict__ X, int64_t n, int64_t xstride,
-                                                  double scale, uint32_t nf_fix, int fb, int tshift, int nbx,
-                                                  int64_t chunk, uint32_t* __restrict__ cnt, int* flags) {
+                                                  double scale, uint32_t nf_fix, int fb, uint32_t wbias,
+                                                  int tshift, int nbx, int64_t chunk, uint32_t* __restrict__ cnt,
+                                                  int* flags) {
   __shared__ uint32_t hist[KMAX];
   for (int i = threadIdx.x; i < nbx; i += blockDim.x) hist[i] = 0;
   __syncthreads();
@@ -144,7 +147,7 @@ __global__ __launch_bounds__(BT) void k_s2_count1(const TX* __restrict__ X, int6
       uint32_t U1, U2;
       bool ok = to_fixed(x1[u], scale, nf_fix, &U1, flags);
       ok = to_fixed(x2[u], scale, nf_fix, &U2, flags) && ok;
-      if (ok) atomicAdd(&hist[(U1 >> fb) >> tshift], 1u);
+      if (ok) atomicAdd(&hist[window_bin(U1, fb, wbias, (int)(nf_fix >> fb), tshift)], 1u);
     }
   }
   __syncthreads();
@@ -158,8 +161,9 @@ __global__ __launch_bounds__(BT) void k_s2_count1(const TX* __restrict__ X, int6
 template <typename TX>
 __global__ __launch_bounds__(BT) void k_s2_scatter1(const TX* __restrict__ X, int64_t n,
                                                     int64_t xstride, const TX* __restrict__ Y, int nw,
-                                                    double scale, uint32_t nf_fix, int fb, int tshift, int nbx,
-                                                    int64_t chunk, const uint32_t* __restrict__ off,
+                                                    double scale, uint32_t nf_fix, int fb, uint32_t wbias,
+                                                    int tshift, int nbx, int64_t chunk,
+                                                    const uint32_t* __restrict__ off,
                                                     const uint64_t* __restrict__ start1,
                                                     uint2* __restrict__ crd1, uint4* __restrict__ wts1,
                                                     int* flags) {
@@ -207,7 +211,7 @@ __global__ __launch_bounds__(BT) void k_s2_scatter1(const TX* __restrict__ X, in
       }
       wb[c] = __float_as_uint(wc);
     }
-    const int key = ok ? (int)((U.x >> fb) >> tshift) : 0;
+    const int key = ok ? window_bin(U.x, fb, wbias, (int)(nf_fix >> fb), tshift) : 0;
     stage_batch<false>(sm, nbx, ok, key, U, make_uint4(wb[0], wb[1], wb[2], wb[3]), make_uint4(wb[4], wb[5], wb[6], wb[7]),
                 make_uint4(wb[8], wb[9], wb[10], wb[11]), make_uint4(wb[12], wb[13], wb[14], wb[15]), crd1, wts1);
   }
@@ -217,7 +221,8 @@ __global__ __launch_bounds__(BT) void k_s2_scatter1(const TX* __restrict__ X, in
 // CU1 loads in flight per thread.
 __global__ __launch_bounds__(BT) void k_s2_count2(const uint2* __restrict__ crd1,
                                                   const uint64_t* __restrict__ start1, int slices, int fb,
-                                                  int tshift, int nbx, uint32_t* __restrict__ cnt2) {
+                                                  uint32_t wbias, int nf, int tshift, int nbx,
+                                                  uint32_t* __restrict__ cnt2) {
   __shared__ uint32_t hist[KMAX];
   for (int i = threadIdx.x; i < nbx; i += blockDim.x) hist[i] = 0;
   __syncthreads();
@@ -230,7 +235,7 @@ __global__ __launch_bounds__(BT) void k_s2_count2(const uint2* __restrict__ crd1
     for (int u = 0; u < CU1; ++u) y[u] = crd1[min(p + (uint64_t)u * BT, q1 - 1)].y;
 #pragma unroll
     for (int u = 0; u < CU1; ++u)
-      if (p + (uint64_t)u * BT < q1) atomicAdd(&hist[(y[u] >> fb) >> tshift], 1u);
+      if (p + (uint64_t)u * BT < q1) atomicAdd(&hist[window_bin(y[u], fb, wbias, nf, tshift)], 1u);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < nbx; i += blockDim.x) cnt2[(int64_t)blockIdx.x * nbx + i] = hist[i];
@@ -271,7 +276,8 @@ __global__ __launch_bounds__(BT) void k_s2_scatter2(const uint2* __restrict__ cr
                                                     const uint64_t* __restrict__ start1,
                                                     const uint32_t* __restrict__ off2,
                                                     const uint64_t* __restrict__ start, int slices, int fb,
-                                                    int tshift, int nbx, uint2* __restrict__ crd,
+                                                    uint32_t wbias, int nf, int tshift, int nbx,
+                                                    uint2* __restrict__ crd,
                                                     uint4* __restrict__ wts) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Stage& sm = *reinterpret_cast<Stage*>(smem_raw);
@@ -306,7 +312,7 @@ __global__ __launch_bounds__(BT) void k_s2_scatter2(const uint2* __restrict__ cr
     const uint2 U = nU;
     const uint4 v0 = n0, v1 = n1, v2 = n2, v3 = n3;
     fetch(base + BT);
-    const int key = ok ? (int)((U.y >> fb) >> tshift) : 0;
+    const int key = ok ? window_bin(U.y, fb, wbias, nf, tshift) : 0;
     stage_batch<true>(sm, nbx, ok, key, U, v0, v1, v2, v3, crd, wts);
   }
 }
@@ -384,35 +390,37 @@ void sort2_carve(Carve& cv, int64_t n, int nbx, Sort2Bufs* b) {
 }
 
 fk_status sort2(hipStream_t st, const void* X, fk_dtype dt, int64_t n, int64_t xstride, const void* Y, int nw,
-                int nf, int fb, double scale, int tshift, int nbx, const Sort2Bufs& b, uint32_t* crd,
+                int nf, int fb, int W, double scale, int tshift, int nbx, const Sort2Bufs& b, uint32_t* crd,
                 uint32_t* wts, uint64_t* start, int* flags) {
-  if (!sort2_ok(nbx) || nw > 16) return FK_EINVAL;
+  if (!sort2_ok(nbx) || nw > 16 || (nf & (nf - 1)) != 0 || (nbx << tshift) != nf) return FK_EINVAL;
   const Sort2Geom g = sort2_geom(n, nbx);
   const uint32_t nf_fix = (uint32_t)nf << fb;
+  const uint32_t one = 1u << fb;
+  const uint32_t wbias = (one - 1u) + 8u * one - ((uint32_t)W << (fb - 1));
   const size_t lds = sizeof(Stage);
   if (dt == FK_F64) {
     const double* Xd = static_cast<const double*>(X);
     hipLaunchKernelGGL(k_s2_count1<double>, dim3(g.nblk1), dim3(BT), 0, st, Xd, n, xstride, scale, nf_fix, fb,
-                       tshift, nbx, g.chunk1, b.cnt1, flags);
+                       wbias, tshift, nbx, g.chunk1, b.cnt1, flags);
     hipLaunchKernelGGL(k_s2_scan1, dim3(1), dim3(1024), 0, st, b.cnt1, nbx, g.nblk1, b.off1, b.start1);
     hipLaunchKernelGGL(k_s2_scatter1<double>, dim3(g.nblk1), dim3(BT), lds, st, Xd, n, xstride,
-                       static_cast<const double*>(Y), nw, scale, nf_fix, fb, tshift, nbx, g.chunk1, b.off1,
+                       static_cast<const double*>(Y), nw, scale, nf_fix, fb, wbias, tshift, nbx, g.chunk1, b.off1,
                        b.start1, reinterpret_cast<uint2*>(b.crd1), reinterpret_cast<uint4*>(b.wts1), flags);
   } else {
     const float* Xf = static_cast<const float*>(X);
     hipLaunchKernelGGL(k_s2_count1<float>, dim3(g.nblk1), dim3(BT), 0, st, Xf, n, xstride, scale, nf_fix, fb,
-                       tshift, nbx, g.chunk1, b.cnt1, flags);
+                       wbias, tshift, nbx, g.chunk1, b.cnt1, flags);
     hipLaunchKernelGGL(k_s2_scan1, dim3(1), dim3(1024), 0, st, b.cnt1, nbx, g.nblk1, b.off1, b.start1);
     hipLaunchKernelGGL(k_s2_scatter1<float>, dim3(g.nblk1), dim3(BT), lds, st, Xf, n, xstride,
-                       static_cast<const float*>(Y), nw, scale, nf_fix, fb, tshift, nbx, g.chunk1, b.off1,
+                       static_cast<const float*>(Y), nw, scale, nf_fix, fb, wbias, tshift, nbx, g.chunk1, b.off1,
                        b.start1, reinterpret_cast<uint2*>(b.crd1), reinterpret_cast<uint4*>(b.wts1), flags);
   }
   hipLaunchKernelGGL(k_s2_count2, dim3(nbx * g.slices), dim3(BT), 0, st, reinterpret_cast<const uint2*>(b.crd1),
-                     b.start1, g.slices, fb, tshift, nbx, b.cnt2);
+                     b.start1, g.slices, fb, wbias, nf, tshift, nbx, b.cnt2);
   hipLaunchKernelGGL(k_s2_scan2, dim3(nbx), dim3(KMAX), 0, st, b.cnt2, b.start1, g.slices, nbx, b.off2, start);
   hipLaunchKernelGGL(k_s2_scatter2, dim3(nbx * g.slices), dim3(BT), lds, st,
                      reinterpret_cast<const uint2*>(b.crd1), reinterpret_cast<const uint4*>(b.wts1), b.start1,
-                     b.off2, start, g.slices, fb, tshift, nbx, reinterpret_cast<uint2*>(crd),
+                     b.off2, start, g.slices, fb, wbias, nf, tshift, nbx, reinterpret_cast<uint2*>(crd),
                      reinterpret_cast<uint4*>(wts));
   return hipGetLastError() == hipSuccess ? FK_OK : FK_EHIP;
 }

@@ -8,12 +8,14 @@
 //
 // * Bins are MB x MB grid cells, sorted beforehand (sort2.hip) so a bin's points
 //   are contiguous: fixed-point coordinates [U1, U2] (8 B) and a 64-byte block of
-//   16 FP32 weights (zero padded) per point.  MB = 2 when the bins are well
-//   filled (fewer subgrid cells per point: (2 + w)^2 against (4 + w)^2), else 4.
+//   16 FP32 weights (zero padded) per point.  A point belongs to the bin holding
+//   the first cell of its window (not its own cell), so the windows of a bin's
+//   points start in MB consecutive cells per axis.  MB = 2 when the bins are well
+//   filled (fewer subgrid cells per point: (1 + w)^2 against (3 + w)^2), else 4.
 // * A workgroup of SWAVE waves takes a slice of one bin; each wave takes the
 //   slice's points 4 at a time (one "chunk"), in stored order and on its own
 //   (no workgroup barrier in the loop).  All windows of a bin's points lie in
-//   its S x S subgrid, S = MB + w, so with the kernel value zero outside a
+//   its S x S subgrid, S = MB + w - 1, so with the kernel value zero outside a
 //   point's own window,
 //     D[c][cell] += sum_k W[c][k] * psi1_k[cell / S] * psi2_k[cell % S]
 //   over the S^2 cells is NT = ceil(S^2 / 16) v_mfma_f32_16x16x4f32 per chunk:
@@ -72,7 +74,7 @@ __global__ __launch_bounds__(64 * SWAVE) void k_spread_mfma(const uint2* __restr
                                                             const uint64_t* __restrict__ start, int nbx, int nf,
                                                             int fb, float beta, int slices,
                                                             double* __restrict__ grid) {
-  constexpr int S = MB + W;
+  constexpr int S = MB + W - 1;
   constexpr int NT = (S * S + 15) / 16;
   static_assert(S <= 15, "subgrid offsets 0..S-1, offset 15 reads zero");
   extern __shared__ double smem_d[];
@@ -92,7 +94,7 @@ __global__ __launch_bounds__(64 * SWAVE) void k_spread_mfma(const uint2* __restr
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   float* tab = reinterpret_cast<float*>(sub + subn) + wv * 64 * PS;   // this wave's 64 rows
   const int bx = b / nbx, by = b - bx * nbx;
-  const int o1 = bx * MB - W / 2, o2 = by * MB - W / 2;
+  const int o1 = bx * MB, o2 = by * MB;   // first subgrid cell (window starts o .. o + MB - 1)
   for (int i = tid; i < S * S * C; i += 64 * SWAVE) sub[i] = 0.0;
   __syncthreads();
 
@@ -169,8 +171,10 @@ __global__ __launch_bounds__(64 * SWAVE) void k_spread_mfma(const uint2* __restr
       float4* r4 = reinterpret_cast<float4*>(row);
 #pragma unroll
       for (int q = 0; q < 8; ++q) r4[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (valid) {
-        const int rel1 = i1 - o1, rel2 = 16 + i2 - o2;
+      // (the sort put the point here because its window starts lie in the bin, so
+      // the relative starts are below MB; the test keeps the table rows in bounds)
+      const int rel1 = (i1 - o1) & (nf - 1), rel2 = 16 + ((i2 - o2) & (nf - 1));
+      if (valid && rel1 < MB && rel2 < 16 + MB) {
 #pragma unroll
         for (int r = 0; r < W; ++r) {
           row[rel1 + r] = psi_es2(s1 + (float)r, bl2, two_over_w);
@@ -243,7 +247,7 @@ fk_status launch_spread_mfma(hipStream_t st, int W, int MB, const uint32_t* crd,
   const int64_t per_bin = (n + nb - 1) / nb;
   const int slices = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (per_bin + 16383) / 16384));
   const int blocks = nb * slices;
-  const size_t lds = sizeof(double) * (((MB + W) * (MB + W) * (nw + 1) + 1) & ~1) +
+  const size_t lds = sizeof(double) * (((MB + W - 1) * (MB + W - 1) * (nw + 1) + 1) & ~1) +
                      sizeof(float) * SWAVE * 64 * PS;
   const float bt = (float)beta;
   const uint2* c2 = reinterpret_cast<const uint2*>(crd);
