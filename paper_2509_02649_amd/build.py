@@ -31,6 +31,7 @@ FLAGS = [
 EXTRA = {
     "spread_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
     "dense.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+    "spread_op.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
 }
 
 

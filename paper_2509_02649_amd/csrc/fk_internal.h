@@ -104,8 +104,18 @@ fk_status launch_spread_mfma(hipStream_t st, int W, int MB, const uint32_t* crd,
                              const uint64_t* start, int nbx, int nb, int nf, int fb, double beta, int64_t n,
                              double* grid);
 
-// Two-pass bin sort for the MFMA spread (sort2.hip): scratch buffers carved from
+// MFMA spread for 0..7 weight channels as per-channel outer products over 8 x 8-cell
+// bins (spread_op.hip).
+int spread_op_bin();
+bool spread_op_ok(int nw, int W);
+fk_status launch_spread_op(hipStream_t st, int W, const uint32_t* crd, const uint32_t* wts, int nw,
+                           const uint64_t* start, int nbx, int nb, int nf, int fb, double beta, int64_t n,
+                           double* grid);
+
+// Two-pass bin sort for the MFMA spreads (sort2.hip): scratch buffers carved from
 // the caller's workspace, and the sort itself (bin starts in start[0..nbx^2]).
+// Records: coordinates (2 words) and sort2_words(nw) weight words per point
+// (16 for 8..16 channels, else the next power of two >= nw, at least 1).
 struct Sort2Bufs {
   uint32_t* cnt1 = nullptr;
   uint32_t* off1 = nullptr;
@@ -116,7 +126,8 @@ struct Sort2Bufs {
   uint32_t* wts1 = nullptr;
 };
 bool sort2_ok(int nbx);
-void sort2_carve(Carve& cv, int64_t n, int nbx, Sort2Bufs* b);
+int sort2_words(int nw);
+void sort2_carve(Carve& cv, int64_t n, int nbx, int wv, Sort2Bufs* b);
 fk_status sort2(hipStream_t st, const void* X, fk_dtype dt, int64_t n, int64_t xstride, const void* Y, int nw,
                 int nf, int fb, int W, double scale, int tshift, int nbx, const Sort2Bufs& b, uint32_t* crd,
                 uint32_t* wts, uint64_t* start, int* flags);

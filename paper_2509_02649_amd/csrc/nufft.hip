@@ -501,13 +501,22 @@ struct BinGeom {
   int64_t chunk;
 };
 
-// Channels whose spread runs on MFMA (spread_mfma.hip): 8..16 weighted channels.
-static bool use_mfma_spread(int nw) { return nw >= 8 && nw <= 16; }
+// Spread used by the 2-D type-1 stage.  kRows: 8..16 weighted channels as the rows
+// of matrix-core products (spread_mfma.hip); kOuter: 0..7 weighted channels as
+// per-channel outer products (spread_op.hip); both after the two-pass bin sort.
+// kAtomic: one counting pass and FP64 LDS atomics (other channel counts or widths).
+enum class Spread2 { kAtomic, kRows, kOuter };
 
-// mf: the points go through the two-pass sort and the MFMA spread (MB x MB bins).
-static BinGeom bin_geom(int nf, int C, int64_t n, bool mf) {
+static Spread2 spread2_kind(int nw, int nf, int W, int64_t n) {
+  if (nw >= 8 && nw <= 16 && spread_mfma_ok(nw, W) && sort2_ok(nf / spread_mfma_bin(nf, n))) return Spread2::kRows;
+  if (spread_op_ok(nw, W) && nf % spread_op_bin() == 0 && sort2_ok(nf / spread_op_bin())) return Spread2::kOuter;
+  return Spread2::kAtomic;
+}
+
+static BinGeom bin_geom(int nf, int C, int64_t n, Spread2 kind) {
   BinGeom g;
-  g.T = mf ? spread_mfma_bin(nf, n) : ((C > 8) ? 16 : 32);
+  g.T = kind == Spread2::kRows ? spread_mfma_bin(nf, n)
+        : kind == Spread2::kOuter ? spread_op_bin() : ((C > 8) ? 16 : 32);
   if (g.T > nf) g.T = nf;
   g.tshift = ilog2(g.T);
   g.nbx = nf / g.T;
@@ -518,33 +527,40 @@ static BinGeom bin_geom(int nf, int C, int64_t n, bool mf) {
   return g;
 }
 
+// Workspace of type1(): the largest layout any kernel width can select (the width
+// follows from K and the context's tolerance, not known here).
 size_t type1_workspace(int d, int64_t n, int nw, int K, double eps) {
   (void)eps;
   int nf = 16;
   while (nf < 2 * (2 * K + 1)) nf <<= 1;
   const int C = nw + 1;
   const int L = 2 * K + 1;
-  Carve cv(nullptr, 0);
-  if (d == 1) {
-    cv.take<double>((size_t)C * nf);
-  } else {
+  auto layout = [&](Spread2 kind) {
+    Carve cv(nullptr, 0);
+    if (d == 1) {
+      cv.take<double>((size_t)C * nf);
+      return cv.off;
+    }
     cv.take<double>((size_t)C * nf * nf);          // FP64 grid
     cv.take<double>((size_t)C * nf * L * 2);        // row-FFT output
-    // the MFMA layout (when the channel count allows it) is the larger of the two
-    BinGeom g = bin_geom(nf, C, n, use_mfma_spread(nw));
+    BinGeom g = bin_geom(nf, C, n, kind);
     cv.take<uint32_t>((size_t)g.nb * g.nblk);
     cv.take<uint32_t>((size_t)g.nb);
     cv.take<uint64_t>((size_t)g.nb + 1);
-    if (use_mfma_spread(nw)) {
+    if (kind != Spread2::kAtomic) {
+      const int wv = sort2_words(nw);
       cv.take<uint32_t>((size_t)n * 2);
-      cv.take<uint32_t>((size_t)n * 16);
+      cv.take<uint32_t>((size_t)n * wv);
       Sort2Bufs sb;
-      sort2_carve(cv, n, g.nbx, &sb);
+      sort2_carve(cv, n, g.nbx, wv, &sb);
     } else {
       cv.take<uint32_t>((size_t)n * (2 + nw));
     }
-  }
-  return cv.off + 256;
+    return cv.off;
+  };
+  size_t sz = layout(Spread2::kAtomic);
+  for (int w = 4; w <= 8; ++w) sz = std::max(sz, layout(spread2_kind(nw, nf, w, n)));
+  return sz + 256;
 }
 
 template <int W>
@@ -624,21 +640,23 @@ fk_status type1(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int64
   if (d != 2) return FK_EINVAL;
   double* grid = cv.take<double>((size_t)C * nf * nf);
   double* rowfft = cv.take<double>((size_t)C * nf * L * 2);
-  const bool split = use_mfma_spread(nw) && spread_mfma_ok(nw, W) && sort2_ok(nf / spread_mfma_bin(nf, n));
-  BinGeom g = bin_geom(nf, C, n, split);
+  const Spread2 kind = spread2_kind(nw, nf, W, n);
+  const bool split = kind != Spread2::kAtomic;   // two-pass sort, then an MFMA spread
+  const int wv = sort2_words(nw);
+  BinGeom g = bin_geom(nf, C, n, kind);
   uint32_t* cnt = cv.take<uint32_t>((size_t)g.nb * g.nblk);
   uint32_t* totals = cv.take<uint32_t>((size_t)g.nb);
   uint64_t* start = cv.take<uint64_t>((size_t)g.nb + 1);
   uint32_t* rec = cv.take<uint32_t>((size_t)n * (split ? 2 : 2 + nw));
-  uint32_t* wts = split ? cv.take<uint32_t>((size_t)n * 16) : nullptr;
+  uint32_t* wts = split ? cv.take<uint32_t>((size_t)n * wv) : nullptr;
   Sort2Bufs sb;
-  if (split) sort2_carve(cv, n, g.nbx, &sb);
+  if (split) sort2_carve(cv, n, g.nbx, wv, &sb);
   if (!cv.ok()) return FK_ENOMEM;
   if (info) info->bin = g.T;
   FK_HIP(hipEventRecord(ev[0], ctx->stream));
   FK_HIP(hipMemsetAsync(grid, 0, sizeof(double) * C * nf * nf, ctx->stream));
   if (split) {
-    // records for the MFMA spread: two-pass sort, coordinates and weight blocks
+    // records for the MFMA spreads: two-pass sort, coordinates and weight words
     fk_status s2 = sort2(ctx->stream, X, dt, n, xstride, Y, nw, nf, fb, W, scale, g.tshift, g.nbx, sb, rec, wts, start,
                          ctx->flags);
     if (s2 != FK_OK) return s2;
@@ -656,11 +674,15 @@ fk_status type1(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int64
   FK_HIP(hipGetLastError());
   FK_HIP(hipEventRecord(ev[1], ctx->stream));
   int64_t per_bin = (n + g.nb - 1) / g.nb;
-  if (split) {
+  if (kind == Spread2::kRows) {
     fk_status s2 = launch_spread_mfma(ctx->stream, W, g.T, rec, wts, nw, start, g.nbx, g.nb, nf, fb, plan.beta, n,
                                       grid);
     if (s2 != FK_OK) return s2;
     if (info) info->bin = -g.T;   // negative: MFMA spread over T x T bins
+  } else if (kind == Spread2::kOuter) {
+    fk_status s2 = launch_spread_op(ctx->stream, W, rec, wts, nw, start, g.nbx, g.nb, nf, fb, plan.beta, n, grid);
+    if (s2 != FK_OK) return s2;
+    if (info) info->bin = -g.T;
   } else {
     const int H = (W + 1) / 2;
     const int S = g.T + 2 * H;

@@ -39,16 +39,10 @@ struct Stage {
   uint4 swts[BT * 4];
 };
 
-// Rank the batch by bucket, stage it in bucket order and write the runs.
-// Every thread of the workgroup calls this once per batch.  Thread t brings point t
-// (key, U).  Its weights v0..v3 are the four 16-byte quarters of point t, or, with
-// kLaneQuarters, the quarter (lane % 4) of the wave's points 16 u + lane / 4 (u = 0..3):
-// loads in that order are contiguous across the wave, and the slots are exchanged
-// inside the wave before the weights are staged.
-template <bool kLaneQuarters>
-__device__ __forceinline__ void stage_batch(Stage& sm, int nk, bool ok, int key, uint2 U, uint4 v0, uint4 v1,
-                                            uint4 v2, uint4 v3, uint2* __restrict__ crd_out,
-                                            uint4* __restrict__ wts_out) {
+// Rank of every point of the batch inside its bucket (LDS atomics), and the
+// exclusive prefix sums of the batch's bucket counts (sm.lofs, sm.total).
+template <class St>
+__device__ __forceinline__ uint32_t rank_scan(St& sm, int nk, bool ok, int key) {
   const int tid = threadIdx.x;
   const uint32_t rank = ok ? atomicAdd(&sm.hist[key], 1u) : 0u;
   __syncthreads();
@@ -76,6 +70,42 @@ __device__ __forceinline__ void stage_batch(Stage& sm, int nk, bool ok, int key,
     if (tid == 63) sm.total = x;
   }
   __syncthreads();
+  return rank;
+}
+
+// Write the staged coordinates as runs, one per bucket (after the staging barrier).
+template <class St>
+__device__ __forceinline__ void write_coords(St& sm, uint2* __restrict__ crd_out) {
+  const int tid = threadIdx.x;
+  if ((uint32_t)tid < sm.total) {
+    const int b = sm.sbin[tid];
+    crd_out[sm.cur[b] + (tid - sm.lofs[b])] = sm.scrd[tid];
+  }
+}
+
+// After the staged batch is written: advance the bucket cursors, clear the counts.
+template <class St>
+__device__ __forceinline__ void advance_cursors(St& sm, int nk) {
+  __syncthreads();
+  for (int b = threadIdx.x; b < nk; b += BT) {
+    sm.cur[b] += sm.hist[b];
+    sm.hist[b] = 0;
+  }
+  __syncthreads();
+}
+
+// Rank the batch by bucket, stage it in bucket order and write the runs.
+// Every thread of the workgroup calls this once per batch.  Thread t brings point t
+// (key, U).  Its weights v0..v3 are the four 16-byte quarters of point t, or, with
+// kLaneQuarters, the quarter (lane % 4) of the wave's points 16 u + lane / 4 (u = 0..3):
+// loads in that order are contiguous across the wave, and the slots are exchanged
+// inside the wave before the weights are staged.
+template <bool kLaneQuarters>
+__device__ __forceinline__ void stage_batch(Stage& sm, int nk, bool ok, int key, uint2 U, uint4 v0, uint4 v1,
+                                            uint4 v2, uint4 v3, uint2* __restrict__ crd_out,
+                                            uint4* __restrict__ wts_out) {
+  const int tid = threadIdx.x;
+  const uint32_t rank = rank_scan(sm, nk, ok, key);
   if (kLaneQuarters) {
     const uint32_t s = ok ? sm.lofs[key] + rank : 0xffffffffu;
     if (ok) {
@@ -102,21 +132,13 @@ __device__ __forceinline__ void stage_batch(Stage& sm, int nk, bool ok, int key,
   }
   __syncthreads();
   const uint32_t total = sm.total;
-  if ((uint32_t)tid < total) {
-    const int b = sm.sbin[tid];
-    crd_out[sm.cur[b] + (tid - sm.lofs[b])] = sm.scrd[tid];
-  }
+  write_coords(sm, crd_out);
   for (uint32_t q = tid; q < total * 4; q += BT) {
     const uint32_t s = q >> 2;
     const int b = sm.sbin[s];
     wts_out[(sm.cur[b] + (s - sm.lofs[b])) * 4 + (q & 3)] = sm.swts[q];
   }
-  __syncthreads();
-  for (int b = tid; b < nk; b += BT) {
-    sm.cur[b] += sm.hist[b];
-    sm.hist[b] = 0;
-  }
-  __syncthreads();
+  advance_cursors(sm, nk);
 }
 
 // Pass 1 counts: bucket = bin row of every valid point, one row of nbx counts per
@@ -317,6 +339,163 @@ __global__ __launch_bounds__(BT) void k_s2_scatter2(const uint2* __restrict__ cr
   }
 }
 
+// ---------------------------------------------------------------- narrow records
+// The same two passes for 0..7 weight channels (the outer-product spread): records of
+// WV = 1, 2, 4 or 8 weight words per point (zero padded), staged word by word.
+template <int WV>
+struct StageN {
+  unsigned long long cur[KMAX];
+  uint32_t hist[KMAX];
+  uint32_t lofs[KMAX];
+  uint32_t total;
+  uint16_t sbin[BT];
+  uint2 scrd[BT];
+  uint32_t swts[BT * WV];
+};
+
+template <int WV>
+__device__ __forceinline__ void write_weights_n(StageN<WV>& sm, uint32_t* __restrict__ wts_out) {
+  const uint32_t total = sm.total;
+  for (uint32_t q = threadIdx.x; q < total * WV; q += BT) {
+    const uint32_t s = q / WV;
+    const int b = sm.sbin[s];
+    wts_out[(sm.cur[b] + (s - sm.lofs[b])) * WV + q % WV] = sm.swts[q];
+  }
+}
+
+template <typename TX, int WV>
+__global__ __launch_bounds__(BT) void k_s2n_scatter1(const TX* __restrict__ X, int64_t n, int64_t xstride,
+                                                     const TX* __restrict__ Y, int nw, double scale,
+                                                     uint32_t nf_fix, int fb, uint32_t wbias, int tshift, int nbx,
+                                                     int64_t chunk, const uint32_t* __restrict__ off,
+                                                     const uint64_t* __restrict__ start1,
+                                                     uint2* __restrict__ crd1, uint32_t* __restrict__ wts1,
+                                                     int* flags) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  StageN<WV>& sm = *reinterpret_cast<StageN<WV>*>(smem_raw);
+  const int tid = threadIdx.x;
+  for (int b = tid; b < nbx; b += BT) {
+    sm.cur[b] = start1[b] + off[(int64_t)blockIdx.x * nbx + b];
+    sm.hist[b] = 0;
+  }
+  __syncthreads();
+  const int64_t beg = (int64_t)blockIdx.x * chunk;
+  const int64_t end = min(n, beg + chunk);
+  if (beg >= end) return;
+  // next batch in flight (index clamped to the chunk; no target row is read when nw = 0)
+  double nx1, nx2;
+  float ny[WV];
+#define FK_FETCH1N(jj)                                                                     \
+  do {                                                                                     \
+    const int64_t jc = min((int64_t)(jj), end - 1);                                        \
+    nx1 = (double)X[jc];                                                                   \
+    nx2 = (double)X[xstride + jc];                                                         \
+    _Pragma("unroll") for (int c = 0; c < WV; ++c)                                         \
+      ny[c] = nw > 0 ? (float)Y[(int64_t)min(c, nw - 1) * n + jc] : 0.f;                  \
+  } while (0)
+  FK_FETCH1N(beg + tid);
+  for (int64_t base = beg; base < end; base += BT) {
+    const int64_t j = base + tid;
+    const double x1 = nx1, x2 = nx2;
+    float w[WV];
+#pragma unroll
+    for (int c = 0; c < WV; ++c) w[c] = ny[c];
+    FK_FETCH1N(base + BT + tid);
+    bool ok = false;
+    uint2 U = make_uint2(0u, 0u);
+    if (j < end) {
+      ok = to_fixed(x1, scale, nf_fix, &U.x, flags);
+      ok = to_fixed(x2, scale, nf_fix, &U.y, flags) && ok;
+    }
+    const int key = ok ? window_bin(U.x, fb, wbias, (int)(nf_fix >> fb), tshift) : 0;
+    const uint32_t rank = rank_scan(sm, nbx, ok, key);
+    if (ok) {
+      const uint32_t s = sm.lofs[key] + rank;
+      sm.sbin[s] = (uint16_t)key;
+      sm.scrd[s] = U;
+#pragma unroll
+      for (int c = 0; c < WV; ++c) {
+        float wc = c < nw ? w[c] : 0.f;
+        if (!(wc == wc) || isinf(wc)) {
+          atomicOr(&flags[kFlagNaN], 1);
+          wc = 0.f;
+        }
+        sm.swts[s * WV + c] = __float_as_uint(wc);
+      }
+    }
+    __syncthreads();
+    write_coords(sm, crd1);
+    write_weights_n(sm, wts1);
+    advance_cursors(sm, nbx);
+  }
+#undef FK_FETCH1N
+}
+
+// Pass 2 for narrow records.  The wave's 64 weight records are read as 64 WV
+// contiguous words (word lane + 64 u of the wave's block), and each word is staged
+// at the slot of its point, taken from the owning lane by a wave shuffle.
+template <int WV>
+__global__ __launch_bounds__(BT) void k_s2n_scatter2(const uint2* __restrict__ crd1,
+                                                     const uint32_t* __restrict__ wts1,
+                                                     const uint64_t* __restrict__ start1,
+                                                     const uint32_t* __restrict__ off2,
+                                                     const uint64_t* __restrict__ start, int slices, int fb,
+                                                     uint32_t wbias, int nf, int tshift, int nbx,
+                                                     uint2* __restrict__ crd, uint32_t* __restrict__ wts) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  StageN<WV>& sm = *reinterpret_cast<StageN<WV>*>(smem_raw);
+  const int tid = threadIdx.x;
+  const int bx = blockIdx.x / slices, sl = blockIdx.x - bx * slices;
+  for (int b = tid; b < nbx; b += BT) {
+    sm.cur[b] = start[(int64_t)bx * nbx + b] + off2[(int64_t)blockIdx.x * nbx + b];
+    sm.hist[b] = 0;
+  }
+  __syncthreads();
+  const uint64_t p0 = start1[bx], len = start1[bx + 1] - p0;
+  const uint64_t q0 = p0 + len * sl / slices, q1 = p0 + len * (sl + 1) / slices;
+  if (q0 >= q1) return;
+  const int lane = tid & 63;
+  const uint64_t wb = (uint64_t)(tid & ~63);
+  uint2 nU;
+  uint32_t nv[WV];
+#define FK_FETCH2N(bb)                                                                      \
+  do {                                                                                      \
+    nU = crd1[min((uint64_t)(bb) + tid, q1 - 1)];                                           \
+    _Pragma("unroll") for (int u = 0; u < WV; ++u) {                                        \
+      const uint32_t m = (uint32_t)lane + 64u * u;                                          \
+      nv[u] = wts1[min((uint64_t)(bb) + wb + m / WV, q1 - 1) * WV + m % WV];               \
+    }                                                                                       \
+  } while (0)
+  FK_FETCH2N(q0);
+  for (uint64_t base = q0; base < q1; base += BT) {
+    const uint64_t p = base + tid;
+    const bool ok = p < q1;
+    const uint2 U = nU;
+    uint32_t v[WV];
+#pragma unroll
+    for (int u = 0; u < WV; ++u) v[u] = nv[u];
+    FK_FETCH2N(base + BT);
+    const int key = ok ? window_bin(U.y, fb, wbias, nf, tshift) : 0;
+    const uint32_t rank = rank_scan(sm, nbx, ok, key);
+    const uint32_t s = ok ? sm.lofs[key] + rank : 0xffffffffu;
+    if (ok) {
+      sm.sbin[s] = (uint16_t)key;
+      sm.scrd[s] = U;
+    }
+#pragma unroll
+    for (int u = 0; u < WV; ++u) {
+      const uint32_t m = (uint32_t)lane + 64u * u;
+      const uint32_t su = __shfl(s, (int)(m / WV), 64);
+      if (su != 0xffffffffu) sm.swts[su * WV + m % WV] = v[u];
+    }
+    __syncthreads();
+    write_coords(sm, crd);
+    write_weights_n(sm, wts);
+    advance_cursors(sm, nbx);
+  }
+#undef FK_FETCH2N
+}
+
 // Offsets of pass 1: off[k][b] = number of points of bucket b in workgroups < k,
 // and start1[b] (start1[nk] = number of valid points).  One workgroup of 1024
 // threads: thread (grp, b) sums a range of workgroups, the group sums are
@@ -374,11 +553,52 @@ Sort2Geom sort2_geom(int64_t n, int nbx) {
   return g;
 }
 
+// Counts (shared with the wide records), scans, and the narrow-record scatters.
+template <int WV>
+fk_status sort2_narrow(hipStream_t st, const void* X, fk_dtype dt, int64_t n, int64_t xstride, const void* Y, int nw,
+                       uint32_t nf_fix, int fb, uint32_t wbias, double scale, int tshift, int nbx,
+                       const Sort2Geom& g, const Sort2Bufs& b, uint32_t* crd, uint32_t* wts, uint64_t* start,
+                       int* flags) {
+  const size_t lds = sizeof(StageN<WV>);
+  const int nf = (int)(nf_fix >> fb);
+  if (dt == FK_F64) {
+    const double* Xd = static_cast<const double*>(X);
+    hipLaunchKernelGGL(k_s2_count1<double>, dim3(g.nblk1), dim3(BT), 0, st, Xd, n, xstride, scale, nf_fix, fb,
+                       wbias, tshift, nbx, g.chunk1, b.cnt1, flags);
+    hipLaunchKernelGGL(k_s2_scan1, dim3(1), dim3(1024), 0, st, b.cnt1, nbx, g.nblk1, b.off1, b.start1);
+    hipLaunchKernelGGL((k_s2n_scatter1<double, WV>), dim3(g.nblk1), dim3(BT), lds, st, Xd, n, xstride,
+                       static_cast<const double*>(Y), nw, scale, nf_fix, fb, wbias, tshift, nbx, g.chunk1, b.off1,
+                       b.start1, reinterpret_cast<uint2*>(b.crd1), b.wts1, flags);
+  } else {
+    const float* Xf = static_cast<const float*>(X);
+    hipLaunchKernelGGL(k_s2_count1<float>, dim3(g.nblk1), dim3(BT), 0, st, Xf, n, xstride, scale, nf_fix, fb,
+                       wbias, tshift, nbx, g.chunk1, b.cnt1, flags);
+    hipLaunchKernelGGL(k_s2_scan1, dim3(1), dim3(1024), 0, st, b.cnt1, nbx, g.nblk1, b.off1, b.start1);
+    hipLaunchKernelGGL((k_s2n_scatter1<float, WV>), dim3(g.nblk1), dim3(BT), lds, st, Xf, n, xstride,
+                       static_cast<const float*>(Y), nw, scale, nf_fix, fb, wbias, tshift, nbx, g.chunk1, b.off1,
+                       b.start1, reinterpret_cast<uint2*>(b.crd1), b.wts1, flags);
+  }
+  hipLaunchKernelGGL(k_s2_count2, dim3(nbx * g.slices), dim3(BT), 0, st, reinterpret_cast<const uint2*>(b.crd1),
+                     b.start1, g.slices, fb, wbias, nf, tshift, nbx, b.cnt2);
+  hipLaunchKernelGGL(k_s2_scan2, dim3(nbx), dim3(KMAX), 0, st, b.cnt2, b.start1, g.slices, nbx, b.off2, start);
+  hipLaunchKernelGGL(k_s2n_scatter2<WV>, dim3(nbx * g.slices), dim3(BT), lds, st,
+                     reinterpret_cast<const uint2*>(b.crd1), b.wts1, b.start1, b.off2, start, g.slices, fb, wbias,
+                     nf, tshift, nbx, reinterpret_cast<uint2*>(crd), wts);
+  return hipGetLastError() == hipSuccess ? FK_OK : FK_EHIP;
+}
+
 }  // namespace
 
 bool sort2_ok(int nbx) { return nbx >= 1 && nbx <= KMAX; }
 
-void sort2_carve(Carve& cv, int64_t n, int nbx, Sort2Bufs* b) {
+int sort2_words(int nw) {
+  if (nw >= 8) return 16;
+  int wv = 1;
+  while (wv < nw) wv <<= 1;
+  return wv;
+}
+
+void sort2_carve(Carve& cv, int64_t n, int nbx, int wv, Sort2Bufs* b) {
   Sort2Geom g = sort2_geom(n, nbx);
   b->cnt1 = cv.take<uint32_t>((size_t)g.nblk1 * nbx);
   b->off1 = cv.take<uint32_t>((size_t)g.nblk1 * nbx);
@@ -386,7 +606,7 @@ void sort2_carve(Carve& cv, int64_t n, int nbx, Sort2Bufs* b) {
   b->cnt2 = cv.take<uint32_t>((size_t)nbx * g.slices * nbx);
   b->off2 = cv.take<uint32_t>((size_t)nbx * g.slices * nbx);
   b->crd1 = cv.take<uint32_t>((size_t)n * 2);
-  b->wts1 = cv.take<uint32_t>((size_t)n * 16);
+  b->wts1 = cv.take<uint32_t>((size_t)n * wv);
 }
 
 fk_status sort2(hipStream_t st, const void* X, fk_dtype dt, int64_t n, int64_t xstride, const void* Y, int nw,
@@ -397,6 +617,19 @@ fk_status sort2(hipStream_t st, const void* X, fk_dtype dt, int64_t n, int64_t x
   const uint32_t nf_fix = (uint32_t)nf << fb;
   const uint32_t one = 1u << fb;
   const uint32_t wbias = (one - 1u) + 8u * one - ((uint32_t)W << (fb - 1));
+  const int wv = sort2_words(nw);
+  if (wv < 16) {
+    switch (wv) {
+      case 1: return sort2_narrow<1>(st, X, dt, n, xstride, Y, nw, nf_fix, fb, wbias, scale, tshift, nbx, g, b, crd,
+                                     wts, start, flags);
+      case 2: return sort2_narrow<2>(st, X, dt, n, xstride, Y, nw, nf_fix, fb, wbias, scale, tshift, nbx, g, b, crd,
+                                     wts, start, flags);
+      case 4: return sort2_narrow<4>(st, X, dt, n, xstride, Y, nw, nf_fix, fb, wbias, scale, tshift, nbx, g, b, crd,
+                                     wts, start, flags);
+      default: return sort2_narrow<8>(st, X, dt, n, xstride, Y, nw, nf_fix, fb, wbias, scale, tshift, nbx, g, b, crd,
+                                      wts, start, flags);
+    }
+  }
   const size_t lds = sizeof(Stage);
   if (dt == FK_F64) {
     const double* Xd = static_cast<const double*>(X);
