@@ -341,21 +341,63 @@ __global__ __launch_bounds__(BT) void k_s2_scatter2(const uint2* __restrict__ cr
 
 // ---------------------------------------------------------------- narrow records
 // The same two passes for 0..7 weight channels (the outer-product spread): records of
-// WV = 1, 2, 4 or 8 weight words per point (zero padded), staged word by word.
+// WV = 1, 2, 4 or 8 weight words per point (zero padded), staged word by word.  A
+// record is small, so each thread takes NPT points per batch (BT NPT points between
+// barriers, longer runs per bucket).
+template <int WV>
+constexpr int narrow_ppt() { return WV <= 2 ? 4 : (WV == 4 ? 2 : 1); }
+
 template <int WV>
 struct StageN {
+  static constexpr int NPT = narrow_ppt<WV>();
   unsigned long long cur[KMAX];
   uint32_t hist[KMAX];
   uint32_t lofs[KMAX];
   uint32_t total;
-  uint16_t sbin[BT];
-  uint2 scrd[BT];
-  uint32_t swts[BT * WV];
+  uint16_t sbin[BT * NPT];
+  uint2 scrd[BT * NPT];
+  uint32_t swts[BT * NPT * WV];
 };
 
+// Exclusive prefix sums of the batch's bucket counts (after the rank atomics).
+template <class St>
+__device__ __forceinline__ void scan_counts(St& sm, int nk) {
+  const int tid = threadIdx.x;
+  __syncthreads();
+  if (tid < 64) {
+    const int per = (nk + 63) / 64;
+    uint32_t s = 0;
+    for (int i = 0; i < per; ++i) {
+      const int b = tid * per + i;
+      if (b < nk) s += sm.hist[b];
+    }
+    uint32_t x = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (tid >= o) x += y;
+    }
+    uint32_t run = x - s;
+    for (int i = 0; i < per; ++i) {
+      const int b = tid * per + i;
+      if (b < nk) {
+        sm.lofs[b] = run;
+        run += sm.hist[b];
+      }
+    }
+    if (tid == 63) sm.total = x;
+  }
+  __syncthreads();
+}
+
 template <int WV>
-__device__ __forceinline__ void write_weights_n(StageN<WV>& sm, uint32_t* __restrict__ wts_out) {
+__device__ __forceinline__ void write_batch_n(StageN<WV>& sm, uint2* __restrict__ crd_out,
+                                              uint32_t* __restrict__ wts_out) {
   const uint32_t total = sm.total;
+  for (uint32_t q = threadIdx.x; q < total; q += BT) {
+    const int b = sm.sbin[q];
+    crd_out[sm.cur[b] + (q - sm.lofs[b])] = sm.scrd[q];
+  }
   for (uint32_t q = threadIdx.x; q < total * WV; q += BT) {
     const uint32_t s = q / WV;
     const int b = sm.sbin[s];
@@ -371,6 +413,7 @@ __global__ __launch_bounds__(BT) void k_s2n_scatter1(const TX* __restrict__ X, i
                                                      const uint64_t* __restrict__ start1,
                                                      uint2* __restrict__ crd1, uint32_t* __restrict__ wts1,
                                                      int* flags) {
+  constexpr int NPT = narrow_ppt<WV>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   StageN<WV>& sm = *reinterpret_cast<StageN<WV>*>(smem_raw);
   const int tid = threadIdx.x;
@@ -382,40 +425,56 @@ __global__ __launch_bounds__(BT) void k_s2n_scatter1(const TX* __restrict__ X, i
   const int64_t beg = (int64_t)blockIdx.x * chunk;
   const int64_t end = min(n, beg + chunk);
   if (beg >= end) return;
-  // next batch in flight (index clamped to the chunk; no target row is read when nw = 0)
-  double nx1, nx2;
-  float ny[WV];
-#define FK_FETCH1N(jj)                                                                     \
-  do {                                                                                     \
-    const int64_t jc = min((int64_t)(jj), end - 1);                                        \
-    nx1 = (double)X[jc];                                                                   \
-    nx2 = (double)X[xstride + jc];                                                         \
+  const int nf = (int)(nf_fix >> fb);
+  // next batch in flight: point base + u BT + tid of slot u (index clamped to the
+  // chunk; no target row is read when nw = 0)
+  double nx1[NPT], nx2[NPT];
+  float ny[NPT][WV];
+#define FK_FETCH1N(bb)                                                                     \
+  _Pragma("unroll") for (int u = 0; u < NPT; ++u) {                                        \
+    const int64_t jc = min((int64_t)(bb) + u * BT + tid, end - 1);                         \
+    nx1[u] = (double)X[jc];                                                                \
+    nx2[u] = (double)X[xstride + jc];                                                      \
     _Pragma("unroll") for (int c = 0; c < WV; ++c)                                         \
-      ny[c] = nw > 0 ? (float)Y[(int64_t)min(c, nw - 1) * n + jc] : 0.f;                  \
-  } while (0)
-  FK_FETCH1N(beg + tid);
-  for (int64_t base = beg; base < end; base += BT) {
-    const int64_t j = base + tid;
-    const double x1 = nx1, x2 = nx2;
-    float w[WV];
+      ny[u][c] = nw > 0 ? (float)Y[(int64_t)min(c, nw - 1) * n + jc] : 0.f;               \
+  }
+  FK_FETCH1N(beg);
+  for (int64_t base = beg; base < end; base += (int64_t)BT * NPT) {
+    double x1[NPT], x2[NPT];
+    float w[NPT][WV];
 #pragma unroll
-    for (int c = 0; c < WV; ++c) w[c] = ny[c];
-    FK_FETCH1N(base + BT + tid);
-    bool ok = false;
-    uint2 U = make_uint2(0u, 0u);
-    if (j < end) {
-      ok = to_fixed(x1, scale, nf_fix, &U.x, flags);
-      ok = to_fixed(x2, scale, nf_fix, &U.y, flags) && ok;
+    for (int u = 0; u < NPT; ++u) {
+      x1[u] = nx1[u];
+      x2[u] = nx2[u];
+#pragma unroll
+      for (int c = 0; c < WV; ++c) w[u][c] = ny[u][c];
     }
-    const int key = ok ? window_bin(U.x, fb, wbias, (int)(nf_fix >> fb), tshift) : 0;
-    const uint32_t rank = rank_scan(sm, nbx, ok, key);
-    if (ok) {
-      const uint32_t s = sm.lofs[key] + rank;
-      sm.sbin[s] = (uint16_t)key;
-      sm.scrd[s] = U;
+    FK_FETCH1N(base + (int64_t)BT * NPT);
+    bool ok[NPT];
+    uint2 U[NPT];
+    int key[NPT];
+    uint32_t rank[NPT];
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+      ok[u] = false;
+      U[u] = make_uint2(0u, 0u);
+      if (base + u * BT + tid < end) {
+        ok[u] = to_fixed(x1[u], scale, nf_fix, &U[u].x, flags);
+        ok[u] = to_fixed(x2[u], scale, nf_fix, &U[u].y, flags) && ok[u];
+      }
+      key[u] = ok[u] ? window_bin(U[u].x, fb, wbias, nf, tshift) : 0;
+      rank[u] = ok[u] ? atomicAdd(&sm.hist[key[u]], 1u) : 0u;
+    }
+    scan_counts(sm, nbx);
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+      if (!ok[u]) continue;
+      const uint32_t s = sm.lofs[key[u]] + rank[u];
+      sm.sbin[s] = (uint16_t)key[u];
+      sm.scrd[s] = U[u];
 #pragma unroll
       for (int c = 0; c < WV; ++c) {
-        float wc = c < nw ? w[c] : 0.f;
+        float wc = c < nw ? w[u][c] : 0.f;
         if (!(wc == wc) || isinf(wc)) {
           atomicOr(&flags[kFlagNaN], 1);
           wc = 0.f;
@@ -424,16 +483,16 @@ __global__ __launch_bounds__(BT) void k_s2n_scatter1(const TX* __restrict__ X, i
       }
     }
     __syncthreads();
-    write_coords(sm, crd1);
-    write_weights_n(sm, wts1);
+    write_batch_n(sm, crd1, wts1);
     advance_cursors(sm, nbx);
   }
 #undef FK_FETCH1N
 }
 
-// Pass 2 for narrow records.  The wave's 64 weight records are read as 64 WV
-// contiguous words (word lane + 64 u of the wave's block), and each word is staged
-// at the slot of its point, taken from the owning lane by a wave shuffle.
+// Pass 2 for narrow records.  Slot u of the batch holds points base + u BT + tid; the
+// wave's 64 weight records of a slot are read as 64 WV contiguous words (word
+// lane + 64 v of the wave's block), and each word is staged at the slot of its
+// point, taken from the owning lane by a wave shuffle.
 template <int WV>
 __global__ __launch_bounds__(BT) void k_s2n_scatter2(const uint2* __restrict__ crd1,
                                                      const uint32_t* __restrict__ wts1,
@@ -442,6 +501,7 @@ __global__ __launch_bounds__(BT) void k_s2n_scatter2(const uint2* __restrict__ c
                                                      const uint64_t* __restrict__ start, int slices, int fb,
                                                      uint32_t wbias, int nf, int tshift, int nbx,
                                                      uint2* __restrict__ crd, uint32_t* __restrict__ wts) {
+  constexpr int NPT = narrow_ppt<WV>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   StageN<WV>& sm = *reinterpret_cast<StageN<WV>*>(smem_raw);
   const int tid = threadIdx.x;
@@ -456,41 +516,54 @@ __global__ __launch_bounds__(BT) void k_s2n_scatter2(const uint2* __restrict__ c
   if (q0 >= q1) return;
   const int lane = tid & 63;
   const uint64_t wb = (uint64_t)(tid & ~63);
-  uint2 nU;
-  uint32_t nv[WV];
+  uint2 nU[NPT];
+  uint32_t nv[NPT][WV];
 #define FK_FETCH2N(bb)                                                                      \
-  do {                                                                                      \
-    nU = crd1[min((uint64_t)(bb) + tid, q1 - 1)];                                           \
-    _Pragma("unroll") for (int u = 0; u < WV; ++u) {                                        \
-      const uint32_t m = (uint32_t)lane + 64u * u;                                          \
-      nv[u] = wts1[min((uint64_t)(bb) + wb + m / WV, q1 - 1) * WV + m % WV];               \
+  _Pragma("unroll") for (int u = 0; u < NPT; ++u) {                                         \
+    const uint64_t g0 = (uint64_t)(bb) + (uint64_t)u * BT;                                  \
+    nU[u] = crd1[min(g0 + tid, q1 - 1)];                                                    \
+    _Pragma("unroll") for (int v = 0; v < WV; ++v) {                                        \
+      const uint32_t m = (uint32_t)lane + 64u * v;                                          \
+      nv[u][v] = wts1[min(g0 + wb + m / WV, q1 - 1) * WV + m % WV];                        \
     }                                                                                       \
-  } while (0)
+  }
   FK_FETCH2N(q0);
-  for (uint64_t base = q0; base < q1; base += BT) {
-    const uint64_t p = base + tid;
-    const bool ok = p < q1;
-    const uint2 U = nU;
-    uint32_t v[WV];
+  for (uint64_t base = q0; base < q1; base += (uint64_t)BT * NPT) {
+    uint2 U[NPT];
+    uint32_t v[NPT][WV];
 #pragma unroll
-    for (int u = 0; u < WV; ++u) v[u] = nv[u];
-    FK_FETCH2N(base + BT);
-    const int key = ok ? window_bin(U.y, fb, wbias, nf, tshift) : 0;
-    const uint32_t rank = rank_scan(sm, nbx, ok, key);
-    const uint32_t s = ok ? sm.lofs[key] + rank : 0xffffffffu;
-    if (ok) {
-      sm.sbin[s] = (uint16_t)key;
-      sm.scrd[s] = U;
+    for (int u = 0; u < NPT; ++u) {
+      U[u] = nU[u];
+#pragma unroll
+      for (int c = 0; c < WV; ++c) v[u][c] = nv[u][c];
     }
+    FK_FETCH2N(base + (uint64_t)BT * NPT);
+    bool ok[NPT];
+    int key[NPT];
+    uint32_t rank[NPT];
 #pragma unroll
-    for (int u = 0; u < WV; ++u) {
-      const uint32_t m = (uint32_t)lane + 64u * u;
-      const uint32_t su = __shfl(s, (int)(m / WV), 64);
-      if (su != 0xffffffffu) sm.swts[su * WV + m % WV] = v[u];
+    for (int u = 0; u < NPT; ++u) {
+      ok[u] = base + (uint64_t)u * BT + tid < q1;
+      key[u] = ok[u] ? window_bin(U[u].y, fb, wbias, nf, tshift) : 0;
+      rank[u] = ok[u] ? atomicAdd(&sm.hist[key[u]], 1u) : 0u;
+    }
+    scan_counts(sm, nbx);
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+      const uint32_t s = ok[u] ? sm.lofs[key[u]] + rank[u] : 0xffffffffu;
+      if (ok[u]) {
+        sm.sbin[s] = (uint16_t)key[u];
+        sm.scrd[s] = U[u];
+      }
+#pragma unroll
+      for (int c = 0; c < WV; ++c) {
+        const uint32_t m = (uint32_t)lane + 64u * c;
+        const uint32_t su = __shfl(s, (int)(m / WV), 64);
+        if (su != 0xffffffffu) sm.swts[su * WV + m % WV] = v[u][c];
+      }
     }
     __syncthreads();
-    write_coords(sm, crd);
-    write_weights_n(sm, wts);
+    write_batch_n(sm, crd, wts);
     advance_cursors(sm, nbx);
   }
 #undef FK_FETCH2N

@@ -6,18 +6,20 @@
 // Four points at a time, the subgrid of channel c takes
 //   D_c[x][y] += sum_k (W_c[k] psi1_k[x]) psi2_k[y],
 // one v_mfma_f32_16x16x4f32 on a 16 x 16 subgrid: A[x][k] = W_c[k] psi1_k[x] and
-// B[k][y] = psi2_k[y].  Lane l = j + 16 k supplies A[j][k] and B[k][j], so it
-// evaluates psi1 and psi2 of point k at subgrid offset j; element v of its result is
-// D[4 k + v][j].  Per point that is CH / 4 MFMAs (CH = WV + 1 channels), against
+// B[k][y] = psi2_k[y].  Lane l = j + 16 k supplies A[j][k] and B[k][j], the kernel
+// values of point k at subgrid offset j; element v of its result is D[4 k + v][j].  Per point that is CH / 4 MFMAs (CH = WV + 1 channels), against
 // ceil(S^2 / 16) / 4 for the channel-row form of spread_mfma.hip, which pays off
 // only with many channels.
 //
 // * Bins are OMB x OMB cells (OMB = 8), sorted beforehand (sort2.hip, records of WV
 //   weight words); a point belongs to the bin holding the first cell of its window,
 //   so all windows of a bin lie in its S x S subgrid, S = OMB + w - 1 <= 16.
-// * A workgroup of OWAVE waves takes a slice of one bin, each wave its chunks of 4
-//   points in turn, with the coordinates and weights of the next OPD chunks in flight.
-// * FP32 accumulators go into the workgroup's FP64 LDS subgrid every OFLUSH chunks
+// * A workgroup of OWAVE waves takes a slice of one bin, each wave its batches of 64
+//   points in turn.  Per batch, one lane per point writes the point's w kernel values
+//   per axis (at their subgrid offsets, zeros elsewhere) and its weights into an LDS
+//   table row; then 16 chunks of 4 points read their operands from the table.  The
+//   next batch's coordinates and weights are loaded meanwhile.
+// * FP32 accumulators go into the workgroup's FP64 LDS subgrid every OFLUSH batches
 //   (1024 points per wave) and at the end; the subgrid is added into the FP64 fine
 //   grid with global FP64 atomics.
 #include "fk_internal.h"
@@ -32,8 +34,7 @@ typedef float floatx4_o __attribute__((ext_vector_type(4)));
 
 constexpr int OMB = 8;       // bin width in cells
 constexpr int OWAVE = 4;     // waves per workgroup
-constexpr int OFLUSH = 256;  // chunks of 4 points per wave between FP32 -> FP64 flushes
-constexpr int OPD = 4;       // chunks in flight per wave
+constexpr int OFLUSH = 16;   // batches of 64 points per wave between FP32 -> FP64 flushes
 
 // Exponential of semicircle psi(s) = exp(beta (sqrt(1 - (2s/w)^2) - 1)) with beta
 // pre-multiplied by log2(e) (exponent in [-beta log2 e, 0]).
@@ -81,6 +82,9 @@ __device__ __forceinline__ WBlk<WV> load_w(const uint32_t* __restrict__ p) {
   return r;
 }
 
+template <int WV>
+constexpr int op_row() { return (32 + WV + 3) & ~3; }   // table row: psi1[16], psi2[16], weights
+
 template <int W, int WV>
 __global__ __launch_bounds__(64 * OWAVE) void k_spread_op(const uint2* __restrict__ crd,
                                                           const uint32_t* __restrict__ wts, int C,
@@ -89,8 +93,10 @@ __global__ __launch_bounds__(64 * OWAVE) void k_spread_op(const uint2* __restric
                                                           double* __restrict__ grid) {
   constexpr int S = OMB + W - 1;
   constexpr int CH = WV + 1;
+  constexpr int PR = op_row<WV>();
   static_assert(S <= 16, "the subgrid must fit one 16 x 16 MFMA tile");
-  __shared__ double sub[CH * 256];   // sub[c][x][y], 16 x 16 per channel
+  __shared__ double sub[CH * 256];                      // sub[c][x][y], 16 x 16 per channel
+  __shared__ __align__(16) float tabs[OWAVE * 64 * PR];  // per wave: 64 rows
   const int b = blockIdx.x / slices;
   const int sl = blockIdx.x - b * slices;
   const uint64_t p0 = start[b], len = start[b + 1] - p0;
@@ -107,18 +113,15 @@ __global__ __launch_bounds__(64 * OWAVE) void k_spread_op(const uint2* __restric
   const float two_over_w = 2.0f / (float)W;
   const float bl2 = beta * 1.44269504088896340736f;
   const uint32_t npts = (uint32_t)(q1 - q0);   // a slice holds < 2^31 points
-  const uint32_t nchunk = (npts + 3) / 4;
+  const uint32_t nbatch = (npts + 63) / 64;
   const uint2* __restrict__ cs = crd + q0;
   const uint32_t* __restrict__ ws = wts + q0 * WV;
-  // unconditional loads, index clamped to the slice
-  uint2 Uq[OPD];
-  WBlk<WV> Wq[OPD];
-#pragma unroll
-  for (int d = 0; d < OPD; ++d) {
-    const uint32_t p = min((wv + d * OWAVE) * 4u + k, npts - 1);
-    Uq[d] = cs[p];
-    Wq[d] = load_w<WV>(ws + (size_t)p * WV);
-  }
+  float* tab = tabs + wv * 64 * PR;
+  float* row = tab + lane * PR;
+  // phase-1 inputs of the wave's next batch in flight (one point per lane; index
+  // clamped to the slice)
+  uint2 Un = cs[min(wv * 64u + lane, npts - 1)];
+  WBlk<WV> Wn = load_w<WV>(ws + (size_t)min(wv * 64u + lane, npts - 1) * WV);
   floatx4_o acc[CH];
 #pragma unroll
   for (int c = 0; c < CH; ++c) acc[c] = floatx4_o{0.f, 0.f, 0.f, 0.f};
@@ -136,37 +139,57 @@ __global__ __launch_bounds__(64 * OWAVE) void k_spread_op(const uint2* __restric
   };
 
   int since = 0;
-  for (uint32_t g = wv; g < nchunk; g += OWAVE * OPD) {
-#pragma unroll
-    for (int d = 0; d < OPD; ++d) {
-      const uint32_t ch = g + d * OWAVE;   // this wave's chunk
-      const uint2 U = Uq[d];
-      const WBlk<WV> Wk = Wq[d];
-      {
-        const uint32_t p = min((ch + OWAVE * OPD) * 4u + k, npts - 1);
-        Uq[d] = cs[p];
-        Wq[d] = load_w<WV>(ws + (size_t)p * WV);
-      }
-      const bool valid = ch * 4u + k < npts;
+  for (uint32_t bb = wv; bb < nbatch; bb += OWAVE) {
+    // Phase 1, one lane per point: its window starts, the w kernel values per axis at
+    // their subgrid offsets (zeros elsewhere) and its weights, in its table row.
+    const uint2 U = Un;
+    const WBlk<WV> Wk = Wn;
+    {
+      const uint32_t p = min((bb + OWAVE) * 64u + lane, npts - 1);
+      Un = cs[p];
+      Wn = load_w<WV>(ws + (size_t)p * WV);
+    }
+    {
+      const bool valid = bb * 64u + lane < npts;
       int i1, i2;
       float s1, s2;
       window(U.x, fb, W, &i1, &s1);
       window(U.y, fb, W, &i2, &s2);
-      // offset of subgrid cell j inside the point's window (the sort keeps the
-      // window start within the bin's first OMB cells)
-      const int d1 = j - ((i1 - o1) & (nf - 1));
-      const int d2 = j - ((i2 - o2) & (nf - 1));
-      const float e1 = psi_es(s1 + (float)d1, bl2, two_over_w);
-      const float e2 = psi_es(s2 + (float)d2, bl2, two_over_w);
-      const float a = (valid && d1 >= 0 && d1 < W) ? e1 : 0.f;
-      const float bv = (valid && d2 >= 0 && d2 < W) ? e2 : 0.f;
+      float4* r4 = reinterpret_cast<float4*>(row);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) r4[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      // the sort keeps the window start within the bin's first OMB cells, so
+      // rel + W - 1 <= S - 1 <= 15; the test keeps the row in bounds regardless
+      const int rel1 = (i1 - o1) & (nf - 1), rel2 = (i2 - o2) & (nf - 1);
+      if (valid && rel1 < OMB && rel2 < OMB) {
+#pragma unroll
+        for (int r = 0; r < W; ++r) {
+          row[rel1 + r] = psi_es(s1 + (float)r, bl2, two_over_w);
+          row[16 + rel2 + r] = psi_es(s2 + (float)r, bl2, two_over_w);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < WV; ++c) row[32 + c] = Wk.v[c];
+    }
+    // the rows written by other lanes of this wave are read below
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // Phase 2: 16 chunks of 4 points on the matrix cores.
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const float* rk = tab + (4 * q + k) * PR;
+      const float a = rk[j];
+      const float bv = rk[16 + j];
       acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc[0], 0, 0, 0);
 #pragma unroll
       for (int c = 1; c < CH; ++c)
-        acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a * Wk.v[c - 1], bv, acc[c], 0, 0, 0);
+        acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a * rk[32 + c - 1], bv, acc[c], 0, 0, 0);
     }
-    since += OPD;
-    if (since >= OFLUSH) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (++since == OFLUSH) {
       flush();
       since = 0;
     }
