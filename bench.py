@@ -58,7 +58,10 @@ def _traffic(kernel: str, n: int):
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", f"{kernel}_hbm_traffic.md")
-    src = os.path.join(ROOT, "paper_2509_02649_amd", "csrc", "spread_mfma.hip")
+    unit = {"k_spread_mfma": "spread_mfma.hip", "k_spread_op": "spread_op.hip"}.get(kernel)
+    if unit is None:
+        return None
+    src = os.path.join(ROOT, "paper_2509_02649_amd", "csrc", unit)
     if not os.path.exists(path) or not os.path.exists(src):
         return None
     text = open(path).read()
@@ -159,8 +162,8 @@ def main():
         work = n * 2.0 * w * w * (ntgt + 1)
         achieved = work / (spread_ms * 1e-3) / 1e12
     else:
-        # dominant kernel: the FP64-LDS spread; algorithmic bytes = inputs read once
-        kernel, bound, unit, peak = "k_spread_2d_binned", "hbm", "GB/s", HBM_PEAK_GBS
+        # dominant kernel: the outer-product MFMA spread; algorithmic bytes = inputs read once
+        kernel, bound, unit, peak = "k_spread_op", "hbm", "GB/s", HBM_PEAK_GBS
         achieved = n * bytes_per_point / (spread_ms * 1e-3) / 1e9
     out = {
         "metric": "Gram+RHS points/s and fit time at 1e-6 Gram err; grad-path vs plain fit ratio",
