@@ -97,12 +97,13 @@ fk_status backward_impl(fk_ctx* ctx, const SolveLayout& s, int d, const double* 
                         double* grad_p, double* grad_theta);
 fk_status reset_flags(fk_ctx* ctx);
 
-// MFMA spread for 8..16 weight channels over MB x MB-cell bins (spread_mfma.hip).
+// MFMA spread for 8..16 weight channels over MB x MB-cell bins (spread_mfma.hip):
+// sorted coordinates, per point its position in the row-grouped weight blocks wrow.
 int spread_mfma_bin(int nf, int64_t n);
 bool spread_mfma_ok(int nw, int W);
-fk_status launch_spread_mfma(hipStream_t st, int W, int MB, const uint32_t* crd, const uint32_t* wts, int nw,
-                             const uint64_t* start, int nbx, int nb, int nf, int fb, double beta, int64_t n,
-                             double* grid);
+fk_status launch_spread_mfma(hipStream_t st, int W, int MB, const uint32_t* crd, const uint32_t* pos,
+                             const uint32_t* wrow, int nw, const uint64_t* start, int nbx, int nb, int nf, int fb,
+                             double beta, int64_t n, double* grid);
 
 // MFMA spread for 0..7 weight channels as per-channel outer products over 8 x 8-cell
 // bins (spread_op.hip).
@@ -115,7 +116,9 @@ fk_status launch_spread_op(hipStream_t st, int W, const uint32_t* crd, const uin
 // Two-pass bin sort for the MFMA spreads (sort2.hip): scratch buffers carved from
 // the caller's workspace, and the sort itself (bin starts in start[0..nbx^2]).
 // Records: coordinates (2 words) and sort2_words(nw) weight words per point
-// (16 for 8..16 channels, else the next power of two >= nw, at least 1).
+// (16 for 8..16 channels, else the next power of two >= nw, at least 1).  With 16
+// words the second pass writes, instead of the weights, each point's position in
+// the row-grouped records of the first pass (b.wts1), one word per point.
 struct Sort2Bufs {
   uint32_t* cnt1 = nullptr;
   uint32_t* off1 = nullptr;

@@ -550,7 +550,7 @@ size_t type1_workspace(int d, int64_t n, int nw, int K, double eps) {
     if (kind != Spread2::kAtomic) {
       const int wv = sort2_words(nw);
       cv.take<uint32_t>((size_t)n * 2);
-      cv.take<uint32_t>((size_t)n * wv);
+      cv.take<uint32_t>((size_t)n * (kind == Spread2::kRows ? 1 : wv));
       Sort2Bufs sb;
       sort2_carve(cv, n, g.nbx, wv, &sb);
     } else {
@@ -648,7 +648,9 @@ fk_status type1(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int64
   uint32_t* totals = cv.take<uint32_t>((size_t)g.nb);
   uint64_t* start = cv.take<uint64_t>((size_t)g.nb + 1);
   uint32_t* rec = cv.take<uint32_t>((size_t)n * (split ? 2 : 2 + nw));
-  uint32_t* wts = split ? cv.take<uint32_t>((size_t)n * wv) : nullptr;
+  // second sorted array: weight words (outer-product spread) or, for the channel-row
+  // spread, each point's position in the row-grouped weight blocks sb.wts1
+  uint32_t* wts = split ? cv.take<uint32_t>((size_t)n * (kind == Spread2::kRows ? 1 : wv)) : nullptr;
   Sort2Bufs sb;
   if (split) sort2_carve(cv, n, g.nbx, wv, &sb);
   if (!cv.ok()) return FK_ENOMEM;
@@ -675,8 +677,8 @@ fk_status type1(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int64
   FK_HIP(hipEventRecord(ev[1], ctx->stream));
   int64_t per_bin = (n + g.nb - 1) / g.nb;
   if (kind == Spread2::kRows) {
-    fk_status s2 = launch_spread_mfma(ctx->stream, W, g.T, rec, wts, nw, start, g.nbx, g.nb, nf, fb, plan.beta, n,
-                                      grid);
+    fk_status s2 = launch_spread_mfma(ctx->stream, W, g.T, rec, wts, sb.wts1, nw, start, g.nbx, g.nb, nf, fb,
+                                      plan.beta, n, grid);
     if (s2 != FK_OK) return s2;
     if (info) info->bin = -g.T;   // negative: MFMA spread over T x T bins
   } else if (kind == Spread2::kOuter) {

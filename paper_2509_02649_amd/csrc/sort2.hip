@@ -1,20 +1,23 @@
-// Two-pass bin sort of the point stream for the MFMA spread (8..16 weight channels).
+// Two-pass bin sort of the point stream for the MFMA spreads.
 //
-// The matrix-core spread takes the points of one MB x MB-cell bin four at a time,
-// so the type-1 stage first orders the stream by bin: per point the fixed-point
-// grid coordinates [U1, U2] (8 B) and a 64-byte block of 16 FP32 weights (zero
-// padded).  A one-pass counting sort into the nbx^2 bins sends consecutive points
-// to unrelated addresses, and on HBM3E such scattered 8- and 64-byte writes run
-// far below the streaming rate.  Here the order is reached in two counting passes
-// over nbx buckets each (the bin row bx, then the bin column by inside a row).
-// A point's bin on an axis is set by the first cell of its kernel window, not by
-// the cell it lies in, so that a bin's windows cover MB + w - 1 cells per axis.
-// A workgroup ranks a batch of BT = 1024 points by bucket in LDS, stages the
-// batch in bucket order, and writes each bucket's part as one contiguous run
-// (about BT / nbx points), so both passes write in runs and read in streams.
+// The matrix-core spreads take the points of one bin four at a time, so the type-1
+// stage first orders the stream by bin.  A one-pass counting sort into the nbx^2
+// bins sends consecutive points to unrelated addresses, and on HBM3E such
+// scattered 8- and 64-byte writes run far below the streaming rate.  Here the order
+// is reached in two counting passes over nbx buckets each (the bin row bx, then the
+// bin column by inside a row).  A point's bin on an axis is set by the first cell of
+// its kernel window, not by the cell it lies in, so that a bin's windows cover
+// MB + w - 1 cells per axis.  A workgroup ranks a batch of points by bucket in LDS,
+// stages the batch in bucket order, and writes each bucket's part as one contiguous
+// run, so both passes write in runs and read in streams.
 //
+// 8..16 weight channels (records of 16 weight words, zero padded):
 //   pass 1: X, Y (structure of arrays)          -> crd1 / wts1, grouped by bx
-//   pass 2: one workgroup per (bx, slice) of it -> crd / wts, grouped by bin
+//   pass 2: one workgroup per (bx, slice) of it -> crd and, per point, its position
+//           in crd1 / wts1, grouped by bin; the 64-byte weight blocks are not moved
+//           again (the spread gathers them from wts1).
+// 0..7 weight channels (records of 1, 2, 4 or 8 weight words):
+//   pass 1 as above; pass 2 -> crd / wts, grouped by bin.
 //
 // The order of points inside a bin is not specified (LDS atomics rank them).
 #include "fk_internal.h"
@@ -95,33 +98,14 @@ __device__ __forceinline__ void advance_cursors(St& sm, int nk) {
 }
 
 // Rank the batch by bucket, stage it in bucket order and write the runs.
-// Every thread of the workgroup calls this once per batch.  Thread t brings point t
-// (key, U).  Its weights v0..v3 are the four 16-byte quarters of point t, or, with
-// kLaneQuarters, the quarter (lane % 4) of the wave's points 16 u + lane / 4 (u = 0..3):
-// loads in that order are contiguous across the wave, and the slots are exchanged
-// inside the wave before the weights are staged.
-template <bool kLaneQuarters>
+// Every thread of the workgroup calls this once per batch with point t (key, U) and
+// its weights v0..v3 (the four 16-byte quarters of its 64-byte block).
 __device__ __forceinline__ void stage_batch(Stage& sm, int nk, bool ok, int key, uint2 U, uint4 v0, uint4 v1,
                                             uint4 v2, uint4 v3, uint2* __restrict__ crd_out,
                                             uint4* __restrict__ wts_out) {
   const int tid = threadIdx.x;
   const uint32_t rank = rank_scan(sm, nk, ok, key);
-  if (kLaneQuarters) {
-    const uint32_t s = ok ? sm.lofs[key] + rank : 0xffffffffu;
-    if (ok) {
-      sm.sbin[s] = (uint16_t)key;
-      sm.scrd[s] = U;
-    }
-    const int lane = tid & 63;
-    const uint32_t s0 = __shfl(s, (lane >> 2), 64);
-    const uint32_t s1 = __shfl(s, 16 + (lane >> 2), 64);
-    const uint32_t s2 = __shfl(s, 32 + (lane >> 2), 64);
-    const uint32_t s3 = __shfl(s, 48 + (lane >> 2), 64);
-    if (s0 != 0xffffffffu) sm.swts[s0 * 4 + (lane & 3)] = v0;
-    if (s1 != 0xffffffffu) sm.swts[s1 * 4 + (lane & 3)] = v1;
-    if (s2 != 0xffffffffu) sm.swts[s2 * 4 + (lane & 3)] = v2;
-    if (s3 != 0xffffffffu) sm.swts[s3 * 4 + (lane & 3)] = v3;
-  } else if (ok) {
+  if (ok) {
     const uint32_t s = sm.lofs[key] + rank;
     sm.sbin[s] = (uint16_t)key;
     sm.scrd[s] = U;
@@ -234,7 +218,7 @@ __global__ __launch_bounds__(BT) void k_s2_scatter1(const TX* __restrict__ X, in
       wb[c] = __float_as_uint(wc);
     }
     const int key = ok ? window_bin(U.x, fb, wbias, (int)(nf_fix >> fb), tshift) : 0;
-    stage_batch<false>(sm, nbx, ok, key, U, make_uint4(wb[0], wb[1], wb[2], wb[3]), make_uint4(wb[4], wb[5], wb[6], wb[7]),
+    stage_batch(sm, nbx, ok, key, U, make_uint4(wb[0], wb[1], wb[2], wb[3]), make_uint4(wb[4], wb[5], wb[6], wb[7]),
                 make_uint4(wb[8], wb[9], wb[10], wb[11]), make_uint4(wb[12], wb[13], wb[14], wb[15]), crd1, wts1);
   }
 }
@@ -293,51 +277,6 @@ __global__ __launch_bounds__(KMAX) void k_s2_scan2(const uint32_t* __restrict__ 
   if (bx == nbx - 1 && by == 0) start[(int64_t)nbx * nbx] = start1[nbx];
 }
 
-// Pass 2 scatter: workgroup (bx, slice) moves its slice of row bx into bin order.
-__global__ __launch_bounds__(BT) void k_s2_scatter2(const uint2* __restrict__ crd1, const uint4* __restrict__ wts1,
-                                                    const uint64_t* __restrict__ start1,
-                                                    const uint32_t* __restrict__ off2,
-                                                    const uint64_t* __restrict__ start, int slices, int fb,
-                                                    uint32_t wbias, int nf, int tshift, int nbx,
-                                                    uint2* __restrict__ crd,
-                                                    uint4* __restrict__ wts) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  Stage& sm = *reinterpret_cast<Stage*>(smem_raw);
-  const int tid = threadIdx.x;
-  const int bx = blockIdx.x / slices, sl = blockIdx.x - bx * slices;
-  for (int b = tid; b < nbx; b += BT) {
-    sm.cur[b] = start[(int64_t)bx * nbx + b] + off2[(int64_t)blockIdx.x * nbx + b];
-    sm.hist[b] = 0;
-  }
-  __syncthreads();
-  const uint64_t p0 = start1[bx], len = start1[bx + 1] - p0;
-  const uint64_t q0 = p0 + len * sl / slices, q1 = p0 + len * (sl + 1) / slices;
-  if (q0 >= q1) return;
-  // The next batch is loaded (indices clamped to the slice) while this one is staged:
-  // the coordinates of point base + tid, and of the wave's 64 weight blocks the
-  // 16-byte words lane, lane + 64, ... (contiguous across the wave).
-  const int lane = tid & 63;
-  const uint64_t wq = (uint64_t)(tid & ~63) + (lane >> 2);
-  uint2 nU;
-  uint4 n0, n1, n2, n3;
-  auto fetch = [&](uint64_t b) {
-    nU = crd1[min(b + tid, q1 - 1)];
-    n0 = wts1[min(b + wq, q1 - 1) * 4 + (lane & 3)];
-    n1 = wts1[min(b + wq + 16, q1 - 1) * 4 + (lane & 3)];
-    n2 = wts1[min(b + wq + 32, q1 - 1) * 4 + (lane & 3)];
-    n3 = wts1[min(b + wq + 48, q1 - 1) * 4 + (lane & 3)];
-  };
-  fetch(q0);
-  for (uint64_t base = q0; base < q1; base += BT) {
-    const uint64_t p = base + tid;
-    const bool ok = p < q1;
-    const uint2 U = nU;
-    const uint4 v0 = n0, v1 = n1, v2 = n2, v3 = n3;
-    fetch(base + BT);
-    const int key = ok ? window_bin(U.y, fb, wbias, nf, tshift) : 0;
-    stage_batch<true>(sm, nbx, ok, key, U, v0, v1, v2, v3, crd, wts);
-  }
-}
 
 // ---------------------------------------------------------------- narrow records
 // The same two passes for 0..7 weight channels (the outer-product spread): records of
@@ -492,8 +431,10 @@ __global__ __launch_bounds__(BT) void k_s2n_scatter1(const TX* __restrict__ X, i
 // Pass 2 for narrow records.  Slot u of the batch holds points base + u BT + tid; the
 // wave's 64 weight records of a slot are read as 64 WV contiguous words (word
 // lane + 64 v of the wave's block), and each word is staged at the slot of its
-// point, taken from the owning lane by a wave shuffle.
-template <int WV>
+// point, taken from the owning lane by a wave shuffle.  With kPosition (WV = 1) the
+// record word is not read but is the point's position in the pass-1 output: the
+// sorted stream then refers back to the weight blocks grouped by bin row.
+template <int WV, bool kPosition>
 __global__ __launch_bounds__(BT) void k_s2n_scatter2(const uint2* __restrict__ crd1,
                                                      const uint32_t* __restrict__ wts1,
                                                      const uint64_t* __restrict__ start1,
@@ -524,7 +465,8 @@ __global__ __launch_bounds__(BT) void k_s2n_scatter2(const uint2* __restrict__ c
     nU[u] = crd1[min(g0 + tid, q1 - 1)];                                                    \
     _Pragma("unroll") for (int v = 0; v < WV; ++v) {                                        \
       const uint32_t m = (uint32_t)lane + 64u * v;                                          \
-      nv[u][v] = wts1[min(g0 + wb + m / WV, q1 - 1) * WV + m % WV];                        \
+      nv[u][v] = kPosition ? (uint32_t)(g0 + wb + m / WV)                                   \
+                           : wts1[min(g0 + wb + m / WV, q1 - 1) * WV + m % WV];             \
     }                                                                                       \
   }
   FK_FETCH2N(q0);
@@ -654,7 +596,7 @@ fk_status sort2_narrow(hipStream_t st, const void* X, fk_dtype dt, int64_t n, in
   hipLaunchKernelGGL(k_s2_count2, dim3(nbx * g.slices), dim3(BT), 0, st, reinterpret_cast<const uint2*>(b.crd1),
                      b.start1, g.slices, fb, wbias, nf, tshift, nbx, b.cnt2);
   hipLaunchKernelGGL(k_s2_scan2, dim3(nbx), dim3(KMAX), 0, st, b.cnt2, b.start1, g.slices, nbx, b.off2, start);
-  hipLaunchKernelGGL(k_s2n_scatter2<WV>, dim3(nbx * g.slices), dim3(BT), lds, st,
+  hipLaunchKernelGGL((k_s2n_scatter2<WV, false>), dim3(nbx * g.slices), dim3(BT), lds, st,
                      reinterpret_cast<const uint2*>(b.crd1), b.wts1, b.start1, b.off2, start, g.slices, fb, wbias,
                      nf, tshift, nbx, reinterpret_cast<uint2*>(crd), wts);
   return hipGetLastError() == hipSuccess ? FK_OK : FK_EHIP;
@@ -686,6 +628,7 @@ fk_status sort2(hipStream_t st, const void* X, fk_dtype dt, int64_t n, int64_t x
                 int nf, int fb, int W, double scale, int tshift, int nbx, const Sort2Bufs& b, uint32_t* crd,
                 uint32_t* wts, uint64_t* start, int* flags) {
   if (!sort2_ok(nbx) || nw > 16 || (nf & (nf - 1)) != 0 || (nbx << tshift) != nf) return FK_EINVAL;
+  if (n > (int64_t)0xffffffff) return FK_EINVAL;   // positions are 32-bit
   const Sort2Geom g = sort2_geom(n, nbx);
   const uint32_t nf_fix = (uint32_t)nf << fb;
   const uint32_t one = 1u << fb;
@@ -724,10 +667,11 @@ fk_status sort2(hipStream_t st, const void* X, fk_dtype dt, int64_t n, int64_t x
   hipLaunchKernelGGL(k_s2_count2, dim3(nbx * g.slices), dim3(BT), 0, st, reinterpret_cast<const uint2*>(b.crd1),
                      b.start1, g.slices, fb, wbias, nf, tshift, nbx, b.cnt2);
   hipLaunchKernelGGL(k_s2_scan2, dim3(nbx), dim3(KMAX), 0, st, b.cnt2, b.start1, g.slices, nbx, b.off2, start);
-  hipLaunchKernelGGL(k_s2_scatter2, dim3(nbx * g.slices), dim3(BT), lds, st,
-                     reinterpret_cast<const uint2*>(b.crd1), reinterpret_cast<const uint4*>(b.wts1), b.start1,
-                     b.off2, start, g.slices, fb, wbias, nf, tshift, nbx, reinterpret_cast<uint2*>(crd),
-                     reinterpret_cast<uint4*>(wts));
+  // pass 2 moves the coordinates and each point's position in the pass-1 output
+  // (into wts, one word per point); the weight blocks stay grouped by bin row in b.wts1
+  hipLaunchKernelGGL((k_s2n_scatter2<1, true>), dim3(nbx * g.slices), dim3(BT), sizeof(StageN<1>), st,
+                     reinterpret_cast<const uint2*>(b.crd1), static_cast<const uint32_t*>(nullptr), b.start1, b.off2,
+                     start, g.slices, fb, wbias, nf, tshift, nbx, reinterpret_cast<uint2*>(crd), wts);
   return hipGetLastError() == hipSuccess ? FK_OK : FK_EHIP;
 }
 

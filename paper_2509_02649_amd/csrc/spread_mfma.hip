@@ -7,11 +7,12 @@
 // matrix product on the matrix cores.
 //
 // * Bins are MB x MB grid cells, sorted beforehand (sort2.hip) so a bin's points
-//   are contiguous: fixed-point coordinates [U1, U2] (8 B) and a 64-byte block of
-//   16 FP32 weights (zero padded) per point.  A point belongs to the bin holding
-//   the first cell of its window (not its own cell), so the windows of a bin's
-//   points start in MB consecutive cells per axis.  MB = 2 when the bins are well
-//   filled (fewer subgrid cells per point: (1 + w)^2 against (3 + w)^2), else 4.
+//   are contiguous: fixed-point coordinates [U1, U2] (8 B) and the point's
+//   position in the row-grouped output of the sort's first pass, where its 64-byte
+//   block of 16 FP32 weights (zero padded) stays.  A point belongs to the bin
+//   holding the first cell of its window (not its own cell), so the windows of a
+//   bin's points start in MB consecutive cells per axis.  MB = 2 when the bins are
+//   well filled (fewer subgrid cells per point: (1 + w)^2 against (3 + w)^2), else 4.
 // * A workgroup of SWAVE waves takes a slice of one bin; each wave takes the
 //   slice's points 4 at a time (one "chunk"), in stored order and on its own
 //   (no workgroup barrier in the loop).  All windows of a bin's points lie in
@@ -21,13 +22,14 @@
 //   over the S^2 cells is NT = ceil(S^2 / 16) v_mfma_f32_16x16x4f32 per chunk:
 //   rows = the 16 target channels, columns = 16 subgrid cells, K = the 4 points.
 //   The ones channel is the column sum of the same kernel products (vector ALUs).
-// * Lane (k = l/16, j = l%16) evaluates psi1 and psi2 of point k at subgrid
-//   offset j (two exponentials); the product for cell (a, b) is gathered from
-//   lanes (k, a) and (k, b) with two lane permutes.
-// * The coordinates and weights of the next SPD chunks are loaded while the
-//   current ones are processed.
+// * Per batch of 64 points, one lane per point writes the point's w kernel values
+//   per axis (at their subgrid offsets, zeros elsewhere) into an LDS table row; the
+//   B operand of cell (a, b) is the product of two table entries.
+// * The weights are gathered by position (64-byte blocks, one batch ahead: into
+//   alternating register sets for MB = 2); coordinates and positions stream one
+//   batch ahead.
 // * FP32 accumulators are added into the workgroup's FP64 LDS subgrid (ds_add_f64)
-//   every SFLUSH chunks and at the end; the subgrid is then added into the FP64
+//   every SFLUSH batches and at the end; the subgrid is then added into the FP64
 //   fine grid with global FP64 atomics.
 //
 // Lane layout of v_mfma_f32_16x16x4f32 (wave64): lane l supplies A[l%16][l/16]
@@ -65,15 +67,13 @@ __device__ __forceinline__ void win_start(uint32_t U, int fb, int w, int* i0, fl
 
 constexpr int SWAVE = 4;     // waves per workgroup, each independent
 constexpr int SFLUSH = 16;   // batches of 64 points between FP32 -> FP64 flushes
-constexpr int SPD = 4;       // weight chunks in flight per wave
 constexpr int PS = 36;       // kernel-value table row (16 psi1 + 16 psi2, padded; 16-byte rows)
 
 template <int W, int MB>
-__global__ __launch_bounds__(64 * SWAVE) void k_spread_mfma(const uint2* __restrict__ crd,
-                                                            const float* __restrict__ wts, int nw,
-                                                            const uint64_t* __restrict__ start, int nbx, int nf,
-                                                            int fb, float beta, int slices,
-                                                            double* __restrict__ grid) {
+__device__ __forceinline__ void spread_mfma_body(const uint2* __restrict__ crd, const uint32_t* __restrict__ pos,
+                                                 const float* __restrict__ wrow, int nw,
+                                                 const uint64_t* __restrict__ start, int nbx, int nf, int fb,
+                                                 float beta, int slices, double* __restrict__ grid) {
   constexpr int S = MB + W - 1;
   constexpr int NT = (S * S + 15) / 16;
   static_assert(S <= 15, "subgrid offsets 0..S-1, offset 15 reads zero");
@@ -144,71 +144,87 @@ __global__ __launch_bounds__(64 * SWAVE) void k_spread_mfma(const uint2* __restr
   const uint32_t npts = (uint32_t)(q1 - q0);
   const uint32_t nbatch = (npts + 63) / 64;
   const uint2* __restrict__ cs = crd + q0;
-  const float* __restrict__ ws = wts + q0 * 16;
-  // Loads are unconditional (index clamped to the slice; weight blocks are zero
-  // padded to 16) so that no branch makes the compiler wait for them early: the
-  // coordinates of the next batch and the weights of the next SPD chunks are in
-  // flight while the current ones are used.
-  auto wload = [&](uint32_t chunk) { return ws[min(chunk * 4 + k, npts - 1) * 16 + j]; };
+  const uint32_t* __restrict__ ps = pos + q0;
+  // Loads are unconditional (index clamped to the slice) so that no branch makes the
+  // compiler wait for them early.  Coordinates and positions are read one lane per
+  // point; the weights of chunk q of a batch are gathered for lane (k, j) as
+  // W[4q + k][j] from the 64-byte block at the point's position, which lane 4q + k
+  // holds.  A batch's gathers are issued one batch ahead, into the other of two
+  // register sets.
   auto cload = [&](uint32_t batch) { return cs[min(batch * 64 + lane, npts - 1)]; };
+  auto pload = [&](uint32_t batch) { return ps[min(batch * 64 + lane, npts - 1)]; };
+#define FK_GATHER(DST, P)                                                                    \
+  _Pragma("unroll") for (int q = 0; q < 16; ++q)                                             \
+    DST[q] = wrow[(size_t)(uint32_t)__shfl((int)(P), 4 * q + k, 64) * 16 + j];
   uint2 Un = cload(wv);
-  float Wq[SPD];
-#pragma unroll
-  for (int d = 0; d < SPD; ++d) Wq[d] = wload(wv * 16 + d);
+  uint32_t Pn = pload(wv);
+  float Wa[16], Wb[16];
+  FK_GATHER(Wa, Pn)
+  Pn = pload(wv + SWAVE);
   float* row = tab + lane * PS;
   int since = 0;
-  for (uint32_t bb = wv; bb < nbatch; bb += SWAVE) {
-    // Phase 1, one lane per point: window starts and the w kernel values per axis,
-    // written into the point's table row (zeros elsewhere).
-    const uint2 U = Un;
-    Un = cload(bb + SWAVE);
-    {
-      const bool valid = bb * 64 + lane < npts;
-      int i1, i2;
-      float s1, s2;
-      win_start(U.x, fb, W, &i1, &s1);
-      win_start(U.y, fb, W, &i2, &s2);
-      float4* r4 = reinterpret_cast<float4*>(row);
-#pragma unroll
-      for (int q = 0; q < 8; ++q) r4[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-      // (the sort put the point here because its window starts lie in the bin, so
-      // the relative starts are below MB; the test keeps the table rows in bounds)
-      const int rel1 = (i1 - o1) & (nf - 1), rel2 = 16 + ((i2 - o2) & (nf - 1));
-      if (valid && rel1 < MB && rel2 < 16 + MB) {
-#pragma unroll
-        for (int r = 0; r < W; ++r) {
-          row[rel1 + r] = psi_es2(s1 + (float)r, bl2, two_over_w);
-          row[rel2 + r] = psi_es2(s2 + (float)r, bl2, two_over_w);
-        }
-      }
+  // One batch: phase 1 builds the kernel-value table of the batch's points (one lane
+  // per point: window starts and the w kernel values per axis, zeros elsewhere),
+  // the next batch's gathers go out, phase 2 runs 16 chunks of 4 points on the
+  // matrix cores with the weights in WC.
+#define FK_BATCH(BB, WC, WN)                                                                 \
+  {                                                                                          \
+    const uint2 U = Un;                                                                      \
+    Un = cload((BB) + SWAVE);                                                                \
+    {                                                                                        \
+      const bool valid = (BB) * 64 + lane < npts;                                            \
+      int i1, i2;                                                                            \
+      float s1, s2;                                                                          \
+      win_start(U.x, fb, W, &i1, &s1);                                                       \
+      win_start(U.y, fb, W, &i2, &s2);                                                       \
+      float4* r4 = reinterpret_cast<float4*>(row);                                           \
+      _Pragma("unroll") for (int q = 0; q < 8; ++q) r4[q] = make_float4(0.f, 0.f, 0.f, 0.f); \
+      const int rel1 = (i1 - o1) & (nf - 1), rel2 = 16 + ((i2 - o2) & (nf - 1));            \
+      if (valid && rel1 < MB && rel2 < 16 + MB) {                                            \
+        _Pragma("unroll") for (int r = 0; r < W; ++r) {                                     \
+          row[rel1 + r] = psi_es2(s1 + (float)r, bl2, two_over_w);                           \
+          row[rel2 + r] = psi_es2(s2 + (float)r, bl2, two_over_w);                           \
+        }                                                                                    \
+      }                                                                                      \
+    }                                                                                        \
+    FK_GATHER(WN, Pn)                                                                        \
+    Pn = pload((BB) + 2 * SWAVE);                                                            \
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");                                   \
+    __builtin_amdgcn_wave_barrier();                                                         \
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");                                   \
+    _Pragma("unroll") for (int q = 0; q < 16; ++q) {                                         \
+      const float aop = WC[q];                                                               \
+      const float* rk = tab + (4 * q + k) * PS;                                              \
+      _Pragma("unroll") for (int t = 0; t < NT; ++t) {                                       \
+        const float bv = rk[offa[t]] * rk[offb[t]];                                          \
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bv, acc[t], 0, 0, 0);             \
+        ones[t] += bv;                                                                       \
+      }                                                                                      \
+    }                                                                                        \
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");                                   \
+    __builtin_amdgcn_wave_barrier();                                                         \
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");                                   \
+    if (++since == SFLUSH) {                                                                 \
+      flush();                                                                               \
+      since = 0;                                                                             \
+    }                                                                                        \
+  }
+  if constexpr (MB == 2) {
+    for (uint32_t bb = wv; bb < nbatch; bb += 2 * SWAVE) {
+      FK_BATCH(bb, Wa, Wb)
+      if (bb + SWAVE < nbatch) FK_BATCH(bb + SWAVE, Wb, Wa)
     }
-    // the rows written by other lanes of this wave are read below
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // Phase 2: 16 chunks of 4 points on the matrix cores.
+  } else {
+    // (more tiles per chunk: one register set copied forward keeps the kernel at
+    // three waves per SIMD, where the unrolled pair would not)
+    for (uint32_t bb = wv; bb < nbatch; bb += SWAVE) {
+      FK_BATCH(bb, Wa, Wb)
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const float aop = Wq[q % SPD];
-      // next weights of this slot: chunk q + SPD of this batch, or of the wave's next batch
-      const uint32_t nxt = (q + SPD < 16) ? bb * 16 + q + SPD : (bb + SWAVE) * 16 + (q + SPD - 16);
-      Wq[q % SPD] = wload(nxt);
-      const float* rk = tab + (4 * q + k) * PS;
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const float bv = rk[offa[t]] * rk[offb[t]];
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bv, acc[t], 0, 0, 0);
-        ones[t] += bv;
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (++since == SFLUSH) {
-      flush();
-      since = 0;
+      for (int q = 0; q < 16; ++q) Wa[q] = Wb[q];
     }
   }
+#undef FK_BATCH
+#undef FK_GATHER
   flush();
   __syncthreads();
   for (int i = tid; i < S * S * C; i += 64 * SWAVE) {
@@ -224,6 +240,21 @@ __global__ __launch_bounds__(64 * SWAVE) void k_spread_mfma(const uint2* __restr
   }
 }
 
+template <int W, int MB>
+__global__ __launch_bounds__(64 * SWAVE) void k_spread_mfma(
+    const uint2* __restrict__ crd, const uint32_t* __restrict__ pos, const float* __restrict__ wrow, int nw,
+    const uint64_t* __restrict__ start, int nbx, int nf, int fb, float beta, int slices, double* __restrict__ grid) {
+  spread_mfma_body<W, MB>(crd, pos, wrow, nw, start, nbx, nf, fb, beta, slices, grid);
+}
+// 4 x 4-cell bins with w <= 7: the compiler is held to the registers of three waves
+// per SIMD (LDS allows three workgroups per CU); left alone it takes more.
+template <int W, int MB>
+__global__ __launch_bounds__(64 * SWAVE) __attribute__((amdgpu_waves_per_eu(3))) void k_spread_mfma_w3(
+    const uint2* __restrict__ crd, const uint32_t* __restrict__ pos, const float* __restrict__ wrow, int nw,
+    const uint64_t* __restrict__ start, int nbx, int nf, int fb, float beta, int slices, double* __restrict__ grid) {
+  spread_mfma_body<W, MB>(crd, pos, wrow, nw, start, nbx, nf, fb, beta, slices, grid);
+}
+
 }  // namespace
 
 int spread_mfma_bin(int nf, int64_t n) {
@@ -234,15 +265,19 @@ int spread_mfma_bin(int nf, int64_t n) {
 bool spread_mfma_ok(int nw, int W) { return nw >= 8 && nw <= 16 && W >= 4 && W <= 8; }
 
 template <int W, int MB>
-static void launch_w(hipStream_t st, int blocks, size_t lds, const uint2* c2, const float* wf, int nw,
-                     const uint64_t* start, int nbx, int nf, int fb, float bt, int slices, double* grid) {
-  hipLaunchKernelGGL((k_spread_mfma<W, MB>), dim3(blocks), dim3(64 * SWAVE), lds, st, c2, wf, nw, start, nbx, nf, fb,
-                     bt, slices, grid);
+static void launch_w(hipStream_t st, int blocks, size_t lds, const uint2* c2, const uint32_t* pos, const float* wf,
+                     int nw, const uint64_t* start, int nbx, int nf, int fb, float bt, int slices, double* grid) {
+  if constexpr (MB == 4 && W <= 7)
+    hipLaunchKernelGGL((k_spread_mfma_w3<W, MB>), dim3(blocks), dim3(64 * SWAVE), lds, st, c2, pos, wf, nw, start,
+                       nbx, nf, fb, bt, slices, grid);
+  else
+    hipLaunchKernelGGL((k_spread_mfma<W, MB>), dim3(blocks), dim3(64 * SWAVE), lds, st, c2, pos, wf, nw, start, nbx,
+                       nf, fb, bt, slices, grid);
 }
 
-fk_status launch_spread_mfma(hipStream_t st, int W, int MB, const uint32_t* crd, const uint32_t* wts, int nw,
-                             const uint64_t* start, int nbx, int nb, int nf, int fb, double beta, int64_t n,
-                             double* grid) {
+fk_status launch_spread_mfma(hipStream_t st, int W, int MB, const uint32_t* crd, const uint32_t* pos,
+                             const uint32_t* wrow, int nw, const uint64_t* start, int nbx, int nb, int nf, int fb,
+                             double beta, int64_t n, double* grid) {
   if (!spread_mfma_ok(nw, W) || (MB != 2 && MB != 4)) return FK_EINVAL;
   const int64_t per_bin = (n + nb - 1) / nb;
   const int slices = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (per_bin + 16383) / 16384));
@@ -251,11 +286,11 @@ fk_status launch_spread_mfma(hipStream_t st, int W, int MB, const uint32_t* crd,
                      sizeof(float) * SWAVE * 64 * PS;
   const float bt = (float)beta;
   const uint2* c2 = reinterpret_cast<const uint2*>(crd);
-  const float* wf = reinterpret_cast<const float*>(wts);
-#define FK_SPREAD_W(WW)                                                                              \
-  case WW:                                                                                           \
-    if (MB == 2) launch_w<WW, 2>(st, blocks, lds, c2, wf, nw, start, nbx, nf, fb, bt, slices, grid); \
-    else launch_w<WW, 4>(st, blocks, lds, c2, wf, nw, start, nbx, nf, fb, bt, slices, grid);         \
+  const float* wf = reinterpret_cast<const float*>(wrow);
+#define FK_SPREAD_W(WW)                                                                                   \
+  case WW:                                                                                                \
+    if (MB == 2) launch_w<WW, 2>(st, blocks, lds, c2, pos, wf, nw, start, nbx, nf, fb, bt, slices, grid); \
+    else launch_w<WW, 4>(st, blocks, lds, c2, pos, wf, nw, start, nbx, nf, fb, bt, slices, grid);         \
     break;
   switch (W) {
     FK_SPREAD_W(4)
