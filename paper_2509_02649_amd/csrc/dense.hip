@@ -185,7 +185,8 @@ __global__ void k_make_scale(const double* __restrict__ H, const double* __restr
   scl[(size_t)l * Np + r] = v;
 }
 
-// A32[l] = S_l (H64 + lambda_l diag(p_real)) S_l in FP32, identity padding.
+// A32[l] = S_l (H64 + lambda_l diag(p_real)) S_l in FP32, identity padding; blocks
+// above the block diagonal are not written (no kernel reads them).
 __global__ __launch_bounds__(256) void k_make_a32(const double* __restrict__ H, const double* __restrict__ preal,
                                                   const double* __restrict__ lams, const double* __restrict__ scl,
                                                   int N, int Np, float* __restrict__ A) {
@@ -193,6 +194,7 @@ __global__ __launch_bounds__(256) void k_make_a32(const double* __restrict__ H, 
   if (idx >= (int64_t)Np * Np) return;
   const int l = blockIdx.y;
   int r = (int)(idx / Np), s = (int)(idx - (int64_t)r * Np);
+  if (s / NB > r / NB) return;   // the factorization reads only the lower block triangle
   float v;
   if (r < N && s < N) {
     double h = H[idx];
@@ -522,33 +524,61 @@ __device__ __forceinline__ void mfma_64xK(const float* Ls, const float (*Bs)[LDB
   }
 }
 
+// One 64 x 64 FP32 tile in four float4 registers per thread (256 threads: thread t
+// holds float4 number t + 256 u of the row-major tile), for loading the next tile of a
+// sweep while the current one is on the matrix cores.
+#define FK_TILE_FETCH(src, ld)                                                               \
+  do {                                                                                       \
+    _Pragma("unroll") for (int u_ = 0; u_ < 4; ++u_) {                                       \
+      const int i_ = threadIdx.x + 256 * u_, r_ = i_ / (NB / 4), c_ = (i_ - r_ * (NB / 4)) * 4; \
+      const float4 v_ = *reinterpret_cast<const float4*>((src) + r_ * (ld) + c_);          \
+      if (u_ == 0) nt0 = v_;                                                                 \
+      if (u_ == 1) nt1 = v_;                                                                 \
+      if (u_ == 2) nt2 = v_;                                                                 \
+      if (u_ == 3) nt3 = v_;                                                                 \
+    }                                                                                        \
+  } while (0)
+#define FK_TILE_STAGE(T)                                                                     \
+  do {                                                                                       \
+    _Pragma("unroll") for (int u_ = 0; u_ < 4; ++u_) {                                       \
+      const int i_ = threadIdx.x + 256 * u_, r_ = i_ / (NB / 4), c_ = (i_ - r_ * (NB / 4)) * 4; \
+      *reinterpret_cast<float4*>((T) + r_ * LDT + c_) = u_ == 0 ? nt0 : u_ == 1 ? nt1 : u_ == 2 ? nt2 : nt3; \
+    }                                                                                        \
+  } while (0)
+
 // Forward step kb of L y = r for every lambda (grid.y): y_kb = inv(L_kk) r_kb, written
-// by block 0; block x updates rows ib = kb + 1 + x: r_ib -= L[ib][kb] y_kb.
+// by block 0; block x then updates rows ib = kb + 1 + x, kb + 1 + x + gridDim.x, ...:
+// r_ib -= L[ib][kb] y_kb, with the next row's tile loaded while the current one is
+// multiplied (two LDS buffers, one barrier per row).
 template <int NCT>
 __global__ __launch_bounds__(256) void k_fwd_mfma(const float* __restrict__ A, int Np, int kb,
                                                   const float* __restrict__ Linv, float* __restrict__ R,
                                                   float* __restrict__ Y, int ncol) {
-  __shared__ float Ls[NB * LDT];
+  __shared__ float Ls[2][NB * LDT];
   __shared__ float Bs[NB][LDB];
   const int l = blockIdx.y;
+  const int nb = Np / NB;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   float* Rl = R + (size_t)l * ncol * Np;
+  const float* Al = A + (size_t)l * Np * Np;
   for (int i = threadIdx.x; i < NB * 16 * NCT; i += blockDim.x) {
     const int t = i / NB, k = i - t * NB;
     Bs[k][t] = t < ncol ? Rl[(size_t)t * Np + kb * NB + k] : 0.f;
   }
-  load_tile(Ls, Linv + ((size_t)l * (Np / NB) + kb) * NB * NB, NB);
+  load_tile(Ls[0], Linv + ((size_t)l * nb + kb) * NB * NB, NB);
+  int ib = kb + 1 + blockIdx.x;
+  float4 nt0, nt1, nt2, nt3;
+  if (ib < nb) FK_TILE_FETCH(Al + (size_t)ib * NB * Np + kb * NB, Np);
   __syncthreads();
   floatx4 acc[NCT];
-  mfma_64xK<false, NCT>(Ls, Bs, acc);
+  mfma_64xK<false, NCT>(Ls[0], Bs, acc);
   __syncthreads();
 #pragma unroll
   for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
     for (int v = 0; v < 4; ++v) Bs[16 * w + 4 * lk + v][ct * 16 + li] = acc[ct][v];
-  const int ib = kb + 1 + blockIdx.x;
-  if (ib * NB < Np) load_tile(Ls, A + (size_t)l * Np * Np + (size_t)ib * NB * Np + kb * NB, Np);
+  if (ib < nb) FK_TILE_STAGE(Ls[1]);
   __syncthreads();
   if (blockIdx.x == 0) {
     float* Yl = Y + (size_t)l * ncol * Np;
@@ -557,44 +587,56 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const float* __restrict__ A, i
       Yl[(size_t)t * Np + kb * NB + r] = Bs[r][t];
     }
   }
-  if (ib * NB >= Np) return;
-  mfma_64xK<false, NCT>(Ls, Bs, acc);
+  int cur = 1;
+  for (; ib < nb; ib += gridDim.x) {
+    const int nx = ib + gridDim.x;
+    if (nx < nb) FK_TILE_FETCH(Al + (size_t)nx * NB * Np + kb * NB, Np);
+    mfma_64xK<false, NCT>(Ls[cur], Bs, acc);
 #pragma unroll
-  for (int ct = 0; ct < NCT; ++ct)
+    for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int t = ct * 16 + li;
-      if (t < ncol) Rl[(size_t)t * Np + ib * NB + 16 * w + 4 * lk + v] -= acc[ct][v];
-    }
+      for (int v = 0; v < 4; ++v) {
+        const int t = ct * 16 + li;
+        if (t < ncol) Rl[(size_t)t * Np + ib * NB + 16 * w + 4 * lk + v] -= acc[ct][v];
+      }
+    if (nx < nb) FK_TILE_STAGE(Ls[cur ^ 1]);
+    __syncthreads();
+    cur ^= 1;
+  }
 }
 
 // Backward step kb of L^T x = y: x_kb = inv(L_kk)^T y_kb (block 0 writes X); block x
-// updates rows jb = x < kb: y_jb -= L[kb][jb]^T x_kb.
+// then updates rows jb = x, x + gridDim.x, ... < kb: y_jb -= L[kb][jb]^T x_kb, the
+// next row's tile loaded while the current one is multiplied.
 template <int NCT>
 __global__ __launch_bounds__(256) void k_bwd_mfma(const float* __restrict__ A, int Np, int kb,
                                                   const float* __restrict__ Linv, float* __restrict__ Yv,
                                                   float* __restrict__ X, int ncol) {
-  __shared__ float Ls[NB * LDT];
+  __shared__ float Ls[2][NB * LDT];
   __shared__ float Bs[NB][LDB];
   const int l = blockIdx.y;
+  const int nb = Np / NB;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   float* Yl = Yv + (size_t)l * ncol * Np;
+  const float* Ak = A + (size_t)l * Np * Np + (size_t)kb * NB * Np;
   for (int i = threadIdx.x; i < NB * 16 * NCT; i += blockDim.x) {
     const int t = i / NB, k = i - t * NB;
     Bs[k][t] = t < ncol ? Yl[(size_t)t * Np + kb * NB + k] : 0.f;
   }
-  load_tile(Ls, Linv + ((size_t)l * (Np / NB) + kb) * NB * NB, NB);
+  load_tile(Ls[0], Linv + ((size_t)l * nb + kb) * NB * NB, NB);
+  int jb = blockIdx.x;
+  float4 nt0, nt1, nt2, nt3;
+  if (jb < kb) FK_TILE_FETCH(Ak + jb * NB, Np);
   __syncthreads();
   floatx4 acc[NCT];
-  mfma_64xK<true, NCT>(Ls, Bs, acc);
+  mfma_64xK<true, NCT>(Ls[0], Bs, acc);
   __syncthreads();
 #pragma unroll
   for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
     for (int v = 0; v < 4; ++v) Bs[16 * w + 4 * lk + v][ct * 16 + li] = acc[ct][v];
-  const int jb = blockIdx.x;
-  if (jb < kb) load_tile(Ls, A + (size_t)l * Np * Np + (size_t)kb * NB * Np + jb * NB, Np);
+  if (jb < kb) FK_TILE_STAGE(Ls[1]);
   __syncthreads();
   if (blockIdx.x == 0) {
     float* Xl = X + (size_t)l * ncol * Np;
@@ -603,15 +645,22 @@ __global__ __launch_bounds__(256) void k_bwd_mfma(const float* __restrict__ A, i
       Xl[(size_t)t * Np + kb * NB + r] = Bs[r][t];
     }
   }
-  if (jb >= kb) return;
-  mfma_64xK<true, NCT>(Ls, Bs, acc);
+  int cur = 1;
+  for (; jb < kb; jb += gridDim.x) {
+    const int nx = jb + gridDim.x;
+    if (nx < kb) FK_TILE_FETCH(Ak + nx * NB, Np);
+    mfma_64xK<true, NCT>(Ls[cur], Bs, acc);
 #pragma unroll
-  for (int ct = 0; ct < NCT; ++ct)
+    for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int t = ct * 16 + li;
-      if (t < ncol) Yl[(size_t)t * Np + jb * NB + 16 * w + 4 * lk + v] -= acc[ct][v];
-    }
+      for (int v = 0; v < 4; ++v) {
+        const int t = ct * 16 + li;
+        if (t < ncol) Yl[(size_t)t * Np + jb * NB + 16 * w + 4 * lk + v] -= acc[ct][v];
+      }
+    if (nx < kb) FK_TILE_STAGE(Ls[cur ^ 1]);
+    __syncthreads();
+    cur ^= 1;
+  }
 }
 
 
@@ -859,8 +908,10 @@ static fk_status factor_all(fk_ctx* ctx, const SolveLayout& s) {
 static fk_status trsm_all(fk_ctx* ctx, const SolveLayout& s, float* R, float* Y, float* X) {
   const int nb = s.Np / NB;
   const bool two = s.ntgt > 16;
+  // workgroups per lambda: about 512 in all (two per CU), each sweeping several rows
+  const int gmax = std::max(1, 512 / s.nlam);
   for (int kb = 0; kb < nb; ++kb) {
-    int g = std::max(1, nb - kb - 1);
+    int g = std::max(1, std::min(gmax, nb - kb - 1));
     if (two)
       hipLaunchKernelGGL(k_fwd_mfma<2>, dim3(g, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv, R, Y,
                          s.ntgt);
@@ -869,7 +920,7 @@ static fk_status trsm_all(fk_ctx* ctx, const SolveLayout& s, float* R, float* Y,
                          s.ntgt);
   }
   for (int kb = nb - 1; kb >= 0; --kb) {
-    int g = std::max(1, kb);
+    int g = std::max(1, std::min(gmax, kb));
     if (two)
       hipLaunchKernelGGL(k_bwd_mfma<2>, dim3(g, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv, Y, X,
                          s.ntgt);
