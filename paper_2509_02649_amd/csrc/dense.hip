@@ -318,6 +318,78 @@ __device__ inline double recip64(double x) {
   return fma(r, e, r);
 }
 
+// The same update for the two block columns kb and kb + 1 at once, over the panels
+// k < kb:  A[i][kb] -= sum L[i][k] L[kb][k]^T  and (i > kb) A[i][kb+1] -= sum
+// L[i][k] L[kb+1][k]^T.  The row panel L[i][.], the bulk of the traffic, is read once
+// for both columns.  One LDS buffer per operand (three tiles, three workgroups per CU);
+// the next k's tiles are loaded into registers while the current ones are multiplied.
+__global__ __launch_bounds__(256) void k_left_update2(float* __restrict__ A, int Np, int kb) {
+  __shared__ __align__(16) float As[NB * LDT];
+  __shared__ __align__(16) float B0[NB * LDT];
+  __shared__ __align__(16) float B1[NB * LDT];
+  const int l = blockIdx.y;
+  const int i = kb + blockIdx.x;
+  float* Al = A + (size_t)l * Np * Np;
+  const float* Ai = Al + (size_t)i * NB * Np;
+  const float* A0 = Al + (size_t)kb * NB * Np;
+  const float* A1 = Al + (size_t)(kb + 1) * NB * Np;
+  int off_g[4], off_s[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int idx = threadIdx.x + q * 256, r = idx / (NB / 4), c = (idx % (NB / 4)) * 4;
+    off_g[q] = r * Np + c;
+    off_s[q] = r * LDT + c;
+  }
+  float4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3, rc0, rc1, rc2, rc3;
+#define FK_GLOAD3(k)                                                                 \
+  do {                                                                               \
+    const float* pa = Ai + (k) * NB;                                                 \
+    const float* pb = A0 + (k) * NB;                                                 \
+    const float* pc = A1 + (k) * NB;                                                 \
+    ra0 = *reinterpret_cast<const float4*>(pa + off_g[0]);                            \
+    ra1 = *reinterpret_cast<const float4*>(pa + off_g[1]);                            \
+    ra2 = *reinterpret_cast<const float4*>(pa + off_g[2]);                            \
+    ra3 = *reinterpret_cast<const float4*>(pa + off_g[3]);                            \
+    rb0 = *reinterpret_cast<const float4*>(pb + off_g[0]);                            \
+    rb1 = *reinterpret_cast<const float4*>(pb + off_g[1]);                            \
+    rb2 = *reinterpret_cast<const float4*>(pb + off_g[2]);                            \
+    rb3 = *reinterpret_cast<const float4*>(pb + off_g[3]);                            \
+    rc0 = *reinterpret_cast<const float4*>(pc + off_g[0]);                            \
+    rc1 = *reinterpret_cast<const float4*>(pc + off_g[1]);                            \
+    rc2 = *reinterpret_cast<const float4*>(pc + off_g[2]);                            \
+    rc3 = *reinterpret_cast<const float4*>(pc + off_g[3]);                            \
+  } while (0)
+#define FK_SSTORE3()                                                                 \
+  do {                                                                               \
+    *reinterpret_cast<float4*>(&As[off_s[0]]) = ra0;                                  \
+    *reinterpret_cast<float4*>(&As[off_s[1]]) = ra1;                                  \
+    *reinterpret_cast<float4*>(&As[off_s[2]]) = ra2;                                  \
+    *reinterpret_cast<float4*>(&As[off_s[3]]) = ra3;                                  \
+    *reinterpret_cast<float4*>(&B0[off_s[0]]) = rb0;                                  \
+    *reinterpret_cast<float4*>(&B0[off_s[1]]) = rb1;                                  \
+    *reinterpret_cast<float4*>(&B0[off_s[2]]) = rb2;                                  \
+    *reinterpret_cast<float4*>(&B0[off_s[3]]) = rb3;                                  \
+    *reinterpret_cast<float4*>(&B1[off_s[0]]) = rc0;                                  \
+    *reinterpret_cast<float4*>(&B1[off_s[1]]) = rc1;                                  \
+    *reinterpret_cast<float4*>(&B1[off_s[2]]) = rc2;                                  \
+    *reinterpret_cast<float4*>(&B1[off_s[3]]) = rc3;                                  \
+  } while (0)
+  floatx4 acc0[2][2] = {}, acc1[2][2] = {};
+  FK_GLOAD3(0);
+  for (int k = 0; k < kb; ++k) {
+    FK_SSTORE3();
+    __syncthreads();
+    if (k + 1 < kb) FK_GLOAD3(k + 1);
+    mfma_tile64(As, B0, acc0);
+    mfma_tile64(As, B1, acc1);
+    __syncthreads();
+  }
+#undef FK_GLOAD3
+#undef FK_SSTORE3
+  store_acc(Al + (size_t)i * NB * Np + kb * NB, Np, acc0, true, -1.0f);
+  if (i > kb) store_acc(Al + (size_t)i * NB * Np + (kb + 1) * NB, Np, acc1, true, -1.0f);
+}
+
 // Factor the diagonal block kb of every lambda (one workgroup per lambda) in FP64;
 // write L_kk (lower) back and inv(L_kk) to Linv[l][kb].
 // Thread (r, q) = (tid / 4, tid % 4) keeps entries r, q + 4u (u = 0..15) of the block
@@ -439,11 +511,11 @@ __global__ __launch_bounds__(256) void k_trsm_panel(float* __restrict__ A, int N
 }
 
 // Left-looking update of block column kb for every lambda (grid.y):
-//   A[i][kb] -= sum_{k < kb} L[i][k] L[kb][k]^T,   i = kb + blockIdx.x,
+//   A[i][kb] -= sum_{k0 <= k < k1} L[i][k] L[kb][k]^T,   i = kb + blockIdx.x,
 // the K loop over the finished panels streamed through double-buffered LDS (the next
 // pair of tiles is loaded into registers while the current pair is on the matrix
-// cores), so every output tile is read and written once per factorization.
-__global__ __launch_bounds__(256) void k_left_update(float* __restrict__ A, int Np, int kb) {
+// cores).
+__global__ __launch_bounds__(256) void k_left_update(float* __restrict__ A, int Np, int kb, int k0, int k1) {
   __shared__ __align__(16) float As[2][NB * LDT];
   __shared__ __align__(16) float Bs[2][NB * LDT];
   const int l = blockIdx.y;
@@ -486,14 +558,14 @@ __global__ __launch_bounds__(256) void k_left_update(float* __restrict__ A, int 
     *reinterpret_cast<float4*>(&Bs[buf][off_s[3]]) = rb3;                             \
   } while (0)
   floatx4 acc[2][2] = {};
-  FK_GLOAD(0);
+  FK_GLOAD(k0);
   FK_SSTORE(0);
   __syncthreads();
-  for (int k = 0; k < kb; ++k) {
-    const int cur = k & 1;
-    if (k + 1 < kb) FK_GLOAD(k + 1);
+  for (int k = k0; k < k1; ++k) {
+    const int cur = (k - k0) & 1;
+    if (k + 1 < k1) FK_GLOAD(k + 1);
     mfma_tile64(As[cur], Bs[cur], acc);
-    if (k + 1 < kb) FK_SSTORE(cur ^ 1);
+    if (k + 1 < k1) FK_SSTORE(cur ^ 1);
     __syncthreads();
   }
 #undef FK_GLOAD
@@ -892,13 +964,28 @@ SolveLayout solve_layout(int N, int nlam, int ntgt, void* base, size_t cap) {
 // (one pass over the column), factor the diagonal block, solve the panel below it.
 static fk_status factor_all(fk_ctx* ctx, const SolveLayout& s) {
   const int nb = s.Np / NB;
-  for (int kb = 0; kb < nb; ++kb) {
-    if (kb > 0)
-      hipLaunchKernelGGL(k_left_update, dim3(nb - kb, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb);
+  auto finish = [&](int kb) {   // diagonal block and the panel below it
     hipLaunchKernelGGL(k_potrf_diag, dim3(s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv, ctx->flags);
     const int rem = nb - kb - 1;
     if (rem > 0)
       hipLaunchKernelGGL(k_trsm_panel, dim3(rem, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv);
+  };
+  // Block columns in pairs (kb, kb + 1): one pass over the panels k < kb updates both,
+  // then column kb is finished, then column kb + 1 takes its remaining term k = kb.
+  for (int kb = 0; kb < nb;) {
+    if (kb > 0 && kb + 1 < nb) {
+      hipLaunchKernelGGL(k_left_update2, dim3(nb - kb, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb);
+      finish(kb);
+      hipLaunchKernelGGL(k_left_update, dim3(nb - kb - 1, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb + 1,
+                         kb, kb + 1);
+      finish(kb + 1);
+      kb += 2;
+    } else {
+      if (kb > 0)
+        hipLaunchKernelGGL(k_left_update, dim3(nb - kb, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, 0, kb);
+      finish(kb);
+      kb += 1;
+    }
   }
   FK_HIP(hipGetLastError());
   return FK_OK;
