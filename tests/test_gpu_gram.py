@@ -57,9 +57,12 @@ def test_gram_2d_other_m(fk, m):
     assert eT <= TOL and eb <= TOL
 
 
-@pytest.mark.parametrize("ntgt,n", [(16, 30_000), (8, 50_000), (7, 20_000), (17, 20_000), (16, 1_000_000)])
+@pytest.mark.parametrize("ntgt,n", [(16, 30_000), (8, 50_000), (7, 20_000), (17, 20_000), (16, 1_000_000),
+                                    (2, 40_000), (3, 40_001), (16, 1), (16, 7), (3, 1), (2, 5)])
 def test_gram_2d_multi_target(fk, ntgt, n):
-    # 8..16 targets take the MFMA spread (bins of 4 x 4 cells); 7 and 17 the atomic spread
+    # 8..16 targets: channel-row MFMA spread (4 x 4-cell bins at these sizes), weights gathered
+    # by position; 0..7 targets: outer-product MFMA spread over 8 x 8-cell bins with 1-, 2-, 4-
+    # or 8-word records; 17 targets: the FP64 atomic spread.  n = 1, 5 and 7 leave most bins empty.
     X = synth.uniform_points(77 + ntgt, 2, n)
     Y = synth.batched_targets(X, 77 + ntgt, ntgt=ntgt)
     eT, eb, info = _errors(fk, X, Y, 32)
