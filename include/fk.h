@@ -102,7 +102,8 @@ typedef struct {
   int refine_iters;    /* FP64 refinement iterations performed */
   int w;               /* spreading kernel width (grid points per dimension) */
   int nf;              /* fine-grid size per dimension */
-  int bin;             /* bin edge (grid points) of the binned spread, 0 = unbinned */
+  int bin;             /* bin edge (grid points) of the binned spread: > 0 FP64-atomic spread,
+                          < 0 matrix-core spread over |bin| x |bin| cells, 0 = unbinned (1-D) */
   double beta;         /* exponential-of-semicircle shape parameter */
   double resid_rel;    /* max over (lambda, target) of ||b - A theta|| / ||b|| in FP64 */
   float t_sort_ms, t_spread_ms, t_fft_ms, t_assemble_ms, t_factor_ms, t_solve_ms, t_total_ms;
@@ -125,7 +126,8 @@ const char* fk_status_string(fk_status s);
  *   b_out[t][k] = n^-1 sum_j Y[t][j] exp(-i k.X_j),   k in {-m..m}^d,  complex128 ntgt x N
  * computed by exponential-of-semicircle spreading onto an oversampled grid, an
  * FFT and deconvolution.  d in {1, 2}; 1 <= m <= 64; 0 <= ntgt <= 32 (Y may be NULL
- * when ntgt = 0); n >= 1. */
+ * when ntgt = 0); n >= 1, and n <= 2^32 - 1 for d = 2 with ntgt <= 16 (point positions
+ * are 32-bit in the bin sort; larger n returns FK_EINVAL). */
 fk_status fk_gram_workspace_size(fk_ctx* ctx, int d, int64_t n, int ntgt, int m, size_t* bytes);
 fk_status fk_gram(fk_ctx* ctx, int d, int64_t n, fk_dtype dtype, const void* X, int ntgt,
                   const void* Y, int m, double* M_out, double* b_out,
