@@ -189,22 +189,20 @@ __global__ void k_make_scale(const double* __restrict__ H, const double* __restr
 // above the block diagonal are not written (no kernel reads them).
 __global__ __launch_bounds__(256) void k_make_a32(const double* __restrict__ H, const double* __restrict__ preal,
                                                   const double* __restrict__ lams, const double* __restrict__ scl,
-                                                  int N, int Np, float* __restrict__ A) {
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                                  int N, int Np, int nlam, float* __restrict__ A) {
+  // one element of H64, read once, written for every lambda
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)Np * Np) return;
-  const int l = blockIdx.y;
-  int r = (int)(idx / Np), s = (int)(idx - (int64_t)r * Np);
+  const int r = (int)(idx / Np), s = (int)(idx - (int64_t)r * Np);
   if (s / NB > r / NB) return;   // the factorization reads only the lower block triangle
-  float v;
-  if (r < N && s < N) {
-    double h = H[idx];
-    if (r == s) h += lams[l] * preal[r];
+  const bool in = r < N && s < N;
+  const double h = in ? H[idx] : 0.0;
+  const double pr = (in && r == s) ? preal[r] : 0.0;
+  const float pad = (r == s) ? 1.0f : 0.0f;
+  for (int l = 0; l < nlam; ++l) {
     const double* sl = scl + (size_t)l * Np;
-    v = (float)(sl[r] * h * sl[s]);
-  } else {
-    v = (r == s) ? 1.0f : 0.0f;
+    A[(size_t)l * Np * Np + idx] = in ? (float)(sl[r] * (h + lams[l] * pr) * sl[s]) : pad;
   }
-  A[(size_t)l * Np * Np + idx] = v;
 }
 
 // preal[r] = p[complex mode of r]
@@ -1101,8 +1099,8 @@ fk_status solve_impl(fk_ctx* ctx, const SolveProblem& P, const SolveLayout& s, d
   }
   hipLaunchKernelGGL(k_make_scale, dim3((Np + 255) / 256, s.nlam), dim3(256), 0, ctx->stream, s.H64, s.preal,
                      s.lams, N, Np, s.scl);
-  hipLaunchKernelGGL(k_make_a32, dim3(gb, s.nlam), dim3(256), 0, ctx->stream, s.H64, s.preal, s.lams, s.scl, N,
-                     Np, s.A32);
+  hipLaunchKernelGGL(k_make_a32, dim3(gb), dim3(256), 0, ctx->stream, s.H64, s.preal, s.lams, s.scl, N, Np,
+                     s.nlam, s.A32);
   hipLaunchKernelGGL(k_rhs_real, dim3((Np + 255) / 256, s.ntgt), dim3(256), 0, ctx->stream, P.b, N, L, Np,
                      s.ntgt, s.Bre);
   FK_HIP(hipGetLastError());
