@@ -657,6 +657,15 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const float* __restrict__ A, i
       Yl[(size_t)t * Np + kb * NB + r] = Bs[r][t];
     }
   }
+  // this lane's part of the right-hand-side block of a row: 4 rows x NCT columns
+  float rr[NCT][4];
+#define FK_R_FETCH(RB)                                                                         \
+  _Pragma("unroll") for (int ct = 0; ct < NCT; ++ct) {                                         \
+    const int t_ = min(ct * 16 + li, ncol - 1);                                                \
+    _Pragma("unroll") for (int v = 0; v < 4; ++v)                                              \
+      rr[ct][v] = Rl[(size_t)t_ * Np + (RB) * NB + 16 * w + 4 * lk + v];                       \
+  }
+  if (ib < nb) FK_R_FETCH(ib)
   int cur = 1;
   for (; ib < nb; ib += gridDim.x) {
     const int nx = ib + gridDim.x;
@@ -667,12 +676,14 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const float* __restrict__ A, i
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int t = ct * 16 + li;
-        if (t < ncol) Rl[(size_t)t * Np + ib * NB + 16 * w + 4 * lk + v] -= acc[ct][v];
+        if (t < ncol) Rl[(size_t)t * Np + ib * NB + 16 * w + 4 * lk + v] = rr[ct][v] - acc[ct][v];
       }
+    if (nx < nb) FK_R_FETCH(nx)
     if (nx < nb) FK_TILE_STAGE(Ls[cur ^ 1]);
     __syncthreads();
     cur ^= 1;
   }
+#undef FK_R_FETCH
 }
 
 // Backward step kb of L^T x = y: x_kb = inv(L_kk)^T y_kb (block 0 writes X); block x
@@ -715,6 +726,14 @@ __global__ __launch_bounds__(256) void k_bwd_mfma(const float* __restrict__ A, i
       Xl[(size_t)t * Np + kb * NB + r] = Bs[r][t];
     }
   }
+  float rr[NCT][4];
+#define FK_R_FETCH(RB)                                                                         \
+  _Pragma("unroll") for (int ct = 0; ct < NCT; ++ct) {                                         \
+    const int t_ = min(ct * 16 + li, ncol - 1);                                                \
+    _Pragma("unroll") for (int v = 0; v < 4; ++v)                                              \
+      rr[ct][v] = Yl[(size_t)t_ * Np + (RB) * NB + 16 * w + 4 * lk + v];                       \
+  }
+  if (jb < kb) FK_R_FETCH(jb)
   int cur = 1;
   for (; jb < kb; jb += gridDim.x) {
     const int nx = jb + gridDim.x;
@@ -725,12 +744,14 @@ __global__ __launch_bounds__(256) void k_bwd_mfma(const float* __restrict__ A, i
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int t = ct * 16 + li;
-        if (t < ncol) Yl[(size_t)t * Np + jb * NB + 16 * w + 4 * lk + v] -= acc[ct][v];
+        if (t < ncol) Yl[(size_t)t * Np + jb * NB + 16 * w + 4 * lk + v] = rr[ct][v] - acc[ct][v];
       }
+    if (nx < kb) FK_R_FETCH(nx)
     if (nx < kb) FK_TILE_STAGE(Ls[cur ^ 1]);
     __syncthreads();
     cur ^= 1;
   }
+#undef FK_R_FETCH
 }
 
 
