@@ -280,7 +280,7 @@ __global__ __launch_bounds__(KMAX) void k_s2_scan2(const uint32_t* __restrict__ 
 
 // ---------------------------------------------------------------- narrow records
 // The same two passes for 0..7 weight channels (the outer-product spread): records of
-// WV = 1, 2, 4 or 8 weight words per point (zero padded), staged word by word.  A
+// WV = 0, 1, 2, 4 or 8 weight words per point (zero padded), staged word by word.  A
 // record is small, so each thread takes NPT points per batch (BT NPT points between
 // barriers, longer runs per bucket).
 template <int WV>
@@ -295,7 +295,7 @@ struct StageN {
   uint32_t total;
   uint16_t sbin[BT * NPT];
   uint2 scrd[BT * NPT];
-  uint32_t swts[BT * NPT * WV];
+  uint32_t swts[BT * NPT * (WV > 0 ? WV : 1)];
 };
 
 // Exclusive prefix sums of the batch's bucket counts (after the rank atomics).
@@ -337,10 +337,12 @@ __device__ __forceinline__ void write_batch_n(StageN<WV>& sm, uint2* __restrict_
     const int b = sm.sbin[q];
     crd_out[sm.cur[b] + (q - sm.lofs[b])] = sm.scrd[q];
   }
-  for (uint32_t q = threadIdx.x; q < total * WV; q += BT) {
-    const uint32_t s = q / WV;
-    const int b = sm.sbin[s];
-    wts_out[(sm.cur[b] + (s - sm.lofs[b])) * WV + q % WV] = sm.swts[q];
+  if constexpr (WV > 0) {
+    for (uint32_t q = threadIdx.x; q < total * WV; q += BT) {
+      const uint32_t s = q / WV;
+      const int b = sm.sbin[s];
+      wts_out[(sm.cur[b] + (s - sm.lofs[b])) * WV + q % WV] = sm.swts[q];
+    }
   }
 }
 
@@ -368,7 +370,7 @@ __global__ __launch_bounds__(BT) void k_s2n_scatter1(const TX* __restrict__ X, i
   // next batch in flight: point base + u BT + tid of slot u (index clamped to the
   // chunk; no target row is read when nw = 0)
   double nx1[NPT], nx2[NPT];
-  float ny[NPT][WV];
+  float ny[NPT][WV > 0 ? WV : 1];
 #define FK_FETCH1N(bb)                                                                     \
   _Pragma("unroll") for (int u = 0; u < NPT; ++u) {                                        \
     const int64_t jc = min((int64_t)(bb) + u * BT + tid, end - 1);                         \
@@ -380,7 +382,7 @@ __global__ __launch_bounds__(BT) void k_s2n_scatter1(const TX* __restrict__ X, i
   FK_FETCH1N(beg);
   for (int64_t base = beg; base < end; base += (int64_t)BT * NPT) {
     double x1[NPT], x2[NPT];
-    float w[NPT][WV];
+    float w[NPT][WV > 0 ? WV : 1];
 #pragma unroll
     for (int u = 0; u < NPT; ++u) {
       x1[u] = nx1[u];
@@ -442,6 +444,7 @@ __global__ __launch_bounds__(BT) void k_s2n_scatter2(const uint2* __restrict__ c
                                                      const uint64_t* __restrict__ start, int slices, int fb,
                                                      uint32_t wbias, int nf, int tshift, int nbx,
                                                      uint2* __restrict__ crd, uint32_t* __restrict__ wts) {
+  constexpr int WD = WV > 0 ? WV : 1;   // divisor for the word index (no words when WV = 0)
   constexpr int NPT = narrow_ppt<WV>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   StageN<WV>& sm = *reinterpret_cast<StageN<WV>*>(smem_raw);
@@ -458,21 +461,21 @@ __global__ __launch_bounds__(BT) void k_s2n_scatter2(const uint2* __restrict__ c
   const int lane = tid & 63;
   const uint64_t wb = (uint64_t)(tid & ~63);
   uint2 nU[NPT];
-  uint32_t nv[NPT][WV];
+  uint32_t nv[NPT][WV > 0 ? WV : 1];
 #define FK_FETCH2N(bb)                                                                      \
   _Pragma("unroll") for (int u = 0; u < NPT; ++u) {                                         \
     const uint64_t g0 = (uint64_t)(bb) + (uint64_t)u * BT;                                  \
     nU[u] = crd1[min(g0 + tid, q1 - 1)];                                                    \
     _Pragma("unroll") for (int v = 0; v < WV; ++v) {                                        \
       const uint32_t m = (uint32_t)lane + 64u * v;                                          \
-      nv[u][v] = kPosition ? (uint32_t)(g0 + wb + m / WV)                                   \
-                           : wts1[min(g0 + wb + m / WV, q1 - 1) * WV + m % WV];             \
+      nv[u][v] = kPosition ? (uint32_t)(g0 + wb + m / WD)                                   \
+                           : wts1[min(g0 + wb + m / WD, q1 - 1) * WV + m % WD];             \
     }                                                                                       \
   }
   FK_FETCH2N(q0);
   for (uint64_t base = q0; base < q1; base += (uint64_t)BT * NPT) {
     uint2 U[NPT];
-    uint32_t v[NPT][WV];
+    uint32_t v[NPT][WV > 0 ? WV : 1];
 #pragma unroll
     for (int u = 0; u < NPT; ++u) {
       U[u] = nU[u];
@@ -500,8 +503,8 @@ __global__ __launch_bounds__(BT) void k_s2n_scatter2(const uint2* __restrict__ c
 #pragma unroll
       for (int c = 0; c < WV; ++c) {
         const uint32_t m = (uint32_t)lane + 64u * c;
-        const uint32_t su = __shfl(s, (int)(m / WV), 64);
-        if (su != 0xffffffffu) sm.swts[su * WV + m % WV] = v[u][c];
+        const uint32_t su = __shfl(s, (int)(m / WD), 64);
+        if (su != 0xffffffffu) sm.swts[su * WV + m % WD] = v[u][c];
       }
     }
     __syncthreads();
@@ -608,6 +611,7 @@ bool sort2_ok(int nbx) { return nbx >= 1 && nbx <= KMAX; }
 
 int sort2_words(int nw) {
   if (nw >= 8) return 16;
+  if (nw == 0) return 0;
   int wv = 1;
   while (wv < nw) wv <<= 1;
   return wv;
@@ -636,6 +640,8 @@ fk_status sort2(hipStream_t st, const void* X, fk_dtype dt, int64_t n, int64_t x
   const int wv = sort2_words(nw);
   if (wv < 16) {
     switch (wv) {
+      case 0: return sort2_narrow<0>(st, X, dt, n, xstride, Y, nw, nf_fix, fb, wbias, scale, tshift, nbx, g, b, crd,
+                                     wts, start, flags);
       case 1: return sort2_narrow<1>(st, X, dt, n, xstride, Y, nw, nf_fix, fb, wbias, scale, tshift, nbx, g, b, crd,
                                      wts, start, flags);
       case 2: return sort2_narrow<2>(st, X, dt, n, xstride, Y, nw, nf_fix, fb, wbias, scale, tshift, nbx, g, b, crd,

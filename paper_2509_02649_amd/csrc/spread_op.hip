@@ -7,12 +7,14 @@
 //   D_c[x][y] += sum_k (W_c[k] psi1_k[x]) psi2_k[y],
 // one v_mfma_f32_16x16x4f32 on a 16 x 16 subgrid: A[x][k] = W_c[k] psi1_k[x] and
 // B[k][y] = psi2_k[y].  Lane l = j + 16 k supplies A[j][k] and B[k][j], the kernel
-// values of point k at subgrid offset j; element v of its result is D[4 k + v][j].  Per point that is CH / 4 MFMAs (CH = WV + 1 channels), against
-// ceil(S^2 / 16) / 4 for the channel-row form of spread_mfma.hip, which pays off
-// only with many channels.
+// values of point k at subgrid offset j; element v of its result is D[4 k + v][j].
+// Per point that is CH / 4 MFMAs (CH = WV + 1 channels), against ceil(S^2 / 16) / 4
+// for the channel-row form of spread_mfma.hip, which pays off only with many
+// channels.
 //
 // * Bins are OMB x OMB cells (OMB = 8), sorted beforehand (sort2.hip, records of WV
-//   weight words); a point belongs to the bin holding the first cell of its window,
+//   = 0, 1, 2, 4 or 8 weight words, WV = 0 for the Gram channel alone); a point
+//   belongs to the bin holding the first cell of its window,
 //   so all windows of a bin lie in its S x S subgrid, S = OMB + w - 1 <= 16.
 // * A workgroup of OWAVE waves takes a slice of one bin, each wave its batches of 64
 //   points in turn.  Per batch, one lane per point writes the point's w kernel values
@@ -57,13 +59,15 @@ __device__ __forceinline__ void window(uint32_t U, int fb, int w, int* i0, float
 
 template <int WV>
 struct WBlk {
-  float v[WV];
+  float v[WV > 0 ? WV : 1];
 };
 
 template <int WV>
 __device__ __forceinline__ WBlk<WV> load_w(const uint32_t* __restrict__ p) {
   WBlk<WV> r;
-  if constexpr (WV == 1) {
+  if constexpr (WV == 0) {
+    r.v[0] = 0.f;
+  } else if constexpr (WV == 1) {
     r.v[0] = __uint_as_float(p[0]);
   } else if constexpr (WV == 2) {
     const uint2 a = *reinterpret_cast<const uint2*>(p);
@@ -82,8 +86,14 @@ __device__ __forceinline__ WBlk<WV> load_w(const uint32_t* __restrict__ p) {
   return r;
 }
 
+// Table row: psi1[16], psi2[16], weights, padded to a multiple of 4 floats that is an
+// odd number of 16-byte words, so that the float4 row writes of 8 consecutive lanes fall
+// into distinct LDS banks (36 floats, or 44 with 8 weight words).
 template <int WV>
-constexpr int op_row() { return (32 + WV + 3) & ~3; }   // table row: psi1[16], psi2[16], weights
+constexpr int op_row() {
+  const int r = (32 + WV + 3) & ~3;
+  return ((r / 4) % 2 == 0) ? r + 4 : r;
+}
 
 template <int W, int WV>
 __global__ __launch_bounds__(64 * OWAVE) void k_spread_op(const uint2* __restrict__ crd,
@@ -219,6 +229,7 @@ template <int W>
 fk_status launch_op_w(hipStream_t st, int wv, int blocks, const uint2* c2, const uint32_t* w, int C,
                       const uint64_t* start, int nbx, int nf, int fb, float bt, int slices, double* grid) {
   switch (wv) {
+    case 0: launch_op<W, 0>(st, blocks, c2, w, C, start, nbx, nf, fb, bt, slices, grid); break;
     case 1: launch_op<W, 1>(st, blocks, c2, w, C, start, nbx, nf, fb, bt, slices, grid); break;
     case 2: launch_op<W, 2>(st, blocks, c2, w, C, start, nbx, nf, fb, bt, slices, grid); break;
     case 4: launch_op<W, 4>(st, blocks, c2, w, C, start, nbx, nf, fb, bt, slices, grid); break;
