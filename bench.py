@@ -84,8 +84,8 @@ def main():
                     help="copy 1 GiB device to device before the steps (reference dispatch for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the point stream would shard "
-              "by an all-reduce of the FP64 fine grids; see the design notes)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (the point stream would shard "
+              "by an all-reduce of the FP64 fine grids or of the extracted M and b)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
