@@ -82,6 +82,18 @@ def test_gram_2d_multi_target_dense_bins(fk, ntgt, n, m):
     assert eT <= TOL and eb <= TOL
 
 
+@pytest.mark.parametrize("n", [3, 250_001])
+def test_gram_only_no_targets(fk, n):
+    # the Gram channel alone (Y = None): records without weight words, one MFMA per 4 points
+    X = synth.uniform_points(63, 2, n)
+    M, b = fk.gram(torch.from_numpy(X).cuda(), None, 24)
+    Mo = oracle.gram_generator(X.astype(np.float64), 24)
+    eT = np.abs(M.cpu().numpy() - Mo).max() / abs(Mo.ravel()[Mo.size // 2])
+    print(f"2-D gram only n={n}: eps_T={eT:.2e}")
+    assert b is None or b.numel() == 0
+    assert eT <= TOL
+
+
 def test_gram_boundary_points_fold(fk):
     # points on the seam: -pi, fp32(pi) > pi, values just inside [-2pi, 2pi) that fold
     pts = np.array([-np.pi, np.float32(np.pi), 0.0, -2 * np.pi + 1e-3, 2 * np.pi - 1e-3, 3.0, -3.0],
