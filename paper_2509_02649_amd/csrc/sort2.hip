@@ -285,10 +285,11 @@ __global__ __launch_bounds__(KMAX) void k_s2_scan2(const uint32_t* __restrict__ 
 // barriers, longer runs per bucket).
 template <int WV>
 constexpr int narrow_ppt() { return WV <= 2 ? 4 : (WV == 4 ? 2 : 1); }
+constexpr int kPosPpt = 8;   // points per thread of the position pass (116 KB of LDS)
 
-template <int WV>
+template <int WV, int P = narrow_ppt<WV>()>
 struct StageN {
-  static constexpr int NPT = narrow_ppt<WV>();
+  static constexpr int NPT = P;
   unsigned long long cur[KMAX];
   uint32_t hist[KMAX];
   uint32_t lofs[KMAX];
@@ -329,8 +330,8 @@ __device__ __forceinline__ void scan_counts(St& sm, int nk) {
   __syncthreads();
 }
 
-template <int WV>
-__device__ __forceinline__ void write_batch_n(StageN<WV>& sm, uint2* __restrict__ crd_out,
+template <int WV, int P>
+__device__ __forceinline__ void write_batch_n(StageN<WV, P>& sm, uint2* __restrict__ crd_out,
                                               uint32_t* __restrict__ wts_out) {
   const uint32_t total = sm.total;
   for (uint32_t q = threadIdx.x; q < total; q += BT) {
@@ -436,7 +437,7 @@ __global__ __launch_bounds__(BT) void k_s2n_scatter1(const TX* __restrict__ X, i
 // point, taken from the owning lane by a wave shuffle.  With kPosition (WV = 1) the
 // record word is not read but is the point's position in the pass-1 output: the
 // sorted stream then refers back to the weight blocks grouped by bin row.
-template <int WV, bool kPosition>
+template <int WV, bool kPosition, int NPT = narrow_ppt<WV>()>
 __global__ __launch_bounds__(BT) void k_s2n_scatter2(const uint2* __restrict__ crd1,
                                                      const uint32_t* __restrict__ wts1,
                                                      const uint64_t* __restrict__ start1,
@@ -445,9 +446,8 @@ __global__ __launch_bounds__(BT) void k_s2n_scatter2(const uint2* __restrict__ c
                                                      uint32_t wbias, int nf, int tshift, int nbx,
                                                      uint2* __restrict__ crd, uint32_t* __restrict__ wts) {
   constexpr int WD = WV > 0 ? WV : 1;   // divisor for the word index (no words when WV = 0)
-  constexpr int NPT = narrow_ppt<WV>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  StageN<WV>& sm = *reinterpret_cast<StageN<WV>*>(smem_raw);
+  StageN<WV, NPT>& sm = *reinterpret_cast<StageN<WV, NPT>*>(smem_raw);
   const int tid = threadIdx.x;
   const int bx = blockIdx.x / slices, sl = blockIdx.x - bx * slices;
   for (int b = tid; b < nbx; b += BT) {
@@ -674,8 +674,9 @@ fk_status sort2(hipStream_t st, const void* X, fk_dtype dt, int64_t n, int64_t x
                      b.start1, g.slices, fb, wbias, nf, tshift, nbx, b.cnt2);
   hipLaunchKernelGGL(k_s2_scan2, dim3(nbx), dim3(KMAX), 0, st, b.cnt2, b.start1, g.slices, nbx, b.off2, start);
   // pass 2 moves the coordinates and each point's position in the pass-1 output
-  // (into wts, one word per point); the weight blocks stay grouped by bin row in b.wts1
-  hipLaunchKernelGGL((k_s2n_scatter2<1, true>), dim3(nbx * g.slices), dim3(BT), sizeof(StageN<1>), st,
+  // (into wts, one word per point); the weight blocks stay grouped by bin row in b.wts1.
+  // Its records are 12 B, so a batch takes kPosPpt points per thread.
+  hipLaunchKernelGGL((k_s2n_scatter2<1, true, kPosPpt>), dim3(nbx * g.slices), dim3(BT), sizeof(StageN<1, kPosPpt>), st,
                      reinterpret_cast<const uint2*>(b.crd1), static_cast<const uint32_t*>(nullptr), b.start1, b.off2,
                      start, g.slices, fb, wbias, nf, tshift, nbx, reinterpret_cast<uint2*>(crd), wts);
   return hipGetLastError() == hipSuccess ? FK_OK : FK_EHIP;
