@@ -16,6 +16,8 @@ evaluated slowly in float64 on the CPU:
   "Tractable domains") and the additive block penalty (Sec. 5).
 * ``solve``    - the normal equations of eq. (kenrel_reg) solved by an FP64
   LAPACK Cholesky (zpotrf/zpotrs through scipy).
+* ``cg``       - the product Sigma x by its dense definition and the textbook
+  Jacobi-preconditioned conjugate-gradient iteration (Sec. 2.3, "Matrix inversion").
 * ``predict``  - f_theta(x) = sum_k theta_k exp(+i k.x) by direct sum (Sec. 2.1).
 * ``krr``      - kernel ridge regression in its n x n kernel form (Sec. 2.1), an
   independent route to theta for small n.
@@ -38,6 +40,7 @@ from .fourier import (modes, gram_generator, rhs, fourier_entry, toeplitz_matrix
 from .penalty import (sobolev_weights, sobolev_bessel_weights, piml_box_fourier_matrix,
                       heat_symbol, piml_heat_penalty, additive_penalty)
 from .solve import system_matrix, solve_system, condition_number, fit
+from .cg import toeplitz_apply, pcg
 from .predict import predict, predict_additive
 from .krr import krr_theta
 from .grad import heldout_mse, heldout_mse_quadratic, mse_gradients
@@ -47,7 +50,7 @@ __all__ = [
     "additive_blocks", "additive_rhs",
     "sobolev_weights", "sobolev_bessel_weights", "piml_box_fourier_matrix", "heat_symbol",
     "piml_heat_penalty", "additive_penalty",
-    "system_matrix", "solve_system", "condition_number", "fit",
+    "system_matrix", "solve_system", "condition_number", "fit", "toeplitz_apply", "pcg",
     "predict", "predict_additive", "krr_theta",
     "heldout_mse", "heldout_mse_quadratic", "mse_gradients",
 ]
