@@ -147,6 +147,38 @@ fk_status fk_solve(fk_ctx* ctx, int d, int m, const double* M, int ntgt, const d
                    const double* lambdas, int nlam, const fk_penalty* pen,
                    double* theta_out, void* ws, size_t ws_bytes, fk_fit_info* info);
 
+/* ---------------------------------------------------------------- iterative solve
+ * The paper's own route to theta (Sec. 2.3, "Matrix inversion"): conjugate gradients on
+ * (Sigma + lambda P) theta = b, where each product with Sigma[k, l] = M[l - k] (Sec. 2.3,
+ * "Covariance matrix") costs O(m^d log m) through an FFT of its circulant embedding
+ * (length Lf = the next power of two >= 4m + 1 per dimension).
+ *
+ * fk_toeplitz_apply: y[v] = Sigma x[v] for nvec vectors.  d = 1, 2 or 3; 1 <= m <= 255
+ * (m <= 63 for d = 3).  M: device complex128, (4m+1)^d entries, as fk_gram writes it;
+ * x, y: device complex128 [nvec][N], N = (2m+1)^d, not overlapping.
+ * Workspace: fk_toeplitz_apply_workspace_size bytes of device memory, owned by the caller.
+ *
+ * fk_solve_cg: all nlam x ntgt systems, lambda_l > 0, iterate together from theta = 0 with
+ * the Jacobi preconditioner M[0] + lambda_l p_k; system (l, t) stops at the first
+ * iteration where the recursively updated residual has ||r|| <= tol ||b_t||
+ * (0 < tol < 1), or after maxit iterations.  A zero right-hand side gives theta = 0 in 0
+ * iterations.  P must be diagonal: FK_PEN_SOBOLEV, _SOBOLEV_BESSEL, _IDENTITY or _DIAG (NULL
+ * = FK_PEN_SOBOLEV with s = 1); FK_PEN_HEAT_BOX returns FK_EINVAL (use fk_solve).
+ * M, b, theta_out: device, layouts as in fk_solve (theta_out [nlam][ntgt][N]).
+ * iters (host, may be NULL): iterations of the slowest system.  relres (host, nlam x ntgt
+ * doubles, may be NULL): final ||b - A theta|| / ||b|| recomputed with one more product.
+ * ntgt * nlam <= 65536.  The call synchronises the context's stream every 4 iterations.
+ * Returns FK_ENOCONV when some system has not met tol after maxit iterations (theta_out then
+ * holds the last iterates), FK_ENOTPD when <p, A p> <= 0 for some system (A not positive
+ * definite in FP64), FK_EINVAL when the centre M[0] is not positive. */
+fk_status fk_toeplitz_apply_workspace_size(fk_ctx* ctx, int d, int m, int nvec, size_t* bytes);
+fk_status fk_toeplitz_apply(fk_ctx* ctx, int d, int m, const double* M, int nvec, const double* x,
+                            double* y, void* ws, size_t ws_bytes);
+fk_status fk_solve_cg_workspace_size(fk_ctx* ctx, int d, int m, int ntgt, int nlam, size_t* bytes);
+fk_status fk_solve_cg(fk_ctx* ctx, int d, int m, const double* M, int ntgt, const double* b,
+                      const double* lambdas, int nlam, const fk_penalty* pen, double tol, int maxit,
+                      double* theta_out, int* iters, double* relres, void* ws, size_t ws_bytes);
+
 /* fk_fit = fk_gram followed by fk_solve (one workspace holding both). */
 fk_status fk_fit_workspace_size(fk_ctx* ctx, int d, int64_t n, int ntgt, int m, int nlam,
                                 size_t* bytes);

@@ -40,7 +40,7 @@ from .fourier import (modes, gram_generator, rhs, fourier_entry, toeplitz_matrix
 from .penalty import (sobolev_weights, sobolev_bessel_weights, piml_box_fourier_matrix,
                       heat_symbol, piml_heat_penalty, additive_penalty)
 from .solve import system_matrix, solve_system, condition_number, fit
-from .cg import toeplitz_apply, pcg
+from .cg import toeplitz_apply, toeplitz_apply_rows, pcg
 from .predict import predict, predict_additive
 from .krr import krr_theta
 from .grad import heldout_mse, heldout_mse_quadratic, mse_gradients
@@ -50,7 +50,7 @@ __all__ = [
     "additive_blocks", "additive_rhs",
     "sobolev_weights", "sobolev_bessel_weights", "piml_box_fourier_matrix", "heat_symbol",
     "piml_heat_penalty", "additive_penalty",
-    "system_matrix", "solve_system", "condition_number", "fit", "toeplitz_apply", "pcg",
+    "system_matrix", "solve_system", "condition_number", "fit", "toeplitz_apply", "toeplitz_apply_rows", "pcg",
     "predict", "predict_additive", "krr_theta",
     "heldout_mse", "heldout_mse_quadratic", "mse_gradients",
 ]

@@ -17,7 +17,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .fourier import toeplitz_matrix
+from .fourier import modes, toeplitz_matrix
 
 
 def toeplitz_apply(M: np.ndarray, x: np.ndarray, m: int) -> np.ndarray:
@@ -27,6 +27,19 @@ def toeplitz_apply(M: np.ndarray, x: np.ndarray, m: int) -> np.ndarray:
     S = toeplitz_matrix(M, m)
     x = np.asarray(x, dtype=np.complex128)
     return x @ S.T if x.ndim == 2 else S @ x
+
+
+def toeplitz_apply_rows(M: np.ndarray, x: np.ndarray, m: int, rows) -> np.ndarray:
+    """Selected entries y[k] = sum_l M[l - k] x[l] of Sigma x, one row at a time, for inputs
+    too large for the dense matrix.  rows are flat mode indices; x is [N]."""
+    d = M.ndim
+    ks = modes(m, d)
+    x = np.asarray(x, dtype=np.complex128)
+    out = np.empty(len(rows), dtype=np.complex128)
+    for i, r in enumerate(rows):
+        diff = ks - ks[r] + 2 * m                       # l - k, shifted to 0..4m
+        out[i] = np.sum(M[tuple(diff[:, a] for a in range(d))] * x)
+    return out
 
 
 def pcg(A: np.ndarray, b: np.ndarray, dg: np.ndarray, tol: float, maxit: int):

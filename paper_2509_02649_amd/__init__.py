@@ -22,7 +22,7 @@ import torch
 from . import _lib
 from ._lib import FkError, fk_fit_info, fk_penalty, fk_options, FK_F32, FK_F64, PEN
 
-__all__ = ["Context", "gram", "solve", "fit", "predict", "heldout_mse", "fit_backward", "additive_gram",
+__all__ = ["Context", "gram", "solve", "solve_cg", "toeplitz_apply", "fit", "predict", "heldout_mse", "fit_backward", "additive_gram",
            "additive_fit", "generate_uniform", "generate_targets", "KernelRidgeGridLoss", "FkError"]
 
 
@@ -158,6 +158,55 @@ def solve(M: torch.Tensor, b: torch.Tensor, m: int, lambdas: Sequence[float], pe
     del keep
     th = torch.view_as_complex(theta)
     return (th, inf.as_dict()) if info else th
+
+
+def toeplitz_apply(M: torch.Tensor, x: torch.Tensor, m: int, ctx: Optional[Context] = None) -> torch.Tensor:
+    """y = Sigma x for Sigma[k, l] = M[l - k] by FFT; x [V, N] complex128 on the device."""
+    ctx = ctx or default_context(M.device.index or 0)
+    ctx.bind_stream()
+    d = M.dim()
+    Mr = torch.view_as_real(M.contiguous()).contiguous()
+    xr = torch.view_as_real(x.reshape(-1, _modes(m, d)).contiguous()).contiguous()
+    V = xr.shape[0]
+    nb = C.c_size_t()
+    _lib.check(ctx.lib.fk_toeplitz_apply_workspace_size(ctx.h, d, m, V, C.byref(nb)),
+               "fk_toeplitz_apply_workspace_size")
+    ws = ctx.workspace(nb.value)
+    y = torch.empty_like(xr)
+    _lib.check(ctx.lib.fk_toeplitz_apply(ctx.h, d, m, _ptr(Mr), V, _ptr(xr), _ptr(y), _ptr(ws), nb.value),
+               "fk_toeplitz_apply")
+    return torch.view_as_complex(y).reshape(x.shape)
+
+
+def solve_cg(M: torch.Tensor, b: torch.Tensor, m: int, lambdas: Sequence[float], penalty: str = "sobolev",
+             s: float = 1.0, tol: float = 1e-10, maxit: int = 1000, ctx: Optional[Context] = None,
+             info: bool = False, **pen_kw):
+    """theta [nlam, T, N] complex128 by Jacobi-preconditioned conjugate gradients with FFT products.
+
+    With info=True also returns {"iters": iterations of the slowest system,
+    "relres": [nlam, T] final ||b - A theta|| / ||b||}."""
+    ctx = ctx or default_context(M.device.index or 0)
+    ctx.bind_stream()
+    d = M.dim()
+    Mr = torch.view_as_real(M.contiguous()).contiguous()
+    br = torch.view_as_real(b.contiguous()).contiguous()
+    T = b.shape[0]
+    lams = (C.c_double * len(lambdas))(*[float(v) for v in lambdas])
+    nlam = len(lambdas)
+    nb = C.c_size_t()
+    _lib.check(ctx.lib.fk_solve_cg_workspace_size(ctx.h, d, m, T, nlam, C.byref(nb)), "fk_solve_cg_workspace_size")
+    ws = ctx.workspace(nb.value)
+    theta = torch.empty((nlam, T, _modes(m, d), 2), dtype=torch.float64, device=M.device)
+    pen, keep = _penalty(penalty, s, **pen_kw)
+    it = C.c_int()
+    rel = (C.c_double * (nlam * T))()
+    _lib.check(ctx.lib.fk_solve_cg(ctx.h, d, m, _ptr(Mr), T, _ptr(br), lams, nlam, C.byref(pen), float(tol),
+                                   int(maxit), _ptr(theta), C.byref(it), rel, _ptr(ws), nb.value), "fk_solve_cg")
+    del keep
+    th = torch.view_as_complex(theta)
+    if info:
+        return th, {"iters": it.value, "relres": [[rel[l * T + t] for t in range(T)] for l in range(nlam)]}
+    return th
 
 
 def fit(X: torch.Tensor, Y: torch.Tensor, m: int, lambdas, penalty: str = "sobolev", s: float = 1.0,

@@ -58,6 +58,14 @@ EXPORTS = {
     "fk_solve": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.POINTER(C.c_double),
                            C.c_int, C.POINTER(fk_penalty), C.c_void_p, C.c_void_p, C.c_size_t,
                            C.POINTER(fk_fit_info)]),
+    "fk_toeplitz_apply_workspace_size": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_size_t)]),
+    "fk_toeplitz_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_size_t]),
+    "fk_solve_cg_workspace_size": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int,
+                                             C.POINTER(C.c_size_t)]),
+    "fk_solve_cg": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.POINTER(C.c_double),
+                              C.c_int, C.POINTER(fk_penalty), C.c_double, C.c_int, C.c_void_p,
+                              C.POINTER(C.c_int), C.POINTER(C.c_double), C.c_void_p, C.c_size_t]),
     "fk_fit_workspace_size": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int, C.c_int, C.c_int,
                                         C.POINTER(C.c_size_t)]),
     "fk_fit": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_int,

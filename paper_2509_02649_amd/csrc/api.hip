@@ -27,7 +27,7 @@ extern "C" fk_status fk_create(fk_ctx** ctx, int device, void* hip_stream) {
   c->opt.max_refine = 8;
   c->opt.refine_tol = 1e-10;
   if (hipMalloc(&c->flags, sizeof(int) * kFlagCount) != hipSuccess ||
-      hipHostMalloc(&c->flags_host, sizeof(int) * kFlagCount, hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc(&c->flags_host, sizeof(int) * 2 * kFlagCount, hipHostMallocDefault) != hipSuccess) {
     delete c;
     return FK_EHIP;
   }
@@ -305,6 +305,53 @@ extern "C" fk_status fk_solve(fk_ctx* ctx, int d, int m, const double* M, int nt
   if (st == FK_OK) st = solve_impl(ctx, P, s, theta_out, info);
   if (info) info->status = st;
   return st;
+}
+
+// ---------------------------------------------------------------- iterative solve
+
+extern "C" fk_status fk_toeplitz_apply_workspace_size(fk_ctx* ctx, int d, int m, int nvec, size_t* bytes) {
+  if (!bytes || !toeplitz_fft_ok(d, m) || nvec < 1) return FK_EINVAL;
+  *bytes = toeplitz_apply_workspace(d, m, nvec);
+  return FK_OK;
+}
+
+extern "C" fk_status fk_toeplitz_apply(fk_ctx* ctx, int d, int m, const double* M, int nvec, const double* x,
+                                       double* y, void* ws, size_t ws_bytes) {
+  if (!ctx || !M || !x || !y || !toeplitz_fft_ok(d, m) || nvec < 1) return FK_EINVAL;
+  if (!ws || ws_bytes < toeplitz_apply_workspace(d, m, nvec)) return FK_ENOMEM;
+  FK_HIP(hipSetDevice(ctx->device));
+  Carve cv(ws, ws_bytes);
+  return toeplitz_apply_impl(ctx, d, m, M, nvec, x, y, cv);
+}
+
+static bool cg_shape_ok(int d, int m, int ntgt, int nlam) {
+  return toeplitz_fft_ok(d, m) && ntgt >= 1 && nlam >= 1 && nlam <= 1024 && (int64_t)ntgt * nlam <= 65536;
+}
+
+extern "C" fk_status fk_solve_cg_workspace_size(fk_ctx* ctx, int d, int m, int ntgt, int nlam, size_t* bytes) {
+  if (!bytes || !cg_shape_ok(d, m, ntgt, nlam)) return FK_EINVAL;
+  *bytes = cg_workspace(d, m, ntgt * nlam, nlam);
+  return FK_OK;
+}
+
+extern "C" fk_status fk_solve_cg(fk_ctx* ctx, int d, int m, const double* M, int ntgt, const double* b,
+                                 const double* lambdas, int nlam, const fk_penalty* pen, double tol, int maxit,
+                                 double* theta_out, int* iters, double* relres, void* ws, size_t ws_bytes) {
+  if (!ctx || !M || !b || !theta_out || !lambdas || !cg_shape_ok(d, m, ntgt, nlam)) return FK_EINVAL;
+  if (!(tol > 0.0) || !(tol < 1.0) || maxit < 1 || maxit > 1000000) return FK_EINVAL;
+  if (pen && pen->kind == FK_PEN_HEAT_BOX) return FK_EINVAL;   // dense penalty: use fk_solve
+  std::vector<double> pw;
+  fk_status st = penalty_weights(pen, d, m, pw);
+  if (st != FK_OK) return st;
+  std::vector<double> lams(lambdas, lambdas + nlam);
+  for (double l : lams)
+    if (!(l > 0.0) || std::isinf(l)) return FK_EINVAL;
+  if (!ws || ws_bytes < cg_workspace(d, m, ntgt * nlam, nlam)) return FK_ENOMEM;
+  FK_HIP(hipSetDevice(ctx->device));
+  st = reset_flags(ctx);
+  if (st != FK_OK) return st;
+  Carve cv(ws, ws_bytes);
+  return cg_solve_impl(ctx, d, m, M, ntgt, b, lams, pw, tol, maxit, theta_out, iters, relres, cv);
 }
 
 static size_t fit_ws(int d, int64_t n, int ntgt, int m, int nlam) {

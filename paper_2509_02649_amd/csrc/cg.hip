@@ -1,0 +1,511 @@
+// Conjugate-gradient solve of (Sigma + lambda P) theta = b with the multilevel-Toeplitz
+// product done by FFT (Sec. 2.3, "Matrix inversion" and "Covariance matrix").
+//
+// Product.  Sigma[k, l] = M[l - k] over k, l in {-m..m}^d.  With mode k stored at
+// position k + m (0..2m) per axis, (Sigma x)[k] = sum_l c[(k + m) - (l + m)] x[l] with
+// c[r] = M[-r], r in [-2m, 2m]^d: a d-dimensional linear convolution, exact as a cyclic one
+// of length Lf >= 4m + 1 per axis (Lf a power of two).  The spectrum FFT(c) / Lf^d is built
+// once per generator.  A product then runs axis by axis over a batch of vectors:
+//   axes 0..d-2 forward (n0 = 2m+1 inputs zero-padded to Lf, all Lf outputs kept),
+//   axis d-1 forward, times the spectrum, inverse (n0 in, n0 out),
+//   axes d-2..0 inverse (Lf in, the n0 outputs at positions 0..2m kept).
+// Forward transforms are decimation in frequency (natural order in, bit-reversed out) and
+// inverse ones decimation in time (bit-reversed in, natural out), so no pass reorders: the
+// spectrum and every intermediate hold frequencies in bit-reversed order.
+//
+// One wave transforms one line in LDS (radix 2, FP64, twiddles tabled per workgroup).
+//
+// CG.  All nlam x ntgt systems iterate together, one workgroup per system for the vector
+// updates; a system leaves the iteration (its lines and updates are skipped) once its
+// recursive residual meets the tolerance.
+#include "fk_internal.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace fk {
+namespace {
+
+constexpr int FT = 256;          // threads per line-FFT workgroup
+constexpr int FLINES = FT / 64;  // lines per workgroup, one wave each
+constexpr int FMAX = 1024;       // longest line
+constexpr int CT = 256;          // threads per CG system workgroup
+
+enum LineMode { kForward = 0, kInverse = 1, kConvolve = 2 };
+
+// One pass over one axis of a batch of row-major arrays.  Line li of a system covers
+// elements o * (n * inner) + i + t * inner, t < n, for o = li / inner, i = li % inner
+// (n = nin on input, nout on output).
+struct LinePass {
+  const double2* in;
+  double2* out;
+  int64_t in_sys, out_sys;   // complex elements per system
+  int64_t lines_per_sys;
+  int64_t inner;
+  int nin, nout;
+  int mode;
+  const double2* spec;       // kConvolve: spectrum lines of Lf entries, line o at o * Lf
+  double spec_scale;
+};
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Decimation in frequency, natural order in, bit-reversed order out, e^{-2 pi i / L}.
+__device__ __forceinline__ void dif_forward(double2* B, const double2* tw, int L, int lane) {
+  for (int len = L, step = 1; len >= 2; len >>= 1, step <<= 1) {
+    const int half = len >> 1;
+    for (int t = lane; t < L / 2; t += 64) {
+      const int grp = t / half, pos = t - grp * half;
+      const int i = grp * len + pos, j = i + half;
+      const double2 u = B[i], v = B[j];
+      B[i] = make_double2(u.x + v.x, u.y + v.y);
+      B[j] = cmul(make_double2(u.x - v.x, u.y - v.y), tw[pos * step]);
+    }
+    __syncthreads();
+  }
+}
+
+// Decimation in time, bit-reversed order in, natural order out, e^{+2 pi i / L}
+// (unnormalised inverse).
+__device__ __forceinline__ void dit_inverse(double2* B, const double2* tw, int L, int lane) {
+  for (int len = 2, step = L / 2; len <= L; len <<= 1, step >>= 1) {
+    const int half = len >> 1;
+    for (int t = lane; t < L / 2; t += 64) {
+      const int grp = t / half, pos = t - grp * half;
+      const int i = grp * len + pos, j = i + half;
+      const double2 w = tw[pos * step];
+      const double2 u = B[i], v = cmul(B[j], make_double2(w.x, -w.y));
+      B[i] = make_double2(u.x + v.x, u.y + v.y);
+      B[j] = make_double2(u.x - v.x, u.y - v.y);
+    }
+    __syncthreads();
+  }
+}
+
+// Dynamic LDS: FLINES lines of L entries, then L / 2 twiddles.
+__global__ __launch_bounds__(FT) void k_line_fft(LinePass a, int L, int64_t nlines, const int* __restrict__ active) {
+  extern __shared__ __align__(16) double2 lds[];
+  double2* tw = lds + FLINES * L;
+  for (int k = threadIdx.x; k < L / 2; k += FT) {
+    double s, c;
+    sincospi(-2.0 * k / L, &s, &c);
+    tw[k] = make_double2(c, s);
+  }
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t line = (int64_t)blockIdx.x * FLINES + wv;
+  bool live = line < nlines;
+  int64_t sys = 0, li = 0;
+  if (live) {
+    sys = line / a.lines_per_sys;
+    li = line - sys * a.lines_per_sys;
+    if (active && !active[sys]) live = false;
+  }
+  const int64_t o = li / a.inner, i = li - o * a.inner;
+  const double2* src = a.in + sys * a.in_sys + o * (a.nin * a.inner) + i;
+  double2* dst = a.out + sys * a.out_sys + o * (a.nout * a.inner) + i;
+  double2* B = lds + wv * L;
+  for (int t = lane; t < L; t += 64) B[t] = (live && t < a.nin) ? src[t * a.inner] : make_double2(0.0, 0.0);
+  __syncthreads();
+  if (a.mode != kInverse) dif_forward(B, tw, L, lane);
+  if (a.mode == kConvolve) {
+    const double2* S = a.spec + o * L;
+    for (int t = lane; t < L; t += 64) {
+      const double2 s = S[t];
+      B[t] = cmul(B[t], make_double2(s.x * a.spec_scale, s.y * a.spec_scale));
+    }
+    __syncthreads();
+  }
+  if (a.mode != kForward) dit_inverse(B, tw, L, lane);
+  if (live)
+    for (int t = lane; t < a.nout; t += 64) dst[t * a.inner] = B[t];
+}
+
+// c[j] = M[-r] at cyclic position j = r mod Lf, r in [-2m, 2m]^d; zero elsewhere.
+__global__ void k_embed(const double2* __restrict__ M, int d, int m, int L, int64_t total, double2* __restrict__ c) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int K = 4 * m + 1;
+  int64_t rem = e, midx = 0;
+  bool in = true;
+  for (int a = d - 1, mul = 1; a >= 0; --a) {
+    const int j = (int)(rem % L);
+    rem /= L;
+    const int r = j <= 2 * m ? j : (j >= L - 2 * m ? j - L : 1 << 30);
+    if (r == 1 << 30) in = false;
+    midx += (int64_t)(2 * m - r) * mul;   // index of M[-r]
+    mul *= K;
+  }
+  c[e] = in ? M[midx] : make_double2(0.0, 0.0);
+}
+
+// ------------------------------------------------------------------ CG vector updates
+
+__global__ void k_zero_int(int* __restrict__ v, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v[i] = 0;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int k = 0; k < CT / 64; ++k) s += red[k];
+  return s;
+}
+
+// theta = 0, r = b, z = r / dg, p = z, rho = <r, z>, bb = ||b||^2.  System s = l ntgt + t.
+__global__ __launch_bounds__(CT) void k_cg_init(const double2* __restrict__ b, int ntgt, int64_t N,
+                                                const double* __restrict__ lams, const double* __restrict__ pw,
+                                                double m0, double2* __restrict__ theta, double2* __restrict__ r,
+                                                double2* __restrict__ p, double* __restrict__ rho,
+                                                double* __restrict__ bb, int* __restrict__ active,
+                                                int* __restrict__ iters, int* __restrict__ nactive) {
+  __shared__ double red[CT / 64];
+  const int s = blockIdx.x;
+  const double lam = lams[s / ntgt];
+  const double2* bt = b + (int64_t)(s % ntgt) * N;
+  double2* th = theta + (int64_t)s * N;
+  double2* rs = r + (int64_t)s * N;
+  double2* ps = p + (int64_t)s * N;
+  double rz = 0.0, b2 = 0.0;
+  for (int64_t k = threadIdx.x; k < N; k += CT) {
+    const double2 v = bt[k];
+    const double inv = 1.0 / (m0 + lam * pw[k]);
+    th[k] = make_double2(0.0, 0.0);
+    rs[k] = v;
+    ps[k] = make_double2(v.x * inv, v.y * inv);
+    const double a = v.x * v.x + v.y * v.y;
+    b2 += a;
+    rz += a * inv;
+  }
+  rz = block_sum(rz, red);
+  b2 = block_sum(b2, red);
+  if (threadIdx.x == 0) {
+    rho[s] = rz;
+    bb[s] = b2;
+    iters[s] = 0;
+    const int on = b2 > 0.0;
+    active[s] = on;
+    if (on) atomicAdd(nactive, 1);
+  }
+}
+
+// One iteration for every active system, given qraw = Sigma p:
+//   q = qraw + lambda P p, alpha = rho / <p, q>, theta += alpha p, r -= alpha q,
+//   stop if ||r||^2 <= tol2 ||b||^2, else z = r / dg, beta = <r, z> / rho, p = z + beta p.
+// A non-positive <p, q> (the matrix is not positive definite in FP64) stops the system
+// and raises the not-positive-definite flag.
+__global__ __launch_bounds__(CT) void k_cg_step(const double2* __restrict__ qraw, int ntgt, int64_t N,
+                                                const double* __restrict__ lams, const double* __restrict__ pw,
+                                                double m0, double tol2, double2* __restrict__ theta,
+                                                double2* __restrict__ r, double2* __restrict__ p,
+                                                double* __restrict__ rho, const double* __restrict__ bb,
+                                                int* __restrict__ active, int* __restrict__ iters,
+                                                int* __restrict__ nactive, int* flags) {
+  __shared__ double red[CT / 64];
+  const int s = blockIdx.x;
+  if (!active[s]) return;
+  const double lam = lams[s / ntgt];
+  const double2* qs = qraw + (int64_t)s * N;
+  double2* th = theta + (int64_t)s * N;
+  double2* rs = r + (int64_t)s * N;
+  double2* ps = p + (int64_t)s * N;
+  const double rho0 = rho[s];
+  double pq = 0.0;
+  for (int64_t k = threadIdx.x; k < N; k += CT) {
+    const double2 pk = ps[k], qk = qs[k];
+    const double lp = lam * pw[k];
+    pq += pk.x * (qk.x + lp * pk.x) + pk.y * (qk.y + lp * pk.y);
+  }
+  pq = block_sum(pq, red);
+  if (!(pq > 0.0)) {
+    if (threadIdx.x == 0) {
+      active[s] = 0;
+      atomicSub(nactive, 1);
+      atomicOr(&flags[kFlagNotPD], 1);
+    }
+    return;
+  }
+  const double alpha = rho0 / pq;
+  double rr = 0.0, rz = 0.0;
+  for (int64_t k = threadIdx.x; k < N; k += CT) {
+    const double2 pk = ps[k], qk = qs[k];
+    const double lp = lam * pw[k];
+    double2 t = th[k], rk = rs[k];
+    t.x += alpha * pk.x;
+    t.y += alpha * pk.y;
+    rk.x -= alpha * (qk.x + lp * pk.x);
+    rk.y -= alpha * (qk.y + lp * pk.y);
+    th[k] = t;
+    rs[k] = rk;
+    const double a = rk.x * rk.x + rk.y * rk.y;
+    rr += a;
+    rz += a / (m0 + lp);
+  }
+  rr = block_sum(rr, red);
+  rz = block_sum(rz, red);
+  const int it = iters[s] + 1;
+  if (rr <= tol2 * bb[s]) {
+    if (threadIdx.x == 0) {
+      iters[s] = it;
+      active[s] = 0;
+      atomicSub(nactive, 1);
+    }
+    return;
+  }
+  const double beta = rz / rho0;
+  for (int64_t k = threadIdx.x; k < N; k += CT) {
+    const double inv = 1.0 / (m0 + lam * pw[k]);
+    const double2 rk = rs[k], pk = ps[k];
+    ps[k] = make_double2(rk.x * inv + beta * pk.x, rk.y * inv + beta * pk.y);
+  }
+  if (threadIdx.x == 0) {
+    rho[s] = rz;
+    iters[s] = it;
+  }
+}
+
+// relres[s] = ||b - (Sigma theta + lambda P theta)|| / ||b|| (0 when b = 0), from qraw = Sigma theta.
+__global__ __launch_bounds__(CT) void k_cg_resid(const double2* __restrict__ b, const double2* __restrict__ qraw,
+                                                 const double2* __restrict__ theta, int ntgt, int64_t N,
+                                                 const double* __restrict__ lams, const double* __restrict__ pw,
+                                                 const double* __restrict__ bb, double* __restrict__ relres) {
+  __shared__ double red[CT / 64];
+  const int s = blockIdx.x;
+  const double lam = lams[s / ntgt];
+  const double2* bt = b + (int64_t)(s % ntgt) * N;
+  const double2* qs = qraw + (int64_t)s * N;
+  const double2* th = theta + (int64_t)s * N;
+  double e = 0.0;
+  for (int64_t k = threadIdx.x; k < N; k += CT) {
+    const double lp = lam * pw[k];
+    const double rx = bt[k].x - qs[k].x - lp * th[k].x;
+    const double ry = bt[k].y - qs[k].y - lp * th[k].y;
+    e += rx * rx + ry * ry;
+  }
+  e = block_sum(e, red);
+  if (threadIdx.x == 0) relres[s] = bb[s] > 0.0 ? sqrt(e / bb[s]) : 0.0;
+}
+
+// ------------------------------------------------------------------ host side
+
+struct ToepGeom {
+  int d = 0, m = 0, n0 = 0, L = 0;
+  int64_t N = 0, spec = 0, tmp = 0;   // complex elements: modes, spectrum, one intermediate
+};
+
+ToepGeom toep_geom(int d, int m) {
+  ToepGeom g;
+  g.d = d;
+  g.m = m;
+  g.n0 = 2 * m + 1;
+  g.L = 2;
+  while (g.L < 4 * m + 1) g.L <<= 1;
+  g.N = 1;
+  g.spec = 1;
+  for (int a = 0; a < d; ++a) {
+    g.N *= g.n0;
+    g.spec *= g.L;
+  }
+  g.tmp = g.spec / g.L * g.n0;
+  return g;
+}
+
+fk_status run_pass(hipStream_t st, const ToepGeom& g, const int64_t* E, int axis, int nout, int mode,
+                   const double2* in, double2* out, int nsys, const double2* spec, double scale, const int* active) {
+  LinePass a;
+  a.in = in;
+  a.out = out;
+  int64_t lines = 1, inner = 1, tot = 1;
+  for (int b = 0; b < g.d; ++b) {
+    tot *= E[b];
+    if (b != axis) lines *= E[b];
+    if (b > axis) inner *= E[b];
+  }
+  a.in_sys = tot;
+  a.out_sys = tot / E[axis] * nout;
+  a.lines_per_sys = lines;
+  a.inner = inner;
+  a.nin = (int)E[axis];
+  a.nout = nout;
+  a.mode = mode;
+  a.spec = spec;
+  a.spec_scale = scale;
+  const int64_t nlines = lines * nsys;
+  const int64_t blocks = (nlines + FLINES - 1) / FLINES;
+  if (blocks > 0x7fffffff) return FK_EINVAL;
+  const size_t lds = sizeof(double2) * ((size_t)FLINES * g.L + g.L / 2);
+  hipLaunchKernelGGL(k_line_fft, dim3((unsigned)blocks), dim3(FT), lds, st, a, g.L, nlines, active);
+  return hipGetLastError() == hipSuccess ? FK_OK : FK_EHIP;
+}
+
+// spec = FFT_d(c) over the Lf^d grid (bit-reversed frequencies).  The passes run in place:
+// a line is read whole into LDS before any of it is written, and lines are disjoint.
+fk_status build_spectrum(hipStream_t st, const ToepGeom& g, const double* M, double2* spec) {
+  const int64_t total = g.spec;
+  hipLaunchKernelGGL(k_embed, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                     reinterpret_cast<const double2*>(M), g.d, g.m, g.L, total, spec);
+  int64_t E[3] = {g.L, g.L, g.L};
+  for (int a = 0; a < g.d; ++a) {
+    fk_status s = run_pass(st, g, E, a, g.L, kForward, spec, spec, 1, nullptr, 1.0, nullptr);
+    if (s != FK_OK) return s;
+  }
+  return FK_OK;
+}
+
+// y = Sigma x for nsys vectors (x, y: nsys x N), intermediates t0, t1 (nsys x g.tmp each).
+fk_status toep_apply(hipStream_t st, const ToepGeom& g, const double2* spec, const double2* x, double2* y,
+                     int nsys, double2* t0, double2* t1, const int* active) {
+  const double scale = 1.0 / (double)g.spec;
+  int64_t E[3] = {g.n0, g.n0, g.n0};
+  const double2* cur = x;
+  double2* bufs[2] = {t0, t1};
+  int nb = 0;
+  fk_status s = FK_OK;
+  for (int a = 0; a < g.d - 1 && s == FK_OK; ++a) {
+    s = run_pass(st, g, E, a, g.L, kForward, cur, bufs[nb], nsys, nullptr, 1.0, active);
+    E[a] = g.L;
+    cur = bufs[nb];
+    nb ^= 1;
+  }
+  if (s != FK_OK) return s;
+  double2* out = g.d == 1 ? y : bufs[nb];
+  s = run_pass(st, g, E, g.d - 1, g.n0, kConvolve, cur, out, nsys, spec, scale, active);
+  cur = out;
+  nb ^= 1;
+  for (int a = g.d - 2; a >= 0 && s == FK_OK; --a) {
+    out = a == 0 ? y : bufs[nb];
+    s = run_pass(st, g, E, a, g.n0, kInverse, cur, out, nsys, nullptr, 1.0, active);
+    E[a] = g.n0;
+    cur = out;
+    nb ^= 1;
+  }
+  return s;
+}
+
+}  // namespace
+
+bool toeplitz_fft_ok(int d, int m) {
+  if (d < 1 || d > 3 || m < 1) return false;
+  const int lim = d == 3 ? 63 : 255;   // Lf <= 256 in 3-D (a 268 MB spectrum), else <= 1024
+  return m <= lim && toep_geom(d, m).L <= FMAX;
+}
+
+size_t toeplitz_apply_workspace(int d, int m, int nvec) {
+  const ToepGeom g = toep_geom(d, m);
+  Carve cv(nullptr, 0);
+  cv.take<double2>((size_t)g.spec);
+  cv.take<double2>((size_t)nvec * g.tmp);
+  cv.take<double2>((size_t)nvec * g.tmp);
+  return cv.off + 256;
+}
+
+fk_status toeplitz_apply_impl(fk_ctx* ctx, int d, int m, const double* M, int nvec, const double* x, double* y,
+                              Carve& cv) {
+  const ToepGeom g = toep_geom(d, m);
+  double2* spec = cv.take<double2>((size_t)g.spec);
+  double2* t0 = cv.take<double2>((size_t)nvec * g.tmp);
+  double2* t1 = cv.take<double2>((size_t)nvec * g.tmp);
+  if (!cv.ok()) return FK_ENOMEM;
+  fk_status s = build_spectrum(ctx->stream, g, M, spec);
+  if (s != FK_OK) return s;
+  return toep_apply(ctx->stream, g, spec, reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), nvec,
+                    t0, t1, nullptr);
+}
+
+size_t cg_workspace(int d, int m, int nsys, int nlam) {
+  const ToepGeom g = toep_geom(d, m);
+  Carve cv(nullptr, 0);
+  cv.take<double2>((size_t)g.spec);
+  cv.take<double2>((size_t)nsys * g.tmp);
+  cv.take<double2>((size_t)nsys * g.tmp);
+  for (int k = 0; k < 3; ++k) cv.take<double2>((size_t)nsys * g.N);   // r, p, qraw
+  cv.take<double>((size_t)g.N);                                          // penalty weights
+  cv.take<double>((size_t)nlam);
+  for (int k = 0; k < 3; ++k) cv.take<double>((size_t)nsys);            // rho, bb, relres
+  for (int k = 0; k < 2; ++k) cv.take<int>((size_t)nsys);               // active, iters
+  cv.take<int>(64);                                                      // counter
+  return cv.off + 256;
+}
+
+fk_status cg_solve_impl(fk_ctx* ctx, int d, int m, const double* M, int ntgt, const double* b,
+                        const std::vector<double>& lams, const std::vector<double>& pw, double tol, int maxit,
+                        double* theta_out, int* iters_out, double* relres_out, Carve& cv) {
+  const ToepGeom g = toep_geom(d, m);
+  const int nlam = (int)lams.size();
+  const int nsys = nlam * ntgt;
+  hipStream_t st = ctx->stream;
+  double2* spec = cv.take<double2>((size_t)g.spec);
+  double2* t0 = cv.take<double2>((size_t)nsys * g.tmp);
+  double2* t1 = cv.take<double2>((size_t)nsys * g.tmp);
+  double2* r = cv.take<double2>((size_t)nsys * g.N);
+  double2* p = cv.take<double2>((size_t)nsys * g.N);
+  double2* q = cv.take<double2>((size_t)nsys * g.N);
+  double* dpw = cv.take<double>((size_t)g.N);
+  double* dlam = cv.take<double>((size_t)nlam);
+  double* rho = cv.take<double>((size_t)nsys);
+  double* bb = cv.take<double>((size_t)nsys);
+  double* relres = cv.take<double>((size_t)nsys);
+  int* active = cv.take<int>((size_t)nsys);
+  int* iters = cv.take<int>((size_t)nsys);
+  int* counter = cv.take<int>(64);
+  if (!cv.ok()) return FK_ENOMEM;
+  double2* theta = reinterpret_cast<double2*>(theta_out);
+  const double2* bv = reinterpret_cast<const double2*>(b);
+
+  // the diagonal of Sigma is M[0] (the centre of the generator), real for a Hermitian Sigma
+  double2 m0c;
+  int64_t centre = 0;
+  for (int a = 0, mul = 1; a < d; ++a, mul *= 4 * m + 1) centre += (int64_t)(2 * m) * mul;
+  FK_HIP(hipMemcpyAsync(&m0c, M + 2 * centre, sizeof(double2), hipMemcpyDeviceToHost, st));
+  FK_HIP(hipMemcpyAsync(dpw, pw.data(), sizeof(double) * g.N, hipMemcpyHostToDevice, st));
+  FK_HIP(hipMemcpyAsync(dlam, lams.data(), sizeof(double) * nlam, hipMemcpyHostToDevice, st));
+  FK_HIP(hipStreamSynchronize(st));
+  const double m0 = m0c.x;
+  if (!(m0 > 0.0) || std::isinf(m0)) return FK_EINVAL;
+
+  fk_status s = build_spectrum(st, g, M, spec);
+  if (s != FK_OK) return s;
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, counter, 64);
+  hipLaunchKernelGGL(k_cg_init, dim3(nsys), dim3(CT), 0, st, bv, ntgt, g.N, dlam, dpw, m0, theta, r, p, rho, bb,
+                     active, iters, counter);
+  const double tol2 = tol * tol;
+  int done_it = 0;
+  int nact = 1;
+  constexpr int kCheck = 4;   // iterations between reads of the active count
+  while (done_it < maxit && nact > 0) {
+    const int run = std::min(kCheck, maxit - done_it);
+    for (int k = 0; k < run; ++k) {
+      s = toep_apply(st, g, spec, p, q, nsys, t0, t1, active);
+      if (s != FK_OK) return s;
+      hipLaunchKernelGGL(k_cg_step, dim3(nsys), dim3(CT), 0, st, q, ntgt, g.N, dlam, dpw, m0, tol2, theta, r, p,
+                         rho, bb, active, iters, counter, ctx->flags);
+    }
+    done_it += run;
+    FK_HIP(hipMemcpyAsync(ctx->flags_host + kFlagCount, counter, sizeof(int), hipMemcpyDeviceToHost, st));
+    FK_HIP(hipStreamSynchronize(st));
+    nact = ctx->flags_host[kFlagCount];
+  }
+  // true residuals from one more product
+  s = toep_apply(st, g, spec, theta, q, nsys, t0, t1, nullptr);
+  if (s != FK_OK) return s;
+  hipLaunchKernelGGL(k_cg_resid, dim3(nsys), dim3(CT), 0, st, bv, q, theta, ntgt, g.N, dlam, dpw, bb, relres);
+  std::vector<int> it_h(nsys);
+  FK_HIP(hipMemcpyAsync(it_h.data(), iters, sizeof(int) * nsys, hipMemcpyDeviceToHost, st));
+  if (relres_out) FK_HIP(hipMemcpyAsync(relres_out, relres, sizeof(double) * nsys, hipMemcpyDeviceToHost, st));
+  FK_HIP(hipStreamSynchronize(st));
+  if (iters_out) {
+    int mx = 0;
+    for (int v : it_h) mx = std::max(mx, v);
+    *iters_out = mx;
+  }
+  s = read_flags(ctx);
+  if (s != FK_OK) return s;
+  return nact > 0 ? FK_ENOCONV : FK_OK;
+}
+
+}  // namespace fk

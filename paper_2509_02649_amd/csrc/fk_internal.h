@@ -142,7 +142,7 @@ struct fk_ctx {
   hipStream_t stream = nullptr;
   fk_options opt{};
   int* flags = nullptr;           // device, fk::kFlagCount ints
-  int* flags_host = nullptr;      // pinned host mirror
+  int* flags_host = nullptr;      // pinned host mirror (kFlagCount ints), then kFlagCount words for counters
   hipEvent_t ev[16] = {};
   // cached deconvolution tables keyed by (K, eps bits)
   std::map<std::pair<int, uint64_t>, std::pair<fk::EsPlan, double*>> es_cache;
@@ -161,4 +161,15 @@ size_t type1_workspace(int d, int64_t n, int nw, int K, double eps);
 fk_status type1(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int64_t xstride,
                 int nw, const void* Y, int K, double sign_scale, double* out,
                 Carve& cv, fk_fit_info* info);
+
+// Multilevel-Toeplitz product by FFT and the conjugate-gradient solve (cg.hip).
+// pw: complex-mode diagonal penalty weights (N, host); theta_out: nlam x ntgt x N complex.
+bool toeplitz_fft_ok(int d, int m);
+size_t toeplitz_apply_workspace(int d, int m, int nvec);
+fk_status toeplitz_apply_impl(fk_ctx* ctx, int d, int m, const double* M, int nvec, const double* x, double* y,
+                              Carve& cv);
+size_t cg_workspace(int d, int m, int nsys, int nlam);
+fk_status cg_solve_impl(fk_ctx* ctx, int d, int m, const double* M, int ntgt, const double* b,
+                        const std::vector<double>& lams, const std::vector<double>& pw, double tol, int maxit,
+                        double* theta_out, int* iters_out, double* relres_out, Carve& cv);
 }  // namespace fk

@@ -65,6 +65,16 @@ def test_workspace_queries_and_host_validation(lib):
     assert L.fk_predict_workspace_size(None, 2, 32, 1, C.byref(nb)) == 0
     assert L.fk_additive_fit_workspace_size(None, 10, 1000, 1, 32, 1, C.byref(nb)) == 0
     assert L.fk_additive_gram_workspace_size(None, 1, 1000, 1, 32, C.byref(nb)) == 1   # d = 1 rejected
+    # iterative solve: spectrum Lf^d, two intermediates Lf^(d-1) (2m+1) and three vectors per system
+    assert L.fk_solve_cg_workspace_size(None, 2, 32, 16, 64, C.byref(nb)) == 0
+    assert nb.value >= 256 * 256 * 16 + 2 * 1024 * 256 * 65 * 16 + 3 * 1024 * 65 * 65 * 16
+    assert L.fk_solve_cg_workspace_size(None, 3, 16, 1, 1, C.byref(nb)) == 0
+    assert L.fk_solve_cg_workspace_size(None, 3, 64, 1, 1, C.byref(nb)) == 1        # 3-D m > 63 rejected
+    assert L.fk_solve_cg_workspace_size(None, 2, 256, 1, 1, C.byref(nb)) == 1       # Lf > 1024 rejected
+    assert L.fk_solve_cg_workspace_size(None, 4, 4, 1, 1, C.byref(nb)) == 1         # d = 4 rejected
+    assert L.fk_solve_cg_workspace_size(None, 2, 8, 1024, 128, C.byref(nb)) == 1    # > 65536 systems
+    assert L.fk_toeplitz_apply_workspace_size(None, 1, 255, 3, C.byref(nb)) == 0
+    assert L.fk_toeplitz_apply_workspace_size(None, 1, 8, 0, C.byref(nb)) == 1      # no vectors
     # entry points reject a null context before touching the device
     assert L.fk_gram(None, 1, 10, 0, C.c_void_p(1), 0, None, 4, C.c_void_p(1), None, C.c_void_p(1), 1 << 20,
                      None) == 1

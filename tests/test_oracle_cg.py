@@ -20,6 +20,18 @@ def test_toeplitz_apply_is_design_matrix_product(d, m, n):
     np.testing.assert_allclose(oracle.toeplitz_apply(M, x[1], m), want[1], atol=1e-12)
 
 
+def test_toeplitz_rows_match_dense_product():
+    rng = np.random.default_rng(11)
+    for d, m in [(1, 6), (2, 3), (3, 2)]:
+        X = rng.uniform(-np.pi, np.pi, size=(d, 17))
+        M = oracle.gram_generator(X, m)
+        N = (2 * m + 1) ** d
+        x = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+        rows = rng.choice(N, 5, replace=False)
+        np.testing.assert_allclose(oracle.toeplitz_apply_rows(M, x, m, rows),
+                                   oracle.toeplitz_apply(M, x, m)[rows], atol=1e-13)
+
+
 def test_toeplitz_apply_planted_transpose_is_caught():
     # Sigma[k, l] = M[l - k]; the transposed reading M[k - l] gives the conjugate matrix,
     # which the design-matrix route tells apart for a non-symmetric sample.
