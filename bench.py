@@ -10,6 +10,9 @@ already resident in HBM:
             factorizations with FP64 refinement, held-out (n_v = 1e7) Gram and MSE,
             and the backward pass (adjoint solves, d/dlog lambda and d/dp).
   sobolev2d 2-D Sobolev, n = 1e7, one target, one lambda: type-1 stage + solve.
+  cg        the batched inputs (n = 1e9, 16 targets, m = 32, 64 lambdas, s = 2 Sobolev
+            weights): type-1 Gram + right-hand sides, then all 1024 systems by
+            Jacobi-preconditioned conjugate gradients with FFT Toeplitz products (tol 1e-10).
 Prints one JSON line.  value = n / (seconds per step) = whole-step points/s.
 """
 from __future__ import annotations
@@ -34,7 +37,7 @@ def _cpu_baseline(workload: str, ntgt: int, m: int):
     import oracle
     import synth
     threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
-    if workload == "batched":
+    if workload in ("batched", "cg"):
         n = 1_500_000
         X = synth.uniform_points(synth.SEED_BASE + 5, 2, n)
         Y = synth.batched_targets(X, synth.SEED_BASE + 5, ntgt)
@@ -72,12 +75,37 @@ def _traffic(kernel: str, n: int):
     return float(b.group(1)) * n
 
 
+def _fft_roofline(fk, torch, M, m, nvec, ctx, reps=5):
+    """FFT Toeplitz product over nvec vectors (the per-iteration product of the CG solve), timed
+    with HIP events on the library's stream.  Algorithmic bytes per call (2-D): every vector read
+    and written once (2 N complex), the two intermediates of Lf x (2m+1) entries written and read
+    once each (4 Lf (2m+1)), and the Lf^2 spectrum read once."""
+    N, n0 = (2 * m + 1) ** 2, 2 * m + 1
+    Lf = 1
+    while Lf < 4 * m + 1:
+        Lf <<= 1
+    x = torch.randn(nvec, N, dtype=torch.complex128, device=M.device)
+    fk.toeplitz_apply(M, x, m, ctx=ctx)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        fk.toeplitz_apply(M, x, m, ctx=ctx)
+    e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = 16.0 * (nvec * (2 * N + 4 * Lf * n0) + Lf * Lf)
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": "k_line_fft", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "ms_per_product": ms, "vectors": nvec}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="batched", choices=["batched", "sobolev2d"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "sobolev2d", "cg"])
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate", action="store_true",
@@ -96,7 +124,7 @@ def main():
     m = 32
     ctx = fk.Context(0)
     vctx = fk.Context(0)
-    if args.workload == "batched":
+    if args.workload in ("batched", "cg"):
         n = args.n or 1_000_000_000
         nv = 10_000_000
         ntgt, nlam = 16, 64
@@ -126,9 +154,18 @@ def main():
         del a, b
 
     infos = []
+    cg_iters = []
+    last = {}
+    CG_TOL = 1e-10
 
     def step():
-        if args.workload == "batched":
+        if args.workload == "cg":
+            M, b, info = fk.gram(X, Y, m, ctx=ctx, info=True)
+            theta, cinf = fk.solve_cg(M, b, m, lams, penalty="sobolev", s=2.0, tol=CG_TOL, ctx=ctx, info=True)
+            last["M"] = M
+            infos.append(info)
+            cg_iters.append(cinf["iters"])
+        elif args.workload == "batched":
             loglam = torch.tensor(np.log(lams), dtype=torch.float64, device=dev, requires_grad=True)
             p = p0.clone().requires_grad_(True)
             theta, info = fk.fit(X, Y, m, lams, penalty="diag", p=p.detach(), ctx=ctx, info=True)
@@ -153,9 +190,9 @@ def main():
 
     spread_ms = float(np.mean([i["spread_kernel_ms"] for i in infos]))
     gr_ms = float(np.mean([i["t_sort_ms"] + i["t_spread_ms"] + i["t_fft_ms"] for i in infos]))
-    fit_ms = float(np.mean([i["t_total_ms"] for i in infos]))
+    fit_ms = float(np.mean([i["t_total_ms"] for i in infos])) if args.workload != "cg" else dt * 1e3
     w = int(infos[-1]["w"])
-    if args.workload == "batched":
+    if args.workload in ("batched", "cg"):
         # dominant kernel: the MFMA spread; algorithmic work 2 w^2 (T + 1) flop per point
         # (every point adds its w x w kernel products to T target channels and the ones channel)
         kernel, bound, unit, peak = "k_spread_mfma", "mfma", "TFLOP/s", MFMA_F32_PEAK_TFLOPS
@@ -176,11 +213,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 spread / f64 grid+FFT / f32 MFMA Cholesky + f64 refinement",
+        "dtype": ("f32 spread / f64 grid+FFT / f64 conjugate gradients with f64 FFT products"
+                  if args.workload == "cg" else "f32 spread / f64 grid+FFT / f32 MFMA Cholesky + f64 refinement"),
         "data": "synthetic (Philox4x32-10 on device)",
         "config": {"workload": ("2-D Sobolev, n=%d fp32 ~U[-pi,pi)^2, %d targets sin(t x1)cos(x2)+N(0,0.01), "
                                 "m=32, %d lambdas, held-out n=1e7 MSE + backward" % (n, ntgt, nlam))
                    if args.workload == "batched" else
+                   ("2-D Sobolev, n=%d fp32 ~U[-pi,pi)^2, %d targets sin(t x1)cos(x2)+N(0,0.01), m=32, s=2, "
+                    "%d lambdas, conjugate gradients to ||r|| <= 1e-10 ||b||" % (n, ntgt, nlam))
+                   if args.workload == "cg" else
                    ("2-D Sobolev, n=%d fp32 ~U[-pi,pi)^2, Y=exp(-|x|^2)+N(0,0.01), m=32, s=2, lambda=n^-0.8"
                     % n),
                    "n": n, "m": m, "targets": ntgt, "lambdas": nlam},
@@ -196,6 +237,10 @@ def main():
     }
     if args.workload == "batched":
         out["grad_vs_fit_ratio"] = dt * 1e3 / fit_ms
+    if args.workload == "cg":
+        out["cg_iters"] = int(max(cg_iters))
+        out["cg_ms"] = dt * 1e3 - gr_ms
+        out["roofline_fft"] = _fft_roofline(fk, torch, last["M"], m, nlam * ntgt, ctx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(args.workload, ntgt, m)
     print(json.dumps(out))

@@ -13,7 +13,8 @@
 // inverse ones decimation in time (bit-reversed in, natural out), so no pass reorders: the
 // spectrum and every intermediate hold frequencies in bit-reversed order.
 //
-// One wave transforms one line in LDS (radix 2, FP64, twiddles tabled per workgroup).
+// One wave transforms one line in LDS (FP64, radix 4 with a radix-2 level when log2 Lf is
+// odd; the twiddle table is computed once per call and copied to LDS by each workgroup).
 //
 // CG.  All nlam x ntgt systems iterate together, one workgroup per system for the vector
 // updates; a system leaves the iteration (its lines and updates are skipped) once its
@@ -52,47 +53,85 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// Decimation in frequency, natural order in, bit-reversed order out, e^{-2 pi i / L}.
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+
+// Decimation in frequency, natural order in, bit-reversed order out, e^{-2 pi i / L}; tw[k] =
+// e^{-2 pi i k / L}, k < L / 2.  Two radix-2 levels per LDS round trip (lengths len and len / 2
+// over the four points pos, pos + len/4, pos + len/2, pos + 3 len/4 of a block), then a last
+// radix-2 level when log2 L is odd.
 __device__ __forceinline__ void dif_forward(double2* B, const double2* tw, int L, int lane) {
-  for (int len = L, step = 1; len >= 2; len >>= 1, step <<= 1) {
-    const int half = len >> 1;
+  int len = L, step = 1;
+  for (; len >= 4; len >>= 2, step <<= 2) {
+    const int q = len >> 2;
+    for (int t = lane; t < L / 4; t += 64) {
+      const int grp = t / q, pos = t - grp * q;
+      const int i0 = grp * len + pos, i1 = i0 + q, i2 = i1 + q, i3 = i2 + q;
+      const double2 a0 = B[i0], a1 = B[i1], a2 = B[i2], a3 = B[i3];
+      const double2 b0 = cadd(a0, a2), b2 = cmul(csub(a0, a2), tw[pos * step]);
+      const double2 b1 = cadd(a1, a3), b3 = cmul(csub(a1, a3), tw[(pos + q) * step]);
+      const double2 w = tw[pos * step * 2];
+      B[i0] = cadd(b0, b1);
+      B[i1] = cmul(csub(b0, b1), w);
+      B[i2] = cadd(b2, b3);
+      B[i3] = cmul(csub(b2, b3), w);
+    }
+    __syncthreads();
+  }
+  if (len == 2) {
     for (int t = lane; t < L / 2; t += 64) {
-      const int grp = t / half, pos = t - grp * half;
-      const int i = grp * len + pos, j = i + half;
-      const double2 u = B[i], v = B[j];
-      B[i] = make_double2(u.x + v.x, u.y + v.y);
-      B[j] = cmul(make_double2(u.x - v.x, u.y - v.y), tw[pos * step]);
+      const double2 u = B[2 * t], v = B[2 * t + 1];
+      B[2 * t] = cadd(u, v);
+      B[2 * t + 1] = csub(u, v);
     }
     __syncthreads();
   }
 }
 
-// Decimation in time, bit-reversed order in, natural order out, e^{+2 pi i / L}
-// (unnormalised inverse).
+// Decimation in time, bit-reversed order in, natural order out, e^{+2 pi i / L} (unnormalised
+// inverse): a first radix-2 level when log2 L is odd, then two levels per LDS round trip
+// (lengths len and 2 len over the points pos, pos + len/2, pos + len, pos + 3 len/2).
 __device__ __forceinline__ void dit_inverse(double2* B, const double2* tw, int L, int lane) {
-  for (int len = 2, step = L / 2; len <= L; len <<= 1, step >>= 1) {
-    const int half = len >> 1;
+  int len = 2, step = L / 2;
+  int lg = 0;
+  while ((1 << lg) < L) ++lg;
+  if (lg & 1) {
     for (int t = lane; t < L / 2; t += 64) {
-      const int grp = t / half, pos = t - grp * half;
-      const int i = grp * len + pos, j = i + half;
-      const double2 w = tw[pos * step];
-      const double2 u = B[i], v = cmul(B[j], make_double2(w.x, -w.y));
-      B[i] = make_double2(u.x + v.x, u.y + v.y);
-      B[j] = make_double2(u.x - v.x, u.y - v.y);
+      const double2 u = B[2 * t], v = B[2 * t + 1];
+      B[2 * t] = cadd(u, v);
+      B[2 * t + 1] = csub(u, v);
+    }
+    __syncthreads();
+    len = 4;
+    step = L / 4;
+  }
+  for (; len <= L / 2; len <<= 2, step >>= 2) {
+    const int h = len >> 1;
+    for (int t = lane; t < L / 4; t += 64) {
+      const int grp = t / h, pos = t - grp * h;
+      const int i0 = grp * 2 * len + pos, i1 = i0 + h, i2 = i0 + len, i3 = i2 + h;
+      const double2 w = cconj(tw[pos * step]);
+      const double2 c1 = cmul(B[i1], w), c3 = cmul(B[i3], w);
+      const double2 a0 = B[i0], a2 = B[i2];
+      const double2 b0 = cadd(a0, c1), b1 = csub(a0, c1), b2 = cadd(a2, c3), b3 = csub(a2, c3);
+      const double2 v2 = cmul(b2, cconj(tw[pos * (step >> 1)]));
+      const double2 v3 = cmul(b3, cconj(tw[(pos + h) * (step >> 1)]));
+      B[i0] = cadd(b0, v2);
+      B[i2] = csub(b0, v2);
+      B[i1] = cadd(b1, v3);
+      B[i3] = csub(b1, v3);
     }
     __syncthreads();
   }
 }
 
-// Dynamic LDS: FLINES lines of L entries, then L / 2 twiddles.
-__global__ __launch_bounds__(FT) void k_line_fft(LinePass a, int L, int64_t nlines, const int* __restrict__ active) {
+// Dynamic LDS: FLINES lines of L entries, then the L / 2 twiddles (copied from tw_g).
+__global__ __launch_bounds__(FT) void k_line_fft(LinePass a, int L, int64_t nlines, const int* __restrict__ active,
+                                                 const double2* __restrict__ tw_g) {
   extern __shared__ __align__(16) double2 lds[];
   double2* tw = lds + FLINES * L;
-  for (int k = threadIdx.x; k < L / 2; k += FT) {
-    double s, c;
-    sincospi(-2.0 * k / L, &s, &c);
-    tw[k] = make_double2(c, s);
-  }
+  for (int k = threadIdx.x; k < L / 2; k += FT) tw[k] = tw_g[k];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t line = (int64_t)blockIdx.x * FLINES + wv;
   bool live = line < nlines;
@@ -120,6 +159,15 @@ __global__ __launch_bounds__(FT) void k_line_fft(LinePass a, int L, int64_t nlin
   if (a.mode != kForward) dit_inverse(B, tw, L, lane);
   if (live)
     for (int t = lane; t < a.nout; t += 64) dst[t * a.inner] = B[t];
+}
+
+// tw[k] = e^{-2 pi i k / L}, k < L / 2.
+__global__ void k_twiddles(int L, double2* __restrict__ tw) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= L / 2) return;
+  double s, c;
+  sincospi(-2.0 * k / L, &s, &c);
+  tw[k] = make_double2(c, s);
 }
 
 // c[j] = M[-r] at cyclic position j = r mod Lf, r in [-2m, 2m]^d; zero elsewhere.
@@ -296,6 +344,7 @@ __global__ __launch_bounds__(CT) void k_cg_resid(const double2* __restrict__ b, 
 struct ToepGeom {
   int d = 0, m = 0, n0 = 0, L = 0;
   int64_t N = 0, spec = 0, tmp = 0;   // complex elements: modes, spectrum, one intermediate
+  double2* tw = nullptr;              // device twiddle table, L / 2 entries
 };
 
 ToepGeom toep_geom(int d, int m) {
@@ -339,13 +388,14 @@ fk_status run_pass(hipStream_t st, const ToepGeom& g, const int64_t* E, int axis
   const int64_t blocks = (nlines + FLINES - 1) / FLINES;
   if (blocks > 0x7fffffff) return FK_EINVAL;
   const size_t lds = sizeof(double2) * ((size_t)FLINES * g.L + g.L / 2);
-  hipLaunchKernelGGL(k_line_fft, dim3((unsigned)blocks), dim3(FT), lds, st, a, g.L, nlines, active);
+  hipLaunchKernelGGL(k_line_fft, dim3((unsigned)blocks), dim3(FT), lds, st, a, g.L, nlines, active, g.tw);
   return hipGetLastError() == hipSuccess ? FK_OK : FK_EHIP;
 }
 
 // spec = FFT_d(c) over the Lf^d grid (bit-reversed frequencies).  The passes run in place:
 // a line is read whole into LDS before any of it is written, and lines are disjoint.
 fk_status build_spectrum(hipStream_t st, const ToepGeom& g, const double* M, double2* spec) {
+  hipLaunchKernelGGL(k_twiddles, dim3((g.L / 2 + 255) / 256), dim3(256), 0, st, g.L, g.tw);
   const int64_t total = g.spec;
   hipLaunchKernelGGL(k_embed, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
                      reinterpret_cast<const double2*>(M), g.d, g.m, g.L, total, spec);
@@ -398,6 +448,7 @@ bool toeplitz_fft_ok(int d, int m) {
 size_t toeplitz_apply_workspace(int d, int m, int nvec) {
   const ToepGeom g = toep_geom(d, m);
   Carve cv(nullptr, 0);
+  cv.take<double2>((size_t)g.L / 2);
   cv.take<double2>((size_t)g.spec);
   cv.take<double2>((size_t)nvec * g.tmp);
   cv.take<double2>((size_t)nvec * g.tmp);
@@ -406,7 +457,8 @@ size_t toeplitz_apply_workspace(int d, int m, int nvec) {
 
 fk_status toeplitz_apply_impl(fk_ctx* ctx, int d, int m, const double* M, int nvec, const double* x, double* y,
                               Carve& cv) {
-  const ToepGeom g = toep_geom(d, m);
+  ToepGeom g = toep_geom(d, m);
+  g.tw = cv.take<double2>((size_t)g.L / 2);
   double2* spec = cv.take<double2>((size_t)g.spec);
   double2* t0 = cv.take<double2>((size_t)nvec * g.tmp);
   double2* t1 = cv.take<double2>((size_t)nvec * g.tmp);
@@ -420,6 +472,7 @@ fk_status toeplitz_apply_impl(fk_ctx* ctx, int d, int m, const double* M, int nv
 size_t cg_workspace(int d, int m, int nsys, int nlam) {
   const ToepGeom g = toep_geom(d, m);
   Carve cv(nullptr, 0);
+  cv.take<double2>((size_t)g.L / 2);
   cv.take<double2>((size_t)g.spec);
   cv.take<double2>((size_t)nsys * g.tmp);
   cv.take<double2>((size_t)nsys * g.tmp);
@@ -435,10 +488,11 @@ size_t cg_workspace(int d, int m, int nsys, int nlam) {
 fk_status cg_solve_impl(fk_ctx* ctx, int d, int m, const double* M, int ntgt, const double* b,
                         const std::vector<double>& lams, const std::vector<double>& pw, double tol, int maxit,
                         double* theta_out, int* iters_out, double* relres_out, Carve& cv) {
-  const ToepGeom g = toep_geom(d, m);
+  ToepGeom g = toep_geom(d, m);
   const int nlam = (int)lams.size();
   const int nsys = nlam * ntgt;
   hipStream_t st = ctx->stream;
+  g.tw = cv.take<double2>((size_t)g.L / 2);
   double2* spec = cv.take<double2>((size_t)g.spec);
   double2* t0 = cv.take<double2>((size_t)nsys * g.tmp);
   double2* t1 = cv.take<double2>((size_t)nsys * g.tmp);
