@@ -71,3 +71,13 @@ def piml_heat_penalty(m: int, lam: float, mu: float, lo=(-np.pi / 2, -np.pi / 2)
 def additive_penalty(m: int, d: int, s: float) -> np.ndarray:
     """Block-diagonal Sobolev weights for the additive model, [d(2m+1)]."""
     return np.concatenate([sobolev_weights(m, 1, s)] * d)
+
+
+def collocation_penalty(Xr: np.ndarray, m: int, mu: float, D: np.ndarray) -> np.ndarray:
+    """mu n_r^-1 D^* (Phi_r^* Phi_r) D (Sec. 4, domains without a closed-form Fourier matrix):
+    the physics term sampled at the n_r collocation points Xr [d, n_r], for the operator whose
+    symbol on exp(i k.x) is the diagonal D [N].  Phi_r^* Phi_r / n_r is the multilevel Toeplitz
+    matrix of the collocation points' own generator."""
+    from .fourier import gram_generator, toeplitz_matrix
+    C = toeplitz_matrix(gram_generator(np.atleast_2d(Xr), m), m)
+    return mu * (np.conj(D)[:, None] * C * D[None, :])

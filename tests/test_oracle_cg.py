@@ -102,3 +102,32 @@ def test_pcg_special_cases():
     # zero right-hand side: zero solution, no iteration
     th, it, _ = oracle.pcg(A, np.zeros(20, complex), np.ones(20), 1e-12, 50)
     assert it == 0 and not th.any()
+
+
+def test_collocation_penalty_is_the_sampled_operator_energy():
+    # theta^* P theta = mu n_r^-1 sum_l |(d_t - d_xx) f_theta(X_r,l)|^2 for the heat operator, with the
+    # derivatives of the oracle's predictor taken by central finite differences at each collocation
+    # point (no symbol, no Toeplitz matrix).  Pins the placement D^* C D (not D C D^*) and the sign of
+    # the derivative symbol.
+    m, nr, mu = 3, 40, 0.7
+    rng = np.random.default_rng(12)
+    r = np.sqrt(rng.uniform(0, 1, nr)) * 1.2
+    a = rng.uniform(0, 2 * np.pi, nr)
+    Xr = np.stack([r * np.cos(a), r * np.sin(a)])            # a disk: no closed-form Fourier matrix used
+    N = (2 * m + 1) ** 2
+    th = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    th = 0.5 * (th + np.conj(th[::-1]))                      # real-valued f
+    P = oracle.collocation_penalty(Xr, m, mu, oracle.heat_symbol(m))
+    quad = np.real(np.conj(th) @ P @ th)
+    f = lambda t, x: oracle.predict(th, np.stack([t, x]), m).real
+    h1, h2 = 1e-5, 1e-3
+    t, x = Xr
+    ft = (f(t + h1, x) - f(t - h1, x)) / (2 * h1)
+    fxx = (f(t, x + h2) - 2 * f(t, x) + f(t, x - h2)) / h2 ** 2
+    want = mu * np.mean((ft - fxx) ** 2)
+    assert abs(quad - want) / want < 1e-5
+    # the conjugate placement D C D^* gives a different value for this sample
+    D = oracle.heat_symbol(m)
+    wrong = np.real(np.conj(th) @ (mu * D[:, None] * oracle.toeplitz_matrix(oracle.gram_generator(Xr, m), m)
+                                   * np.conj(D)[None, :]) @ th)
+    assert abs(wrong - want) / want > 1e-3
