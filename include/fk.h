@@ -147,6 +147,17 @@ fk_status fk_solve(fk_ctx* ctx, int d, int m, const double* M, int ntgt, const d
                    const double* lambdas, int nlam, const fk_penalty* pen,
                    double* theta_out, void* ws, size_t ws_bytes, fk_fit_info* info);
 
+/* ---------------------------------------------------------------- restriction to a smaller m
+ * fk_restrict: the generator and right-hand sides for m_to <= m_from from those for m_from.
+ * M[q] and b_k (Sec. 2.3) do not depend on m: a smaller basis keeps the frequencies
+ * ||q||_inf <= 2 m_to and ||k||_inf <= m_to, the centred sub-blocks.  So one type-1 stage at the
+ * largest m of a sweep (over m, or over s with m tied to s) serves every smaller m.
+ * d = 1, 2 or 3; 1 <= m_to <= m_from <= 255; 0 <= ntgt.  Device complex128: M_in (4m_from+1)^d,
+ * b_in ntgt x (2m_from+1)^d, M_out (4m_to+1)^d, b_out ntgt x (2m_to+1)^d (b may be NULL when
+ * ntgt = 0); outputs must not overlap inputs.  Synchronises the context's stream. */
+fk_status fk_restrict(fk_ctx* ctx, int d, int m_from, int m_to, int ntgt, const double* M_in,
+                      const double* b_in, double* M_out, double* b_out);
+
 /* ---------------------------------------------------------------- iterative solve
  * The paper's own route to theta (Sec. 2.3, "Matrix inversion"): conjugate gradients on
  * (Sigma + lambda P) theta = b, where each product with Sigma[k, l] = M[l - k] (Sec. 2.3,
@@ -178,6 +189,23 @@ fk_status fk_solve_cg_workspace_size(fk_ctx* ctx, int d, int m, int ntgt, int nl
 fk_status fk_solve_cg(fk_ctx* ctx, int d, int m, const double* M, int ntgt, const double* b,
                       const double* lambdas, int nlam, const fk_penalty* pen, double tol, int maxit,
                       double* theta_out, int* iters, double* relres, void* ws, size_t ws_bytes);
+
+/* fk_solve_cg_collocation: the physics-informed estimator on a domain without a closed-form
+ * Fourier matrix (Sec. 4, intractable domains): the same iteration on
+ *   (Sigma + lambda P + mu D^* Sigma_r D) theta = b,
+ * where Sigma_r[k, l] = Mr[l - k] is the Gram of n_r collocation points sampled over the domain
+ * (Mr: device complex128, (4m+1)^d entries, the generator fk_gram returns for those points with
+ * no targets) and D = diag(Dsym) is the operator's symbol on exp(i k.x) (Dsym: device complex128
+ * [N]; for sum_alpha a_alpha d^alpha it is sum_alpha a_alpha prod_l (i k_l)^alpha_l).  mu >= 0.
+ * Each iteration takes two FFT products; the preconditioner is
+ * M[0] + lambda p_k + mu |D_k|^2 Mr[0].  Other arguments, results and errors as fk_solve_cg; the
+ * workspace is fk_solve_cg_collocation_workspace_size bytes. */
+fk_status fk_solve_cg_collocation_workspace_size(fk_ctx* ctx, int d, int m, int ntgt, int nlam,
+                                                 size_t* bytes);
+fk_status fk_solve_cg_collocation(fk_ctx* ctx, int d, int m, const double* M, int ntgt, const double* b,
+                                  const double* lambdas, int nlam, const fk_penalty* pen, double mu,
+                                  const double* Mr, const double* Dsym, double tol, int maxit,
+                                  double* theta_out, int* iters, double* relres, void* ws, size_t ws_bytes);
 
 /* fk_fit = fk_gram followed by fk_solve (one workspace holding both). */
 fk_status fk_fit_workspace_size(fk_ctx* ctx, int d, int64_t n, int ntgt, int m, int nlam,

@@ -22,7 +22,7 @@ import torch
 from . import _lib
 from ._lib import FkError, fk_fit_info, fk_penalty, fk_options, FK_F32, FK_F64, PEN
 
-__all__ = ["Context", "gram", "solve", "solve_cg", "toeplitz_apply", "fit", "predict", "heldout_mse", "fit_backward", "additive_gram",
+__all__ = ["Context", "gram", "restrict", "solve", "solve_cg", "toeplitz_apply", "fit", "predict", "heldout_mse", "fit_backward", "additive_gram",
            "additive_fit", "generate_uniform", "generate_targets", "KernelRidgeGridLoss", "FkError"]
 
 
@@ -160,6 +160,22 @@ def solve(M: torch.Tensor, b: torch.Tensor, m: int, lambdas: Sequence[float], pe
     return (th, inf.as_dict()) if info else th
 
 
+def restrict(M: torch.Tensor, b: Optional[torch.Tensor], m_from: int, m_to: int, ctx: Optional[Context] = None):
+    """(M, b) for the basis ||k||_inf <= m_to from those of m_from >= m_to (centred sub-blocks)."""
+    ctx = ctx or default_context(M.device.index or 0)
+    ctx.bind_stream()
+    d = M.dim()
+    Mr = torch.view_as_real(M.contiguous()).contiguous()
+    T = 0 if b is None else b.shape[0]
+    br = None if b is None else torch.view_as_real(b.contiguous()).contiguous()
+    Mo = torch.empty(((4 * m_to + 1) ** d, 2), dtype=torch.float64, device=M.device)
+    bo = torch.empty((max(T, 1), _modes(m_to, d), 2), dtype=torch.float64, device=M.device)
+    _lib.check(ctx.lib.fk_restrict(ctx.h, d, m_from, m_to, T, _ptr(Mr), _ptr(br), _ptr(Mo), _ptr(bo)),
+               "fk_restrict")
+    Mo = torch.view_as_complex(Mo).reshape((4 * m_to + 1,) * d)
+    return Mo, (None if b is None else torch.view_as_complex(bo)[:T])
+
+
 def toeplitz_apply(M: torch.Tensor, x: torch.Tensor, m: int, ctx: Optional[Context] = None) -> torch.Tensor:
     """y = Sigma x for Sigma[k, l] = M[l - k] by FFT; x [V, N] complex128 on the device."""
     ctx = ctx or default_context(M.device.index or 0)
@@ -180,9 +196,11 @@ def toeplitz_apply(M: torch.Tensor, x: torch.Tensor, m: int, ctx: Optional[Conte
 
 def solve_cg(M: torch.Tensor, b: torch.Tensor, m: int, lambdas: Sequence[float], penalty: str = "sobolev",
              s: float = 1.0, tol: float = 1e-10, maxit: int = 1000, ctx: Optional[Context] = None,
-             info: bool = False, **pen_kw):
+             info: bool = False, collocation=None, **pen_kw):
     """theta [nlam, T, N] complex128 by Jacobi-preconditioned conjugate gradients with FFT products.
 
+    collocation = (mu, Mr, D) adds the physics term mu D^* Sigma_r D: Mr the generator of the
+    collocation points (from gram(Xr, None, m)), D [N] complex128 the operator symbol, on the device.
     With info=True also returns {"iters": iterations of the slowest system,
     "relres": [nlam, T] final ||b - A theta|| / ||b||}."""
     ctx = ctx or default_context(M.device.index or 0)
@@ -194,14 +212,30 @@ def solve_cg(M: torch.Tensor, b: torch.Tensor, m: int, lambdas: Sequence[float],
     lams = (C.c_double * len(lambdas))(*[float(v) for v in lambdas])
     nlam = len(lambdas)
     nb = C.c_size_t()
-    _lib.check(ctx.lib.fk_solve_cg_workspace_size(ctx.h, d, m, T, nlam, C.byref(nb)), "fk_solve_cg_workspace_size")
-    ws = ctx.workspace(nb.value)
     theta = torch.empty((nlam, T, _modes(m, d), 2), dtype=torch.float64, device=M.device)
     pen, keep = _penalty(penalty, s, **pen_kw)
     it = C.c_int()
     rel = (C.c_double * (nlam * T))()
-    _lib.check(ctx.lib.fk_solve_cg(ctx.h, d, m, _ptr(Mr), T, _ptr(br), lams, nlam, C.byref(pen), float(tol),
-                                   int(maxit), _ptr(theta), C.byref(it), rel, _ptr(ws), nb.value), "fk_solve_cg")
+    if collocation is None:
+        _lib.check(ctx.lib.fk_solve_cg_workspace_size(ctx.h, d, m, T, nlam, C.byref(nb)),
+                   "fk_solve_cg_workspace_size")
+        ws = ctx.workspace(nb.value)
+        _lib.check(ctx.lib.fk_solve_cg(ctx.h, d, m, _ptr(Mr), T, _ptr(br), lams, nlam, C.byref(pen), float(tol),
+                                       int(maxit), _ptr(theta), C.byref(it), rel, _ptr(ws), nb.value),
+                   "fk_solve_cg")
+    else:
+        mu, Mcol, Dsym = collocation
+        Mcr = torch.view_as_real(Mcol.contiguous()).contiguous()
+        Dr = torch.view_as_real(Dsym.reshape(-1).to(torch.complex128).contiguous()).contiguous()
+        if Dr.shape[0] != _modes(m, d) or Mcr.numel() != Mr.numel():
+            raise ValueError("collocation generator or symbol of the wrong size")
+        _lib.check(ctx.lib.fk_solve_cg_collocation_workspace_size(ctx.h, d, m, T, nlam, C.byref(nb)),
+                   "fk_solve_cg_collocation_workspace_size")
+        ws = ctx.workspace(nb.value)
+        _lib.check(ctx.lib.fk_solve_cg_collocation(ctx.h, d, m, _ptr(Mr), T, _ptr(br), lams, nlam, C.byref(pen),
+                                                   float(mu), _ptr(Mcr), _ptr(Dr), float(tol), int(maxit),
+                                                   _ptr(theta), C.byref(it), rel, _ptr(ws), nb.value),
+                   "fk_solve_cg_collocation")
     del keep
     th = torch.view_as_complex(theta)
     if info:

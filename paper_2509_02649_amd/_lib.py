@@ -58,6 +58,8 @@ EXPORTS = {
     "fk_solve": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.POINTER(C.c_double),
                            C.c_int, C.POINTER(fk_penalty), C.c_void_p, C.c_void_p, C.c_size_t,
                            C.POINTER(fk_fit_info)]),
+    "fk_restrict": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                              C.c_void_p]),
     "fk_toeplitz_apply_workspace_size": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_size_t)]),
     "fk_toeplitz_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_size_t]),
@@ -66,6 +68,12 @@ EXPORTS = {
     "fk_solve_cg": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.POINTER(C.c_double),
                               C.c_int, C.POINTER(fk_penalty), C.c_double, C.c_int, C.c_void_p,
                               C.POINTER(C.c_int), C.POINTER(C.c_double), C.c_void_p, C.c_size_t]),
+    "fk_solve_cg_collocation_workspace_size": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int,
+                                                         C.POINTER(C.c_size_t)]),
+    "fk_solve_cg_collocation": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p,
+                                          C.POINTER(C.c_double), C.c_int, C.POINTER(fk_penalty), C.c_double,
+                                          C.c_void_p, C.c_void_p, C.c_double, C.c_int, C.c_void_p,
+                                          C.POINTER(C.c_int), C.POINTER(C.c_double), C.c_void_p, C.c_size_t]),
     "fk_fit_workspace_size": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int, C.c_int, C.c_int,
                                         C.POINTER(C.c_size_t)]),
     "fk_fit": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_int,

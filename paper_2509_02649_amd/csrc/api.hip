@@ -134,6 +134,25 @@ __global__ void k_extract_gram(const double* __restrict__ c, int d, int m, int n
   b[2 * ((size_t)t * totN + i) + 1] = ct[2 * src + 1];
 }
 
+// Centred sub-block of `count` row-major d-dimensional arrays: out[c][i] = in[c][i + off] per
+// coordinate, off = (Lin - Lout) / 2 (the frequencies |q| <= (Lout - 1) / 2 of a larger set).
+__global__ void k_restrict(const double2* __restrict__ in, int d, int Lin, int Lout, int64_t tot_out, int count,
+                           double2* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= tot_out * count) return;
+  const int64_t c = e / tot_out;
+  int64_t rem = e - c * tot_out, src = 0, mul = 1, tot_in = 1;
+  const int off = (Lin - Lout) / 2;
+  for (int a = 0; a < d; ++a) {
+    const int64_t j = rem % Lout;
+    rem /= Lout;
+    src += (j + off) * mul;
+    mul *= Lin;
+  }
+  for (int a = 0; a < d; ++a) tot_in *= Lin;
+  out[e] = in[c * tot_in + src];
+}
+
 }  // namespace fk
 
 // ------------------------------------------------------------------ fk_gram
@@ -307,6 +326,27 @@ extern "C" fk_status fk_solve(fk_ctx* ctx, int d, int m, const double* M, int nt
   return st;
 }
 
+// ---------------------------------------------------------------- restriction to a smaller m
+
+extern "C" fk_status fk_restrict(fk_ctx* ctx, int d, int m_from, int m_to, int ntgt, const double* M_in,
+                                 const double* b_in, double* M_out, double* b_out) {
+  if (!ctx || d < 1 || d > 3 || m_to < 1 || m_to > m_from || m_from > 255 || ntgt < 0 || ntgt > 65536)
+    return FK_EINVAL;
+  if (!M_in || !M_out || (ntgt > 0 && (!b_in || !b_out))) return FK_EINVAL;
+  FK_HIP(hipSetDevice(ctx->device));
+  const int64_t totM = ipow(4 * m_to + 1, d), totB = ipow(2 * m_to + 1, d);
+  hipLaunchKernelGGL(k_restrict, dim3((unsigned)((totM + 255) / 256)), dim3(256), 0, ctx->stream,
+                     reinterpret_cast<const double2*>(M_in), d, 4 * m_from + 1, 4 * m_to + 1, totM, 1,
+                     reinterpret_cast<double2*>(M_out));
+  if (ntgt > 0)
+    hipLaunchKernelGGL(k_restrict, dim3((unsigned)((totB * ntgt + 255) / 256)), dim3(256), 0, ctx->stream,
+                       reinterpret_cast<const double2*>(b_in), d, 2 * m_from + 1, 2 * m_to + 1, totB, ntgt,
+                       reinterpret_cast<double2*>(b_out));
+  FK_HIP(hipGetLastError());
+  FK_HIP(hipStreamSynchronize(ctx->stream));
+  return FK_OK;
+}
+
 // ---------------------------------------------------------------- iterative solve
 
 extern "C" fk_status fk_toeplitz_apply_workspace_size(fk_ctx* ctx, int d, int m, int nvec, size_t* bytes) {
@@ -330,13 +370,21 @@ static bool cg_shape_ok(int d, int m, int ntgt, int nlam) {
 
 extern "C" fk_status fk_solve_cg_workspace_size(fk_ctx* ctx, int d, int m, int ntgt, int nlam, size_t* bytes) {
   if (!bytes || !cg_shape_ok(d, m, ntgt, nlam)) return FK_EINVAL;
-  *bytes = cg_workspace(d, m, ntgt * nlam, nlam);
+  *bytes = cg_workspace(d, m, ntgt * nlam, nlam, false);
   return FK_OK;
 }
 
-extern "C" fk_status fk_solve_cg(fk_ctx* ctx, int d, int m, const double* M, int ntgt, const double* b,
-                                 const double* lambdas, int nlam, const fk_penalty* pen, double tol, int maxit,
-                                 double* theta_out, int* iters, double* relres, void* ws, size_t ws_bytes) {
+extern "C" fk_status fk_solve_cg_collocation_workspace_size(fk_ctx* ctx, int d, int m, int ntgt, int nlam,
+                                                            size_t* bytes) {
+  if (!bytes || !cg_shape_ok(d, m, ntgt, nlam)) return FK_EINVAL;
+  *bytes = cg_workspace(d, m, ntgt * nlam, nlam, true);
+  return FK_OK;
+}
+
+static fk_status cg_common(fk_ctx* ctx, int d, int m, const double* M, int ntgt, const double* b,
+                           const double* lambdas, int nlam, const fk_penalty* pen, double mu, const double* Mr,
+                           const double* Dsym, double tol, int maxit, double* theta_out, int* iters,
+                           double* relres, void* ws, size_t ws_bytes) {
   if (!ctx || !M || !b || !theta_out || !lambdas || !cg_shape_ok(d, m, ntgt, nlam)) return FK_EINVAL;
   if (!(tol > 0.0) || !(tol < 1.0) || maxit < 1 || maxit > 1000000) return FK_EINVAL;
   if (pen && pen->kind == FK_PEN_HEAT_BOX) return FK_EINVAL;   // dense penalty: use fk_solve
@@ -346,12 +394,29 @@ extern "C" fk_status fk_solve_cg(fk_ctx* ctx, int d, int m, const double* M, int
   std::vector<double> lams(lambdas, lambdas + nlam);
   for (double l : lams)
     if (!(l > 0.0) || std::isinf(l)) return FK_EINVAL;
-  if (!ws || ws_bytes < cg_workspace(d, m, ntgt * nlam, nlam)) return FK_ENOMEM;
+  if (!ws || ws_bytes < cg_workspace(d, m, ntgt * nlam, nlam, Mr != nullptr)) return FK_ENOMEM;
   FK_HIP(hipSetDevice(ctx->device));
   st = reset_flags(ctx);
   if (st != FK_OK) return st;
   Carve cv(ws, ws_bytes);
-  return cg_solve_impl(ctx, d, m, M, ntgt, b, lams, pw, tol, maxit, theta_out, iters, relres, cv);
+  return cg_solve_impl(ctx, d, m, M, ntgt, b, lams, pw, mu, Mr, Dsym, tol, maxit, theta_out, iters, relres, cv);
+}
+
+extern "C" fk_status fk_solve_cg(fk_ctx* ctx, int d, int m, const double* M, int ntgt, const double* b,
+                                 const double* lambdas, int nlam, const fk_penalty* pen, double tol, int maxit,
+                                 double* theta_out, int* iters, double* relres, void* ws, size_t ws_bytes) {
+  return cg_common(ctx, d, m, M, ntgt, b, lambdas, nlam, pen, 0.0, nullptr, nullptr, tol, maxit, theta_out, iters,
+                   relres, ws, ws_bytes);
+}
+
+extern "C" fk_status fk_solve_cg_collocation(fk_ctx* ctx, int d, int m, const double* M, int ntgt, const double* b,
+                                             const double* lambdas, int nlam, const fk_penalty* pen, double mu,
+                                             const double* Mr, const double* Dsym, double tol, int maxit,
+                                             double* theta_out, int* iters, double* relres, void* ws,
+                                             size_t ws_bytes) {
+  if (!Mr || !Dsym || !(mu >= 0.0) || std::isinf(mu)) return FK_EINVAL;
+  return cg_common(ctx, d, m, M, ntgt, b, lambdas, nlam, pen, mu, Mr, Dsym, tol, maxit, theta_out, iters, relres, ws,
+                   ws_bytes);
 }
 
 static size_t fit_ws(int d, int64_t n, int ntgt, int m, int nlam) {

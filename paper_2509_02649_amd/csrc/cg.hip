@@ -194,6 +194,35 @@ __global__ void k_zero_int(int* __restrict__ v, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) v[i] = 0;
 }
 
+// Optional physics term mu D^* Sigma_r D of the collocation form (Sec. 4): the operator symbol D
+// (N complex), v = Sigma_r (D x) for the vector x of the current step (nsys x N), mu, and
+// mu Re M_r[0] for the diagonal.  D == nullptr: no such term.
+struct Colloc {
+  const double2* D = nullptr;
+  const double2* v = nullptr;
+  double mu = 0.0, mu_m0r = 0.0;
+};
+
+__device__ __forceinline__ double colloc_diag(const Colloc& c, int64_t k) {
+  if (!c.D) return 0.0;
+  const double2 d = c.D[k];
+  return c.mu_m0r * (d.x * d.x + d.y * d.y);
+}
+
+// mu conj(D_k) v[s][k]
+__device__ __forceinline__ double2 colloc_term(const Colloc& c, int64_t s, int64_t N, int64_t k) {
+  if (!c.D) return make_double2(0.0, 0.0);
+  const double2 d = c.D[k], w = c.v[s * N + k];
+  return make_double2(c.mu * (d.x * w.x + d.y * w.y), c.mu * (d.x * w.y - d.y * w.x));
+}
+
+// u[s][k] = D_k x[s][k]
+__global__ void k_diag_mul(const double2* __restrict__ D, const double2* __restrict__ x, int64_t N, int64_t total,
+                           double2* __restrict__ u) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
+    u[e] = cmul(D[e % N], x[e]);
+}
+
 __device__ __forceinline__ double block_sum(double v, double* red) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
   const int w = threadIdx.x >> 6;
@@ -208,10 +237,11 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // theta = 0, r = b, z = r / dg, p = z, rho = <r, z>, bb = ||b||^2.  System s = l ntgt + t.
 __global__ __launch_bounds__(CT) void k_cg_init(const double2* __restrict__ b, int ntgt, int64_t N,
                                                 const double* __restrict__ lams, const double* __restrict__ pw,
-                                                double m0, double2* __restrict__ theta, double2* __restrict__ r,
-                                                double2* __restrict__ p, double* __restrict__ rho,
-                                                double* __restrict__ bb, int* __restrict__ active,
-                                                int* __restrict__ iters, int* __restrict__ nactive) {
+                                                double m0, Colloc cl, double2* __restrict__ theta,
+                                                double2* __restrict__ r, double2* __restrict__ p,
+                                                double* __restrict__ rho, double* __restrict__ bb,
+                                                int* __restrict__ active, int* __restrict__ iters,
+                                                int* __restrict__ nactive) {
   __shared__ double red[CT / 64];
   const int s = blockIdx.x;
   const double lam = lams[s / ntgt];
@@ -222,7 +252,7 @@ __global__ __launch_bounds__(CT) void k_cg_init(const double2* __restrict__ b, i
   double rz = 0.0, b2 = 0.0;
   for (int64_t k = threadIdx.x; k < N; k += CT) {
     const double2 v = bt[k];
-    const double inv = 1.0 / (m0 + lam * pw[k]);
+    const double inv = 1.0 / (m0 + lam * pw[k] + colloc_diag(cl, k));
     th[k] = make_double2(0.0, 0.0);
     rs[k] = v;
     ps[k] = make_double2(v.x * inv, v.y * inv);
@@ -249,7 +279,7 @@ __global__ __launch_bounds__(CT) void k_cg_init(const double2* __restrict__ b, i
 // and raises the not-positive-definite flag.
 __global__ __launch_bounds__(CT) void k_cg_step(const double2* __restrict__ qraw, int ntgt, int64_t N,
                                                 const double* __restrict__ lams, const double* __restrict__ pw,
-                                                double m0, double tol2, double2* __restrict__ theta,
+                                                double m0, Colloc cl, double tol2, double2* __restrict__ theta,
                                                 double2* __restrict__ r, double2* __restrict__ p,
                                                 double* __restrict__ rho, const double* __restrict__ bb,
                                                 int* __restrict__ active, int* __restrict__ iters,
@@ -265,9 +295,9 @@ __global__ __launch_bounds__(CT) void k_cg_step(const double2* __restrict__ qraw
   const double rho0 = rho[s];
   double pq = 0.0;
   for (int64_t k = threadIdx.x; k < N; k += CT) {
-    const double2 pk = ps[k], qk = qs[k];
+    const double2 pk = ps[k], qk = qs[k], ck = colloc_term(cl, s, N, k);
     const double lp = lam * pw[k];
-    pq += pk.x * (qk.x + lp * pk.x) + pk.y * (qk.y + lp * pk.y);
+    pq += pk.x * (qk.x + lp * pk.x + ck.x) + pk.y * (qk.y + lp * pk.y + ck.y);
   }
   pq = block_sum(pq, red);
   if (!(pq > 0.0)) {
@@ -281,18 +311,18 @@ __global__ __launch_bounds__(CT) void k_cg_step(const double2* __restrict__ qraw
   const double alpha = rho0 / pq;
   double rr = 0.0, rz = 0.0;
   for (int64_t k = threadIdx.x; k < N; k += CT) {
-    const double2 pk = ps[k], qk = qs[k];
+    const double2 pk = ps[k], qk = qs[k], ck = colloc_term(cl, s, N, k);
     const double lp = lam * pw[k];
     double2 t = th[k], rk = rs[k];
     t.x += alpha * pk.x;
     t.y += alpha * pk.y;
-    rk.x -= alpha * (qk.x + lp * pk.x);
-    rk.y -= alpha * (qk.y + lp * pk.y);
+    rk.x -= alpha * (qk.x + lp * pk.x + ck.x);
+    rk.y -= alpha * (qk.y + lp * pk.y + ck.y);
     th[k] = t;
     rs[k] = rk;
     const double a = rk.x * rk.x + rk.y * rk.y;
     rr += a;
-    rz += a / (m0 + lp);
+    rz += a / (m0 + lp + colloc_diag(cl, k));
   }
   rr = block_sum(rr, red);
   rz = block_sum(rz, red);
@@ -307,7 +337,7 @@ __global__ __launch_bounds__(CT) void k_cg_step(const double2* __restrict__ qraw
   }
   const double beta = rz / rho0;
   for (int64_t k = threadIdx.x; k < N; k += CT) {
-    const double inv = 1.0 / (m0 + lam * pw[k]);
+    const double inv = 1.0 / (m0 + lam * pw[k] + colloc_diag(cl, k));
     const double2 rk = rs[k], pk = ps[k];
     ps[k] = make_double2(rk.x * inv + beta * pk.x, rk.y * inv + beta * pk.y);
   }
@@ -321,7 +351,8 @@ __global__ __launch_bounds__(CT) void k_cg_step(const double2* __restrict__ qraw
 __global__ __launch_bounds__(CT) void k_cg_resid(const double2* __restrict__ b, const double2* __restrict__ qraw,
                                                  const double2* __restrict__ theta, int ntgt, int64_t N,
                                                  const double* __restrict__ lams, const double* __restrict__ pw,
-                                                 const double* __restrict__ bb, double* __restrict__ relres) {
+                                                 Colloc cl, const double* __restrict__ bb,
+                                                 double* __restrict__ relres) {
   __shared__ double red[CT / 64];
   const int s = blockIdx.x;
   const double lam = lams[s / ntgt];
@@ -331,8 +362,9 @@ __global__ __launch_bounds__(CT) void k_cg_resid(const double2* __restrict__ b, 
   double e = 0.0;
   for (int64_t k = threadIdx.x; k < N; k += CT) {
     const double lp = lam * pw[k];
-    const double rx = bt[k].x - qs[k].x - lp * th[k].x;
-    const double ry = bt[k].y - qs[k].y - lp * th[k].y;
+    const double2 ck = colloc_term(cl, s, N, k);
+    const double rx = bt[k].x - qs[k].x - lp * th[k].x - ck.x;
+    const double ry = bt[k].y - qs[k].y - lp * th[k].y - ck.y;
     e += rx * rx + ry * ry;
   }
   e = block_sum(e, red);
@@ -469,7 +501,7 @@ fk_status toeplitz_apply_impl(fk_ctx* ctx, int d, int m, const double* M, int nv
                     t0, t1, nullptr);
 }
 
-size_t cg_workspace(int d, int m, int nsys, int nlam) {
+size_t cg_workspace(int d, int m, int nsys, int nlam, bool colloc) {
   const ToepGeom g = toep_geom(d, m);
   Carve cv(nullptr, 0);
   cv.take<double2>((size_t)g.L / 2);
@@ -482,15 +514,34 @@ size_t cg_workspace(int d, int m, int nsys, int nlam) {
   for (int k = 0; k < 3; ++k) cv.take<double>((size_t)nsys);            // rho, bb, relres
   for (int k = 0; k < 2; ++k) cv.take<int>((size_t)nsys);               // active, iters
   cv.take<int>(64);                                                      // counter
+  if (colloc) {
+    cv.take<double2>((size_t)g.spec);                                    // collocation spectrum
+    cv.take<double2>((size_t)nsys * g.N);                                // D x
+    cv.take<double2>((size_t)nsys * g.N);                                // Sigma_r D x
+  }
   return cv.off + 256;
 }
 
+static double centre_of(hipStream_t st, const double* M, int d, int m, fk_status* err) {
+  double2 c;
+  int64_t centre = 0;
+  for (int a = 0, mul = 1; a < d; ++a, mul *= 4 * m + 1) centre += (int64_t)(2 * m) * mul;
+  if (hipMemcpyAsync(&c, M + 2 * centre, sizeof(double2), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    *err = FK_EHIP;
+    return 0.0;
+  }
+  return c.x;
+}
+
 fk_status cg_solve_impl(fk_ctx* ctx, int d, int m, const double* M, int ntgt, const double* b,
-                        const std::vector<double>& lams, const std::vector<double>& pw, double tol, int maxit,
-                        double* theta_out, int* iters_out, double* relres_out, Carve& cv) {
+                        const std::vector<double>& lams, const std::vector<double>& pw, double mu, const double* Mr,
+                        const double* Dsym, double tol, int maxit, double* theta_out, int* iters_out,
+                        double* relres_out, Carve& cv) {
   ToepGeom g = toep_geom(d, m);
   const int nlam = (int)lams.size();
   const int nsys = nlam * ntgt;
+  const bool colloc = Mr != nullptr;
   hipStream_t st = ctx->stream;
   g.tw = cv.take<double2>((size_t)g.L / 2);
   double2* spec = cv.take<double2>((size_t)g.spec);
@@ -507,25 +558,48 @@ fk_status cg_solve_impl(fk_ctx* ctx, int d, int m, const double* M, int ntgt, co
   int* active = cv.take<int>((size_t)nsys);
   int* iters = cv.take<int>((size_t)nsys);
   int* counter = cv.take<int>(64);
+  double2 *spec_r = nullptr, *u = nullptr, *v = nullptr;
+  if (colloc) {
+    spec_r = cv.take<double2>((size_t)g.spec);
+    u = cv.take<double2>((size_t)nsys * g.N);
+    v = cv.take<double2>((size_t)nsys * g.N);
+  }
   if (!cv.ok()) return FK_ENOMEM;
   double2* theta = reinterpret_cast<double2*>(theta_out);
   const double2* bv = reinterpret_cast<const double2*>(b);
 
   // the diagonal of Sigma is M[0] (the centre of the generator), real for a Hermitian Sigma
-  double2 m0c;
-  int64_t centre = 0;
-  for (int a = 0, mul = 1; a < d; ++a, mul *= 4 * m + 1) centre += (int64_t)(2 * m) * mul;
-  FK_HIP(hipMemcpyAsync(&m0c, M + 2 * centre, sizeof(double2), hipMemcpyDeviceToHost, st));
+  fk_status s = FK_OK;
+  const double m0 = centre_of(st, M, d, m, &s);
+  if (s != FK_OK) return s;
+  if (!(m0 > 0.0) || std::isinf(m0)) return FK_EINVAL;
+  Colloc cl;
+  if (colloc) {
+    const double m0r = centre_of(st, Mr, d, m, &s);
+    if (s != FK_OK) return s;
+    if (!(m0r > 0.0) || std::isinf(m0r)) return FK_EINVAL;
+    cl.D = reinterpret_cast<const double2*>(Dsym);
+    cl.v = v;
+    cl.mu = mu;
+    cl.mu_m0r = mu * m0r;
+  }
   FK_HIP(hipMemcpyAsync(dpw, pw.data(), sizeof(double) * g.N, hipMemcpyHostToDevice, st));
   FK_HIP(hipMemcpyAsync(dlam, lams.data(), sizeof(double) * nlam, hipMemcpyHostToDevice, st));
-  FK_HIP(hipStreamSynchronize(st));
-  const double m0 = m0c.x;
-  if (!(m0 > 0.0) || std::isinf(m0)) return FK_EINVAL;
 
-  fk_status s = build_spectrum(st, g, M, spec);
+  s = build_spectrum(st, g, M, spec);
+  if (s == FK_OK && colloc) s = build_spectrum(st, g, Mr, spec_r);
   if (s != FK_OK) return s;
+  const int64_t tot = (int64_t)nsys * g.N;
+  const unsigned dblocks = (unsigned)std::min<int64_t>(4096, (tot + 255) / 256);
+  // q = Sigma x, and with the physics term v = Sigma_r (D x)
+  auto product = [&](const double2* x, const int* act) -> fk_status {
+    fk_status e = toep_apply(st, g, spec, x, q, nsys, t0, t1, act);
+    if (e != FK_OK || !colloc) return e;
+    hipLaunchKernelGGL(k_diag_mul, dim3(dblocks), dim3(256), 0, st, cl.D, x, g.N, tot, u);
+    return toep_apply(st, g, spec_r, u, v, nsys, t0, t1, act);
+  };
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, counter, 64);
-  hipLaunchKernelGGL(k_cg_init, dim3(nsys), dim3(CT), 0, st, bv, ntgt, g.N, dlam, dpw, m0, theta, r, p, rho, bb,
+  hipLaunchKernelGGL(k_cg_init, dim3(nsys), dim3(CT), 0, st, bv, ntgt, g.N, dlam, dpw, m0, cl, theta, r, p, rho, bb,
                      active, iters, counter);
   const double tol2 = tol * tol;
   int done_it = 0;
@@ -534,9 +608,9 @@ fk_status cg_solve_impl(fk_ctx* ctx, int d, int m, const double* M, int ntgt, co
   while (done_it < maxit && nact > 0) {
     const int run = std::min(kCheck, maxit - done_it);
     for (int k = 0; k < run; ++k) {
-      s = toep_apply(st, g, spec, p, q, nsys, t0, t1, active);
+      s = product(p, active);
       if (s != FK_OK) return s;
-      hipLaunchKernelGGL(k_cg_step, dim3(nsys), dim3(CT), 0, st, q, ntgt, g.N, dlam, dpw, m0, tol2, theta, r, p,
+      hipLaunchKernelGGL(k_cg_step, dim3(nsys), dim3(CT), 0, st, q, ntgt, g.N, dlam, dpw, m0, cl, tol2, theta, r, p,
                          rho, bb, active, iters, counter, ctx->flags);
     }
     done_it += run;
@@ -545,16 +619,16 @@ fk_status cg_solve_impl(fk_ctx* ctx, int d, int m, const double* M, int ntgt, co
     nact = ctx->flags_host[kFlagCount];
   }
   // true residuals from one more product
-  s = toep_apply(st, g, spec, theta, q, nsys, t0, t1, nullptr);
+  s = product(theta, nullptr);
   if (s != FK_OK) return s;
-  hipLaunchKernelGGL(k_cg_resid, dim3(nsys), dim3(CT), 0, st, bv, q, theta, ntgt, g.N, dlam, dpw, bb, relres);
+  hipLaunchKernelGGL(k_cg_resid, dim3(nsys), dim3(CT), 0, st, bv, q, theta, ntgt, g.N, dlam, dpw, cl, bb, relres);
   std::vector<int> it_h(nsys);
   FK_HIP(hipMemcpyAsync(it_h.data(), iters, sizeof(int) * nsys, hipMemcpyDeviceToHost, st));
   if (relres_out) FK_HIP(hipMemcpyAsync(relres_out, relres, sizeof(double) * nsys, hipMemcpyDeviceToHost, st));
   FK_HIP(hipStreamSynchronize(st));
   if (iters_out) {
     int mx = 0;
-    for (int v : it_h) mx = std::max(mx, v);
+    for (int it : it_h) mx = std::max(mx, it);
     *iters_out = mx;
   }
   s = read_flags(ctx);

@@ -168,8 +168,11 @@ bool toeplitz_fft_ok(int d, int m);
 size_t toeplitz_apply_workspace(int d, int m, int nvec);
 fk_status toeplitz_apply_impl(fk_ctx* ctx, int d, int m, const double* M, int nvec, const double* x, double* y,
                               Carve& cv);
-size_t cg_workspace(int d, int m, int nsys, int nlam);
+// Mr, Dsym (device, nullable together): generator of the collocation points and the operator
+// symbol of the physics term mu D^* Sigma_r D.
+size_t cg_workspace(int d, int m, int nsys, int nlam, bool colloc);
 fk_status cg_solve_impl(fk_ctx* ctx, int d, int m, const double* M, int ntgt, const double* b,
-                        const std::vector<double>& lams, const std::vector<double>& pw, double tol, int maxit,
-                        double* theta_out, int* iters_out, double* relres_out, Carve& cv);
+                        const std::vector<double>& lams, const std::vector<double>& pw, double mu, const double* Mr,
+                        const double* Dsym, double tol, int maxit, double* theta_out, int* iters_out,
+                        double* relres_out, Carve& cv);
 }  // namespace fk

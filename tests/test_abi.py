@@ -73,6 +73,10 @@ def test_workspace_queries_and_host_validation(lib):
     assert L.fk_solve_cg_workspace_size(None, 2, 256, 1, 1, C.byref(nb)) == 1       # Lf > 1024 rejected
     assert L.fk_solve_cg_workspace_size(None, 4, 4, 1, 1, C.byref(nb)) == 1         # d = 4 rejected
     assert L.fk_solve_cg_workspace_size(None, 2, 8, 1024, 128, C.byref(nb)) == 1    # > 65536 systems
+    plain = nb.value
+    assert L.fk_solve_cg_collocation_workspace_size(None, 2, 8, 1024, 128, C.byref(nb)) == 1
+    assert L.fk_solve_cg_collocation_workspace_size(None, 3, 16, 1, 1, C.byref(nb)) == 0
+    assert nb.value > plain                                                        # + spectrum, D x, Sigma_r D x
     assert L.fk_toeplitz_apply_workspace_size(None, 1, 255, 3, C.byref(nb)) == 0
     assert L.fk_toeplitz_apply_workspace_size(None, 1, 8, 0, C.byref(nb)) == 1      # no vectors
     # entry points reject a null context before touching the device

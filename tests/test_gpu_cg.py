@@ -134,3 +134,91 @@ def test_solve_cg_batched_shape_against_dense_path(fk):
         ref = oracle.solve_system(oracle.system_matrix(Mh, m, lams[l], p), bh[t])
         got = th_cg[l, t].cpu().numpy()
         assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-9
+
+
+def _disk(n, radius, rng):
+    r = np.sqrt(rng.uniform(0, 1, n)) * radius
+    a = rng.uniform(0, 2 * np.pi, n)
+    return np.stack([r * np.cos(a), r * np.sin(a)])
+
+
+@pytest.mark.parametrize("m,mu", [(6, 1e-3), (10, 1e-4)])
+def test_solve_cg_collocation_parity(fk, m, mu):
+    # Sec. 4, intractable domains: heat operator d_t - d_xx sampled at n_r collocation points in a disk;
+    # data in the same disk.  Generators from the oracle (solver parity), then from the device Gram
+    # (end to end).
+    print(f"cg collocation m={m} mu={mu}", flush=True)
+    rng = np.random.default_rng(40 + m)
+    n, nr, lams, tol = 20_000, 15_000, [1e-2, 1e-4], 1e-12
+    X = _disk(n, 1.3, rng)
+    Y = np.stack([np.exp(-X[0]) * np.sin(X[1]) + 0.05 * rng.standard_normal(n) for _ in range(2)])
+    Xr = _disk(nr, 1.3, rng)
+    M, Mr = oracle.gram_generator(X, m), oracle.gram_generator(Xr, m)
+    b = oracle.rhs(X, Y, m)
+    D = oracle.heat_symbol(m)
+    p = oracle.sobolev_weights(m, 2, 1.0)
+    P = oracle.collocation_penalty(Xr, m, mu, D)
+    th, inf = fk.solve_cg(_cplx(M), _cplx(b), m, lams, penalty="sobolev", s=1.0, tol=tol, maxit=5000, info=True,
+                          collocation=(mu, _cplx(Mr), _cplx(D)))
+    th = th.cpu().numpy()
+    dg = M[2 * m, 2 * m].real + mu * np.abs(D) ** 2 * Mr[2 * m, 2 * m].real
+    it_ref = 0
+    for l, lam in enumerate(lams):
+        A = oracle.system_matrix(M, m, lam, p) + P
+        ref = oracle.solve_system(A, b)
+        kappa = oracle.condition_number(A)
+        for t in range(2):
+            err = np.linalg.norm(th[l, t] - ref[t]) / np.linalg.norm(ref[t])
+            assert err <= max(1e-10, 10 * kappa * tol), (lam, t, err, kappa)
+            _, it, _ = oracle.pcg(A, b[t], dg + lam * p, tol, 5000)
+            it_ref = max(it_ref, it)
+    # hundreds of iterations: rounding (FFT against dense products) may shift the count a little
+    assert abs(inf["iters"] - it_ref) <= 2 + 0.1 * it_ref, (inf["iters"], it_ref)
+    # end to end: both generators and b from the device type-1 stage (Gram error <= 1e-6 relative,
+    # so theta moves by up to about kappa times that)
+    Xd = torch.from_numpy(X).cuda()
+    Md, bd = fk.gram(Xd, torch.from_numpy(Y).cuda(), m)
+    Mrd, _ = fk.gram(torch.from_numpy(Xr).cuda(), None, m)
+    th2 = fk.solve_cg(Md, bd, m, lams, penalty="sobolev", s=1.0, tol=1e-11,
+                      collocation=(mu, Mrd, _cplx(D))).cpu().numpy()
+    for l, lam in enumerate(lams):
+        A = oracle.system_matrix(M, m, lam, p) + P
+        ref = oracle.solve_system(A, b)
+        bar = max(1e-4, 1e-6 * oracle.condition_number(A))
+        assert np.linalg.norm(th2[l] - ref) / np.linalg.norm(ref) < bar
+    # mu = 0 is the plain iteration
+    th0 = fk.solve_cg(_cplx(M), _cplx(b), m, lams, penalty="sobolev", s=1.0, tol=1e-12,
+                      collocation=(0.0, _cplx(Mr), _cplx(D))).cpu().numpy()
+    th1 = fk.solve_cg(_cplx(M), _cplx(b), m, lams, penalty="sobolev", s=1.0, tol=1e-12).cpu().numpy()
+    assert np.abs(th0 - th1).max() <= 1e-12 * np.abs(th1).max()
+
+
+def test_restrict_serves_a_sweep_over_s(fk):
+    # One type-1 stage at the largest m of a sweep serves every smaller m (M[q] and b_k do not depend
+    # on m).  The sweep ties m and lambda to s as in the Sobolev rates, m = n^(1/(2s+d)),
+    # lambda = n^(-2s/(2s+d)), and solves each s by conjugate gradients.
+    print("restrict / s sweep", flush=True)
+    rng = np.random.default_rng(77)
+    n, d = 30_000, 2
+    X = rng.uniform(-np.pi, np.pi, (d, n))
+    Y = (np.sin(X[0]) * np.cos(2 * X[1]) + 0.1 * rng.standard_normal(n))[None, :]
+    Xd, Yd = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    sweep = [(s, int(round(n ** (1 / (2 * s + d)))), n ** (-2 * s / (2 * s + d))) for s in (1.0, 1.5, 2.0, 3.0)]
+    mmax = max(m for _, m, _ in sweep)
+    Mbig, bbig = fk.gram(Xd, Yd, mmax)
+    scale_b = np.abs(Y).mean()
+    for s, m, lam in sweep:
+        Mm, bm = fk.restrict(Mbig, bbig, mmax, m)
+        o, ob = 2 * (mmax - m), mmax - m
+        assert torch.equal(Mm, Mbig[o:o + 4 * m + 1, o:o + 4 * m + 1])
+        bb = bbig.reshape(1, 2 * mmax + 1, 2 * mmax + 1)[:, ob:ob + 2 * m + 1, ob:ob + 2 * m + 1].reshape(1, -1)
+        assert torch.equal(bm, bb)
+        Mref, bref = oracle.gram_generator(X, m), oracle.rhs(X, Y, m)
+        assert np.abs(Mm.cpu().numpy() - Mref).max() / Mref[2 * m, 2 * m].real <= 1e-6
+        assert np.abs(bm.cpu().numpy() - bref).max() / scale_b <= 1e-6
+        th = fk.solve_cg(Mm, bm, m, [lam], penalty="sobolev", s=s, tol=1e-12).cpu().numpy()
+        A = oracle.system_matrix(Mref, m, lam, oracle.sobolev_weights(m, d, s))
+        ref = oracle.solve_system(A, bref)
+        assert np.linalg.norm(th[0] - ref) / np.linalg.norm(ref) <= max(1e-4, 1e-6 * oracle.condition_number(A))
+    with pytest.raises(fk.FkError):
+        fk.restrict(Mbig, bbig, mmax, mmax + 1)
