@@ -125,7 +125,8 @@ const char* fk_status_string(fk_status s);
  *   M_out[q] = n^-1 sum_j exp(+i q.X_j),          q in {-2m..2m}^d,  complex128 (4m+1)^d
  *   b_out[t][k] = n^-1 sum_j Y[t][j] exp(-i k.X_j),   k in {-m..m}^d,  complex128 ntgt x N
  * computed by exponential-of-semicircle spreading onto an oversampled grid, an
- * FFT and deconvolution.  d in {1, 2}; 1 <= m <= 64; 0 <= ntgt <= 32 (Y may be NULL
+ * FFT and deconvolution.  d in {1, 2, 3}; 1 <= m <= 64 (m <= 31 and ntgt <= 8 for d = 3, whose
+ * spread adds into an FP64 grid of up to 256^3 per channel by FP64 atomics); 0 <= ntgt <= 32 (Y may be NULL
  * when ntgt = 0); n >= 1, and n <= 2^32 - 1 for d = 2 with ntgt <= 16 (point positions
  * are 32-bit in the bin sort; larger n returns FK_EINVAL). */
 fk_status fk_gram_workspace_size(fk_ctx* ctx, int d, int64_t n, int ntgt, int m, size_t* bytes);

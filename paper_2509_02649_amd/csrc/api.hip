@@ -109,8 +109,8 @@ static float elapsed(hipEvent_t a, hipEvent_t b) {
 __global__ void k_extract_gram(const double* __restrict__ c, int d, int m, int ntgt, double* __restrict__ M,
                                double* __restrict__ b) {
   const int K = 2 * m, LK = 2 * K + 1, L = 2 * m + 1;
-  const int totK = d == 1 ? LK : LK * LK;
-  const int totN = d == 1 ? L : L * L;
+  const int totK = d == 1 ? LK : (d == 2 ? LK * LK : LK * LK * LK);
+  const int totN = d == 1 ? L : (d == 2 ? L * L : L * L * L);
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (blockIdx.y == 0) {
     if (i >= totK) return;
@@ -125,9 +125,12 @@ __global__ void k_extract_gram(const double* __restrict__ c, int d, int m, int n
   int src;
   if (d == 1) {
     src = i + m;
-  } else {
+  } else if (d == 2) {
     int k1 = i / L, k2 = i - k1 * L;
     src = (k1 + m) * LK + (k2 + m);
+  } else {
+    int k1 = i / (L * L), r = i - k1 * L * L, k2 = r / L, k3 = r - k2 * L;
+    src = ((k1 + m) * LK + (k2 + m)) * LK + (k3 + m);
   }
   const double* ct = c + 2 * (size_t)(t + 1) * totK;
   b[2 * ((size_t)t * totN + i)] = ct[2 * src];
@@ -157,18 +160,25 @@ __global__ void k_restrict(const double2* __restrict__ in, int d, int Lin, int L
 
 // ------------------------------------------------------------------ fk_gram
 
+static int64_t ipow(int64_t a, int d) {
+  int64_t r = 1;
+  while (d-- > 0) r *= a;
+  return r;
+}
+
 static size_t gram_ws(int d, int64_t n, int ntgt, int m) {
   const int K = 2 * m;
   const int LK = 2 * K + 1;
-  const int64_t tot = d == 1 ? LK : (int64_t)LK * LK;
+  const int64_t tot = ipow(LK, d);
   Carve cv(nullptr, 0);
   cv.take<double>((size_t)2 * (ntgt + 1) * tot);
   return cv.off + type1_workspace(d, n, ntgt, K, 0) + 512;
 }
 
 static fk_status check_gram_args(int d, int64_t n, int ntgt, int m, const void* X, const void* Y) {
-  if (d != 1 && d != 2) return FK_EINVAL;
+  if (d < 1 || d > 3) return FK_EINVAL;
   if (n < 1 || m < 1 || m > 64 || ntgt < 0 || ntgt > 32) return FK_EINVAL;
+  if (d == 3 && (m > 31 || ntgt > 8)) return FK_EINVAL;   // FP64 grid 256^3 per channel
   if (!X || (ntgt > 0 && !Y)) return FK_EINVAL;
   if (d == 2 && n > (int64_t)1 << 34) return FK_EINVAL;
   return FK_OK;
@@ -186,13 +196,12 @@ fk_status gram_impl(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, i
                     double* M_out, double* b_out, Carve& cv, fk_fit_info* info) {
   const int K = 2 * m;
   const int LK = 2 * K + 1;
-  const int64_t tot = d == 1 ? LK : (int64_t)LK * LK;
+  const int64_t tot = ipow(LK, d);
   double* c = cv.take<double>((size_t)2 * (ntgt + 1) * tot);
   if (!cv.ok()) return FK_ENOMEM;
   fk_status st = type1(ctx, d, n, dt, X, n, ntgt, Y, K, 1.0 / (double)n, c, cv, info);
   if (st != FK_OK) return st;
-  const int L = 2 * m + 1;
-  const int totN = d == 1 ? L : L * L;
+  const int64_t totN = ipow(2 * m + 1, d);
   int mx = (int)std::max<int64_t>(tot, totN);
   hipLaunchKernelGGL(k_extract_gram, dim3((mx + 255) / 256, ntgt + 1), dim3(256), 0, ctx->stream, c, d, m, ntgt,
                      M_out, b_out);
@@ -231,11 +240,6 @@ extern "C" fk_status fk_gram(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const v
 
 // ------------------------------------------------------------------ fk_solve / fk_fit
 
-static int64_t ipow(int64_t a, int d) {
-  int64_t r = 1;
-  while (d-- > 0) r *= a;
-  return r;
-}
 
 static fk_status penalty_weights(const fk_penalty* pen, int d, int m, std::vector<double>& p) {
   const int L = 2 * m + 1;
@@ -431,7 +435,7 @@ static size_t fit_ws(int d, int64_t n, int ntgt, int m, int nlam) {
 extern "C" fk_status fk_fit_workspace_size(fk_ctx* ctx, int d, int64_t n, int ntgt, int m, int nlam,
                                            size_t* bytes) {
   if (!bytes) return FK_EINVAL;
-  if (check_gram_args(d, n, ntgt, m, (void*)1, (void*)1) != FK_OK || ntgt < 1 || nlam < 1 || nlam > 1024)
+  if (check_gram_args(d, n, ntgt, m, (void*)1, (void*)1) != FK_OK || ntgt < 1 || nlam < 1 || nlam > 1024 || d > 2)
     return FK_EINVAL;
   *bytes = fit_ws(d, n, ntgt, m, nlam);
   return FK_OK;

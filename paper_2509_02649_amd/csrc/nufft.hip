@@ -244,6 +244,62 @@ __global__ __launch_bounds__(256) void k_spread_1d(const void* __restrict__ X, f
   }
 }
 
+// ------------------------------------------------------------------ 3-D spread (FP64 global atomics)
+// One thread per point: the w^3 window of every channel (channel 0 with weight 1) is added into
+// the FP64 grid [C][nf][nf][nf] by hardware FP64 atomics.  Kernel values in FP32, as in 1-D.
+template <int W>
+__global__ __launch_bounds__(256) void k_spread_3d(const void* __restrict__ X, fk_dtype dt, int64_t n,
+                                                   int64_t xstride, const void* __restrict__ Y, int nw, int nf,
+                                                   int fb, double scale, EsDev es, double* __restrict__ grid,
+                                                   int* flags) {
+  const uint32_t nf_fix = (uint32_t)nf << fb;
+  const int64_t cube = (int64_t)nf * nf * nf;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t U[3];
+    bool ok = true;
+    for (int a = 0; a < 3; ++a) ok = to_fixed(load_coord(X, dt, a * xstride + j), scale, nf_fix, &U[a], flags) && ok;
+    if (!ok) continue;
+    float k[3][W];
+    int base[3];
+    for (int a = 0; a < 3; ++a) {
+      int i0;
+      float s0;
+      window_start(U[a], fb, W, &i0, &s0);
+#pragma unroll
+      for (int t = 0; t < W; ++t) k[a][t] = es_eval(s0 + (float)t, es);
+      base[a] = i0 < 0 ? i0 + nf : i0;
+    }
+    for (int c = 0; c <= nw; ++c) {
+      float wc = 1.0f;
+      if (c > 0) {
+        wc = load_weight(Y, dt, (int64_t)(c - 1) * n + j);
+        if (!(wc == wc) || isinf(wc)) {
+          atomicOr(&flags[kFlagNaN], 1);
+          continue;
+        }
+      }
+      double* g = grid + (int64_t)c * cube;
+      for (int a1 = 0; a1 < W; ++a1) {
+        int l1 = base[0] + a1;
+        l1 = l1 >= nf ? l1 - nf : l1;
+        const float v1 = wc * k[0][a1];
+        for (int a2 = 0; a2 < W; ++a2) {
+          int l2 = base[1] + a2;
+          l2 = l2 >= nf ? l2 - nf : l2;
+          const float v12 = v1 * k[1][a2];
+          double* row = g + ((int64_t)l1 * nf + l2) * nf;
+#pragma unroll
+          for (int a3 = 0; a3 < W; ++a3) {
+            int l3 = base[2] + a3;
+            l3 = l3 >= nf ? l3 - nf : l3;
+            atomicAdd(&row[l3], (double)(v12 * k[2][a3]));
+          }
+        }
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ 2-D binned spread
 // Bins are T x T tiles of the nf x nf grid: nbx = nf / T bins per axis.
 
@@ -541,6 +597,12 @@ size_t type1_workspace(int d, int64_t n, int nw, int K, double eps) {
       cv.take<double>((size_t)C * nf);
       return cv.off;
     }
+    if (d == 3) {
+      cv.take<double>((size_t)C * nf * nf * nf);      // FP64 grid
+      cv.take<double>((size_t)C * nf * nf * L * 2);   // after the axis-2 transform
+      cv.take<double>((size_t)C * nf * L * L * 2);    // after the axis-1 transform
+      return cv.off;
+    }
     cv.take<double>((size_t)C * nf * nf);          // FP64 grid
     cv.take<double>((size_t)C * nf * L * 2);        // row-FFT output
     BinGeom g = bin_geom(nf, C, n, kind);
@@ -569,6 +631,14 @@ static void launch_spread_1d(fk_ctx* ctx, int blocks, size_t lds, const void* X,
                              int64_t chunk) {
   hipLaunchKernelGGL(k_spread_1d<W>, dim3(blocks), dim3(256), lds, ctx->stream, X, dt, n, Y, nw, 1, nf,
                      fb, scale, es, grid, ctx->flags, chunk);
+}
+
+template <int W>
+static void launch_spread_3d(fk_ctx* ctx, const void* X, fk_dtype dt, int64_t n, int64_t xstride, const void* Y,
+                             int nw, int nf, int fb, double scale, EsDev es, double* grid) {
+  const int blocks = (int)std::min<int64_t>(65536, std::max<int64_t>(1, (n + 255) / 256));
+  hipLaunchKernelGGL(k_spread_3d<W>, dim3(blocks), dim3(256), 0, ctx->stream, X, dt, n, xstride, Y, nw, nf, fb,
+                     scale, es, grid, ctx->flags);
 }
 
 template <int W>
@@ -635,6 +705,33 @@ fk_status type1(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int64
     FK_HIP(hipGetLastError());
     FK_HIP(hipEventRecord(ev[3], ctx->stream));
     if (info) info->bin = 0;
+    return FK_OK;
+  }
+  if (d == 3) {
+    // spread, then transforms along axis 2 (C nf^2 lines), axis 1 (C nf L lines) and axis 0
+    // (C L^2 lines), each pruned to |q| <= K and deconvolved along its own axis
+    const int64_t nf3 = (int64_t)nf * nf * nf;
+    double* grid = cv.take<double>((size_t)C * nf3);
+    double* ta = cv.take<double>((size_t)C * nf * nf * L * 2);
+    double* tb = cv.take<double>((size_t)C * nf * L * L * 2);
+    if (!cv.ok()) return FK_ENOMEM;
+    if (info) info->bin = 0;
+    FK_HIP(hipEventRecord(ev[0], ctx->stream));
+    FK_HIP(hipMemsetAsync(grid, 0, sizeof(double) * C * nf3, ctx->stream));
+    FK_HIP(hipEventRecord(ev[1], ctx->stream));
+    FK_W_SWITCH(W, launch_spread_3d<WW>(ctx, X, dt, n, xstride, Y, nw, nf, fb, scale, es, grid));
+    FK_HIP(hipGetLastError());
+    FK_HIP(hipEventRecord(ev[2], ctx->stream));
+    hipLaunchKernelGGL(k_fft_line, dim3(C * nf * nf), dim3(256), 0, ctx->stream, grid, 0, (int64_t)1, (int64_t)nf,
+                       (int64_t)0, 1, nf, logn, phihat, K, 1.0, ta, (int64_t)1, (int64_t)L, (int64_t)0);
+    hipLaunchKernelGGL(k_fft_line, dim3(C * nf * L), dim3(256), 0, ctx->stream, ta, 1, (int64_t)L,
+                       (int64_t)nf * L, (int64_t)1, L, nf, logn, phihat, K, 1.0, tb, (int64_t)L, (int64_t)L * L,
+                       (int64_t)1);
+    hipLaunchKernelGGL(k_fft_line, dim3(C * L * L), dim3(256), 0, ctx->stream, tb, 1, (int64_t)L * L,
+                       (int64_t)nf * L * L, (int64_t)1, L * L, nf, logn, phihat, K, sign_scale, out,
+                       (int64_t)L * L, (int64_t)L * L * L, (int64_t)1);
+    FK_HIP(hipGetLastError());
+    FK_HIP(hipEventRecord(ev[3], ctx->stream));
     return FK_OK;
   }
   if (d != 2) return FK_EINVAL;

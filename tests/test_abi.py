@@ -56,7 +56,11 @@ def test_workspace_queries_and_host_validation(lib):
     assert L.fk_gram_workspace_size(None, 2, 10_000_000, 1, 32, C.byref(nb)) == 0
     # 2-D: FP64 grid 2 x 512^2, records 3 words per point, bin tables
     assert nb.value >= 10_000_000 * 12 + 2 * 512 * 512 * 8
-    assert L.fk_gram_workspace_size(None, 3, 100, 1, 8, C.byref(nb)) == 1          # d = 3 rejected
+    assert L.fk_gram_workspace_size(None, 3, 100, 1, 8, C.byref(nb)) == 0          # 3-D: FP64 grid 2 x 128^3
+    assert nb.value >= 2 * 128 ** 3 * 8
+    assert L.fk_gram_workspace_size(None, 3, 100, 1, 32, C.byref(nb)) == 1         # 3-D m > 31 rejected
+    assert L.fk_gram_workspace_size(None, 4, 100, 1, 4, C.byref(nb)) == 1          # d = 4 rejected
+    assert L.fk_fit_workspace_size(None, 3, 100, 1, 8, 1, C.byref(nb)) == 1        # dense fit is 1-D / 2-D
     assert L.fk_gram_workspace_size(None, 1, 0, 1, 8, C.byref(nb)) == 1            # n = 0 rejected
     assert L.fk_gram_workspace_size(None, 1, 100, 1, 65, C.byref(nb)) == 1         # m > 64 rejected
     assert L.fk_solve_workspace_size(None, 2, 32, 16, 64, C.byref(nb)) == 0

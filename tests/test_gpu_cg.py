@@ -222,3 +222,26 @@ def test_restrict_serves_a_sweep_over_s(fk):
         assert np.linalg.norm(th[0] - ref) / np.linalg.norm(ref) <= max(1e-4, 1e-6 * oracle.condition_number(A))
     with pytest.raises(fk.FkError):
         fk.restrict(Mbig, bbig, mmax, mmax + 1)
+
+
+@pytest.mark.parametrize("m,n,ntgt", [(4, 50_001, 1), (9, 200_000, 2)])
+def test_gram_3d_and_cg_fit(fk, m, n, ntgt):
+    # 3-D type-1 stage (FP64-atomic spread, three pruned transforms) against the oracle's direct sums,
+    # then a 3-D fit by conjugate gradients against the oracle's Cholesky solve.
+    print(f"gram 3-D m={m} n={n}", flush=True)
+    rng = np.random.default_rng(300 + m)
+    X = rng.uniform(-np.pi, np.pi, (3, n))
+    Y = np.stack([np.cos(X[0] - t) * np.sin(X[1]) * np.cos(X[2]) + 0.1 * rng.standard_normal(n) for t in range(ntgt)])
+    for dt in (torch.float64, torch.float32):
+        Xd, Yd = torch.from_numpy(X).to(dt).cuda(), torch.from_numpy(Y).to(dt).cuda()
+        M, b = fk.gram(Xd, Yd, m)
+        Xh, Yh = Xd.double().cpu().numpy(), Yd.double().cpu().numpy()
+        Mref, bref = oracle.gram_generator(Xh, m), oracle.rhs(Xh, Yh, m)
+        eps_T = np.abs(M.cpu().numpy() - Mref).max() / Mref[(2 * m,) * 3].real
+        eps_b = np.abs(b.cpu().numpy() - bref).max() / np.abs(Yh).mean()
+        assert eps_T <= 1e-6 and eps_b <= 1e-6, (dt, eps_T, eps_b)
+    lam = 1e-3
+    th = fk.solve_cg(M, b, m, [lam], penalty="sobolev", s=1.5, tol=1e-12).cpu().numpy()
+    A = oracle.system_matrix(Mref, m, lam, oracle.sobolev_weights(m, 3, 1.5))
+    ref = oracle.solve_system(A, bref)
+    assert np.linalg.norm(th[0] - ref) / np.linalg.norm(ref) <= max(1e-4, 1e-6 * oracle.condition_number(A))
