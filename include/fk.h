@@ -220,7 +220,8 @@ fk_status fk_fit(fk_ctx* ctx, int d, int64_t n, fk_dtype dtype, const void* X, i
  * Sec. 2.1 evaluated at new points), by deconvolution, an inverse FFT onto an
  * oversampled grid and exponential-of-semicircle interpolation.  theta is device
  * complex128 [ntheta][N] (Hermitian-symmetric for a real f; the imaginary part of
- * the sum is dropped); out is device float32 [ntheta][nq].  d in {1, 2}. */
+ * the sum is dropped); out is device float32 [ntheta][nq].  d in {1, 2, 3} (d = 3: m <= 31,
+ * ntheta <= 64, oversampled grid up to 128^3 per coefficient set). */
 fk_status fk_predict_workspace_size(fk_ctx* ctx, int d, int m, int ntheta, size_t* bytes);
 fk_status fk_predict(fk_ctx* ctx, int d, int m, int ntheta, const double* theta, int64_t nq,
                      fk_dtype dtype, const void* Xq, float* out, void* ws, size_t ws_bytes);

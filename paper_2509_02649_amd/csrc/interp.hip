@@ -112,20 +112,22 @@ __global__ __launch_bounds__(256) void k_interp(const float* __restrict__ grid, 
   auto ld = [&](int64_t idx) -> double {
     return dt == FK_F64 ? static_cast<const double*>(Xq)[idx] : (double)static_cast<const float*>(Xq)[idx];
   };
-  int i1, i2 = 0;
-  float s1, s2 = 0.f;
+  int i1, i2 = 0, i3 = 0;
+  float s1, s2 = 0.f, s3 = 0.f;
   bool ok = window_of(ld(j), nf, W, &i1, &s1);
-  if (d == 2) ok = window_of(ld(nq + j), nf, W, &i2, &s2) && ok;
+  if (d >= 2) ok = window_of(ld(nq + j), nf, W, &i2, &s2) && ok;
+  if (d == 3) ok = window_of(ld(2 * nq + j), nf, W, &i3, &s3) && ok;
   if (!ok) {
     atomicOr(&flags[kFlagRange], 1);
     for (int t = 0; t < T; ++t) out[(int64_t)t * nq + j] = __int_as_float(0x7fc00000);
     return;
   }
-  float k1[W], k2[W];
+  float k1[W], k2[W], k3[W];
 #pragma unroll
   for (int a = 0; a < W; ++a) {
     k1[a] = es_eval2(s1 + (float)a, es);
-    k2[a] = d == 2 ? es_eval2(s2 + (float)a, es) : 1.f;
+    k2[a] = d >= 2 ? es_eval2(s2 + (float)a, es) : 1.f;
+    k3[a] = d == 3 ? es_eval2(s3 + (float)a, es) : 1.f;
   }
   for (int t = 0; t < T; ++t) {
     float acc = 0.f;
@@ -136,6 +138,27 @@ __global__ __launch_bounds__(256) void k_interp(const float* __restrict__ grid, 
         int l = i1 + a;
         l = l < 0 ? l + nf : (l >= nf ? l - nf : l);
         acc += g[l] * k1[a];
+      }
+    } else if (d == 3) {
+      const float* g = grid + (int64_t)t * nf * nf * nf;
+      for (int a = 0; a < W; ++a) {
+        int l1 = i1 + a;
+        l1 = l1 < 0 ? l1 + nf : (l1 >= nf ? l1 - nf : l1);
+        float ra = 0.f;
+        for (int b = 0; b < W; ++b) {
+          int l2 = i2 + b;
+          l2 = l2 < 0 ? l2 + nf : (l2 >= nf ? l2 - nf : l2);
+          const float* row = g + ((int64_t)l1 * nf + l2) * nf;
+          float rb = 0.f;
+#pragma unroll
+          for (int c = 0; c < W; ++c) {
+            int l3 = i3 + c;
+            l3 = l3 < 0 ? l3 + nf : (l3 >= nf ? l3 - nf : l3);
+            rb += row[l3] * k3[c];
+          }
+          ra += rb * k2[b];
+        }
+        acc += ra * k1[a];
       }
     } else {
       const float* g = grid + (int64_t)t * nf * nf;
@@ -164,15 +187,31 @@ static int ilog2i(int v) {
   return r;
 }
 
+static size_t grid_cells(int d, int nf) {
+  size_t g = 1;
+  for (int a = 0; a < d; ++a) g *= (size_t)nf;
+  return g;
+}
+
 static size_t predict_ws(int d, int m, int T) {
   int nf = 16;
   while (nf < 2 * (2 * m + 1)) nf <<= 1;
   const int L = 2 * m + 1;
   Carve cv(nullptr, 0);
   if (d == 2) cv.take<double>((size_t)T * nf * L * 2);
-  cv.take<double>((size_t)T * (d == 2 ? (size_t)nf * nf : nf));
-  cv.take<float>((size_t)T * (d == 2 ? (size_t)nf * nf : nf));
+  if (d == 3) {
+    cv.take<double>((size_t)T * nf * L * L * 2);
+    cv.take<double>((size_t)T * nf * nf * L * 2);
+  }
+  cv.take<double>((size_t)T * grid_cells(d, nf));
+  cv.take<float>((size_t)T * grid_cells(d, nf));
   return cv.off + 512;
+}
+
+// d = 3 is limited to m <= 31 (grid 128^3) and 64 coefficient sets per call.
+static bool predict_shape_ok(int d, int m, int T) {
+  if (d < 1 || d > 3 || m < 1 || m > 64 || T < 1 || T > 4096) return false;
+  return d < 3 || (m <= 31 && T <= 64);
 }
 
 }  // namespace fk
@@ -180,7 +219,7 @@ static size_t predict_ws(int d, int m, int T) {
 using namespace fk;
 
 extern "C" fk_status fk_predict_workspace_size(fk_ctx* ctx, int d, int m, int ntheta, size_t* bytes) {
-  if (!bytes || (d != 1 && d != 2) || m < 1 || m > 64 || ntheta < 1 || ntheta > 4096) return FK_EINVAL;
+  if (!bytes || !predict_shape_ok(d, m, ntheta)) return FK_EINVAL;
   *bytes = predict_ws(d, m, ntheta);
   return FK_OK;
 }
@@ -205,8 +244,7 @@ extern "C" fk_status fk_predict_workspace_size(fk_ctx* ctx, int d, int m, int nt
 
 extern "C" fk_status fk_predict(fk_ctx* ctx, int d, int m, int T, const double* theta, int64_t nq, fk_dtype dt,
                                 const void* Xq, float* out, void* ws, size_t ws_bytes) {
-  if (!ctx || !theta || !Xq || !out || (d != 1 && d != 2) || m < 1 || m > 64 || T < 1 || T > 4096 || nq < 1)
-    return FK_EINVAL;
+  if (!ctx || !theta || !Xq || !out || !predict_shape_ok(d, m, T) || nq < 1) return FK_EINVAL;
   if (dt != FK_F32 && dt != FK_F64) return FK_EINVAL;
   if (!ws || ws_bytes < predict_ws(d, m, T)) return FK_ENOMEM;
   FK_HIP(hipSetDevice(ctx->device));
@@ -219,13 +257,26 @@ extern "C" fk_status fk_predict(fk_ctx* ctx, int d, int m, int T, const double* 
   const int nf = plan.nf, logn = ilog2i(nf), L = 2 * m + 1;
   Carve cv(ws, ws_bytes);
   double* tmp = d == 2 ? cv.take<double>((size_t)T * nf * L * 2) : nullptr;
-  double* g64 = cv.take<double>((size_t)T * (d == 2 ? (size_t)nf * nf : nf));
-  float* g32 = cv.take<float>((size_t)T * (d == 2 ? (size_t)nf * nf : nf));
+  double* ta = d == 3 ? cv.take<double>((size_t)T * nf * L * L * 2) : nullptr;
+  double* tb = d == 3 ? cv.take<double>((size_t)T * nf * nf * L * 2) : nullptr;
+  double* g64 = cv.take<double>((size_t)T * grid_cells(d, nf));
+  float* g32 = cv.take<float>((size_t)T * grid_cells(d, nf));
   if (!cv.ok()) return FK_ENOMEM;
   if (d == 1) {
     // one line per target: theta[t][q + m] -> g64[t][l] (real part)
     hipLaunchKernelGGL(k_ifft_line, dim3(T), dim3(256), 0, ctx->stream, theta, (int64_t)1, (int64_t)L, (int64_t)0,
                        1, m, phihat, nf, logn, g64, 1, (int64_t)1, (int64_t)nf, (int64_t)0);
+  } else if (d == 3) {
+    // axis 0: for each (t, q2, q3) the line over q1 (stride L^2) -> ta[t][l1][q2][q3]
+    hipLaunchKernelGGL(k_ifft_line, dim3(T * L * L), dim3(256), 0, ctx->stream, theta, (int64_t)L * L,
+                       (int64_t)L * L * L, (int64_t)1, L * L, m, phihat, nf, logn, ta, 0, (int64_t)L * L,
+                       (int64_t)nf * L * L, (int64_t)1);
+    // axis 1: for each (t, l1, q3) the line over q2 (stride L) -> tb[t][l1][l2][q3]
+    hipLaunchKernelGGL(k_ifft_line, dim3(T * nf * L), dim3(256), 0, ctx->stream, ta, (int64_t)L, (int64_t)L * L,
+                       (int64_t)1, L, m, phihat, nf, logn, tb, 0, (int64_t)L, (int64_t)nf * L, (int64_t)1);
+    // axis 2: for each (t, l1, l2) the contiguous line over q3 -> g64[t][l1][l2][l3] real part
+    hipLaunchKernelGGL(k_ifft_line, dim3(T * nf * nf), dim3(256), 0, ctx->stream, tb, (int64_t)1, (int64_t)L,
+                       (int64_t)0, 1, m, phihat, nf, logn, g64, 1, (int64_t)1, (int64_t)nf, (int64_t)0);
   } else {
     // pass A: for each (t, q2): line over q1 (stride L) -> tmp[t][l1][q2] (complex, stride L)
     hipLaunchKernelGGL(k_ifft_line, dim3(T * L), dim3(256), 0, ctx->stream, theta, (int64_t)L, (int64_t)L * L,
@@ -234,7 +285,7 @@ extern "C" fk_status fk_predict(fk_ctx* ctx, int d, int m, int T, const double* 
     hipLaunchKernelGGL(k_ifft_line, dim3(T * nf), dim3(256), 0, ctx->stream, tmp, (int64_t)1, (int64_t)L,
                        (int64_t)0, 1, m, phihat, nf, logn, g64, 1, (int64_t)1, (int64_t)nf, (int64_t)0);
   }
-  const int64_t gsz = (int64_t)T * (d == 2 ? (int64_t)nf * nf : nf);
+  const int64_t gsz = (int64_t)T * (int64_t)grid_cells(d, nf);
   hipLaunchKernelGGL(k_d2f_grid, dim3((gsz + 255) / 256), dim3(256), 0, ctx->stream, g64, g32, gsz);
   EsDev2 es{(float)plan.beta, 2.0f / (float)plan.w};
   const int blocks = (int)((nq + 255) / 256);

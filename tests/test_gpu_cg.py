@@ -245,3 +245,26 @@ def test_gram_3d_and_cg_fit(fk, m, n, ntgt):
     A = oracle.system_matrix(Mref, m, lam, oracle.sobolev_weights(m, 3, 1.5))
     ref = oracle.solve_system(A, bref)
     assert np.linalg.norm(th[0] - ref) / np.linalg.norm(ref) <= max(1e-4, 1e-6 * oracle.condition_number(A))
+
+
+@pytest.mark.parametrize("m,nq", [(3, 1001), (12, 20_000)])
+def test_predict_3d_matches_direct_sum(fk, m, nq):
+    # 3-D type-2: f(x) = Re sum_k theta_k exp(+i k.x) against the oracle's direct sum; bound as in
+    # 1-D / 2-D: eps ||theta||_1 with the FP32 interpolation.
+    print(f"predict 3-D m={m}", flush=True)
+    rng = np.random.default_rng(500 + m)
+    N = (2 * m + 1) ** 3
+    k = oracle.modes(m, 3)
+    decay = 1.0 / (1.0 + (k ** 2).sum(1))
+    th = []
+    for _ in range(2):
+        z = (rng.standard_normal(N) + 1j * rng.standard_normal(N)) * decay
+        th.append(0.5 * (z + np.conj(z[::-1])))
+    th = np.stack(th)
+    Xq = rng.uniform(-np.pi, np.pi, size=(3, nq)).astype(np.float32)
+    f = fk.predict(torch.from_numpy(th).cuda(), torch.from_numpy(Xq).cuda(), m).cpu().numpy()
+    fo = oracle.predict(th, Xq.astype(np.float64), m).real
+    bound = 2e-6 * np.abs(th).sum(axis=1, keepdims=True)
+    err = np.abs(f - fo)
+    print(f"predict 3-D m={m}: max err {err.max():.2e}, bound {bound.min():.2e}")
+    assert (err <= bound).all()

@@ -131,3 +131,14 @@ def test_collocation_penalty_is_the_sampled_operator_energy():
     wrong = np.real(np.conj(th) @ (mu * D[:, None] * oracle.toeplitz_matrix(oracle.gram_generator(Xr, m), m)
                                    * np.conj(D)[None, :]) @ th)
     assert abs(wrong - want) / want > 1e-3
+
+
+def test_predict_3d_small_is_the_explicit_sum():
+    # the oracle's axis-by-axis contraction against a plain loop over the 27 modes of m = 1
+    rng = np.random.default_rng(13)
+    th = rng.standard_normal(27) + 1j * rng.standard_normal(27)
+    Xq = rng.uniform(-np.pi, np.pi, (3, 5))
+    want = np.zeros(5, complex)
+    for i, k in enumerate(oracle.modes(1, 3)):
+        want += th[i] * np.exp(1j * (k @ Xq))
+    np.testing.assert_allclose(oracle.predict(th, Xq, 1), want, atol=1e-13)
