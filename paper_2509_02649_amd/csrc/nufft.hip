@@ -300,6 +300,153 @@ __global__ __launch_bounds__(256) void k_spread_3d(const void* __restrict__ X, f
   }
 }
 
+// ------------------------------------------------------------------ 3-D binned spread
+// Bins are T^3 blocks of window-start cells (nbx = nf / T per axis).  A point's window start
+// i0 = ceil(u - w/2) per axis places it in bin (i0 mod nf) >> tshift, and its whole window then
+// lies in the bin's subgrid of S = T + w - 1 cells per axis starting at the bin origin.
+
+__device__ __forceinline__ bool fixed3(const void* X, fk_dtype dt, int64_t xstride, int64_t j, double scale,
+                                       uint32_t nf_fix, uint32_t U[3], int* flags) {
+  bool ok = true;
+  for (int a = 0; a < 3; ++a) ok = to_fixed(load_coord(X, dt, a * xstride + j), scale, nf_fix, &U[a], flags) && ok;
+  return ok;
+}
+
+__device__ __forceinline__ int bin3_of(const uint32_t U[3], int fb, int w, int nf, int tshift, int nbx) {
+  int b = 0;
+  for (int a = 0; a < 3; ++a) {
+    int i0;
+    float s0;
+    window_start(U[a], fb, w, &i0, &s0);
+    b = b * nbx + ((i0 & (nf - 1)) >> tshift);
+  }
+  return b;
+}
+
+__global__ __launch_bounds__(256) void k_bin3_count(const void* __restrict__ X, fk_dtype dt, int64_t n,
+                                                    int64_t xstride, int nf, int fb, double scale, int w,
+                                                    int tshift, int nbx, uint32_t* __restrict__ cnt, int* flags) {
+  const uint32_t nf_fix = (uint32_t)nf << fb;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t U[3];
+    if (!fixed3(X, dt, xstride, j, scale, nf_fix, U, flags)) continue;
+    atomicAdd(&cnt[bin3_of(U, fb, w, nf, tshift, nbx)], 1u);
+  }
+}
+
+// start[b] = sum of cnt[< b] (start[nb] = valid points), cursor[b] = start[b].  One workgroup.
+__global__ __launch_bounds__(1024) void k_bin3_scan(const uint32_t* __restrict__ cnt, int nb,
+                                                    uint64_t* __restrict__ start, uint64_t* __restrict__ cursor) {
+  __shared__ uint64_t part[1024];
+  const int t = threadIdx.x;
+  const int per = (nb + 1023) / 1024;
+  const int b0 = min(nb, t * per), b1 = min(nb, b0 + per);
+  uint64_t sum = 0;
+  for (int b = b0; b < b1; ++b) sum += cnt[b];
+  part[t] = sum;
+  __syncthreads();
+  if (t == 0) {
+    uint64_t run = 0;
+    for (int k = 0; k < 1024; ++k) {
+      const uint64_t v = part[k];
+      part[k] = run;
+      run += v;
+    }
+    start[nb] = run;
+  }
+  __syncthreads();
+  uint64_t run = part[t];
+  for (int b = b0; b < b1; ++b) {
+    start[b] = run;
+    cursor[b] = run;
+    run += cnt[b];
+  }
+}
+
+// Records of 3 + nw words: the fixed-point coordinates, then the weights (a NaN or Inf weight
+// raises the flag and is stored as 0).
+__global__ __launch_bounds__(256) void k_bin3_scatter(const void* __restrict__ X, fk_dtype dt, int64_t n,
+                                                      int64_t xstride, const void* __restrict__ Y, int nw, int nf,
+                                                      int fb, double scale, int w, int tshift, int nbx,
+                                                      unsigned long long* __restrict__ cursor,
+                                                      uint32_t* __restrict__ rec, int* flags) {
+  const uint32_t nf_fix = (uint32_t)nf << fb;
+  const int R = 3 + nw;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t U[3];
+    if (!fixed3(X, dt, xstride, j, scale, nf_fix, U, flags)) continue;
+    const unsigned long long pos = atomicAdd(&cursor[bin3_of(U, fb, w, nf, tshift, nbx)], 1ull);
+    uint32_t* r = rec + pos * R;
+    r[0] = U[0];
+    r[1] = U[1];
+    r[2] = U[2];
+    for (int c = 0; c < nw; ++c) {
+      float wc = load_weight(Y, dt, (int64_t)c * n + j);
+      if (!(wc == wc) || isinf(wc)) {
+        atomicOr(&flags[kFlagNaN], 1);
+        wc = 0.f;
+      }
+      r[3 + c] = __float_as_uint(wc);
+    }
+  }
+}
+
+// One workgroup per (bin, slice): the slice's points add their windows into the bin's LDS
+// subgrid [C][S][S][S] by FP64 LDS atomics; the subgrid is then added into the FP64 grid.
+template <int W>
+__global__ __launch_bounds__(256) void k_spread_3d_binned(const uint32_t* __restrict__ rec, int nw,
+                                                          const uint64_t* __restrict__ start, int nbx, int T,
+                                                          int nf, int fb, EsDev es, int slices,
+                                                          double* __restrict__ grid) {
+  extern __shared__ double sub[];
+  const int S = T + W - 1, S3 = S * S * S, C = nw + 1, R = 3 + nw;
+  const int bin = blockIdx.x / slices, sl = blockIdx.x - bin * slices;
+  for (int i = threadIdx.x; i < C * S3; i += blockDim.x) sub[i] = 0.0;
+  __syncthreads();
+  const uint64_t p0 = start[bin], len = start[bin + 1] - p0;
+  const uint64_t q0 = p0 + len * sl / slices, q1 = p0 + len * (sl + 1) / slices;
+  const int bz = bin % nbx, by = (bin / nbx) % nbx, bx = bin / (nbx * nbx);
+  const int o[3] = {bx * T, by * T, bz * T};
+  for (uint64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
+    const uint32_t* r = rec + q * R;
+    float k[3][W];
+    int rel[3];
+    for (int a = 0; a < 3; ++a) {
+      int i0;
+      float s0;
+      window_start(r[a], fb, W, &i0, &s0);
+      rel[a] = (i0 & (nf - 1)) - o[a];
+#pragma unroll
+      for (int t = 0; t < W; ++t) k[a][t] = es_eval(s0 + (float)t, es);
+    }
+    for (int c = 0; c < C; ++c) {
+      const float wc = c == 0 ? 1.0f : __uint_as_float(r[2 + c]);
+      double* g = sub + c * S3;
+      for (int a1 = 0; a1 < W; ++a1) {
+        const float v1 = wc * k[0][a1];
+        for (int a2 = 0; a2 < W; ++a2) {
+          const float v12 = v1 * k[1][a2];
+          double* row = g + ((rel[0] + a1) * S + (rel[1] + a2)) * S + rel[2];
+#pragma unroll
+          for (int a3 = 0; a3 < W; ++a3) atomicAdd(&row[a3], (double)(v12 * k[2][a3]));
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < C * S3; i += blockDim.x) {
+    const double v = sub[i];
+    if (v == 0.0) continue;
+    const int c = i / S3, cell = i - c * S3;
+    const int x = cell / (S * S), y = (cell / S) % S, z = cell % S;
+    int gx = o[0] + x, gy = o[1] + y, gz = o[2] + z;
+    gx -= gx >= nf ? nf : 0;
+    gy -= gy >= nf ? nf : 0;
+    gz -= gz >= nf ? nf : 0;
+    atomicAdd(&grid[(((int64_t)c * nf + gx) * nf + gy) * nf + gz], v);
+  }
+}
+
 // ------------------------------------------------------------------ 2-D binned spread
 // Bins are T x T tiles of the nf x nf grid: nbx = nf / T bins per axis.
 
@@ -601,6 +748,11 @@ size_t type1_workspace(int d, int64_t n, int nw, int K, double eps) {
       cv.take<double>((size_t)C * nf * nf * nf);      // FP64 grid
       cv.take<double>((size_t)C * nf * nf * L * 2);   // after the axis-2 transform
       cv.take<double>((size_t)C * nf * L * L * 2);    // after the axis-1 transform
+      const size_t nb = (size_t)(nf / 2) * (nf / 2) * (nf / 2);   // the smallest bins (T = 2)
+      cv.take<uint32_t>(nb);                          // counts
+      cv.take<uint64_t>(nb + 1);                      // starts
+      cv.take<uint64_t>(nb);                          // cursors
+      cv.take<uint32_t>((size_t)n * (3 + nw));        // records
       return cv.off;
     }
     cv.take<double>((size_t)C * nf * nf);          // FP64 grid
@@ -631,6 +783,14 @@ static void launch_spread_1d(fk_ctx* ctx, int blocks, size_t lds, const void* X,
                              int64_t chunk) {
   hipLaunchKernelGGL(k_spread_1d<W>, dim3(blocks), dim3(256), lds, ctx->stream, X, dt, n, Y, nw, 1, nf,
                      fb, scale, es, grid, ctx->flags, chunk);
+}
+
+template <int W>
+static void launch_spread_3d_binned(fk_ctx* ctx, int blocks, size_t lds, const uint32_t* rec, int nw,
+                                    const uint64_t* start, int nbx, int T, int nf, int fb, EsDev es, int slices,
+                                    double* grid) {
+  hipLaunchKernelGGL(k_spread_3d_binned<W>, dim3(blocks), dim3(256), lds, ctx->stream, rec, nw, start, nbx, T, nf,
+                     fb, es, slices, grid);
 }
 
 template <int W>
@@ -714,12 +874,54 @@ fk_status type1(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int64
     double* grid = cv.take<double>((size_t)C * nf3);
     double* ta = cv.take<double>((size_t)C * nf * nf * L * 2);
     double* tb = cv.take<double>((size_t)C * nf * L * L * 2);
+    // bins of T^3 window-start cells, T the largest of 8, 4, 2 whose subgrid fits 96 KB of LDS
+    int T3 = 0;
+    for (int t = 8; t >= 2; t >>= 1) {
+      const size_t Sx = (size_t)(t + W - 1);
+      if (nf % t == 0 && (size_t)C * Sx * Sx * Sx * sizeof(double) <= 96 * 1024) {
+        T3 = t;
+        break;
+      }
+    }
+    const int nbx3 = T3 ? nf / T3 : 1;
+    const int64_t nb3 = (int64_t)nbx3 * nbx3 * nbx3;
+    uint32_t* cnt3 = nullptr;
+    uint64_t *start3 = nullptr, *cursor3 = nullptr;
+    uint32_t* rec3 = nullptr;
+    if (T3) {
+      cnt3 = cv.take<uint32_t>((size_t)nb3);
+      start3 = cv.take<uint64_t>((size_t)nb3 + 1);
+      cursor3 = cv.take<uint64_t>((size_t)nb3);
+      rec3 = cv.take<uint32_t>((size_t)n * (3 + nw));
+    }
     if (!cv.ok()) return FK_ENOMEM;
-    if (info) info->bin = 0;
+    if (info) info->bin = T3;
     FK_HIP(hipEventRecord(ev[0], ctx->stream));
     FK_HIP(hipMemsetAsync(grid, 0, sizeof(double) * C * nf3, ctx->stream));
+    const int pblocks = (int)std::min<int64_t>(65536, std::max<int64_t>(1, (n + 255) / 256));
+    if (T3) {
+      const int tshift = ilog2(T3);
+      FK_HIP(hipMemsetAsync(cnt3, 0, sizeof(uint32_t) * nb3, ctx->stream));
+      hipLaunchKernelGGL(k_bin3_count, dim3(pblocks), dim3(256), 0, ctx->stream, X, dt, n, xstride, nf, fb, scale, W,
+                         tshift, nbx3, cnt3, ctx->flags);
+      hipLaunchKernelGGL(k_bin3_scan, dim3(1), dim3(1024), 0, ctx->stream, cnt3, (int)nb3, start3, cursor3);
+      hipLaunchKernelGGL(k_bin3_scatter, dim3(pblocks), dim3(256), 0, ctx->stream, X, dt, n, xstride, Y, nw, nf, fb,
+                         scale, W, tshift, nbx3, reinterpret_cast<unsigned long long*>(cursor3), rec3, ctx->flags);
+      FK_HIP(hipGetLastError());
+    }
     FK_HIP(hipEventRecord(ev[1], ctx->stream));
-    FK_W_SWITCH(W, launch_spread_3d<WW>(ctx, X, dt, n, xstride, Y, nw, nf, fb, scale, es, grid));
+    if (T3) {
+      const int64_t per_bin = (n + nb3 - 1) / nb3;
+      const int slices = (int)std::max<int64_t>(1, std::min<int64_t>(256, (per_bin + 2047) / 2048));
+      const int S = T3 + W - 1;
+      const size_t lds = sizeof(double) * C * S * S * S;
+      const int64_t blocks = nb3 * slices;
+      if (blocks > 0x7fffffff) return FK_EINVAL;
+      FK_W_SWITCH(W, launch_spread_3d_binned<WW>(ctx, (int)blocks, lds, rec3, nw, start3, nbx3, T3, nf, fb, es, slices,
+                                                 grid));
+    } else {
+      FK_W_SWITCH(W, launch_spread_3d<WW>(ctx, X, dt, n, xstride, Y, nw, nf, fb, scale, es, grid));
+    }
     FK_HIP(hipGetLastError());
     FK_HIP(hipEventRecord(ev[2], ctx->stream));
     hipLaunchKernelGGL(k_fft_line, dim3(C * nf * nf), dim3(256), 0, ctx->stream, grid, 0, (int64_t)1, (int64_t)nf,
