@@ -96,7 +96,7 @@ def _fft_roofline(fk, torch, M, m, nvec, ctx, reps=5):
     ms = e0.elapsed_time(e1) / reps
     nbytes = 16.0 * (nvec * (2 * N + 4 * Lf * n0) + Lf * Lf)
     achieved = nbytes / (ms * 1e-3) / 1e9
-    return {"bound": "hbm", "kernel": "k_line_fft", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+    return {"bound": "hbm", "kernel": "k_line_fft256" if Lf == 256 else "k_line_fft", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None, "ms_per_product": ms, "vectors": nvec}
 
 

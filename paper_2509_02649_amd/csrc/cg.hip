@@ -161,6 +161,111 @@ __global__ __launch_bounds__(FT) void k_line_fft(LinePass a, int L, int64_t nlin
     for (int t = lane; t < a.nout; t += 64) dst[t * a.inner] = B[t];
 }
 
+// ---- Lf = 256: four-step transform, 16 lanes per line, 16 points per lane in registers.
+// A line's point t lives in lane t % 16, register t / 16, before and after each transform
+// (natural order in and out), so forward, spectrum product and inverse chain in registers with
+// one LDS transpose per transform.  All passes of a call with Lf = 256 take this kernel, the
+// spectrum included, so its natural order is consistent.
+constexpr int R16_LINES = FT / 16;   // lines per workgroup
+constexpr int R16_ROW = 17;          // padded row of the 16 x 16 transpose (no bank conflicts)
+
+__device__ __forceinline__ double2 w256(const double2* tw, int e, bool inv) {
+  e &= 255;
+  const double2 v = e >= 128 ? make_double2(-tw[e - 128].x, -tw[e - 128].y) : tw[e];
+  return inv ? cconj(v) : v;
+}
+
+// In place: (a, b, c, d) -> the 4-point DFT with W4 = -i (forward) or +i (inverse).
+__device__ __forceinline__ void dft4(double2& a, double2& b, double2& c, double2& d, bool inv) {
+  const double2 s0 = cadd(a, c), d0 = csub(a, c), s1 = cadd(b, d), d1 = csub(b, d);
+  const double2 jd1 = inv ? make_double2(-d1.y, d1.x) : make_double2(d1.y, -d1.x);
+  a = cadd(s0, s1);
+  c = csub(s0, s1);
+  b = cadd(d0, jd1);
+  d = csub(d0, jd1);
+}
+
+// v[k] <- sum_n v[n] W16^{nk}: 4 x 4 with twiddles W16^{n_a k_b}, n = n_a + 4 n_b, k = k_b + 4 k_a.
+__device__ __forceinline__ void dft16(double2 v[16], const double2* tw, bool inv) {
+  double2 A[16];
+#pragma unroll
+  for (int na = 0; na < 4; ++na) {
+    double2 a = v[na], b = v[na + 4], c = v[na + 8], d = v[na + 12];
+    dft4(a, b, c, d, inv);
+    A[na * 4 + 0] = a;
+    A[na * 4 + 1] = na ? cmul(b, w256(tw, 16 * na, inv)) : b;
+    A[na * 4 + 2] = na ? cmul(c, w256(tw, 32 * na, inv)) : c;
+    A[na * 4 + 3] = na ? cmul(d, w256(tw, 48 * na, inv)) : d;
+  }
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb) {
+    double2 a = A[kb], b = A[4 + kb], c = A[8 + kb], d = A[12 + kb];
+    dft4(a, b, c, d, inv);
+    v[kb] = a;
+    v[kb + 4] = b;
+    v[kb + 8] = c;
+    v[kb + 12] = d;
+  }
+}
+
+// 256-point DFT of the line held by 16 lanes (lane l16 holds points l16 + 16 r in v[r]); X is the
+// line's 16 x R16_ROW LDS transpose buffer.  Every thread of the workgroup calls it together.
+__device__ __forceinline__ void fft256(double2 v[16], double2* X, const double2* tw, int l16, bool inv) {
+  dft16(v, tw, inv);
+#pragma unroll
+  for (int k1 = 0; k1 < 16; ++k1) X[k1 * R16_ROW + l16] = cmul(v[k1], w256(tw, l16 * k1, inv));
+  __syncthreads();
+#pragma unroll
+  for (int n2 = 0; n2 < 16; ++n2) v[n2] = X[l16 * R16_ROW + n2];
+  __syncthreads();
+  dft16(v, tw, inv);
+}
+
+// Dynamic LDS: R16_LINES transpose buffers of 16 x R16_ROW entries, then 128 twiddles.
+__global__ __launch_bounds__(FT) void k_line_fft256(LinePass a, int64_t nlines, const int* __restrict__ active,
+                                                    const double2* __restrict__ tw_g) {
+  extern __shared__ __align__(16) double2 lds[];
+  double2* tw = lds + R16_LINES * 16 * R16_ROW;
+  for (int k = threadIdx.x; k < 128; k += FT) tw[k] = tw_g[k];
+  const int ls = threadIdx.x >> 4, l16 = threadIdx.x & 15;
+  const int64_t line = (int64_t)blockIdx.x * R16_LINES + ls;
+  bool live = line < nlines;
+  int64_t sys = 0, li = 0;
+  if (live) {
+    sys = line / a.lines_per_sys;
+    li = line - sys * a.lines_per_sys;
+    if (active && !active[sys]) live = false;
+  }
+  const int64_t o = li / a.inner, i = li - o * a.inner;
+  const double2* src = a.in + sys * a.in_sys + o * (a.nin * a.inner) + i;
+  double2* dst = a.out + sys * a.out_sys + o * (a.nout * a.inner) + i;
+  double2 v[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int t = l16 + 16 * r;
+    v[r] = (live && t < a.nin) ? src[t * a.inner] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  double2* X = lds + ls * 16 * R16_ROW;
+  if (a.mode != kInverse) fft256(v, X, tw, l16, false);
+  if (a.mode == kConvolve) {
+    const double2* S = a.spec + o * 256;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const double2 sp = live ? S[l16 + 16 * r] : make_double2(0.0, 0.0);
+      v[r] = cmul(v[r], make_double2(sp.x * a.spec_scale, sp.y * a.spec_scale));
+    }
+  }
+  if (a.mode != kForward) fft256(v, X, tw, l16, true);
+  if (live) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int t = l16 + 16 * r;
+      if (t < a.nout) dst[t * a.inner] = v[r];
+    }
+  }
+}
+
 // tw[k] = e^{-2 pi i k / L}, k < L / 2.
 __global__ void k_twiddles(int L, double2* __restrict__ tw) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -419,6 +524,13 @@ fk_status run_pass(hipStream_t st, const ToepGeom& g, const int64_t* E, int axis
   const int64_t nlines = lines * nsys;
   const int64_t blocks = (nlines + FLINES - 1) / FLINES;
   if (blocks > 0x7fffffff) return FK_EINVAL;
+  if (g.L == 256) {
+    const int64_t b256 = (nlines + R16_LINES - 1) / R16_LINES;
+    if (b256 > 0x7fffffff) return FK_EINVAL;
+    const size_t lds = sizeof(double2) * ((size_t)R16_LINES * 16 * R16_ROW + 128);
+    hipLaunchKernelGGL(k_line_fft256, dim3((unsigned)b256), dim3(FT), lds, st, a, nlines, active, g.tw);
+    return hipGetLastError() == hipSuccess ? FK_OK : FK_EHIP;
+  }
   const size_t lds = sizeof(double2) * ((size_t)FLINES * g.L + g.L / 2);
   hipLaunchKernelGGL(k_line_fft, dim3((unsigned)blocks), dim3(FT), lds, st, a, g.L, nlines, active, g.tw);
   return hipGetLastError() == hipSuccess ? FK_OK : FK_EHIP;
