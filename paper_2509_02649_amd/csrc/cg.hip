@@ -232,8 +232,15 @@ __global__ __launch_bounds__(FT) void k_line_fft256(LinePass a, int64_t nlines, 
   bool live = line < nlines;
   int64_t sys = 0, li = 0;
   if (live) {
-    sys = line / a.lines_per_sys;
-    li = line - sys * a.lines_per_sys;
+    if (a.mode == kConvolve) {
+      // systems fastest: the lines of a workgroup share one spectrum line
+      const int64_t nsys = nlines / a.lines_per_sys;
+      li = line / nsys;
+      sys = line - li * nsys;
+    } else {
+      sys = line / a.lines_per_sys;
+      li = line - sys * a.lines_per_sys;
+    }
     if (active && !active[sys]) live = false;
   }
   const int64_t o = li / a.inner, i = li - o * a.inner;
