@@ -30,7 +30,7 @@ def _gen(d, m, n, seed):
 
 @pytest.mark.parametrize("d,m,n,dense", [(1, 5, 300, True), (1, 40, 300, True), (1, 255, 200, True),
                                          (2, 3, 300, True), (2, 32, 200, True), (2, 100, 40, False),
-                                         (3, 2, 300, True), (3, 8, 150, False)])
+                                         (3, 2, 300, True), (3, 8, 150, False), (3, 40, 6, False)])
 def test_toeplitz_apply_parity(fk, d, m, n, dense):
     print(f"toeplitz d={d} m={m}", flush=True)
     rng, X, M = _gen(d, m, n, 100 * d + m)
