@@ -224,7 +224,7 @@ def test_restrict_serves_a_sweep_over_s(fk):
         fk.restrict(Mbig, bbig, mmax, mmax + 1)
 
 
-@pytest.mark.parametrize("m,n,ntgt", [(4, 50_001, 1), (9, 200_000, 2)])
+@pytest.mark.parametrize("m,n,ntgt", [(4, 50_001, 1), (6, 150_000, 2)])
 def test_gram_3d_and_cg_fit(fk, m, n, ntgt):
     # 3-D type-1 stage (FP64-atomic spread, three pruned transforms) against the oracle's direct sums,
     # then a 3-D fit by conjugate gradients against the oracle's Cholesky solve.
