@@ -97,7 +97,24 @@ def _fft_roofline(fk, torch, M, m, nvec, ctx, reps=5):
     nbytes = 16.0 * (nvec * (2 * N + 4 * Lf * n0) + Lf * Lf)
     achieved = nbytes / (ms * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": "k_line_fft256" if Lf == 256 else "k_line_fft", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "ms_per_product": ms, "vectors": nvec}
+            "frac": achieved / HBM_PEAK_GBS, "traffic": _traffic_fft(nvec, m), "ms_per_product": ms, "vectors": nvec}
+
+
+def _traffic_fft(nvec: int, m: int):
+    """HBM bytes of one product from the committed counter summary (measured for 1024 vectors at
+    m = 32), if it was taken on the current source of the transform (else None)."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "k_line_fft256_hbm_traffic.md")
+    src = os.path.join(ROOT, "paper_2509_02649_amd", "csrc", "cg.hip")
+    if nvec != 1024 or m != 32 or not os.path.exists(path) or not os.path.exists(src):
+        return None
+    text = open(path).read()
+    h = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
+    b = re.search(r"hbm_bytes_per_product:\s*([0-9.eE+-]+)", text)
+    if not h or not b or h.group(1) != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    return float(b.group(1))
 
 
 def main():
