@@ -182,7 +182,8 @@ fk_status fk_restrict(fk_ctx* ctx, int d, int m_from, int m_to, int ntgt, const 
  * ntgt * nlam <= 65536.  The call synchronises the context's stream every 4 iterations.
  * Returns FK_ENOCONV when some system has not met tol after maxit iterations (theta_out then
  * holds the last iterates), FK_ENOTPD when <p, A p> <= 0 for some system (A not positive
- * definite in FP64), FK_EINVAL when the centre M[0] is not positive. */
+ * definite in FP64), FK_ENAN when b holds a NaN or Inf or a NaN reaches <p, A p>, FK_EINVAL
+ * when the centre M[0] is not positive. */
 fk_status fk_toeplitz_apply_workspace_size(fk_ctx* ctx, int d, int m, int nvec, size_t* bytes);
 fk_status fk_toeplitz_apply(fk_ctx* ctx, int d, int m, const double* M, int nvec, const double* x,
                             double* y, void* ws, size_t ws_bytes);

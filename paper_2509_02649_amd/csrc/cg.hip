@@ -353,7 +353,7 @@ __global__ __launch_bounds__(CT) void k_cg_init(const double2* __restrict__ b, i
                                                 double2* __restrict__ r, double2* __restrict__ p,
                                                 double* __restrict__ rho, double* __restrict__ bb,
                                                 int* __restrict__ active, int* __restrict__ iters,
-                                                int* __restrict__ nactive) {
+                                                int* __restrict__ nactive, int* flags) {
   __shared__ double red[CT / 64];
   const int s = blockIdx.x;
   const double lam = lams[s / ntgt];
@@ -378,7 +378,8 @@ __global__ __launch_bounds__(CT) void k_cg_init(const double2* __restrict__ b, i
     rho[s] = rz;
     bb[s] = b2;
     iters[s] = 0;
-    const int on = b2 > 0.0;
+    if (!(b2 == b2) || isinf(b2)) atomicOr(&flags[kFlagNaN], 1);   // a NaN or Inf right-hand side
+    const int on = b2 > 0.0 && !isinf(b2);
     active[s] = on;
     if (on) atomicAdd(nactive, 1);
   }
@@ -416,7 +417,7 @@ __global__ __launch_bounds__(CT) void k_cg_step(const double2* __restrict__ qraw
     if (threadIdx.x == 0) {
       active[s] = 0;
       atomicSub(nactive, 1);
-      atomicOr(&flags[kFlagNotPD], 1);
+      atomicOr(&flags[pq == pq ? kFlagNotPD : kFlagNaN], 1);   // NaN: a NaN in M or b reached the product
     }
     return;
   }
@@ -719,7 +720,7 @@ fk_status cg_solve_impl(fk_ctx* ctx, int d, int m, const double* M, int ntgt, co
   };
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, counter, 64);
   hipLaunchKernelGGL(k_cg_init, dim3(nsys), dim3(CT), 0, st, bv, ntgt, g.N, dlam, dpw, m0, cl, theta, r, p, rho, bb,
-                     active, iters, counter);
+                     active, iters, counter, ctx->flags);
   const double tol2 = tol * tol;
   int done_it = 0;
   int nact = 1;

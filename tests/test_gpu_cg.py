@@ -108,6 +108,17 @@ def test_solve_cg_edge_cases(fk):
     with pytest.raises(fk.FkError) as e:
         fk.solve_cg(_cplx(M), _cplx(b), m, [0.0])
     assert e.value.code == 1
+    # a NaN in b, or in an off-centre entry of M: FK_ENAN, not a silent zero or a pivot error
+    bn = b.copy()
+    bn[2, 5] = np.nan
+    with pytest.raises(fk.FkError) as e:
+        fk.solve_cg(_cplx(M), _cplx(bn), m, [1e-3])
+    assert e.value.code == 3
+    Mn = M.copy()
+    Mn[0, 3] = np.nan
+    with pytest.raises(fk.FkError) as e:
+        fk.solve_cg(_cplx(Mn), _cplx(b), m, [1e-3])
+    assert e.value.code == 3
 
 
 def test_solve_cg_batched_shape_against_dense_path(fk):
