@@ -12,8 +12,8 @@ evaluated slowly in float64 on the CPU:
   "Covariance vector" and "Covariance matrix"), plus the additive-model block
   Gram (Sec. 5, "Complexity").
 * ``penalty``  - the Sobolev weights (Sec. 3.1), the low-bias identity (Sec. 3.2),
-  the physics-informed penalty lambda S^2 + mu D^* C D on a box (Sec. 4,
-  "Tractable domains"), its collocation form (Sec. 4, intractable domains) and the
+  the physics-informed penalty lambda S^2 + mu D^* C D on a box for any linear
+  constant-coefficient operator (Sec. 4, "Tractable domains"), its collocation form (Sec. 4, intractable domains) and the
   additive block penalty (Sec. 5).
 * ``solve``    - the normal equations of eq. (kenrel_reg) solved by an FP64
   LAPACK Cholesky (zpotrf/zpotrs through scipy).
@@ -39,7 +39,8 @@ brute force or a high-precision sum; none is "parity unpinned".
 from .fourier import (modes, gram_generator, rhs, fourier_entry, toeplitz_matrix, design_matrix,
                       additive_blocks, additive_rhs)
 from .penalty import (sobolev_weights, sobolev_bessel_weights, piml_box_fourier_matrix,
-                      heat_symbol, piml_heat_penalty, additive_penalty, collocation_penalty)
+                      heat_symbol, piml_heat_penalty, pde_symbol, piml_box_penalty, additive_penalty,
+                      collocation_penalty)
 from .solve import system_matrix, solve_system, condition_number, fit
 from .cg import toeplitz_apply, toeplitz_apply_rows, pcg
 from .predict import predict, predict_additive
@@ -50,7 +51,7 @@ __all__ = [
     "modes", "gram_generator", "rhs", "fourier_entry", "toeplitz_matrix", "design_matrix",
     "additive_blocks", "additive_rhs",
     "sobolev_weights", "sobolev_bessel_weights", "piml_box_fourier_matrix", "heat_symbol",
-    "piml_heat_penalty", "additive_penalty", "collocation_penalty",
+    "piml_heat_penalty", "pde_symbol", "piml_box_penalty", "additive_penalty", "collocation_penalty",
     "system_matrix", "solve_system", "condition_number", "fit", "toeplitz_apply", "toeplitz_apply_rows", "pcg",
     "predict", "predict_additive", "krr_theta",
     "heldout_mse", "heldout_mse_quadratic", "mse_gradients",

@@ -20,17 +20,30 @@ def test_sobolev_weights_closed_form():
 
 def test_box_fourier_matrix_against_quadrature():
     m = 2
-    lo, hi = (-np.pi / 2, -np.pi / 2), (np.pi / 2, np.pi / 2)
-    C = oracle.piml_box_fourier_matrix(m, lo, hi, L=np.pi / 2)
     ks = oracle.modes(m, 2)
     rng = np.random.default_rng(0)
-    for _ in range(6):
-        i, j = rng.integers(0, ks.shape[0], 2)
-        q = ks[i] - ks[j]
-        re = integrate.dblquad(lambda y, x: np.cos(q[0] * x + q[1] * y), lo[0], hi[0], lo[1], hi[1])[0]
-        im = integrate.dblquad(lambda y, x: np.sin(q[0] * x + q[1] * y), lo[0], hi[0], lo[1], hi[1])[0]
-        assert abs(C[i, j] - (re + 1j * im) / (2 * np.pi) ** 2) < 1e-10
+    # entries: (2 pi)^-2 int_box exp(i <l - k, x>) dx, on the centred box and on an off-centre one
+    for lo, hi in [((-np.pi / 2, -np.pi / 2), (np.pi / 2, np.pi / 2)), ((-0.4, 0.1), (1.3, 2.0))]:
+        C = oracle.piml_box_fourier_matrix(m, lo, hi, L=np.pi / 2)
+        for _ in range(6):
+            i, j = rng.integers(0, ks.shape[0], 2)
+            q = ks[j] - ks[i]
+            re = integrate.dblquad(lambda y, x: np.cos(q[0] * x + q[1] * y), lo[0], hi[0], lo[1], hi[1])[0]
+            im = integrate.dblquad(lambda y, x: np.sin(q[0] * x + q[1] * y), lo[0], hi[0], lo[1], hi[1])[0]
+            assert abs(C[i, j] - (re + 1j * im) / (2 * np.pi) ** 2) < 1e-10
+    # theta^* C theta is the box integral of |f_theta|^2 (the identity the estimator of Sec. 4 needs),
+    # by Gauss-Legendre quadrature of the oracle's predictor on the off-centre box
+    th = rng.standard_normal(ks.shape[0]) + 1j * rng.standard_normal(ks.shape[0])
+    lo, hi = (-0.4, 0.1), (1.3, 2.0)
+    C = oracle.piml_box_fourier_matrix(m, lo, hi, L=np.pi / 2)
+    xg, wg = np.polynomial.legendre.leggauss(30)
+    a = [0.5 * (hi[i] - lo[i]) * xg + 0.5 * (hi[i] + lo[i]) for i in range(2)]
+    W = np.outer(0.5 * (hi[0] - lo[0]) * wg, 0.5 * (hi[1] - lo[1]) * wg)
+    T, Xx = np.meshgrid(a[0], a[1], indexing="ij")
+    f = oracle.predict(th, np.stack([T.ravel(), Xx.ravel()]), m).reshape(T.shape)
+    assert abs(np.sum(W * np.abs(f) ** 2) / (2 * np.pi) ** 2 - np.real(np.conj(th) @ C @ th)) < 1e-12
     # the symmetric box gives a real symmetric matrix with the sinc closed form
+    C = oracle.piml_box_fourier_matrix(m, (-np.pi / 2, -np.pi / 2), (np.pi / 2, np.pi / 2), L=np.pi / 2)
     q = ks[:, None, :] - ks[None, :, :]
     sinc = lambda t: np.where(t == 0, np.pi, 2 * np.sin(t * np.pi / 2) / np.where(t == 0, 1, t))
     np.testing.assert_allclose(C, sinc(q[..., 0]) * sinc(q[..., 1]) / (2 * np.pi) ** 2, atol=1e-14)
@@ -218,3 +231,134 @@ def test_gradients_against_central_differences():
     eps = 1e-6
     fdt = (Lq(th + eps * dth) - Lq(th - eps * dth)) / (2 * eps)
     assert abs(fdt - 2 * np.real(np.conj(g) @ dth)) < 1e-7 * max(1.0, abs(fdt))
+
+
+# ---------------------------------------------------------------- condition number and additive penalty
+
+def _unitary(n, seed):
+    rng = np.random.default_rng(seed)
+    Z = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    Q, R = np.linalg.qr(Z)
+    return Q * (np.diag(R) / np.abs(np.diag(R)))[None, :]
+
+
+def test_condition_number_of_known_spectrum():
+    # diagonal: the ratio of the extreme entries, whatever their order
+    assert oracle.condition_number(np.diag([3.0, 0.5, 12.0, 2.0])) == pytest.approx(24.0, rel=1e-14)
+    # Q diag(ev) Q^* with the spectrum 10^linspace(0, 4): kappa = 1e4 exactly, and no diagonal
+    # entry or Gershgorin bound gives it (a ratio of diagonal entries would read far less)
+    ev = 10.0 ** np.linspace(0.0, 4.0, 24)
+    Q = _unitary(24, 7)
+    A = (Q * ev[None, :]) @ np.conj(Q).T
+    A = 0.5 * (A + np.conj(A).T)
+    assert oracle.condition_number(A) == pytest.approx(1e4, rel=1e-9)
+    dg = np.real(np.diag(A))
+    assert dg.max() / dg.min() < 1e3
+    # scaling leaves it unchanged; the inverse has the same condition number
+    assert oracle.condition_number(5.0 * A) == pytest.approx(1e4, rel=1e-9)
+    assert oracle.condition_number(np.linalg.inv(A)) == pytest.approx(1e4, rel=1e-8)
+
+
+def test_condition_number_of_the_2d_sobolev_system_brackets_the_weights():
+    # Sigma of equispaced points on the torus is the identity (M = delta), so
+    # kappa(I + lambda diag(p)) = (1 + lambda p_max) / (1 + lambda p_min) exactly
+    m, d, s, lam = 3, 2, 2.0, 1e-2
+    g = np.arange(16) * (2 * np.pi / 16) - np.pi
+    X = np.stack([np.repeat(g, 16), np.tile(g, 16)])
+    M = oracle.gram_generator(X, m)
+    p = oracle.sobolev_weights(m, d, s)
+    A = oracle.system_matrix(M, m, lam, p)
+    assert oracle.condition_number(A) == pytest.approx((1 + lam * p.max()) / (1 + lam * p.min()), rel=1e-10)
+
+
+def test_additive_penalty_closed_form_in_block_order():
+    # one block of Sobolev weights 1 + |k|^(2s), k = -m..m, per component, components in order
+    np.testing.assert_array_equal(oracle.additive_penalty(2, 3, 1.5), np.array([9.0, 2.0, 1.0, 2.0, 9.0] * 3))
+    np.testing.assert_array_equal(oracle.additive_penalty(2, 2, 1.0), np.array([5.0, 2.0, 1.0, 2.0, 5.0] * 2))
+    np.testing.assert_array_equal(oracle.additive_penalty(1, 4, 0.0), np.full(12, 2.0))
+
+
+def test_additive_penalty_is_the_sum_of_component_sobolev_norms():
+    # theta^* diag(p) theta = sum_a (2 pi)^-1 int |f_a|^2 + |f_a'|^2 dx (s = 1), for
+    # f_a(x) = sum_k theta_{a,k} exp(i k x); the derivative is taken by central differences
+    rng = np.random.default_rng(8)
+    d, m = 3, 4
+    L = 2 * m + 1
+    th = rng.standard_normal(d * L) + 1j * rng.standard_normal(d * L)
+    quad = np.real(np.conj(th) @ (oracle.additive_penalty(m, d, 1.0) * th))
+    xg, wg = np.polynomial.legendre.leggauss(64)
+    x = np.pi * xg
+    h = 1e-5
+    total = 0.0
+    for a in range(d):
+        f = lambda u: oracle.predict(th[a * L:(a + 1) * L], u[None, :], m)
+        fp = (f(x + h) - f(x - h)) / (2 * h)
+        total += np.sum(np.pi * wg * (np.abs(f(x)) ** 2 + np.abs(fp) ** 2)) / (2 * np.pi)
+    assert abs(total - quad) / quad < 1e-8
+
+
+# ---------------------------------------------------------------- general operators on a box
+
+def _box_integral_of_operator(th, m, d, lo, hi, apply_op, npts=48):
+    """(2 pi)^-d int_box |op f_theta|^2 by Gauss-Legendre quadrature, op applied by finite differences."""
+    xg, wg = np.polynomial.legendre.leggauss(npts)
+    axes = [0.5 * (hi[a] - lo[a]) * xg + 0.5 * (hi[a] + lo[a]) for a in range(d)]
+    wts = [0.5 * (hi[a] - lo[a]) * wg for a in range(d)]
+    grid = np.meshgrid(*axes, indexing="ij")
+    W = wts[0] if d == 1 else np.outer(wts[0], wts[1])
+    f = lambda *u: oracle.predict(th, np.stack([g.ravel() for g in u]), m).reshape(u[0].shape)
+    v = apply_op(f, *grid)
+    return np.sum(W * np.abs(v) ** 2) / (2 * np.pi) ** d
+
+
+def test_pde_symbol_reduces_to_the_heat_symbol():
+    np.testing.assert_array_equal(oracle.pde_symbol(3, 2, [[1, 0], [0, 2]], [1.0, -1.0]), oracle.heat_symbol(3))
+
+
+@pytest.mark.parametrize("case", ["1d_paper", "2d_mixed"])
+def test_pde_box_penalty_quadratic_form_against_quadrature(case):
+    rng = np.random.default_rng(30)
+    if case == "1d_paper":
+        # the paper's one-dimensional constraint f' - f = 0 on Omega = ]0, 1[ (L = pi/2: radians = x)
+        d, m, lo, hi = 1, 6, (0.0,), (1.0,)
+        alphas, coefs = [[1], [0]], [1.0, -1.0]
+        h = 1e-5
+        op = lambda f, x: (f(x + h) - f(x - h)) / (2 * h) - f(x)
+    else:
+        # d_t d_x + 0.5 d_xx + d_t - 2 on an off-centre box
+        d, m, lo, hi = 2, 3, (-1.0, -0.3), (0.5, 1.2)
+        alphas, coefs = [[1, 1], [0, 2], [1, 0], [0, 0]], [1.0, 0.5, 1.0, -2.0]
+        h = 1e-3
+        op = lambda f, t, x: ((f(t + h, x + h) - f(t + h, x - h) - f(t - h, x + h) + f(t - h, x - h)) / (4 * h * h)
+                              + 0.5 * (f(t, x + h) - 2 * f(t, x) + f(t, x - h)) / (h * h)
+                              + (f(t + h, x) - f(t - h, x)) / (2 * h) - 2 * f(t, x))
+    N = (2 * m + 1) ** d
+    th = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    th = 0.5 * (th + np.conj(th[::-1]))          # a real function
+    D = oracle.pde_symbol(m, d, alphas, coefs)
+    P = oracle.piml_box_penalty(m, d, 0.0, 1.0, D, lo, hi)
+    quad_form = np.real(np.conj(th) @ P @ th)
+    integral = _box_integral_of_operator(th, m, d, lo, hi, op)
+    assert abs(integral - quad_form) / quad_form < 2e-5
+    # the printed sign of the symbol (-i k) gives another operator (odd derivatives flip)
+    Dbad = oracle.pde_symbol(m, d, alphas, [c * (-1) ** int(np.sum(a)) for a, c in zip(alphas, coefs)])
+    bad = np.real(np.conj(th) @ oracle.piml_box_penalty(m, d, 0.0, 1.0, Dbad, lo, hi) @ th)
+    assert abs(bad - integral) / integral > 1e-3
+
+
+def test_pde_box_system_matches_direct_minimization():
+    # Sec. 4: theta-hat minimises n^-1 |Phi th - Y|^2 + lambda |S th|^2 + mu int_Omega |D f|^2 (scaled
+    # by (2 pi)^-d); compare the normal equations with a least-squares solve of the stacked system.
+    rng = np.random.default_rng(31)
+    m, n, lam, mu = 5, 400, 1e-3, 1.0
+    X = rng.uniform(0.0, 1.0, size=(1, n))
+    Y = np.exp(X[0]) + rng.standard_normal(n)
+    D = oracle.pde_symbol(m, 1, [[1], [0]], [1.0, -1.0])
+    Q = oracle.piml_box_penalty(m, 1, lam, mu, D, (0.0,), (1.0,), s=1.0)
+    theta, M, b = oracle.fit(X, Y[None, :], m, 0.0, Q)
+    Phi = oracle.design_matrix(X, m)
+    Lq = np.linalg.cholesky(Q)
+    stacked = np.concatenate([Phi / np.sqrt(n), np.conj(Lq).T])
+    rhs_ = np.concatenate([Y / np.sqrt(n), np.zeros(Q.shape[0])])
+    th_ls = np.linalg.lstsq(stacked, rhs_, rcond=None)[0]
+    np.testing.assert_allclose(theta[0], th_ls, atol=1e-9 * np.abs(th_ls).max())
