@@ -18,6 +18,7 @@ Prints one JSON line.  value = n / (seconds per step) = whole-step points/s.
 from __future__ import annotations
 
 import argparse
+import ctypes as C
 import json
 import math
 import os
@@ -31,8 +32,30 @@ HBM_PEAK_GBS = 8000.0
 MFMA_F32_PEAK_TFLOPS = 157.3
 
 
-def _cpu_baseline(workload: str, ntgt: int, m: int):
-    """Time the FP64 CPU oracle (direct Fourier sums) on a bounded prefix of the workload."""
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _blas_vendor() -> str:
+    import numpy as np
+    try:
+        cfg = np.show_config(mode="dicts")
+        b = cfg.get("Build Dependencies", {}).get("blas", {})
+        return f"{b.get('name', '?')} {b.get('version', '')}".strip()
+    except Exception:
+        return "unknown"
+
+
+def _cpu_baseline(workload: str, ntgt: int, m: int, lam: float):
+    """Time the FP64 CPU oracle on a bounded prefix of the workload: the direct Fourier sums for M and
+    b (linear in n, so points/s extrapolates) and, separately, one FP64 LAPACK Cholesky solve of the
+    (2m+1)^2 system (independent of n)."""
     import numpy as np
     import oracle
     import synth
@@ -47,12 +70,18 @@ def _cpu_baseline(workload: str, ntgt: int, m: int):
         X, Y = w["X"], w["Y"]
     X64, Y64 = X.astype(np.float64), Y.astype(np.float64)
     t0 = time.perf_counter()
-    oracle.gram_generator(X64, m)
-    oracle.rhs(X64, Y64, m)
+    M = oracle.gram_generator(X64, m)
+    b = oracle.rhs(X64, Y64, m)
     dt = time.perf_counter() - t0
+    p = oracle.sobolev_weights(m, 2, 2.0)
+    t1 = time.perf_counter()
+    oracle.solve_system(oracle.system_matrix(M, m, lam, p), b)
+    ds = time.perf_counter() - t1
     return {"value": n / dt, "unit": "points/s", "cores": int(threads), "kind": "oracle",
+            "cpu_model": _cpu_model(), "blas": _blas_vendor(), "solve_s_per_lambda": ds,
             "sample": f"FP64 direct sums for M (|q|<=2m) and {ntgt} right-hand sides on the first {n} points "
-                      f"({dt:.1f} s)"}
+                      f"({dt:.1f} s); one FP64 LAPACK Cholesky solve of the {(2 * m + 1) ** 2}-unknown complex "
+                      f"system for the {ntgt} targets ({ds:.1f} s per lambda)"}
 
 
 def _traffic(kernel: str, n: int):
@@ -117,6 +146,43 @@ def _traffic_fft(nvec: int, m: int):
     return float(b.group(1))
 
 
+def _extra_batched(fk, torch, np, X, Y, m, ctx, theta, reps=3):
+    """Further figures on the batched inputs (outside the timed steps):
+    * the single-target type-1 stage on the same n points (the first target row, one lambda), HIP-event
+      time; algorithmic HBM bytes 12 per point;
+    * the type-2 prediction at n_q = 1e8 query points for 16 coefficient sets (one lambda's fits),
+      timed with HIP events on the library's stream; algorithmic HBM bytes: 4d B of coordinates read
+      and 4 B per set written per point."""
+    n = X.shape[1]
+    one = []
+    for _ in range(reps + 1):
+        _, inf = fk.fit(X, Y[:1], m, [float(n) ** -0.8], penalty="sobolev", s=2.0, ctx=ctx, info=True)
+        one.append(inf)
+    one = one[1:]
+    gr1 = float(np.mean([i["t_sort_ms"] + i["t_spread_ms"] + i["t_fft_ms"] for i in one]))
+    res = {"single_target": {"n": n, "gram_rhs_ms": gr1, "sort_ms": float(np.mean([i["t_sort_ms"] for i in one])),
+                                  "spread_ms": float(np.mean([i["t_spread_ms"] for i in one])),
+                                  "points_per_s": n / (gr1 * 1e-3),
+                                  "hbm_frac": n * 12.0 / (gr1 * 1e-3) / (HBM_PEAK_GBS * 1e9)}}
+    nq = 100_000_000
+    Xq = fk.generate_uniform(2509026495 + 2000, 2, nq, ctx=ctx)
+    th = theta[theta.shape[0] // 2].contiguous()          # [16, N]
+    fk.predict(th, Xq, m, ctx=ctx)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        fk.predict(th, Xq, m, ctx=ctx)
+    e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    T = th.shape[0]
+    res["predict"] = {"nq": nq, "sets": T, "ms": ms, "points_per_s": nq / (ms * 1e-3),
+                      "hbm_frac": nq * (8.0 + 4.0 * T) / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)}
+    del Xq
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,7 +205,8 @@ def main():
 
     dev = torch.device("cuda:0")
     m = 32
-    ctx = fk.Context(0)
+    # the autograd Function and the plain fits share one context (one cached workspace)
+    ctx = fk.default_context(0)
     vctx = fk.Context(0)
     if args.workload in ("batched", "cg"):
         n = args.n or 1_000_000_000
@@ -174,6 +241,17 @@ def main():
     cg_iters = []
     last = {}
     CG_TOL = 1e-10
+    if args.workload in ("batched", "sobolev2d"):
+        # size the shared workspace once, for the largest call (the plain fit)
+        nb = C.c_size_t()
+        fk._lib.check(ctx.lib.fk_fit_workspace_size(ctx.h, 2, n, ntgt, m, nlam, C.byref(nb)), "ws")
+        ctx.workspace(nb.value)
+
+    def plain_fit():
+        pen = dict(penalty="diag", p=p0) if args.workload == "batched" else dict(penalty="sobolev", s=2.0)
+        theta, info = fk.fit(X, Y, m, lams, ctx=ctx, info=True, **pen)
+        infos.append(info)
+        last["theta"] = theta
 
     def step():
         if args.workload == "cg":
@@ -183,31 +261,42 @@ def main():
             infos.append(info)
             cg_iters.append(cinf["iters"])
         elif args.workload == "batched":
+            # the gradient path: the autograd Function's forward (fit, held-out Gram and MSE) and backward
+            # (adjoint solves, d/dlog lambda and d/dp)
             loglam = torch.tensor(np.log(lams), dtype=torch.float64, device=dev, requires_grad=True)
             p = p0.clone().requires_grad_(True)
-            theta, info = fk.fit(X, Y, m, lams, penalty="diag", p=p.detach(), ctx=ctx, info=True)
-            Mv, bv = fk.gram(Xv, Yv, m, ctx=vctx)
-            yv2 = fk.mean_square(Yv, ctx=vctx)
-            mse = fk.heldout_mse(Mv, bv, yv2, m, nlam, ctx)
-            gl, gp, _ = fk.fit_backward(torch.ones_like(mse), m, 2, ctx)
-            infos.append(info)
+            mse, theta = fk.KernelRidgeGridLoss.apply(loglam, p, X, Y, Xv, Yv, m)
+            mse.sum().backward()
+            last["grad"] = loglam.grad
         else:
-            theta, info = fk.fit(X, Y, m, lams, penalty="sobolev", s=2.0, ctx=ctx, info=True)
-            infos.append(info)
+            plain_fit()
 
+    def timed(fn, k):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / k
+
+    if args.workload == "batched":
+        # plain fit (type-1 stage + 64 factorizations + refined solves), wall clock, with its stage times
+        plain_fit()
+        infos.clear()
+        fit_s = timed(plain_fit, args.steps)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    infos.clear()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
+    if args.workload != "batched":
+        infos.clear()
+    dt = timed(step, args.steps)
 
     spread_ms = float(np.mean([i["spread_kernel_ms"] for i in infos]))
     gr_ms = float(np.mean([i["t_sort_ms"] + i["t_spread_ms"] + i["t_fft_ms"] for i in infos]))
-    fit_ms = float(np.mean([i["t_total_ms"] for i in infos])) if args.workload != "cg" else dt * 1e3
+    if args.workload == "batched":
+        fit_ms = fit_s * 1e3
+    else:
+        fit_ms = float(np.mean([i["t_total_ms"] for i in infos])) if args.workload != "cg" else dt * 1e3
     w = int(infos[-1]["w"])
     if args.workload in ("batched", "cg"):
         # dominant kernel: the MFMA spread; algorithmic work 2 w^2 (T + 1) flop per point
@@ -252,14 +341,27 @@ def main():
                      "frac": achieved / peak, "traffic": _traffic(kernel, n)},
         "gram_rhs_hbm_frac": n * bytes_per_point / (gr_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
     }
+    if args.workload in ("batched", "sobolev2d"):
+        # the dense solve on the FP32 matrix cores: nlam Cholesky factorizations of the N x N real form,
+        # N^3/3 flop each (one real-form factor per lambda)
+        N = (2 * m + 1) ** 2
+        fac_ms = out["stage_ms"]["t_factor_ms"]
+        ach = nlam * N ** 3 / 3.0 / (fac_ms * 1e-3) / 1e12
+        out["roofline_solve"] = {"bound": "mfma", "kernel": "factorization (k_left_update2, k_left_update, "
+                                 "k_potrf_diag, k_trsm_panel)", "achieved": ach, "peak": MFMA_F32_PEAK_TFLOPS,
+                                 "unit": "TFLOP/s", "frac": ach / MFMA_F32_PEAK_TFLOPS, "factor_ms": fac_ms,
+                                 "flop": nlam * N ** 3 / 3.0}
     if args.workload == "batched":
+        # grad path (autograd Function forward + backward) over the plain fit, both wall clock
         out["grad_vs_fit_ratio"] = dt * 1e3 / fit_ms
+        out["grad_step_ms"] = dt * 1e3
+        out.update(_extra_batched(fk, torch, np, X, Y, m, ctx, last["theta"]))
     if args.workload == "cg":
         out["cg_iters"] = int(max(cg_iters))
         out["cg_ms"] = dt * 1e3 - gr_ms
         out["roofline_fft"] = _fft_roofline(fk, torch, last["M"], m, nlam * ntgt, ctx)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = _cpu_baseline(args.workload, ntgt, m)
+        out["cpu_baseline"] = _cpu_baseline(args.workload, ntgt, m, lams[nlam // 2])
     print(json.dumps(out))
 
 

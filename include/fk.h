@@ -70,20 +70,28 @@ typedef enum {
   FK_PEN_IDENTITY = 2,        /* diag 1, the low-bias estimator     (Sec. 3.2, Prop. low-bias) */
   FK_PEN_DIAG = 3,            /* diag p, p given by the caller (host array of N doubles, p_k > 0,
                                  p_{-k} = p_k) */
-  FK_PEN_HEAT_BOX = 4         /* d = 2, modes (k_t, k_x):
-                                 lambda diag(1 + ||k||^2) + mu D^* C D      (Sec. 4, tractable domains)
-                                 with D_k = i k_t + k_x^2 (the operator d_t - d_xx on exp(i k.x)) and
-                                 C[k, l] = (2 pi)^-2 prod_a int_{lo_a}^{hi_a} exp(i (k_a - l_a) u) du,
-                                 the Fourier matrix of the box [lo, hi] in radians */
+  FK_PEN_HEAT_BOX = 4,        /* d = 2, modes (k_t, k_x): FK_PEN_PDE_BOX for the heat operator d_t - d_xx
+                                 (D_k = i k_t + k_x^2) with s = 1 (alpha, coef unused) */
+  FK_PEN_PDE_BOX = 5          /* d = 1 or 2, the physics-informed penalty of Sec. 4 (tractable domains):
+                                   lambda diag(1 + ||k||^(2s)) + mu D^* C D
+                                 for the linear constant-coefficient operator sum_t coef[t] d^alpha[t]:
+                                   D_k = sum_t coef[t] prod_a (i k_a)^alpha[t][a]  (its action on exp(i k.x)),
+                                   C[k, l] = (2 pi)^-d prod_a int_{lo_a}^{hi_a} exp(i (l_a - k_a) u) du,
+                                 the Fourier matrix of the box [lo, hi] (radians), so that theta^* C theta =
+                                 (2 pi)^-d int_box |f_theta|^2 and theta^* D^* C D theta =
+                                 (2 pi)^-d int_box |sum_t coef[t] d^alpha[t] f_theta|^2 */
 } fk_pen_kind;
 
 typedef struct {
   int kind;            /* fk_pen_kind */
-  double s;            /* Sobolev order for FK_PEN_SOBOLEV / _BESSEL */
+  double s;            /* Sobolev order for FK_PEN_SOBOLEV / _BESSEL / _PDE_BOX (s >= 0) */
   const double* p;     /* host, N weights for FK_PEN_DIAG, else NULL */
-  double mu;           /* FK_PEN_HEAT_BOX: weight of the PDE term */
-  double box_lo[2];    /* FK_PEN_HEAT_BOX: box corners in radians */
-  double box_hi[2];
+  double mu;           /* FK_PEN_HEAT_BOX / _PDE_BOX: weight of the PDE term (>= 0) */
+  double box_lo[2];    /* FK_PEN_HEAT_BOX / _PDE_BOX: box corners in radians (entries 0..d-1 used, */
+  double box_hi[2];    /*   box_lo[a] < box_hi[a]) */
+  int nterms;          /* FK_PEN_PDE_BOX: number of operator terms, 1..16 */
+  const int* alpha;    /* FK_PEN_PDE_BOX: host, nterms x d derivative orders, each 0..8 */
+  const double* coef;  /* FK_PEN_PDE_BOX: host, nterms finite real coefficients */
 } fk_penalty;
 
 /* Options; zero-initialised means defaults. */
@@ -93,6 +101,9 @@ typedef struct {
   double refine_tol;   /* relative FP64 residual target (default 1e-10) */
   int keep_factors;    /* 1: keep Cholesky factors in the workspace for fk_heldout_mse /
                           fk_fit_backward (always on; field reserved) */
+  int autotune;        /* launch-shape autotuning (see "Autotuning" below): 0 = as the FK_AUTOTUNE
+                          environment variable says (default: tune), 1 = built-in shapes only,
+                          2 = re-measure even when the table has an entry, 3 = tune at first use */
 } fk_options;
 
 /* Per-call report, filled by fk_fit / fk_gram when non-NULL. */
@@ -228,6 +239,15 @@ fk_status fk_predict(fk_ctx* ctx, int d, int m, int ntheta, const double* theta,
                      fk_dtype dtype, const void* Xq, float* out, void* ws, size_t ws_bytes);
 
 /* ---------------------------------------------------------------- held-out loss and gradients
+ * Kept factors.  fk_solve and fk_fit leave, at the start of their workspace, the FP32 factors of
+ * every lambda, the FP64 real-form Gram and the solutions; a successful call (FK_OK or
+ * FK_ENOCONV) registers that workspace (its address and the shape d, m, nlam, ntgt).  Any later
+ * library call that writes a workspace overlapping it (fk_gram, fk_solve, fk_fit, fk_predict,
+ * the additive and iterative entry points, from any context) removes the registration, and
+ * fk_heldout_mse / fk_fit_backward then return FK_EINVAL instead of reading overwritten factors.
+ * Writes into the buffer from outside the library are not seen: the caller must not reuse the
+ * workspace memory while it wants the gradients.
+ *
  * After fk_solve (or fk_fit) on workspace `ws`, with the held-out Gram generator Mv
  * (device complex128 (4m+1)^d), right-hand sides bv (device complex128 ntgt x N) and
  * yv2[t] = n_v^-1 sum_j Yv[t][j]^2 (device, ntgt doubles):
@@ -242,16 +262,27 @@ fk_status fk_heldout_mse(fk_ctx* ctx, int d, int m, int ntgt, int nlam, const do
  * term of the held-out loss above.  Y is device [ntgt][n] (fp32 or fp64); n >= 1. */
 fk_status fk_mean_square(fk_ctx* ctx, int ntgt, int64_t n, fk_dtype dtype, const void* Y, double* out);
 
-/* fk_fit_backward: given grad_mse[l][t] = dLoss/dmse[l][t] (device, nlam x ntgt),
- * with g = Sigma_v theta - bv and u = A_l^-1 g (adjoint solve with the kept factors):
- *   grad_loglam[l] = sum_t grad_mse[l][t] * (-2 lambda_l Re(u^* P theta))      (device, nlam)
- *   grad_p[k]      = sum_{l,t} grad_mse[l][t] * (-2 lambda_l Re(conj(u_k) theta_k))   (device, N;
- *                    only for diagonal penalties, else left untouched)
- *   grad_theta[l][t] = grad_mse[l][t] * g                 (device complex128, may be NULL)
- * Requires the fk_heldout_mse call on the same workspace. */
+/* fk_fit_backward: the gradients of a real loss Loss(mse, theta) through theta = A_l^-1 b_t, where
+ * mse is the held-out loss above.  Complex gradients follow the Wirtinger convention:
+ * dLoss/dconj(theta), the vector G with dLoss = 2 Re(G^* dtheta) (PyTorch's .grad of a complex
+ * tensor is 2 G).  Inputs:
+ *   grad_mse[l][t] = dLoss/dmse[l][t]                        (device, nlam x ntgt doubles)
+ *   grad_theta_in[l][t][k] = dLoss/dconj(theta) from every other use of theta (device complex128
+ *                    nlam x ntgt x N, or NULL for none); only its Hermitian-symmetric part acts, as
+ *                    theta stays Hermitian-symmetric (real data) for every lambda and p.
+ * With g = Sigma_v theta - bv (= d mse / d conj(theta)), G = grad_mse * g + grad_theta_in and the
+ * adjoint u = A_l^-1 G (solved with the kept factors and FP64 refinement):
+ *   grad_loglam[l] = sum_t -2 lambda_l Re(u^* P theta)                  (device, nlam)
+ *   grad_p[k]      = sum_{l,t} -2 lambda_l Re(conj(u_k) theta_k)         (device, N; only for diagonal
+ *                    penalties: it is dLoss/dp_k for the weights p_k = p_{-k} taken as independent
+ *                    entries, else left untouched; may be NULL)
+ *   grad_theta[l][t] = grad_mse[l][t] * g   (device complex128, may be NULL: the Wirtinger gradient
+ *                    of the mse term with respect to conj(theta), theta held fixed)
+ * Requires the fk_heldout_mse call on the same workspace after its fk_solve / fk_fit (FK_EINVAL
+ * otherwise, see "Kept factors").  Returns FK_ENAN if the adjoint right-hand sides are not finite. */
 fk_status fk_fit_backward(fk_ctx* ctx, int d, int m, int ntgt, int nlam, const double* grad_mse,
-                          double* grad_loglam, double* grad_p, double* grad_theta,
-                          void* ws, size_t ws_bytes);
+                          const double* grad_theta_in, double* grad_loglam, double* grad_p,
+                          double* grad_theta, void* ws, size_t ws_bytes);
 
 /* ---------------------------------------------------------------- additive model (Sec. 5)
  * fk_additive_gram: block Gram B (device complex128, [d(2m+1)]^2 row-major) with blocks
@@ -273,6 +304,32 @@ fk_status fk_additive_fit_workspace_size(fk_ctx* ctx, int d, int64_t n, int ntgt
 fk_status fk_additive_fit(fk_ctx* ctx, int d, int64_t n, fk_dtype dtype, const void* X, int ntgt,
                           const void* Y, int m, const double* lambdas, int nlam, double s,
                           double* theta_out, void* ws, size_t ws_bytes, fk_fit_info* info);
+
+/* ---------------------------------------------------------------- autotuning
+ * Launch shapes of the large stages are chosen by measurement (not in the paper: its grid search,
+ * Sec. 5, repeats one type-1 stage and many solves, so their speed is what the search costs):
+ *   - the 2-D type-1 stage with 0..16 targets and n >= 2^22 points: the bin edge of the channel-row
+ *     spread (2 or 4 cells), points per spreading workgroup, workgroups of the first sort pass and
+ *     points per slice of the second;
+ *   - the dense solve with Np^2 nlam >= 2^28 (Np = N rounded up to 64): workgroups per
+ *     triangular-solve launch and whether block columns are factored in pairs.
+ * At the first call of a shape without a table entry the library times each candidate (coordinate
+ * descent, one knob at a time, on the call's own data; the call then runs with the fastest) and
+ * records "<arch> <stage> <shape> = <knob>=<value> ... ms=<time>" in a process-wide table; every
+ * candidate is a correct configuration, so results differ only by rounding.  Environment:
+ * FK_AUTOTUNE_CACHE = path of a text file read at the first lookup and appended with each new
+ * entry; FK_AUTOTUNE = off | force (or fk_options.autotune).  Entries may be written by hand to pin
+ * a configuration.
+ *
+ * fk_autotune_load: merge the entries of a table file (lines "<key> = <knob>=<int> ...", '#'
+ *   comments; malformed lines are skipped).  Host only; FK_EINVAL if the file cannot be read.
+ * fk_autotune_table: the table as text (one entry per line, sorted by key) into buf (host, cap
+ *   bytes, NUL-terminated); *len = its length without the NUL.  buf = NULL only queries len;
+ *   FK_EINVAL if cap is too small.
+ * fk_autotune_clear: empty the table (the cache file is not read again in this process). */
+fk_status fk_autotune_load(const char* path);
+fk_status fk_autotune_table(char* buf, size_t cap, size_t* len);
+fk_status fk_autotune_clear(void);
 
 /* ---------------------------------------------------------------- synthetic inputs
  * fk_generate_uniform: X[a][j] = (float)(lo_a + (hi_a - lo_a) * u), u = (w >> 8) 2^-24

@@ -45,7 +45,7 @@ from .solve import system_matrix, solve_system, condition_number, fit
 from .cg import toeplitz_apply, toeplitz_apply_rows, pcg
 from .predict import predict, predict_additive
 from .krr import krr_theta
-from .grad import heldout_mse, heldout_mse_quadratic, mse_gradients
+from .grad import heldout_mse, heldout_mse_quadratic, mse_gradients, theta_path_gradients
 
 __all__ = [
     "modes", "gram_generator", "rhs", "fourier_entry", "toeplitz_matrix", "design_matrix",
@@ -54,5 +54,5 @@ __all__ = [
     "piml_heat_penalty", "pde_symbol", "piml_box_penalty", "additive_penalty", "collocation_penalty",
     "system_matrix", "solve_system", "condition_number", "fit", "toeplitz_apply", "toeplitz_apply_rows", "pcg",
     "predict", "predict_additive", "krr_theta",
-    "heldout_mse", "heldout_mse_quadratic", "mse_gradients",
+    "heldout_mse", "heldout_mse_quadratic", "mse_gradients", "theta_path_gradients",
 ]

@@ -38,6 +38,17 @@ def heldout_mse_quadratic(theta: np.ndarray, Mv: np.ndarray, bv: np.ndarray, yv2
     return quad - 2.0 * lin + np.asarray(yv2, dtype=np.float64)
 
 
+def theta_path_gradients(A: np.ndarray, theta: np.ndarray, p: np.ndarray, lam: float, G: np.ndarray):
+    """Gradients through theta = A^-1 b, A = Sigma + lambda diag(p), of a loss whose Wirtinger
+    gradient with respect to conj(theta) is G (dLoss = 2 Re(G^* dtheta)).
+
+    d theta / d lambda = -A^-1 diag(p) theta and d theta / d p_k = -lambda A^-1 e_k theta_k, so with
+    u = A^-1 G (A Hermitian): returns (dLoss/dlog lambda = -2 lambda Re(u^* diag(p) theta),
+    dLoss/dp [N] = -2 lambda Re(conj(u) theta))."""
+    u = np.linalg.solve(A, G)
+    return float(-2.0 * lam * np.real(np.conj(u) @ (p * theta))), -2.0 * lam * np.real(np.conj(u) * theta)
+
+
 def mse_gradients(A: np.ndarray, theta: np.ndarray, p: np.ndarray, lam: float,
                   Mv: np.ndarray, bv: np.ndarray, m: int):
     """Gradients of the held-out MSE for one lambda and one target.

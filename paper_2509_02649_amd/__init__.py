@@ -22,8 +22,9 @@ import torch
 from . import _lib
 from ._lib import FkError, fk_fit_info, fk_penalty, fk_options, FK_F32, FK_F64, PEN
 
-__all__ = ["Context", "gram", "restrict", "solve", "solve_cg", "toeplitz_apply", "fit", "predict", "heldout_mse", "fit_backward", "additive_gram",
-           "additive_fit", "generate_uniform", "generate_targets", "KernelRidgeGridLoss", "FkError"]
+__all__ = ["Context", "gram", "restrict", "solve", "solve_workspace_size", "solve_cg", "toeplitz_apply", "fit", "predict", "heldout_mse", "fit_backward", "additive_gram",
+           "additive_fit", "generate_uniform", "generate_targets", "KernelRidgeGridLoss", "FkError",
+           "autotune_table", "autotune_load", "autotune_clear"]
 
 
 def _stream_ptr(device):
@@ -51,7 +52,8 @@ def _dev_tensor(t: torch.Tensor, name: str) -> torch.Tensor:
 class Context:
     """A library context bound to one device; enqueues on torch's current stream."""
 
-    def __init__(self, device: int = 0, eps: float = 2e-7, max_refine: int = 8, refine_tol: float = 1e-10):
+    def __init__(self, device: int = 0, eps: float = 2e-7, max_refine: int = 8, refine_tol: float = 1e-10,
+                 autotune: int = 0):
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device visible: libfastkernel needs an MI355X")
         self.lib = _lib.load()
@@ -59,7 +61,7 @@ class Context:
         h = C.c_void_p()
         _lib.check(self.lib.fk_create(C.byref(h), device, _stream_ptr(device)), "fk_create")
         self.h = h
-        opt = fk_options(eps, max_refine, refine_tol, 1)
+        opt = fk_options(eps, max_refine, refine_tol, 1, autotune)
         _lib.check(self.lib.fk_set_options(self.h, C.byref(opt)), "fk_set_options")
         self._ws = None
 
@@ -94,17 +96,32 @@ def default_context(device: int = 0) -> Context:
 
 
 def _penalty(kind: str, s: float = 1.0, p: Optional[torch.Tensor] = None, mu: float = 0.0,
-             box_lo=(-math.pi / 2, -math.pi / 2), box_hi=(math.pi / 2, math.pi / 2)):
+             box_lo=(-math.pi / 2, -math.pi / 2), box_hi=(math.pi / 2, math.pi / 2), alpha=None, coef=None):
+    """The fk_penalty struct (and the host arrays it points to, to keep alive during the call).
+
+    kind "pde_box": lambda diag(1 + ||k||^(2s)) + mu D^* C D for the operator sum_t coef[t] d^alpha[t]
+    on the box [box_lo, box_hi] (radians; Sec. 4, tractable domains), alpha [nterms][d] integers."""
     pen = fk_penalty()
     pen.kind = PEN[kind]
     pen.s = float(s)
-    keep = None
+    keep = []
     if kind == "diag":
-        keep = (C.c_double * p.numel())(*[float(v) for v in p.detach().cpu().double().tolist()])
-        pen.p = C.cast(keep, C.POINTER(C.c_double))
+        arr = (C.c_double * p.numel())(*[float(v) for v in p.detach().cpu().double().tolist()])
+        keep.append(arr)
+        pen.p = C.cast(arr, C.POINTER(C.c_double))
     pen.mu = float(mu)
-    pen.box_lo[0], pen.box_lo[1] = box_lo
-    pen.box_hi[0], pen.box_hi[1] = box_hi
+    lo = list(box_lo) + [0.0] * (2 - len(box_lo))
+    hi = list(box_hi) + [0.0] * (2 - len(box_hi))
+    pen.box_lo[0], pen.box_lo[1] = lo[:2]
+    pen.box_hi[0], pen.box_hi[1] = hi[:2]
+    if kind == "pde_box":
+        flat = [int(v) for row in alpha for v in (row if hasattr(row, "__len__") else [row])]
+        a = (C.c_int * len(flat))(*flat)
+        c = (C.c_double * len(coef))(*[float(v) for v in coef])
+        keep += [a, c]
+        pen.nterms = len(coef)
+        pen.alpha = C.cast(a, C.POINTER(C.c_int))
+        pen.coef = C.cast(c, C.POINTER(C.c_double))
     return pen, keep
 
 
@@ -136,9 +153,21 @@ def gram(X: torch.Tensor, Y: Optional[torch.Tensor], m: int, ctx: Optional[Conte
     return (M, b, inf.as_dict()) if info else (M, b)
 
 
+def solve_workspace_size(d: int, m: int, T: int, nlam: int, ctx: Optional[Context] = None) -> int:
+    """Bytes of the workspace fk_solve needs (and in which it keeps the factors for the gradients)."""
+    ctx = ctx or default_context(0)
+    nb = C.c_size_t()
+    _lib.check(ctx.lib.fk_solve_workspace_size(ctx.h, d, m, T, nlam, C.byref(nb)), "fk_solve_workspace_size")
+    return nb.value
+
+
 def solve(M: torch.Tensor, b: torch.Tensor, m: int, lambdas: Sequence[float], penalty: str = "sobolev",
-          s: float = 1.0, ctx: Optional[Context] = None, info: bool = False, **pen_kw):
-    """theta [nlam, T, N] complex128 from the generator M and right-hand sides b [T, N]."""
+          s: float = 1.0, ctx: Optional[Context] = None, info: bool = False, ws: Optional[torch.Tensor] = None,
+          **pen_kw):
+    """theta [nlam, T, N] complex128 from the generator M and right-hand sides b [T, N].
+
+    ws: an explicit uint8 device workspace (at least solve_workspace_size bytes) that keeps the
+    factors for heldout_mse / fit_backward; default: the context's cached workspace."""
     ctx = ctx or default_context(M.device.index or 0)
     ctx.bind_stream()
     d = M.dim()
@@ -149,7 +178,11 @@ def solve(M: torch.Tensor, b: torch.Tensor, m: int, lambdas: Sequence[float], pe
     nlam = len(lambdas)
     nb = C.c_size_t()
     _lib.check(ctx.lib.fk_solve_workspace_size(ctx.h, d, m, T, nlam, C.byref(nb)), "fk_solve_workspace_size")
-    ws = ctx.workspace(nb.value)
+    if ws is None:
+        ws = ctx.workspace(nb.value)
+    elif ws.numel() < nb.value:
+        raise ValueError("workspace too small")
+    nb = C.c_size_t(ws.numel())
     theta = torch.empty((nlam, T, _modes(m, d), 2), dtype=torch.float64, device=M.device)
     pen, keep = _penalty(penalty, s, **pen_kw)
     inf = fk_fit_info()
@@ -287,8 +320,8 @@ def predict(theta: torch.Tensor, Xq: torch.Tensor, m: int, ctx: Optional[Context
 
 
 def heldout_mse(Mv: torch.Tensor, bv: torch.Tensor, yv2: torch.Tensor, m: int, nlam: int,
-                ctx: Context) -> torch.Tensor:
-    """mse [nlam, T] of the last solve on ctx's workspace against held-out statistics."""
+                ctx: Context, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """mse [nlam, T] of the last solve kept in ws (default: ctx's workspace) against held-out statistics."""
     ctx.bind_stream()
     d = Mv.dim()
     T = bv.shape[0]
@@ -296,7 +329,7 @@ def heldout_mse(Mv: torch.Tensor, bv: torch.Tensor, yv2: torch.Tensor, m: int, n
     br = torch.view_as_real(bv.contiguous()).contiguous()
     y2 = yv2.to(torch.float64).contiguous()
     out = torch.empty((nlam, T), dtype=torch.float64, device=Mv.device)
-    ws = ctx._ws
+    ws = ctx._ws if ws is None else ws
     _lib.check(ctx.lib.fk_heldout_mse(ctx.h, d, m, T, nlam, _ptr(Mr), _ptr(br), _ptr(y2), _ptr(out), _ptr(ws),
                                       ws.numel()), "fk_heldout_mse")
     return out
@@ -314,8 +347,12 @@ def mean_square(Y: torch.Tensor, ctx: Optional[Context] = None) -> torch.Tensor:
     return out
 
 
-def fit_backward(grad_mse: torch.Tensor, m: int, d: int, ctx: Context, want_theta: bool = False):
-    """Gradients (log lambda [nlam], p [N], theta [nlam, T, N] or None) of sum(grad_mse * mse)."""
+def fit_backward(grad_mse: torch.Tensor, m: int, d: int, ctx: Context, want_theta: bool = False,
+                 grad_theta_in: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None):
+    """Gradients (log lambda [nlam], p [N], theta [nlam, T, N] or None) of
+    Loss = sum(grad_mse * mse) + (the loss whose Wirtinger gradient dLoss/dconj(theta) is grad_theta_in),
+    through theta = A^-1 b, with the factors kept in ws (default: ctx's workspace).  The theta gradient
+    returned (want_theta) is the Wirtinger gradient of sum(grad_mse * mse) with theta held fixed."""
     ctx.bind_stream()
     nlam, T = grad_mse.shape
     g = grad_mse.to(torch.float64).contiguous()
@@ -323,9 +360,12 @@ def fit_backward(grad_mse: torch.Tensor, m: int, d: int, ctx: Context, want_thet
     gl = torch.empty(nlam, dtype=torch.float64, device=g.device)
     gp = torch.empty(N, dtype=torch.float64, device=g.device)
     gt = torch.empty((nlam, T, N, 2), dtype=torch.float64, device=g.device) if want_theta else None
-    ws = ctx._ws
-    _lib.check(ctx.lib.fk_fit_backward(ctx.h, d, m, T, nlam, _ptr(g), _ptr(gl), _ptr(gp), _ptr(gt), _ptr(ws),
-                                       ws.numel()), "fk_fit_backward")
+    gin = None
+    if grad_theta_in is not None:
+        gin = torch.view_as_real(grad_theta_in.to(torch.complex128).reshape(nlam, T, N).contiguous()).contiguous()
+    ws = ctx._ws if ws is None else ws
+    _lib.check(ctx.lib.fk_fit_backward(ctx.h, d, m, T, nlam, _ptr(g), _ptr(gin), _ptr(gl), _ptr(gp), _ptr(gt),
+                                       _ptr(ws), ws.numel()), "fk_fit_backward")
     return gl, gp, (torch.view_as_complex(gt) if want_theta else None)
 
 
@@ -372,6 +412,25 @@ def additive_fit(X: torch.Tensor, Y: torch.Tensor, m: int, lambdas, s: float = 1
     return (th, inf.as_dict()) if info else th
 
 
+def autotune_table() -> str:
+    """The library's table of measured launch shapes, one "<key> = <knob>=<value> ... ms=<t>" per line."""
+    lib = _lib.load()
+    n = C.c_size_t()
+    _lib.check(lib.fk_autotune_table(None, 0, C.byref(n)), "fk_autotune_table")
+    buf = C.create_string_buffer(n.value + 1)
+    _lib.check(lib.fk_autotune_table(buf, n.value + 1, C.byref(n)), "fk_autotune_table")
+    return buf.value.decode()
+
+
+def autotune_load(path: str) -> None:
+    """Merge a table file (lines "<key> = <knob>=<int> ...") into the library's table."""
+    _lib.check(_lib.load().fk_autotune_load(path.encode()), "fk_autotune_load")
+
+
+def autotune_clear() -> None:
+    _lib.check(_lib.load().fk_autotune_clear(), "fk_autotune_clear")
+
+
 def generate_uniform(seed: int, d: int, n: int, lo=None, hi=None, start: int = 0, device: int = 0,
                      ctx: Optional[Context] = None) -> torch.Tensor:
     """Philox4x32-10 uniform points [d, n] float32 on the device (same stream as the test generator)."""
@@ -401,31 +460,45 @@ def generate_targets(seed: int, X: torch.Tensor, ntgt: int, sigma: float = 0.1, 
 class KernelRidgeGridLoss(torch.autograd.Function):
     """Held-out MSE of the fitted estimator over a grid of lambdas and targets.
 
-    forward(loglam [nlam] float64, p [N] float64, X, Y, Xv, Yv, m) -> mse [nlam, T]
-    The fit uses the diagonal penalty p (e.g. Sobolev weights); backward runs the
-    adjoint solve with the kept factors and returns gradients with respect to
-    log lambda and p.  Not in the paper: it makes the lambda grid search of
-    Sec. 5 differentiable.
+    forward(loglam [nlam] float64, p [N] float64, X, Y, Xv, Yv, m)
+        -> (mse [nlam, T] float64, theta [nlam, T, N] complex128)
+    The fit uses the diagonal penalty p (e.g. Sobolev weights).  Both outputs are differentiable:
+    backward runs one adjoint solve per (lambda, target) with the kept factors, on the combined
+    right-hand side of the mse term and of any other use of theta, and returns the gradients with
+    respect to log lambda and p.  Each apply keeps its factors in a workspace of its own, so several
+    applies (cross-validation folds, repeated calls) can be alive in one graph.  Not in the paper: it
+    makes the lambda grid search of Sec. 5 differentiable.
     """
 
     @staticmethod
     def forward(ctx_, loglam, p, X, Y, Xv, Yv, m):
         fkc = default_context(X.device.index or 0)
         lams = torch.exp(loglam.detach()).cpu().tolist()
-        theta = fit(X, Y, m, lams, penalty="diag", p=p.detach(), ctx=fkc)
+        d = X.shape[0]
+        # type-1 stage in the context's shared workspace; factors in this apply's own
+        M, b = gram(X, Y, m, ctx=fkc)
+        kept = torch.empty(solve_workspace_size(d, m, Y.shape[0], len(lams), fkc), dtype=torch.uint8,
+                           device=X.device)
+        theta = solve(M, b, m, lams, penalty="diag", p=p.detach(), ctx=fkc, ws=kept)
         vctx = _validation_context(fkc)
         Mv, bv = gram(Xv, Yv, m, ctx=vctx)
         yv2 = mean_square(Yv, vctx)
-        mse = heldout_mse(Mv, bv, yv2, m, len(lams), fkc)
+        mse = heldout_mse(Mv, bv, yv2, m, len(lams), fkc, ws=kept)
         ctx_.fkc = fkc
+        ctx_.kept = kept
         ctx_.m = m
-        ctx_.d = X.shape[0]
-        ctx_.mark_non_differentiable(theta)
-        return mse
+        ctx_.d = d
+        ctx_.set_materialize_grads(False)
+        return mse, theta
 
     @staticmethod
-    def backward(ctx_, grad_mse):
-        gl, gp, _ = fit_backward(grad_mse.contiguous(), ctx_.m, ctx_.d, ctx_.fkc)
+    def backward(ctx_, grad_mse, grad_theta):
+        if grad_mse is None:
+            nlam, T = grad_theta.shape[:2]
+            grad_mse = torch.zeros((nlam, T), dtype=torch.float64, device=grad_theta.device)
+        # PyTorch's gradient of a complex tensor is 2 dLoss/dconj(theta); the library takes dLoss/dconj(theta)
+        gin = None if grad_theta is None else 0.5 * grad_theta
+        gl, gp, _ = fit_backward(grad_mse.contiguous(), ctx_.m, ctx_.d, ctx_.fkc, grad_theta_in=gin, ws=ctx_.kept)
         return gl, gp, None, None, None, None, None
 
 

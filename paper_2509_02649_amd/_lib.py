@@ -13,7 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfastkernel.so")
 
 FK_F32, FK_F64 = 0, 1
-PEN = {"sobolev": 0, "sobolev_bessel": 1, "identity": 2, "diag": 3, "heat_box": 4}
+PEN = {"sobolev": 0, "sobolev_bessel": 1, "identity": 2, "diag": 3, "heat_box": 4, "pde_box": 5}
 STATUS = ["FK_OK", "FK_EINVAL", "FK_ERANGE", "FK_ENAN", "FK_ENOTPD", "FK_ENOCONV", "FK_ENOMEM", "FK_EHIP"]
 
 
@@ -26,12 +26,13 @@ class FkError(RuntimeError):
 
 class fk_penalty(C.Structure):
     _fields_ = [("kind", C.c_int), ("s", C.c_double), ("p", C.POINTER(C.c_double)), ("mu", C.c_double),
-                ("box_lo", C.c_double * 2), ("box_hi", C.c_double * 2)]
+                ("box_lo", C.c_double * 2), ("box_hi", C.c_double * 2), ("nterms", C.c_int),
+                ("alpha", C.POINTER(C.c_int)), ("coef", C.POINTER(C.c_double))]
 
 
 class fk_options(C.Structure):
     _fields_ = [("eps", C.c_double), ("max_refine", C.c_int), ("refine_tol", C.c_double),
-                ("keep_factors", C.c_int)]
+                ("keep_factors", C.c_int), ("autotune", C.c_int)]
 
 
 class fk_fit_info(C.Structure):
@@ -85,7 +86,7 @@ EXPORTS = {
     "fk_heldout_mse": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_void_p, C.c_size_t]),
     "fk_fit_backward": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p,
-                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]),
+                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]),
     "fk_additive_gram_workspace_size": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int, C.c_int,
                                                   C.POINTER(C.c_size_t)]),
     "fk_additive_gram": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int, C.c_void_p, C.c_int, C.c_void_p,
@@ -95,6 +96,9 @@ EXPORTS = {
     "fk_additive_fit": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int, C.c_void_p, C.c_int, C.c_void_p,
                                   C.c_int, C.POINTER(C.c_double), C.c_int, C.c_double, C.c_void_p, C.c_void_p,
                                   C.c_size_t, C.POINTER(fk_fit_info)]),
+    "fk_autotune_load": (C.c_int, [C.c_char_p]),
+    "fk_autotune_table": (C.c_int, [C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]),
+    "fk_autotune_clear": (C.c_int, []),
     "fk_generate_uniform": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int, C.c_int64, C.c_int64,
                                       C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]),
     "fk_mean_square": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int, C.c_void_p, C.c_void_p]),

@@ -3,7 +3,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 namespace fk {
@@ -158,6 +160,46 @@ __global__ void k_restrict(const double2* __restrict__ in, int d, int Lin, int L
 
 }  // namespace fk
 
+// ------------------------------------------------------------------ kept factors
+// A workspace holding the factors and solutions of a solve stays registered until any library
+// call writes a workspace that overlaps it; fk_heldout_mse / fk_fit_backward look it up.
+namespace fk {
+namespace {
+struct KeptEntry {
+  uintptr_t base;
+  size_t bytes;
+  int device, kind, d, m, N, nlam, ntgt, stage;
+};
+std::mutex g_kept_mu;
+std::vector<KeptEntry> g_kept;
+}  // namespace
+
+void kept_invalidate(const void* ws, size_t bytes) {
+  if (!ws) return;
+  const uintptr_t a = reinterpret_cast<uintptr_t>(ws), b = a + bytes;
+  std::lock_guard<std::mutex> lk(g_kept_mu);
+  g_kept.erase(std::remove_if(g_kept.begin(), g_kept.end(),
+                              [&](const KeptEntry& e) { return e.base < b && a < e.base + e.bytes; }),
+               g_kept.end());
+}
+
+void kept_register(const void* ws, size_t bytes, int device, int kind, int d, int m, int N, int nlam, int ntgt,
+                   int stage) {
+  kept_invalidate(ws, bytes);
+  std::lock_guard<std::mutex> lk(g_kept_mu);
+  g_kept.push_back({reinterpret_cast<uintptr_t>(ws), bytes, device, kind, d, m, N, nlam, ntgt, stage});
+}
+
+bool kept_find(const void* ws, int device, int kind, int d, int m, int N, int nlam, int ntgt, int min_stage) {
+  std::lock_guard<std::mutex> lk(g_kept_mu);
+  for (const KeptEntry& e : g_kept)
+    if (e.base == reinterpret_cast<uintptr_t>(ws) && e.device == device && e.kind == kind && e.d == d && e.m == m &&
+        e.N == N && e.nlam == nlam && e.ntgt == ntgt && e.stage >= min_stage)
+      return true;
+  return false;
+}
+}  // namespace fk
+
 // ------------------------------------------------------------------ fk_gram
 
 static int64_t ipow(int64_t a, int d) {
@@ -218,6 +260,7 @@ extern "C" fk_status fk_gram(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const v
   if (dt != FK_F32 && dt != FK_F64) return FK_EINVAL;
   if (ws_bytes < gram_ws(d, n, ntgt, m) || !ws) return FK_ENOMEM;
   FK_HIP(hipSetDevice(ctx->device));
+  kept_invalidate(ws, ws_bytes);
   if (info) {
     std::memset(info, 0, sizeof(*info));
     info->bad_index = -1;
@@ -264,6 +307,7 @@ static fk_status penalty_weights(const fk_penalty* pen, int d, int m, std::vecto
         p[i] = pen->p[i];
         break;
       case FK_PEN_HEAT_BOX: p[i] = 1.0 + r2; break;
+      case FK_PEN_PDE_BOX: p[i] = 1.0 + std::pow(r2, s); break;
       default: return FK_EINVAL;
     }
     if (!(p[i] > 0.0) || std::isinf(p[i])) return FK_EINVAL;
@@ -271,8 +315,52 @@ static fk_status penalty_weights(const fk_penalty* pen, int d, int m, std::vecto
   if (kind == FK_PEN_DIAG)
     for (int64_t i = 0; i < N; ++i)
       if (p[i] != p[N - 1 - i]) return FK_EINVAL;   // p_{-k} = p_k required for the real form
-  if (kind == FK_PEN_SOBOLEV || kind == FK_PEN_SOBOLEV_BESSEL)
+  if (kind == FK_PEN_SOBOLEV || kind == FK_PEN_SOBOLEV_BESSEL || kind == FK_PEN_PDE_BOX)
     if (!(s >= 0.0) || s > 64) return FK_EINVAL;
+  return FK_OK;
+}
+
+// Operator symbol D_k = sum_t coef[t] prod_a (i k_a)^alpha[t][a] (Sec. 4: the derivative of exp(i k.x)
+// along axis a is i k_a exp(i k.x)), complex interleaved over the N modes.  The heat box is the
+// operator d_t - d_xx.
+static fk_status pde_symbol(const fk_penalty* pen, int d, int m, std::vector<double>& D) {
+  static const int heat_alpha[4] = {1, 0, 0, 2};
+  static const double heat_coef[2] = {1.0, -1.0};
+  const bool heat = pen->kind == FK_PEN_HEAT_BOX;
+  const int nt = heat ? 2 : pen->nterms;
+  const int* alpha = heat ? heat_alpha : pen->alpha;
+  const double* coef = heat ? heat_coef : pen->coef;
+  if (nt < 1 || nt > 16 || !alpha || !coef) return FK_EINVAL;
+  for (int t = 0; t < nt; ++t) {
+    if (!std::isfinite(coef[t])) return FK_EINVAL;
+    for (int a = 0; a < d; ++a)
+      if (alpha[t * d + a] < 0 || alpha[t * d + a] > 8) return FK_EINVAL;
+  }
+  const int L = 2 * m + 1;
+  const int64_t N = ipow(L, d);
+  D.assign(2 * N, 0.0);
+  for (int64_t i = 0; i < N; ++i) {
+    int k[2] = {0, 0};
+    int64_t ii = i;
+    for (int a = d - 1; a >= 0; --a) {
+      k[a] = (int)(ii % L) - m;
+      ii /= L;
+    }
+    double re = 0.0, im = 0.0;
+    for (int t = 0; t < nt; ++t) {
+      double tr = coef[t], ti = 0.0;   // coef * prod_a (i k_a)^alpha
+      for (int a = 0; a < d; ++a)
+        for (int e = 0; e < alpha[t * d + a]; ++e) {   // multiply by i k_a
+          const double nr = -ti * k[a], ni = tr * k[a];
+          tr = nr;
+          ti = ni;
+        }
+      re += tr;
+      im += ti;
+    }
+    D[2 * i] = re;
+    D[2 * i + 1] = im;
+  }
   return FK_OK;
 }
 
@@ -280,15 +368,17 @@ static fk_status build_problem(int d, int m, const double* M, const double* b, c
                                const fk_penalty* pen, SolveProblem& P) {
   if ((d != 1 && d != 2) || m < 1 || m > 64 || nlam < 1 || nlam > 1024 || !lambdas) return FK_EINVAL;
   P.kind = SolveProblem::kToeplitz;
-  if (pen && pen->kind == FK_PEN_HEAT_BOX) {
-    if (d != 2 || !(pen->mu >= 0.0)) return FK_EINVAL;
-    P.kind = SolveProblem::kToeplitzHeat;
+  if (pen && (pen->kind == FK_PEN_HEAT_BOX || pen->kind == FK_PEN_PDE_BOX)) {
+    if ((pen->kind == FK_PEN_HEAT_BOX && d != 2) || !(pen->mu >= 0.0) || std::isinf(pen->mu)) return FK_EINVAL;
+    P.kind = SolveProblem::kToeplitzPde;
     P.mu = pen->mu;
-    for (int a = 0; a < 2; ++a) {
+    for (int a = 0; a < d; ++a) {
       P.lo[a] = pen->box_lo[a];
       P.hi[a] = pen->box_hi[a];
-      if (!(P.hi[a] > P.lo[a])) return FK_EINVAL;
+      if (!(P.hi[a] > P.lo[a]) || std::isinf(P.hi[a]) || std::isinf(P.lo[a])) return FK_EINVAL;
     }
+    fk_status st = pde_symbol(pen, d, m, P.dsym);
+    if (st != FK_OK) return st;
   }
   P.M = M;
   P.b = b;
@@ -320,12 +410,15 @@ extern "C" fk_status fk_solve(fk_ctx* ctx, int d, int m, const double* M, int nt
   SolveLayout s = solve_layout(P.L, nlam, ntgt, ws, ws_bytes);
   if (!ws || s.bytes > ws_bytes) return FK_ENOMEM;
   FK_HIP(hipSetDevice(ctx->device));
+  kept_invalidate(ws, ws_bytes);
   if (info) {
     std::memset(info, 0, sizeof(*info));
     info->bad_index = -1;
   }
   st = reset_flags(ctx);
   if (st == FK_OK) st = solve_impl(ctx, P, s, theta_out, info);
+  if (st == FK_OK || st == FK_ENOCONV)
+    kept_register(ws, s.bytes, ctx->device, kKeptToeplitz, d, m, P.L, nlam, ntgt, 1);
   if (info) info->status = st;
   return st;
 }
@@ -364,6 +457,7 @@ extern "C" fk_status fk_toeplitz_apply(fk_ctx* ctx, int d, int m, const double* 
   if (!ctx || !M || !x || !y || !toeplitz_fft_ok(d, m) || nvec < 1) return FK_EINVAL;
   if (!ws || ws_bytes < toeplitz_apply_workspace(d, m, nvec)) return FK_ENOMEM;
   FK_HIP(hipSetDevice(ctx->device));
+  kept_invalidate(ws, ws_bytes);
   Carve cv(ws, ws_bytes);
   return toeplitz_apply_impl(ctx, d, m, M, nvec, x, y, cv);
 }
@@ -391,7 +485,7 @@ static fk_status cg_common(fk_ctx* ctx, int d, int m, const double* M, int ntgt,
                            double* relres, void* ws, size_t ws_bytes) {
   if (!ctx || !M || !b || !theta_out || !lambdas || !cg_shape_ok(d, m, ntgt, nlam)) return FK_EINVAL;
   if (!(tol > 0.0) || !(tol < 1.0) || maxit < 1 || maxit > 1000000) return FK_EINVAL;
-  if (pen && pen->kind == FK_PEN_HEAT_BOX) return FK_EINVAL;   // dense penalty: use fk_solve
+  if (pen && (pen->kind == FK_PEN_HEAT_BOX || pen->kind == FK_PEN_PDE_BOX)) return FK_EINVAL;   // dense: fk_solve
   std::vector<double> pw;
   fk_status st = penalty_weights(pen, d, m, pw);
   if (st != FK_OK) return st;
@@ -400,6 +494,7 @@ static fk_status cg_common(fk_ctx* ctx, int d, int m, const double* M, int ntgt,
     if (!(l > 0.0) || std::isinf(l)) return FK_EINVAL;
   if (!ws || ws_bytes < cg_workspace(d, m, ntgt * nlam, nlam, Mr != nullptr)) return FK_ENOMEM;
   FK_HIP(hipSetDevice(ctx->device));
+  kept_invalidate(ws, ws_bytes);
   st = reset_flags(ctx);
   if (st != FK_OK) return st;
   Carve cv(ws, ws_bytes);
@@ -452,6 +547,7 @@ extern "C" fk_status fk_fit(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const vo
   if (st != FK_OK) return st;
   if (!ws || ws_bytes < fit_ws(d, n, ntgt, m, nlam)) return FK_ENOMEM;
   FK_HIP(hipSetDevice(ctx->device));
+  kept_invalidate(ws, ws_bytes);
   if (info) {
     std::memset(info, 0, sizeof(*info));
     info->bad_index = -1;
@@ -477,6 +573,8 @@ extern "C" fk_status fk_fit(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const vo
     return st;
   }
   st = solve_impl(ctx, P, s, theta_out, info);
+  if (st == FK_OK || st == FK_ENOCONV)
+    kept_register(ws, s.bytes, ctx->device, kKeptToeplitz, d, m, P.L, nlam, ntgt, 1);
   if (info) {
     info->status = st;
     info->t_total_ms = elapsed(ctx->ev[0], ctx->ev[8]);
@@ -494,10 +592,12 @@ extern "C" fk_status fk_heldout_mse(fk_ctx* ctx, int d, int m, int ntgt, int nla
     return FK_EINVAL;
   SolveLayout s = solve_layout((int)ipow(2 * m + 1, d), nlam, ntgt, ws, ws_bytes);
   if (!ws || s.bytes > ws_bytes) return FK_ENOMEM;
+  if (!kept_find(ws, ctx->device, kKeptToeplitz, d, m, s.N, nlam, ntgt, 1)) return FK_EINVAL;
   FK_HIP(hipSetDevice(ctx->device));
   fk_status st = heldout_mse_impl(ctx, s, d, m, Mv, bv, yv2, mse_out);
   if (st != FK_OK) return st;
   FK_HIP(hipStreamSynchronize(ctx->stream));
+  kept_register(ws, s.bytes, ctx->device, kKeptToeplitz, d, m, s.N, nlam, ntgt, 2);
   return FK_OK;
 }
 
@@ -545,15 +645,16 @@ extern "C" fk_status fk_mean_square(fk_ctx* ctx, int ntgt, int64_t n, fk_dtype d
 }
 
 extern "C" fk_status fk_fit_backward(fk_ctx* ctx, int d, int m, int ntgt, int nlam, const double* grad_mse,
-                                     double* grad_loglam, double* grad_p, double* grad_theta, void* ws,
-                                     size_t ws_bytes) {
+                                     const double* grad_theta_in, double* grad_loglam, double* grad_p,
+                                     double* grad_theta, void* ws, size_t ws_bytes) {
   if (!ctx || !grad_mse || !grad_loglam || (d != 1 && d != 2) || m < 1 || m > 64 || ntgt < 1 || ntgt > 32 ||
       nlam < 1 || nlam > 1024)
     return FK_EINVAL;
   SolveLayout s = solve_layout((int)ipow(2 * m + 1, d), nlam, ntgt, ws, ws_bytes);
   if (!ws || s.bytes > ws_bytes) return FK_ENOMEM;
+  if (!kept_find(ws, ctx->device, kKeptToeplitz, d, m, s.N, nlam, ntgt, 2)) return FK_EINVAL;
   FK_HIP(hipSetDevice(ctx->device));
-  fk_status st = backward_impl(ctx, s, d, grad_mse, grad_loglam, grad_p, grad_theta);
+  fk_status st = backward_impl(ctx, s, d, grad_mse, grad_theta_in, grad_loglam, grad_p, grad_theta);
   if (st != FK_OK) return st;
   FK_HIP(hipStreamSynchronize(ctx->stream));
   return FK_OK;
@@ -669,6 +770,7 @@ extern "C" fk_status fk_additive_gram(fk_ctx* ctx, int d, int64_t n, fk_dtype dt
   if (dt != FK_F32 && dt != FK_F64) return FK_EINVAL;
   if (!ws || ws_bytes < additive_gram_ws(d, n, ntgt, m)) return FK_ENOMEM;
   FK_HIP(hipSetDevice(ctx->device));
+  kept_invalidate(ws, ws_bytes);
   if (info) {
     std::memset(info, 0, sizeof(*info));
     info->bad_index = -1;
@@ -714,6 +816,7 @@ extern "C" fk_status fk_additive_fit(fk_ctx* ctx, int d, int64_t n, fk_dtype dt,
   if (!(s >= 0.0) || s > 64) return FK_EINVAL;
   if (!ws || ws_bytes < additive_fit_ws(d, n, ntgt, m, nlam)) return FK_ENOMEM;
   FK_HIP(hipSetDevice(ctx->device));
+  kept_invalidate(ws, ws_bytes);
   if (info) {
     std::memset(info, 0, sizeof(*info));
     info->bad_index = -1;

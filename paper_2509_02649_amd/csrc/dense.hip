@@ -22,6 +22,8 @@
 #include "fk_internal.h"
 
 #include <cmath>
+#include <cstdio>
+#include <string>
 #include <vector>
 
 namespace fk {
@@ -114,10 +116,13 @@ struct ToeplitzQ {
   }
 };
 
-// Heat-equation penalty mu conj(D_k) C[k,l] D_l, D_k = i k_t + k_x^2, modes (k_t, k_x),
-// C[k,l] = (2 pi)^-2 prod_a int_{lo_a}^{hi_a} exp(i (k_a - l_a) u) du.
-struct HeatQ {
-  int m;
+// Physics-informed penalty of a box (Sec. 4, tractable domains): mu conj(D_k) C[k, l] D_l with the
+// operator symbol D (device, N complex) and C[k, l] = (2 pi)^-d prod_a int_{lo_a}^{hi_a}
+// exp(i (l_a - k_a) u) du, so that theta^* C theta = (2 pi)^-d int_box |f_theta|^2 for
+// f_theta = sum_k theta_k exp(i k.x).  d = 1 or 2.
+struct PdeQ {
+  const double* dsym;
+  int m, d;
   double mu, lo0, hi0, lo1, hi1;
   __device__ static cplx box(int q, double lo, double hi) {
     if (q == 0) return {hi - lo, 0.0};
@@ -129,13 +134,20 @@ struct HeatQ {
   }
   __device__ cplx operator()(int i, int j) const {
     const int L = 2 * m + 1;
-    int kt = i / L - m, kx = i % L - m, lt = j / L - m, lx = j % L - m;
-    cplx ct = box(kt - lt, lo0, hi0), cx = box(kx - lx, lo1, hi1);
-    const double s = 1.0 / (4.0 * kPi * kPi);
-    cplx C = {(ct.re * cx.re - ct.im * cx.im) * s, (ct.re * cx.im + ct.im * cx.re) * s};
-    cplx Dk = {(double)(kx * kx), (double)kt}, Dl = {(double)(lx * lx), (double)lt};
+    cplx C;
+    if (d == 1) {
+      C = box((j - m) - (i - m), lo0, hi0);
+      const double s = 1.0 / (2.0 * kPi);
+      C = {C.re * s, C.im * s};
+    } else {
+      const int k0 = i / L - m, k1 = i % L - m, l0 = j / L - m, l1 = j % L - m;
+      const cplx c0 = box(l0 - k0, lo0, hi0), c1 = box(l1 - k1, lo1, hi1);
+      const double s = 1.0 / (4.0 * kPi * kPi);
+      C = {(c0.re * c1.re - c0.im * c1.im) * s, (c0.re * c1.im + c0.im * c1.re) * s};
+    }
+    const cplx Dk = {dsym[2 * i], dsym[2 * i + 1]}, Dl = {dsym[2 * j], dsym[2 * j + 1]};
     // conj(Dk) * C * Dl
-    cplx t = {Dk.re * C.re + Dk.im * C.im, Dk.re * C.im - Dk.im * C.re};
+    const cplx t = {Dk.re * C.re + Dk.im * C.im, Dk.re * C.im - Dk.im * C.re};
     return {mu * (t.re * Dl.re - t.im * Dl.im), mu * (t.re * Dl.im + t.im * Dl.re)};
   }
 };
@@ -966,6 +978,7 @@ SolveLayout solve_layout(int N, int nlam, int ntgt, void* base, size_t cap) {
   s.R64 = cv.take<double>(nc * Np);
   s.U64 = cv.take<double>(nc * Np);
   s.G64 = cv.take<double>(nc * Np);
+  s.Gadj = cv.take<double>(nc * Np);
   s.R32 = cv.take<float>(nc * Np);
   s.Y32 = cv.take<float>(nc * Np);
   s.D32 = cv.take<float>(nc * Np);
@@ -974,6 +987,7 @@ SolveLayout solve_layout(int N, int nlam, int ntgt, void* base, size_t cap) {
   s.Bv = cv.take<double>((size_t)ntgt * Np);
   s.pcx = cv.take<double>((size_t)N);
   s.scl = cv.take<double>((size_t)nlam * Np);
+  s.dsym = cv.take<double>((size_t)2 * N);
   s.bytes = cv.off + 256;
   return s;
 }
@@ -981,7 +995,7 @@ SolveLayout solve_layout(int N, int nlam, int ntgt, void* base, size_t cap) {
 // Factor A32[l] = L L^T for every lambda (blocked, right-looking).
 // Left-looking blocked Cholesky: per block column, update with the finished panels
 // (one pass over the column), factor the diagonal block, solve the panel below it.
-static fk_status factor_all(fk_ctx* ctx, const SolveLayout& s) {
+static fk_status factor_all(fk_ctx* ctx, const SolveLayout& s, const DenseShape& sh) {
   const int nb = s.Np / NB;
   auto finish = [&](int kb) {   // diagonal block and the panel below it
     hipLaunchKernelGGL(k_potrf_diag, dim3(s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv, ctx->flags);
@@ -992,7 +1006,7 @@ static fk_status factor_all(fk_ctx* ctx, const SolveLayout& s) {
   // Block columns in pairs (kb, kb + 1): one pass over the panels k < kb updates both,
   // then column kb is finished, then column kb + 1 takes its remaining term k = kb.
   for (int kb = 0; kb < nb;) {
-    if (kb > 0 && kb + 1 < nb) {
+    if (sh.pair && kb > 0 && kb + 1 < nb) {
       hipLaunchKernelGGL(k_left_update2, dim3(nb - kb, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb);
       finish(kb);
       hipLaunchKernelGGL(k_left_update, dim3(nb - kb - 1, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb + 1,
@@ -1011,11 +1025,11 @@ static fk_status factor_all(fk_ctx* ctx, const SolveLayout& s) {
 }
 
 // D32 = A^-1 R32 per lambda (ncol = ntgt columns each), through Y32.
-static fk_status trsm_all(fk_ctx* ctx, const SolveLayout& s, float* R, float* Y, float* X) {
+static fk_status trsm_all(fk_ctx* ctx, const SolveLayout& s, const DenseShape& sh, float* R, float* Y, float* X) {
   const int nb = s.Np / NB;
   const bool two = s.ntgt > 16;
-  // workgroups per lambda: about 512 in all (two per CU), each sweeping several rows
-  const int gmax = std::max(1, 512 / s.nlam);
+  // workgroups per lambda: about sh.trsm_wg in all, each sweeping several rows
+  const int gmax = std::max(1, sh.trsm_wg / s.nlam);
   for (int kb = 0; kb < nb; ++kb) {
     int g = std::max(1, std::min(gmax, nb - kb - 1));
     if (two)
@@ -1041,8 +1055,8 @@ static fk_status trsm_all(fk_ctx* ctx, const SolveLayout& s, float* R, float* Y,
 // Solve (H64 + lambda diag(preal)) X = RHS for all (lambda, target) with FP32
 // factors and FP64 refinement.  RHS given per target (Bre) or per column (rhs_cols).
 // Returns the number of refinement steps and the worst relative residual.
-static fk_status refine_solve(fk_ctx* ctx, const SolveLayout& s, const double* rhs_cols, double* X,
-                              int* iters_out, double* resid_out, int* bad_out) {
+static fk_status refine_solve(fk_ctx* ctx, const SolveLayout& s, const DenseShape& sh, const double* rhs_cols,
+                              double* X, int* iters_out, double* resid_out, int* bad_out) {
   const int64_t tot = (int64_t)s.nlam * s.ntgt * s.Np;
   const int nc = s.nlam * s.ntgt;
   const int thr = 256;
@@ -1065,7 +1079,7 @@ static fk_status refine_solve(fk_ctx* ctx, const SolveLayout& s, const double* r
   for (;; ++it) {
     hipLaunchKernelGGL(k_scale_d2f, dim3(blocks), dim3(thr), 0, ctx->stream, s.R64, s.scl, s.Np, s.ntgt, s.R32,
                        tot);
-    fk_status st = trsm_all(ctx, s, s.R32, s.Y32, s.D32);
+    fk_status st = trsm_all(ctx, s, sh, s.R32, s.Y32, s.D32);
     if (st != FK_OK) return st;
     hipLaunchKernelGGL(k_scale_axpy_f2d, dim3(blocks), dim3(thr), 0, ctx->stream, s.D32, s.scl, s.Np, s.ntgt, X,
                        tot);
@@ -1079,6 +1093,14 @@ static fk_status refine_solve(fk_ctx* ctx, const SolveLayout& s, const double* r
     worst = 0.0;
     bad = -1;
     for (int c = 0; c < nc; ++c) {
+      // a NaN or Inf right-hand side (or one that the solve turned into one) is an input error,
+      // not a refinement stall
+      if (!std::isfinite(nh[c]) || !std::isfinite(nh[nc + c])) {
+        *iters_out = it;
+        *resid_out = nh[c];
+        *bad_out = c / s.ntgt;
+        return FK_ENAN;
+      }
       double rel = nh[nc + c] > 0 ? std::sqrt(nh[c] / nh[nc + c]) : std::sqrt(nh[c]);
       if (!(rel <= worst)) {
         worst = rel;
@@ -1091,6 +1113,81 @@ static fk_status refine_solve(fk_ctx* ctx, const SolveLayout& s, const double* r
   *resid_out = worst;
   *bad_out = bad;
   return worst <= tol ? FK_OK : FK_ENOCONV;
+}
+
+static std::string dense_key(const fk_ctx* ctx, const SolveLayout& s) {
+  char key[128];
+  std::snprintf(key, sizeof(key), "%s dense Np=%d nlam=%d ntgt=%d", tune_arch(ctx->device).c_str(), s.Np, s.nlam,
+                s.ntgt);
+  return key;
+}
+
+static bool dense_tunable(const SolveLayout& s) { return (double)s.Np * s.Np * s.nlam >= (double)(1 << 28); }
+
+// The table's launch shape of this dense shape (the defaults when there is none).
+static DenseShape dense_shape(const fk_ctx* ctx, const SolveLayout& s) {
+  DenseShape sh;
+  std::map<std::string, double> v;
+  if (tune_mode(ctx) == kTuneOff || !tune_lookup(dense_key(ctx, s), &v)) return sh;
+  if (v.count("trsm_wg") && v["trsm_wg"] >= 64 && v["trsm_wg"] <= 4096) sh.trsm_wg = (int)v["trsm_wg"];
+  if (v.count("pair")) sh.pair = v["pair"] != 0.0;
+  return sh;
+}
+
+// Launch shape of the factorization and the triangular solves.  Tuning (large batched solves whose
+// shape has no table entry): each pairing candidate rebuilds the FP32 matrices and factors them, the
+// last leaves valid factors (*factored); each solve width is timed on zero right-hand sides.
+static fk_status tune_dense(fk_ctx* ctx, const SolveLayout& s, DenseShape* out, bool* factored) {
+  const int mode = tune_mode(ctx);
+  *factored = false;
+  *out = dense_shape(ctx, s);
+  if (mode == kTuneOff || !dense_tunable(s)) return FK_OK;
+  std::map<std::string, double> v;
+  if (mode != kTuneForce && tune_lookup(dense_key(ctx, s), &v)) return FK_OK;
+  const int64_t tot2 = (int64_t)s.Np * s.Np;
+  const int gb = (int)((tot2 + 255) / 256);
+  hipEvent_t e0 = ctx->ev[11], e1 = ctx->ev[12];
+  DenseShape sh;
+  float best_f = 0.f;
+  for (int pair : {1, 0}) {
+    DenseShape c = sh;
+    c.pair = pair;
+    hipLaunchKernelGGL(k_make_a32, dim3(gb), dim3(256), 0, ctx->stream, s.H64, s.preal, s.lams, s.scl, s.N, s.Np,
+                       s.nlam, s.A32);
+    FK_HIP(hipEventRecord(e0, ctx->stream));
+    fk_status st = factor_all(ctx, s, c);
+    if (st != FK_OK) return st;
+    FK_HIP(hipEventRecord(e1, ctx->stream));
+    FK_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    FK_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (pair == 1 || ms < best_f) {
+      best_f = ms;
+      sh.pair = pair;
+    }
+  }
+  *factored = true;
+  const size_t nv = (size_t)s.nlam * s.ntgt * s.Np;
+  FK_HIP(hipMemsetAsync(s.R32, 0, sizeof(float) * nv, ctx->stream));
+  float best_t = 0.f;
+  for (int wg : {512, 256, 1024}) {
+    DenseShape c = sh;
+    c.trsm_wg = wg;
+    FK_HIP(hipEventRecord(e0, ctx->stream));
+    fk_status st = trsm_all(ctx, s, c, s.R32, s.Y32, s.D32);
+    if (st != FK_OK) return st;
+    FK_HIP(hipEventRecord(e1, ctx->stream));
+    FK_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    FK_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (wg == 512 || ms < best_t) {
+      best_t = ms;
+      sh.trsm_wg = wg;
+    }
+  }
+  tune_store(dense_key(ctx, s), {{"pair", sh.pair}, {"trsm_wg", sh.trsm_wg}}, best_f + best_t);
+  *out = sh;
+  return FK_OK;
 }
 
 fk_status solve_impl(fk_ctx* ctx, const SolveProblem& P, const SolveLayout& s, double* theta_out,
@@ -1110,10 +1207,11 @@ fk_status solve_impl(fk_ctx* ctx, const SolveProblem& P, const SolveLayout& s, d
   if (P.kind == SolveProblem::kToeplitz) {
     ToeplitzQ q{P.M, P.m, P.d};
     hipLaunchKernelGGL(k_assemble_real<ToeplitzQ>, dim3(gb), dim3(256), 0, ctx->stream, q, N, L, Np, s.H64);
-  } else if (P.kind == SolveProblem::kToeplitzHeat) {
-    using HQ = SumQ<ToeplitzQ, HeatQ>;
-    HQ q{ToeplitzQ{P.M, P.m, P.d}, HeatQ{P.m, P.mu, P.lo[0], P.hi[0], P.lo[1], P.hi[1]}};
-    hipLaunchKernelGGL(k_assemble_real<HQ>, dim3(gb), dim3(256), 0, ctx->stream, q, N, L, Np, s.H64);
+  } else if (P.kind == SolveProblem::kToeplitzPde) {
+    FK_HIP(hipMemcpyAsync(s.dsym, P.dsym.data(), sizeof(double) * 2 * N, hipMemcpyHostToDevice, ctx->stream));
+    using PQ = SumQ<ToeplitzQ, PdeQ>;
+    PQ q{ToeplitzQ{P.M, P.m, P.d}, PdeQ{s.dsym, P.m, P.d, P.mu, P.lo[0], P.hi[0], P.lo[1], P.hi[1]}};
+    hipLaunchKernelGGL(k_assemble_real<PQ>, dim3(gb), dim3(256), 0, ctx->stream, q, N, L, Np, s.H64);
   } else {
     DenseQ q{P.B, N};
     hipLaunchKernelGGL(k_assemble_real<DenseQ>, dim3(gb), dim3(256), 0, ctx->stream, q, N, L, Np, s.H64);
@@ -1125,9 +1223,15 @@ fk_status solve_impl(fk_ctx* ctx, const SolveProblem& P, const SolveLayout& s, d
   hipLaunchKernelGGL(k_rhs_real, dim3((Np + 255) / 256, s.ntgt), dim3(256), 0, ctx->stream, P.b, N, L, Np,
                      s.ntgt, s.Bre);
   FK_HIP(hipGetLastError());
-  FK_HIP(hipEventRecord(ev[6], ctx->stream));
-  fk_status st = factor_all(ctx, s);
+  DenseShape sh;
+  bool factored = false;
+  fk_status st = tune_dense(ctx, s, &sh, &factored);
   if (st != FK_OK) return st;
+  FK_HIP(hipEventRecord(ev[6], ctx->stream));
+  if (!factored) {
+    st = factor_all(ctx, s, sh);
+    if (st != FK_OK) return st;
+  }
   FK_HIP(hipEventRecord(ev[7], ctx->stream));
   st = read_flags(ctx);
   if (st != FK_OK) {
@@ -1136,7 +1240,7 @@ fk_status solve_impl(fk_ctx* ctx, const SolveProblem& P, const SolveLayout& s, d
   }
   int iters = 0, bad = -1;
   double resid = 0.0;
-  st = refine_solve(ctx, s, nullptr, s.X64, &iters, &resid, &bad);
+  st = refine_solve(ctx, s, sh, nullptr, s.X64, &iters, &resid, &bad);
   hipLaunchKernelGGL(k_theta_from_real, dim3((N + 255) / 256, s.nlam * s.ntgt), dim3(256), 0, ctx->stream, s.X64,
                      N, L, Np, s.ntgt, theta_out);
   FK_HIP(hipGetLastError());
@@ -1218,21 +1322,41 @@ fk_status heldout_mse_impl(fk_ctx* ctx, const SolveLayout& s, int d, int m, cons
   return FK_OK;
 }
 
-// grad_loglam[l] = sum_t gm[l,t] (-2 lambda_l) u.(preal o x);  grad_p (complex modes) likewise.
+// Adjoint right-hand sides in real form: Gadj[c] = gm[c] G64[c] + (1/2) d(Loss)/dc of the incoming
+// Wirtinger gradient gin[c] = dLoss/dconj(theta_c) (complex, N modes).  With theta = U c (real c),
+// dLoss/dc_r = 2 Re(gin^* dtheta/dc_r), so the real-form entry is Re gin_0 (constant),
+// (Re gin_k + Re gin_-k)/sqrt2 (cosine of k) and (Im gin_-k - Im gin_k)/sqrt2 (sine of k): the
+// projection onto Hermitian-symmetric theta, where every fitted theta lies.
+__global__ void k_adjoint_rhs(const double* __restrict__ G64, const double* __restrict__ gm,
+                              const double* __restrict__ gin, int N, int L, int Np, double* __restrict__ Gadj) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (r >= Np) return;
+  double v = gm[c] * G64[(size_t)c * Np + r];
+  if (gin && r < N) {
+    int ty, k, nk;
+    real_to_complex(r, L, &ty, &k, &nk);
+    const double* g = gin + 2 * (size_t)c * N;
+    const double rs2 = 0.70710678118654752440;
+    v += ty == 0 ? g[2 * k] : (ty == 1 ? rs2 * (g[2 * k] + g[2 * nk]) : rs2 * (g[2 * nk + 1] - g[2 * k + 1]));
+  }
+  Gadj[(size_t)c * Np + r] = v;
+}
+
+// grad_loglam[l] = sum_t (-2 lambda_l) u.(preal o x), u the adjoint solution of the combined
+// right-hand side;  grad_p (complex modes) likewise.
 __global__ __launch_bounds__(256) void k_grad_loglam(const double* __restrict__ U, const double* __restrict__ X,
                                                      const double* __restrict__ preal, const double* __restrict__ lams,
-                                                     const double* __restrict__ gm, int Np, int ntgt,
-                                                     double* __restrict__ out) {
+                                                     int Np, int ntgt, double* __restrict__ out) {
   __shared__ double part[256];
   const int l = blockIdx.x;
   double s = 0.0;
   for (int t = 0; t < ntgt; ++t) {
     const double* u = U + ((size_t)l * ntgt + t) * Np;
     const double* x = X + ((size_t)l * ntgt + t) * Np;
-    double g = gm[l * ntgt + t];
     double a = 0.0;
     for (int i = threadIdx.x; i < Np; i += blockDim.x) a += u[i] * preal[i] * x[i];
-    s += g * a;
+    s += a;
   }
   part[threadIdx.x] = s;
   __syncthreads();
@@ -1244,8 +1368,7 @@ __global__ __launch_bounds__(256) void k_grad_loglam(const double* __restrict__ 
 }
 
 __global__ void k_grad_p(const double* __restrict__ U, const double* __restrict__ X, const double* __restrict__ lams,
-                         const double* __restrict__ gm, int N, int L, int Np, int nlam, int ntgt,
-                         double* __restrict__ gp) {
+                         int N, int L, int Np, int nlam, int ntgt, double* __restrict__ gp) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= N) return;
   int ty, k, nk;
@@ -1256,7 +1379,7 @@ __global__ void k_grad_p(const double* __restrict__ U, const double* __restrict_
     for (int t = 0; t < ntgt; ++t) {
       const size_t o = ((size_t)l * ntgt + t) * Np;
       double v = ty == 0 ? U[o + r] * X[o + r] : 0.5 * (U[o + r] * X[o + r] + U[o + r + 1] * X[o + r + 1]);
-      s += gm[l * ntgt + t] * (-2.0 * lams[l]) * v;
+      s += (-2.0 * lams[l]) * v;
     }
   gp[k] = s;
   if (ty == 1) gp[nk] = s;
@@ -1269,19 +1392,21 @@ __global__ void k_scale_cols_cplx(double* __restrict__ th, const double* __restr
   th[(size_t)c * 2 * N + i] *= gm[c];
 }
 
-fk_status backward_impl(fk_ctx* ctx, const SolveLayout& s, int d, const double* gm, double* grad_loglam,
-                        double* grad_p, double* grad_theta) {
+fk_status backward_impl(fk_ctx* ctx, const SolveLayout& s, int d, const double* gm, const double* gin,
+                        double* grad_loglam, double* grad_p, double* grad_theta) {
   const int N = s.N, Np = s.Np, L = N;   // one real-form block of all N modes
   const int nc = s.nlam * s.ntgt;
   int iters = 0, bad = -1;
   double resid = 0.0;
-  // u = A^-1 g for every (lambda, target): columns of G64 are the right-hand sides
-  fk_status st = refine_solve(ctx, s, s.G64, s.U64, &iters, &resid, &bad);
+  // u = A^-1 (gm g + gin) for every (lambda, target)
+  hipLaunchKernelGGL(k_adjoint_rhs, dim3((Np + 255) / 256, nc), dim3(256), 0, ctx->stream, s.G64, gm, gin, N, L, Np,
+                     s.Gadj);
+  fk_status st = refine_solve(ctx, s, dense_shape(ctx, s), s.Gadj, s.U64, &iters, &resid, &bad);
   if (st != FK_OK && st != FK_ENOCONV) return st;
-  hipLaunchKernelGGL(k_grad_loglam, dim3(s.nlam), dim3(256), 0, ctx->stream, s.U64, s.X64, s.preal, s.lams, gm, Np,
+  hipLaunchKernelGGL(k_grad_loglam, dim3(s.nlam), dim3(256), 0, ctx->stream, s.U64, s.X64, s.preal, s.lams, Np,
                      s.ntgt, grad_loglam);
   if (grad_p)
-    hipLaunchKernelGGL(k_grad_p, dim3((N + 255) / 256), dim3(256), 0, ctx->stream, s.U64, s.X64, s.lams, gm, N, L,
+    hipLaunchKernelGGL(k_grad_p, dim3((N + 255) / 256), dim3(256), 0, ctx->stream, s.U64, s.X64, s.lams, N, L,
                        Np, s.nlam, s.ntgt, grad_p);
   if (grad_theta) {
     hipLaunchKernelGGL(k_theta_from_real, dim3((N + 255) / 256, nc), dim3(256), 0, ctx->stream, s.G64, N, L, Np,

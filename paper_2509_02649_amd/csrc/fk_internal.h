@@ -4,6 +4,7 @@
 #include <cstdint>
 #include <cstddef>
 #include <map>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -67,6 +68,7 @@ struct SolveLayout {
   double* R64 = nullptr;   // residuals
   double* U64 = nullptr;   // adjoint solutions
   double* G64 = nullptr;   // held-out gradient directions
+  double* Gadj = nullptr;  // adjoint right-hand sides
   float* R32 = nullptr;
   float* Y32 = nullptr;
   float* D32 = nullptr;
@@ -75,26 +77,39 @@ struct SolveLayout {
   double* Bv = nullptr;    // held-out real right-hand sides
   double* pcx = nullptr;   // N complex-mode weights
   double* scl = nullptr;   // nlam x Np diagonal equilibration of the FP32 factor
+  double* dsym = nullptr;  // N complex: operator symbol of a physics-informed penalty
   size_t bytes = 0;
 };
 SolveLayout solve_layout(int N, int nlam, int ntgt, void* base, size_t cap);
 
 struct SolveProblem {
-  enum Kind { kToeplitz = 0, kToeplitzHeat = 1, kDense = 2 } kind = kToeplitz;
+  enum Kind { kToeplitz = 0, kToeplitzPde = 1, kDense = 2 } kind = kToeplitz;
   const double* M = nullptr;  // generator (Toeplitz kinds)
   const double* B = nullptr;  // dense complex matrix (kDense)
   const double* b = nullptr;  // complex right-hand sides ntgt x N
   int m = 0, d = 0, L = 0;    // L: complex modes per real-form block
   std::vector<double> p;      // complex-mode diagonal weights (N)
   std::vector<double> lams;   // nlam
+  // kToeplitzPde: mu D^* C D with the operator symbol D (N complex, interleaved) and the box
+  // [lo, hi] of the Fourier matrix C (d <= 2)
+  std::vector<double> dsym;
   double mu = 0, lo[2] = {0, 0}, hi[2] = {0, 0};
 };
 fk_status solve_impl(fk_ctx* ctx, const SolveProblem& P, const SolveLayout& s, double* theta_out,
                      fk_fit_info* info);
 fk_status heldout_mse_impl(fk_ctx* ctx, const SolveLayout& s, int d, int m, const double* Mv, const double* bv,
                            const double* yv2, double* mse);
-fk_status backward_impl(fk_ctx* ctx, const SolveLayout& s, int d, const double* gm, double* grad_loglam,
-                        double* grad_p, double* grad_theta);
+// gin: device complex [nlam][ntgt][N] dLoss/dconj(theta) from other uses of theta, or null.
+fk_status backward_impl(fk_ctx* ctx, const SolveLayout& s, int d, const double* gm, const double* gin,
+                        double* grad_loglam, double* grad_p, double* grad_theta);
+
+// Registry of workspaces that hold kept factors (process-wide, all contexts and devices).
+// stage 1: factors and solutions of a solve; stage 2: held-out gradient directions as well.
+enum KeptKind { kKeptToeplitz = 0, kKeptDense = 1 };
+void kept_invalidate(const void* ws, size_t bytes);
+void kept_register(const void* ws, size_t bytes, int device, int kind, int d, int m, int N, int nlam, int ntgt,
+                   int stage);
+bool kept_find(const void* ws, int device, int kind, int d, int m, int N, int nlam, int ntgt, int min_stage);
 fk_status reset_flags(fk_ctx* ctx);
 
 // MFMA spread for 8..16 weight channels over MB x MB-cell bins (spread_mfma.hip):
@@ -103,7 +118,7 @@ int spread_mfma_bin(int nf, int64_t n);
 bool spread_mfma_ok(int nw, int W);
 fk_status launch_spread_mfma(hipStream_t st, int W, int MB, const uint32_t* crd, const uint32_t* pos,
                              const uint32_t* wrow, int nw, const uint64_t* start, int nbx, int nb, int nf, int fb,
-                             double beta, int64_t n, double* grid);
+                             double beta, int64_t n, int spread_pts, double* grid);
 
 // MFMA spread for 0..7 weight channels as per-channel outer products over 8 x 8-cell
 // bins (spread_op.hip).
@@ -111,7 +126,30 @@ int spread_op_bin();
 bool spread_op_ok(int nw, int W);
 fk_status launch_spread_op(hipStream_t st, int W, const uint32_t* crd, const uint32_t* wts, int nw,
                            const uint64_t* start, int nbx, int nb, int nf, int fb, double beta, int64_t n,
-                           double* grid);
+                           int spread_pts, double* grid);
+
+// Autotuner (tune.hip): process-wide table of measured launch shapes.
+enum TuneMode { kTuneEnv = 0, kTuneOff = 1, kTuneForce = 2, kTuneAuto = 3 };
+int tune_mode(const fk_ctx* ctx);
+std::string tune_arch(int device);
+bool tune_lookup(const std::string& key, std::map<std::string, double>* values);
+void tune_store(const std::string& key, const std::map<std::string, double>& values, double ms);
+
+// Launch shape of the sorted 2-D type-1 stage.
+struct T1Shape {
+  int mb = 0;                 // bin edge of the channel-row spread (2 or 4 cells); 0: by density
+  int spread_pts = 16384;     // points per spreading workgroup (a slice of one bin)
+  int sort_blk = 512;         // workgroups of the first sort pass (at most; fewer for small n)
+  int sort_slice = 65536;     // points per workgroup of the second sort pass
+};
+constexpr int kSortBlkMax = 1024;
+constexpr int kSortSliceMin = 32768;
+
+// Launch shape of the dense solve.
+struct DenseShape {
+  int trsm_wg = 512;          // workgroups per triangular-solve launch (over all lambdas)
+  int pair = 1;               // factor block columns in pairs (row panels read once for two)
+};
 
 // Two-pass bin sort for the MFMA spreads (sort2.hip): scratch buffers carved from
 // the caller's workspace, and the sort itself (bin starts in start[0..nbx^2]).
@@ -130,10 +168,12 @@ struct Sort2Bufs {
 };
 bool sort2_ok(int nbx);
 int sort2_words(int nw);
+// Buffers for any shape with at most kSortBlkMax first-pass workgroups and slices of at least
+// kSortSliceMin points.
 void sort2_carve(Carve& cv, int64_t n, int nbx, int wv, Sort2Bufs* b);
 fk_status sort2(hipStream_t st, const void* X, fk_dtype dt, int64_t n, int64_t xstride, const void* Y, int nw,
-                int nf, int fb, int W, double scale, int tshift, int nbx, const Sort2Bufs& b, uint32_t* crd,
-                uint32_t* wts, uint64_t* start, int* flags);
+                int nf, int fb, int W, double scale, int tshift, int nbx, const T1Shape& shape, const Sort2Bufs& b,
+                uint32_t* crd, uint32_t* wts, uint64_t* start, int* flags);
 
 }  // namespace fk
 

@@ -248,6 +248,7 @@ extern "C" fk_status fk_predict(fk_ctx* ctx, int d, int m, int T, const double* 
   if (dt != FK_F32 && dt != FK_F64) return FK_EINVAL;
   if (!ws || ws_bytes < predict_ws(d, m, T)) return FK_ENOMEM;
   FK_HIP(hipSetDevice(ctx->device));
+  kept_invalidate(ws, ws_bytes);
   EsPlan plan;
   const double* phihat;
   fk_status st = get_es_plan(ctx, m, &plan, &phihat);

@@ -34,6 +34,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 
@@ -716,9 +717,16 @@ static Spread2 spread2_kind(int nw, int nf, int W, int64_t n) {
   return Spread2::kAtomic;
 }
 
-static BinGeom bin_geom(int nf, int C, int64_t n, Spread2 kind) {
+// Bin edge of the channel-row spread: the shape's choice when the sort can take it, else the
+// density rule.
+static int rows_bin(int nf, int64_t n, int mb) {
+  if ((mb == 2 || mb == 4) && sort2_ok(nf / mb)) return mb;
+  return spread_mfma_bin(nf, n);
+}
+
+static BinGeom bin_geom(int nf, int C, int64_t n, Spread2 kind, int mb = 0) {
   BinGeom g;
-  g.T = kind == Spread2::kRows ? spread_mfma_bin(nf, n)
+  g.T = kind == Spread2::kRows ? rows_bin(nf, n, mb)
         : kind == Spread2::kOuter ? spread_op_bin() : ((C > 8) ? 16 : 32);
   if (g.T > nf) g.T = nf;
   g.tshift = ilog2(g.T);
@@ -758,6 +766,10 @@ size_t type1_workspace(int d, int64_t n, int nw, int K, double eps) {
     cv.take<double>((size_t)C * nf * nf);          // FP64 grid
     cv.take<double>((size_t)C * nf * L * 2);        // row-FFT output
     BinGeom g = bin_geom(nf, C, n, kind);
+    if (kind == Spread2::kRows) {                   // bin starts for the finest bins any shape takes
+      const BinGeom g2 = bin_geom(nf, C, n, kind, 2);
+      if (g2.nb > g.nb) g = g2;
+    }
     cv.take<uint32_t>((size_t)g.nb * g.nblk);
     cv.take<uint32_t>((size_t)g.nb);
     cv.take<uint64_t>((size_t)g.nb + 1);
@@ -779,9 +791,9 @@ size_t type1_workspace(int d, int64_t n, int nw, int K, double eps) {
 
 template <int W>
 static void launch_spread_1d(fk_ctx* ctx, int blocks, size_t lds, const void* X, fk_dtype dt, int64_t n,
-                             const void* Y, int nw, int nf, int fb, double scale, EsDev es, double* grid,
+                             const void* Y, int nw, int ones, int nf, int fb, double scale, EsDev es, double* grid,
                              int64_t chunk) {
-  hipLaunchKernelGGL(k_spread_1d<W>, dim3(blocks), dim3(256), lds, ctx->stream, X, dt, n, Y, nw, 1, nf,
+  hipLaunchKernelGGL(k_spread_1d<W>, dim3(blocks), dim3(256), lds, ctx->stream, X, dt, n, Y, nw, ones, nf,
                      fb, scale, es, grid, ctx->flags, chunk);
 }
 
@@ -827,6 +839,74 @@ static void launch_spread_2d(fk_ctx* ctx, int blocks, size_t lds, const uint32_t
     default: return FK_EINVAL;                       \
   }
 
+// Launch shape of the sorted 2-D type-1 stage: the table's entry for this shape, or (when the
+// problem is large enough for shapes to matter and the mode allows) coordinate descent over the
+// candidates, each run on the call's own data and timed between ev[0] and ev[2].
+template <class Run>
+static fk_status tune_t1(fk_ctx* ctx, int d, int nf, int W, int nw, int64_t n, bool rows, Run& run, T1Shape* out) {
+  T1Shape sh;
+  const int mode = tune_mode(ctx);
+  if (mode == kTuneOff) {
+    *out = sh;
+    return FK_OK;
+  }
+  char key[160];
+  std::snprintf(key, sizeof(key), "%s t1 d=%d nf=%d w=%d nw=%d n=2^%d", tune_arch(ctx->device).c_str(), d, nf, W, nw,
+                ilog2((int)std::min<int64_t>(n >> 10, 1 << 30)) + 10);
+  std::map<std::string, double> v;
+  if (mode != kTuneForce && tune_lookup(key, &v)) {
+    if (v.count("mb")) sh.mb = (int)v["mb"];
+    if (v.count("spread_pts") && v["spread_pts"] >= 256) sh.spread_pts = (int)v["spread_pts"];
+    if (v.count("sort_blk") && v["sort_blk"] >= 1 && v["sort_blk"] <= kSortBlkMax) sh.sort_blk = (int)v["sort_blk"];
+    if (v.count("sort_slice") && v["sort_slice"] >= kSortSliceMin) sh.sort_slice = (int)v["sort_slice"];
+    *out = sh;
+    return FK_OK;
+  }
+  if (n < ((int64_t)1 << 22)) {   // small problems: launch and latency bound, the defaults
+    *out = sh;
+    return FK_OK;
+  }
+  auto time_of = [&](const T1Shape& s, float* ms) -> fk_status {
+    fk_status st = run(s);
+    if (st != FK_OK) return st;
+    FK_HIP(hipEventSynchronize(ctx->ev[2]));
+    FK_HIP(hipEventElapsedTime(ms, ctx->ev[0], ctx->ev[2]));
+    return FK_OK;
+  };
+  float best;
+  fk_status st = time_of(sh, &best);
+  if (st != FK_OK) return st;
+  auto knob = [&](int T1Shape::*field, std::initializer_list<int> cands) -> fk_status {
+    for (int c : cands) {
+      if (sh.*field == c) continue;
+      T1Shape t = sh;
+      t.*field = c;
+      float ms;
+      fk_status s = time_of(t, &ms);
+      if (s != FK_OK) return s;
+      if (ms < best) {
+        best = ms;
+        sh = t;
+      }
+    }
+    return FK_OK;
+  };
+  if (rows) {
+    sh.mb = spread_mfma_bin(nf, n);
+    st = knob(&T1Shape::mb, {2, 4});
+    if (st != FK_OK) return st;
+  }
+  if ((st = knob(&T1Shape::spread_pts, {4096, 8192, 16384, 32768})) != FK_OK) return st;
+  if ((st = knob(&T1Shape::sort_blk, {256, 512, 1024})) != FK_OK) return st;
+  if ((st = knob(&T1Shape::sort_slice, {32768, 65536, 131072})) != FK_OK) return st;
+  std::map<std::string, double> rec{{"spread_pts", sh.spread_pts}, {"sort_blk", sh.sort_blk},
+                                    {"sort_slice", sh.sort_slice}};
+  if (rows) rec["mb"] = sh.mb;
+  tune_store(key, rec, best);
+  *out = sh;
+  return FK_OK;
+}
+
 // out: complex128 [C][(2K+1)^d], C = nw + 1, channel 0 = weight 1.
 // out_c[q] = sign_scale * sum_j w_cj exp(-i q.x_j).
 fk_status type1(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int64_t xstride, int nw,
@@ -854,10 +934,21 @@ fk_status type1(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int64
     FK_HIP(hipMemsetAsync(grid, 0, sizeof(double) * C * nf, ctx->stream));
     int blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 4095) / 4096));
     int64_t chunk = (n + blocks - 1) / blocks;
-    size_t lds = sizeof(double) * C * nf;
-    if (lds > 160 * 1024) return FK_EINVAL;
+    // channels per launch: as many whole FP64 grids as 160 KB of LDS holds (the ones channel
+    // goes with the first launch); the grid is [C][nf], so a launch writes channels ones + c0 ..
+    const int per = (int)((160 * 1024) / (sizeof(double) * nf));
+    if (per < 2) return FK_EINVAL;
+    const size_t esz = dt == FK_F64 ? sizeof(double) : sizeof(float);
     FK_HIP(hipEventRecord(ev[1], ctx->stream));
-    FK_W_SWITCH(W, launch_spread_1d<WW>(ctx, blocks, lds, X, dt, n, Y, nw, nf, fb, scale, es, grid, chunk));
+    for (int c0 = 0, first = 1; first || c0 < nw; first = 0) {
+      const int cnt = std::min(per - first, nw - c0);
+      const void* Yc = Y ? static_cast<const void*>(static_cast<const char*>(Y) + esz * (size_t)c0 * n) : nullptr;
+      double* gc = grid + (size_t)(first ? 0 : 1 + c0) * nf;
+      const size_t lds = sizeof(double) * (size_t)(cnt + first) * nf;
+      FK_W_SWITCH(W, launch_spread_1d<WW>(ctx, blocks, lds, X, dt, n, Yc, cnt, first, nf, fb, scale, es, gc,
+                                          chunk));
+      c0 += cnt;
+    }
     FK_HIP(hipGetLastError());
     FK_HIP(hipEventRecord(ev[2], ctx->stream));
     hipLaunchKernelGGL(k_fft_line, dim3(C), dim3(256), 0, ctx->stream, grid, 0, (int64_t)1, (int64_t)nf,
@@ -942,59 +1033,76 @@ fk_status type1(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int64
   const Spread2 kind = spread2_kind(nw, nf, W, n);
   const bool split = kind != Spread2::kAtomic;   // two-pass sort, then an MFMA spread
   const int wv = sort2_words(nw);
-  BinGeom g = bin_geom(nf, C, n, kind);
-  uint32_t* cnt = cv.take<uint32_t>((size_t)g.nb * g.nblk);
-  uint32_t* totals = cv.take<uint32_t>((size_t)g.nb);
-  uint64_t* start = cv.take<uint64_t>((size_t)g.nb + 1);
+  BinGeom gmax = bin_geom(nf, C, n, kind);
+  if (kind == Spread2::kRows) {
+    const BinGeom g2 = bin_geom(nf, C, n, kind, 2);
+    if (g2.nb > gmax.nb) gmax = g2;
+  }
+  uint32_t* cnt = cv.take<uint32_t>((size_t)gmax.nb * gmax.nblk);
+  uint32_t* totals = cv.take<uint32_t>((size_t)gmax.nb);
+  uint64_t* start = cv.take<uint64_t>((size_t)gmax.nb + 1);
   uint32_t* rec = cv.take<uint32_t>((size_t)n * (split ? 2 : 2 + nw));
   // second sorted array: weight words (outer-product spread) or, for the channel-row
   // spread, each point's position in the row-grouped weight blocks sb.wts1
   uint32_t* wts = split ? cv.take<uint32_t>((size_t)n * (kind == Spread2::kRows ? 1 : wv)) : nullptr;
   Sort2Bufs sb;
-  if (split) sort2_carve(cv, n, g.nbx, wv, &sb);
+  if (split) sort2_carve(cv, n, gmax.nbx, wv, &sb);
   if (!cv.ok()) return FK_ENOMEM;
-  if (info) info->bin = g.T;
-  FK_HIP(hipEventRecord(ev[0], ctx->stream));
-  FK_HIP(hipMemsetAsync(grid, 0, sizeof(double) * C * nf * nf, ctx->stream));
-  if (split) {
-    // records for the MFMA spreads: two-pass sort, coordinates and weight words
-    fk_status s2 = sort2(ctx->stream, X, dt, n, xstride, Y, nw, nf, fb, W, scale, g.tshift, g.nbx, sb, rec, wts, start,
+  // The binning and the spread for one launch shape, between events ev[0] .. ev[2].
+  auto run = [&](const T1Shape& sh) -> fk_status {
+    const BinGeom g = bin_geom(nf, C, n, kind, sh.mb);
+    if (info) info->bin = g.T;
+    FK_HIP(hipEventRecord(ev[0], ctx->stream));
+    FK_HIP(hipMemsetAsync(grid, 0, sizeof(double) * C * nf * nf, ctx->stream));
+    if (split) {
+      // records for the MFMA spreads: two-pass sort, coordinates and weight words
+      fk_status s2 = sort2(ctx->stream, X, dt, n, xstride, Y, nw, nf, fb, W, scale, g.tshift, g.nbx, sh, sb, rec, wts,
+                           start, ctx->flags);
+      if (s2 != FK_OK) return s2;
+    } else {
+      hipLaunchKernelGGL(k_bin_count, dim3(g.nblk), dim3(256), sizeof(uint32_t) * g.nb, ctx->stream, X, dt, n,
+                         xstride, nf, fb, scale, g.tshift, g.nbx, cnt, g.nblk, g.chunk, ctx->flags);
+      FK_HIP(hipGetLastError());
+      hipLaunchKernelGGL(k_scan_cols, dim3((g.nb + 255) / 256), dim3(256), 0, ctx->stream, cnt, g.nb, g.nblk,
+                         totals);
+      hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, ctx->stream, totals, g.nb, start);
+      hipLaunchKernelGGL(k_bin_scatter, dim3(g.nblk), dim3(1024), sizeof(unsigned long long) * g.nb, ctx->stream, X,
+                         dt, n, xstride, Y, nw, nf, fb, scale, g.tshift, g.nbx, cnt, start, g.chunk, rec,
                          ctx->flags);
-    if (s2 != FK_OK) return s2;
-  } else {
-    hipLaunchKernelGGL(k_bin_count, dim3(g.nblk), dim3(256), sizeof(uint32_t) * g.nb, ctx->stream, X, dt, n,
-                       xstride, nf, fb, scale, g.tshift, g.nbx, cnt, g.nblk, g.chunk, ctx->flags);
+    }
     FK_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_scan_cols, dim3((g.nb + 255) / 256), dim3(256), 0, ctx->stream, cnt, g.nb, g.nblk,
-                       totals);
-    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, ctx->stream, totals, g.nb, start);
-    hipLaunchKernelGGL(k_bin_scatter, dim3(g.nblk), dim3(1024), sizeof(unsigned long long) * g.nb, ctx->stream, X,
-                       dt, n, xstride, Y, nw, nf, fb, scale, g.tshift, g.nbx, cnt, start, g.chunk, rec,
-                       ctx->flags);
-  }
-  FK_HIP(hipGetLastError());
-  FK_HIP(hipEventRecord(ev[1], ctx->stream));
-  int64_t per_bin = (n + g.nb - 1) / g.nb;
-  if (kind == Spread2::kRows) {
-    fk_status s2 = launch_spread_mfma(ctx->stream, W, g.T, rec, wts, sb.wts1, nw, start, g.nbx, g.nb, nf, fb,
-                                      plan.beta, n, grid);
+    FK_HIP(hipEventRecord(ev[1], ctx->stream));
+    int64_t per_bin = (n + g.nb - 1) / g.nb;
+    if (kind == Spread2::kRows) {
+      fk_status s2 = launch_spread_mfma(ctx->stream, W, g.T, rec, wts, sb.wts1, nw, start, g.nbx, g.nb, nf, fb,
+                                        plan.beta, n, sh.spread_pts, grid);
+      if (s2 != FK_OK) return s2;
+      if (info) info->bin = -g.T;   // negative: MFMA spread over T x T bins
+    } else if (kind == Spread2::kOuter) {
+      fk_status s2 = launch_spread_op(ctx->stream, W, rec, wts, nw, start, g.nbx, g.nb, nf, fb, plan.beta, n,
+                                      sh.spread_pts, grid);
+      if (s2 != FK_OK) return s2;
+      if (info) info->bin = -g.T;
+    } else {
+      const int H = (W + 1) / 2;
+      const int S = g.T + 2 * H;
+      size_t lds = sizeof(double) * S * S * C;
+      if (lds > 160 * 1024) return FK_EINVAL;
+      int slices = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (per_bin + 8191) / 8192));
+      int blocks = g.nb * slices;
+      FK_W_SWITCH(W, launch_spread_2d<WW>(ctx, blocks, lds, rec, nw, start, g.nbx, g.T, nf, fb, es, slices, grid));
+    }
+    FK_HIP(hipGetLastError());
+    FK_HIP(hipEventRecord(ev[2], ctx->stream));
+    return FK_OK;
+  };
+  T1Shape shape;
+  if (split) {
+    fk_status s2 = tune_t1(ctx, d, nf, W, nw, n, kind == Spread2::kRows, run, &shape);
     if (s2 != FK_OK) return s2;
-    if (info) info->bin = -g.T;   // negative: MFMA spread over T x T bins
-  } else if (kind == Spread2::kOuter) {
-    fk_status s2 = launch_spread_op(ctx->stream, W, rec, wts, nw, start, g.nbx, g.nb, nf, fb, plan.beta, n, grid);
-    if (s2 != FK_OK) return s2;
-    if (info) info->bin = -g.T;
-  } else {
-    const int H = (W + 1) / 2;
-    const int S = g.T + 2 * H;
-    size_t lds = sizeof(double) * S * S * C;
-    if (lds > 160 * 1024) return FK_EINVAL;
-    int slices = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (per_bin + 8191) / 8192));
-    int blocks = g.nb * slices;
-    FK_W_SWITCH(W, launch_spread_2d<WW>(ctx, blocks, lds, rec, nw, start, g.nbx, g.T, nf, fb, es, slices, grid));
   }
-  FK_HIP(hipGetLastError());
-  FK_HIP(hipEventRecord(ev[2], ctx->stream));
+  st = run(shape);
+  if (st != FK_OK) return st;
   // rows: lines along dim 2 (contiguous), C*nf lines -> rowfft[c][i1][q2]
   hipLaunchKernelGGL(k_fft_line, dim3(C * nf), dim3(256), 0, ctx->stream, grid, 0, (int64_t)1, (int64_t)nf,
                      (int64_t)0, 1, nf, logn, phihat, K, 1.0, rowfft, (int64_t)1, (int64_t)L, (int64_t)0);

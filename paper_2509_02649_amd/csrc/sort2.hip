@@ -563,11 +563,13 @@ struct Sort2Geom {
   int64_t chunk1;
 };
 
-Sort2Geom sort2_geom(int64_t n, int nbx) {
+// First pass: up to blk workgroups of at least 65536 points each; second pass: slices of about
+// slice_pts points per bin row (at most 256).
+Sort2Geom sort2_geom(int64_t n, int nbx, int blk, int64_t slice_pts) {
   Sort2Geom g;
-  g.nblk1 = (int)std::min<int64_t>(512, std::max<int64_t>(1, (n + 65535) / 65536));
+  g.nblk1 = (int)std::min<int64_t>(blk, std::max<int64_t>(1, (n + 65535) / 65536));
   g.chunk1 = (n + g.nblk1 - 1) / g.nblk1;
-  g.slices = (int)std::min<int64_t>(256, std::max<int64_t>(1, (n / nbx + 65535) / 65536));
+  g.slices = (int)std::min<int64_t>(256, std::max<int64_t>(1, (n / nbx + slice_pts - 1) / slice_pts));
   return g;
 }
 
@@ -618,7 +620,7 @@ int sort2_words(int nw) {
 }
 
 void sort2_carve(Carve& cv, int64_t n, int nbx, int wv, Sort2Bufs* b) {
-  Sort2Geom g = sort2_geom(n, nbx);
+  Sort2Geom g = sort2_geom(n, nbx, kSortBlkMax, kSortSliceMin);
   b->cnt1 = cv.take<uint32_t>((size_t)g.nblk1 * nbx);
   b->off1 = cv.take<uint32_t>((size_t)g.nblk1 * nbx);
   b->start1 = cv.take<uint64_t>((size_t)nbx + 1);
@@ -629,11 +631,12 @@ void sort2_carve(Carve& cv, int64_t n, int nbx, int wv, Sort2Bufs* b) {
 }
 
 fk_status sort2(hipStream_t st, const void* X, fk_dtype dt, int64_t n, int64_t xstride, const void* Y, int nw,
-                int nf, int fb, int W, double scale, int tshift, int nbx, const Sort2Bufs& b, uint32_t* crd,
-                uint32_t* wts, uint64_t* start, int* flags) {
+                int nf, int fb, int W, double scale, int tshift, int nbx, const T1Shape& shape, const Sort2Bufs& b,
+                uint32_t* crd, uint32_t* wts, uint64_t* start, int* flags) {
   if (!sort2_ok(nbx) || nw > 16 || (nf & (nf - 1)) != 0 || (nbx << tshift) != nf) return FK_EINVAL;
   if (n > (int64_t)0xffffffff) return FK_EINVAL;   // positions are 32-bit
-  const Sort2Geom g = sort2_geom(n, nbx);
+  if (shape.sort_blk < 1 || shape.sort_blk > kSortBlkMax || shape.sort_slice < kSortSliceMin) return FK_EINVAL;
+  const Sort2Geom g = sort2_geom(n, nbx, shape.sort_blk, shape.sort_slice);
   const uint32_t nf_fix = (uint32_t)nf << fb;
   const uint32_t one = 1u << fb;
   const uint32_t wbias = (one - 1u) + 8u * one - ((uint32_t)W << (fb - 1));

@@ -277,10 +277,10 @@ static void launch_w(hipStream_t st, int blocks, size_t lds, const uint2* c2, co
 
 fk_status launch_spread_mfma(hipStream_t st, int W, int MB, const uint32_t* crd, const uint32_t* pos,
                              const uint32_t* wrow, int nw, const uint64_t* start, int nbx, int nb, int nf, int fb,
-                             double beta, int64_t n, double* grid) {
-  if (!spread_mfma_ok(nw, W) || (MB != 2 && MB != 4)) return FK_EINVAL;
+                             double beta, int64_t n, int spread_pts, double* grid) {
+  if (!spread_mfma_ok(nw, W) || (MB != 2 && MB != 4) || spread_pts < 256) return FK_EINVAL;
   const int64_t per_bin = (n + nb - 1) / nb;
-  const int slices = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (per_bin + 16383) / 16384));
+  const int slices = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (per_bin + spread_pts - 1) / spread_pts));
   const int blocks = nb * slices;
   const size_t lds = sizeof(double) * (((MB + W - 1) * (MB + W - 1) * (nw + 1) + 1) & ~1) +
                      sizeof(float) * SWAVE * 64 * PS;

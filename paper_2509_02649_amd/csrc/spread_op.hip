@@ -247,11 +247,11 @@ bool spread_op_ok(int nw, int W) { return nw >= 0 && nw <= 7 && W >= 4 && W <= 8
 
 fk_status launch_spread_op(hipStream_t st, int W, const uint32_t* crd, const uint32_t* wts, int nw,
                            const uint64_t* start, int nbx, int nb, int nf, int fb, double beta, int64_t n,
-                           double* grid) {
-  if (!spread_op_ok(nw, W) || nbx * OMB != nf) return FK_EINVAL;
+                           int spread_pts, double* grid) {
+  if (!spread_op_ok(nw, W) || nbx * OMB != nf || spread_pts < 256) return FK_EINVAL;
   const int wv = sort2_words(nw);
   const int64_t per_bin = (n + nb - 1) / nb;
-  const int slices = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (per_bin + 16383) / 16384));
+  const int slices = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (per_bin + spread_pts - 1) / spread_pts));
   const int blocks = nb * slices;
   const uint2* c2 = reinterpret_cast<const uint2*>(crd);
   const float bt = (float)beta;

@@ -86,3 +86,31 @@ def test_workspace_queries_and_host_validation(lib):
     # entry points reject a null context before touching the device
     assert L.fk_gram(None, 1, 10, 0, C.c_void_p(1), 0, None, 4, C.c_void_p(1), None, C.c_void_p(1), 1 << 20,
                      None) == 1
+
+
+def test_autotune_table_file_roundtrip(tmp_path):
+    # host-only: the table file format of the launch-shape autotuner (no device is touched)
+    from paper_2509_02649_amd import _lib
+    L = _lib.load(LIB)
+    path = tmp_path / "tune.txt"
+    path.write_text(
+        "# measured on gfx950\n"
+        "gfx950 t1 d=2 nf=512 w=7 nw=16 n=2^30 = mb=2 spread_pts=16384 sort_blk=512 sort_slice=65536 ms=75.3\n"
+        "gfx950 dense Np=4288 nlam=64 ntgt=16 = pair=1 trsm_wg=256   # trailing comment\n"
+        "gfx950 broken = mb=two\n"
+        "no separator here\n"
+        "gfx950 empty = \n")
+    assert L.fk_autotune_clear() == 0
+    assert L.fk_autotune_load(str(path).encode()) == 0
+    n = C.c_size_t()
+    assert L.fk_autotune_table(None, 0, C.byref(n)) == 0
+    buf = C.create_string_buffer(n.value + 1)
+    assert L.fk_autotune_table(buf, 2, C.byref(n)) == 1                     # too small
+    assert L.fk_autotune_table(buf, n.value + 1, C.byref(n)) == 0
+    lines = buf.value.decode().splitlines()
+    assert lines == ["gfx950 dense Np=4288 nlam=64 ntgt=16 = pair=1 trsm_wg=256",
+                     "gfx950 t1 d=2 nf=512 w=7 nw=16 n=2^30 = mb=2 spread_pts=16384 sort_blk=512 sort_slice=65536 "
+                     "ms=75.3"]
+    assert L.fk_autotune_load(str(tmp_path / "missing.txt").encode()) == 1
+    assert L.fk_autotune_clear() == 0
+    assert L.fk_autotune_table(None, 0, C.byref(n)) == 0 and n.value == 0

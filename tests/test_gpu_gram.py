@@ -42,6 +42,19 @@ def test_gram_1d_small_config_fp64(fk):
     assert eT <= TOL and eb <= TOL
 
 
+@pytest.mark.parametrize("m,ntgt", [(64, 32), (64, 19), (40, 32)])
+def test_gram_1d_many_channels(fk, m, ntgt):
+    # more channels than one workgroup's LDS holds as whole FP64 grids (C x nf x 8 B > 160 KB at
+    # nf = 1024): the channels are spread in groups, the ones channel with the first
+    rng = np.random.default_rng(m + ntgt)
+    n = 30_001
+    X = rng.uniform(-np.pi, np.pi, size=(1, n)).astype(np.float32)
+    Y = rng.standard_normal((ntgt, n)).astype(np.float32)
+    eT, eb, info = _errors(fk, X, Y, m)
+    print(f"1-D m={m} T={ntgt}: eps_T={eT:.2e} eps_b={eb:.2e} nf={info['nf']}")
+    assert eT <= TOL and eb <= TOL
+
+
 @pytest.mark.parametrize("n", [1, 7, 1000, 65_537])
 def test_gram_2d_sizes_and_ragged(fk, n):
     w = synth.workload_2d(n=n, seed=11 + n)

@@ -53,47 +53,150 @@ def test_predict_type1_type2_identity(fk):
     assert abs(lhs - rhs) / rhs < 1e-5
 
 
+def _grad_problem(seed, m=8, n=100_000, nv=50_000, T=3):
+    X = synth.uniform_points(seed, 2, n)
+    Y = synth.batched_targets(X, seed, ntgt=T)
+    Xv = synth.uniform_points(seed + 1, 2, nv)
+    Yv = synth.batched_targets(Xv, seed + 1, ntgt=T)
+    X64, Y64, Xv64, Yv64 = (a.astype(np.float64) for a in (X, Y, Xv, Yv))
+    o = dict(M=oracle.gram_generator(X64, m), b=oracle.rhs(X64, Y64, m), Mv=oracle.gram_generator(Xv64, m),
+             bv=oracle.rhs(Xv64, Yv64, m), Xv64=Xv64, Yv64=Yv64)
+    dev = [torch.from_numpy(a).cuda() for a in (X, Y, Xv, Yv)]
+    return dev, o
+
+
 def test_heldout_mse_and_gradients(fk):
-    m, n, nv, T = 8, 100_000, 50_000, 3
-    X = synth.uniform_points(21, 2, n)
-    Y = synth.batched_targets(X, 21, ntgt=T)
-    Xv = synth.uniform_points(22, 2, nv)
-    Yv = synth.batched_targets(Xv, 22, ntgt=T)
+    m, T = 8, 3
+    (X, Y, Xv, Yv), o = _grad_problem(21, m=m, T=T)
     lams = [1e-4, 1e-2]
     p = oracle.sobolev_weights(m, 2, 2.0)
+    N = p.size
     loglam = torch.tensor(np.log(lams), dtype=torch.float64, device="cuda", requires_grad=True)
     pt = torch.tensor(p, dtype=torch.float64, device="cuda", requires_grad=True)
-    mse = fk.KernelRidgeGridLoss.apply(loglam, pt, torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(),
-                                       torch.from_numpy(Xv).cuda(), torch.from_numpy(Yv).cuda(), m)
-    w = torch.tensor(np.random.default_rng(0).uniform(0.5, 1.5, size=(len(lams), T)), device="cuda")
-    (mse * w).sum().backward()
+    mse, theta = fk.KernelRidgeGridLoss.apply(loglam, pt, X, Y, Xv, Yv, m)
+    rng = np.random.default_rng(0)
+    w = torch.tensor(rng.uniform(0.5, 1.5, size=(len(lams), T)), device="cuda")
+    # a second use of theta: E = sum Re(conj(c) theta), so dE/dconj(theta) = c / 2
+    c = rng.standard_normal((len(lams), T, N)) + 1j * rng.standard_normal((len(lams), T, N))
+    ct = torch.from_numpy(c).cuda()
+    ((mse * w).sum() + (torch.conj(ct) * theta).real.sum()).backward()
     mse = mse.detach().cpu().numpy()
-    # oracle
-    X64, Y64, Xv64, Yv64 = (a.astype(np.float64) for a in (X, Y, Xv, Yv))
-    M = oracle.gram_generator(X64, m)
-    b = oracle.rhs(X64, Y64, m)
-    Mv = oracle.gram_generator(Xv64, m)
-    bv = oracle.rhs(Xv64, Yv64, m)
     wn = w.cpu().numpy()
     g_ll = np.zeros(len(lams))
     g_p = np.zeros_like(p)
     for i, lam in enumerate(lams):
-        A = oracle.system_matrix(M, m, lam, p)
-        th = oracle.solve_system(A, b)
-        mo = oracle.heldout_mse(th, Xv64, Yv64, m)
+        A = oracle.system_matrix(o["M"], m, lam, p)
+        th = oracle.solve_system(A, o["b"])
+        assert _rel_herm(theta[i].detach().cpu().numpy(), th) <= 1e-4
+        mo = oracle.heldout_mse(th, o["Xv64"], o["Yv64"], m)
         # the loss inherits the type-1 error: |d mse| <= eps_T ||theta||_1^2 + 2 eps_b mean|Yv| ||theta||_1
         l1 = np.abs(th).sum(axis=1)
-        bound = 1e-6 * (l1 ** 2 + 2 * np.abs(Yv64).mean(axis=1) * l1)
+        bound = 1e-6 * (l1 ** 2 + 2 * np.abs(o["Yv64"]).mean(axis=1) * l1)
         assert (np.abs(mse[i] - mo) <= bound).all()
         for t in range(T):
-            dll, dp, _ = oracle.mse_gradients(A, th[t], p, lam, Mv, bv[t], m)
-            g_ll[i] += wn[i, t] * dll
-            g_p += wn[i, t] * dp
+            _, _, g = oracle.mse_gradients(A, th[t], p, lam, o["Mv"], o["bv"][t], m)
+            dll, dp = oracle.theta_path_gradients(A, th[t], p, lam, wn[i, t] * g + 0.5 * c[i, t])
+            g_ll[i] += dll
+            g_p += dp
     gl = loglam.grad.cpu().numpy()
     gp = pt.grad.cpu().numpy()
     print("dlog lambda gpu", gl, "oracle", g_ll)
     assert np.abs(gl - g_ll).max() <= 1e-4 * np.abs(g_ll).max()
     assert np.abs(gp - g_p).max() <= 1e-4 * np.abs(g_p).max()
+
+
+def _rel_herm(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def test_theta_gradient_of_the_heldout_loss(fk):
+    # fit_backward(want_theta): dL/dconj(theta) = grad_mse * (Sigma_v theta - b_v), the Wirtinger
+    # convention of the header (PyTorch's .grad would be twice this)
+    m, T = 6, 2
+    (X, Y, Xv, Yv), o = _grad_problem(41, m=m, T=T)
+    lams = [3e-3]
+    p = oracle.sobolev_weights(m, 2, 1.0)
+    ctx = fk.Context(0)
+    theta = fk.fit(X, Y, m, lams, penalty="sobolev", s=1.0, ctx=ctx)
+    vctx = fk.Context(0)
+    Mv, bv = fk.gram(Xv, Yv, m, ctx=vctx)
+    mse = fk.heldout_mse(Mv, bv, fk.mean_square(Yv, ctx=vctx), m, len(lams), ctx)
+    gm = torch.tensor([[0.7, -1.3]], dtype=torch.float64, device="cuda")
+    _, _, gt = fk.fit_backward(gm, m, 2, ctx, want_theta=True)
+    A = oracle.system_matrix(o["M"], m, lams[0], p)
+    th = oracle.solve_system(A, o["b"])
+    for t in range(T):
+        _, _, g = oracle.mse_gradients(A, th[t], p, lams[0], o["Mv"], o["bv"][t], m)
+        want = gm[0, t].item() * g
+        got = gt[0, t].cpu().numpy()
+        assert np.linalg.norm(got - want) <= 1e-4 * np.linalg.norm(want)
+    del mse, theta
+
+
+def test_two_applies_alive_in_one_graph(fk):
+    # two folds with different data summed into one loss: each apply keeps its own factors
+    m, T = 6, 2
+    lams = [1e-3, 1e-1]
+    p = oracle.sobolev_weights(m, 2, 2.0)
+    loglam = torch.tensor(np.log(lams), dtype=torch.float64, device="cuda", requires_grad=True)
+    pt = torch.tensor(p, dtype=torch.float64, device="cuda", requires_grad=True)
+    total = 0
+    folds = []
+    for seed in (51, 61):
+        (X, Y, Xv, Yv), o = _grad_problem(seed, m=m, n=60_000, nv=30_000, T=T)
+        mse, _ = fk.KernelRidgeGridLoss.apply(loglam, pt, X, Y, Xv, Yv, m)
+        total = total + mse.sum()
+        folds.append(o)
+    total.backward()
+    g_ll = np.zeros(len(lams))
+    g_p = np.zeros_like(p)
+    for o in folds:
+        for i, lam in enumerate(lams):
+            A = oracle.system_matrix(o["M"], m, lam, p)
+            th = oracle.solve_system(A, o["b"])
+            for t in range(T):
+                dll, dp, _ = oracle.mse_gradients(A, th[t], p, lam, o["Mv"], o["bv"][t], m)
+                g_ll[i] += dll
+                g_p += dp
+    gl = loglam.grad.cpu().numpy()
+    assert np.abs(gl - g_ll).max() <= 1e-4 * np.abs(g_ll).max()
+    assert np.abs(pt.grad.cpu().numpy() - g_p).max() <= 1e-4 * np.abs(g_p).max()
+
+
+def test_kept_factors_are_guarded(fk):
+    # a call that writes the workspace holding the factors makes the gradient calls refuse (FK_EINVAL)
+    m, T = 6, 1
+    (X, Y, Xv, Yv), _ = _grad_problem(71, m=m, n=20_000, nv=10_000, T=T)
+    ctx, vctx = fk.Context(0), fk.Context(0)
+    Mv, bv = fk.gram(Xv, Yv, m, ctx=vctx)
+    yv2 = fk.mean_square(Yv, ctx=vctx)
+    gm = torch.ones((1, T), dtype=torch.float64, device="cuda")
+    fk.fit(X, Y, m, [1e-3], ctx=ctx)
+    fk.gram(X, Y, m, ctx=ctx)                      # overwrites the factors (same workspace)
+    with pytest.raises(fk.FkError) as e:
+        fk.heldout_mse(Mv, bv, yv2, m, 1, ctx)
+    assert e.value.code == 1
+    fk.fit(X, Y, m, [1e-3], ctx=ctx)
+    fk.heldout_mse(Mv, bv, yv2, m, 1, ctx)
+    fk.predict(torch.zeros((1, (2 * m + 1) ** 2), dtype=torch.complex128, device="cuda"), Xv, m, ctx=ctx)
+    with pytest.raises(fk.FkError) as e:
+        fk.fit_backward(gm, m, 2, ctx)
+    assert e.value.code == 1
+    # backward before any held-out loss, and a shape mismatch, are refused too
+    fk.fit(X, Y, m, [1e-3], ctx=ctx)
+    with pytest.raises(fk.FkError) as e:
+        fk.fit_backward(gm, m, 2, ctx)
+    assert e.value.code == 1
+    with pytest.raises(fk.FkError) as e:
+        fk.heldout_mse(Mv, bv, yv2, m, 2, ctx)
+    assert e.value.code == 1
+    fk.heldout_mse(Mv, bv, yv2, m, 1, ctx)
+    gl, _, _ = fk.fit_backward(gm, m, 2, ctx)
+    assert torch.isfinite(gl).all()
+    # a NaN loss weight reaches the adjoint solve: FK_ENAN, not a stalled refinement
+    with pytest.raises(fk.FkError) as e:
+        fk.fit_backward(torch.full((1, T), float("nan"), dtype=torch.float64, device="cuda"), m, 2, ctx)
+    assert e.value.code == 3
 
 
 @pytest.mark.parametrize("T,n,dt", [(16, 1_000_003, np.float32), (3, 1, np.float64), (1, 70_000, np.float64)])

@@ -362,3 +362,51 @@ def test_pde_box_system_matches_direct_minimization():
     rhs_ = np.concatenate([Y / np.sqrt(n), np.zeros(Q.shape[0])])
     th_ls = np.linalg.lstsq(stacked, rhs_, rcond=None)[0]
     np.testing.assert_allclose(theta[0], th_ls, atol=1e-9 * np.abs(th_ls).max())
+
+
+def test_theta_path_gradients_against_central_differences():
+    # a loss of theta alone, E(theta) = Re(c^* theta) + |theta_j|^2, through theta(lambda, p) = A^-1 b
+    m, Xv, Yv, M, b, Mv, bv, p = _setup(24)
+    rng = np.random.default_rng(25)
+    N = p.size
+    c = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    j = 7
+    E = lambda th: np.real(np.conj(c) @ th) + abs(th[j]) ** 2
+    lam = 2e-2
+    A = oracle.system_matrix(M, m, lam, p)
+    th = oracle.solve_system(A, b)
+    G = 0.5 * c
+    G[j] += th[j]                        # Wirtinger gradient of E with respect to conj(theta)
+    dll, dp = oracle.theta_path_gradients(A, th, p, lam, G)
+    th_at = lambda lm, pp: oracle.solve_system(oracle.system_matrix(M, m, lm, pp), b)
+    h = 1e-4
+    fd = (E(th_at(lam * np.exp(h), p)) - E(th_at(lam * np.exp(-h), p))) / (2 * h)
+    assert abs(fd - dll) <= 1e-7 * max(1.0, abs(dll))
+    for k in [0, 11, 24, 40]:
+        e = np.zeros_like(p)
+        e[k] = 1e-5 * p[k]
+        fdp = (E(th_at(lam, p + e)) - E(th_at(lam, p - e))) / (2e-5 * p[k])
+        assert abs(fdp - dp[k]) <= 1e-6 * np.abs(dp).max()
+    # the mse gradients are the special case G = g (held-out Wirtinger gradient)
+    dll2, dp2, g = oracle.mse_gradients(A, th, p, lam, Mv, bv, m)
+    a, bb = oracle.theta_path_gradients(A, th, p, lam, g)
+    assert a == pytest.approx(dll2, rel=1e-12) and np.allclose(bb, dp2, rtol=1e-12, atol=0)
+
+
+def test_mse_theta_gradient_along_hermitian_directions():
+    # the library reports dL/dconj(theta) = g; along Hermitian-symmetric directions (the only ones a
+    # real fit moves in) the directional derivative of the held-out loss is 2 Re(g^* dtheta)
+    m, Xv, Yv, M, b, Mv, bv, p = _setup(26)
+    A = oracle.system_matrix(M, m, 1e-2, p)
+    th = oracle.solve_system(A, b)
+    _, _, g = oracle.mse_gradients(A, th, p, 1e-2, Mv, bv, m)
+    rng = np.random.default_rng(27)
+    yv2 = np.mean(Yv ** 2)
+    for _ in range(3):
+        dth = rng.standard_normal(th.size) + 1j * rng.standard_normal(th.size)
+        dth = 0.5 * (dth + np.conj(dth[::-1]))
+        eps = 1e-5
+        Lp = oracle.heldout_mse(th + eps * dth, Xv, Yv[None, :], m)[0]
+        Lm = oracle.heldout_mse(th - eps * dth, Xv, Yv[None, :], m)[0]
+        assert abs((Lp - Lm) / (2 * eps) - 2 * np.real(np.conj(g) @ dth)) < 1e-7
+    del yv2
