@@ -273,9 +273,12 @@ fk_status fk_mean_square(fk_ctx* ctx, int ntgt, int64_t n, fk_dtype dtype, const
  * With g = Sigma_v theta - bv (= d mse / d conj(theta)), G = grad_mse * g + grad_theta_in and the
  * adjoint u = A_l^-1 G (solved with the kept factors and FP64 refinement):
  *   grad_loglam[l] = sum_t -2 lambda_l Re(u^* P theta)                  (device, nlam)
- *   grad_p[k]      = sum_{l,t} -2 lambda_l Re(conj(u_k) theta_k)         (device, N; only for diagonal
- *                    penalties: it is dLoss/dp_k for the weights p_k = p_{-k} taken as independent
- *                    entries, else left untouched; may be NULL)
+ *   grad_p[k]      = sum_{l,t} -lambda_l Re(conj(u_k) theta_k + conj(u_-k) theta_-k)
+ *                    (device, N; only for diagonal penalties, else left untouched; may be NULL).
+ *                    The weights are tied (p_{-k} = p_k is required), so this is the gradient
+ *                    projected onto symmetric weights: grad_p[k] = grad_p[-k] = half of dLoss/dq for
+ *                    the common value q = p_k = p_{-k}.  For a Hermitian-symmetric G it equals
+ *                    -2 lambda_l Re(conj(u_k) theta_k) summed over (l, t).
  *   grad_theta[l][t] = grad_mse[l][t] * g   (device complex128, may be NULL: the Wirtinger gradient
  *                    of the mse term with respect to conj(theta), theta held fixed)
  * Requires the fk_heldout_mse call on the same workspace after its fk_solve / fk_fit (FK_EINVAL

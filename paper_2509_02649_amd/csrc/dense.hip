@@ -226,7 +226,9 @@ __global__ void k_real_weights(const double* __restrict__ p, int N, int L, doubl
   preal[r] = p[k];
 }
 
-// Real right-hand sides Bre[t][r] (Np rows, zero padded) from complex b[t][k].
+// Real right-hand sides Bre[t][r] (Np rows, zero padded) from complex b[t][k].  The real form reads
+// the mode k of each pair (k, -k) only (b_-k = conj b_k for real data); a NaN or Inf in either entry
+// of the pair is carried into the row, so that the residual norms report it.
 __global__ void k_rhs_real(const double* __restrict__ b, int N, int L, int Np, int ntgt,
                            double* __restrict__ Bre) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -239,6 +241,8 @@ __global__ void k_rhs_real(const double* __restrict__ b, int N, int L, int Np, i
     const double* bt = b + 2 * (size_t)t * N;
     const double s2 = 1.41421356237309504880;
     v = ty == 0 ? bt[2 * k] : (ty == 1 ? s2 * bt[2 * k] : -s2 * bt[2 * k + 1]);
+    const double pair = bt[2 * k] + bt[2 * k + 1] + bt[2 * nk] + bt[2 * nk + 1];
+    if (!isfinite(pair)) v = pair - pair;   // NaN
   }
   Bre[(size_t)t * Np + r] = v;
 }

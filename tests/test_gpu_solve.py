@@ -185,11 +185,14 @@ def test_fit_pde_box_2d_operator_off_centre_box(fk):
     e = _rel(tg[0].cpu().numpy(), th)
     print(f"PDE box 2-D: kappa={kappa:.2e} rel={e:.2e}")
     assert kappa <= 1e6 and e <= TOL
-    # the heat operator through the general kind equals the heat kind
+    # the heat operator through the general kind equals the heat kind; both solve the same M and b
+    # (two type-1 stages differ in the order of their atomic additions, so not bit for bit)
     w = synth.workload_piml(n=100_000)
     Xh, Yh, mh = w["X"], w["Y"], w["m"]
-    a = fk.fit(torch.from_numpy(Xh).cuda(), torch.from_numpy(Yh).cuda(), mh, w["lam"], penalty="heat_box", mu=1e-3)
-    g, _ = _pde_fit(fk, Xh, Yh, mh, w["lam"], 1e-3, [[1, 0], [0, 2]], [1.0, -1.0], (-np.pi / 2,) * 2, (np.pi / 2,) * 2)
+    Mh, bh = fk.gram(torch.from_numpy(Xh).cuda(), torch.from_numpy(Yh).cuda(), mh)
+    a = fk.solve(Mh, bh, mh, [w["lam"]], penalty="heat_box", mu=1e-3)
+    g = fk.solve(Mh, bh, mh, [w["lam"]], penalty="pde_box", s=1.0, mu=1e-3, alpha=[[1, 0], [0, 2]],
+                 coef=[1.0, -1.0], box_lo=(-np.pi / 2,) * 2, box_hi=(np.pi / 2,) * 2)
     assert _rel(g.cpu().numpy(), a.cpu().numpy()) < 1e-12
 
 
@@ -218,9 +221,10 @@ def test_solve_reports_non_finite_right_hand_side(fk):
     X = rng.uniform(-np.pi, np.pi, size=(2, 5000))
     M = oracle.gram_generator(X, 4)
     b = oracle.rhs(X, np.sin(X[:1]), 4)
-    for v in [np.nan, np.inf]:
+    # index 7 is the -k member of its pair (the real form reads the +k member), 40 is k = 0
+    for v, i in [(np.nan, 7), (np.inf, 7), (np.nan, 40), (-np.inf, 80 - 7)]:
         bb = b.copy()
-        bb[0, 7] = v
+        bb[0, i] = v
         with pytest.raises(fk.FkError) as e:
             fk.solve(_cplx(M), _cplx(bb), 4, [1e-3, 1e-2])
         assert e.value.code == 3
