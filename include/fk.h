@@ -238,6 +238,20 @@ fk_status fk_predict_workspace_size(fk_ctx* ctx, int d, int m, int ntheta, size_
 fk_status fk_predict(fk_ctx* ctx, int d, int m, int ntheta, const double* theta, int64_t nq,
                      fk_dtype dtype, const void* Xq, float* out, void* ws, size_t ws_bytes);
 
+/* fk_predict_noalloc: fk_predict without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, result and errors as fk_predict, computed by the same kernels.  It
+ * calls no hipMalloc / hipFree: its intermediates (the deconvolution table and the oversampled
+ * grids) live in one library-owned device array of 64 MiB per device, resolved by fk_create and held
+ * until the process ends.  Shapes whose fk_predict_workspace_size exceeds
+ * fk_predict_noalloc_max_bytes() return FK_ENOMEM (nothing enqueued); d = 2 with m = 32 fits up to
+ * 63 coefficient sets.  Every call on a device shares that array and leaves its contents there:
+ * calls that overlap in time on one device (several streams, threads or contexts) race and must be
+ * serialised by the caller. */
+fk_status fk_predict_noalloc(fk_ctx* ctx, int d, int m, int ntheta, const double* theta, int64_t nq,
+                             fk_dtype dtype, const void* Xq, float* out);
+size_t fk_predict_noalloc_max_bytes(void);
+
 /* ---------------------------------------------------------------- held-out loss and gradients
  * Kept factors.  fk_solve and fk_fit leave, at the start of their workspace, the FP32 factors of
  * every lambda, the FP64 real-form Gram and the solutions; a successful call (FK_OK or

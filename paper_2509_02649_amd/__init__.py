@@ -22,7 +22,7 @@ import torch
 from . import _lib
 from ._lib import FkError, fk_fit_info, fk_penalty, fk_options, FK_F32, FK_F64, PEN
 
-__all__ = ["Context", "gram", "restrict", "solve", "solve_workspace_size", "solve_cg", "toeplitz_apply", "fit", "predict", "heldout_mse", "fit_backward", "additive_gram",
+__all__ = ["Context", "gram", "restrict", "solve", "solve_workspace_size", "solve_cg", "toeplitz_apply", "fit", "predict", "predict_noalloc", "heldout_mse", "fit_backward", "additive_gram",
            "additive_fit", "generate_uniform", "generate_targets", "KernelRidgeGridLoss", "FkError",
            "autotune_table", "autotune_load", "autotune_clear"]
 
@@ -316,6 +316,21 @@ def predict(theta: torch.Tensor, Xq: torch.Tensor, m: int, ctx: Optional[Context
     out = torch.empty((T, nq), dtype=torch.float32, device=Xq.device)
     _lib.check(ctx.lib.fk_predict(ctx.h, d, m, T, _ptr(th), nq, _dtype_code(Xq), _ptr(Xq), _ptr(out), _ptr(ws),
                                   nb.value), "fk_predict")
+    return out
+
+
+def predict_noalloc(theta: torch.Tensor, Xq: torch.Tensor, m: int, ctx: Optional[Context] = None) -> torch.Tensor:
+    """predict() through fk_predict_noalloc: no workspace, the library's fixed device array instead.
+    Calls on one device share that array and must not overlap."""
+    ctx = ctx or default_context(Xq.device.index or 0)
+    ctx.bind_stream()
+    Xq = _dev_tensor(Xq, "Xq")
+    d, nq = Xq.shape
+    th = torch.view_as_real(theta.reshape(-1, _modes(m, d)).contiguous()).contiguous()
+    T = th.shape[0]
+    out = torch.empty((T, nq), dtype=torch.float32, device=Xq.device)
+    _lib.check(ctx.lib.fk_predict_noalloc(ctx.h, d, m, T, _ptr(th), nq, _dtype_code(Xq), _ptr(Xq), _ptr(out)),
+               "fk_predict_noalloc")
     return out
 
 

@@ -83,6 +83,9 @@ EXPORTS = {
     "fk_predict_workspace_size": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_size_t)]),
     "fk_predict": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_int64, C.c_int, C.c_void_p,
                              C.c_void_p, C.c_void_p, C.c_size_t]),
+    "fk_predict_noalloc": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_int64, C.c_int,
+                                     C.c_void_p, C.c_void_p]),
+    "fk_predict_noalloc_max_bytes": (C.c_size_t, []),
     "fk_heldout_mse": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_void_p, C.c_size_t]),
     "fk_fit_backward": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p,

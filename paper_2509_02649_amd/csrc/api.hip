@@ -35,6 +35,12 @@ extern "C" fk_status fk_create(fk_ctx** ctx, int device, void* hip_stream) {
   }
   for (auto& e : c->ev)
     if (hipEventCreate(&e) != hipSuccess) return FK_EHIP;
+  // the allocation-free prediction's device array, resolved once per device
+  fk_status st = scratch_init(device);
+  if (st != FK_OK) {
+    fk_destroy(c);
+    return st;
+  }
   *ctx = c;
   return FK_OK;
 }

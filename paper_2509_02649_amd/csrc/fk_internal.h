@@ -186,11 +186,17 @@ struct fk_ctx {
   hipEvent_t ev[16] = {};
   // cached deconvolution tables keyed by (K, eps bits)
   std::map<std::pair<int, uint64_t>, std::pair<fk::EsPlan, double*>> es_cache;
+  // the same plans without device tables (for the allocation-free entry point)
+  std::map<std::pair<int, uint64_t>, fk::EsPlan> es_host_cache;
 };
 
 namespace fk {
 // Returns the ES plan and a device copy of its phihat table (owned by ctx).
 fk_status get_es_plan(fk_ctx* ctx, int K, EsPlan* plan, const double** d_phihat);
+// The same plan, host tables only (no device memory is allocated).
+fk_status get_es_plan_host(fk_ctx* ctx, int K, EsPlan* plan);
+// Resolves this device's copy of the allocation-free prediction's device array (device current).
+fk_status scratch_init(int device);
 fk_status finish(fk_ctx* ctx, fk_status st, fk_fit_info* info);
 fk_status read_flags(fk_ctx* ctx);
 

@@ -11,6 +11,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 namespace fk {
 
@@ -242,18 +243,13 @@ extern "C" fk_status fk_predict_workspace_size(fk_ctx* ctx, int d, int m, int nt
     default: return FK_EINVAL;                       \
   }
 
-extern "C" fk_status fk_predict(fk_ctx* ctx, int d, int m, int T, const double* theta, int64_t nq, fk_dtype dt,
-                                const void* Xq, float* out, void* ws, size_t ws_bytes) {
-  if (!ctx || !theta || !Xq || !out || !predict_shape_ok(d, m, T) || nq < 1) return FK_EINVAL;
-  if (dt != FK_F32 && dt != FK_F64) return FK_EINVAL;
-  if (!ws || ws_bytes < predict_ws(d, m, T)) return FK_ENOMEM;
-  FK_HIP(hipSetDevice(ctx->device));
-  kept_invalidate(ws, ws_bytes);
-  EsPlan plan;
-  const double* phihat;
-  fk_status st = get_es_plan(ctx, m, &plan, &phihat);
-  if (st != FK_OK) return st;
-  st = reset_flags(ctx);
+namespace fk {
+
+// The type-2 stage on a caller-given workspace and deconvolution table (device, plan.K + 1 doubles).
+static fk_status predict_impl(fk_ctx* ctx, const EsPlan& plan, const double* phihat, int d, int m, int T,
+                              const double* theta, int64_t nq, fk_dtype dt, const void* Xq, float* out, void* ws,
+                              size_t ws_bytes) {
+  fk_status st = reset_flags(ctx);
   if (st != FK_OK) return st;
   const int nf = plan.nf, logn = ilog2i(nf), L = 2 * m + 1;
   Carve cv(ws, ws_bytes);
@@ -294,6 +290,84 @@ extern "C" fk_status fk_predict(fk_ctx* ctx, int d, int m, int T, const double* 
                                           dt, nq, es, out, ctx->flags));
   FK_HIP(hipGetLastError());
   return read_flags(ctx);
+}
+
+static bool predict_args_ok(fk_ctx* ctx, int d, int m, int T, const double* theta, int64_t nq, fk_dtype dt,
+                            const void* Xq, const float* out) {
+  return ctx && theta && Xq && out && predict_shape_ok(d, m, T) && nq >= 1 && (dt == FK_F32 || dt == FK_F64);
+}
+
+// ------------------------------------------------------------------ allocation-free prediction
+// A file-scope device array holds the intermediates of fk_predict_noalloc: the deconvolution table
+// at its start, then the workspace that fk_predict would take from the caller.  Each device has its
+// own copy; host code uses only the address hipGetSymbolAddress returns for the device (the array's
+// name on the host is a stand-in, not a device address).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr size_t kScratchTable = 1024;   // phihat, at most 65 doubles
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch[kMaxDevices] = {};
+
+// Resolves this device's copy of the array; called with the device current (from fk_create, and
+// again by the entry point if that failed).  Returns FK_EHIP if the address cannot be taken.
+fk_status scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return FK_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[device]) return FK_OK;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return FK_EHIP;
+  g_scratch[device] = ptr;
+  return FK_OK;
+}
+
+struct Table65 {
+  double v[65];
+};
+
+__global__ void k_put_table(Table65 t, int count, double* __restrict__ dst) {
+  const int i = threadIdx.x;
+  if (i < count) dst[i] = t.v[i];
+}
+
+}  // namespace fk
+
+extern "C" fk_status fk_predict(fk_ctx* ctx, int d, int m, int T, const double* theta, int64_t nq, fk_dtype dt,
+                                const void* Xq, float* out, void* ws, size_t ws_bytes) {
+  if (!predict_args_ok(ctx, d, m, T, theta, nq, dt, Xq, out)) return FK_EINVAL;
+  if (!ws || ws_bytes < predict_ws(d, m, T)) return FK_ENOMEM;
+  FK_HIP(hipSetDevice(ctx->device));
+  kept_invalidate(ws, ws_bytes);
+  EsPlan plan;
+  const double* phihat;
+  fk_status st = get_es_plan(ctx, m, &plan, &phihat);
+  if (st != FK_OK) return st;
+  return predict_impl(ctx, plan, phihat, d, m, T, theta, nq, dt, Xq, out, ws, ws_bytes);
+}
+
+extern "C" size_t fk_predict_noalloc_max_bytes(void) { return kScratchBytes - kScratchTable; }
+
+extern "C" fk_status fk_predict_noalloc(fk_ctx* ctx, int d, int m, int T, const double* theta, int64_t nq,
+                                        fk_dtype dt, const void* Xq, float* out) {
+  if (!predict_args_ok(ctx, d, m, T, theta, nq, dt, Xq, out)) return FK_EINVAL;
+  if (predict_ws(d, m, T) > kScratchBytes - kScratchTable) return FK_ENOMEM;
+  FK_HIP(hipSetDevice(ctx->device));
+  fk_status st = scratch_init(ctx->device);
+  if (st != FK_OK) return st;
+  unsigned char* base = static_cast<unsigned char*>(g_scratch[ctx->device]);
+  EsPlan plan;
+  st = get_es_plan_host(ctx, m, &plan);
+  if (st != FK_OK) return st;
+  if (plan.phihat.size() != (size_t)m + 1 || m + 1 > 65) return FK_EINVAL;
+  // the deconvolution table goes in by value (a kernel argument), so no host buffer must outlive the call
+  Table65 tab{};
+  for (int i = 0; i <= m; ++i) tab.v[i] = plan.phihat[i];
+  double* phihat = reinterpret_cast<double*>(base);
+  hipLaunchKernelGGL(k_put_table, dim3(1), dim3(128), 0, ctx->stream, tab, m + 1, phihat);
+  FK_HIP(hipGetLastError());
+  return predict_impl(ctx, plan, phihat, d, m, T, theta, nq, dt, Xq, out, base + kScratchTable,
+                      kScratchBytes - kScratchTable);
 }
 
 // ------------------------------------------------------------------ Philox4x32-10 generator

@@ -168,6 +168,22 @@ fk_status get_es_plan(fk_ctx* ctx, int K, EsPlan* plan, const double** d_phihat)
   return FK_OK;
 }
 
+fk_status get_es_plan_host(fk_ctx* ctx, int K, EsPlan* plan) {
+  double eps = ctx->opt.eps > 0 ? ctx->opt.eps : 2e-7;
+  uint64_t bits;
+  std::memcpy(&bits, &eps, 8);
+  auto key = std::make_pair(K, bits);
+  auto dev = ctx->es_cache.find(key);
+  if (dev != ctx->es_cache.end()) {
+    *plan = dev->second.first;
+    return FK_OK;
+  }
+  auto it = ctx->es_host_cache.find(key);
+  if (it == ctx->es_host_cache.end()) it = ctx->es_host_cache.emplace(key, make_es_plan(K, eps)).first;
+  *plan = it->second;
+  return FK_OK;
+}
+
 // ------------------------------------------------------------------ device helpers
 
 struct EsDev {

@@ -13,7 +13,7 @@ LIB = os.path.join(ROOT, "paper_2509_02649_amd", "libfastkernel.so")
 
 def declared():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:fk_status|const char\*)\s+(fk_[a-z0-9_]+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:fk_status|const char\*|size_t)\s+(fk_[a-z0-9_]+)\s*\(", text, re.M)))
 
 
 @pytest.fixture(scope="module")
