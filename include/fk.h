@@ -245,7 +245,7 @@ fk_status fk_predict(fk_ctx* ctx, int d, int m, int ntheta, const double* theta,
  * grids) live in one library-owned device array of 64 MiB per device, resolved by fk_create and held
  * until the process ends.  Shapes whose fk_predict_workspace_size exceeds
  * fk_predict_noalloc_max_bytes() return FK_ENOMEM (nothing enqueued); d = 2 with m = 32 fits up to
- * 63 coefficient sets.  Every call on a device shares that array and leaves its contents there:
+ * 266 coefficient sets.  Every call on a device shares that array and leaves its contents there:
  * calls that overlap in time on one device (several streams, threads or contexts) race and must be
  * serialised by the caller. */
 fk_status fk_predict_noalloc(fk_ctx* ctx, int d, int m, int ntheta, const double* theta, int64_t nq,

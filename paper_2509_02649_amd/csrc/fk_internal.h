@@ -36,7 +36,8 @@ struct EsPlan {
   std::vector<double> phihat;  // size K+1
 };
 
-EsPlan make_es_plan(int K, double eps);
+// nf_fixed > 0 fixes the grid size (any even length), else the smallest power of two >= 2(2K+1).
+EsPlan make_es_plan(int K, double eps, int nf_fixed = 0);
 
 // Workspace carving: bump allocator over the caller's buffer.
 struct Carve {
@@ -192,9 +193,9 @@ struct fk_ctx {
 
 namespace fk {
 // Returns the ES plan and a device copy of its phihat table (owned by ctx).
-fk_status get_es_plan(fk_ctx* ctx, int K, EsPlan* plan, const double** d_phihat);
+fk_status get_es_plan(fk_ctx* ctx, int K, EsPlan* plan, const double** d_phihat, int nf_fixed = 0);
 // The same plan, host tables only (no device memory is allocated).
-fk_status get_es_plan_host(fk_ctx* ctx, int K, EsPlan* plan);
+fk_status get_es_plan_host(fk_ctx* ctx, int K, EsPlan* plan, int nf_fixed = 0);
 // Resolves this device's copy of the allocation-free prediction's device array (device current).
 fk_status scratch_init(int device);
 fk_status finish(fk_ctx* ctx, fk_status st, fk_fit_info* info);

@@ -80,15 +80,18 @@ __global__ void k_d2f_grid(const double* __restrict__ a, float* __restrict__ b, 
   if (i < n) b[i] = (float)a[i];
 }
 
+// ES kernel psi(s) = exp(beta (sqrt(1 - (2s/w)^2) - 1)) with beta pre-multiplied by log2 e, so that
+// the hardware exp2 takes the exponent directly (it lies in [-beta log2 e, 0]: no range handling) and
+// the hardware square root needs no denormal scaling (1 - z^2 below 2^-126 gives psi ~ e^-beta).
 struct EsDev2 {
-  float beta;
+  float beta_log2e;
   float two_over_w;
 };
 
 __device__ __forceinline__ float es_eval2(float s, EsDev2 es) {
-  float z = s * es.two_over_w;
-  float r = fmaxf(1.0f - z * z, 0.0f);
-  return __expf(es.beta * (__fsqrt_rn(r) - 1.0f));
+  const float z = s * es.two_over_w;
+  const float r = fmaxf(fmaf(-z, z, 1.0f), 0.0f);
+  return __builtin_amdgcn_exp2f(fmaf(es.beta_log2e, __builtin_amdgcn_sqrtf(r), -es.beta_log2e));
 }
 
 // Grid coordinate in FP64 -> window start i0 = ceil(u - w/2) and offset s0 = i0 - u.
@@ -98,6 +101,19 @@ __device__ __forceinline__ bool window_of(double x, int nf, int w, int* i0, floa
   if (x < -3.14159265358979323846) x += two_pi;
   if (x >= 3.14159265358979323846) x -= two_pi;
   double u = (x + 3.14159265358979323846) * ((double)nf / two_pi);
+  double c = ceil(u - 0.5 * w);
+  *i0 = (int)c;
+  *s0 = (float)(c - u);
+  return true;
+}
+
+// window_of with the grid scale nf / 2 pi given (no division per point).
+__device__ __forceinline__ bool window_at(double x, double scale, int w, int* i0, float* s0) {
+  const double two_pi = 6.283185307179586476925;
+  if (!(x == x) || x < -two_pi || x >= two_pi) return false;
+  if (x < -3.14159265358979323846) x += two_pi;
+  if (x >= 3.14159265358979323846) x -= two_pi;
+  double u = (x + 3.14159265358979323846) * scale;
   double c = ceil(u - 0.5 * w);
   *i0 = (int)c;
   *s0 = (float)(c - u);
@@ -182,6 +198,174 @@ __global__ __launch_bounds__(256) void k_interp(const float* __restrict__ grid, 
   }
 }
 
+// ------------------------------------------------------------------ 2-D prediction from an LDS grid
+// For d = 2 the oversampled grid of one coefficient set is small enough for LDS when its length is
+// any even number near 2.2 (2m + 1) (not a power of two): the inverse transforms are then plain
+// FP64 DFTs (a few hundred lines of at most 186 outputs), and every interpolation read is an LDS
+// read instead of an L2 request.
+
+constexpr int kNf2Max = 186;   // (nf + kMaxW)^2 FP32 values fit 160 KB of LDS
+
+// Grid length of the LDS path for d = 2 (0 when the grid would not fit LDS).
+static int predict_nf2(int m) {
+  const int L = 2 * m + 1;
+  const int nf = ((int)std::ceil(2.2 * L) + 7) & ~7;
+  return nf <= kNf2Max ? nf : 0;
+}
+
+static size_t pad_stride(int nf, int W) { return ((size_t)(nf + W) * (nf + W) + 63) & ~size_t(63); }
+
+// Inverse DFT along axis 0 of theta (one line per (set, q2)), pruned input frequencies q1 = -K..K,
+// deconvolved:  tmp[t][l1][q2] = sum_q1 theta[t][q1][q2] (-1)^q1 / phihat[|q1|] e^{+2 pi i q1 l1 / nf}.
+__global__ __launch_bounds__(256) void k_idft_cols(const double* __restrict__ theta, int K, int nf,
+                                                   const double* __restrict__ phihat, double* __restrict__ tmp) {
+  __shared__ double twr[kNf2Max], twi[kNf2Max];
+  __shared__ double ar[129], ai[129];
+  const int L = 2 * K + 1;
+  const int line = blockIdx.x;   // t * L + q2
+  const int t = line / L, q2 = line - t * L;
+  for (int i = threadIdx.x; i < nf; i += blockDim.x) {
+    double sn, cs;
+    sincospi(2.0 * i / nf, &sn, &cs);
+    twr[i] = cs;
+    twi[i] = sn;
+  }
+  const double* src = theta + 2 * ((size_t)t * L * L + q2);
+  for (int q = threadIdx.x; q < L; q += blockDim.x) {
+    const int aq = q - K < 0 ? K - q : q - K;
+    double f = 1.0 / phihat[aq];
+    if (aq & 1) f = -f;
+    ar[q] = src[2 * (size_t)q * L] * f;
+    ai[q] = src[2 * (size_t)q * L + 1] * f;
+  }
+  __syncthreads();
+  double* dst = tmp + 2 * ((size_t)t * nf * L + q2);
+  for (int l = threadIdx.x; l < nf; l += blockDim.x) {
+    int r = (int)(((int64_t)(nf - K) * l) % nf);   // (-K) l mod nf
+    double sr = 0.0, si = 0.0;
+    for (int q = 0; q < L; ++q) {
+      sr += ar[q] * twr[r] - ai[q] * twi[r];
+      si += ar[q] * twi[r] + ai[q] * twr[r];
+      r += l;
+      if (r >= nf) r -= nf;
+    }
+    dst[2 * (size_t)l * L] = sr;
+    dst[2 * (size_t)l * L + 1] = si;
+  }
+}
+
+// Inverse DFT along axis 1 (one line per (set, l1)), deconvolved, real part in FP32, written into
+// the periodically padded grid g[t][p1][p2] (P = nf + W rows and columns, padded index p holding the
+// grid point (p - W/2) mod nf), so that every window of W cells is contiguous without wrapping.
+__global__ __launch_bounds__(256) void k_idft_rows_pad(const double* __restrict__ tmp, int K, int nf, int W,
+                                                       const double* __restrict__ phihat, size_t pstride,
+                                                       float* __restrict__ g) {
+  __shared__ double twr[kNf2Max], twi[kNf2Max];
+  __shared__ double ar[129], ai[129];
+  const int L = 2 * K + 1, P = nf + W, H = W / 2;
+  const int line = blockIdx.x;   // t * nf + l1
+  const int t = line / nf, l1 = line - t * nf;
+  for (int i = threadIdx.x; i < nf; i += blockDim.x) {
+    double sn, cs;
+    sincospi(2.0 * i / nf, &sn, &cs);
+    twr[i] = cs;
+    twi[i] = sn;
+  }
+  const double* src = tmp + 2 * ((size_t)t * nf * L + (size_t)l1 * L);
+  for (int q = threadIdx.x; q < L; q += blockDim.x) {
+    const int aq = q - K < 0 ? K - q : q - K;
+    double f = 1.0 / phihat[aq];
+    if (aq & 1) f = -f;
+    ar[q] = src[2 * q] * f;
+    ai[q] = src[2 * q + 1] * f;
+  }
+  __syncthreads();
+  float* gt = g + (size_t)t * pstride;
+  for (int p2 = threadIdx.x; p2 < P; p2 += blockDim.x) {
+    int l = p2 - H;
+    l = l < 0 ? l + nf : (l >= nf ? l - nf : l);
+    int r = (int)(((int64_t)(nf - K) * l) % nf);
+    double sr = 0.0;
+    for (int q = 0; q < L; ++q) {
+      sr += ar[q] * twr[r] - ai[q] * twi[r];
+      r += l;
+      if (r >= nf) r -= nf;
+    }
+    const float v = (float)sr;
+    // padded rows of grid row l1: l1 + H, and its periodic copies inside [0, P)
+    for (int p1 = l1 + H - nf; p1 < P; p1 += nf)
+      if (p1 >= 0) gt[(size_t)p1 * P + p2] = v;
+  }
+}
+
+// f_t(x_j) for one coefficient set t and one chunk of points, from the padded grid in LDS.
+// Blocks: the T sets of a chunk are consecutive among the blocks one XCD receives (blocks go to
+// the 8 XCDs round robin), so the chunk's coordinates are read from HBM once per chunk and then
+// from that XCD's L2.
+template <int W>
+__global__ __launch_bounds__(1024) void k_interp2_lds(const float* __restrict__ gpad, size_t pstride, int nf, int T,
+                                                      const void* __restrict__ Xq, fk_dtype dt, int64_t nq,
+                                                      int64_t per_chunk, int64_t nchunk, double scale, EsDev2 es,
+                                                      float* __restrict__ out, int* flags) {
+  extern __shared__ float gl[];
+  constexpr int H = W / 2;
+  const int P = nf + W;
+  const int64_t b = blockIdx.x, xcd = b & 7, k = b >> 3;
+  const int t = (int)(k % T);
+  const int64_t chunk = (k / T) * 8 + xcd;
+  if (chunk >= nchunk) return;
+  const int64_t j0 = chunk * per_chunk;
+  const int64_t j1 = min(nq, j0 + per_chunk);
+  if (j0 >= j1) return;
+  {
+    const float4* src = reinterpret_cast<const float4*>(gpad + (size_t)t * pstride);
+    float4* dst = reinterpret_cast<float4*>(gl);
+    const int n4 = (int)(pstride / 4);
+    for (int i = threadIdx.x; i < n4; i += blockDim.x) dst[i] = src[i];
+  }
+  __syncthreads();
+  auto ld = [&](int64_t idx) -> double {
+    return dt == FK_F64 ? static_cast<const double*>(Xq)[idx] : (double)static_cast<const float*>(Xq)[idx];
+  };
+  // one point: f_t(x_j), or NaN and the range flag for a coordinate outside [-2 pi, 2 pi)
+  auto one = [&](int64_t j) -> float {
+    int i1, i2;
+    float s1, s2;
+    const bool ok1 = window_at(ld(j), scale, W, &i1, &s1);
+    const bool ok2 = window_at(ld(nq + j), scale, W, &i2, &s2);
+    if (!(ok1 && ok2)) {
+      atomicOr(&flags[kFlagRange], 1);
+      return __int_as_float(0x7fc00000);
+    }
+    float k1[W], k2[W];
+#pragma unroll
+    for (int a = 0; a < W; ++a) {
+      k1[a] = es_eval2(s1 + (float)a, es);
+      k2[a] = es_eval2(s2 + (float)a, es);
+    }
+    const float* gp = gl + (i1 + H) * P + (i2 + H);
+    float acc = 0.f;
+#pragma unroll
+    for (int a = 0; a < W; ++a) {
+      const float* row = gp + a * P;
+      float ra = 0.f;
+#pragma unroll
+      for (int c = 0; c < W; ++c) ra += row[c] * k2[c];
+      acc += ra * k1[a];
+    }
+    return acc;
+  };
+  // two points per thread and step (independent chains of LDS reads)
+  const int64_t stride = blockDim.x;
+  int64_t j = j0 + threadIdx.x;
+  for (; j + stride < j1; j += 2 * stride) {
+    const float a = one(j), b = one(j + stride);
+    out[(int64_t)t * nq + j] = a;
+    out[(int64_t)t * nq + j + stride] = b;
+  }
+  if (j < j1) out[(int64_t)t * nq + j] = one(j);
+}
+
 static int ilog2i(int v) {
   int r = 0;
   while ((1 << r) < v) ++r;
@@ -199,6 +383,12 @@ static size_t predict_ws(int d, int m, int T) {
   while (nf < 2 * (2 * m + 1)) nf <<= 1;
   const int L = 2 * m + 1;
   Carve cv(nullptr, 0);
+  if (d == 2 && predict_nf2(m)) {
+    const int nf2 = predict_nf2(m);
+    cv.take<double>((size_t)T * nf2 * L * 2);
+    cv.take<float>((size_t)T * pad_stride(nf2, kMaxW));
+    return cv.off + 512;
+  }
   if (d == 2) cv.take<double>((size_t)T * nf * L * 2);
   if (d == 3) {
     cv.take<double>((size_t)T * nf * L * L * 2);
@@ -253,6 +443,30 @@ static fk_status predict_impl(fk_ctx* ctx, const EsPlan& plan, const double* phi
   if (st != FK_OK) return st;
   const int nf = plan.nf, logn = ilog2i(nf), L = 2 * m + 1;
   Carve cv(ws, ws_bytes);
+  if (d == 2 && predict_nf2(m) == nf) {
+    // two pruned FP64 DFTs into padded FP32 grids, then one LDS-resident grid per workgroup
+    const int W = plan.w;
+    const size_t pst = pad_stride(nf, W);
+    double* t2 = cv.take<double>((size_t)T * nf * L * 2);
+    float* gp = cv.take<float>((size_t)T * pst);
+    if (!cv.ok()) return FK_ENOMEM;
+    hipLaunchKernelGGL(k_idft_cols, dim3(T * L), dim3(256), 0, ctx->stream, theta, m, nf, phihat, t2);
+    hipLaunchKernelGGL(k_idft_rows_pad, dim3(T * nf), dim3(256), 0, ctx->stream, t2, m, nf, W, phihat, pst, gp);
+    int64_t per_chunk = 32768;
+    if ((nq + per_chunk - 1) / per_chunk * T < 2048)
+      per_chunk = std::max<int64_t>(1024, (nq * T + 2047) / 2048);
+    const int64_t nchunk = (nq + per_chunk - 1) / per_chunk;
+    const int64_t nchunk8 = (nchunk + 7) & ~int64_t(7);
+    const int64_t blocks = nchunk8 * T;
+    if (blocks > 0x7fffffff) return FK_EINVAL;
+    EsDev2 es{(float)(plan.beta * 1.44269504088896340736), 2.0f / (float)W};
+    const size_t lds = sizeof(float) * pst;
+    FK_W_SWITCH2(W, hipLaunchKernelGGL(k_interp2_lds<WW>, dim3((unsigned)blocks), dim3(1024), lds, ctx->stream, gp,
+                                       pst, nf, T, Xq, dt, nq, per_chunk, nchunk, (double)nf / (2.0 * 3.14159265358979323846),
+                                       es, out, ctx->flags));
+    FK_HIP(hipGetLastError());
+    return read_flags(ctx);
+  }
   double* tmp = d == 2 ? cv.take<double>((size_t)T * nf * L * 2) : nullptr;
   double* ta = d == 3 ? cv.take<double>((size_t)T * nf * L * L * 2) : nullptr;
   double* tb = d == 3 ? cv.take<double>((size_t)T * nf * nf * L * 2) : nullptr;
@@ -284,7 +498,7 @@ static fk_status predict_impl(fk_ctx* ctx, const EsPlan& plan, const double* phi
   }
   const int64_t gsz = (int64_t)T * (int64_t)grid_cells(d, nf);
   hipLaunchKernelGGL(k_d2f_grid, dim3((gsz + 255) / 256), dim3(256), 0, ctx->stream, g64, g32, gsz);
-  EsDev2 es{(float)plan.beta, 2.0f / (float)plan.w};
+  EsDev2 es{(float)(plan.beta * 1.44269504088896340736), 2.0f / (float)plan.w};
   const int blocks = (int)((nq + 255) / 256);
   FK_W_SWITCH2(plan.w, hipLaunchKernelGGL(k_interp<WW>, dim3(blocks), dim3(256), 0, ctx->stream, g32, d, nf, T, Xq,
                                           dt, nq, es, out, ctx->flags));
@@ -341,7 +555,7 @@ extern "C" fk_status fk_predict(fk_ctx* ctx, int d, int m, int T, const double* 
   kept_invalidate(ws, ws_bytes);
   EsPlan plan;
   const double* phihat;
-  fk_status st = get_es_plan(ctx, m, &plan, &phihat);
+  fk_status st = get_es_plan(ctx, m, &plan, &phihat, d == 2 ? predict_nf2(m) : 0);
   if (st != FK_OK) return st;
   return predict_impl(ctx, plan, phihat, d, m, T, theta, nq, dt, Xq, out, ws, ws_bytes);
 }
@@ -357,7 +571,7 @@ extern "C" fk_status fk_predict_noalloc(fk_ctx* ctx, int d, int m, int T, const 
   if (st != FK_OK) return st;
   unsigned char* base = static_cast<unsigned char*>(g_scratch[ctx->device]);
   EsPlan plan;
-  st = get_es_plan_host(ctx, m, &plan);
+  st = get_es_plan_host(ctx, m, &plan, d == 2 ? predict_nf2(m) : 0);
   if (st != FK_OK) return st;
   if (plan.phihat.size() != (size_t)m + 1 || m + 1 > 65) return FK_EINVAL;
   // the deconvolution table goes in by value (a kernel argument), so no host buffer must outlive the call

@@ -113,12 +113,14 @@ static double es_error(int nf, int K, int w, double beta, const std::vector<doub
   return worst;
 }
 
-EsPlan make_es_plan(int K, double eps) {
-  // Fine grid: the smallest power of two with oversampling nf / (2K+1) >= 2.
+EsPlan make_es_plan(int K, double eps, int nf_fixed) {
+  // Fine grid: nf_fixed when given, else the smallest power of two with oversampling
+  // nf / (2K+1) >= 2.
   EsPlan p;
   p.K = K;
   int nf = 16;
   while (nf < 2 * (2 * K + 1)) nf <<= 1;
+  if (nf_fixed > 0) nf = nf_fixed;
   p.nf = nf;
   std::vector<double> gx, gw;
   gauss_legendre(160, gx, gw);
@@ -150,14 +152,14 @@ EsPlan make_es_plan(int K, double eps) {
   return p;
 }
 
-fk_status get_es_plan(fk_ctx* ctx, int K, EsPlan* plan, const double** d_phihat) {
+fk_status get_es_plan(fk_ctx* ctx, int K, EsPlan* plan, const double** d_phihat, int nf_fixed) {
   double eps = ctx->opt.eps > 0 ? ctx->opt.eps : 2e-7;
   uint64_t bits;
   std::memcpy(&bits, &eps, 8);
-  auto key = std::make_pair(K, bits);
+  auto key = std::make_pair(K + (nf_fixed << 16), bits);
   auto it = ctx->es_cache.find(key);
   if (it == ctx->es_cache.end()) {
-    EsPlan p = make_es_plan(K, eps);
+    EsPlan p = make_es_plan(K, eps, nf_fixed);
     double* d = nullptr;
     FK_HIP(hipMalloc(&d, sizeof(double) * (K + 1)));
     FK_HIP(hipMemcpy(d, p.phihat.data(), sizeof(double) * (K + 1), hipMemcpyHostToDevice));
@@ -168,18 +170,18 @@ fk_status get_es_plan(fk_ctx* ctx, int K, EsPlan* plan, const double** d_phihat)
   return FK_OK;
 }
 
-fk_status get_es_plan_host(fk_ctx* ctx, int K, EsPlan* plan) {
+fk_status get_es_plan_host(fk_ctx* ctx, int K, EsPlan* plan, int nf_fixed) {
   double eps = ctx->opt.eps > 0 ? ctx->opt.eps : 2e-7;
   uint64_t bits;
   std::memcpy(&bits, &eps, 8);
-  auto key = std::make_pair(K, bits);
+  auto key = std::make_pair(K + (nf_fixed << 16), bits);
   auto dev = ctx->es_cache.find(key);
   if (dev != ctx->es_cache.end()) {
     *plan = dev->second.first;
     return FK_OK;
   }
   auto it = ctx->es_host_cache.find(key);
-  if (it == ctx->es_host_cache.end()) it = ctx->es_host_cache.emplace(key, make_es_plan(K, eps)).first;
+  if (it == ctx->es_host_cache.end()) it = ctx->es_host_cache.emplace(key, make_es_plan(K, eps, nf_fixed)).first;
   *plan = it->second;
   return FK_OK;
 }
