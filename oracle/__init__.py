@@ -36,7 +36,7 @@ Parity status: every function here is pinned by the tests in
 ``tests/test_oracle_*.py`` against closed forms, a different library routine,
 brute force or a high-precision sum; none is "parity unpinned".
 """
-from .fourier import (modes, gram_generator, rhs, fourier_entry, toeplitz_matrix, design_matrix,
+from .fourier import (modes, gram_generator, rhs, fourier_entry, fourier_entries, toeplitz_matrix, design_matrix,
                       additive_blocks, additive_rhs)
 from .penalty import (sobolev_weights, sobolev_bessel_weights, piml_box_fourier_matrix,
                       heat_symbol, piml_heat_penalty, pde_symbol, piml_box_penalty, additive_penalty,
@@ -48,7 +48,7 @@ from .krr import krr_theta
 from .grad import heldout_mse, heldout_mse_quadratic, mse_gradients, theta_path_gradients
 
 __all__ = [
-    "modes", "gram_generator", "rhs", "fourier_entry", "toeplitz_matrix", "design_matrix",
+    "modes", "gram_generator", "rhs", "fourier_entry", "fourier_entries", "toeplitz_matrix", "design_matrix",
     "additive_blocks", "additive_rhs",
     "sobolev_weights", "sobolev_bessel_weights", "piml_box_fourier_matrix", "heat_symbol",
     "piml_heat_penalty", "pde_symbol", "piml_box_penalty", "additive_penalty", "collocation_penalty",

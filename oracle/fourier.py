@@ -10,9 +10,39 @@ tables (no reordering beyond the sum over points).
 """
 from __future__ import annotations
 
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 
-CHUNK = 1 << 15
+CHUNK = 1 << 14
+
+
+def _threads() -> int:
+    """Worker threads: FK_ORACLE_THREADS, else OMP_NUM_THREADS, else the core count (at most 16)."""
+    v = os.environ.get("FK_ORACLE_THREADS") or os.environ.get("OMP_NUM_THREADS")
+    return max(1, int(v) if v else min(16, os.cpu_count() or 1))
+
+
+def _chunk_sum(fn, n: int, chunk: int, out: np.ndarray) -> np.ndarray:
+    """out += fn(s, e) over the chunks [s, e) of range(n), added in chunk order.
+
+    The chunks are evaluated by a pool of threads (numpy releases the GIL in its kernels; each
+    chunk's arithmetic is the same as in a serial loop) with BLAS held to one thread each; the
+    partial sums are added in the order of the chunks, so the result does not depend on the
+    number of threads."""
+    starts = list(range(0, n, chunk))
+    nt = min(_threads(), len(starts))
+    if nt <= 1:
+        for s in starts:
+            out += fn(s, min(n, s + chunk))
+        return out
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1, user_api="blas"), ThreadPoolExecutor(nt) as pool:
+        for w in range(0, len(starts), 4 * nt):
+            for part in pool.map(lambda s: fn(s, min(n, s + chunk)), starts[w:w + 4 * nt]):
+                out += part
+    return out
 
 
 def modes(m: int, d: int) -> np.ndarray:
@@ -23,13 +53,16 @@ def modes(m: int, d: int) -> np.ndarray:
 
 
 def _powers(x: np.ndarray, K: int) -> np.ndarray:
-    """E[j, K + q] = exp(i q x_j) for q = -K..K (float64 complex)."""
+    """E[j, K + q] = exp(i q x_j) for q = -K..K (float64 complex).
+
+    Built one power at a time (E[., q] = E[., q - 1] exp(i x)) in rows of contiguous memory and
+    returned as the transposed view, so that each step streams through memory."""
     z = np.exp(1j * x.astype(np.float64))
-    pos = np.empty((x.shape[0], K + 1), dtype=np.complex128)
-    pos[:, 0] = 1.0
+    pos = np.empty((K + 1, x.shape[0]), dtype=np.complex128)
+    pos[0] = 1.0
     for q in range(1, K + 1):
-        pos[:, q] = pos[:, q - 1] * z
-    return np.concatenate([np.conj(pos[:, :0:-1]), pos], axis=1)
+        pos[q] = pos[q - 1] * z
+    return np.concatenate([np.conj(pos[:0:-1]), pos], axis=0).T
 
 
 def _weighted_sum(X: np.ndarray, W: np.ndarray, K: int, sign: int) -> np.ndarray:
@@ -37,13 +70,13 @@ def _weighted_sum(X: np.ndarray, W: np.ndarray, K: int, sign: int) -> np.ndarray
     d, n = X.shape
     C = W.shape[0]
     L = 2 * K + 1
-    acc = np.zeros((C,) + (L,) * d, dtype=np.complex128)
-    for s in range(0, n, CHUNK):
-        e = min(n, s + CHUNK)
+
+    def part(s, e):
         tabs = [_powers(X[a, s:e], K) for a in range(d)]
         if sign < 0:
             tabs = [np.conj(t) for t in tabs]
         w = W[:, s:e].astype(np.float64)
+        acc = np.zeros((C,) + (L,) * d, dtype=np.complex128)
         if d == 1:
             acc += w @ tabs[0]
         elif d == 2:
@@ -55,6 +88,9 @@ def _weighted_sum(X: np.ndarray, W: np.ndarray, K: int, sign: int) -> np.ndarray
                 for a in range(1, d):
                     prod = (prod[:, :, None] * tabs[a][:, None, :]).reshape(e - s, -1)
                 acc[c] += prod.sum(axis=0).reshape((L,) * d)
+        return acc
+
+    acc = _chunk_sum(part, n, CHUNK, np.zeros((C,) + (L,) * d, dtype=np.complex128))
     return acc.reshape(C, -1)
 
 
@@ -103,6 +139,28 @@ def fourier_entry(X: np.ndarray, w, q, sign: int, chunk: int = 1 << 22) -> compl
     return acc / n
 
 
+def fourier_entries(X: np.ndarray, W, qs, sign: int, chunk: int = 1 << 20) -> np.ndarray:
+    """Entries S[t, f] = n^-1 sum_j W[t, j] exp(sign * i qs[f].X_j) for a few frequency vectors qs
+    [F, d] and weight rows W [T, n] (W = None: one row of ones), by direct evaluation of each
+    exponential in float64 (Sec. 2.3).  The exponentials of a chunk are shared by all weight rows.
+    For sampled entries of very large inputs; returns complex128 [T, F]."""
+    X = np.atleast_2d(X)
+    d, n = X.shape
+    qs = np.asarray(qs, dtype=np.float64).reshape(-1, d)
+    T = 1 if W is None else np.atleast_2d(W).shape[0]
+    Wr = None if W is None else np.atleast_2d(W)
+
+    def part(s, e):
+        phase = qs @ X[:, s:e].astype(np.float64)          # [F, c]
+        z = np.exp(sign * 1j * phase)
+        if Wr is None:
+            return z.sum(axis=1)[None, :]
+        return Wr[:, s:e].astype(np.float64) @ z.T         # [T, F]
+
+    acc = _chunk_sum(part, n, chunk, np.zeros((T, qs.shape[0]), dtype=np.complex128))
+    return acc / n
+
+
 def toeplitz_matrix(M: np.ndarray, m: int) -> np.ndarray:
     """The multilevel Toeplitz matrix Sigma[k, l] = M[l - k] over k, l in {-m..m}^d."""
     d = M.ndim
@@ -124,11 +182,12 @@ def additive_blocks(X: np.ndarray, m: int) -> np.ndarray:
     X = np.atleast_2d(X)
     d, n = X.shape
     L = 2 * m + 1
-    B = np.zeros((d * L, d * L), dtype=np.complex128)
-    for s in range(0, n, CHUNK):
-        e = min(n, s + CHUNK)
+
+    def part(s, e):
         E = np.concatenate([_powers(X[a, s:e], m) for a in range(d)], axis=1)  # [c, d*L]
-        B += np.conj(E).T @ E
+        return np.conj(E).T @ E
+
+    B = _chunk_sum(part, n, CHUNK, np.zeros((d * L, d * L), dtype=np.complex128))
     return B / n
 
 

@@ -16,8 +16,10 @@ def fk():
     return fk
 
 
-@pytest.mark.parametrize("d,m,n", [(3, 8, 20_000), (10, 32, 200_000)])
+@pytest.mark.parametrize("d,m,n", [(3, 8, 20_000), (10, 32, 200_000), (10, 32, 1_000_000)])
 def test_additive_gram_and_fit(fk, d, m, n):
+    # the last case is the first 1e6 points of the additive workload (d = 10, m = 32, n = 1e8),
+    # every block entry and right-hand side element against the oracle
     w = synth.workload_additive(n=n, d=d)
     X, Y = w["X"], w["Y"]
     Xd, Yd = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()

@@ -21,7 +21,7 @@ def fk():
     return fk
 
 
-def _errors(fk, X, Y, m):
+def _errors(fk, X, Y, m, keep=None):
     Xd = torch.from_numpy(X).cuda()
     Yd = torch.from_numpy(Y).cuda()
     M, b, info = fk.gram(Xd, Yd, m, info=True)
@@ -32,6 +32,8 @@ def _errors(fk, X, Y, m):
     eT = np.abs(M - Mo).max() / abs(Mo.ravel()[Mo.size // 2])
     scale = np.abs(Y.astype(np.float64)).mean(axis=1, keepdims=True)
     eb = (np.abs(b - bo) / scale).max()
+    if keep is not None:
+        keep.update(Mo=Mo, bo=bo, Xd=Xd, Yd=Yd)
     return eT, eb, info
 
 
@@ -124,12 +126,23 @@ def test_gram_half_box_points(fk):
 
 
 def test_gram_full_size_2d_config(fk):
-    # 2-D Sobolev configuration at full size: n = 1e7 fp32 points, m = 32
+    # 2-D Sobolev configuration at full size: n = 1e7 fp32 points, m = 32, s = 2, lambda = n^-0.8;
+    # the type-1 outputs element by element, then theta end to end (type-1 stage + solve)
     w = synth.workload_2d()
-    eT, eb, info = _errors(fk, w["X"], w["Y"], w["m"])
+    o = {}
+    eT, eb, info = _errors(fk, w["X"], w["Y"], w["m"], keep=o)
     print(f"2-D n=1e7 m=32: eps_T={eT:.2e} eps_b={eb:.2e} spread={info['t_spread_ms']:.3f} ms "
           f"sort={info['t_sort_ms']:.3f} ms total={info['t_total_ms']:.3f} ms")
     assert eT <= TOL and eb <= TOL
+    m, lam = w["m"], w["lam"]
+    p = oracle.sobolev_weights(m, 2, w["s"])
+    A = oracle.system_matrix(o["Mo"], m, lam, p)
+    th = oracle.solve_system(A, o["bo"])
+    kappa = oracle.condition_number(A)
+    tg = fk.fit(o["Xd"], o["Yd"], m, lam, penalty="sobolev", s=w["s"])[0].cpu().numpy()
+    e = np.linalg.norm(tg - th) / np.linalg.norm(th)
+    print(f"2-D n=1e7 theta end to end: rel={e:.2e} kappa={kappa:.2e}")
+    assert kappa <= 1e6 and e <= 1e-4
 
 
 def test_invalid_inputs_are_reported(fk):
@@ -183,22 +196,30 @@ def test_gram_full_size_batched_sampled(fk):
     M = M.cpu().numpy()
     b = b.cpu().numpy()
     Xh = X.cpu().numpy()
-    y0 = Y[0].cpu().numpy()
-    del X, Y, ctx
+    del X, ctx
+    gc.collect()
+    torch.cuda.empty_cache()
+    Yh = Y.cpu().numpy()                      # [16, 1e9] fp32, 64 GB of host memory
+    del Y
     gc.collect()
     torch.cuda.empty_cache()
     c = 2 * m
     assert abs(M[c, c] - 1.0) <= 1e-6
     errs = []
-    for q in [(1, 0), (64, -64)]:
-        mo = oracle.fourier_entry(Xh, None, q, +1)
-        errs.append(abs(M[c + q[0], c + q[1]] - mo))
-        print(f"M{q}: {errs[-1]:.2e}", flush=True)
-    scale = float(np.abs(y0.astype(np.float64)).mean())
-    b0 = b[0].reshape(2 * m + 1, 2 * m + 1)
-    for k in [(-32, 31)]:
-        bo = oracle.fourier_entry(Xh, y0, k, -1)
-        errs.append(abs(b0[m + k[0], m + k[1]] - bo) / scale)
-        print(f"b0{k}: {errs[-1]:.2e}", flush=True)
+    # M: q = 0, the four corners of the +-2m square, the axes' ends and two interior frequencies
+    qs = np.array([(0, 0), (1, 0), (64, -64), (-64, 64), (64, 64), (-64, -1), (0, 64), (37, -5), (-12, 50)])
+    mo = oracle.fourier_entries(Xh, None, qs, +1)[0]
+    for q, v in zip(qs, mo):
+        errs.append(abs(M[c + q[0], c + q[1]] - v))
+    print(f"M at {len(qs)} frequencies: max error {max(errs):.2e}", flush=True)
+    # b: every target at two frequencies (the exponentials shared by the 16 weight rows)
+    ks = np.array([(-32, 31), (5, -17)])
+    bo = oracle.fourier_entries(Xh, Yh, ks, -1)           # [16, 2]
+    for t in range(T):
+        sc = float(np.abs(Yh[t]).mean(dtype=np.float64))
+        bt = b[t].reshape(2 * m + 1, 2 * m + 1)
+        for f, k in enumerate(ks):
+            errs.append(abs(bt[m + k[0], m + k[1]] - bo[t, f]) / sc)
+    print(f"b of {T} targets at {len(ks)} frequencies: max error {max(errs[len(qs):]):.2e}", flush=True)
     print(f"n=1e9 T=16 sampled: errors {['%.2e' % e for e in errs]}")
     assert max(errs) <= TOL

@@ -11,6 +11,7 @@ import synth
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-4
+TOL_GRAM = 1e-6
 
 
 @pytest.fixture(scope="module")
@@ -132,6 +133,46 @@ def test_fit_physics_informed_heat(fk, mu):
     e = _rel(tg[0].cpu().numpy(), th)
     print(f"PIML mu={mu}: rel={e:.2e} iters={info['refine_iters']}")
     assert e <= TOL
+
+
+def test_fit_physics_informed_heat_full_size(fk):
+    # The heat workload at full size: n = 1e8 points in [-pi/2, pi/2]^2, m = 20, lambda = 1e-4,
+    # mu = 1e-3 (the pass/fail case).  Sampled entries of M and b against the oracle's direct sums
+    # (all of M over 1e8 points would take the oracle minutes); theta against the oracle's FP64
+    # solve of the same M and b; and the whole fit (type-1 stage + solve) against that.
+    # inputs made on the device (the host generator would take minutes at 1e8 points): the
+    # workload's Philox points, and Y = e^-t sin x + N(0, 0.05^2) with torch's seeded normal draws
+    n, m, lam, mu = 100_000_000, 20, 1e-4, 1e-3
+    Xd = fk.generate_uniform(synth.SEED_BASE + 3, 2, n, lo=(-np.pi / 2,) * 2, hi=(np.pi / 2,) * 2)
+    g = torch.Generator(device="cuda").manual_seed(synth.SEED_BASE + 3)
+    noise = torch.randn((1, n), generator=g, device="cuda", dtype=torch.float32)
+    Yd = (torch.exp(-Xd[0:1].double()) * torch.sin(Xd[1:2].double()) + 0.05 * noise.double()).float()
+    del noise
+    X, Y = Xd.cpu().numpy(), Yd.cpu().numpy()
+    M, b = fk.gram(Xd, Yd, m)
+    M, b = M.cpu().numpy(), b.cpu().numpy()
+    c = 2 * m
+    qs = np.array([(0, 0), (1, 0), (0, 1), (40, -40), (-40, -40), (17, 3), (-9, 33)])
+    mo = oracle.fourier_entries(X, None, qs, +1)[0]
+    eT = max(abs(M[c + q[0], c + q[1]] - v) for q, v in zip(qs, mo))
+    ks = np.array([(0, 0), (1, 0), (0, 1), (-20, 20), (13, -7)])
+    bo = oracle.fourier_entries(X, Y, ks, -1)[0]
+    sc = float(np.abs(Y).mean(dtype=np.float64))
+    b2 = b[0].reshape(2 * m + 1, 2 * m + 1)
+    eb = max(abs(b2[m + k[0], m + k[1]] - v) / sc for k, v in zip(ks, bo))
+    print(f"PIML n=1e8 sampled: eps_T={eT:.2e} eps_b={eb:.2e}")
+    assert eT <= TOL_GRAM and eb <= TOL_GRAM
+    Q = oracle.piml_heat_penalty(m, lam, mu)
+    A = oracle.system_matrix(M, m, 0.0, Q)
+    th = oracle.solve_system(A, b)
+    kappa = oracle.condition_number(A)
+    ts = fk.solve(_cplx(M), _cplx(b), m, [lam], penalty="heat_box", mu=mu)[0].cpu().numpy()
+    tg, info = fk.fit(Xd, Yd, m, lam, penalty="heat_box", mu=mu, info=True)
+    e_s = _rel(ts, th)
+    e = _rel(tg[0].cpu().numpy(), th)
+    print(f"PIML n=1e8 mu=1e-3: kappa={kappa:.2e} solver-only {e_s:.2e} end-to-end {e:.2e} "
+          f"iters={info['refine_iters']}")
+    assert kappa <= 1e6 and e_s <= TOL and e <= TOL
 
 
 def _pde_fit(fk, X, Y, m, lam, mu, alpha, coef, lo, hi, s=1.0):

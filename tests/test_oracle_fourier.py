@@ -204,3 +204,40 @@ def test_fourier_entry_closed_forms_and_tables():
         assert abs(oracle.fourier_entry(X, None, (q1, q2), +1, chunk=1000) - M[q1 + 6, q2 + 6]) < 1e-13
     for (k1, k2) in [(1, 2), (-3, 3)]:
         assert abs(oracle.fourier_entry(X, Y[0], (k1, k2), -1, chunk=777) - b[k1 + 3, k2 + 3]) < 1e-13
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_sampled_entries_match_the_table_sums(d):
+    # fourier_entries (one exp per point and frequency) against gram_generator / rhs (power
+    # recurrences and matrix products): two routes to the same sums; chunks smaller than n so the
+    # ordered accumulation over chunks and threads is exercised
+    rng = np.random.default_rng(40 + d)
+    m, n = 4, 20_011
+    X = rng.uniform(-2 * np.pi, 2 * np.pi, size=(d, n))
+    Y = rng.standard_normal((3, n))
+    M = oracle.gram_generator(X, m)
+    b = oracle.rhs(X, Y, m).reshape((3,) + (2 * m + 1,) * d)
+    qs = rng.integers(-2 * m, 2 * m + 1, size=(6, d))
+    ks = rng.integers(-m, m + 1, size=(5, d))
+    eM = oracle.fourier_entries(X, None, qs, +1, chunk=4096)
+    eb = oracle.fourier_entries(X, Y, ks, -1, chunk=4096)
+    assert eM.shape == (1, 6) and eb.shape == (3, 5)
+    for f, q in enumerate(qs):
+        assert abs(eM[0, f] - M[tuple(q + 2 * m)]) <= 1e-13
+        assert abs(eM[0, f] - oracle.fourier_entry(X, None, q, +1)) <= 1e-13
+    for f, k in enumerate(ks):
+        for t in range(3):
+            assert abs(eb[t, f] - b[(t,) + tuple(k + m)]) <= 1e-13
+    # the sign matters: the + sign gives the conjugate of the - sign's weighted sum
+    assert np.abs(oracle.fourier_entries(X, Y, ks, +1) - np.conj(eb)).max() <= 1e-13
+    assert np.abs(oracle.fourier_entries(X, Y, ks, +1) - eb).max() > 1e-3
+
+
+def test_chunk_sums_do_not_depend_on_the_thread_count(monkeypatch):
+    rng = np.random.default_rng(7)
+    X = rng.uniform(-np.pi, np.pi, size=(2, 50_000))
+    monkeypatch.setenv("FK_ORACLE_THREADS", "1")
+    a = oracle.gram_generator(X, 3)
+    monkeypatch.setenv("FK_ORACLE_THREADS", "5")
+    b = oracle.gram_generator(X, 3)
+    assert np.array_equal(a, b)
