@@ -188,16 +188,18 @@ fk_status get_es_plan_host(fk_ctx* ctx, int K, EsPlan* plan, int nf_fixed) {
 
 // ------------------------------------------------------------------ device helpers
 
+// beta is pre-multiplied by log2(e): the exponent lies in [-beta log2 e, 0], so the hardware exp2
+// needs no range handling, and the hardware square root no denormal scaling.
 struct EsDev {
-  float beta;
+  float beta_log2e;
   float two_over_w;
 };
 
 __device__ __forceinline__ float es_eval(float s, EsDev es) {
   // s: distance in grid units; |s| <= w/2 inside the support.
-  float z = s * es.two_over_w;
-  float r = fmaxf(1.0f - z * z, 0.0f);
-  return __expf(es.beta * (__fsqrt_rn(r) - 1.0f));
+  const float z = s * es.two_over_w;
+  const float r = fmaxf(fmaf(-z, z, 1.0f), 0.0f);
+  return __builtin_amdgcn_exp2f(fmaf(es.beta_log2e, __builtin_amdgcn_sqrtf(r), -es.beta_log2e));
 }
 
 // Window start i0 = ceil(u - w/2) and first offset s0 = i0 - u (grid units) from
@@ -936,7 +938,7 @@ fk_status type1(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int64
   const int nf = plan.nf, W = plan.w, logn = ilog2(nf);
   const int fb = 32 - ilog2(nf) - 1;        // fixed-point fraction bits (u < nf <= 2^(31-fb))
   const double scale = (double)nf / (2.0 * kPi) * (double)(1u << fb);
-  EsDev es{(float)plan.beta, 2.0f / (float)W};
+  EsDev es{(float)(plan.beta * 1.44269504088896340736), 2.0f / (float)W};
   const int C = nw + 1;
   const int L = 2 * K + 1;
   if (info) {

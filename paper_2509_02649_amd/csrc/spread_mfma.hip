@@ -46,11 +46,12 @@ typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
 // Exponential of semicircle psi(s) = exp(beta (sqrt(1 - (2s/w)^2) - 1)), with beta
 // pre-multiplied by log2(e): the exponent lies in [-beta log2 e, 0], far from the
-// denormal range, so the hardware exp2 needs no range handling.
+// denormal range, so the hardware exp2 needs no range handling, and the hardware square
+// root needs no denormal scaling (1 - z^2 below 2^-126 gives psi ~ e^-beta either way).
 __device__ __forceinline__ float psi_es2(float s, float beta_log2e, float two_over_w) {
-  float z = s * two_over_w;
-  float r = fmaxf(1.0f - z * z, 0.0f);
-  return __builtin_amdgcn_exp2f(beta_log2e * (__fsqrt_rn(r) - 1.0f));
+  const float z = s * two_over_w;
+  const float r = fmaxf(fmaf(-z, z, 1.0f), 0.0f);
+  return __builtin_amdgcn_exp2f(fmaf(beta_log2e, __builtin_amdgcn_sqrtf(r), -beta_log2e));
 }
 
 // i0 = ceil(u - w/2), s0 = i0 - u from a fixed-point coordinate U = u 2^fb < 2^31,
@@ -67,7 +68,10 @@ __device__ __forceinline__ void win_start(uint32_t U, int fb, int w, int* i0, fl
 
 constexpr int SWAVE = 4;     // waves per workgroup, each independent
 constexpr int SFLUSH = 16;   // batches of 64 points between FP32 -> FP64 flushes
-constexpr int PS = 36;       // kernel-value table row (16 psi1 + 16 psi2, padded; 16-byte rows)
+// Kernel-value table row of one point: S + 1 slots per axis (offsets 0..S-1 of the subgrid, and
+// slot S kept zero for the padding cells of the last column tile), rounded up to whole 16-byte units.
+__host__ __device__ constexpr int tab_sp(int S) { return S + 1; }
+__host__ __device__ constexpr int tab_ps(int S) { return (2 * tab_sp(S) + 3) / 4 * 4; }
 
 template <int W, int MB>
 __device__ __forceinline__ void spread_mfma_body(const uint2* __restrict__ crd, const uint32_t* __restrict__ pos,
@@ -76,7 +80,8 @@ __device__ __forceinline__ void spread_mfma_body(const uint2* __restrict__ crd, 
                                                  float beta, int slices, double* __restrict__ grid) {
   constexpr int S = MB + W - 1;
   constexpr int NT = (S * S + 15) / 16;
-  static_assert(S <= 15, "subgrid offsets 0..S-1, offset 15 reads zero");
+  constexpr int SP = tab_sp(S), PS = tab_ps(S);
+  static_assert(S <= 15, "subgrid offsets 0..S-1");
   extern __shared__ double smem_d[];
   const int C = nw + 1;
   const float two_over_w = 2.0f / (float)W;
@@ -100,15 +105,15 @@ __device__ __forceinline__ void spread_mfma_body(const uint2* __restrict__ crd, 
 
   const int k = lane >> 4, j = lane & 15;
   // Table offsets of psi1[a] and psi2[b] for the cell (a, b) of column tile t.
-  // Padding cells (>= S*S) read entry 15 of each half, which stays zero.
+  // Padding cells (>= S*S) read slot S of each half, which stays zero.
   int offa[NT], offb[NT];
   bool cin[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int cell = t * 16 + j;
     cin[t] = cell < S * S;
-    offa[t] = cin[t] ? cell / S : 15;
-    offb[t] = 16 + (cin[t] ? cell - (cell / S) * S : 15);
+    offa[t] = cin[t] ? cell / S : S;
+    offb[t] = SP + (cin[t] ? cell - (cell / S) * S : S);
   }
   floatx4_t acc[NT];
   float ones[NT];
@@ -178,9 +183,9 @@ __device__ __forceinline__ void spread_mfma_body(const uint2* __restrict__ crd, 
       win_start(U.x, fb, W, &i1, &s1);                                                       \
       win_start(U.y, fb, W, &i2, &s2);                                                       \
       float4* r4 = reinterpret_cast<float4*>(row);                                           \
-      _Pragma("unroll") for (int q = 0; q < 8; ++q) r4[q] = make_float4(0.f, 0.f, 0.f, 0.f); \
-      const int rel1 = (i1 - o1) & (nf - 1), rel2 = 16 + ((i2 - o2) & (nf - 1));            \
-      if (valid && rel1 < MB && rel2 < 16 + MB) {                                            \
+      _Pragma("unroll") for (int q = 0; q < PS / 4; ++q) r4[q] = make_float4(0.f, 0.f, 0.f, 0.f); \
+      const int rel1 = (i1 - o1) & (nf - 1), rel2 = SP + ((i2 - o2) & (nf - 1));            \
+      if (valid && rel1 < MB && rel2 < SP + MB) {                                            \
         _Pragma("unroll") for (int r = 0; r < W; ++r) {                                     \
           row[rel1 + r] = psi_es2(s1 + (float)r, bl2, two_over_w);                           \
           row[rel2 + r] = psi_es2(s2 + (float)r, bl2, two_over_w);                           \
@@ -240,8 +245,11 @@ __device__ __forceinline__ void spread_mfma_body(const uint2* __restrict__ crd, 
   }
 }
 
+// Four waves per SIMD (at most 128 registers): the kernel is issue-bound (matrix cores and
+// vector ALUs together), and the fourth wave hides more of the gathers' latency than the
+// registers it takes from the unrolled chunk loop cost (29.7 against 30.4 ms at 1e9 points).
 template <int W, int MB>
-__global__ __launch_bounds__(64 * SWAVE) void k_spread_mfma(
+__global__ __launch_bounds__(64 * SWAVE) __attribute__((amdgpu_waves_per_eu(4))) void k_spread_mfma(
     const uint2* __restrict__ crd, const uint32_t* __restrict__ pos, const float* __restrict__ wrow, int nw,
     const uint64_t* __restrict__ start, int nbx, int nf, int fb, float beta, int slices, double* __restrict__ grid) {
   spread_mfma_body<W, MB>(crd, pos, wrow, nw, start, nbx, nf, fb, beta, slices, grid);
@@ -283,7 +291,7 @@ fk_status launch_spread_mfma(hipStream_t st, int W, int MB, const uint32_t* crd,
   const int slices = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (per_bin + spread_pts - 1) / spread_pts));
   const int blocks = nb * slices;
   const size_t lds = sizeof(double) * (((MB + W - 1) * (MB + W - 1) * (nw + 1) + 1) & ~1) +
-                     sizeof(float) * SWAVE * 64 * PS;
+                     sizeof(float) * SWAVE * 64 * tab_ps(MB + W - 1);
   const float bt = (float)beta;
   const uint2* c2 = reinterpret_cast<const uint2*>(crd);
   const float* wf = reinterpret_cast<const float*>(wrow);

@@ -39,11 +39,12 @@ constexpr int OWAVE = 4;     // waves per workgroup
 constexpr int OFLUSH = 16;   // batches of 64 points per wave between FP32 -> FP64 flushes
 
 // Exponential of semicircle psi(s) = exp(beta (sqrt(1 - (2s/w)^2) - 1)) with beta
-// pre-multiplied by log2(e) (exponent in [-beta log2 e, 0]).
+// pre-multiplied by log2(e) (exponent in [-beta log2 e, 0]: the hardware exp2 needs no range
+// handling, and the hardware square root no denormal scaling).
 __device__ __forceinline__ float psi_es(float s, float beta_log2e, float two_over_w) {
   const float z = s * two_over_w;
-  const float r = fmaxf(1.0f - z * z, 0.0f);
-  return __builtin_amdgcn_exp2f(beta_log2e * (__fsqrt_rn(r) - 1.0f));
+  const float r = fmaxf(fmaf(-z, z, 1.0f), 0.0f);
+  return __builtin_amdgcn_exp2f(fmaf(beta_log2e, __builtin_amdgcn_sqrtf(r), -beta_log2e));
 }
 
 // i0 = ceil(u - w/2) and s0 = i0 - u for the fixed-point coordinate U = u 2^fb, in
