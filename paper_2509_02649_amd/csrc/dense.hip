@@ -992,7 +992,7 @@ SolveLayout solve_layout(int N, int nlam, int ntgt, void* base, size_t cap) {
   s.pcx = cv.take<double>((size_t)N);
   s.scl = cv.take<double>((size_t)nlam * Np);
   s.dsym = cv.take<double>((size_t)2 * N);
-  s.bytes = cv.off + 256;
+  s.bytes = ((cv.off + 255) & ~size_t(255)) + 256;   // a multiple of 256: what follows stays aligned
   return s;
 }
 

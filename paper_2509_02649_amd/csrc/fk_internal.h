@@ -40,11 +40,22 @@ struct EsPlan {
 EsPlan make_es_plan(int K, double eps, int nf_fixed = 0);
 
 // Workspace carving: bump allocator over the caller's buffer.
+// Every array starts on a 256-byte boundary of the device address space: a base that is not
+// aligned is first moved up to the next boundary (the workspace sizes carry that much slack).
+// The 64-byte weight blocks of the sort and the spread's gathers rely on it: one block per half
+// cache line, not one straddling two lines.
 struct Carve {
   char* base;
   size_t off = 0;
   size_t cap;
-  Carve(void* b, size_t c) : base(static_cast<char*>(b)), cap(c) {}
+  Carve(void* b, size_t c) : base(static_cast<char*>(b)), cap(c) {
+    const size_t mis = reinterpret_cast<uintptr_t>(base) & 255u;
+    if (base && mis) {
+      const size_t skip = 256 - mis;
+      base += skip;
+      cap = cap > skip ? cap - skip : 0;
+    }
+  }
   template <class T>
   T* take(size_t count) {
     off = (off + 255) & ~size_t(255);
