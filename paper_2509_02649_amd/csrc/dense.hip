@@ -1371,22 +1371,40 @@ __global__ __launch_bounds__(256) void k_grad_loglam(const double* __restrict__ 
   if (threadIdx.x == 0) out[l] = -2.0 * lams[l] * part[0];
 }
 
-__global__ void k_grad_p(const double* __restrict__ U, const double* __restrict__ X, const double* __restrict__ lams,
-                         int N, int L, int Np, int nlam, int ntgt, double* __restrict__ gp) {
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= N) return;
-  int ty, k, nk;
-  real_to_complex(r, L, &ty, &k, &nk);
-  if (ty == 2) return;
+// grad_p over the (lambda, target) systems: blockIdx.y takes one slice of them, its four waves
+// a quarter of the slice each, lane = real-form row; the slices' sums are added into gp, which
+// k_zero_d cleared.
+constexpr int kGradPSlices = 16;
+__global__ void k_zero_d(double* __restrict__ x, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_grad_p(const double* __restrict__ U, const double* __restrict__ X,
+                                                const double* __restrict__ lams, int N, int L, int Np, int nlam,
+                                                int ntgt, double* __restrict__ gp) {
+  __shared__ double part[4][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r = blockIdx.x * 64 + lane;
+  const int nc = nlam * ntgt;
+  const int c0 = (int)((int64_t)nc * blockIdx.y / gridDim.y), c1 = (int)((int64_t)nc * (blockIdx.y + 1) / gridDim.y);
+  int ty = 2, k = 0, nk = 0;
+  if (r < N) real_to_complex(r, L, &ty, &k, &nk);
   double s = 0.0;
-  for (int l = 0; l < nlam; ++l)
-    for (int t = 0; t < ntgt; ++t) {
-      const size_t o = ((size_t)l * ntgt + t) * Np;
-      double v = ty == 0 ? U[o + r] * X[o + r] : 0.5 * (U[o + r] * X[o + r] + U[o + r + 1] * X[o + r + 1]);
+  if (ty != 2)
+    for (int c = c0 + wv; c < c1; c += 4) {
+      const int l = c / ntgt;
+      const size_t o = (size_t)c * Np;
+      const double v = ty == 0 ? U[o + r] * X[o + r] : 0.5 * (U[o + r] * X[o + r] + U[o + r + 1] * X[o + r + 1]);
       s += (-2.0 * lams[l]) * v;
     }
-  gp[k] = s;
-  if (ty == 1) gp[nk] = s;
+  part[wv][lane] = s;
+  __syncthreads();
+  if (wv == 0 && ty != 2) {
+    const double t = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+    atomicAdd(&gp[k], t);
+    if (ty == 1) atomicAdd(&gp[nk], t);
+  }
 }
 
 __global__ void k_scale_cols_cplx(double* __restrict__ th, const double* __restrict__ gm, int N) {
@@ -1409,9 +1427,11 @@ fk_status backward_impl(fk_ctx* ctx, const SolveLayout& s, int d, const double* 
   if (st != FK_OK && st != FK_ENOCONV) return st;
   hipLaunchKernelGGL(k_grad_loglam, dim3(s.nlam), dim3(256), 0, ctx->stream, s.U64, s.X64, s.preal, s.lams, Np,
                      s.ntgt, grad_loglam);
-  if (grad_p)
-    hipLaunchKernelGGL(k_grad_p, dim3((N + 255) / 256), dim3(256), 0, ctx->stream, s.U64, s.X64, s.lams, N, L,
-                       Np, s.nlam, s.ntgt, grad_p);
+  if (grad_p) {
+    hipLaunchKernelGGL(k_zero_d, dim3((N + 255) / 256), dim3(256), 0, ctx->stream, grad_p, N);
+    hipLaunchKernelGGL(k_grad_p, dim3((N + 63) / 64, kGradPSlices), dim3(256), 0, ctx->stream, s.U64, s.X64, s.lams,
+                       N, L, Np, s.nlam, s.ntgt, grad_p);
+  }
   if (grad_theta) {
     hipLaunchKernelGGL(k_theta_from_real, dim3((N + 255) / 256, nc), dim3(256), 0, ctx->stream, s.G64, N, L, Np,
                        s.ntgt, grad_theta);
