@@ -20,13 +20,15 @@ def _herm(rng, N, scale=1.0):
     return 0.5 * (th + np.conj(th[::-1]))
 
 
-@pytest.mark.parametrize("d,m,nq", [(1, 50, 10_000), (2, 32, 100_003), (2, 5, 17)])
+# (2, 41): the largest m whose grid fits LDS, with 40 coefficient sets; (2, 45): the global-memory
+# path beyond it
+@pytest.mark.parametrize("d,m,nq", [(1, 50, 10_000), (2, 32, 100_003), (2, 5, 17), (2, 41, 5_001), (2, 45, 5_001)])
 def test_predict_matches_direct_sum(fk, d, m, nq):
     rng = np.random.default_rng(d + m)
     N = (2 * m + 1) ** d
     k = oracle.modes(m, d)
     decay = 1.0 / (1.0 + (k ** 2).sum(1))
-    th = np.stack([_herm(rng, N) * decay, _herm(rng, N) * decay])
+    th = np.stack([_herm(rng, N) * decay for _ in range(40 if (d, m) == (2, 41) else 2)])
     Xq = rng.uniform(-np.pi, np.pi, size=(d, nq)).astype(np.float32)
     f = fk.predict(torch.from_numpy(th).cuda(), torch.from_numpy(Xq).cuda(), m).cpu().numpy()
     fo = oracle.predict(th, Xq.astype(np.float64), m).real
