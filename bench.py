@@ -52,22 +52,18 @@ def _blas_vendor() -> str:
         return "unknown"
 
 
-def _cpu_baseline(workload: str, ntgt: int, m: int, lam: float):
-    """Time the FP64 CPU oracle on a bounded prefix of the workload: the direct Fourier sums for M and
-    b (linear in n, so points/s extrapolates) and, separately, one FP64 LAPACK Cholesky solve of the
-    (2m+1)^2 system (independent of n)."""
+def _cpu_baseline(Xd, Yd, m: int, lam: float):
+    """Time the FP64 CPU oracle on a bounded prefix of the workload's own inputs (copied from the
+    device): the direct Fourier sums for M and b (linear in n, so points/s extrapolates) and,
+    separately, one FP64 LAPACK Cholesky solve of the (2m+1)^2 system (independent of n)."""
     import numpy as np
     import oracle
-    import synth
-    threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
-    if workload in ("batched", "cg"):
-        n = 1_500_000
-        X = synth.uniform_points(synth.SEED_BASE + 5, 2, n)
-        Y = synth.batched_targets(X, synth.SEED_BASE + 5, ntgt)
-    else:
-        n = 1_000_000
-        w = synth.workload_2d(n=n)
-        X, Y = w["X"], w["Y"]
+    from oracle.fourier import _threads
+    threads = str(_threads())
+    ntgt = Yd.shape[0]
+    n = min(Xd.shape[1], 12_000_000 if ntgt > 1 else 4_000_000)   # about 10-20 s of host work
+    X = Xd[:, :n].cpu().numpy()
+    Y = Yd[:, :n].cpu().numpy()
     X64, Y64 = X.astype(np.float64), Y.astype(np.float64)
     t0 = time.perf_counter()
     M = oracle.gram_generator(X64, m)
@@ -361,7 +357,7 @@ def main():
         out["cg_ms"] = dt * 1e3 - gr_ms
         out["roofline_fft"] = _fft_roofline(fk, torch, last["M"], m, nlam * ntgt, ctx)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = _cpu_baseline(args.workload, ntgt, m, lams[nlam // 2])
+        out["cpu_baseline"] = _cpu_baseline(X, Y, m, lams[nlam // 2])
     print(json.dumps(out))
 
 
