@@ -30,11 +30,17 @@
  *   bytes (256-byte aligned).  The library allocates no device memory inside
  *   compute calls except its small per-context plan tables (created on first
  *   use of a shape and freed by fk_destroy).
- * - Work is enqueued on the context's HIP stream.  Every compute entry point
- *   ends with one synchronisation of that stream, at which device-detected
- *   conditions (NaN input, out-of-range input, non-positive pivot, no
- *   convergence) become the returned status.  Host-side argument checks
- *   return FK_EINVAL before anything is enqueued.
+ * - Work is enqueued on the context's HIP stream (the additive model's
+ *   transforms also on a second stream of the context, created at first use
+ *   with the default priority and joined back before the call returns).
+ *   Every compute entry point returns after synchronising that stream, and
+ *   device-detected conditions (NaN input, out-of-range input, non-positive
+ *   pivot, no convergence) become the returned status there.  The fits
+ *   synchronise once per refinement step (its residual norms, which come back
+ *   with the error flags of every stage before it, decide whether another step
+ *   runs) and once at the end; a first use of an untuned large shape also
+ *   synchronises around its timed trials.  Host-side argument checks return
+ *   FK_EINVAL before anything is enqueued.
  * - A context must not be used by two threads at once; distinct contexts are
  *   independent.  No exception crosses this ABI.
  */

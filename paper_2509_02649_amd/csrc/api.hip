@@ -50,6 +50,11 @@ extern "C" fk_status fk_destroy(fk_ctx* ctx) {
   hipSetDevice(ctx->device);
   hipStreamSynchronize(ctx->stream);
   for (auto& kv : ctx->es_cache) hipFree(kv.second.second);
+  if (ctx->aux_stream) {
+    hipStreamSynchronize(ctx->aux_stream);
+    hipStreamDestroy(ctx->aux_stream);
+    for (auto& e : ctx->aux_ev) hipEventDestroy(e);
+  }
   hipFree(ctx->flags);
   hipHostFree(ctx->flags_host);
   for (auto& e : ctx->ev) hipEventDestroy(e);
@@ -101,6 +106,10 @@ fk_status read_flags(fk_ctx* ctx) {
   FK_HIP(hipMemcpyAsync(ctx->flags_host, ctx->flags, sizeof(int) * kFlagCount, hipMemcpyDeviceToHost,
                         ctx->stream));
   FK_HIP(hipStreamSynchronize(ctx->stream));
+  return flag_status(ctx);
+}
+
+fk_status flag_status(const fk_ctx* ctx) {
   if (ctx->flags_host[kFlagNaN]) return FK_ENAN;
   if (ctx->flags_host[kFlagRange]) return FK_ERANGE;
   if (ctx->flags_host[kFlagNotPD]) return FK_ENOTPD;
@@ -567,22 +576,17 @@ extern "C" fk_status fk_fit(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const vo
   st = reset_flags(ctx);
   if (st == FK_OK) st = gram_impl(ctx, d, n, dt, X, ntgt, Y, m, M, b, cv, info);
   if (st != FK_OK) return st;
-  st = read_flags(ctx);
-  if (info) {
-    info->t_sort_ms = elapsed(ctx->ev[0], ctx->ev[1]);
-    info->t_spread_ms = elapsed(ctx->ev[1], ctx->ev[2]);
-    info->spread_kernel_ms = info->t_spread_ms;
-    info->t_fft_ms = elapsed(ctx->ev[2], ctx->ev[4]);
-  }
-  if (st != FK_OK) {
-    if (info) info->status = st;
-    return st;
-  }
+  // No synchronization here: the solve is queued behind the type-1 stage, and the flags the stage
+  // raises (NaN, range) come back with the solve's first residual norms, ahead of its own status.
   st = solve_impl(ctx, P, s, theta_out, info);
   if (st == FK_OK || st == FK_ENOCONV)
     kept_register(ws, s.bytes, ctx->device, kKeptToeplitz, d, m, P.L, nlam, ntgt, 1);
   if (info) {
     info->status = st;
+    info->t_sort_ms = elapsed(ctx->ev[0], ctx->ev[1]);
+    info->t_spread_ms = elapsed(ctx->ev[1], ctx->ev[2]);
+    info->spread_kernel_ms = info->t_spread_ms;
+    info->t_fft_ms = elapsed(ctx->ev[2], ctx->ev[4]);
     info->t_total_ms = elapsed(ctx->ev[0], ctx->ev[8]);
   }
   return st;
@@ -713,15 +717,30 @@ __global__ void k_additive_assemble(const double* __restrict__ c1, const double*
   }
 }
 
+// Workspace of one type-1 transform of the additive model (the larger of the 1-D and pairwise ones).
+static size_t additive_region(int64_t n, int T, int m) {
+  const size_t t1 = type1_workspace(1, n, T, 2 * m, 0);
+  const size_t t2 = type1_workspace(2, n, 0, m, 0);
+  return (std::max(t1, t2) + 1023) & ~size_t(255);
+}
+
 static size_t additive_gram_ws(int d, int64_t n, int T, int m) {
   const int L = 2 * m + 1, K1 = 4 * m + 1;
   const int npair = d * (d - 1) / 2;
   Carve cv(nullptr, 0);
   cv.take<double>((size_t)2 * d * (T + 1) * K1);
   cv.take<double>((size_t)2 * npair * L * L);
-  size_t t1 = type1_workspace(1, n, T, 2 * m, 0);
-  size_t t2 = type1_workspace(2, n, 0, m, 0);
-  return cv.off + std::max(t1, t2) + 1024;
+  cv.take<char>(additive_region(n, T, m));   // two transforms in flight, one region each
+  cv.take<char>(additive_region(n, T, m));
+  return cv.off + 1024;
+}
+
+// The second stream of the additive model's transforms (created on first use, default priority).
+static fk_status aux_stream(fk_ctx* ctx) {
+  if (ctx->aux_stream) return FK_OK;
+  FK_HIP(hipStreamCreateWithFlags(&ctx->aux_stream, hipStreamNonBlocking));
+  for (auto& e : ctx->aux_ev) FK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  return FK_OK;
 }
 
 fk_status additive_gram_impl(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int T, const void* Y,
@@ -730,23 +749,48 @@ fk_status additive_gram_impl(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const v
   const int npair = d * (d - 1) / 2;
   double* c1 = cv.take<double>((size_t)2 * d * (T + 1) * K1);
   double* c2 = cv.take<double>((size_t)2 * npair * L * L);
+  const size_t region = additive_region(n, T, m);
+  char* reg[2] = {cv.take<char>(region), cv.take<char>(region)};
   if (!cv.ok()) return FK_ENOMEM;
+  fk_status st = aux_stream(ctx);
+  if (st != FK_OK) return st;
   const size_t esz = dt == FK_F64 ? 8 : 4;
   const char* Xc = static_cast<const char*>(X);
-  for (int a = 0; a < d; ++a) {
-    Carve sub = cv;
-    fk_status st = type1(ctx, 1, n, dt, Xc + esz * (size_t)a * n, n, T, Y, 2 * m, 1.0 / (double)n,
-                         c1 + 2 * (size_t)a * (T + 1) * K1, sub, info);
-    if (st != FK_OK) return st;
-  }
-  int p = 0;
+  // The d(d-1)/2 pairwise and d one-dimensional transforms, two in flight: task k runs on the
+  // caller's stream (even k) or the aux stream (odd k), each side in a workspace region of its own.
+  // Both kinds are HBM-bound (sorting passes, record gathers), so the gain is the filling of each
+  // other's launch tails and gaps.  Task 0, the first pair, runs alone first: the pairwise launch
+  // shape, tuned at its first use (the one-dimensional transforms have none), is then measured without
+  // the other stream, and the later pairs find it in the table.
+  std::vector<std::pair<int, int>> tasks;
   for (int a = 0; a < d; ++a)
-    for (int bb = a + 1; bb < d; ++bb, ++p) {
-      Carve sub = cv;
-      fk_status st = type1(ctx, 2, n, dt, Xc + esz * (size_t)a * n, (int64_t)(bb - a) * n, 0, nullptr, m,
-                           1.0 / (double)n, c2 + 2 * (size_t)p * L * L, sub, info);
-      if (st != FK_OK) return st;
+    for (int bb = a + 1; bb < d; ++bb) tasks.push_back({a, bb});
+  for (int a = 0; a < d; ++a) tasks.push_back({a, -1});
+  hipStream_t S = ctx->stream, Bs = ctx->aux_stream;
+  int p = 0;
+  for (size_t k = 0; k < tasks.size() && st == FK_OK; ++k) {
+    if (k == 1) {
+      FK_HIP(hipEventRecord(ctx->aux_ev[0], S));
+      FK_HIP(hipStreamWaitEvent(Bs, ctx->aux_ev[0], 0));
     }
+    const int side = (int)(k & 1);
+    ctx->stream = side ? Bs : S;
+    Carve sub(reg[side], region);
+    const int a = tasks[k].first, bb = tasks[k].second;
+    if (bb < 0) {
+      st = type1(ctx, 1, n, dt, Xc + esz * (size_t)a * n, n, T, Y, 2 * m, 1.0 / (double)n,
+                 c1 + 2 * (size_t)a * (T + 1) * K1, sub, info);
+    } else {
+      st = type1(ctx, 2, n, dt, Xc + esz * (size_t)a * n, (int64_t)(bb - a) * n, 0, nullptr, m, 1.0 / (double)n,
+                 c2 + 2 * (size_t)p * L * L, sub, info);
+      ++p;
+    }
+    ctx->stream = S;
+  }
+  // join: the caller's stream waits for the aux stream's work (also on an error, before returning)
+  FK_HIP(hipEventRecord(ctx->aux_ev[1], Bs));
+  FK_HIP(hipStreamWaitEvent(S, ctx->aux_ev[1], 0));
+  if (st != FK_OK) return st;
   const int Nc = d * L;
   const int tot = std::max(Nc * Nc, T * Nc);
   hipLaunchKernelGGL(k_additive_assemble, dim3((tot + 255) / 256), dim3(256), 0, ctx->stream, c1, c2, d, m, T, B, b);
@@ -852,11 +896,7 @@ extern "C" fk_status fk_additive_fit(fk_ctx* ctx, int d, int64_t n, fk_dtype dt,
   if (st == FK_OK) st = additive_gram_impl(ctx, d, n, dt, X, ntgt, Y, m, B, b, cv, info);
   if (st != FK_OK) return st;
   FK_HIP(hipEventRecord(ctx->ev[10], ctx->stream));
-  st = read_flags(ctx);
-  if (st != FK_OK) {
-    if (info) info->status = st;
-    return st;
-  }
+  // (the transforms' flags come back with the solve's first residual norms)
   st = solve_impl(ctx, P, sl, theta_out, info);
   if (info) {
     info->status = st;

@@ -1059,8 +1059,12 @@ static fk_status trsm_all(fk_ctx* ctx, const SolveLayout& s, const DenseShape& s
 // Solve (H64 + lambda diag(preal)) X = RHS for all (lambda, target) with FP32
 // factors and FP64 refinement.  RHS given per target (Bre) or per column (rhs_cols).
 // Returns the number of refinement steps and the worst relative residual.
+// With check_flags, every step's norm read-back also brings the context's error flags (the stages
+// queued before the solve raised them: input NaN, range, not positive definite), and those are
+// reported first: the caller then needs no synchronization of its own before the solve.
 static fk_status refine_solve(fk_ctx* ctx, const SolveLayout& s, const DenseShape& sh, const double* rhs_cols,
-                              double* X, int* iters_out, double* resid_out, int* bad_out) {
+                              double* X, int* iters_out, double* resid_out, int* bad_out,
+                              bool check_flags = false) {
   const int64_t tot = (int64_t)s.nlam * s.ntgt * s.Np;
   const int nc = s.nlam * s.ntgt;
   const int thr = 256;
@@ -1093,7 +1097,19 @@ static fk_status refine_solve(fk_ctx* ctx, const SolveLayout& s, const DenseShap
     FK_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_colnorm2, dim3(nc), dim3(256), 0, ctx->stream, s.R64, s.Np, s.norms);
     FK_HIP(hipMemcpyAsync(nh.data(), s.norms, sizeof(double) * 2 * nc, hipMemcpyDeviceToHost, ctx->stream));
+    if (check_flags)
+      FK_HIP(hipMemcpyAsync(ctx->flags_host, ctx->flags, sizeof(int) * kFlagCount, hipMemcpyDeviceToHost,
+                            ctx->stream));
     FK_HIP(hipStreamSynchronize(ctx->stream));
+    if (check_flags) {
+      const fk_status fs = flag_status(ctx);
+      if (fs != FK_OK) {
+        *iters_out = it;
+        *resid_out = 0.0;
+        *bad_out = fs == FK_ENOTPD ? ctx->flags_host[kFlagNotPD + 1] : -1;
+        return fs;
+      }
+    }
     worst = 0.0;
     bad = -1;
     for (int c = 0; c < nc; ++c) {
@@ -1148,6 +1164,9 @@ static fk_status tune_dense(fk_ctx* ctx, const SolveLayout& s, DenseShape* out, 
   if (mode == kTuneOff || !dense_tunable(s)) return FK_OK;
   std::map<std::string, double> v;
   if (mode != kTuneForce && tune_lookup(dense_key(ctx, s), &v)) return FK_OK;
+  // the trials synchronize anyway: no shape is measured on a system the earlier stages flagged
+  fk_status fs = read_flags(ctx);
+  if (fs != FK_OK) return fs;
   const int64_t tot2 = (int64_t)s.Np * s.Np;
   const int gb = (int)((tot2 + 255) / 256);
   hipEvent_t e0 = ctx->ev[11], e1 = ctx->ev[12];
@@ -1237,14 +1256,10 @@ fk_status solve_impl(fk_ctx* ctx, const SolveProblem& P, const SolveLayout& s, d
     if (st != FK_OK) return st;
   }
   FK_HIP(hipEventRecord(ev[7], ctx->stream));
-  st = read_flags(ctx);
-  if (st != FK_OK) {
-    if (info) info->bad_index = ctx->flags_host[kFlagNotPD + 1];
-    return st;
-  }
+  // the flags of the earlier stages and of the factorization come back with the first residual norms
   int iters = 0, bad = -1;
   double resid = 0.0;
-  st = refine_solve(ctx, s, sh, nullptr, s.X64, &iters, &resid, &bad);
+  st = refine_solve(ctx, s, sh, nullptr, s.X64, &iters, &resid, &bad, true);
   hipLaunchKernelGGL(k_theta_from_real, dim3((N + 255) / 256, s.nlam * s.ntgt), dim3(256), 0, ctx->stream, s.X64,
                      N, L, Np, s.ntgt, theta_out);
   FK_HIP(hipGetLastError());

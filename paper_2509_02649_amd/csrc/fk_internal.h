@@ -200,6 +200,9 @@ struct fk_ctx {
   std::map<std::pair<int, uint64_t>, std::pair<fk::EsPlan, double*>> es_cache;
   // the same plans without device tables (for the allocation-free entry point)
   std::map<std::pair<int, uint64_t>, fk::EsPlan> es_host_cache;
+  // second stream (default priority) and events of the additive model's overlapped transforms
+  hipStream_t aux_stream = nullptr;
+  hipEvent_t aux_ev[2] = {};
 };
 
 namespace fk {
@@ -211,6 +214,8 @@ fk_status get_es_plan_host(fk_ctx* ctx, int K, EsPlan* plan, int nf_fixed = 0);
 fk_status scratch_init(int device);
 fk_status finish(fk_ctx* ctx, fk_status st, fk_fit_info* info);
 fk_status read_flags(fk_ctx* ctx);
+// the status the host mirror of the flags holds (after a read-back that the caller synchronized)
+fk_status flag_status(const fk_ctx* ctx);
 
 // Type-1 stage.  Computes c_c[q] = sum_j w_cj exp(-i q.x_j) for |q_a| <= K on C
 // channels (channel 0 has weight 1 when `ones_channel`), written as complex128
