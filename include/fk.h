@@ -155,9 +155,11 @@ fk_status fk_gram(fk_ctx* ctx, int d, int64_t n, fk_dtype dtype, const void* X, 
  * fk_solve: theta[l][t] = (Sigma + lambda_l M^*M)^-1 b[t] for every lambda in `lambdas`
  * (host array, nlam >= 1, each > 0) and every right-hand side t (eq. kenrel_reg), from
  * the generator M (device, complex128 (4m+1)^d) and b (device, complex128 ntgt x N).
- * The Hermitian system is solved in its equivalent real cosine/sine form by an FP32
- * blocked Cholesky (MFMA) per lambda, batched over lambda, with FP64 iterative
- * refinement.  theta_out: device complex128 [nlam][ntgt][N].
+ * The Hermitian system is solved in its equivalent real cosine/sine form by a blocked
+ * Cholesky of its diagonally equilibrated FP32 matrix per lambda, batched over lambda
+ * (finished panels kept as pairs of FP16 halves, about 22 significant bits, their
+ * products accumulated in FP32 on the matrix cores), with FP64 iterative refinement.
+ * theta_out: device complex128 [nlam][ntgt][N].
  * The workspace also keeps the factors, the FP64 real-form Gram and the real-form
  * solutions for fk_heldout_mse / fk_fit_backward on the same workspace. */
 fk_status fk_solve_workspace_size(fk_ctx* ctx, int d, int m, int ntgt, int nlam, size_t* bytes);
@@ -259,8 +261,8 @@ fk_status fk_predict_noalloc(fk_ctx* ctx, int d, int m, int ntheta, const double
 size_t fk_predict_noalloc_max_bytes(void);
 
 /* ---------------------------------------------------------------- held-out loss and gradients
- * Kept factors.  fk_solve and fk_fit leave, at the start of their workspace, the FP32 factors of
- * every lambda, the FP64 real-form Gram and the solutions; a successful call (FK_OK or
+ * Kept factors.  fk_solve and fk_fit leave, at the start of their workspace, the factors of
+ * every lambda (in the format above), the FP64 real-form Gram and the solutions; a successful call (FK_OK or
  * FK_ENOCONV) registers that workspace (its address and the shape d, m, nlam, ntgt).  Any later
  * library call that writes a workspace overlapping it (fk_gram, fk_solve, fk_fit, fk_predict,
  * the additive and iterative entry points, from any context) removes the registration, and

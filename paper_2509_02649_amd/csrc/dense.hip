@@ -1,5 +1,6 @@
 // Dense stage: assembly of the normal equations in real cosine/sine form, a
-// batched FP32 blocked Cholesky on MFMA, FP32 triangular solves, and FP64
+// batched blocked Cholesky of FP32 matrices on MFMA (finished panels kept as FP16
+// pairs, products on the FP16 matrix cores), FP32 triangular solves, and FP64
 // iterative refinement (eq. kenrel_reg; the paper's additive model solves the
 // same kind of system directly, Sec. 5 "Complexity").
 //
@@ -17,8 +18,9 @@
 // multiple of 64, padded with the identity (factor) or zeros (FP64 Gram), so the
 // blocked kernels never see a ragged edge.  One FP64 Gram H64 (with any dense,
 // lambda-independent penalty folded in) serves all lambdas; each lambda has its
-// own FP32 matrix, overwritten by its Cholesky factor, and the inverses of its
-// 64 x 64 diagonal blocks.
+// own FP32 matrix, overwritten by its Cholesky factor (FP32 diagonal blocks, the
+// blocks below them as FP16 pairs in the same 32-bit slots), and the inverses of
+// its 64 x 64 diagonal blocks.
 #include "fk_internal.h"
 
 #include <cmath>
@@ -33,6 +35,54 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 constexpr int NB = 64;     // block size of the factorization
 constexpr int LDT = NB + 4; // LDS row stride (floats) of a 64 x 64 tile
+
+// ------------------------------------------------------------------ factor panels as FP16 pairs
+// A finished panel of the factor keeps each entry as two FP16 halves in its 32-bit slot:
+// a = hi + 2^-11 lo with hi = fp16(a) and lo = fp16(2^11 (a - hi)), both rounded to nearest (the
+// splitting of Ootomo and Yokota, 2022, for FP32-accurate products on FP16 matrix units).  The
+// left-looking updates multiply such panels as hi*hi + 2^-11 (hi*lo + lo*hi) with FP32 accumulation,
+// the lo*lo term (2^-22 relative) dropped: about 22 significant bits per operand at the FP16 matrix
+// rate (one v_mfma_f32_16x16x32_f16, 16 cycles, per 16 x 16 x 32 term against eight FP32 16x16x4
+// steps, 256 cycles).  The equilibrated factor's entries are at most 1 in magnitude, far inside the
+// FP16 range, and the scaled lo keeps entries below the FP16 normal range to 2^-35 absolute.
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+constexpr float kSplitScale = 2048.f;
+
+__device__ __forceinline__ uint32_t split_pack(float a) {
+  const _Float16 hi = (_Float16)a;
+  const _Float16 lo = (_Float16)((a - (float)hi) * kSplitScale);
+  return (uint32_t)__builtin_bit_cast(uint16_t, hi) | ((uint32_t)__builtin_bit_cast(uint16_t, lo) << 16);
+}
+
+__device__ __forceinline__ float split_unpack(uint32_t w) {
+  const float hi = (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu));
+  const float lo = (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
+  return fmaf(lo, 1.f / kSplitScale, hi);
+}
+
+// A 64 x 64 split tile in LDS: the hi and the lo halves as two row-major FP16 tiles of 128-byte
+// rows, unpadded (three tiles per workgroup, three workgroups per CU).  The 16-byte chunk j of row r
+// is stored at chunk j ^ sw(r), sw(r) = (r mod 8) ^ (r / 8 mod 2): the 16 rows that one matrix-core
+// operand read touches (16 lanes, 16 bytes each) then fall on distinct banks.
+struct SplitTile {
+  _Float16 hi[NB * NB];
+  _Float16 lo[NB * NB];
+};
+__device__ __forceinline__ int split_off(int r, int c) {   // c: first of 4 (staging) or 8 (reads) columns
+  return r * NB + ((((c >> 3) ^ (r & 7) ^ ((r >> 3) & 1))) << 3) + (c & 7);
+}
+
+// Four packed entries of one tile row (LDS offset off = split_off(row, first column)) into the hi
+// and lo tiles.
+__device__ __forceinline__ void split_stage(SplitTile& T, int off, uint4 v) {
+  uint2 h, o;
+  h.x = (v.x & 0xffffu) | (v.y << 16);
+  h.y = (v.z & 0xffffu) | (v.w << 16);
+  o.x = (v.x >> 16) | (v.y & 0xffff0000u);
+  o.y = (v.z >> 16) | (v.w & 0xffff0000u);
+  *reinterpret_cast<uint2*>(&T.hi[off]) = h;
+  *reinterpret_cast<uint2*>(&T.lo[off]) = o;
+}
 
 // ------------------------------------------------------------------ real-form index maps
 
@@ -320,7 +370,113 @@ __device__ __forceinline__ void store_acc(float* dst, int64_t ld, const floatx4 
       }
 }
 
+// acc[t] += As Bt^T over the 64 k of split tiles (t = 0: B0, t = 1: B1), for the 2 x 2 blocks of
+// 16 x 16 a wave owns (rows 32 (w >> 1).., columns 32 (w & 1)..): hi*hi into acc, hi*lo + lo*hi into
+// accx.  For v_mfma_f32_16x16x32_f16 lane l supplies row l % 16 of A and column l % 16 of B at the
+// 8 k of its lane group l / 16 (the same 8 for both operands); its result layout is the one of
+// the FP32 instruction above.
+template <int NBT>
+__device__ __forceinline__ void mfma_split64(const SplitTile& As, const SplitTile& B0, const SplitTile& B1,
+                                             floatx4 (&acc)[NBT][2][2], floatx4 (&accx)[NBT][2][2]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+  const int li = lane & 15, kq = 8 * (lane >> 4);
+#pragma unroll
+  for (int k = 0; k < NB; k += 32) {
+    half8 ah[2], al[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int o = split_off(r0 + 16 * u + li, k + kq);
+      ah[u] = *reinterpret_cast<const half8*>(&As.hi[o]);
+      al[u] = *reinterpret_cast<const half8*>(&As.lo[o]);
+    }
+#pragma unroll
+    for (int t = 0; t < NBT; ++t) {
+      const SplitTile& Bt = t == 0 ? B0 : B1;
+      half8 bh[2], bl[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int o = split_off(c0 + 16 * u + li, k + kq);
+        bh[u] = *reinterpret_cast<const half8*>(&Bt.hi[o]);
+        bl[u] = *reinterpret_cast<const half8*>(&Bt.lo[o]);
+      }
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+          acc[t][rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[rb], bh[cb], acc[t][rb][cb], 0, 0, 0);
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+          accx[t][rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[rb], bl[cb], accx[t][rb][cb], 0, 0, 0);
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+          accx[t][rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[rb], bh[cb], accx[t][rb][cb], 0, 0, 0);
+    }
+  }
+}
+
+// dst tile -= acc + 2^-11 accx
+__device__ __forceinline__ void store_split_update(float* dst, int64_t ld, const floatx4 (&acc)[2][2],
+                                                   const floatx4 (&accx)[2][2]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = r0 + rb * 16 + 4 * (lane >> 4) + v;
+        const int c = c0 + cb * 16 + (lane & 15);
+        dst[r * ld + c] -= fmaf(accx[rb][cb][v], 1.f / kSplitScale, acc[rb][cb][v]);
+      }
+}
+
+// dst tile = acc as packed FP16 pairs (a finished panel tile of the factor)
+__device__ __forceinline__ void store_acc_split(float* dst, int64_t ld, const floatx4 acc[2][2]) {
+  uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = r0 + rb * 16 + 4 * (lane >> 4) + v;
+        const int c = c0 + cb * 16 + (lane & 15);
+        d[r * ld + c] = split_pack(acc[rb][cb][v]);
+      }
+}
+
 // ------------------------------------------------------------------ Cholesky kernels
+
+// XCD-aware placement of a (rows x nlam) grid launched as one dimension.  The hardware deals the
+// workgroups round-robin over the 8 XCDs (XCD = id mod 8); this bijection gives XCD x the
+// consecutive run of pairs (lambda, row) in the order (lambda mod 8, lambda / 8, row), so that the
+// workgroups of one lambda share one L2, which then holds the column tiles they all read.  Any
+// dealing order gives the same result; only the locality depends on it.
+__device__ __forceinline__ void xcd_place(int rows, int nlam, int* lam, int* row) {
+  const int G = rows * nlam, id = blockIdx.x;
+  const int x = id & 7, slot = id >> 3;
+  int off = 0;   // workgroups dealt to the XCDs before x
+  for (int y = 0; y < x; ++y) off += (G - y + 7) >> 3;
+  const int q = off + slot;
+  int c = 0, base = 0;   // lambda class c = lambda mod 8 holds ceil((nlam - c) / 8) lambdas
+  while (c < 7) {
+    const int n = ((nlam - c + 7) >> 3) * rows;
+    if (q < base + n) break;
+    base += n;
+    ++c;
+  }
+  const int r = q - base;
+  *lam = c + 8 * (r / rows);
+  *row = r % rows;
+}
 
 // 1/x for a positive normal x: hardware reciprocal and two Newton steps
 // (r <- r + r (1 - x r)), a few ulp in FP64.
@@ -335,73 +491,54 @@ __device__ inline double recip64(double x) {
 // The same update for the two block columns kb and kb + 1 at once, over the panels
 // k < kb:  A[i][kb] -= sum L[i][k] L[kb][k]^T  and (i > kb) A[i][kb+1] -= sum
 // L[i][k] L[kb+1][k]^T.  The row panel L[i][.], the bulk of the traffic, is read once
-// for both columns.  One LDS buffer per operand (three tiles, three workgroups per CU);
-// the next k's tiles are loaded into registers while the current ones are multiplied.
-__global__ __launch_bounds__(256) void k_left_update2(float* __restrict__ A, int Np, int kb) {
-  __shared__ __align__(16) float As[NB * LDT];
-  __shared__ __align__(16) float B0[NB * LDT];
-  __shared__ __align__(16) float B1[NB * LDT];
-  const int l = blockIdx.y;
-  const int i = kb + blockIdx.x;
+// for both columns.  The finished panels are FP16 pairs (split tiles in LDS, products on the
+// FP16 matrix cores); one LDS buffer per operand, the next k's tiles loaded into registers
+// while the current ones are multiplied.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_left_update2(float* __restrict__ A,
+                                                                                             int Np, int kb,
+                                                                                             int nlam) {
+  __shared__ __align__(16) SplitTile As;
+  __shared__ __align__(16) SplitTile B0;
+  __shared__ __align__(16) SplitTile B1;
+  int l, i;
+  xcd_place(Np / NB - kb, nlam, &l, &i);
+  i += kb;
   float* Al = A + (size_t)l * Np * Np;
-  const float* Ai = Al + (size_t)i * NB * Np;
-  const float* A0 = Al + (size_t)kb * NB * Np;
-  const float* A1 = Al + (size_t)(kb + 1) * NB * Np;
+  const uint32_t* Ai = reinterpret_cast<const uint32_t*>(Al + (size_t)i * NB * Np);
+  const uint32_t* A0 = reinterpret_cast<const uint32_t*>(Al + (size_t)kb * NB * Np);
+  const uint32_t* A1 = reinterpret_cast<const uint32_t*>(Al + (size_t)(kb + 1) * NB * Np);
   int off_g[4], off_s[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int idx = threadIdx.x + q * 256, r = idx / (NB / 4), c = (idx % (NB / 4)) * 4;
     off_g[q] = r * Np + c;
-    off_s[q] = r * LDT + c;
+    off_s[q] = split_off(r, c);
   }
-  float4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3, rc0, rc1, rc2, rc3;
-#define FK_GLOAD3(k)                                                                 \
-  do {                                                                               \
-    const float* pa = Ai + (k) * NB;                                                 \
-    const float* pb = A0 + (k) * NB;                                                 \
-    const float* pc = A1 + (k) * NB;                                                 \
-    ra0 = *reinterpret_cast<const float4*>(pa + off_g[0]);                            \
-    ra1 = *reinterpret_cast<const float4*>(pa + off_g[1]);                            \
-    ra2 = *reinterpret_cast<const float4*>(pa + off_g[2]);                            \
-    ra3 = *reinterpret_cast<const float4*>(pa + off_g[3]);                            \
-    rb0 = *reinterpret_cast<const float4*>(pb + off_g[0]);                            \
-    rb1 = *reinterpret_cast<const float4*>(pb + off_g[1]);                            \
-    rb2 = *reinterpret_cast<const float4*>(pb + off_g[2]);                            \
-    rb3 = *reinterpret_cast<const float4*>(pb + off_g[3]);                            \
-    rc0 = *reinterpret_cast<const float4*>(pc + off_g[0]);                            \
-    rc1 = *reinterpret_cast<const float4*>(pc + off_g[1]);                            \
-    rc2 = *reinterpret_cast<const float4*>(pc + off_g[2]);                            \
-    rc3 = *reinterpret_cast<const float4*>(pc + off_g[3]);                            \
-  } while (0)
-#define FK_SSTORE3()                                                                 \
-  do {                                                                               \
-    *reinterpret_cast<float4*>(&As[off_s[0]]) = ra0;                                  \
-    *reinterpret_cast<float4*>(&As[off_s[1]]) = ra1;                                  \
-    *reinterpret_cast<float4*>(&As[off_s[2]]) = ra2;                                  \
-    *reinterpret_cast<float4*>(&As[off_s[3]]) = ra3;                                  \
-    *reinterpret_cast<float4*>(&B0[off_s[0]]) = rb0;                                  \
-    *reinterpret_cast<float4*>(&B0[off_s[1]]) = rb1;                                  \
-    *reinterpret_cast<float4*>(&B0[off_s[2]]) = rb2;                                  \
-    *reinterpret_cast<float4*>(&B0[off_s[3]]) = rb3;                                  \
-    *reinterpret_cast<float4*>(&B1[off_s[0]]) = rc0;                                  \
-    *reinterpret_cast<float4*>(&B1[off_s[1]]) = rc1;                                  \
-    *reinterpret_cast<float4*>(&B1[off_s[2]]) = rc2;                                  \
-    *reinterpret_cast<float4*>(&B1[off_s[3]]) = rc3;                                  \
-  } while (0)
-  floatx4 acc0[2][2] = {}, acc1[2][2] = {};
-  FK_GLOAD3(0);
+  uint4 ra[4], rb[4], rc[4];
+  auto gload = [&](int k) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ra[q] = *reinterpret_cast<const uint4*>(Ai + k * NB + off_g[q]);
+      rb[q] = *reinterpret_cast<const uint4*>(A0 + k * NB + off_g[q]);
+      rc[q] = *reinterpret_cast<const uint4*>(A1 + k * NB + off_g[q]);
+    }
+  };
+  floatx4 acc[2][2][2] = {}, accx[2][2][2] = {};
+  gload(0);
   for (int k = 0; k < kb; ++k) {
-    FK_SSTORE3();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      split_stage(As, off_s[q], ra[q]);
+      split_stage(B0, off_s[q], rb[q]);
+      split_stage(B1, off_s[q], rc[q]);
+    }
     __syncthreads();
-    if (k + 1 < kb) FK_GLOAD3(k + 1);
-    mfma_tile64(As, B0, acc0);
-    mfma_tile64(As, B1, acc1);
+    if (k + 1 < kb) gload(k + 1);
+    mfma_split64<2>(As, B0, B1, acc, accx);
     __syncthreads();
   }
-#undef FK_GLOAD3
-#undef FK_SSTORE3
-  store_acc(Al + (size_t)i * NB * Np + kb * NB, Np, acc0, true, -1.0f);
-  if (i > kb) store_acc(Al + (size_t)i * NB * Np + (kb + 1) * NB, Np, acc1, true, -1.0f);
+  store_split_update(Al + (size_t)i * NB * Np + kb * NB, Np, acc[0], accx[0]);
+  if (i > kb) store_split_update(Al + (size_t)i * NB * Np + (kb + 1) * NB, Np, acc[1], accx[1]);
 }
 
 // Factor the diagonal block kb of every lambda (one workgroup per lambda) in FP64;
@@ -509,10 +646,11 @@ __global__ __launch_bounds__(256) void k_potrf_diag(float* __restrict__ A, int N
 
 // Panel: L[i][kb] = A[i][kb] * inv(L_kk)^T for block rows i > kb.
 __global__ __launch_bounds__(256) void k_trsm_panel(float* __restrict__ A, int Np, int kb,
-                                                    const float* __restrict__ Linv) {
+                                                    const float* __restrict__ Linv, int nlam) {
   __shared__ float As[NB * LDT], Bs[NB * LDT];
-  const int l = blockIdx.y;
-  const int ib = kb + 1 + blockIdx.x;
+  int l, ib;
+  xcd_place(Np / NB - kb - 1, nlam, &l, &ib);
+  ib += kb + 1;
   float* Al = A + (size_t)l * Np * Np;
   float* src = Al + (size_t)ib * NB * Np + kb * NB;
   load_tile(As, src, Np);
@@ -521,70 +659,52 @@ __global__ __launch_bounds__(256) void k_trsm_panel(float* __restrict__ A, int N
   __syncthreads();
   floatx4 acc[2][2] = {};
   mfma_tile64(As, Bs, acc);
-  store_acc(src, Np, acc, false, 1.0f);
+  store_acc_split(src, Np, acc);   // finished: FP16 pairs for the updates and the solves
 }
 
 // Left-looking update of block column kb for every lambda (grid.y):
 //   A[i][kb] -= sum_{k0 <= k < k1} L[i][k] L[kb][k]^T,   i = kb + blockIdx.x,
-// the K loop over the finished panels streamed through double-buffered LDS (the next
-// pair of tiles is loaded into registers while the current pair is on the matrix
-// cores).
-__global__ __launch_bounds__(256) void k_left_update(float* __restrict__ A, int Np, int kb, int k0, int k1) {
-  __shared__ __align__(16) float As[2][NB * LDT];
-  __shared__ __align__(16) float Bs[2][NB * LDT];
-  const int l = blockIdx.y;
-  const int i = kb + blockIdx.x;
+// the K loop over the finished panels (FP16 pairs, split tiles in LDS) with the next pair of
+// tiles loaded into registers while the current pair is on the matrix cores.
+__global__ __launch_bounds__(256) void k_left_update(float* __restrict__ A, int Np, int kb, int k0, int k1,
+                                                     int nlam) {
+  __shared__ __align__(16) SplitTile As;
+  __shared__ __align__(16) SplitTile Bs;
+  int l, i;
+  xcd_place(Np / NB - kb, nlam, &l, &i);
+  i += kb;
   float* Al = A + (size_t)l * Np * Np;
-  const float* Ai = Al + (size_t)i * NB * Np;
-  const float* Ak = Al + (size_t)kb * NB * Np;
-  constexpr int PER = NB * NB / 4 / 256;   // float4 per thread per tile
-  int off_g[PER], off_s[PER];
+  const uint32_t* Ai = reinterpret_cast<const uint32_t*>(Al + (size_t)i * NB * Np);
+  const uint32_t* Ak = reinterpret_cast<const uint32_t*>(Al + (size_t)kb * NB * Np);
+  int off_g[4], off_s[4];
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
+  for (int q = 0; q < 4; ++q) {
     const int idx = threadIdx.x + q * 256, r = idx / (NB / 4), c = (idx % (NB / 4)) * 4;
     off_g[q] = r * Np + c;
-    off_s[q] = r * LDT + c;
+    off_s[q] = split_off(r, c);
   }
-  float4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
-  static_assert(PER == 4, "four float4 per thread per tile");
-#define FK_GLOAD(k)                                                                  \
-  do {                                                                               \
-    const float* pa = Ai + (k) * NB;                                                 \
-    const float* pb = Ak + (k) * NB;                                                 \
-    ra0 = *reinterpret_cast<const float4*>(pa + off_g[0]);                            \
-    ra1 = *reinterpret_cast<const float4*>(pa + off_g[1]);                            \
-    ra2 = *reinterpret_cast<const float4*>(pa + off_g[2]);                            \
-    ra3 = *reinterpret_cast<const float4*>(pa + off_g[3]);                            \
-    rb0 = *reinterpret_cast<const float4*>(pb + off_g[0]);                            \
-    rb1 = *reinterpret_cast<const float4*>(pb + off_g[1]);                            \
-    rb2 = *reinterpret_cast<const float4*>(pb + off_g[2]);                            \
-    rb3 = *reinterpret_cast<const float4*>(pb + off_g[3]);                            \
-  } while (0)
-#define FK_SSTORE(buf)                                                               \
-  do {                                                                               \
-    *reinterpret_cast<float4*>(&As[buf][off_s[0]]) = ra0;                             \
-    *reinterpret_cast<float4*>(&As[buf][off_s[1]]) = ra1;                             \
-    *reinterpret_cast<float4*>(&As[buf][off_s[2]]) = ra2;                             \
-    *reinterpret_cast<float4*>(&As[buf][off_s[3]]) = ra3;                             \
-    *reinterpret_cast<float4*>(&Bs[buf][off_s[0]]) = rb0;                             \
-    *reinterpret_cast<float4*>(&Bs[buf][off_s[1]]) = rb1;                             \
-    *reinterpret_cast<float4*>(&Bs[buf][off_s[2]]) = rb2;                             \
-    *reinterpret_cast<float4*>(&Bs[buf][off_s[3]]) = rb3;                             \
-  } while (0)
-  floatx4 acc[2][2] = {};
-  FK_GLOAD(k0);
-  FK_SSTORE(0);
-  __syncthreads();
+  uint4 ra[4], rb[4];
+  auto gload = [&](int k) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ra[q] = *reinterpret_cast<const uint4*>(Ai + k * NB + off_g[q]);
+      rb[q] = *reinterpret_cast<const uint4*>(Ak + k * NB + off_g[q]);
+    }
+  };
+  floatx4 acc[1][2][2] = {}, accx[1][2][2] = {};
+  gload(k0);
   for (int k = k0; k < k1; ++k) {
-    const int cur = (k - k0) & 1;
-    if (k + 1 < k1) FK_GLOAD(k + 1);
-    mfma_tile64(As[cur], Bs[cur], acc);
-    if (k + 1 < k1) FK_SSTORE(cur ^ 1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      split_stage(As, off_s[q], ra[q]);
+      split_stage(Bs, off_s[q], rb[q]);
+    }
+    __syncthreads();
+    if (k + 1 < k1) gload(k + 1);
+    mfma_split64<1>(As, Bs, Bs, acc, accx);
     __syncthreads();
   }
-#undef FK_GLOAD
-#undef FK_SSTORE
-  store_acc(Al + (size_t)i * NB * Np + kb * NB, Np, acc, true, -1.0f);
+  store_split_update(Al + (size_t)i * NB * Np + kb * NB, Np, acc[0], accx[0]);
 }
 
 // ------------------------------------------------------------------ triangular solves (FP32)
@@ -610,14 +730,15 @@ __device__ __forceinline__ void mfma_64xK(const float* Ls, const float (*Bs)[LDB
   }
 }
 
-// One 64 x 64 FP32 tile in four float4 registers per thread (256 threads: thread t
-// holds float4 number t + 256 u of the row-major tile), for loading the next tile of a
-// sweep while the current one is on the matrix cores.
+// One 64 x 64 tile of a finished panel (FP16 pairs) in four uint4 registers per thread
+// (256 threads: thread t holds the four entries number t + 256 u of the row-major tile),
+// for loading the next tile of a sweep while the current one is on the matrix cores; the
+// staging into LDS unpacks it to FP32.
 #define FK_TILE_FETCH(src, ld)                                                               \
   do {                                                                                       \
     _Pragma("unroll") for (int u_ = 0; u_ < 4; ++u_) {                                       \
       const int i_ = threadIdx.x + 256 * u_, r_ = i_ / (NB / 4), c_ = (i_ - r_ * (NB / 4)) * 4; \
-      const float4 v_ = *reinterpret_cast<const float4*>((src) + r_ * (ld) + c_);          \
+      const uint4 v_ = *reinterpret_cast<const uint4*>((src) + r_ * (ld) + c_);            \
       if (u_ == 0) nt0 = v_;                                                                 \
       if (u_ == 1) nt1 = v_;                                                                 \
       if (u_ == 2) nt2 = v_;                                                                 \
@@ -628,7 +749,9 @@ __device__ __forceinline__ void mfma_64xK(const float* Ls, const float (*Bs)[LDB
   do {                                                                                       \
     _Pragma("unroll") for (int u_ = 0; u_ < 4; ++u_) {                                       \
       const int i_ = threadIdx.x + 256 * u_, r_ = i_ / (NB / 4), c_ = (i_ - r_ * (NB / 4)) * 4; \
-      *reinterpret_cast<float4*>((T) + r_ * LDT + c_) = u_ == 0 ? nt0 : u_ == 1 ? nt1 : u_ == 2 ? nt2 : nt3; \
+      const uint4 q_ = u_ == 0 ? nt0 : u_ == 1 ? nt1 : u_ == 2 ? nt2 : nt3;                 \
+      *reinterpret_cast<float4*>((T) + r_ * LDT + c_) =                                      \
+          make_float4(split_unpack(q_.x), split_unpack(q_.y), split_unpack(q_.z), split_unpack(q_.w)); \
     }                                                                                        \
   } while (0)
 
@@ -654,7 +777,7 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const float* __restrict__ A, i
   }
   load_tile(Ls[0], Linv + ((size_t)l * nb + kb) * NB * NB, NB);
   int ib = kb + 1 + blockIdx.x;
-  float4 nt0, nt1, nt2, nt3;
+  uint4 nt0, nt1, nt2, nt3;
   if (ib < nb) FK_TILE_FETCH(Al + (size_t)ib * NB * Np + kb * NB, Np);
   __syncthreads();
   floatx4 acc[NCT];
@@ -723,7 +846,7 @@ __global__ __launch_bounds__(256) void k_bwd_mfma(const float* __restrict__ A, i
   }
   load_tile(Ls[0], Linv + ((size_t)l * nb + kb) * NB * NB, NB);
   int jb = blockIdx.x;
-  float4 nt0, nt1, nt2, nt3;
+  uint4 nt0, nt1, nt2, nt3;
   if (jb < kb) FK_TILE_FETCH(Ak + jb * NB, Np);
   __syncthreads();
   floatx4 acc[NCT];
@@ -1005,21 +1128,24 @@ static fk_status factor_all(fk_ctx* ctx, const SolveLayout& s, const DenseShape&
     hipLaunchKernelGGL(k_potrf_diag, dim3(s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv, ctx->flags);
     const int rem = nb - kb - 1;
     if (rem > 0)
-      hipLaunchKernelGGL(k_trsm_panel, dim3(rem, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv);
+      hipLaunchKernelGGL(k_trsm_panel, dim3(rem * s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv,
+                         s.nlam);
   };
   // Block columns in pairs (kb, kb + 1): one pass over the panels k < kb updates both,
   // then column kb is finished, then column kb + 1 takes its remaining term k = kb.
   for (int kb = 0; kb < nb;) {
     if (sh.pair && kb > 0 && kb + 1 < nb) {
-      hipLaunchKernelGGL(k_left_update2, dim3(nb - kb, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb);
+      hipLaunchKernelGGL(k_left_update2, dim3((nb - kb) * s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb,
+                         s.nlam);
       finish(kb);
-      hipLaunchKernelGGL(k_left_update, dim3(nb - kb - 1, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb + 1,
-                         kb, kb + 1);
+      hipLaunchKernelGGL(k_left_update, dim3((nb - kb - 1) * s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np,
+                         kb + 1, kb, kb + 1, s.nlam);
       finish(kb + 1);
       kb += 2;
     } else {
       if (kb > 0)
-        hipLaunchKernelGGL(k_left_update, dim3(nb - kb, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, 0, kb);
+        hipLaunchKernelGGL(k_left_update, dim3((nb - kb) * s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, 0,
+                           kb, s.nlam);
       finish(kb);
       kb += 1;
     }
