@@ -543,27 +543,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 
 // Factor the diagonal block kb of every lambda (one workgroup per lambda) in FP64;
 // write L_kk (lower) back and inv(L_kk) to Linv[l][kb].
-// Thread (r, q) = (tid / 4, tid % 4) keeps entries r, q + 4u (u = 0..15) of the block
-// in registers.  Right-looking, unscaled: at step j column j has received every update,
-// its owners publish it to P[.][j] (never written again), one barrier, and each row
-// below applies a[r][k] -= P[r][j] P[k][j] / P[j][j].  Then L[r][c] = P[r][c] / sqrt(P[c][c]).
-// The inverse X = inv(L) uses T = diag(sqrt P) X, which obeys
-// T[i][c] = delta_ic - sum_{k<i} (P[i][k] / P[k][k]) T[k][c]: the same right-looking
-// sweep over rows, each finished row published to a two-slot LDS buffer.
+// Thread (r, q) = (tid / 4, tid % 4) keeps entries r, q + 4u (u = 0..15) of the block, and
+// of T below, in registers.  Right-looking, unscaled: at step j column j has received every
+// update, its owners publish it to P[.][j] (never written again), one barrier, and each row
+// below applies a[r][k] -= f P[k][j] with f = P[r][j] / P[j][j].  Then L[r][c] = P[r][c] /
+// sqrt(P[c][c]).  The same row operations turn the identity into T = diag(sqrt P) inv(L):
+// T[i][c] = delta_ic - sum_{k<i} (P[i][k] / P[k][k]) T[k][c], so row j of T is final at step j,
+// is published with column j (two-slot LDS buffer), and rows r > j take t[r][.] -= f T[j][.]
+// in the same step: one sweep of 64 barriers for the factor and its inverse.
 __global__ __launch_bounds__(256) void k_potrf_diag(float* __restrict__ A, int Np, int kb,
                                                     float* __restrict__ Linv, int* flags) {
   __shared__ double P[NB][NB + 1];
   __shared__ double trow[2][NB];
-  __shared__ double piv[NB], rpiv[NB], sq[NB], rsq[NB];
+  __shared__ double piv[NB], sq[NB], rsq[NB];
   __shared__ int bad;
   const int l = blockIdx.x;
   float* Ab = A + (size_t)l * Np * Np + (size_t)kb * NB * Np + kb * NB;
   const int r = threadIdx.x >> 2, q = threadIdx.x & 3;
-  double a[16];
+  double a[16], t[16];
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int k = 4 * u + q;
     a[u] = (k <= r) ? (double)Ab[(size_t)r * Np + k] : 0.0;
+    t[u] = (k == r) ? 1.0 : 0.0;
   }
   if (threadIdx.x == 0) bad = 0;
   // unrolled, so that the register holding column j is known at compile time
@@ -576,48 +578,40 @@ __global__ __launch_bounds__(256) void k_potrf_diag(float* __restrict__ A, int N
         if (u == (j >> 2)) v = a[u];
       P[r][j] = v;
     }
+    if (r == j) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) trow[j & 1][4 * u + q] = t[u];
+    }
     __syncthreads();
     // all loads first and unconditionally (rows k < j of P[.][j] are not yet written:
     // their values are discarded by the select), so the reads share one wait
     const double pj = P[j][j];
     const double prj = P[r][j];
-    double pk[16];
+    double pk[16], tv[16];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) pk[u] = P[4 * u + q][j];
+    for (int u = 0; u < 16; ++u) {
+      pk[u] = P[4 * u + q][j];
+      tv[u] = trow[j & 1][4 * u + q];
+    }
     const bool badj = !(pj > 0.0);  // non-positive or NaN pivot
     const double rp = recip64(badj ? 1.0 : pj);
-    const double f = prj * rp;
+    const double f = r > j ? prj * rp : 0.0;
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int k = 4 * u + q;
       const double upd = fma(-f, pk[u], a[u]);
       a[u] = (k > j && k <= r) ? upd : a[u];
+      t[u] = fma(-f, tv[u], t[u]);   // T[j][c] = 0 for c > j: no change there
     }
     if (threadIdx.x == 0) {
       piv[j] = badj ? 1.0 : pj;
-      rpiv[j] = rp;
       if (badj) bad = 1;
     }
   }
-  // inverse: a[] now holds T[r][q + 4u]
+  // t[] holds T[r][q + 4u]
 #pragma unroll
-  for (int u = 0; u < 16; ++u) a[u] = (4 * u + q == r) ? 1.0 : 0.0;
-  for (int j = 0; j < NB; ++j) {
-    if (r == j) {
-#pragma unroll
-      for (int u = 0; u < 16; ++u) trow[j & 1][4 * u + q] = a[u];
-    }
-    __syncthreads();
-    // row j of T is zero beyond its diagonal, so columns c > j take a zero update
-    if (r > j) {
-      const double g = P[r][j] * rpiv[j];
-      double tv[16];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) tv[u] = trow[j & 1][4 * u + q];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) a[u] = fma(-g, tv[u], a[u]);
-    }
-  }
+  for (int u = 0; u < 16; ++u) a[u] = t[u];
+  __syncthreads();   // the last pivot (thread 0, after the last step's barrier)
   if (threadIdx.x < NB) {
     const double d = sqrt(piv[threadIdx.x]);
     sq[threadIdx.x] = d;
