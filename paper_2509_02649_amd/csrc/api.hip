@@ -57,6 +57,7 @@ extern "C" fk_status fk_destroy(fk_ctx* ctx) {
   }
   hipFree(ctx->flags);
   hipHostFree(ctx->flags_host);
+  if (ctx->stage) hipHostFree(ctx->stage);
   for (auto& e : ctx->ev) hipEventDestroy(e);
   delete ctx;
   return FK_OK;
@@ -99,6 +100,36 @@ fk_status reset_flags(fk_ctx* ctx) {
   int init[kFlagCount] = {0, 0, 0, 0x7fffffff, 0, 0x7fffffff, 0, 0};
   std::memcpy(ctx->flags_host, init, sizeof(init));
   FK_HIP(hipMemcpyAsync(ctx->flags, ctx->flags_host, sizeof(init), hipMemcpyHostToDevice, ctx->stream));
+  return FK_OK;
+}
+
+void* stage_take(fk_ctx* ctx, size_t bytes) {
+  bytes = (bytes + 15) & ~size_t(15);
+  if (ctx->stage_off + bytes > ctx->stage_cap) {
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return nullptr;
+    ctx->stage_off = 0;
+    if (bytes > ctx->stage_cap) {
+      const size_t cap = std::max(bytes, (size_t)4 << 20);
+      if (ctx->stage) hipHostFree(ctx->stage);
+      ctx->stage = nullptr;
+      ctx->stage_cap = 0;
+      void* p = nullptr;
+      if (hipHostMalloc(&p, cap, hipHostMallocDefault) != hipSuccess) return nullptr;
+      ctx->stage = static_cast<char*>(p);
+      ctx->stage_cap = cap;
+    }
+  }
+  void* p = ctx->stage + ctx->stage_off;
+  ctx->stage_off += bytes;
+  return p;
+}
+
+fk_status stage_upload(fk_ctx* ctx, void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return FK_OK;
+  void* h = stage_take(ctx, bytes);
+  if (!h) return FK_EHIP;
+  std::memcpy(h, src, bytes);
+  FK_HIP(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, ctx->stream));
   return FK_OK;
 }
 

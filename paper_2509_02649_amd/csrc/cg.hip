@@ -703,8 +703,9 @@ fk_status cg_solve_impl(fk_ctx* ctx, int d, int m, const double* M, int ntgt, co
     cl.mu = mu;
     cl.mu_m0r = mu * m0r;
   }
-  FK_HIP(hipMemcpyAsync(dpw, pw.data(), sizeof(double) * g.N, hipMemcpyHostToDevice, st));
-  FK_HIP(hipMemcpyAsync(dlam, lams.data(), sizeof(double) * nlam, hipMemcpyHostToDevice, st));
+  s = stage_upload(ctx, dpw, pw.data(), sizeof(double) * g.N);
+  if (s == FK_OK) s = stage_upload(ctx, dlam, lams.data(), sizeof(double) * nlam);
+  if (s != FK_OK) return s;
 
   s = build_spectrum(st, g, M, spec);
   if (s == FK_OK && colloc) s = build_spectrum(st, g, Mr, spec_r);

@@ -1200,7 +1200,9 @@ static fk_status refine_solve(fk_ctx* ctx, const SolveLayout& s, const DenseShap
   hipLaunchKernelGGL(k_colnorm2, dim3(nc), dim3(256), 0, ctx->stream, s.R64, s.Np, s.norms + nc);
   const int maxit = ctx->opt.max_refine;
   const double tol = ctx->opt.refine_tol;
-  std::vector<double> nh(2 * nc);
+  // the norms come back through the context's pinned staging area (an asynchronous copy)
+  double* nh = static_cast<double*>(stage_take(ctx, sizeof(double) * 2 * nc));
+  if (!nh) return FK_EHIP;
   int it = 0;
   double worst = 0.0;
   int bad = -1;
@@ -1216,7 +1218,7 @@ static fk_status refine_solve(fk_ctx* ctx, const SolveLayout& s, const DenseShap
                  s.preal, s.lams, s.R64);
     FK_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_colnorm2, dim3(nc), dim3(256), 0, ctx->stream, s.R64, s.Np, s.norms);
-    FK_HIP(hipMemcpyAsync(nh.data(), s.norms, sizeof(double) * 2 * nc, hipMemcpyDeviceToHost, ctx->stream));
+    FK_HIP(hipMemcpyAsync(nh, s.norms, sizeof(double) * 2 * nc, hipMemcpyDeviceToHost, ctx->stream));
     if (check_flags)
       FK_HIP(hipMemcpyAsync(ctx->flags_host, ctx->flags, sizeof(int) * kFlagCount, hipMemcpyDeviceToHost,
                             ctx->stream));
@@ -1340,8 +1342,9 @@ fk_status solve_impl(fk_ctx* ctx, const SolveProblem& P, const SolveLayout& s, d
   hipEvent_t* ev = ctx->ev;
   FK_HIP(hipEventRecord(ev[5], ctx->stream));
   // penalty weights (complex modes) -> device, real-form weights
-  FK_HIP(hipMemcpyAsync(s.pcx, P.p.data(), sizeof(double) * N, hipMemcpyHostToDevice, ctx->stream));
-  FK_HIP(hipMemcpyAsync(s.lams, P.lams.data(), sizeof(double) * s.nlam, hipMemcpyHostToDevice, ctx->stream));
+  fk_status up = stage_upload(ctx, s.pcx, P.p.data(), sizeof(double) * N);
+  if (up == FK_OK) up = stage_upload(ctx, s.lams, P.lams.data(), sizeof(double) * s.nlam);
+  if (up != FK_OK) return up;
   FK_HIP(hipMemsetAsync(s.preal, 0, sizeof(double) * Np, ctx->stream));
   hipLaunchKernelGGL(k_real_weights, dim3((N + 255) / 256), dim3(256), 0, ctx->stream, s.pcx, N, L, s.preal);
   // FP64 real-form Gram (+ dense lambda-independent penalty)
@@ -1351,7 +1354,8 @@ fk_status solve_impl(fk_ctx* ctx, const SolveProblem& P, const SolveLayout& s, d
     ToeplitzQ q{P.M, P.m, P.d};
     hipLaunchKernelGGL(k_assemble_real<ToeplitzQ>, dim3(gb), dim3(256), 0, ctx->stream, q, N, L, Np, s.H64);
   } else if (P.kind == SolveProblem::kToeplitzPde) {
-    FK_HIP(hipMemcpyAsync(s.dsym, P.dsym.data(), sizeof(double) * 2 * N, hipMemcpyHostToDevice, ctx->stream));
+    up = stage_upload(ctx, s.dsym, P.dsym.data(), sizeof(double) * 2 * N);
+    if (up != FK_OK) return up;
     using PQ = SumQ<ToeplitzQ, PdeQ>;
     PQ q{ToeplitzQ{P.M, P.m, P.d}, PdeQ{s.dsym, P.m, P.d, P.mu, P.lo[0], P.hi[0], P.lo[1], P.hi[1]}};
     hipLaunchKernelGGL(k_assemble_real<PQ>, dim3(gb), dim3(256), 0, ctx->stream, q, N, L, Np, s.H64);

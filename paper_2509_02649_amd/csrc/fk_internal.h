@@ -203,6 +203,9 @@ struct fk_ctx {
   // second stream (default priority) and events of the additive model's overlapped transforms
   hipStream_t aux_stream = nullptr;
   hipEvent_t aux_ev[2] = {};
+  // pinned host staging area for small uploads and read-backs on the context's stream
+  char* stage = nullptr;
+  size_t stage_cap = 0, stage_off = 0;
 };
 
 namespace fk {
@@ -214,6 +217,12 @@ fk_status get_es_plan_host(fk_ctx* ctx, int K, EsPlan* plan, int nf_fixed = 0);
 fk_status scratch_init(int device);
 fk_status finish(fk_ctx* ctx, fk_status st, fk_fit_info* info);
 fk_status read_flags(fk_ctx* ctx);
+// `bytes` of the context's pinned staging area (16-byte aligned), for an asynchronous copy on the
+// context's stream; nullptr on failure.  Space is handed out in order; when the area is full the
+// stream is synchronized (every copy through it has then completed) and it restarts, grown if needed.
+void* stage_take(fk_ctx* ctx, size_t bytes);
+// Upload of a small host array through the staging area (asynchronous on the context's stream).
+fk_status stage_upload(fk_ctx* ctx, void* dst, const void* src, size_t bytes);
 // the status the host mirror of the flags holds (after a read-back that the caller synchronized)
 fk_status flag_status(const fk_ctx* ctx);
 
