@@ -1020,15 +1020,36 @@ __global__ __launch_bounds__(256) void k_resid64_narrow(const double* __restrict
 
 static void launch_resid(hipStream_t st, const double* H, int N, int Np, const double* X, int ncols, int ntgt,
                          int rhs_per_col, const double* Bre, const double* preal, const double* lams, double* R) {
-  if (ncols <= NARROW)
+  if (ncols <= NARROW) {
     hipLaunchKernelGGL(k_resid64_narrow, dim3((Np + 3) / 4), dim3(256), 0, st, H, N, Np, X, ncols, ntgt,
                        rhs_per_col, Bre, preal, lams, R);
-  else if (ncols <= 256)
-    hipLaunchKernelGGL(k_resid64_mfma<2>, dim3(Np / 64, (ncols + 63) / 64), dim3(256), 0, st, H, N, Np, X, ncols,
-                       ntgt, rhs_per_col, Bre, preal, lams, R);
+    return;
+  }
+  // Column tile of 32 WN: the one with the fewest tile columns per CU, counting every CU's last
+  // round as full (ceil(tiles / 256 CUs) rounds x TN columns of work each); ties to the wider tile,
+  // which reuses each loaded H value more.  For 1024 columns: WN = 3 (737 tiles, 3 rounds x 96)
+  // against WN = 4 (536 tiles, 3 rounds x 128).
+  int best_wn = 4;
+  long best = -1;
+  for (int wn = 4; wn >= 2; --wn) {
+    const long tiles = (long)(Np / 64) * ((ncols + 32 * wn - 1) / (32 * wn));
+    const long cost = (tiles + 255) / 256 * (32 * wn);
+    if (best < 0 || cost < best) {
+      best = cost;
+      best_wn = wn;
+    }
+  }
+  const int TN = 32 * best_wn;
+  const dim3 grid(Np / 64, (ncols + TN - 1) / TN);
+  if (best_wn == 4)
+    hipLaunchKernelGGL(k_resid64_mfma<4>, grid, dim3(256), 0, st, H, N, Np, X, ncols, ntgt, rhs_per_col, Bre, preal,
+                       lams, R);
+  else if (best_wn == 3)
+    hipLaunchKernelGGL(k_resid64_mfma<3>, grid, dim3(256), 0, st, H, N, Np, X, ncols, ntgt, rhs_per_col, Bre, preal,
+                       lams, R);
   else
-    hipLaunchKernelGGL(k_resid64_mfma<4>, dim3(Np / 64, (ncols + 127) / 128), dim3(256), 0, st, H, N, Np, X, ncols,
-                       ntgt, rhs_per_col, Bre, preal, lams, R);
+    hipLaunchKernelGGL(k_resid64_mfma<2>, grid, dim3(256), 0, st, H, N, Np, X, ncols, ntgt, rhs_per_col, Bre, preal,
+                       lams, R);
 }
 
 // Column norms squared of Rres and of the right-hand sides (per column), FP64.
