@@ -48,6 +48,35 @@ def test_solver_only_parity(fk, d, m, n, s, lam):
     assert e <= TOL
 
 
+def test_unrefined_solve_is_fp32_class(fk):
+    # The factorization keeps its finished panels as FP16 pairs (about 22 significant bits) and
+    # accumulates their products in FP32.  Without the FP64 refinement (max_refine = 0, any residual
+    # accepted) its solution must be as accurate as an FP32 LAPACK Cholesky solve of the same
+    # equilibrated system: the FP32 accumulation over 2432-long dot products, not the operands'
+    # representation, sets the factor's error.
+    import scipy.linalg as sl
+    m, n = 24, 200_000
+    X = synth.uniform_points(4242, 2, n)
+    Y = synth.batched_targets(X, 4242, ntgt=2)
+    M, b = fk.gram(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(), m)
+    Mh, bh = M.cpu().numpy(), b.cpu().numpy()
+    p = oracle.sobolev_weights(m, 2, 2.0)
+    lams = [1e-2, 1e-4, 1e-6]
+    ctx0 = fk.Context(0, max_refine=0, refine_tol=1e30)
+    th0 = fk.solve(M, b, m, lams, penalty="sobolev", s=2.0, ctx=ctx0).cpu().numpy()
+    for i, lam in enumerate(lams):
+        A = oracle.system_matrix(Mh, m, lam, p)
+        ref = oracle.solve_system(A, bh)
+        dg = 1.0 / np.sqrt(np.diag(A).real)
+        A32 = (dg[:, None] * A * dg[None, :]).astype(np.complex64)
+        c = sl.cho_factor(A32, lower=True)
+        th32 = np.stack([dg * sl.cho_solve(c, (dg * bt).astype(np.complex64)) for bt in bh])
+        e32 = _rel(th32, ref)
+        e0 = _rel(th0[i], ref)
+        print(f"lambda={lam:.0e}: unrefined GPU solve {e0:.2e}, FP32 LAPACK {e32:.2e}")
+        assert e0 <= 2.0 * e32 + 1e-7
+
+
 def test_fit_1d_small_config(fk):
     w = synth.workload_1d()
     X, Y, m = w["X"], w["Y"], w["m"]
