@@ -707,12 +707,14 @@ __global__ __launch_bounds__(256) void k_left_update(float* __restrict__ A, int 
 // MFMA product of a 64 x 64 LDS tile (or its transpose) with a 64 x (16*NCT) LDS
 // block: wave w computes rows 16w..16w+15.  Lane layout as in mfma_tile64.
 constexpr int LDB = 33;   // row stride of the 64 x ncol blocks (ncol <= 32)
-template <bool TRANS, int NCT>
+template <bool TRANS, int NCT, bool ACC = false>
 __device__ __forceinline__ void mfma_64xK(const float* Ls, const float (*Bs)[LDB], floatx4 acc[NCT]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
+  if (!ACC) {
 #pragma unroll
-  for (int ct = 0; ct < NCT; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int ct = 0; ct < NCT; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+  }
 #pragma unroll 4
   for (int k0 = 0; k0 < NB; k0 += 4) {
     const float a = TRANS ? Ls[(k0 + lk) * LDT + 16 * w + li] : Ls[(16 * w + li) * LDT + k0 + lk];
@@ -881,6 +883,194 @@ __global__ __launch_bounds__(256) void k_bwd_mfma(const float* __restrict__ A, i
       }
     if (nx < kb) FK_R_FETCH(nx)
     if (nx < kb) FK_TILE_STAGE(Ls[cur ^ 1]);
+    __syncthreads();
+    cur ^= 1;
+  }
+#undef FK_R_FETCH
+}
+
+
+// Two forward steps kb, kb + 1 in one launch (kb + 1 < nb).  Every workgroup solves the 128-row
+// diagonal part itself: y_kb = inv(L_kk) r_kb, then r_{kb+1} -= L[kb+1][kb] y_kb and y_{kb+1} =
+// inv(L_{kb+1,kb+1}) r_{kb+1}; block 0 writes both blocks of Y.  Block x then updates rows ib = kb + 2
+// + x, kb + 2 + x + gridDim.x, ...: r_ib -= L[ib][kb] y_kb + L[ib][kb+1] y_{kb+1}, the tiles streamed
+// through the two LDS buffers in the order (ib, kb), (ib, kb + 1), (next ib, kb), ... (one barrier
+// per tile).  Half the dependent launches of the one-step sweep.
+template <int NCT>
+__global__ __launch_bounds__(256) void k_fwd2_mfma(const float* __restrict__ A, int Np, int kb,
+                                                   const float* __restrict__ Linv, float* __restrict__ R,
+                                                   float* __restrict__ Y, int ncol) {
+  __shared__ float Ls[2][NB * LDT];
+  __shared__ float Bs[2 * NB][LDB];
+  const int l = blockIdx.y;
+  const int nb = Np / NB;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  float* Rl = R + (size_t)l * ncol * Np;
+  const float* Al = A + (size_t)l * Np * Np;
+  for (int i = threadIdx.x; i < 2 * NB * 16 * NCT; i += blockDim.x) {
+    const int t = i / (2 * NB), k = i - t * (2 * NB);
+    Bs[k][t] = t < ncol ? Rl[(size_t)t * Np + kb * NB + k] : 0.f;
+  }
+  load_tile(Ls[0], Linv + ((size_t)l * nb + kb) * NB * NB, NB);
+  uint4 nt0, nt1, nt2, nt3;
+  FK_TILE_FETCH(Al + (size_t)(kb + 1) * NB * Np + kb * NB, Np);
+  FK_TILE_STAGE(Ls[1]);
+  __syncthreads();
+  floatx4 acc[NCT];
+  mfma_64xK<false, NCT>(Ls[0], Bs, acc);   // y_kb
+  __syncthreads();
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Bs[16 * w + 4 * lk + v][ct * 16 + li] = acc[ct][v];
+  __syncthreads();
+  mfma_64xK<false, NCT>(Ls[1], Bs, acc);   // L[kb+1][kb] y_kb
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Bs[NB + 16 * w + 4 * lk + v][ct * 16 + li] -= acc[ct][v];
+  load_tile(Ls[0], Linv + ((size_t)l * nb + kb + 1) * NB * NB, NB);
+  __syncthreads();
+  mfma_64xK<false, NCT>(Ls[0], Bs + NB, acc);   // y_{kb+1}
+  const int ib0 = kb + 2 + blockIdx.x;
+  if (ib0 < nb) FK_TILE_FETCH(Al + (size_t)ib0 * NB * Np + kb * NB, Np);
+  __syncthreads();
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Bs[NB + 16 * w + 4 * lk + v][ct * 16 + li] = acc[ct][v];
+  if (ib0 < nb) FK_TILE_STAGE(Ls[1]);
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    float* Yl = Y + (size_t)l * ncol * Np;
+    for (int i = threadIdx.x; i < ncol * 2 * NB; i += blockDim.x) {
+      const int t = i / (2 * NB), r = i - t * (2 * NB);
+      Yl[(size_t)t * Np + kb * NB + r] = Bs[r][t];
+    }
+  }
+  float rr[NCT][4];
+#define FK_R_FETCH(RB)                                                                         \
+  _Pragma("unroll") for (int ct = 0; ct < NCT; ++ct) {                                         \
+    const int t_ = min(ct * 16 + li, ncol - 1);                                                \
+    _Pragma("unroll") for (int v = 0; v < 4; ++v)                                              \
+      rr[ct][v] = Rl[(size_t)t_ * Np + (RB) * NB + 16 * w + 4 * lk + v];                       \
+  }
+  if (ib0 < nb) FK_R_FETCH(ib0)
+  int cur = 1;
+  for (int ib = ib0; ib < nb; ib += gridDim.x) {
+    // tile (ib, kb) is in Ls[cur]; (ib, kb + 1) comes next
+    FK_TILE_FETCH(Al + (size_t)ib * NB * Np + (kb + 1) * NB, Np);
+    mfma_64xK<false, NCT>(Ls[cur], Bs, acc);
+    FK_TILE_STAGE(Ls[cur ^ 1]);
+    __syncthreads();
+    cur ^= 1;
+    const int nx = ib + gridDim.x;
+    if (nx < nb) FK_TILE_FETCH(Al + (size_t)nx * NB * Np + kb * NB, Np);
+    mfma_64xK<false, NCT, true>(Ls[cur], Bs + NB, acc);
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int t = ct * 16 + li;
+        if (t < ncol) Rl[(size_t)t * Np + ib * NB + 16 * w + 4 * lk + v] = rr[ct][v] - acc[ct][v];
+      }
+    if (nx < nb) FK_R_FETCH(nx)
+    if (nx < nb) FK_TILE_STAGE(Ls[cur ^ 1]);
+    __syncthreads();
+    cur ^= 1;
+  }
+#undef FK_R_FETCH
+}
+
+// Two backward steps kb, kb - 1 in one launch (kb >= 1): x_kb = inv(L_kk)^T y_kb, then y_{kb-1} -=
+// L[kb][kb-1]^T x_kb and x_{kb-1} = inv(L_{kb-1,kb-1})^T y_{kb-1} in every workgroup (block 0 writes
+// both blocks of X); block x then updates rows jb = x, x + gridDim.x, ... < kb - 1: y_jb -= L[kb][jb]^T
+// x_kb + L[kb-1][jb]^T x_{kb-1}, the two tiles of a row streamed one after the other.
+template <int NCT>
+__global__ __launch_bounds__(256) void k_bwd2_mfma(const float* __restrict__ A, int Np, int kb,
+                                                   const float* __restrict__ Linv, float* __restrict__ Yv,
+                                                   float* __restrict__ X, int ncol) {
+  __shared__ float Ls[2][NB * LDT];
+  __shared__ float Bs[2 * NB][LDB];
+  const int l = blockIdx.y;
+  const int nb = Np / NB;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  float* Yl = Yv + (size_t)l * ncol * Np;
+  const float* Ak = A + (size_t)l * Np * Np + (size_t)kb * NB * Np;         // block row kb
+  const float* Ak1 = A + (size_t)l * Np * Np + (size_t)(kb - 1) * NB * Np;  // block row kb - 1
+  for (int i = threadIdx.x; i < 2 * NB * 16 * NCT; i += blockDim.x) {
+    const int t = i / (2 * NB), k = i - t * (2 * NB);
+    const int row = k < NB ? kb * NB + k : (kb - 1) * NB + (k - NB);
+    Bs[k][t] = t < ncol ? Yl[(size_t)t * Np + row] : 0.f;
+  }
+  load_tile(Ls[0], Linv + ((size_t)l * nb + kb) * NB * NB, NB);
+  uint4 nt0, nt1, nt2, nt3;
+  FK_TILE_FETCH(Ak + (kb - 1) * NB, Np);   // L[kb][kb-1]
+  FK_TILE_STAGE(Ls[1]);
+  __syncthreads();
+  floatx4 acc[NCT];
+  mfma_64xK<true, NCT>(Ls[0], Bs, acc);   // x_kb
+  __syncthreads();
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Bs[16 * w + 4 * lk + v][ct * 16 + li] = acc[ct][v];
+  __syncthreads();
+  mfma_64xK<true, NCT>(Ls[1], Bs, acc);   // L[kb][kb-1]^T x_kb
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Bs[NB + 16 * w + 4 * lk + v][ct * 16 + li] -= acc[ct][v];
+  load_tile(Ls[0], Linv + ((size_t)l * nb + kb - 1) * NB * NB, NB);
+  __syncthreads();
+  mfma_64xK<true, NCT>(Ls[0], Bs + NB, acc);   // x_{kb-1}
+  const int jb0 = blockIdx.x;
+  if (jb0 < kb - 1) FK_TILE_FETCH(Ak + jb0 * NB, Np);
+  __syncthreads();
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Bs[NB + 16 * w + 4 * lk + v][ct * 16 + li] = acc[ct][v];
+  if (jb0 < kb - 1) FK_TILE_STAGE(Ls[1]);
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    float* Xl = X + (size_t)l * ncol * Np;
+    for (int i = threadIdx.x; i < ncol * 2 * NB; i += blockDim.x) {
+      const int t = i / (2 * NB), k = i - t * (2 * NB);
+      const int row = k < NB ? kb * NB + k : (kb - 1) * NB + (k - NB);
+      Xl[(size_t)t * Np + row] = Bs[k][t];
+    }
+  }
+  float rr[NCT][4];
+#define FK_R_FETCH(RB)                                                                         \
+  _Pragma("unroll") for (int ct = 0; ct < NCT; ++ct) {                                         \
+    const int t_ = min(ct * 16 + li, ncol - 1);                                                \
+    _Pragma("unroll") for (int v = 0; v < 4; ++v)                                              \
+      rr[ct][v] = Yl[(size_t)t_ * Np + (RB) * NB + 16 * w + 4 * lk + v];                       \
+  }
+  if (jb0 < kb - 1) FK_R_FETCH(jb0)
+  int cur = 1;
+  for (int jb = jb0; jb < kb - 1; jb += gridDim.x) {
+    // tile (kb, jb) is in Ls[cur]; (kb - 1, jb) comes next
+    FK_TILE_FETCH(Ak1 + jb * NB, Np);
+    mfma_64xK<true, NCT>(Ls[cur], Bs, acc);
+    FK_TILE_STAGE(Ls[cur ^ 1]);
+    __syncthreads();
+    cur ^= 1;
+    const int nx = jb + gridDim.x;
+    if (nx < kb - 1) FK_TILE_FETCH(Ak + nx * NB, Np);
+    mfma_64xK<true, NCT, true>(Ls[cur], Bs + NB, acc);
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int t = ct * 16 + li;
+        if (t < ncol) Yl[(size_t)t * Np + jb * NB + 16 * w + 4 * lk + v] = rr[ct][v] - acc[ct][v];
+      }
+    if (nx < kb - 1) FK_R_FETCH(nx)
+    if (nx < kb - 1) FK_TILE_STAGE(Ls[cur ^ 1]);
     __syncthreads();
     cur ^= 1;
   }
@@ -1175,23 +1365,48 @@ static fk_status trsm_all(fk_ctx* ctx, const SolveLayout& s, const DenseShape& s
   const bool two = s.ntgt > 16;
   // workgroups per lambda: about sh.trsm_wg in all, each sweeping several rows
   const int gmax = std::max(1, sh.trsm_wg / s.nlam);
-  for (int kb = 0; kb < nb; ++kb) {
-    int g = std::max(1, std::min(gmax, nb - kb - 1));
-    if (two)
-      hipLaunchKernelGGL(k_fwd_mfma<2>, dim3(g, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv, R, Y,
-                         s.ntgt);
-    else
-      hipLaunchKernelGGL(k_fwd_mfma<1>, dim3(g, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv, R, Y,
-                         s.ntgt);
+  // two block columns per launch (the last one alone when nb is odd)
+  for (int kb = 0; kb < nb;) {
+    if (kb + 1 < nb) {
+      const int g = std::max(1, std::min(gmax, nb - kb - 2));
+      if (two)
+        hipLaunchKernelGGL(k_fwd2_mfma<2>, dim3(g, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv, R,
+                           Y, s.ntgt);
+      else
+        hipLaunchKernelGGL(k_fwd2_mfma<1>, dim3(g, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv, R,
+                           Y, s.ntgt);
+      kb += 2;
+    } else {
+      const int g = std::max(1, std::min(gmax, nb - kb - 1));
+      if (two)
+        hipLaunchKernelGGL(k_fwd_mfma<2>, dim3(g, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv, R,
+                           Y, s.ntgt);
+      else
+        hipLaunchKernelGGL(k_fwd_mfma<1>, dim3(g, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv, R,
+                           Y, s.ntgt);
+      kb += 1;
+    }
   }
-  for (int kb = nb - 1; kb >= 0; --kb) {
-    int g = std::max(1, std::min(gmax, kb));
-    if (two)
-      hipLaunchKernelGGL(k_bwd_mfma<2>, dim3(g, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv, Y, X,
-                         s.ntgt);
-    else
-      hipLaunchKernelGGL(k_bwd_mfma<1>, dim3(g, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv, Y, X,
-                         s.ntgt);
+  for (int kb = nb - 1; kb >= 0;) {
+    if (kb >= 1) {
+      const int g = std::max(1, std::min(gmax, kb - 1));
+      if (two)
+        hipLaunchKernelGGL(k_bwd2_mfma<2>, dim3(g, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv, Y,
+                           X, s.ntgt);
+      else
+        hipLaunchKernelGGL(k_bwd2_mfma<1>, dim3(g, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv, Y,
+                           X, s.ntgt);
+      kb -= 2;
+    } else {
+      const int g = std::max(1, std::min(gmax, kb));
+      if (two)
+        hipLaunchKernelGGL(k_bwd_mfma<2>, dim3(g, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv, Y,
+                           X, s.ntgt);
+      else
+        hipLaunchKernelGGL(k_bwd_mfma<1>, dim3(g, s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv, Y,
+                           X, s.ntgt);
+      kb -= 1;
+    }
   }
   FK_HIP(hipGetLastError());
   return FK_OK;
