@@ -338,6 +338,9 @@ fk_status fk_additive_fit(fk_ctx* ctx, int d, int64_t n, fk_dtype dtype, const v
  *     points per slice of the second;
  *   - the dense solve with Np^2 nlam >= 2^28 (Np = N rounded up to 64): workgroups per
  *     triangular-solve launch and whether block columns are factored in pairs.
+ * A table entry of a dense shape may also hold diag64=1 (never chosen by the tuner): the 64 x 64
+ * diagonal blocks of the factorization are then factored in FP64 instead of FP32 (slower; the
+ * FP32 default matches an FP32 LAPACK factorization's accuracy).
  * At the first call of a shape without a table entry the library times each candidate (coordinate
  * descent, one knob at a time, on the call's own data; the call then runs with the fastest) and
  * records "<arch> <stage> <shape> = <knob>=<value> ... ms=<time>" in a process-wide table; every

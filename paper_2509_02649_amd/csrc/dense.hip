@@ -487,6 +487,12 @@ __device__ inline double recip64(double x) {
   e = fma(-x, r, 1.0);
   return fma(r, e, r);
 }
+__device__ inline double recip_t(double x) { return recip64(x); }
+// 1/x for a positive normal FP32 x: hardware reciprocal and one Newton step (about 1 ulp).
+__device__ inline float recip_t(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
 
 // The same update for the two block columns kb and kb + 1 at once, over the panels
 // k < kb:  A[i][kb] -= sum L[i][k] L[kb][k]^T  and (i > kb) A[i][kb+1] -= sum
@@ -551,28 +557,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // T[i][c] = delta_ic - sum_{k<i} (P[i][k] / P[k][k]) T[k][c], so row j of T is final at step j,
 // is published with column j (two-slot LDS buffer), and rows r > j take t[r][.] -= f T[j][.]
 // in the same step: one sweep of 64 barriers for the factor and its inverse.
+template <typename Real>
 __global__ __launch_bounds__(256) void k_potrf_diag(float* __restrict__ A, int Np, int kb,
                                                     float* __restrict__ Linv, int* flags) {
-  __shared__ double P[NB][NB + 1];
-  __shared__ double trow[2][NB];
-  __shared__ double piv[NB], sq[NB], rsq[NB];
+  __shared__ Real P[NB][NB + 1];
+  __shared__ Real trow[2][NB];
+  __shared__ Real piv[NB], sq[NB], rsq[NB];
   __shared__ int bad;
   const int l = blockIdx.x;
   float* Ab = A + (size_t)l * Np * Np + (size_t)kb * NB * Np + kb * NB;
   const int r = threadIdx.x >> 2, q = threadIdx.x & 3;
-  double a[16], t[16];
+  Real a[16], t[16];
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int k = 4 * u + q;
-    a[u] = (k <= r) ? (double)Ab[(size_t)r * Np + k] : 0.0;
-    t[u] = (k == r) ? 1.0 : 0.0;
+    a[u] = (k <= r) ? (Real)Ab[(size_t)r * Np + k] : Real(0);
+    t[u] = (k == r) ? Real(1) : Real(0);
   }
   if (threadIdx.x == 0) bad = 0;
   // unrolled, so that the register holding column j is known at compile time
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     if (q == (j & 3) && r >= j) {
-      double v = a[0];
+      Real v = a[0];
 #pragma unroll
       for (int u = 1; u < 16; ++u)
         if (u == (j >> 2)) v = a[u];
@@ -585,26 +592,26 @@ __global__ __launch_bounds__(256) void k_potrf_diag(float* __restrict__ A, int N
     __syncthreads();
     // all loads first and unconditionally (rows k < j of P[.][j] are not yet written:
     // their values are discarded by the select), so the reads share one wait
-    const double pj = P[j][j];
-    const double prj = P[r][j];
-    double pk[16], tv[16];
+    const Real pj = P[j][j];
+    const Real prj = P[r][j];
+    Real pk[16], tv[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       pk[u] = P[4 * u + q][j];
       tv[u] = trow[j & 1][4 * u + q];
     }
-    const bool badj = !(pj > 0.0);  // non-positive or NaN pivot
-    const double rp = recip64(badj ? 1.0 : pj);
-    const double f = r > j ? prj * rp : 0.0;
+    const bool badj = !(pj > Real(0));  // non-positive or NaN pivot
+    const Real rp = recip_t(badj ? Real(1) : pj);
+    const Real f = r > j ? prj * rp : Real(0);
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int k = 4 * u + q;
-      const double upd = fma(-f, pk[u], a[u]);
+      const Real upd = fma(-f, pk[u], a[u]);
       a[u] = (k > j && k <= r) ? upd : a[u];
       t[u] = fma(-f, tv[u], t[u]);   // T[j][c] = 0 for c > j: no change there
     }
     if (threadIdx.x == 0) {
-      piv[j] = badj ? 1.0 : pj;
+      piv[j] = badj ? Real(1) : pj;
       if (badj) bad = 1;
     }
   }
@@ -613,13 +620,13 @@ __global__ __launch_bounds__(256) void k_potrf_diag(float* __restrict__ A, int N
   for (int u = 0; u < 16; ++u) a[u] = t[u];
   __syncthreads();   // the last pivot (thread 0, after the last step's barrier)
   if (threadIdx.x < NB) {
-    const double d = sqrt(piv[threadIdx.x]);
+    const Real d = sqrt(piv[threadIdx.x]);
     sq[threadIdx.x] = d;
-    rsq[threadIdx.x] = 1.0 / d;
+    rsq[threadIdx.x] = Real(1) / d;
   }
   __syncthreads();
   float* Li = Linv + ((size_t)l * (Np / NB) + kb) * NB * NB;
-  const double rs = rsq[r];
+  const Real rs = rsq[r];
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int c = 4 * u + q;
@@ -1330,7 +1337,12 @@ SolveLayout solve_layout(int N, int nlam, int ntgt, void* base, size_t cap) {
 static fk_status factor_all(fk_ctx* ctx, const SolveLayout& s, const DenseShape& sh) {
   const int nb = s.Np / NB;
   auto finish = [&](int kb) {   // diagonal block and the panel below it
-    hipLaunchKernelGGL(k_potrf_diag, dim3(s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv, ctx->flags);
+    if (sh.diag64)
+      hipLaunchKernelGGL(k_potrf_diag<double>, dim3(s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv,
+                         ctx->flags);
+    else
+      hipLaunchKernelGGL(k_potrf_diag<float>, dim3(s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv,
+                         ctx->flags);
     const int rem = nb - kb - 1;
     if (rem > 0)
       hipLaunchKernelGGL(k_trsm_panel, dim3(rem * s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv,
@@ -1509,6 +1521,7 @@ static DenseShape dense_shape(const fk_ctx* ctx, const SolveLayout& s) {
   if (tune_mode(ctx) == kTuneOff || !tune_lookup(dense_key(ctx, s), &v)) return sh;
   if (v.count("trsm_wg") && v["trsm_wg"] >= 64 && v["trsm_wg"] <= 4096) sh.trsm_wg = (int)v["trsm_wg"];
   if (v.count("pair")) sh.pair = v["pair"] != 0.0;
+  if (v.count("diag64")) sh.diag64 = v["diag64"] != 0.0;
   return sh;
 }
 

@@ -161,6 +161,7 @@ constexpr int kSortSliceMin = 32768;
 struct DenseShape {
   int trsm_wg = 512;          // workgroups per triangular-solve launch (over all lambdas)
   int pair = 1;               // factor block columns in pairs (row panels read once for two)
+  int diag64 = 0;             // diagonal blocks factored in FP64 (1) or FP32 (0)
 };
 
 // Two-pass bin sort for the MFMA spreads (sort2.hip): scratch buffers carved from
