@@ -547,10 +547,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   if (i > kb) store_split_update(Al + (size_t)i * NB * Np + (kb + 1) * NB, Np, acc[1], accx[1]);
 }
 
-// Factor the diagonal block kb of every lambda (one workgroup per lambda) in FP64;
-// write L_kk (lower) back and inv(L_kk) to Linv[l][kb].
+// Factor the diagonal block kb of every lambda (one workgroup per lambda) in Real (FP32, or FP64
+// when the launch shape asks for it); write L_kk (lower) back and inv(L_kk) to Linv[l][kb].
+// Within the 64 x 64 block the sweep is right-looking:
 // Thread (r, q) = (tid / 4, tid % 4) keeps entries r, q + 4u (u = 0..15) of the block, and
-// of T below, in registers.  Right-looking, unscaled: at step j column j has received every
+// of T below, in registers.  Unscaled: at step j column j has received every
 // update, its owners publish it to P[.][j] (never written again), one barrier, and each row
 // below applies a[r][k] -= f P[k][j] with f = P[r][j] / P[j][j].  Then L[r][c] = P[r][c] /
 // sqrt(P[c][c]).  The same row operations turn the identity into T = diag(sqrt P) inv(L):
@@ -1331,9 +1332,9 @@ SolveLayout solve_layout(int N, int nlam, int ntgt, void* base, size_t cap) {
   return s;
 }
 
-// Factor A32[l] = L L^T for every lambda (blocked, right-looking).
-// Left-looking blocked Cholesky: per block column, update with the finished panels
-// (one pass over the column), factor the diagonal block, solve the panel below it.
+// Factor A32[l] = L L^T for every lambda: left-looking blocked Cholesky, per block column an
+// update with the finished panels (one pass over the column), the factorization of the
+// diagonal block, the solve of the panel below it.
 static fk_status factor_all(fk_ctx* ctx, const SolveLayout& s, const DenseShape& sh) {
   const int nb = s.Np / NB;
   auto finish = [&](int kb) {   // diagonal block and the panel below it
