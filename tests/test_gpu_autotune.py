@@ -82,7 +82,8 @@ def test_every_dense_shape_solves_the_system(fk, tmp_path):
     ref = {i: oracle.solve_system(oracle.system_matrix(Mh, m, lams[i], p), bh) for i in (0, nlam - 1)}
     key = f"{_arch()} dense Np=2432 nlam={nlam} ntgt=2"
     try:
-        for sh in [dict(pair=0, trsm_wg=256), dict(pair=1, trsm_wg=1024), dict(pair=1, trsm_wg=512)]:
+        for sh in [dict(pair=0, trsm_wg=256), dict(pair=1, trsm_wg=1024), dict(pair=1, trsm_wg=512),
+                   dict(pair=1, trsm_wg=512, diag64=1)]:
             _pin(fk, tmp_path, key, sh)
             th, info = fk.solve(M, b, m, lams, penalty="sobolev", s=2.0, info=True)
             assert info["resid_rel"] <= 1e-10
