@@ -235,6 +235,20 @@ fk_status fk_fit(fk_ctx* ctx, int d, int64_t n, fk_dtype dtype, const void* X, i
                  const void* Y, int m, const double* lambdas, int nlam, const fk_penalty* pen,
                  double* theta_out, void* ws, size_t ws_bytes, fk_fit_info* info);
 
+/* fk_fit_kept: fk_fit with its two parts in two workspaces: ws_solve (solve_bytes of
+ * fk_fit_kept_workspace_size, the same layout as fk_solve's workspace) keeps the factors, the FP64
+ * real-form Gram and the solutions for fk_heldout_mse / fk_fit_backward (see "Kept factors"), and
+ * ws_scratch (scratch_bytes) holds M, b and the type-1 stage's buffers, free again when the call
+ * returns.  So a caller keeping the factors of several fits keeps only their ws_solve buffers, and
+ * shares one scratch buffer.  The two buffers must not overlap (FK_EINVAL).  Results and errors as
+ * fk_fit; the stage and the solve run without a synchronisation between them. */
+fk_status fk_fit_kept_workspace_size(fk_ctx* ctx, int d, int64_t n, int ntgt, int m, int nlam,
+                                     size_t* solve_bytes, size_t* scratch_bytes);
+fk_status fk_fit_kept(fk_ctx* ctx, int d, int64_t n, fk_dtype dtype, const void* X, int ntgt,
+                      const void* Y, int m, const double* lambdas, int nlam, const fk_penalty* pen,
+                      double* theta_out, void* ws_solve, size_t ws_solve_bytes, void* ws_scratch,
+                      size_t ws_scratch_bytes, fk_fit_info* info);
+
 /* ---------------------------------------------------------------- type-2 stage
  * fk_predict: out[t][j] = Re sum_k theta[t][k] exp(+i k.Xq_j) (the estimator of
  * Sec. 2.1 evaluated at new points), by deconvolution, an inverse FFT onto an

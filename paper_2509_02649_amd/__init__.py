@@ -22,7 +22,8 @@ import torch
 from . import _lib
 from ._lib import FkError, fk_fit_info, fk_penalty, fk_options, FK_F32, FK_F64, PEN
 
-__all__ = ["Context", "gram", "restrict", "solve", "solve_workspace_size", "solve_cg", "toeplitz_apply", "fit", "predict", "predict_noalloc", "heldout_mse", "fit_backward", "additive_gram",
+__all__ = ["Context", "gram", "restrict", "solve", "solve_workspace_size", "fit_kept_workspace_size", "solve_cg",
+           "toeplitz_apply", "fit", "predict", "predict_noalloc", "heldout_mse", "fit_backward", "additive_gram",
            "additive_fit", "generate_uniform", "generate_targets", "KernelRidgeGridLoss", "FkError",
            "autotune_table", "autotune_load", "autotune_clear"]
 
@@ -276,9 +277,23 @@ def solve_cg(M: torch.Tensor, b: torch.Tensor, m: int, lambdas: Sequence[float],
     return th
 
 
+def fit_kept_workspace_size(d: int, n: int, T: int, m: int, nlam: int, ctx: Optional[Context] = None):
+    """(solve_bytes, scratch_bytes) of fk_fit_kept: the part that keeps the factors, and the type-1 scratch."""
+    ctx = ctx or default_context(0)
+    sb, tb = C.c_size_t(), C.c_size_t()
+    _lib.check(ctx.lib.fk_fit_kept_workspace_size(ctx.h, d, n, T, m, nlam, C.byref(sb), C.byref(tb)),
+               "fk_fit_kept_workspace_size")
+    return sb.value, tb.value
+
+
 def fit(X: torch.Tensor, Y: torch.Tensor, m: int, lambdas, penalty: str = "sobolev", s: float = 1.0,
-        ctx: Optional[Context] = None, info: bool = False, **pen_kw):
-    """fit(X, Y, m, lambda(s), penalty) -> theta [nlam, T, N] complex128 (one workspace, one sync)."""
+        ctx: Optional[Context] = None, info: bool = False, ws: Optional[torch.Tensor] = None, **pen_kw):
+    """fit(X, Y, m, lambda(s), penalty) -> theta [nlam, T, N] complex128 (the type-1 stage and the solve
+    in one call).
+
+    ws: an explicit uint8 device workspace (at least the solve_bytes of fit_kept_workspace_size) that
+    keeps the factors for heldout_mse / fit_backward; the type-1 stage then runs in the context's
+    cached workspace (fk_fit_kept).  Default: both in the context's cached workspace (fk_fit)."""
     ctx = ctx or default_context(X.device.index or 0)
     ctx.bind_stream()
     if isinstance(lambdas, (int, float)):
@@ -289,14 +304,23 @@ def fit(X: torch.Tensor, Y: torch.Tensor, m: int, lambdas, penalty: str = "sobol
     T = Y.shape[0]
     lams = (C.c_double * len(lambdas))(*[float(v) for v in lambdas])
     nlam = len(lambdas)
-    nb = C.c_size_t()
-    _lib.check(ctx.lib.fk_fit_workspace_size(ctx.h, d, n, T, m, nlam, C.byref(nb)), "fk_fit_workspace_size")
-    ws = ctx.workspace(nb.value)
     theta = torch.empty((nlam, T, _modes(m, d), 2), dtype=torch.float64, device=X.device)
     pen, keep = _penalty(penalty, s, **pen_kw)
     inf = fk_fit_info()
-    _lib.check(ctx.lib.fk_fit(ctx.h, d, n, _dtype_code(X), _ptr(X), T, _ptr(Y), m, lams, nlam, C.byref(pen),
-                              _ptr(theta), _ptr(ws), nb.value, C.byref(inf)), "fk_fit")
+    if ws is None:
+        nb = C.c_size_t()
+        _lib.check(ctx.lib.fk_fit_workspace_size(ctx.h, d, n, T, m, nlam, C.byref(nb)), "fk_fit_workspace_size")
+        w = ctx.workspace(nb.value)
+        _lib.check(ctx.lib.fk_fit(ctx.h, d, n, _dtype_code(X), _ptr(X), T, _ptr(Y), m, lams, nlam, C.byref(pen),
+                                  _ptr(theta), _ptr(w), nb.value, C.byref(inf)), "fk_fit")
+    else:
+        if ws.device != X.device or ws.dtype != torch.uint8 or not ws.is_contiguous():
+            raise ValueError("ws must be a contiguous uint8 tensor on the device of X")
+        _, tb = fit_kept_workspace_size(d, n, T, m, nlam, ctx)
+        w = ctx.workspace(tb)
+        _lib.check(ctx.lib.fk_fit_kept(ctx.h, d, n, _dtype_code(X), _ptr(X), T, _ptr(Y), m, lams, nlam,
+                                       C.byref(pen), _ptr(theta), _ptr(ws), ws.numel(), _ptr(w), tb,
+                                       C.byref(inf)), "fk_fit_kept")
     del keep
     th = torch.view_as_complex(theta)
     return (th, inf.as_dict()) if info else th
@@ -490,11 +514,10 @@ class KernelRidgeGridLoss(torch.autograd.Function):
         fkc = default_context(X.device.index or 0)
         lams = torch.exp(loglam.detach()).cpu().tolist()
         d = X.shape[0]
-        # type-1 stage in the context's shared workspace; factors in this apply's own
-        M, b = gram(X, Y, m, ctx=fkc)
-        kept = torch.empty(solve_workspace_size(d, m, Y.shape[0], len(lams), fkc), dtype=torch.uint8,
-                           device=X.device)
-        theta = solve(M, b, m, lams, penalty="diag", p=p.detach(), ctx=fkc, ws=kept)
+        # type-1 stage in the context's shared workspace, factors in this apply's own (one call)
+        sb, _ = fit_kept_workspace_size(d, X.shape[1], Y.shape[0], m, len(lams), fkc)
+        kept = torch.empty(sb, dtype=torch.uint8, device=X.device)
+        theta = fit(X, Y, m, lams, penalty="diag", p=p.detach(), ctx=fkc, ws=kept)
         vctx = _validation_context(fkc)
         Mv, bv = gram(Xv, Yv, m, ctx=vctx)
         yv2 = mean_square(Yv, vctx)

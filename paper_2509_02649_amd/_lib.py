@@ -80,6 +80,11 @@ EXPORTS = {
     "fk_fit": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_int,
                          C.POINTER(C.c_double), C.c_int, C.POINTER(fk_penalty), C.c_void_p, C.c_void_p, C.c_size_t,
                          C.POINTER(fk_fit_info)]),
+    "fk_fit_kept_workspace_size": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int, C.c_int, C.c_int,
+                                             C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+    "fk_fit_kept": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_int,
+                              C.POINTER(C.c_double), C.c_int, C.POINTER(fk_penalty), C.c_void_p, C.c_void_p,
+                              C.c_size_t, C.c_void_p, C.c_size_t, C.POINTER(fk_fit_info)]),
     "fk_predict_workspace_size": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_size_t)]),
     "fk_predict": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_int64, C.c_int, C.c_void_p,
                              C.c_void_p, C.c_void_p, C.c_size_t]),

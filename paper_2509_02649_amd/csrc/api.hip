@@ -564,13 +564,10 @@ extern "C" fk_status fk_solve_cg_collocation(fk_ctx* ctx, int d, int m, const do
                    ws_bytes);
 }
 
+static size_t fit_scratch(int d, int64_t n, int ntgt, int m);
 static size_t fit_ws(int d, int64_t n, int ntgt, int m, int nlam) {
   const int64_t N = ipow(2 * m + 1, d);
-  size_t a = solve_layout((int)N, nlam, ntgt, nullptr, 0).bytes;
-  Carve cv(nullptr, 0);
-  cv.take<double>((size_t)2 * ipow(4 * m + 1, d));
-  cv.take<double>((size_t)2 * ntgt * N);
-  return a + cv.off + gram_ws(d, n, ntgt, m) + 1024;
+  return solve_layout((int)N, nlam, ntgt, nullptr, 0).bytes + fit_scratch(d, n, ntgt, m);
 }
 
 extern "C" fk_status fk_fit_workspace_size(fk_ctx* ctx, int d, int64_t n, int ntgt, int m, int nlam,
@@ -582,24 +579,37 @@ extern "C" fk_status fk_fit_workspace_size(fk_ctx* ctx, int d, int64_t n, int nt
   return FK_OK;
 }
 
-extern "C" fk_status fk_fit(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int ntgt, const void* Y,
-                            int m, const double* lambdas, int nlam, const fk_penalty* pen, double* theta_out,
-                            void* ws, size_t ws_bytes, fk_fit_info* info) {
+// The type-1 stage's part of a fit: M, b and the stage's scratch.
+static size_t fit_scratch(int d, int64_t n, int ntgt, int m) {
+  const int64_t N = ipow(2 * m + 1, d);
+  Carve cv(nullptr, 0);
+  cv.take<double>((size_t)2 * ipow(4 * m + 1, d));
+  cv.take<double>((size_t)2 * ntgt * N);
+  return cv.off + gram_ws(d, n, ntgt, m) + 1024;
+}
+
+// fk_fit with the solve's layout (factors, FP64 Gram, solutions: what the gradients read) in wss and
+// the type-1 stage (M, b and its scratch) in wst.
+static fk_status fit_impl(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int ntgt, const void* Y, int m,
+                          const double* lambdas, int nlam, const fk_penalty* pen, double* theta_out, void* wss,
+                          size_t wss_bytes, void* wst, size_t wst_bytes, fk_fit_info* info) {
   if (!ctx || !theta_out) return FK_EINVAL;
   if (check_gram_args(d, n, ntgt, m, X, Y) != FK_OK || ntgt < 1) return FK_EINVAL;
   if (dt != FK_F32 && dt != FK_F64) return FK_EINVAL;
   SolveProblem P;
   fk_status st = build_problem(d, m, nullptr, nullptr, lambdas, nlam, pen, P);
   if (st != FK_OK) return st;
-  if (!ws || ws_bytes < fit_ws(d, n, ntgt, m, nlam)) return FK_ENOMEM;
+  if (!wss || !wst) return FK_ENOMEM;
+  SolveLayout s = solve_layout(P.L, nlam, ntgt, wss, wss_bytes);
+  if (s.bytes > wss_bytes || wst_bytes < fit_scratch(d, n, ntgt, m)) return FK_ENOMEM;
   FK_HIP(hipSetDevice(ctx->device));
-  kept_invalidate(ws, ws_bytes);
+  kept_invalidate(wss, wss_bytes);
+  kept_invalidate(wst, wst_bytes);
   if (info) {
     std::memset(info, 0, sizeof(*info));
     info->bad_index = -1;
   }
-  SolveLayout s = solve_layout(P.L, nlam, ntgt, ws, ws_bytes);
-  Carve cv(static_cast<char*>(ws) + s.bytes, ws_bytes - s.bytes);
+  Carve cv(wst, wst_bytes);
   double* M = cv.take<double>((size_t)2 * ipow(4 * m + 1, d));
   double* b = cv.take<double>((size_t)2 * ntgt * P.L);
   P.M = M;
@@ -611,7 +621,7 @@ extern "C" fk_status fk_fit(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const vo
   // raises (NaN, range) come back with the solve's first residual norms, ahead of its own status.
   st = solve_impl(ctx, P, s, theta_out, info);
   if (st == FK_OK || st == FK_ENOCONV)
-    kept_register(ws, s.bytes, ctx->device, kKeptToeplitz, d, m, P.L, nlam, ntgt, 1);
+    kept_register(wss, s.bytes, ctx->device, kKeptToeplitz, d, m, P.L, nlam, ntgt, 1);
   if (info) {
     info->status = st;
     info->t_sort_ms = elapsed(ctx->ev[0], ctx->ev[1]);
@@ -621,6 +631,40 @@ extern "C" fk_status fk_fit(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const vo
     info->t_total_ms = elapsed(ctx->ev[0], ctx->ev[8]);
   }
   return st;
+}
+
+extern "C" fk_status fk_fit(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int ntgt, const void* Y,
+                            int m, const double* lambdas, int nlam, const fk_penalty* pen, double* theta_out,
+                            void* ws, size_t ws_bytes, fk_fit_info* info) {
+  if (!ctx || !theta_out) return FK_EINVAL;
+  if (check_gram_args(d, n, ntgt, m, X, Y) != FK_OK || ntgt < 1 || nlam < 1) return FK_EINVAL;
+  if (!ws || ws_bytes < fit_ws(d, n, ntgt, m, nlam)) return FK_ENOMEM;
+  const size_t sb = solve_layout((int)ipow(2 * m + 1, d), nlam, ntgt, nullptr, 0).bytes;
+  return fit_impl(ctx, d, n, dt, X, ntgt, Y, m, lambdas, nlam, pen, theta_out, ws, sb,
+                  static_cast<char*>(ws) + sb, ws_bytes - sb, info);
+}
+
+extern "C" fk_status fk_fit_kept_workspace_size(fk_ctx* ctx, int d, int64_t n, int ntgt, int m, int nlam,
+                                                size_t* solve_bytes, size_t* scratch_bytes) {
+  if (!solve_bytes || !scratch_bytes) return FK_EINVAL;
+  if (check_gram_args(d, n, ntgt, m, (void*)1, (void*)1) != FK_OK || ntgt < 1 || nlam < 1 || nlam > 1024 || d > 2)
+    return FK_EINVAL;
+  *solve_bytes = solve_layout((int)ipow(2 * m + 1, d), nlam, ntgt, nullptr, 0).bytes;
+  *scratch_bytes = fit_scratch(d, n, ntgt, m);
+  return FK_OK;
+}
+
+extern "C" fk_status fk_fit_kept(fk_ctx* ctx, int d, int64_t n, fk_dtype dt, const void* X, int ntgt,
+                                 const void* Y, int m, const double* lambdas, int nlam, const fk_penalty* pen,
+                                 double* theta_out, void* ws_solve, size_t ws_solve_bytes, void* ws_scratch,
+                                 size_t ws_scratch_bytes, fk_fit_info* info) {
+  if (ws_solve && ws_scratch) {
+    const char* a = static_cast<const char*>(ws_solve);
+    const char* b = static_cast<const char*>(ws_scratch);
+    if (a < b + ws_scratch_bytes && b < a + ws_solve_bytes) return FK_EINVAL;   // overlapping workspaces
+  }
+  return fit_impl(ctx, d, n, dt, X, ntgt, Y, m, lambdas, nlam, pen, theta_out, ws_solve, ws_solve_bytes, ws_scratch,
+                  ws_scratch_bytes, info);
 }
 
 // ------------------------------------------------------------------ held-out loss / backward

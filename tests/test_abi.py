@@ -66,6 +66,13 @@ def test_workspace_queries_and_host_validation(lib):
     assert L.fk_solve_workspace_size(None, 2, 32, 16, 64, C.byref(nb)) == 0
     Np = 4288
     assert nb.value >= 64 * Np * Np * 4 + 2 * Np * Np * 8
+    # the fit's two parts: the solve's layout (as fk_solve's) and the type-1 scratch, summing to fk_fit's
+    solve_b = nb.value
+    sb, tb, fb = C.c_size_t(), C.c_size_t(), C.c_size_t()
+    assert L.fk_fit_kept_workspace_size(None, 2, 10_000_000, 16, 32, 64, C.byref(sb), C.byref(tb)) == 0
+    assert L.fk_fit_workspace_size(None, 2, 10_000_000, 16, 32, 64, C.byref(fb)) == 0
+    assert sb.value == solve_b and sb.value + tb.value == fb.value
+    assert L.fk_fit_kept_workspace_size(None, 3, 100, 1, 8, 1, C.byref(sb), C.byref(tb)) == 1   # 1-D / 2-D only
     assert L.fk_predict_workspace_size(None, 2, 32, 1, C.byref(nb)) == 0
     assert L.fk_additive_fit_workspace_size(None, 10, 1000, 1, 32, 1, C.byref(nb)) == 0
     assert L.fk_additive_gram_workspace_size(None, 1, 1000, 1, 32, C.byref(nb)) == 1   # d = 1 rejected

@@ -208,6 +208,37 @@ def test_kept_factors_are_guarded(fk):
     assert e.value.code == 3
 
 
+def test_fit_kept_matches_fit_and_keeps_factors(fk):
+    # fk_fit_kept: the same theta as fk_fit (the type-1 stage's atomics only reorder additions, and both
+    # refinements stop at a 1e-10 relative residual, so the two thetas agree to about kappa 1e-10), its
+    # factors kept in the caller's buffer for the held-out loss, and overlapping buffers refused
+    m, T, lams = 6, 2, [1e-2, 1e-3]
+    (X, Y, Xv, Yv), _ = _grad_problem(73, m=m, n=50_000, nv=10_000, T=T)
+    ctx, vctx = fk.Context(0), fk.Context(0)
+    th_ref = fk.fit(X, Y, m, lams, ctx=ctx)
+    sb, tb = fk.fit_kept_workspace_size(2, X.shape[1], T, m, len(lams), ctx)
+    kept = torch.empty(sb, dtype=torch.uint8, device="cuda")
+    th = fk.fit(X, Y, m, lams, ctx=ctx, ws=kept)
+    e = (torch.linalg.vector_norm(th - th_ref) / torch.linalg.vector_norm(th_ref)).item()
+    print(f"fit_kept vs fit: {e:.2e}")
+    assert e <= 1e-6
+    Mv, bv = fk.gram(Xv, Yv, m, ctx=vctx)
+    yv2 = fk.mean_square(Yv, ctx=vctx)
+    mse_k = fk.heldout_mse(Mv, bv, yv2, m, len(lams), ctx, ws=kept)
+    fk.fit(X, Y, m, lams, ctx=ctx)   # the context's own workspace: the kept buffer is untouched
+    mse_r = fk.heldout_mse(Mv, bv, yv2, m, len(lams), ctx)
+    print(f"held-out mse, kept buffer vs context workspace: {((mse_k - mse_r).abs() / mse_r.abs()).max().item():.2e}")
+    assert torch.allclose(mse_k, mse_r, rtol=1e-6, atol=0)
+    big = torch.empty(sb + tb, dtype=torch.uint8, device="cuda")
+    L = ctx.lib
+    out = torch.empty((len(lams), T, (2 * m + 1) ** 2, 2), dtype=torch.float64, device="cuda")
+    lam_c = (fk.C.c_double * 2)(*lams)
+    pen = fk.fk_penalty()
+    code = L.fk_fit_kept(ctx.h, 2, X.shape[1], 0, fk._ptr(X), T, fk._ptr(Y), m, lam_c, 2, fk.C.byref(pen),
+                         fk._ptr(out), fk._ptr(big), sb, fk.C.c_void_p(big.data_ptr() + sb // 2), tb, None)
+    assert code == 1   # FK_EINVAL: the two workspaces overlap
+
+
 @pytest.mark.parametrize("T,n,dt", [(16, 1_000_003, np.float32), (3, 1, np.float64), (1, 70_000, np.float64)])
 def test_mean_square(fk, T, n, dt):
     # the constant term of the held-out loss: exact FP64 sums of squares of the stored values
