@@ -123,6 +123,24 @@ def test_fit_many_lambdas_and_targets(fk):
             assert _rel(tg[i, t], th[t]) <= TOL
 
 
+def test_solve_more_than_16_right_hand_sides(fk):
+    # 20 right-hand sides: the triangular solves take 32-column blocks (two 16-column MFMA tiles)
+    rng = np.random.default_rng(2020)
+    m, n, T = 8, 30_000, 20
+    X = rng.uniform(-np.pi, np.pi, size=(2, n))
+    Y = rng.standard_normal((T, n))
+    M = oracle.gram_generator(X, m)
+    b = oracle.rhs(X, Y, m)
+    p = oracle.sobolev_weights(m, 2, 2.0)
+    lams = [1e-4, 1e-2]
+    tg = fk.solve(_cplx(M), _cplx(b), m, lams, penalty="sobolev", s=2.0).cpu().numpy()
+    for i, lam in enumerate(lams):
+        th = oracle.solve_system(oracle.system_matrix(M, m, lam, p), b)
+        e = max(_rel(tg[i, t], th[t]) for t in range(T))
+        print(f"{T} right-hand sides, lambda={lam:.0e}: worst rel {e:.2e}")
+        assert e <= TOL
+
+
 def test_fit_low_bias_and_bessel_penalties(fk):
     X = synth.uniform_points(5, 2, 100_000)
     Y = synth.batched_targets(X, 5, ntgt=1)
