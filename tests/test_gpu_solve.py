@@ -123,6 +123,31 @@ def test_fit_many_lambdas_and_targets(fk):
             assert _rel(tg[i, t], th[t]) <= TOL
 
 
+def test_solve_at_the_batched_benchmark_shape(fk):
+    # the dense stage exactly as the benchmark runs it: N = 4225 unknowns (m = 32), 64 lambdas in
+    # [1e-8, 1e-1], 16 targets (paired FP16-pair panel updates, FP32 diagonal blocks, two block columns
+    # per triangular-solve launch), on a Gram from 2e6 device-generated points; three lambdas checked
+    # against the oracle's FP64 solve of the same system
+    m, T, nlam = 32, 16, 64
+    ctx = fk.Context(0)
+    X = fk.generate_uniform(2509026495, 2, 2_000_000, ctx=ctx)
+    Y = fk.generate_targets(2509026495, X, T, ctx=ctx)
+    M, b = fk.gram(X, Y, m, ctx=ctx)
+    lams = [10.0 ** (-8.0 + 7.0 * i / (nlam - 1)) for i in range(nlam)]
+    tg, info = fk.solve(M, b, m, lams, penalty="sobolev", s=2.0, ctx=ctx, info=True)
+    print(f"benchmark shape: resid {info['resid_rel']:.1e}, {info['refine_iters']} refinement steps, "
+          f"factor {info['t_factor_ms']:.2f} ms")
+    assert info["resid_rel"] <= 1e-10
+    Mh, bh, th = M.cpu().numpy(), b.cpu().numpy(), tg.cpu().numpy()
+    p = oracle.sobolev_weights(m, 2, 2.0)
+    for i in (0, 31, 63):
+        A = oracle.system_matrix(Mh, m, lams[i], p)
+        ref = oracle.solve_system(A, bh)
+        e = max(_rel(th[i, t], ref[t]) for t in range(T))
+        print(f"lambda={lams[i]:.1e}: worst rel {e:.2e}")
+        assert e <= TOL
+
+
 def test_solve_more_than_16_right_hand_sides(fk):
     # 20 right-hand sides: the triangular solves take 32-column blocks (two 16-column MFMA tiles)
     rng = np.random.default_rng(2020)
