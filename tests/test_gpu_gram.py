@@ -109,6 +109,25 @@ def test_gram_only_no_targets(fk, n):
     assert eT <= TOL
 
 
+@pytest.mark.parametrize("ntgt", [16, 1])
+@pytest.mark.parametrize("shape", ["square", "line"])
+def test_gram_clustered_points(fk, ntgt, shape):
+    # skewed inputs for the two-pass sort and the binned spreads: every point in one small square
+    # (one or a few bins take all 300k points, cut into slices; every other bin empty), or on the
+    # line x1 = 0.3 (one bin row takes all points in the first pass)
+    rng = np.random.default_rng(17 + ntgt)
+    n = 300_000
+    if shape == "square":
+        X = rng.uniform(0.1, 0.112, size=(2, n))
+    else:
+        X = np.stack([np.full(n, 0.3), rng.uniform(-np.pi, np.pi, size=n)])
+    X = X.astype(np.float32)
+    Y = rng.standard_normal((ntgt, n)).astype(np.float32)
+    eT, eb, info = _errors(fk, X, Y, 8)
+    print(f"clustered ({shape}) T={ntgt}: eps_T={eT:.2e} eps_b={eb:.2e} bin={info['bin']}")
+    assert eT <= TOL and eb <= TOL
+
+
 def test_gram_boundary_points_fold(fk):
     # points on the seam: -pi, fp32(pi) > pi, values just inside [-2pi, 2pi) that fold
     pts = np.array([-np.pi, np.float32(np.pi), 0.0, -2 * np.pi + 1e-3, 2 * np.pi - 1e-3, 3.0, -3.0],
