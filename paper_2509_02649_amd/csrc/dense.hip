@@ -738,24 +738,48 @@ __device__ __forceinline__ void mfma_64xK(const float* Ls, const float (*Bs)[LDB
 // (256 threads: thread t holds the four entries number t + 256 u of the row-major tile),
 // for loading the next tile of a sweep while the current one is on the matrix cores; the
 // staging into LDS unpacks it to FP32.
-#define FK_TILE_FETCH(src, ld)                                                               \
+#define FK_TILE_FETCH_TO(src, ld, a0, a1, a2, a3)                                            \
   do {                                                                                       \
     _Pragma("unroll") for (int u_ = 0; u_ < 4; ++u_) {                                       \
       const int i_ = threadIdx.x + 256 * u_, r_ = i_ / (NB / 4), c_ = (i_ - r_ * (NB / 4)) * 4; \
       const uint4 v_ = *reinterpret_cast<const uint4*>((src) + r_ * (ld) + c_);            \
-      if (u_ == 0) nt0 = v_;                                                                 \
-      if (u_ == 1) nt1 = v_;                                                                 \
-      if (u_ == 2) nt2 = v_;                                                                 \
-      if (u_ == 3) nt3 = v_;                                                                 \
+      if (u_ == 0) a0 = v_;                                                                  \
+      if (u_ == 1) a1 = v_;                                                                  \
+      if (u_ == 2) a2 = v_;                                                                  \
+      if (u_ == 3) a3 = v_;                                                                  \
     }                                                                                        \
   } while (0)
-#define FK_TILE_STAGE(T)                                                                     \
+#define FK_TILE_STAGE_FROM(T, a0, a1, a2, a3)                                                \
   do {                                                                                       \
     _Pragma("unroll") for (int u_ = 0; u_ < 4; ++u_) {                                       \
       const int i_ = threadIdx.x + 256 * u_, r_ = i_ / (NB / 4), c_ = (i_ - r_ * (NB / 4)) * 4; \
-      const uint4 q_ = u_ == 0 ? nt0 : u_ == 1 ? nt1 : u_ == 2 ? nt2 : nt3;                 \
+      const uint4 q_ = u_ == 0 ? a0 : u_ == 1 ? a1 : u_ == 2 ? a2 : a3;                     \
       *reinterpret_cast<float4*>((T) + r_ * LDT + c_) =                                      \
           make_float4(split_unpack(q_.x), split_unpack(q_.y), split_unpack(q_.z), split_unpack(q_.w)); \
+    }                                                                                        \
+  } while (0)
+#define FK_TILE_FETCH(src, ld) FK_TILE_FETCH_TO(src, ld, nt0, nt1, nt2, nt3)
+#define FK_TILE_STAGE(T) FK_TILE_STAGE_FROM(T, nt0, nt1, nt2, nt3)
+
+// A contiguous 64 x 64 FP32 tile (an inverted diagonal block) in four float4 registers per lane,
+// and its store into an LDS tile of row stride LDT (256 threads).  Named registers rather than an
+// array, which the compiler would keep in scratch memory across the products.
+#define FK_F32_FETCH_TO(src, a0, a1, a2, a3)                                                 \
+  do {                                                                                       \
+    _Pragma("unroll") for (int u_ = 0; u_ < 4; ++u_) {                                       \
+      const int i_ = threadIdx.x + 256 * u_, r_ = i_ / (NB / 4), c_ = (i_ - r_ * (NB / 4)) * 4; \
+      const float4 v_ = *reinterpret_cast<const float4*>((src) + r_ * NB + c_);            \
+      if (u_ == 0) a0 = v_;                                                                  \
+      if (u_ == 1) a1 = v_;                                                                  \
+      if (u_ == 2) a2 = v_;                                                                  \
+      if (u_ == 3) a3 = v_;                                                                  \
+    }                                                                                        \
+  } while (0)
+#define FK_F32_STAGE_FROM(T, a0, a1, a2, a3)                                                 \
+  do {                                                                                       \
+    _Pragma("unroll") for (int u_ = 0; u_ < 4; ++u_) {                                       \
+      const int i_ = threadIdx.x + 256 * u_, r_ = i_ / (NB / 4), c_ = (i_ - r_ * (NB / 4)) * 4; \
+      *reinterpret_cast<float4*>((T) + r_ * LDT + c_) = u_ == 0 ? a0 : u_ == 1 ? a1 : u_ == 2 ? a2 : a3; \
     }                                                                                        \
   } while (0)
 
@@ -916,13 +940,37 @@ __global__ __launch_bounds__(256) void k_fwd2_mfma(const float* __restrict__ A, 
   const int li = lane & 15, lk = lane >> 4;
   float* Rl = R + (size_t)l * ncol * Np;
   const float* Al = A + (size_t)l * Np * Np;
-  for (int i = threadIdx.x; i < 2 * NB * 16 * NCT; i += blockDim.x) {
-    const int t = i / (2 * NB), k = i - t * (2 * NB);
-    Bs[k][t] = t < ncol ? Rl[(size_t)t * Np + kb * NB + k] : 0.f;
+  const int ib0 = kb + 2 + blockIdx.x;
+  // Every global load of the two diagonal steps and of the first row goes out here, before any
+  // is used: the prologue waits for memory once instead of three times.
+  constexpr int NBS = 2 * NB * 16 * NCT / 256;   // right-hand-side entries per thread
+  float bsv[NBS];
+#pragma unroll
+  for (int u = 0; u < NBS; ++u) {
+    const int i = threadIdx.x + 256 * u, t = i / (2 * NB), k = i - t * (2 * NB);
+    bsv[u] = t < ncol ? Rl[(size_t)t * Np + kb * NB + k] : 0.f;
   }
-  load_tile(Ls[0], Linv + ((size_t)l * nb + kb) * NB * NB, NB);
-  uint4 nt0, nt1, nt2, nt3;
+  float4 d00, d01, d02, d03, d10, d11, d12, d13;
+  FK_F32_FETCH_TO(Linv + ((size_t)l * nb + kb) * NB * NB, d00, d01, d02, d03);
+  FK_F32_FETCH_TO(Linv + ((size_t)l * nb + kb + 1) * NB * NB, d10, d11, d12, d13);
+  uint4 nt0, nt1, nt2, nt3, ns0, ns1, ns2, ns3;
   FK_TILE_FETCH(Al + (size_t)(kb + 1) * NB * Np + kb * NB, Np);
+  if (ib0 < nb) FK_TILE_FETCH_TO(Al + (size_t)ib0 * NB * Np + kb * NB, Np, ns0, ns1, ns2, ns3);
+  // this lane's part of the right-hand-side block of a row: 4 rows x NCT columns
+  float rr[NCT][4];
+#define FK_R_FETCH(RB)                                                                         \
+  _Pragma("unroll") for (int ct = 0; ct < NCT; ++ct) {                                         \
+    const int t_ = min(ct * 16 + li, ncol - 1);                                                \
+    _Pragma("unroll") for (int v = 0; v < 4; ++v)                                              \
+      rr[ct][v] = Rl[(size_t)t_ * Np + (RB) * NB + 16 * w + 4 * lk + v];                       \
+  }
+  if (ib0 < nb) FK_R_FETCH(ib0)
+#pragma unroll
+  for (int u = 0; u < NBS; ++u) {
+    const int i = threadIdx.x + 256 * u, t = i / (2 * NB), k = i - t * (2 * NB);
+    Bs[k][t] = bsv[u];
+  }
+  FK_F32_STAGE_FROM(Ls[0], d00, d01, d02, d03);
   FK_TILE_STAGE(Ls[1]);
   __syncthreads();
   floatx4 acc[NCT];
@@ -938,17 +986,15 @@ __global__ __launch_bounds__(256) void k_fwd2_mfma(const float* __restrict__ A, 
   for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
     for (int v = 0; v < 4; ++v) Bs[NB + 16 * w + 4 * lk + v][ct * 16 + li] -= acc[ct][v];
-  load_tile(Ls[0], Linv + ((size_t)l * nb + kb + 1) * NB * NB, NB);
+  FK_F32_STAGE_FROM(Ls[0], d10, d11, d12, d13);
   __syncthreads();
   mfma_64xK<false, NCT>(Ls[0], Bs + NB, acc);   // y_{kb+1}
-  const int ib0 = kb + 2 + blockIdx.x;
-  if (ib0 < nb) FK_TILE_FETCH(Al + (size_t)ib0 * NB * Np + kb * NB, Np);
   __syncthreads();
 #pragma unroll
   for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
     for (int v = 0; v < 4; ++v) Bs[NB + 16 * w + 4 * lk + v][ct * 16 + li] = acc[ct][v];
-  if (ib0 < nb) FK_TILE_STAGE(Ls[1]);
+  if (ib0 < nb) FK_TILE_STAGE_FROM(Ls[1], ns0, ns1, ns2, ns3);
   __syncthreads();
   if (blockIdx.x == 0) {
     float* Yl = Y + (size_t)l * ncol * Np;
@@ -957,14 +1003,6 @@ __global__ __launch_bounds__(256) void k_fwd2_mfma(const float* __restrict__ A, 
       Yl[(size_t)t * Np + kb * NB + r] = Bs[r][t];
     }
   }
-  float rr[NCT][4];
-#define FK_R_FETCH(RB)                                                                         \
-  _Pragma("unroll") for (int ct = 0; ct < NCT; ++ct) {                                         \
-    const int t_ = min(ct * 16 + li, ncol - 1);                                                \
-    _Pragma("unroll") for (int v = 0; v < 4; ++v)                                              \
-      rr[ct][v] = Rl[(size_t)t_ * Np + (RB) * NB + 16 * w + 4 * lk + v];                       \
-  }
-  if (ib0 < nb) FK_R_FETCH(ib0)
   int cur = 1;
   for (int ib = ib0; ib < nb; ib += gridDim.x) {
     // tile (ib, kb) is in Ls[cur]; (ib, kb + 1) comes next
@@ -1008,14 +1046,36 @@ __global__ __launch_bounds__(256) void k_bwd2_mfma(const float* __restrict__ A, 
   float* Yl = Yv + (size_t)l * ncol * Np;
   const float* Ak = A + (size_t)l * Np * Np + (size_t)kb * NB * Np;         // block row kb
   const float* Ak1 = A + (size_t)l * Np * Np + (size_t)(kb - 1) * NB * Np;  // block row kb - 1
-  for (int i = threadIdx.x; i < 2 * NB * 16 * NCT; i += blockDim.x) {
-    const int t = i / (2 * NB), k = i - t * (2 * NB);
+  const int jb0 = blockIdx.x;
+  // every global load of the two diagonal steps and of the first row goes out here
+  constexpr int NBS = 2 * NB * 16 * NCT / 256;   // right-hand-side entries per thread
+  float bsv[NBS];
+#pragma unroll
+  for (int u = 0; u < NBS; ++u) {
+    const int i = threadIdx.x + 256 * u, t = i / (2 * NB), k = i - t * (2 * NB);
     const int row = k < NB ? kb * NB + k : (kb - 1) * NB + (k - NB);
-    Bs[k][t] = t < ncol ? Yl[(size_t)t * Np + row] : 0.f;
+    bsv[u] = t < ncol ? Yl[(size_t)t * Np + row] : 0.f;
   }
-  load_tile(Ls[0], Linv + ((size_t)l * nb + kb) * NB * NB, NB);
-  uint4 nt0, nt1, nt2, nt3;
+  float4 d00, d01, d02, d03, d10, d11, d12, d13;
+  FK_F32_FETCH_TO(Linv + ((size_t)l * nb + kb) * NB * NB, d00, d01, d02, d03);
+  FK_F32_FETCH_TO(Linv + ((size_t)l * nb + kb - 1) * NB * NB, d10, d11, d12, d13);
+  uint4 nt0, nt1, nt2, nt3, ns0, ns1, ns2, ns3;
   FK_TILE_FETCH(Ak + (kb - 1) * NB, Np);   // L[kb][kb-1]
+  if (jb0 < kb - 1) FK_TILE_FETCH_TO(Ak + jb0 * NB, Np, ns0, ns1, ns2, ns3);
+  float rr[NCT][4];
+#define FK_R_FETCH(RB)                                                                         \
+  _Pragma("unroll") for (int ct = 0; ct < NCT; ++ct) {                                         \
+    const int t_ = min(ct * 16 + li, ncol - 1);                                                \
+    _Pragma("unroll") for (int v = 0; v < 4; ++v)                                              \
+      rr[ct][v] = Yl[(size_t)t_ * Np + (RB) * NB + 16 * w + 4 * lk + v];                       \
+  }
+  if (jb0 < kb - 1) FK_R_FETCH(jb0)
+#pragma unroll
+  for (int u = 0; u < NBS; ++u) {
+    const int i = threadIdx.x + 256 * u, t = i / (2 * NB), k = i - t * (2 * NB);
+    Bs[k][t] = bsv[u];
+  }
+  FK_F32_STAGE_FROM(Ls[0], d00, d01, d02, d03);
   FK_TILE_STAGE(Ls[1]);
   __syncthreads();
   floatx4 acc[NCT];
@@ -1031,17 +1091,15 @@ __global__ __launch_bounds__(256) void k_bwd2_mfma(const float* __restrict__ A, 
   for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
     for (int v = 0; v < 4; ++v) Bs[NB + 16 * w + 4 * lk + v][ct * 16 + li] -= acc[ct][v];
-  load_tile(Ls[0], Linv + ((size_t)l * nb + kb - 1) * NB * NB, NB);
+  FK_F32_STAGE_FROM(Ls[0], d10, d11, d12, d13);
   __syncthreads();
   mfma_64xK<true, NCT>(Ls[0], Bs + NB, acc);   // x_{kb-1}
-  const int jb0 = blockIdx.x;
-  if (jb0 < kb - 1) FK_TILE_FETCH(Ak + jb0 * NB, Np);
   __syncthreads();
 #pragma unroll
   for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
     for (int v = 0; v < 4; ++v) Bs[NB + 16 * w + 4 * lk + v][ct * 16 + li] = acc[ct][v];
-  if (jb0 < kb - 1) FK_TILE_STAGE(Ls[1]);
+  if (jb0 < kb - 1) FK_TILE_STAGE_FROM(Ls[1], ns0, ns1, ns2, ns3);
   __syncthreads();
   if (blockIdx.x == 0) {
     float* Xl = X + (size_t)l * ncol * Np;
@@ -1051,14 +1109,6 @@ __global__ __launch_bounds__(256) void k_bwd2_mfma(const float* __restrict__ A, 
       Xl[(size_t)t * Np + row] = Bs[k][t];
     }
   }
-  float rr[NCT][4];
-#define FK_R_FETCH(RB)                                                                         \
-  _Pragma("unroll") for (int ct = 0; ct < NCT; ++ct) {                                         \
-    const int t_ = min(ct * 16 + li, ncol - 1);                                                \
-    _Pragma("unroll") for (int v = 0; v < 4; ++v)                                              \
-      rr[ct][v] = Yl[(size_t)t_ * Np + (RB) * NB + 16 * w + 4 * lk + v];                       \
-  }
-  if (jb0 < kb - 1) FK_R_FETCH(jb0)
   int cur = 1;
   for (int jb = jb0; jb < kb - 1; jb += gridDim.x) {
     // tile (kb, jb) is in Ls[cur]; (kb - 1, jb) comes next
@@ -1565,7 +1615,7 @@ static fk_status tune_dense(fk_ctx* ctx, const SolveLayout& s, DenseShape* out, 
   const size_t nv = (size_t)s.nlam * s.ntgt * s.Np;
   FK_HIP(hipMemsetAsync(s.R32, 0, sizeof(float) * nv, ctx->stream));
   float best_t = 0.f;
-  for (int wg : {512, 256, 1024}) {
+  for (int wg : {512, 768, 256, 1024}) {
     DenseShape c = sh;
     c.trsm_wg = wg;
     FK_HIP(hipEventRecord(e0, ctx->stream));

@@ -159,7 +159,7 @@ constexpr int kSortSliceMin = 32768;
 
 // Launch shape of the dense solve.
 struct DenseShape {
-  int trsm_wg = 512;          // workgroups per triangular-solve launch (over all lambdas)
+  int trsm_wg = 768;          // workgroups per triangular-solve launch (over all lambdas; 3 per CU)
   int pair = 1;               // factor block columns in pairs (row panels read once for two)
   int diag64 = 0;             // diagonal blocks factored in FP64 (1) or FP32 (0)
 };
