@@ -345,11 +345,36 @@ __device__ __forceinline__ void mfma_tile64(const float* As, const float* Bs, fl
 
 // Load a 64 x 64 FP32 tile (row-major, leading dimension ld) into LDS (rows of LDT
 // floats, 16-byte aligned).
-__device__ __forceinline__ void load_tile(float* T, const float* src, int64_t ld) {
-  for (int i = threadIdx.x; i < NB * NB / 4; i += blockDim.x) {
-    int r = i / (NB / 4), c = (i - r * (NB / 4)) * 4;
-    *reinterpret_cast<float4*>(T + r * LDT + c) = *reinterpret_cast<const float4*>(src + r * ld + c);
-  }
+// A 64 x 64 FP32 tile (row stride ld) in four float4 registers per lane of a 256-thread
+// workgroup, and its store into an LDS tile of row stride LDT (named registers: an array would be
+// kept in scratch memory by the compiler where it lives across other work).
+#define FK_F32_LOAD4(src, ld, a0, a1, a2, a3)                                                \
+  do {                                                                                       \
+    _Pragma("unroll") for (int u_ = 0; u_ < 4; ++u_) {                                       \
+      const int i_ = threadIdx.x + 256 * u_, r_ = i_ / (NB / 4), c_ = (i_ - r_ * (NB / 4)) * 4; \
+      const float4 v_ = *reinterpret_cast<const float4*>((src) + r_ * (ld) + c_);          \
+      if (u_ == 0) a0 = v_;                                                                  \
+      if (u_ == 1) a1 = v_;                                                                  \
+      if (u_ == 2) a2 = v_;                                                                  \
+      if (u_ == 3) a3 = v_;                                                                  \
+    }                                                                                        \
+  } while (0)
+#define FK_F32_STORE4(T, a0, a1, a2, a3)                                                     \
+  do {                                                                                       \
+    _Pragma("unroll") for (int u_ = 0; u_ < 4; ++u_) {                                       \
+      const int i_ = threadIdx.x + 256 * u_, r_ = i_ / (NB / 4), c_ = (i_ - r_ * (NB / 4)) * 4; \
+      *reinterpret_cast<float4*>((T) + r_ * LDT + c_) = u_ == 0 ? a0 : u_ == 1 ? a1 : u_ == 2 ? a2 : a3; \
+    }                                                                                        \
+  } while (0)
+
+// Two tiles into LDS, all eight loads of a lane issued before any store (one memory latency).
+__device__ __forceinline__ void load_tiles2(float* T0, const float* src0, int64_t ld0, float* T1, const float* src1,
+                                            int64_t ld1) {
+  float4 v0, v1, v2, v3, w0, w1, w2, w3;
+  FK_F32_LOAD4(src0, ld0, v0, v1, v2, v3);
+  FK_F32_LOAD4(src1, ld1, w0, w1, w2, w3);
+  FK_F32_STORE4(T0, v0, v1, v2, v3);
+  FK_F32_STORE4(T1, w0, w1, w2, w3);
 }
 
 // dst tile (+)= sign * acc
@@ -633,8 +658,9 @@ __global__ __launch_bounds__(256) void k_potrf_diag(float* __restrict__ A, int N
     const int c = 4 * u + q;
     Li[r * NB + c] = (c <= r) ? (float)(a[u] * rs) : 0.0f;
   }
-  for (int i = threadIdx.x; i < NB * NB; i += blockDim.x) {
-    const int rr = i / NB, c = i - rr * NB;
+#pragma unroll
+  for (int u = 0; u < NB * NB / 256; ++u) {   // 256 threads
+    const int i = threadIdx.x + 256 * u, rr = i / NB, c = i - rr * NB;
     float v = 0.0f;
     if (c == rr) v = (float)sq[c];
     else if (c < rr) v = (float)(P[rr][c] * rsq[c]);
@@ -655,9 +681,8 @@ __global__ __launch_bounds__(256) void k_trsm_panel(float* __restrict__ A, int N
   ib += kb + 1;
   float* Al = A + (size_t)l * Np * Np;
   float* src = Al + (size_t)ib * NB * Np + kb * NB;
-  load_tile(As, src, Np);
   const float* Li = Linv + ((size_t)l * (Np / NB) + kb) * NB * NB;
-  load_tile(Bs, Li, NB);
+  load_tiles2(As, src, Np, Bs, Li, NB);
   __syncthreads();
   floatx4 acc[2][2] = {};
   mfma_tile64(As, Bs, acc);
@@ -761,28 +786,6 @@ __device__ __forceinline__ void mfma_64xK(const float* Ls, const float (*Bs)[LDB
 #define FK_TILE_FETCH(src, ld) FK_TILE_FETCH_TO(src, ld, nt0, nt1, nt2, nt3)
 #define FK_TILE_STAGE(T) FK_TILE_STAGE_FROM(T, nt0, nt1, nt2, nt3)
 
-// A contiguous 64 x 64 FP32 tile (an inverted diagonal block) in four float4 registers per lane,
-// and its store into an LDS tile of row stride LDT (256 threads).  Named registers rather than an
-// array, which the compiler would keep in scratch memory across the products.
-#define FK_F32_FETCH_TO(src, a0, a1, a2, a3)                                                 \
-  do {                                                                                       \
-    _Pragma("unroll") for (int u_ = 0; u_ < 4; ++u_) {                                       \
-      const int i_ = threadIdx.x + 256 * u_, r_ = i_ / (NB / 4), c_ = (i_ - r_ * (NB / 4)) * 4; \
-      const float4 v_ = *reinterpret_cast<const float4*>((src) + r_ * NB + c_);            \
-      if (u_ == 0) a0 = v_;                                                                  \
-      if (u_ == 1) a1 = v_;                                                                  \
-      if (u_ == 2) a2 = v_;                                                                  \
-      if (u_ == 3) a3 = v_;                                                                  \
-    }                                                                                        \
-  } while (0)
-#define FK_F32_STAGE_FROM(T, a0, a1, a2, a3)                                                 \
-  do {                                                                                       \
-    _Pragma("unroll") for (int u_ = 0; u_ < 4; ++u_) {                                       \
-      const int i_ = threadIdx.x + 256 * u_, r_ = i_ / (NB / 4), c_ = (i_ - r_ * (NB / 4)) * 4; \
-      *reinterpret_cast<float4*>((T) + r_ * LDT + c_) = u_ == 0 ? a0 : u_ == 1 ? a1 : u_ == 2 ? a2 : a3; \
-    }                                                                                        \
-  } while (0)
-
 // Forward step kb of L y = r for every lambda (grid.y): y_kb = inv(L_kk) r_kb, written
 // by block 0; block x then updates rows ib = kb + 1 + x, kb + 1 + x + gridDim.x, ...:
 // r_ib -= L[ib][kb] y_kb, with the next row's tile loaded while the current one is
@@ -799,14 +802,25 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const float* __restrict__ A, i
   const int li = lane & 15, lk = lane >> 4;
   float* Rl = R + (size_t)l * ncol * Np;
   const float* Al = A + (size_t)l * Np * Np;
-  for (int i = threadIdx.x; i < NB * 16 * NCT; i += blockDim.x) {
-    const int t = i / NB, k = i - t * NB;
-    Bs[k][t] = t < ncol ? Rl[(size_t)t * Np + kb * NB + k] : 0.f;
-  }
-  load_tile(Ls[0], Linv + ((size_t)l * nb + kb) * NB * NB, NB);
+  // every load of the prologue goes out before any is used
   int ib = kb + 1 + blockIdx.x;
   uint4 nt0, nt1, nt2, nt3;
   if (ib < nb) FK_TILE_FETCH(Al + (size_t)ib * NB * Np + kb * NB, Np);
+  constexpr int NBS = NB * 16 * NCT / 256;   // right-hand-side entries per thread
+  float bsv[NBS];
+#pragma unroll
+  for (int u = 0; u < NBS; ++u) {
+    const int i = threadIdx.x + 256 * u, t = i / NB, k = i - t * NB;
+    bsv[u] = t < ncol ? Rl[(size_t)t * Np + kb * NB + k] : 0.f;
+  }
+  float4 d0, d1, d2, d3;
+  FK_F32_LOAD4(Linv + ((size_t)l * nb + kb) * NB * NB, NB, d0, d1, d2, d3);
+#pragma unroll
+  for (int u = 0; u < NBS; ++u) {
+    const int i = threadIdx.x + 256 * u, t = i / NB, k = i - t * NB;
+    Bs[k][t] = bsv[u];
+  }
+  FK_F32_STORE4(Ls[0], d0, d1, d2, d3);
   __syncthreads();
   floatx4 acc[NCT];
   mfma_64xK<false, NCT>(Ls[0], Bs, acc);
@@ -868,14 +882,25 @@ __global__ __launch_bounds__(256) void k_bwd_mfma(const float* __restrict__ A, i
   const int li = lane & 15, lk = lane >> 4;
   float* Yl = Yv + (size_t)l * ncol * Np;
   const float* Ak = A + (size_t)l * Np * Np + (size_t)kb * NB * Np;
-  for (int i = threadIdx.x; i < NB * 16 * NCT; i += blockDim.x) {
-    const int t = i / NB, k = i - t * NB;
-    Bs[k][t] = t < ncol ? Yl[(size_t)t * Np + kb * NB + k] : 0.f;
-  }
-  load_tile(Ls[0], Linv + ((size_t)l * nb + kb) * NB * NB, NB);
+  // every load of the prologue goes out before any is used
   int jb = blockIdx.x;
   uint4 nt0, nt1, nt2, nt3;
   if (jb < kb) FK_TILE_FETCH(Ak + jb * NB, Np);
+  constexpr int NBS = NB * 16 * NCT / 256;   // right-hand-side entries per thread
+  float bsv[NBS];
+#pragma unroll
+  for (int u = 0; u < NBS; ++u) {
+    const int i = threadIdx.x + 256 * u, t = i / NB, k = i - t * NB;
+    bsv[u] = t < ncol ? Yl[(size_t)t * Np + kb * NB + k] : 0.f;
+  }
+  float4 d0, d1, d2, d3;
+  FK_F32_LOAD4(Linv + ((size_t)l * nb + kb) * NB * NB, NB, d0, d1, d2, d3);
+#pragma unroll
+  for (int u = 0; u < NBS; ++u) {
+    const int i = threadIdx.x + 256 * u, t = i / NB, k = i - t * NB;
+    Bs[k][t] = bsv[u];
+  }
+  FK_F32_STORE4(Ls[0], d0, d1, d2, d3);
   __syncthreads();
   floatx4 acc[NCT];
   mfma_64xK<true, NCT>(Ls[0], Bs, acc);
@@ -951,8 +976,8 @@ __global__ __launch_bounds__(256) void k_fwd2_mfma(const float* __restrict__ A, 
     bsv[u] = t < ncol ? Rl[(size_t)t * Np + kb * NB + k] : 0.f;
   }
   float4 d00, d01, d02, d03, d10, d11, d12, d13;
-  FK_F32_FETCH_TO(Linv + ((size_t)l * nb + kb) * NB * NB, d00, d01, d02, d03);
-  FK_F32_FETCH_TO(Linv + ((size_t)l * nb + kb + 1) * NB * NB, d10, d11, d12, d13);
+  FK_F32_LOAD4(Linv + ((size_t)l * nb + kb) * NB * NB, NB, d00, d01, d02, d03);
+  FK_F32_LOAD4(Linv + ((size_t)l * nb + kb + 1) * NB * NB, NB, d10, d11, d12, d13);
   uint4 nt0, nt1, nt2, nt3, ns0, ns1, ns2, ns3;
   FK_TILE_FETCH(Al + (size_t)(kb + 1) * NB * Np + kb * NB, Np);
   if (ib0 < nb) FK_TILE_FETCH_TO(Al + (size_t)ib0 * NB * Np + kb * NB, Np, ns0, ns1, ns2, ns3);
@@ -970,7 +995,7 @@ __global__ __launch_bounds__(256) void k_fwd2_mfma(const float* __restrict__ A, 
     const int i = threadIdx.x + 256 * u, t = i / (2 * NB), k = i - t * (2 * NB);
     Bs[k][t] = bsv[u];
   }
-  FK_F32_STAGE_FROM(Ls[0], d00, d01, d02, d03);
+  FK_F32_STORE4(Ls[0], d00, d01, d02, d03);
   FK_TILE_STAGE(Ls[1]);
   __syncthreads();
   floatx4 acc[NCT];
@@ -986,7 +1011,7 @@ __global__ __launch_bounds__(256) void k_fwd2_mfma(const float* __restrict__ A, 
   for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
     for (int v = 0; v < 4; ++v) Bs[NB + 16 * w + 4 * lk + v][ct * 16 + li] -= acc[ct][v];
-  FK_F32_STAGE_FROM(Ls[0], d10, d11, d12, d13);
+  FK_F32_STORE4(Ls[0], d10, d11, d12, d13);
   __syncthreads();
   mfma_64xK<false, NCT>(Ls[0], Bs + NB, acc);   // y_{kb+1}
   __syncthreads();
@@ -1057,8 +1082,8 @@ __global__ __launch_bounds__(256) void k_bwd2_mfma(const float* __restrict__ A, 
     bsv[u] = t < ncol ? Yl[(size_t)t * Np + row] : 0.f;
   }
   float4 d00, d01, d02, d03, d10, d11, d12, d13;
-  FK_F32_FETCH_TO(Linv + ((size_t)l * nb + kb) * NB * NB, d00, d01, d02, d03);
-  FK_F32_FETCH_TO(Linv + ((size_t)l * nb + kb - 1) * NB * NB, d10, d11, d12, d13);
+  FK_F32_LOAD4(Linv + ((size_t)l * nb + kb) * NB * NB, NB, d00, d01, d02, d03);
+  FK_F32_LOAD4(Linv + ((size_t)l * nb + kb - 1) * NB * NB, NB, d10, d11, d12, d13);
   uint4 nt0, nt1, nt2, nt3, ns0, ns1, ns2, ns3;
   FK_TILE_FETCH(Ak + (kb - 1) * NB, Np);   // L[kb][kb-1]
   if (jb0 < kb - 1) FK_TILE_FETCH_TO(Ak + jb0 * NB, Np, ns0, ns1, ns2, ns3);
@@ -1075,7 +1100,7 @@ __global__ __launch_bounds__(256) void k_bwd2_mfma(const float* __restrict__ A, 
     const int i = threadIdx.x + 256 * u, t = i / (2 * NB), k = i - t * (2 * NB);
     Bs[k][t] = bsv[u];
   }
-  FK_F32_STAGE_FROM(Ls[0], d00, d01, d02, d03);
+  FK_F32_STORE4(Ls[0], d00, d01, d02, d03);
   FK_TILE_STAGE(Ls[1]);
   __syncthreads();
   floatx4 acc[NCT];
@@ -1091,7 +1116,7 @@ __global__ __launch_bounds__(256) void k_bwd2_mfma(const float* __restrict__ A, 
   for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
     for (int v = 0; v < 4; ++v) Bs[NB + 16 * w + 4 * lk + v][ct * 16 + li] -= acc[ct][v];
-  FK_F32_STAGE_FROM(Ls[0], d10, d11, d12, d13);
+  FK_F32_STORE4(Ls[0], d10, d11, d12, d13);
   __syncthreads();
   mfma_64xK<true, NCT>(Ls[0], Bs + NB, acc);   // x_{kb-1}
   __syncthreads();
