@@ -248,23 +248,57 @@ __global__ void k_make_scale(const double* __restrict__ H, const double* __restr
 }
 
 // A32[l] = S_l (H64 + lambda_l diag(p_real)) S_l in FP32, identity padding; blocks
-// above the block diagonal are not written (no kernel reads them).
+// above the block diagonal are not written (no kernel reads them).  One workgroup per 64 x 64
+// tile of the lower block triangle (blockIdx.x enumerates them row by row); a thread takes four
+// consecutive columns of four rows of H64, read once, and writes them for every lambda.
 __global__ __launch_bounds__(256) void k_make_a32(const double* __restrict__ H, const double* __restrict__ preal,
                                                   const double* __restrict__ lams, const double* __restrict__ scl,
                                                   int N, int Np, int nlam, float* __restrict__ A) {
-  // one element of H64, read once, written for every lambda
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)Np * Np) return;
-  const int r = (int)(idx / Np), s = (int)(idx - (int64_t)r * Np);
-  if (s / NB > r / NB) return;   // the factorization reads only the lower block triangle
-  const bool in = r < N && s < N;
-  const double h = in ? H[idx] : 0.0;
-  const double pr = (in && r == s) ? preal[r] : 0.0;
-  const float pad = (r == s) ? 1.0f : 0.0f;
+  // tile index x -> (rb, cb), cb <= rb, x = rb (rb + 1) / 2 + cb
+  const int x = blockIdx.x;
+  int rb = (int)((sqrt(8.0 * x + 1.0) - 1.0) * 0.5);
+  while ((rb + 1) * (rb + 2) / 2 <= x) ++rb;
+  while (rb * (rb + 1) / 2 > x) --rb;
+  const int cb = x - rb * (rb + 1) / 2;
+  const int cc = (threadIdx.x & 15) * 4, r0 = threadIdx.x >> 4;
+  const int s = cb * NB + cc;
+  double h[4][4], pr[4];
+  int rows[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int r = rb * NB + r0 + 16 * u;
+    rows[u] = r;
+    pr[u] = (r < N) ? preal[r] : 0.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) h[u][e] = (r < N && s + e < N) ? H[(size_t)r * Np + s + e] : 0.0;
+  }
   for (int l = 0; l < nlam; ++l) {
     const double* sl = scl + (size_t)l * Np;
-    A[(size_t)l * Np * Np + idx] = in ? (float)(sl[r] * (h + lams[l] * pr) * sl[s]) : pad;
+    const double lam = lams[l];
+    double ss[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) ss[e] = sl[s + e];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = rows[u];
+      const double sr = sl[r];
+      float o[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c = s + e;
+        const bool in = r < N && c < N;
+        const double pd = (in && r == c) ? pr[u] : 0.0;
+        o[e] = in ? (float)(sr * (h[u][e] + lam * pd) * ss[e]) : (r == c ? 1.0f : 0.0f);
+      }
+      *reinterpret_cast<float4*>(A + (size_t)l * Np * Np + (size_t)r * Np + s) = make_float4(o[0], o[1], o[2], o[3]);
+    }
   }
+}
+
+// Workgroups of k_make_a32: the 64 x 64 tiles of the lower block triangle.
+static unsigned a32_tiles(int Np) {
+  const unsigned nb = (unsigned)(Np / NB);
+  return nb * (nb + 1) / 2;
 }
 
 // preal[r] = p[complex mode of r]
@@ -1622,7 +1656,7 @@ static fk_status tune_dense(fk_ctx* ctx, const SolveLayout& s, DenseShape* out, 
   for (int pair : {1, 0}) {
     DenseShape c = sh;
     c.pair = pair;
-    hipLaunchKernelGGL(k_make_a32, dim3(gb), dim3(256), 0, ctx->stream, s.H64, s.preal, s.lams, s.scl, s.N, s.Np,
+    hipLaunchKernelGGL(k_make_a32, dim3(a32_tiles(s.Np)), dim3(256), 0, ctx->stream, s.H64, s.preal, s.lams, s.scl, s.N, s.Np,
                        s.nlam, s.A32);
     FK_HIP(hipEventRecord(e0, ctx->stream));
     fk_status st = factor_all(ctx, s, c);
@@ -1690,7 +1724,7 @@ fk_status solve_impl(fk_ctx* ctx, const SolveProblem& P, const SolveLayout& s, d
   }
   hipLaunchKernelGGL(k_make_scale, dim3((Np + 255) / 256, s.nlam), dim3(256), 0, ctx->stream, s.H64, s.preal,
                      s.lams, N, Np, s.scl);
-  hipLaunchKernelGGL(k_make_a32, dim3(gb), dim3(256), 0, ctx->stream, s.H64, s.preal, s.lams, s.scl, N, Np,
+  hipLaunchKernelGGL(k_make_a32, dim3(a32_tiles(Np)), dim3(256), 0, ctx->stream, s.H64, s.preal, s.lams, s.scl, N, Np,
                      s.nlam, s.A32);
   hipLaunchKernelGGL(k_rhs_real, dim3((Np + 255) / 256, s.ntgt), dim3(256), 0, ctx->stream, P.b, N, L, Np,
                      s.ntgt, s.Bre);
