@@ -692,11 +692,23 @@ template <typename TY>
 __global__ __launch_bounds__(256) void k_sum_squares(const TY* __restrict__ Y, int64_t n, double* __restrict__ out) {
   __shared__ double part[4];
   const TY* y = Y + (int64_t)blockIdx.y * n;
-  double s = 0.0;
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-    const double v = (double)y[j];
-    s += v * v;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // four loads in flight per thread, four partial sums
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  for (; j + 3 * stride < n; j += 4 * stride) {
+    const double v0 = (double)y[j], v1 = (double)y[j + stride], v2 = (double)y[j + 2 * stride],
+                 v3 = (double)y[j + 3 * stride];
+    s0 = fma(v0, v0, s0);
+    s1 = fma(v1, v1, s1);
+    s2 = fma(v2, v2, s2);
+    s3 = fma(v3, v3, s3);
   }
+  for (; j < n; j += stride) {
+    const double v = (double)y[j];
+    s0 = fma(v, v, s0);
+  }
+  double s = (s0 + s1) + (s2 + s3);
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
   __syncthreads();

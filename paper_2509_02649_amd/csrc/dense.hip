@@ -26,6 +26,7 @@
 #include <cmath>
 #include <cstdio>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 namespace fk {
@@ -164,6 +165,39 @@ struct ToeplitzQ {
     }
     return {M[2 * idx], M[2 * idx + 1]};
   }
+  // Linear offset of mode i in the generator grid (sum over axes of k_a G^a): the entry (i, j) is at
+  // off(j) - off(i) + centre, so four entries of one real-form element need four decodes, not eight.
+  __device__ int off(int i) const {
+    const int L = 2 * m + 1, G = 4 * m + 1;
+    int o = 0, mul = 1;
+    for (int a = d - 1; a >= 0; --a) {
+      const int qd = i / L;
+      o += (i - qd * L - m) * mul;
+      i = qd;
+      mul *= G;
+    }
+    return o;
+  }
+  __device__ int centre() const {
+    const int G = 4 * m + 1;
+    int c = 0, mul = 1;
+    for (int a = 0; a < d; ++a) {
+      c += 2 * m * mul;
+      mul *= G;
+    }
+    return c;
+  }
+};
+
+// The four complex entries that real_entry reads for one real-form element (modes k, -k of the
+// row and l, -l of the column), through mode offsets: entry (i, j) at M[off(j) - off(i) + centre].
+struct ToeplitzPairQ {
+  const double* M;
+  int c, k, l, ok, onk, ol, onl;
+  __device__ cplx operator()(int i, int j) const {
+    const int idx = (j == l ? ol : onl) - (i == k ? ok : onk) + c;
+    return {M[2 * idx], M[2 * idx + 1]};
+  }
 };
 
 // Physics-informed penalty of a box (Sec. 4, tractable domains): mu conj(D_k) C[k, l] D_l with the
@@ -226,7 +260,17 @@ __global__ __launch_bounds__(256) void k_assemble_real(Q q, int N, int L, int Np
   if (idx >= (int64_t)Np * Np) return;
   int r = (int)(idx / Np), s = (int)(idx - (int64_t)r * Np);
   double v = 0.0;
-  if (r < N && s < N) v = real_entry(q, r, s, L);
+  if (r < N && s < N) {
+    if constexpr (std::is_same<Q, ToeplitzQ>::value) {
+      int tr, k, nk, ts, l, nl;
+      real_to_complex(r, L, &tr, &k, &nk);
+      real_to_complex(s, L, &ts, &l, &nl);
+      const ToeplitzPairQ pq{q.M, q.centre(), k, l, q.off(k), q.off(nk), q.off(l), q.off(nl)};
+      v = real_entry(pq, r, s, L);
+    } else {
+      v = real_entry(q, r, s, L);
+    }
+  }
   H[idx] = v;
 }
 
