@@ -653,7 +653,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // Factor the diagonal block kb of every lambda (one workgroup per lambda) in Real (FP32, or FP64
 // when the launch shape asks for it); write L_kk (lower) back and inv(L_kk) to Linv[l][kb].
 // Within the 64 x 64 block the sweep is right-looking:
-// Thread (r, q) = (tid / 4, tid % 4) keeps entries r, q + 4u (u = 0..15) of the block, and
+// Thread (r, q) = (tid / 8, tid % 8) keeps entries r, q + 8u (u = 0..7) of the block, and
 // of T below, in registers.  Unscaled: at step j column j has received every
 // update, its owners publish it to P[.][j] (never written again), one barrier, and each row
 // below applies a[r][k] -= f P[k][j] with f = P[r][j] / P[j][j].  Then L[r][c] = P[r][c] /
@@ -661,20 +661,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // T[i][c] = delta_ic - sum_{k<i} (P[i][k] / P[k][k]) T[k][c], so row j of T is final at step j,
 // is published with column j (two-slot LDS buffer), and rows r > j take t[r][.] -= f T[j][.]
 // in the same step: one sweep of 64 barriers for the factor and its inverse.
+constexpr int kPotrfThreads = 512;
 template <typename Real>
-__global__ __launch_bounds__(256) void k_potrf_diag(float* __restrict__ A, int Np, int kb,
+__global__ __launch_bounds__(kPotrfThreads) void k_potrf_diag(float* __restrict__ A, int Np, int kb,
                                                     float* __restrict__ Linv, int* flags) {
   __shared__ Real P[NB][NB + 1];
   __shared__ Real trow[2][NB];
   __shared__ Real piv[NB], sq[NB], rsq[NB];
   __shared__ int bad;
+  constexpr int TPR = kPotrfThreads / NB, EPT = NB / TPR;   // threads per row, entries per thread
   const int l = blockIdx.x;
   float* Ab = A + (size_t)l * Np * Np + (size_t)kb * NB * Np + kb * NB;
-  const int r = threadIdx.x >> 2, q = threadIdx.x & 3;
-  Real a[16], t[16];
+  const int r = threadIdx.x / TPR, q = threadIdx.x % TPR;
+  Real a[EPT], t[EPT];
 #pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int k = 4 * u + q;
+  for (int u = 0; u < EPT; ++u) {
+    const int k = TPR * u + q;
     a[u] = (k <= r) ? (Real)Ab[(size_t)r * Np + k] : Real(0);
     t[u] = (k == r) ? Real(1) : Real(0);
   }
@@ -682,34 +684,34 @@ __global__ __launch_bounds__(256) void k_potrf_diag(float* __restrict__ A, int N
   // unrolled, so that the register holding column j is known at compile time
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    if (q == (j & 3) && r >= j) {
+    if (q == (j % TPR) && r >= j) {
       Real v = a[0];
 #pragma unroll
-      for (int u = 1; u < 16; ++u)
-        if (u == (j >> 2)) v = a[u];
+      for (int u = 1; u < EPT; ++u)
+        if (u == (j / TPR)) v = a[u];
       P[r][j] = v;
     }
     if (r == j) {
 #pragma unroll
-      for (int u = 0; u < 16; ++u) trow[j & 1][4 * u + q] = t[u];
+      for (int u = 0; u < EPT; ++u) trow[j & 1][TPR * u + q] = t[u];
     }
     __syncthreads();
     // all loads first and unconditionally (rows k < j of P[.][j] are not yet written:
     // their values are discarded by the select), so the reads share one wait
     const Real pj = P[j][j];
     const Real prj = P[r][j];
-    Real pk[16], tv[16];
+    Real pk[EPT], tv[EPT];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      pk[u] = P[4 * u + q][j];
-      tv[u] = trow[j & 1][4 * u + q];
+    for (int u = 0; u < EPT; ++u) {
+      pk[u] = P[TPR * u + q][j];
+      tv[u] = trow[j & 1][TPR * u + q];
     }
     const bool badj = !(pj > Real(0));  // non-positive or NaN pivot
     const Real rp = recip_t(badj ? Real(1) : pj);
     const Real f = r > j ? prj * rp : Real(0);
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int k = 4 * u + q;
+    for (int u = 0; u < EPT; ++u) {
+      const int k = TPR * u + q;
       const Real upd = fma(-f, pk[u], a[u]);
       a[u] = (k > j && k <= r) ? upd : a[u];
       t[u] = fma(-f, tv[u], t[u]);   // T[j][c] = 0 for c > j: no change there
@@ -719,9 +721,9 @@ __global__ __launch_bounds__(256) void k_potrf_diag(float* __restrict__ A, int N
       if (badj) bad = 1;
     }
   }
-  // t[] holds T[r][q + 4u]
+  // t[] holds T[r][q + TPR u]
 #pragma unroll
-  for (int u = 0; u < 16; ++u) a[u] = t[u];
+  for (int u = 0; u < EPT; ++u) a[u] = t[u];
   __syncthreads();   // the last pivot (thread 0, after the last step's barrier)
   if (threadIdx.x < NB) {
     const Real d = sqrt(piv[threadIdx.x]);
@@ -732,13 +734,13 @@ __global__ __launch_bounds__(256) void k_potrf_diag(float* __restrict__ A, int N
   float* Li = Linv + ((size_t)l * (Np / NB) + kb) * NB * NB;
   const Real rs = rsq[r];
 #pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int c = 4 * u + q;
+  for (int u = 0; u < EPT; ++u) {
+    const int c = TPR * u + q;
     Li[r * NB + c] = (c <= r) ? (float)(a[u] * rs) : 0.0f;
   }
 #pragma unroll
-  for (int u = 0; u < NB * NB / 256; ++u) {   // 256 threads
-    const int i = threadIdx.x + 256 * u, rr = i / NB, c = i - rr * NB;
+  for (int u = 0; u < NB * NB / kPotrfThreads; ++u) {
+    const int i = threadIdx.x + kPotrfThreads * u, rr = i / NB, c = i - rr * NB;
     float v = 0.0f;
     if (c == rr) v = (float)sq[c];
     else if (c < rr) v = (float)(P[rr][c] * rsq[c]);
@@ -1492,10 +1494,10 @@ static fk_status factor_all(fk_ctx* ctx, const SolveLayout& s, const DenseShape&
   const int nb = s.Np / NB;
   auto finish = [&](int kb) {   // diagonal block and the panel below it
     if (sh.diag64)
-      hipLaunchKernelGGL(k_potrf_diag<double>, dim3(s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv,
+      hipLaunchKernelGGL(k_potrf_diag<double>, dim3(s.nlam), dim3(kPotrfThreads), 0, ctx->stream, s.A32, s.Np, kb, s.Linv,
                          ctx->flags);
     else
-      hipLaunchKernelGGL(k_potrf_diag<float>, dim3(s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.Linv,
+      hipLaunchKernelGGL(k_potrf_diag<float>, dim3(s.nlam), dim3(kPotrfThreads), 0, ctx->stream, s.A32, s.Np, kb, s.Linv,
                          ctx->flags);
     const int rem = nb - kb - 1;
     if (rem > 0)
