@@ -603,14 +603,27 @@ __device__ inline float recip_t(float x) {
 // for both columns.  The finished panels are FP16 pairs (split tiles in LDS, products on the
 // FP16 matrix cores); one LDS buffer per operand, the next k's tiles loaded into registers
 // while the current ones are multiplied.
+template <bool PART>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_left_update2(float* __restrict__ A,
                                                                                              int Np, int kb,
-                                                                                             int nlam) {
+                                                                                             int nlam, int nsplit,
+                                                                                             float* __restrict__ part) {
   __shared__ __align__(16) SplitTile As;
   __shared__ __align__(16) SplitTile B0;
   __shared__ __align__(16) SplitTile B1;
-  int l, i;
-  xcd_place(Np / NB - kb, nlam, &l, &i);
+  const int rows = Np / NB - kb;
+  int l, i, k0 = 0, k1 = kb, sidx = 0;
+  if constexpr (PART) {
+    // workgroup (sidx, l, i): panels k0 <= k < k1 of the split sidx of the sum
+    const int b = blockIdx.x;
+    i = b % rows;
+    l = (b / rows) % nlam;
+    sidx = b / (rows * nlam);
+    k0 = (int)((int64_t)kb * sidx / nsplit);
+    k1 = (int)((int64_t)kb * (sidx + 1) / nsplit);
+  } else {
+    xcd_place(rows, nlam, &l, &i);
+  }
   i += kb;
   float* Al = A + (size_t)l * Np * Np;
   const uint32_t* Ai = reinterpret_cast<const uint32_t*>(Al + (size_t)i * NB * Np);
@@ -633,8 +646,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     }
   };
   floatx4 acc[2][2][2] = {}, accx[2][2][2] = {};
-  gload(0);
-  for (int k = 0; k < kb; ++k) {
+  if (k0 < k1) gload(k0);
+  for (int k = k0; k < k1; ++k) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       split_stage(As, off_s[q], ra[q]);
@@ -642,12 +655,67 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       split_stage(B1, off_s[q], rc[q]);
     }
     __syncthreads();
-    if (k + 1 < kb) gload(k + 1);
+    if (k + 1 < k1) gload(k + 1);
     mfma_split64<2>(As, B0, B1, acc, accx);
     __syncthreads();
   }
-  store_split_update(Al + (size_t)i * NB * Np + kb * NB, Np, acc[0], accx[0]);
-  if (i > kb) store_split_update(Al + (size_t)i * NB * Np + (kb + 1) * NB, Np, acc[1], accx[1]);
+  if constexpr (PART) {
+    // this split's part of the 64 x 128 update, row-major, columns kb then kb + 1
+    float* dst = part + ((size_t)(sidx * nlam + l) * rows + (i - kb)) * (NB * 2 * NB);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int rb2 = 0; rb2 < 2; ++rb2)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = r0 + rb2 * 16 + 4 * (lane >> 4) + v;
+            const int c = c0 + cb * 16 + (lane & 15);
+            dst[r * (2 * NB) + t * NB + c] = fmaf(accx[t][rb2][cb][v], 1.f / kSplitScale, acc[t][rb2][cb][v]);
+          }
+  } else {
+    store_split_update(Al + (size_t)i * NB * Np + kb * NB, Np, acc[0], accx[0]);
+    if (i > kb) store_split_update(Al + (size_t)i * NB * Np + (kb + 1) * NB, Np, acc[1], accx[1]);
+  }
+}
+
+// The split update's parts added in a fixed order (the result does not depend on timing) and
+// subtracted from block columns kb, kb + 1 (the tile above the diagonal left alone).  Workgroup
+// (tile, eighth): 256 threads x 4 consecutive entries; all parts of an entry are loaded before the
+// first addition, so a workgroup waits for memory once.
+constexpr int kMaxSplit = 16;
+__global__ __launch_bounds__(256) void k_left_update2_sum(float* __restrict__ A, int Np, int kb, int nlam,
+                                                          int nsplit, const float* __restrict__ part) {
+  const int rows = Np / NB - kb;
+  const int tile_id = blockIdx.x >> 3, eighth = blockIdx.x & 7;
+  const int ii = tile_id % rows, l = tile_id / rows, i = kb + ii;
+  const size_t tile = (size_t)NB * 2 * NB, stride = (size_t)nlam * rows * tile;
+  const int e = (eighth * 256 + threadIdx.x) * 4, r = e / (2 * NB), c = e - r * (2 * NB);
+  if (c >= NB && i == kb) return;   // above the diagonal (all four entries: c is a multiple of 4)
+  const float* src = part + ((size_t)l * rows + ii) * tile + e;
+  float4 v[kMaxSplit];
+#pragma unroll
+  for (int sp = 0; sp < kMaxSplit; ++sp)
+    if (sp < nsplit) v[sp] = *reinterpret_cast<const float4*>(src + sp * stride);
+  float4 sum = v[0];
+#pragma unroll
+  for (int sp = 1; sp < kMaxSplit; ++sp)
+    if (sp < nsplit) {
+      sum.x += v[sp].x;
+      sum.y += v[sp].y;
+      sum.z += v[sp].z;
+      sum.w += v[sp].w;
+    }
+  float4* dst = reinterpret_cast<float4*>(A + (size_t)l * Np * Np + (size_t)i * NB * Np + kb * NB + (size_t)r * Np + c);
+  float4 d = *dst;
+  d.x -= sum.x;
+  d.y -= sum.y;
+  d.z -= sum.z;
+  d.w -= sum.w;
+  *dst = d;
 }
 
 // Factor the diagonal block kb of every lambda (one workgroup per lambda) in Real (FP32, or FP64
@@ -1483,8 +1551,22 @@ SolveLayout solve_layout(int N, int nlam, int ntgt, void* base, size_t cap) {
   s.pcx = cv.take<double>((size_t)N);
   s.scl = cv.take<double>((size_t)nlam * Np);
   s.dsym = cv.take<double>((size_t)2 * N);
+  // parts of the split paired updates: 768 tiles of 64 x 128 at most (fewer for small systems)
+  const int nb = (int)(Np / NB);
+  s.part_tiles = (int)std::min<int64_t>(768, (int64_t)nb * nb * nlam);
+  s.upart = cv.take<float>((size_t)s.part_tiles * NB * 2 * NB);
   s.bytes = ((cv.off + 255) & ~size_t(255)) + 256;   // a multiple of 256: what follows stays aligned
   return s;
+}
+
+// Splits of the paired update's sum over panels when its grid is small (few lambdas, or the last
+// block columns): about three workgroups per CU in all, at least two panels per split, within the
+// workspace's part tiles.  1 = no split.
+static int update_split(int wgs, int kb, int part_tiles) {
+  if (wgs >= 512 || kb < 4) return 1;
+  int ns = std::min(std::min(kb / 2, kMaxSplit), 768 / wgs);
+  ns = std::min(ns, part_tiles / wgs);
+  return std::max(ns, 1);
 }
 
 // Factor A32[l] = L L^T for every lambda: left-looking blocked Cholesky, per block column an
@@ -1508,8 +1590,17 @@ static fk_status factor_all(fk_ctx* ctx, const SolveLayout& s, const DenseShape&
   // then column kb is finished, then column kb + 1 takes its remaining term k = kb.
   for (int kb = 0; kb < nb;) {
     if (sh.pair && kb > 0 && kb + 1 < nb) {
-      hipLaunchKernelGGL(k_left_update2, dim3((nb - kb) * s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np, kb,
-                         s.nlam);
+      const int wgs = (nb - kb) * s.nlam;
+      const int nsplit = update_split(wgs, kb, s.part_tiles);
+      if (nsplit > 1) {
+        hipLaunchKernelGGL(k_left_update2<true>, dim3(wgs * nsplit), dim3(256), 0, ctx->stream, s.A32, s.Np, kb,
+                           s.nlam, nsplit, s.upart);
+        hipLaunchKernelGGL(k_left_update2_sum, dim3(wgs * 8), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.nlam,
+                           nsplit, s.upart);
+      } else {
+        hipLaunchKernelGGL(k_left_update2<false>, dim3(wgs), dim3(256), 0, ctx->stream, s.A32, s.Np, kb, s.nlam, 1,
+                           nullptr);
+      }
       finish(kb);
       hipLaunchKernelGGL(k_left_update, dim3((nb - kb - 1) * s.nlam), dim3(256), 0, ctx->stream, s.A32, s.Np,
                          kb + 1, kb, kb + 1, s.nlam);

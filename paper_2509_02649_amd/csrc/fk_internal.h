@@ -90,6 +90,8 @@ struct SolveLayout {
   double* pcx = nullptr;   // N complex-mode weights
   double* scl = nullptr;   // nlam x Np diagonal equilibration of the FP32 factor
   double* dsym = nullptr;  // N complex: operator symbol of a physics-informed penalty
+  float* upart = nullptr;  // part_tiles x 64 x 128: parts of the split paired updates
+  int part_tiles = 0;
   size_t bytes = 0;
 };
 SolveLayout solve_layout(int N, int nlam, int ntgt, void* base, size_t cap);
