@@ -148,6 +148,26 @@ def test_solve_at_the_batched_benchmark_shape(fk):
         assert e <= TOL
 
 
+def test_split_update_solve_is_deterministic(fk):
+    # a few lambdas and targets at N = 4225: the paired updates' grids are small, so from the third
+    # pair of block columns on their sums over the panels are split and the parts added in a fixed
+    # order; two solves of the same system give the same bits, and theta matches the oracle
+    m, T, lams = 32, 2, [1e-6, 1e-4, 1e-2]
+    ctx = fk.Context(0)
+    X = fk.generate_uniform(2509026496, 2, 1_000_000, ctx=ctx)
+    Y = fk.generate_targets(2509026496, X, T, ctx=ctx)
+    M, b = fk.gram(X, Y, m, ctx=ctx)
+    t1 = fk.solve(M, b, m, lams, penalty="sobolev", s=2.0, ctx=ctx).cpu().numpy()
+    t2 = fk.solve(M, b, m, lams, penalty="sobolev", s=2.0, ctx=ctx).cpu().numpy()
+    assert np.array_equal(t1, t2)
+    Mh, bh = M.cpu().numpy(), b.cpu().numpy()
+    p = oracle.sobolev_weights(m, 2, 2.0)
+    ref = oracle.solve_system(oracle.system_matrix(Mh, m, lams[1], p), bh)
+    e = max(_rel(t1[1, t], ref[t]) for t in range(T))
+    print(f"split updates, lambda={lams[1]:.0e}: worst rel {e:.2e}")
+    assert e <= TOL
+
+
 def test_solve_more_than_16_right_hand_sides(fk):
     # 20 right-hand sides: the triangular solves take 32-column blocks (two 16-column MFMA tiles)
     rng = np.random.default_rng(2020)
