@@ -124,6 +124,9 @@ typedef struct {
   double beta;         /* exponential-of-semicircle shape parameter */
   double resid_rel;    /* max over (lambda, target) of ||b - A theta|| / ||b|| in FP64 */
   float t_sort_ms, t_spread_ms, t_fft_ms, t_assemble_ms, t_factor_ms, t_solve_ms, t_total_ms;
+                       /* stage times (HIP events).  On the call that tunes a dense shape (see
+                          "Autotuning") the trials run inside the assembly interval, whose last
+                          factorization is kept, so t_factor_ms is then about 0 */
   double spread_kernel_ms;   /* device time of the spreading kernel alone */
 } fk_fit_info;
 
