@@ -29,7 +29,7 @@ def _cplx(a):
 
 
 @pytest.mark.parametrize("d,m,n,s,lam", [(1, 50, 10_000, 1.0, 1e4 ** (-2 / 3)), (2, 8, 50_000, 2.0, 1e-3),
-                                         (2, 32, 100_000, 2.0, 1e-3)])
+                                         (2, 16, 60_000, 2.0, 1e-3), (2, 32, 100_000, 2.0, 1e-3)])
 def test_solver_only_parity(fk, d, m, n, s, lam):
     rng = np.random.default_rng(d * 100 + m)
     X = rng.uniform(-np.pi, np.pi, size=(d, n))
