@@ -15,6 +15,7 @@ from __future__ import annotations
 
 import ctypes as C
 import math
+import threading
 from typing import Optional, Sequence
 
 import torch
@@ -514,13 +515,38 @@ class KernelRidgeGridLoss(torch.autograd.Function):
         fkc = default_context(X.device.index or 0)
         lams = torch.exp(loglam.detach()).cpu().tolist()
         d = X.shape[0]
-        # type-1 stage in the context's shared workspace, factors in this apply's own (one call)
+        # The fit (type-1 stage in the context's shared workspace, factors in this apply's own), and
+        # meanwhile the held-out Gram on a second host thread, in a second context on a stream of
+        # its own (the library calls release the interpreter lock): its kernels fill the GPU around
+        # the fit's instead of following them.
         sb, _ = fit_kept_workspace_size(d, X.shape[1], Y.shape[0], m, len(lams), fkc)
         kept = torch.empty(sb, dtype=torch.uint8, device=X.device)
-        theta = fit(X, Y, m, lams, penalty="diag", p=p.detach(), ctx=fkc, ws=kept)
         vctx = _validation_context(fkc)
-        Mv, bv = gram(Xv, Yv, m, ctx=vctx)
-        yv2 = mean_square(Yv, vctx)
+        main = torch.cuda.current_stream(X.device)
+        vs = _validation_stream(X.device)
+        vs.wait_stream(main)
+        held: dict = {}
+
+        def _heldout():
+            try:
+                with torch.cuda.stream(vs):
+                    held["Mv"], held["bv"] = gram(Xv, Yv, m, ctx=vctx)
+                    held["yv2"] = mean_square(Yv, vctx)
+            except BaseException as e:   # re-raised on the calling thread
+                held["err"] = e
+
+        worker = threading.Thread(target=_heldout)
+        worker.start()
+        try:
+            theta = fit(X, Y, m, lams, penalty="diag", p=p.detach(), ctx=fkc, ws=kept)
+        finally:
+            worker.join()
+        if "err" in held:
+            raise held["err"]
+        main.wait_stream(vs)
+        Mv, bv, yv2 = held["Mv"], held["bv"], held["yv2"]
+        for t in (Mv, bv, yv2):
+            t.record_stream(main)
         mse = heldout_mse(Mv, bv, yv2, m, len(lams), fkc, ws=kept)
         ctx_.fkc = fkc
         ctx_.kept = kept
@@ -541,6 +567,17 @@ class KernelRidgeGridLoss(torch.autograd.Function):
 
 
 _valctx: dict = {}
+_valstream: dict = {}
+
+
+def _validation_stream(device) -> torch.cuda.Stream:
+    """The held-out Gram's stream on this device (default priority, created once)."""
+    dev = torch.device(device)
+    s = _valstream.get(dev.index)
+    if s is None:
+        s = torch.cuda.Stream(device=dev)
+        _valstream[dev.index] = s
+    return s
 
 
 def _validation_context(fkc: Context) -> Context:
