@@ -506,8 +506,10 @@ class KernelRidgeGridLoss(torch.autograd.Function):
     backward runs one adjoint solve per (lambda, target) with the kept factors, on the combined
     right-hand side of the mse term and of any other use of theta, and returns the gradients with
     respect to log lambda and p.  Each apply keeps its factors in a workspace of its own, so several
-    applies (cross-validation folds, repeated calls) can be alive in one graph.  Not in the paper: it
-    makes the lambda grid search of Sec. 5 differentiable.
+    applies (cross-validation folds, repeated calls) can be alive in one graph.  The held-out Gram is
+    computed on a second host thread, in a second library context on a second stream of the device,
+    while the fit runs; applies on one device are therefore not to be issued from several threads at
+    once.  Not in the paper: it makes the lambda grid search of Sec. 5 differentiable.
     """
 
     @staticmethod
