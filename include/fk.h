@@ -38,7 +38,9 @@
  *   pivot, no convergence) become the returned status there.  The fits
  *   synchronise once per refinement step (its residual norms, which come back
  *   with the error flags of every stage before it, decide whether another step
- *   runs) and once at the end; a first use of an untuned large shape also
+ *   runs; with refine_tol below 1e-8 the first solve's check is skipped, since
+ *   an FP32-class solve does not reach such a tolerance without refinement) and
+ *   once at the end; a first use of an untuned large shape also
  *   synchronises around its timed trials.  Host-side argument checks return
  *   FK_EINVAL before anything is enqueued.
  * - A context must not be used by two threads at once; distinct contexts are
