@@ -361,7 +361,8 @@ fk_status fk_additive_fit(fk_ctx* ctx, int d, int64_t n, fk_dtype dtype, const v
  * diagonal blocks of the factorization are then factored in FP64 instead of FP32 (slower; the
  * FP32 default matches an FP32 LAPACK factorization's accuracy).
  * At the first call of a shape without a table entry the library times each candidate (coordinate
- * descent, one knob at a time, on the call's own data; the call then runs with the fastest) and
+ * descent, one knob at a time, on the call's own data, a type-1 candidate as the better of two runs;
+ * the call then runs with the fastest) and
  * records "<arch> <stage> <shape> = <knob>=<value> ... ms=<time>" in a process-wide table; every
  * candidate is a correct configuration, so results differ only by rounding.  Environment:
  * FK_AUTOTUNE_CACHE = path of a text file read at the first lookup and appended with each new
