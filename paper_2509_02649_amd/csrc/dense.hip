@@ -1988,10 +1988,11 @@ __global__ void k_adjoint_rhs(const double* __restrict__ G64, const double* __re
 
 // grad_loglam[l] = sum_t (-2 lambda_l) u.(preal o x), u the adjoint solution of the combined
 // right-hand side;  grad_p (complex modes) likewise.
-__global__ __launch_bounds__(256) void k_grad_loglam(const double* __restrict__ U, const double* __restrict__ X,
-                                                     const double* __restrict__ preal, const double* __restrict__ lams,
-                                                     int Np, int ntgt, double* __restrict__ out) {
-  __shared__ double part[256];
+// One workgroup of 1024 threads per lambda (the sum runs over ntgt x Np terms).
+__global__ __launch_bounds__(1024) void k_grad_loglam(const double* __restrict__ U, const double* __restrict__ X,
+                                                      const double* __restrict__ preal, const double* __restrict__ lams,
+                                                      int Np, int ntgt, double* __restrict__ out) {
+  __shared__ double part[1024];
   const int l = blockIdx.x;
   double s = 0.0;
   for (int t = 0; t < ntgt; ++t) {
@@ -2003,7 +2004,7 @@ __global__ __launch_bounds__(256) void k_grad_loglam(const double* __restrict__ 
   }
   part[threadIdx.x] = s;
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
+  for (int o = 512; o > 0; o >>= 1) {
     if (threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
     __syncthreads();
   }
@@ -2064,7 +2065,7 @@ fk_status backward_impl(fk_ctx* ctx, const SolveLayout& s, int d, const double* 
                      s.Gadj);
   fk_status st = refine_solve(ctx, s, dense_shape(ctx, s), s.Gadj, s.U64, &iters, &resid, &bad);
   if (st != FK_OK && st != FK_ENOCONV) return st;
-  hipLaunchKernelGGL(k_grad_loglam, dim3(s.nlam), dim3(256), 0, ctx->stream, s.U64, s.X64, s.preal, s.lams, Np,
+  hipLaunchKernelGGL(k_grad_loglam, dim3(s.nlam), dim3(1024), 0, ctx->stream, s.U64, s.X64, s.preal, s.lams, Np,
                      s.ntgt, grad_loglam);
   if (grad_p) {
     hipLaunchKernelGGL(k_zero_d, dim3((N + 255) / 256), dim3(256), 0, ctx->stream, grad_p, N);
