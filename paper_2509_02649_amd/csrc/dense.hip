@@ -1777,8 +1777,9 @@ static DenseShape dense_shape(const fk_ctx* ctx, const SolveLayout& s) {
 }
 
 // Launch shape of the factorization and the triangular solves.  Tuning (large batched solves whose
-// shape has no table entry): each pairing candidate rebuilds the FP32 matrices and factors them, the
-// last leaves valid factors (*factored); each solve width is timed on zero right-hand sides.
+// shape has no table entry): each pairing candidate rebuilds the FP32 matrices and factors them, and
+// the chosen one's factors are left in place (*factored; rebuilt if another candidate ran last);
+// each solve width is timed on zero right-hand sides.
 static fk_status tune_dense(fk_ctx* ctx, const SolveLayout& s, DenseShape* out, bool* factored) {
   const int mode = tune_mode(ctx);
   *factored = false;
@@ -1789,8 +1790,6 @@ static fk_status tune_dense(fk_ctx* ctx, const SolveLayout& s, DenseShape* out, 
   // the trials synchronize anyway: no shape is measured on a system the earlier stages flagged
   fk_status fs = read_flags(ctx);
   if (fs != FK_OK) return fs;
-  const int64_t tot2 = (int64_t)s.Np * s.Np;
-  const int gb = (int)((tot2 + 255) / 256);
   hipEvent_t e0 = ctx->ev[11], e1 = ctx->ev[12];
   DenseShape sh;
   float best_f = 0.f;
@@ -1810,6 +1809,14 @@ static fk_status tune_dense(fk_ctx* ctx, const SolveLayout& s, DenseShape* out, 
       best_f = ms;
       sh.pair = pair;
     }
+  }
+  // the factors the call goes on with are those of the chosen pairing, so that the first call of a
+  // shape gives the same bits as the later ones
+  if (sh.pair != 0) {
+    hipLaunchKernelGGL(k_make_a32, dim3(a32_tiles(s.Np)), dim3(256), 0, ctx->stream, s.H64, s.preal, s.lams, s.scl,
+                       s.N, s.Np, s.nlam, s.A32);
+    fk_status st = factor_all(ctx, s, sh);
+    if (st != FK_OK) return st;
   }
   *factored = true;
   const size_t nv = (size_t)s.nlam * s.ntgt * s.Np;
