@@ -45,6 +45,10 @@
  *   FK_EINVAL before anything is enqueued.
  * - A context must not be used by two threads at once; distinct contexts are
  *   independent.  No exception crosses this ABI.
+ * - Repeatability: the dense stage (fk_solve, the solve of fk_fit, the
+ *   gradients) gives the same bits for the same inputs and launch shapes; the
+ *   type-1 sums (fk_gram) accumulate with FP64 atomics and agree between runs
+ *   to FP64 rounding.
  */
 #ifndef FASTKERNEL_FK_H
 #define FASTKERNEL_FK_H
